@@ -1,0 +1,227 @@
+"""ctypes binding of the CPU oracle (oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the slow, obviously-correct reference the HIP path
+is checked against.  Only the tests, the smoke check and the CPU-baseline leg
+of the benchmark import this package; the product library never does.
+
+Inputs are the arrays of a scene built by the seeded scene generator
+(per-body arrays over a global, env-major body index).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GROUND = 0xFFFF
+MAX_POINTS = 16
+
+
+class PhysParams(C.Structure):
+    _fields_ = [("dt", C.c_float), ("substeps", C.c_int32), ("k", C.c_float),
+                ("c", C.c_float), ("g", C.c_float * 3)]
+
+
+class RenderParams(C.Structure):
+    _fields_ = [
+        ("sphere_v", C.c_void_p), ("sphere_f", C.c_void_p), ("sphere_n", C.c_void_p),
+        ("sphere_nv", C.c_int32), ("sphere_nf", C.c_int32),
+        ("cube_v", C.c_void_p), ("cube_f", C.c_void_p), ("cube_n", C.c_void_p),
+        ("cube_nv", C.c_int32), ("cube_nf", C.c_int32),
+        ("ground_v", C.c_void_p), ("ground_f", C.c_void_p), ("ground_nf", C.c_int32),
+        ("light", C.c_float * 3), ("palette", C.c_float * 24), ("ground_albedo", C.c_float),
+        ("near_w", C.c_float), ("guard", C.c_float)]
+
+
+class Point(C.Structure):
+    _fields_ = [("n", C.c_float * 3), ("delta", C.c_float), ("xc", C.c_float * 3),
+                ("a_is_first", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = os.path.join(HERE, "liboracle.so")
+        if not os.path.exists(path):
+            from . import build as _b
+            _b.build()
+        _lib = C.CDLL(path)
+        _lib.oracle_step_env.restype = C.c_int
+        _lib.oracle_render_image.restype = C.c_int
+        _lib.oracle_run_batch.restype = C.c_int
+        _lib.oracle_narrowphase.restype = C.c_int
+        _lib.oracle_setup_triangle.restype = C.c_int
+        _lib.oracle_covers.restype = C.c_int
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def phys_params(scene) -> PhysParams:
+    g = (C.c_float * 3)(*[float(x) for x in scene.gravity])
+    return PhysParams(float(np.float32(scene.dt)), int(scene.substeps), float(scene.k_contact),
+                      float(scene.c_damp), g)
+
+
+class _Render:
+    """Keeps the template arrays alive while the struct points at them."""
+
+    def __init__(self, light=None, palette=None, ground_albedo=None, near=None, guard=None):
+        from paper_2605_01352_amd import scenegen as sg
+        t = sg.templates()
+        self.arrs = [np.ascontiguousarray(a) for a in (
+            t.sphere_v, t.sphere_f.astype(np.int32), t.sphere_n, t.cube_v,
+            t.cube_f.astype(np.int32), t.cube_n, t.ground_v, t.ground_f.astype(np.int32))]
+        sv, sf, sn, cv, cf, cn, gv, gf = self.arrs
+        light = sg.LIGHT if light is None else light
+        palette = sg.PALETTE if palette is None else palette
+        self.s = RenderParams(
+            _p(sv), _p(sf), _p(sn), len(sv), len(sf), _p(cv), _p(cf), _p(cn), len(cv), len(cf),
+            _p(gv), _p(gf), len(gf),
+            (C.c_float * 3)(*np.asarray(light, np.float32).tolist()),
+            (C.c_float * 24)(*np.asarray(palette, np.float32).reshape(-1).tolist()),
+            float(sg.GROUND_ALBEDO if ground_albedo is None else ground_albedo),
+            float(sg.NEAR if near is None else near),
+            float(sg.GUARD_BAND if guard is None else guard))
+
+
+_RENDER: Optional[_Render] = None
+
+
+def render_params() -> _Render:
+    global _RENDER
+    if _RENDER is None:
+        _RENDER = _Render()
+    return _RENDER
+
+
+def step_env(scene, e: int, state: Dict[str, np.ndarray], record_pairs: bool = False,
+             pair_cap: int = 4096) -> Tuple[int, Optional[List[np.ndarray]]]:
+    """Advance env e of `state` (global arrays, modified in place) by one step.
+
+    Returns (status, per-substep sorted pair arrays [k,2] or None).
+    """
+    L = lib()
+    b0, b1 = int(scene.body_off[e]), int(scene.body_off[e + 1])
+    n = b1 - b0
+    sl = lambda a: np.ascontiguousarray(a[b0:b1])
+    pos, vel, quat, om = (np.ascontiguousarray(state[k][b0:b1]) for k in ("pos", "vel", "quat", "omega"))
+    prm = phys_params(scene)
+    S = int(scene.substeps)
+    pairs = np.zeros((S, pair_cap, 2), np.int32) if record_pairs else None
+    npairs = np.zeros(S, np.int32)
+    bt, sz, rb, im, iI = sl(scene.btype), sl(scene.size), sl(scene.rbound), sl(scene.inv_m), sl(scene.inv_I)
+    st = L.oracle_step_env(n, _p(bt), _p(sz), _p(rb), _p(im), _p(iI), _p(pos), _p(vel), _p(quat),
+                           _p(om), C.byref(prm), _p(pairs) if pairs is not None else None,
+                           pair_cap, _p(npairs))
+    state["pos"][b0:b1], state["vel"][b0:b1] = pos, vel
+    state["quat"][b0:b1], state["omega"][b0:b1] = quat, om
+    out = [pairs[s, :npairs[s]].copy() for s in range(S)] if record_pairs else None
+    return st, out
+
+
+def step_scene(scene, state: Dict[str, np.ndarray], envs: Optional[Sequence[int]] = None,
+               record_pairs: bool = False):
+    """One step of the given envs (all by default).  Returns (statuses, pairs)
+    where pairs[e] is the list of per-substep pair arrays."""
+    envs = range(scene.n_envs) if envs is None else envs
+    sts, prs = {}, {}
+    for e in envs:
+        sts[e], prs[e] = step_env(scene, e, state, record_pairs)
+    return sts, prs
+
+
+def narrowphase(scene, state, i: int, j: int) -> List[Point]:
+    """Contact points of bodies i < j (global ids of one env) or i and ground."""
+    pts = (Point * MAX_POINTS)()
+    pos = np.ascontiguousarray(state["pos"], np.float32)
+    quat = np.ascontiguousarray(state["quat"], np.float32)
+    bt = np.ascontiguousarray(scene.btype)
+    sz = np.ascontiguousarray(scene.size)
+    n = lib().oracle_narrowphase(i, j, _p(bt), _p(sz), _p(pos), _p(quat), pts)
+    return [pts[k] for k in range(n)]
+
+
+def render_image(scene, state, cam: int, e: Optional[int] = None, debug: bool = False):
+    """Render camera `cam` (global camera index) of its env.
+
+    Returns dict(rgb [H,W,3] u8, depth [H,W] u32, winner, cover (debug only)).
+    """
+    if e is None:
+        e = int(np.searchsorted(scene.cam_off, cam, side="right") - 1)
+    b0, b1 = int(scene.body_off[e]), int(scene.body_off[e + 1])
+    W, H = int(scene.cam_w[cam]), int(scene.cam_h[cam])
+    rgb = np.zeros((H, W, 3), np.uint8)
+    depth = np.zeros((H, W), np.uint32)
+    winner = np.zeros((H, W), np.int32) if debug else None
+    cover = np.zeros((H, W), np.int32) if debug else None
+    sl = lambda a: np.ascontiguousarray(a[b0:b1])
+    bt, sz, al = sl(scene.btype), sl(scene.size), sl(scene.albedo)
+    pos, quat = sl(state["pos"]), sl(state["quat"])
+    vp = np.ascontiguousarray(scene.cam_vp[cam], np.float32)
+    rp = render_params()
+    lib().oracle_render_image(b1 - b0, _p(bt), _p(sz), _p(al), _p(pos), _p(quat), _p(vp), W, H,
+                              C.byref(rp.s), _p(rgb), _p(depth),
+                              _p(winner) if debug else None, _p(cover) if debug else None)
+    out = dict(rgb=rgb, depth=depth)
+    if debug:
+        out.update(winner=winner, cover=cover)
+    return out
+
+
+def setup_triangle(w0, w1, w2, vp, W, H, near=0.05, guard=8192.0):
+    X = np.zeros(3, np.int32)
+    Y = np.zeros(3, np.int32)
+    z = np.zeros(3, np.float32)
+    A = C.c_int64(0)
+    f = lambda a: np.ascontiguousarray(a, np.float32)
+    a0, a1, a2, v = f(w0), f(w1), f(w2), f(vp).reshape(16)
+    ok = lib().oracle_setup_triangle(_p(a0), _p(a1), _p(a2), _p(v), W, H, C.c_float(near),
+                                     C.c_float(guard), _p(X), _p(Y), _p(z), C.byref(A))
+    return bool(ok), X, Y, z, A.value
+
+
+def covers(X, Y, px, py) -> bool:
+    X = np.ascontiguousarray(X, np.int32)
+    Y = np.ascontiguousarray(Y, np.int32)
+    return bool(lib().oracle_covers(_p(X), _p(Y), int(px), int(py)))
+
+
+def image_offsets(scene) -> np.ndarray:
+    px = scene.cam_w.astype(np.int64) * scene.cam_h.astype(np.int64)
+    return np.concatenate([[0], np.cumsum(px)[:-1]]).astype(np.int64)
+
+
+def run_batch(scene, state, n_steps: int, nthreads: int, do_render: bool = True):
+    """Multi-threaded batch run (whole envs per thread) for the CPU baseline.
+
+    Modifies `state` in place; returns (status, rgb, depth) of the last step.
+    """
+    off = image_offsets(scene)
+    total = int((scene.cam_w.astype(np.int64) * scene.cam_h).sum())
+    rgb = np.zeros(total * 3, np.uint8)
+    depth = np.zeros(total, np.uint32)
+    c = lambda a, dt=None: np.ascontiguousarray(a if dt is None else a.astype(dt))
+    arrs = dict(bo=c(scene.body_off, np.int32), bt=c(scene.btype), sz=c(scene.size),
+                rb=c(scene.rbound), im=c(scene.inv_m), iI=c(scene.inv_I), al=c(scene.albedo),
+                co=c(scene.cam_off, np.int32), vp=c(scene.cam_vp, np.float32),
+                cw=c(scene.cam_w, np.int32), ch=c(scene.cam_h, np.int32), io=c(off))
+    for k in ("pos", "vel", "quat", "omega"):
+        state[k] = np.ascontiguousarray(state[k], np.float32)
+    prm = phys_params(scene)
+    rp = render_params()
+    st = lib().oracle_run_batch(
+        scene.n_envs, _p(arrs["bo"]), _p(arrs["bt"]), _p(arrs["sz"]), _p(arrs["rb"]),
+        _p(arrs["im"]), _p(arrs["iI"]), _p(arrs["al"]), _p(state["pos"]), _p(state["vel"]),
+        _p(state["quat"]), _p(state["omega"]), C.byref(prm), _p(arrs["co"]), _p(arrs["vp"]),
+        _p(arrs["cw"]), _p(arrs["ch"]), _p(arrs["io"]), C.byref(rp.s), _p(rgb), _p(depth),
+        int(n_steps), int(nthreads), int(do_render))
+    return st, rgb, depth

@@ -1,0 +1,552 @@
+/*
+ * CPU oracle: physics step and rasterizer, single-threaded per env.
+ *
+ * TEST INFRASTRUCTURE ONLY -- see oracle.h.  Compiled with -ffp-contract=off
+ * and no fast-math; every floating-point expression is evaluated exactly in
+ * the order written.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct { float x, y, z; } v3;
+
+static v3 mk(float x, float y, float z) { v3 r = {x, y, z}; return r; }
+static v3 add(v3 a, v3 b) { return mk(a.x + b.x, a.y + b.y, a.z + b.z); }
+static v3 sub(v3 a, v3 b) { return mk(a.x - b.x, a.y - b.y, a.z - b.z); }
+static v3 scl(v3 a, float s) { return mk(a.x * s, a.y * s, a.z * s); }
+static v3 neg(v3 a) { return mk(-a.x, -a.y, -a.z); }
+/* dot product, summed left to right */
+static float dot(v3 a, v3 b) { return (a.x * b.x + a.y * b.y) + a.z * b.z; }
+static v3 cross(v3 a, v3 b) {
+  return mk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+static float comp(v3 a, int k) { return k == 0 ? a.x : (k == 1 ? a.y : a.z); }
+
+/* Rotation matrix of a quaternion (w,x,y,z), row-major m[3*r+c]; the
+ * standard unit-quaternion formula, evaluated as written. */
+static void quat_mat(const float* q, float* m) {
+  float w = q[0], x = q[1], y = q[2], z = q[3];
+  float xx = x * x, yy = y * y, zz = z * z, xy = x * y, xz = x * z, yz = y * z;
+  float wx = w * x, wy = w * y, wz = w * z;
+  m[0] = 1.0f - 2.0f * (yy + zz); m[1] = 2.0f * (xy - wz);        m[2] = 2.0f * (xz + wy);
+  m[3] = 2.0f * (xy + wz);        m[4] = 1.0f - 2.0f * (xx + zz); m[5] = 2.0f * (yz - wx);
+  m[6] = 2.0f * (xz - wy);        m[7] = 2.0f * (yz + wx);        m[8] = 1.0f - 2.0f * (xx + yy);
+}
+/* R v (rows dotted with v) */
+static v3 mat_vec(const float* m, v3 v) {
+  return mk((m[0] * v.x + m[1] * v.y) + m[2] * v.z,
+            (m[3] * v.x + m[4] * v.y) + m[5] * v.z,
+            (m[6] * v.x + m[7] * v.y) + m[8] * v.z);
+}
+/* R^T v (columns dotted with v) */
+static v3 mat_tvec(const float* m, v3 v) {
+  return mk((m[0] * v.x + m[3] * v.y) + m[6] * v.z,
+            (m[1] * v.x + m[4] * v.y) + m[7] * v.z,
+            (m[2] * v.x + m[5] * v.y) + m[8] * v.z);
+}
+
+static v3 load3(const float* a, int32_t i) { return mk(a[3 * i], a[3 * i + 1], a[3 * i + 2]); }
+
+/* Corner k of a cube of half-extent a: sign + on axis t iff bit t of k set. */
+static v3 cube_vertex(v3 p, const float* R, float a, int k) {
+  v3 w = mk((k & 1) ? a : -a, (k & 2) ? a : -a, (k & 4) ? a : -a);
+  return add(p, mat_vec(R, w));
+}
+
+/* Deepest-face axis of a local point strictly inside a box of half-extent a:
+ * argmin over axes of (a - |u_axis|), lowest axis on ties. */
+static int min_axis(v3 u, float a, float* depth) {
+  float d0 = a - fabsf(u.x), d1 = a - fabsf(u.y), d2 = a - fabsf(u.z);
+  int m = 0;
+  float dm = d0;
+  if (d1 < dm) { m = 1; dm = d1; }
+  if (d2 < dm) { m = 2; dm = d2; }
+  *depth = dm;
+  return m;
+}
+
+static v3 axis_dir(int m, float s) {
+  return mk(m == 0 ? s : 0.0f, m == 1 ? s : 0.0f, m == 2 ? s : 0.0f);
+}
+
+/* ---------------------------------------------------------------------------
+ * Narrowphase.  "Contact" means penetration strictly greater than zero.
+ * Each point names the body "A" pushed along +n.
+ * ------------------------------------------------------------------------- */
+
+static int np_sphere_sphere(v3 pi, float ri, v3 pj, float rj, oracle_point* out) {
+  v3 d = sub(pi, pj);
+  float d2 = dot(d, d);
+  float s = ri + rj;
+  if (!(d2 < s * s)) return 0;
+  float L = sqrtf(d2);
+  v3 n = L > 0.0f ? mk(d.x / L, d.y / L, d.z / L) : mk(0.0f, 0.0f, 1.0f);
+  float delta = s - L;
+  v3 xc = add(pj, scl(n, rj - 0.5f * delta));
+  out->n[0] = n.x; out->n[1] = n.y; out->n[2] = n.z;
+  out->delta = delta;
+  out->xc[0] = xc.x; out->xc[1] = xc.y; out->xc[2] = xc.z;
+  out->a_is_first = 1;
+  return 1;
+}
+
+/* sphere (centre c, radius r) against cube (p, R, a); normal from cube to sphere */
+static int np_sphere_cube(v3 c, float r, v3 p, const float* R, float a, int sphere_first,
+                          oracle_point* out) {
+  v3 u = mat_tvec(R, sub(c, p));
+  v3 e = mk(fminf(fmaxf(u.x, -a), a), fminf(fmaxf(u.y, -a), a), fminf(fmaxf(u.z, -a), a));
+  v3 rv = sub(u, e);
+  float L2 = dot(rv, rv);
+  if (!(L2 < r * r)) return 0;
+  v3 nl;
+  float delta;
+  if (L2 > 0.0f) {
+    float L = sqrtf(L2);
+    nl = mk(rv.x / L, rv.y / L, rv.z / L);
+    delta = r - L;
+  } else {
+    float dm;
+    int m = min_axis(u, a, &dm);
+    nl = axis_dir(m, comp(u, m) >= 0.0f ? 1.0f : -1.0f);
+    delta = r + dm;
+  }
+  v3 n = mat_vec(R, nl);
+  v3 xc = add(p, mat_vec(R, e));
+  out->n[0] = n.x; out->n[1] = n.y; out->n[2] = n.z;
+  out->delta = delta;
+  out->xc[0] = xc.x; out->xc[1] = xc.y; out->xc[2] = xc.z;
+  out->a_is_first = sphere_first;
+  return 1;
+}
+
+/* vertices of cube A (pa, Ra, aa) strictly inside cube B (pb, Rb, ab) */
+static int np_vertices_in_box(v3 pa, const float* Ra, float aa, v3 pb, const float* Rb, float ab,
+                              int a_first, oracle_point* out) {
+  int cnt = 0;
+  for (int k = 0; k < 8; ++k) {
+    v3 v = cube_vertex(pa, Ra, aa, k);
+    v3 u = mat_tvec(Rb, sub(v, pb));
+    if (fabsf(u.x) < ab && fabsf(u.y) < ab && fabsf(u.z) < ab) {
+      float dm;
+      int m = min_axis(u, ab, &dm);
+      v3 n = mat_vec(Rb, axis_dir(m, comp(u, m) >= 0.0f ? 1.0f : -1.0f));
+      oracle_point* o = &out[cnt++];
+      o->n[0] = n.x; o->n[1] = n.y; o->n[2] = n.z;
+      o->delta = dm;
+      o->xc[0] = v.x; o->xc[1] = v.y; o->xc[2] = v.z;
+      o->a_is_first = a_first;
+    }
+  }
+  return cnt;
+}
+
+static int np_ground(int32_t i, const uint8_t* type, const float* size, const float* pos,
+                     const float* quat, oracle_point* out) {
+  v3 p = load3(pos, i);
+  float a = size[i];
+  if (type[i] == 0) {
+    if (!(p.z < a)) return 0;
+    out->n[0] = 0.0f; out->n[1] = 0.0f; out->n[2] = 1.0f;
+    out->delta = a - p.z;
+    out->xc[0] = p.x; out->xc[1] = p.y; out->xc[2] = p.z - a;
+    out->a_is_first = 1;
+    return 1;
+  }
+  float R[9];
+  quat_mat(quat + 4 * i, R);
+  int cnt = 0;
+  for (int k = 0; k < 8; ++k) {
+    v3 v = cube_vertex(p, R, a, k);
+    if (v.z < 0.0f) {
+      oracle_point* o = &out[cnt++];
+      o->n[0] = 0.0f; o->n[1] = 0.0f; o->n[2] = 1.0f;
+      o->delta = -v.z;
+      o->xc[0] = v.x; o->xc[1] = v.y; o->xc[2] = v.z;
+      o->a_is_first = 1;
+    }
+  }
+  return cnt;
+}
+
+int oracle_narrowphase(int32_t i, int32_t j, const uint8_t* type, const float* size,
+                       const float* pos, const float* quat, oracle_point* pts) {
+  if (j == ORACLE_GROUND) return np_ground(i, type, size, pos, quat, pts);
+  v3 pi = load3(pos, i), pj = load3(pos, j);
+  float Ri[9], Rj[9];
+  quat_mat(quat + 4 * i, Ri);
+  quat_mat(quat + 4 * j, Rj);
+  if (type[i] == 0 && type[j] == 0) return np_sphere_sphere(pi, size[i], pj, size[j], pts);
+  if (type[i] == 0 && type[j] == 1) return np_sphere_cube(pi, size[i], pj, Rj, size[j], 1, pts);
+  if (type[i] == 1 && type[j] == 0) return np_sphere_cube(pj, size[j], pi, Ri, size[i], 0, pts);
+  int c = np_vertices_in_box(pi, Ri, size[i], pj, Rj, size[j], 1, pts);
+  c += np_vertices_in_box(pj, Rj, size[j], pi, Ri, size[i], 0, pts + c);
+  return c;
+}
+
+/* ---------------------------------------------------------------------------
+ * Physics step
+ * ------------------------------------------------------------------------- */
+
+typedef struct { v3 F, T; } acc_t;
+
+static int finite3(v3 a) { return isfinite(a.x) && isfinite(a.y) && isfinite(a.z); }
+
+int oracle_step_env(int32_t n, const uint8_t* type, const float* size, const float* rbound,
+                    const float* inv_m, const float* inv_I, float* pos, float* vel,
+                    float* quat, float* omega, const oracle_phys_params* prm,
+                    int32_t* pairs, int32_t pair_cap, int32_t* npairs) {
+  const float h = prm->dt / (float)prm->substeps;
+  const float hh = 0.5f * h;
+  const v3 g = mk(prm->g[0], prm->g[1], prm->g[2]);
+  acc_t* acc = (acc_t*)malloc(sizeof(acc_t) * (size_t)(n > 0 ? n : 1));
+  oracle_point pts[ORACLE_MAX_POINTS];
+  int status = 0;
+
+  for (int s = 0; s < prm->substeps; ++s) {
+    int32_t np = 0;
+    for (int32_t b = 0; b < n; ++b) { acc[b].F = mk(0, 0, 0); acc[b].T = mk(0, 0, 0); }
+
+    /* Walk pairs in sorted (i, j) order, the ground last in each row; all
+     * tests use the substep-start state. */
+    for (int32_t i = 0; i < n; ++i) {
+      v3 pi = load3(pos, i);
+      for (int32_t j = i + 1; j <= n; ++j) {
+        int32_t jj = (j == n) ? ORACLE_GROUND : j;
+        int cand;
+        if (jj == ORACLE_GROUND) {
+          cand = pi.z < rbound[i];
+        } else {
+          v3 d = sub(pi, load3(pos, j));
+          float rs = rbound[i] + rbound[j];
+          cand = dot(d, d) <= rs * rs;
+        }
+        if (!cand) continue;
+        int cnt = oracle_narrowphase(i, jj, type, size, pos, quat, pts);
+        if (cnt == 0) continue;
+        if (pairs) {
+          if (np >= pair_cap) { status = -1; }
+          else {
+            pairs[(size_t)s * pair_cap * 2 + 2 * np] = i;
+            pairs[(size_t)s * pair_cap * 2 + 2 * np + 1] = jj;
+          }
+        }
+        ++np;
+        /* Forces of the pair's points, summed per pair in point order, then
+         * added to each body in pair order. */
+        v3 pA = pi, vA = load3(vel, i), wA = load3(omega, i);
+        v3 pB = mk(0, 0, 0), vB = mk(0, 0, 0), wB = mk(0, 0, 0);
+        if (jj != ORACLE_GROUND) { pB = load3(pos, jj); vB = load3(vel, jj); wB = load3(omega, jj); }
+        v3 SF = mk(0, 0, 0), Ti = mk(0, 0, 0), Tj = mk(0, 0, 0);
+        for (int k = 0; k < cnt; ++k) {
+          v3 nrm = mk(pts[k].n[0], pts[k].n[1], pts[k].n[2]);
+          v3 xc = mk(pts[k].xc[0], pts[k].xc[1], pts[k].xc[2]);
+          /* body A of this point is pushed along +n */
+          v3 pa = pts[k].a_is_first ? pA : pB, va = pts[k].a_is_first ? vA : vB;
+          v3 wa = pts[k].a_is_first ? wA : wB;
+          v3 pb = pts[k].a_is_first ? pB : pA, vb = pts[k].a_is_first ? vB : vA;
+          v3 wb = pts[k].a_is_first ? wB : wA;
+          v3 velA = add(va, cross(wa, sub(xc, pa)));
+          v3 vrel;
+          if (jj == ORACLE_GROUND) {
+            vrel = velA; /* the ground does not move */
+          } else {
+            v3 velB = add(vb, cross(wb, sub(xc, pb)));
+            vrel = sub(velA, velB);
+          }
+          float vn = dot(vrel, nrm);
+          float f = prm->k * pts[k].delta - prm->c * vn;
+          if (f < 0.0f) f = 0.0f;
+          v3 F = scl(nrm, f);
+          v3 Fi = pts[k].a_is_first ? F : neg(F); /* force on the pair's first body */
+          SF = add(SF, Fi);
+          Ti = add(Ti, cross(sub(xc, pA), Fi));
+          if (jj != ORACLE_GROUND) Tj = add(Tj, cross(sub(xc, pB), neg(Fi)));
+        }
+        acc[i].F = add(acc[i].F, SF);
+        acc[i].T = add(acc[i].T, Ti);
+        if (jj != ORACLE_GROUND) {
+          acc[jj].F = sub(acc[jj].F, SF);
+          acc[jj].T = add(acc[jj].T, Tj);
+        }
+      }
+    }
+    if (npairs) npairs[s] = np;
+
+    /* Semi-implicit Euler: v then p (with the new v); omega then q. */
+    for (int32_t b = 0; b < n; ++b) {
+      v3 v = load3(vel, b), p = load3(pos, b), w = load3(omega, b);
+      v3 a = add(scl(acc[b].F, inv_m[b]), g);
+      v = add(v, scl(a, h));
+      p = add(p, scl(v, h));
+      w = add(w, scl(scl(acc[b].T, inv_I[b]), h));
+      float* q = quat + 4 * b;
+      float qw = q[0], qx = q[1], qy = q[2], qz = q[3];
+      /* dq = (0, w) (x) q, Hamilton product */
+      float dw = (-w.x * qx - w.y * qy) - w.z * qz;
+      float dx = (w.x * qw + w.y * qz) - w.z * qy;
+      float dy = (w.y * qw + w.z * qx) - w.x * qz;
+      float dz = (w.z * qw + w.x * qy) - w.y * qx;
+      qw = qw + hh * dw; qx = qx + hh * dx; qy = qy + hh * dy; qz = qz + hh * dz;
+      float n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
+      float inv = 1.0f / sqrtf(n2);
+      q[0] = qw * inv; q[1] = qx * inv; q[2] = qy * inv; q[3] = qz * inv;
+      vel[3 * b] = v.x; vel[3 * b + 1] = v.y; vel[3 * b + 2] = v.z;
+      pos[3 * b] = p.x; pos[3 * b + 1] = p.y; pos[3 * b + 2] = p.z;
+      omega[3 * b] = w.x; omega[3 * b + 1] = w.y; omega[3 * b + 2] = w.z;
+      if (status == 0 && !(finite3(v) && finite3(p) && finite3(w) && isfinite(q[0]) &&
+                           isfinite(q[1]) && isfinite(q[2]) && isfinite(q[3])))
+        status = 2;
+    }
+  }
+  free(acc);
+  return status;
+}
+
+/* ---------------------------------------------------------------------------
+ * Rasterizer
+ * ------------------------------------------------------------------------- */
+
+int oracle_setup_triangle(const float* w0, const float* w1, const float* w2, const float* vp,
+                          int32_t W, int32_t H, float near_w, float guard,
+                          int32_t* X, int32_t* Y, float* z, int64_t* area) {
+  const float* wv[3] = {w0, w1, w2};
+  int32_t Xs[3], Ys[3];
+  float zs[3];
+  for (int k = 0; k < 3; ++k) {
+    float x = wv[k][0], y = wv[k][1], zz = wv[k][2];
+    float c[4];
+    for (int r = 0; r < 4; ++r)
+      c[r] = ((vp[4 * r] * x + vp[4 * r + 1] * y) + vp[4 * r + 2] * zz) + vp[4 * r + 3];
+    if (c[3] < near_w) return 0;
+    float nx = c[0] / c[3], ny = c[1] / c[3], nz = c[2] / c[3];
+    float sx = (nx * 0.5f + 0.5f) * (float)W;
+    float sy = (0.5f - ny * 0.5f) * (float)H;
+    if (fabsf(sx) > guard || fabsf(sy) > guard) return 0;
+    Xs[k] = (int32_t)rintf(sx * 256.0f);
+    Ys[k] = (int32_t)rintf(sy * 256.0f);
+    zs[k] = nz;
+  }
+  /* A triangle counter-clockwise in y-up NDC is clockwise in y-down screen
+   * space; taking the vertices in the order (0, 2, 1) makes its signed area
+   * positive. */
+  const int ord[3] = {0, 2, 1};
+  for (int k = 0; k < 3; ++k) { X[k] = Xs[ord[k]]; Y[k] = Ys[ord[k]]; z[k] = zs[ord[k]]; }
+  int64_t A = (int64_t)(X[1] - X[0]) * (int64_t)(Y[2] - Y[0]) -
+              (int64_t)(Y[1] - Y[0]) * (int64_t)(X[2] - X[0]);
+  *area = A;
+  return A > 0;
+}
+
+static int64_t edge_fn(int32_t xa, int32_t ya, int32_t xb, int32_t yb, int64_t px, int64_t py) {
+  return (int64_t)(xb - xa) * (py - ya) - (int64_t)(yb - ya) * (px - xa);
+}
+
+/* top-left edge in y-down screen space, for triangles of positive area */
+static int top_left(int32_t xa, int32_t ya, int32_t xb, int32_t yb) {
+  int32_t dx = xb - xa, dy = yb - ya;
+  return dy < 0 || (dy == 0 && dx > 0);
+}
+
+static int edge_in(int64_t E, int32_t xa, int32_t ya, int32_t xb, int32_t yb) {
+  return E > 0 || (E == 0 && top_left(xa, ya, xb, yb));
+}
+
+int oracle_covers(const int32_t* X, const int32_t* Y, int32_t px, int32_t py) {
+  int64_t Px = 256 * (int64_t)px + 128, Py = 256 * (int64_t)py + 128;
+  int64_t E0 = edge_fn(X[1], Y[1], X[2], Y[2], Px, Py);
+  int64_t E1 = edge_fn(X[2], Y[2], X[0], Y[0], Px, Py);
+  int64_t E2 = edge_fn(X[0], Y[0], X[1], Y[1], Px, Py);
+  return edge_in(E0, X[1], Y[1], X[2], Y[2]) && edge_in(E1, X[2], Y[2], X[0], Y[0]) &&
+         edge_in(E2, X[0], Y[0], X[1], Y[1]);
+}
+
+static void raster_tri(const float* w0, const float* w1, const float* w2, uint32_t prim,
+                       const float* vp, int32_t W, int32_t Hh, const oracle_render_params* rp,
+                       uint64_t* keys, int32_t* cover) {
+  int32_t X[3], Y[3];
+  float z[3];
+  int64_t A;
+  if (!oracle_setup_triangle(w0, w1, w2, vp, W, Hh, rp->near_w, rp->guard, X, Y, z, &A)) return;
+  int32_t xmin = X[0], xmax = X[0], ymin = Y[0], ymax = Y[0];
+  for (int k = 1; k < 3; ++k) {
+    if (X[k] < xmin) xmin = X[k];
+    if (X[k] > xmax) xmax = X[k];
+    if (Y[k] < ymin) ymin = Y[k];
+    if (Y[k] > ymax) ymax = Y[k];
+  }
+  /* a superset of the pixels whose centres can lie in the bounding box */
+  int32_t px0 = (xmin >> 8) - 1, px1 = (xmax >> 8) + 1;
+  int32_t py0 = (ymin >> 8) - 1, py1 = (ymax >> 8) + 1;
+  if (px0 < 0) px0 = 0;
+  if (py0 < 0) py0 = 0;
+  if (px1 > W - 1) px1 = W - 1;
+  if (py1 > Hh - 1) py1 = Hh - 1;
+  float invA = 1.0f / (float)A;
+  for (int32_t py = py0; py <= py1; ++py) {
+    for (int32_t px = px0; px <= px1; ++px) {
+      int64_t Px = 256 * (int64_t)px + 128, Py = 256 * (int64_t)py + 128;
+      int64_t E0 = edge_fn(X[1], Y[1], X[2], Y[2], Px, Py);
+      int64_t E1 = edge_fn(X[2], Y[2], X[0], Y[0], Px, Py);
+      int64_t E2 = edge_fn(X[0], Y[0], X[1], Y[1], Px, Py);
+      if (!(edge_in(E0, X[1], Y[1], X[2], Y[2]) && edge_in(E1, X[2], Y[2], X[0], Y[0]) &&
+            edge_in(E2, X[0], Y[0], X[1], Y[1])))
+        continue;
+      size_t pix = (size_t)py * W + px;
+      if (cover) cover[pix] += 1;
+      /* E0 weights vertex 0, E1 vertex 1, E2 vertex 2 */
+      float zz = (((float)E0 * z[0] + (float)E1 * z[1]) + (float)E2 * z[2]) * invA;
+      uint32_t D = (uint32_t)rintf(fminf(fmaxf(zz, 0.0f), 1.0f) * 16777215.0f);
+      uint64_t key = ((uint64_t)D << 32) | prim;
+      if (key < keys[pix]) keys[pix] = key;
+    }
+  }
+}
+
+int oracle_render_image(int32_t n, const uint8_t* type, const float* size,
+                        const uint8_t* albedo, const float* pos, const float* quat,
+                        const float* vp, int32_t W, int32_t H, const oracle_render_params* rp,
+                        uint8_t* rgb, uint32_t* depth, int32_t* winner, int32_t* cover) {
+  size_t npix = (size_t)W * (size_t)H;
+  uint64_t* keys = (uint64_t*)malloc(sizeof(uint64_t) * (npix ? npix : 1));
+  if (!keys) return -1;
+  for (size_t i = 0; i < npix; ++i) keys[i] = UINT64_MAX;
+  if (cover) memset(cover, 0, sizeof(int32_t) * npix);
+
+  /* prim ids: 0..ground_nf-1 the ground, then each body's faces in order */
+  uint32_t prim = 0;
+  for (int f = 0; f < rp->ground_nf; ++f, ++prim) {
+    const int32_t* fi = rp->ground_f + 3 * f;
+    raster_tri(rp->ground_v + 3 * fi[0], rp->ground_v + 3 * fi[1], rp->ground_v + 3 * fi[2],
+               prim, vp, W, H, rp, keys, cover);
+  }
+  for (int32_t b = 0; b < n; ++b) {
+    float R[9];
+    quat_mat(quat + 4 * b, R);
+    v3 p = load3(pos, b);
+    float s = size[b];
+    const float* tv = type[b] ? rp->cube_v : rp->sphere_v;
+    const int32_t* tf = type[b] ? rp->cube_f : rp->sphere_f;
+    int32_t nf = type[b] ? rp->cube_nf : rp->sphere_nf;
+    for (int f = 0; f < nf; ++f, ++prim) {
+      float wv[3][3];
+      for (int k = 0; k < 3; ++k) {
+        v3 t = load3(tv, tf[3 * f + k]);
+        v3 w = add(p, mat_vec(R, scl(t, s)));
+        wv[k][0] = w.x; wv[k][1] = w.y; wv[k][2] = w.z;
+      }
+      raster_tri(wv[0], wv[1], wv[2], prim, vp, W, H, rp, keys, cover);
+    }
+  }
+
+  /* Lambert shading of each pixel's winner */
+  v3 L = mk(rp->light[0], rp->light[1], rp->light[2]);
+  for (size_t i = 0; i < npix; ++i) {
+    uint64_t key = keys[i];
+    if (key == UINT64_MAX) {
+      rgb[3 * i] = rgb[3 * i + 1] = rgb[3 * i + 2] = 0;
+      depth[i] = 0xFFFFFFFFu;
+      if (winner) winner[i] = -1;
+      continue;
+    }
+    uint32_t pr = (uint32_t)(key & 0xFFFFFFFFu);
+    depth[i] = (uint32_t)(key >> 32);
+    if (winner) winner[i] = (int32_t)pr;
+    v3 nrm;
+    float alb[3];
+    if (pr < (uint32_t)rp->ground_nf) {
+      nrm = mk(0.0f, 0.0f, 1.0f);
+      alb[0] = alb[1] = alb[2] = rp->ground_albedo;
+    } else {
+      uint32_t rem = pr - (uint32_t)rp->ground_nf;
+      int32_t b = 0;
+      for (;;) {
+        uint32_t nf = (uint32_t)(type[b] ? rp->cube_nf : rp->sphere_nf);
+        if (rem < nf) break;
+        rem -= nf;
+        ++b;
+      }
+      float R[9];
+      quat_mat(quat + 4 * b, R);
+      nrm = mat_vec(R, load3(type[b] ? rp->cube_n : rp->sphere_n, (int32_t)rem));
+      for (int c = 0; c < 3; ++c) alb[c] = rp->palette[3 * albedo[b] + c];
+    }
+    float l = fmaxf(0.0f, dot(nrm, L));
+    for (int c = 0; c < 3; ++c) {
+      float col = alb[c] * (0.2f + 0.8f * l);
+      rgb[3 * i + c] = (uint8_t)fminf(255.0f, rintf(col * 255.0f));
+    }
+  }
+  free(keys);
+  return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Multi-threaded batch driver (whole envs per thread)
+ * ------------------------------------------------------------------------- */
+
+typedef struct {
+  int32_t tid, nthreads, n_envs, n_steps, do_render;
+  const int32_t* body_off; const uint8_t* type; const float *size, *rbound, *inv_m, *inv_I;
+  const uint8_t* albedo; float *pos, *vel, *quat, *omega;
+  const oracle_phys_params* prm;
+  const int32_t* cam_off; const float* cam_vp; const int32_t *cam_w, *cam_h;
+  const int64_t* img_off; const oracle_render_params* rp; uint8_t* rgb; uint32_t* depth;
+  int status;
+} batch_job;
+
+static void* batch_worker(void* arg) {
+  batch_job* j = (batch_job*)arg;
+  for (int32_t e = j->tid; e < j->n_envs; e += j->nthreads) {
+    int32_t b0 = j->body_off[e], nb = j->body_off[e + 1] - b0;
+    for (int32_t t = 0; t < j->n_steps; ++t) {
+      int st = oracle_step_env(nb, j->type + b0, j->size + b0, j->rbound + b0, j->inv_m + b0,
+                               j->inv_I + b0, j->pos + 3 * b0, j->vel + 3 * b0,
+                               j->quat + 4 * b0, j->omega + 3 * b0, j->prm, NULL, 0, NULL);
+      if (st && !j->status) j->status = st;
+      if (!j->do_render) continue;
+      for (int32_t c = j->cam_off[e]; c < j->cam_off[e + 1]; ++c) {
+        int64_t o = j->img_off[c];
+        oracle_render_image(nb, j->type + b0, j->size + b0, j->albedo + b0, j->pos + 3 * b0,
+                            j->quat + 4 * b0, j->cam_vp + 16 * c, j->cam_w[c], j->cam_h[c],
+                            j->rp, j->rgb + 3 * o, j->depth + o, NULL, NULL);
+      }
+    }
+  }
+  return NULL;
+}
+
+int oracle_run_batch(int32_t n_envs, const int32_t* body_off, const uint8_t* type,
+                     const float* size, const float* rbound, const float* inv_m,
+                     const float* inv_I, const uint8_t* albedo, float* pos, float* vel,
+                     float* quat, float* omega, const oracle_phys_params* prm,
+                     const int32_t* cam_off, const float* cam_vp, const int32_t* cam_w,
+                     const int32_t* cam_h, const int64_t* img_off,
+                     const oracle_render_params* rp, uint8_t* rgb, uint32_t* depth,
+                     int32_t n_steps, int32_t nthreads, int32_t do_render) {
+  if (nthreads < 1) nthreads = 1;
+  batch_job* jobs = (batch_job*)calloc((size_t)nthreads, sizeof(batch_job));
+  pthread_t* th = (pthread_t*)calloc((size_t)nthreads, sizeof(pthread_t));
+  for (int t = 0; t < nthreads; ++t) {
+    batch_job* j = &jobs[t];
+    j->tid = t; j->nthreads = nthreads; j->n_envs = n_envs; j->n_steps = n_steps;
+    j->do_render = do_render;
+    j->body_off = body_off; j->type = type; j->size = size; j->rbound = rbound;
+    j->inv_m = inv_m; j->inv_I = inv_I; j->albedo = albedo; j->pos = pos; j->vel = vel;
+    j->quat = quat; j->omega = omega; j->prm = prm; j->cam_off = cam_off; j->cam_vp = cam_vp;
+    j->cam_w = cam_w; j->cam_h = cam_h; j->img_off = img_off; j->rp = rp; j->rgb = rgb;
+    j->depth = depth;
+    pthread_create(&th[t], NULL, batch_worker, j);
+  }
+  int status = 0;
+  for (int t = 0; t < nthreads; ++t) {
+    pthread_join(th[t], NULL);
+    if (jobs[t].status && !status) status = jobs[t].status;
+  }
+  free(jobs);
+  free(th);
+  return status;
+}

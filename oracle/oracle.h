@@ -1,0 +1,126 @@
+/*
+ * CPU oracle of the batched embodied-AI step: a rigid-body physics step and a
+ * software rasterizer, plain single-threaded C, IEEE binary32 throughout.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the slow, obviously-correct reference
+ * that the HIP path is checked against.  Only the test suite, the smoke check
+ * and the CPU-baseline leg of the benchmark may load it; the product library
+ * never does.  It shares no code with the HIP path.
+ *
+ * Build: gcc -O2 -ffp-contract=off (no fast-math): every expression is
+ * evaluated exactly as written, left to right, with correctly rounded
+ * division and square root and round-to-nearest-even rintf.
+ *
+ * The paper (VUDA, arXiv 2605.01352) treats the physics engine and the
+ * renderer as black boxes (Background, Workload Characterization) and states
+ * no algorithm for either; the computation here follows the readings listed
+ * in the project's design notes: penalty (spring-dashpot) contact with
+ * semi-implicit Euler, and an edge-function rasterizer with 24.8 fixed point,
+ * a top-left fill rule and a (depth, primitive id) z-test.
+ */
+#ifndef VUDA_ORACLE_H
+#define VUDA_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORACLE_GROUND 0xFFFF
+#define ORACLE_MAX_POINTS 16
+
+/* Physics parameters: dt, substeps, contact stiffness k, damping c, gravity. */
+typedef struct {
+  float dt;
+  int32_t substeps;
+  float k;
+  float c;
+  float g[3];
+} oracle_phys_params;
+
+/* Mesh templates (unit size) and shading constants. */
+typedef struct {
+  const float* sphere_v; const int32_t* sphere_f; const float* sphere_n;
+  int32_t sphere_nv, sphere_nf;
+  const float* cube_v; const int32_t* cube_f; const float* cube_n;
+  int32_t cube_nv, cube_nf;
+  const float* ground_v; const int32_t* ground_f;
+  int32_t ground_nf;
+  float light[3];
+  float palette[24];
+  float ground_albedo;
+  float near_w;     /* cull a triangle if any vertex has clip w below this */
+  float guard;      /* cull a triangle if any |screen coord| exceeds this  */
+} oracle_render_params;
+
+/* One contact point as the narrowphase reports it. */
+typedef struct {
+  float n[3];      /* unit normal; pushes body "A" along +n */
+  float delta;     /* penetration depth, > 0                */
+  float xc[3];     /* contact point                         */
+  int32_t a_is_first; /* 1 if A is the pair's first body     */
+} oracle_point;
+
+/*
+ * Advance one env by one step (`substeps` substeps).  Body arrays are the
+ * env's slices: pos/vel/omega [n][3], quat [n][4] (w,x,y,z), updated in place.
+ * If pairs != NULL, the sorted contact-pair set of every substep is written:
+ * pairs[s*pair_cap*2 + 2*k + {0,1}] = (i, j), j = ORACLE_GROUND for ground,
+ * and npairs[s] = its size.
+ * Returns 0; -1 if a pair list exceeds pair_cap; 2 if the new state holds a
+ * non-finite value.
+ */
+int oracle_step_env(int32_t n, const uint8_t* type, const float* size, const float* rbound,
+                    const float* inv_m, const float* inv_I, float* pos, float* vel,
+                    float* quat, float* omega, const oracle_phys_params* prm,
+                    int32_t* pairs, int32_t pair_cap, int32_t* npairs);
+
+/* Narrowphase of one body pair (i < j) or of body i with the ground
+ * (j = ORACLE_GROUND), evaluated on the given state.  Returns the number of
+ * contact points written to pts (at most ORACLE_MAX_POINTS). */
+int oracle_narrowphase(int32_t i, int32_t j, const uint8_t* type, const float* size,
+                       const float* pos, const float* quat, oracle_point* pts);
+
+/*
+ * Render one camera of one env.  rgb [H][W][3] u8, depth [H][W] u32 (24-bit
+ * unorm depth, 0xFFFFFFFF background).  winner [H][W] (prim id or -1) and
+ * cover [H][W] (number of covering, non-culled triangles) may be NULL.
+ */
+int oracle_render_image(int32_t n, const uint8_t* type, const float* size,
+                        const uint8_t* albedo, const float* pos, const float* quat,
+                        const float* vp, int32_t W, int32_t H, const oracle_render_params* rp,
+                        uint8_t* rgb, uint32_t* depth, int32_t* winner, int32_t* cover);
+
+/* Screen-space setup of one triangle given world-space vertices: writes the
+ * snapped 24.8 vertices (in edge order) and depths; returns 1 if the triangle
+ * survives culling, 0 otherwise.  Exposed for the coverage pins. */
+int oracle_setup_triangle(const float* w0, const float* w1, const float* w2, const float* vp,
+                          int32_t W, int32_t H, float near_w, float guard,
+                          int32_t* X, int32_t* Y, float* z, int64_t* area);
+
+/* Coverage of one snapped triangle (vertices in edge order, area > 0) at a
+ * pixel centre (256*px+128, 256*py+128).  Returns 1 if covered. */
+int oracle_covers(const int32_t* X, const int32_t* Y, int32_t px, int32_t py);
+
+/*
+ * Whole-batch driver for the CPU baseline: runs n_steps of (physics step of
+ * every env, then render every camera of every env), sharding whole envs over
+ * nthreads POSIX threads; the per-env work is the single-threaded code above.
+ * Body arrays are global (env-major) with offsets body_off[E+1]; cameras
+ * cam_off[E+1], cam_vp [C][16], cam_w/cam_h [C]; image outputs are packed at
+ * pixel offsets img_off[C].  Returns 0 or the first nonzero per-env status.
+ */
+int oracle_run_batch(int32_t n_envs, const int32_t* body_off, const uint8_t* type,
+                     const float* size, const float* rbound, const float* inv_m,
+                     const float* inv_I, const uint8_t* albedo, float* pos, float* vel,
+                     float* quat, float* omega, const oracle_phys_params* prm,
+                     const int32_t* cam_off, const float* cam_vp, const int32_t* cam_w,
+                     const int32_t* cam_h, const int64_t* img_off,
+                     const oracle_render_params* rp, uint8_t* rgb, uint32_t* depth,
+                     int32_t n_steps, int32_t nthreads, int32_t do_render);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,71 @@
+"""Input generator: seeded reproducibility, batch-position independence and
+the distributions of the synthetic workloads (no GPU)."""
+import math
+
+import numpy as np
+
+from paper_2605_01352_amd import scenegen as sg
+
+
+def test_templates():
+    t = sg.templates()
+    assert t.sphere_v.shape == (42, 3) and t.sphere_f.shape == (80, 3)
+    assert t.cube_v.shape == (8, 3) and t.cube_f.shape == (12, 3)
+    np.testing.assert_allclose(np.linalg.norm(t.sphere_v, axis=1), 1.0, atol=1e-6)
+    # outward winding: face normals point away from the centre
+    for v, f, n in ((t.sphere_v, t.sphere_f, t.sphere_n), (t.cube_v, t.cube_f, t.cube_n)):
+        cen = v[f].mean(axis=1)
+        assert (np.einsum("ij,ij->i", cen, n) > 0).all()
+        # closed 2-manifold: every edge used twice, once per direction
+        edges = {}
+        for a, b, c in f:
+            for e in ((a, b), (b, c), (c, a)):
+                edges[e] = edges.get(e, 0) + 1
+        assert all(edges.get((b, a), 0) == 1 for (a, b) in edges)
+
+
+def test_splitmix64_reference_values():
+    # SplitMix64 seeded with 0 yields these first outputs (published sequence)
+    out = [int(sg.draw_u64(np.uint64(0), np.uint64(k))) for k in range(3)]
+    assert out == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def test_reproducible_and_position_independent():
+    a = sg.config_scene(2, n_envs=8)
+    b = sg.config_scene(2, n_envs=8)
+    for k in ("pos", "quat", "size"):
+        assert np.array_equal(getattr(a, k), getattr(b, k))
+    c = sg.config_scene(2, n_envs=3, env_gid0=5)
+    assert np.array_equal(c.pos, a.pos[a.body_off[5]:])
+
+
+def test_distributions_and_no_initial_overlap():
+    s = sg.config_scene(2, n_envs=64)
+    assert (s.counts() == 32).all()
+    sph = s.btype == sg.SPHERE
+    assert sph.sum() == s.n_bodies // 2
+    assert s.size[sph].min() >= 0.05 and s.size[sph].max() <= 0.15
+    assert s.size[~sph].min() >= 0.03 and s.size[~sph].max() <= 0.12
+    for e in range(s.n_envs):
+        b0, b1 = s.body_off[e], s.body_off[e + 1]
+        p = s.pos[b0:b1].astype(np.float64)
+        r = s.rbound[b0:b1].astype(np.float64)
+        d = np.linalg.norm(p[:, None] - p[None], axis=2)
+        np.fill_diagonal(d, 10)
+        assert (d > r[:, None] + r[None]).all()
+        assert (np.abs(p[:, :2]) <= 0.5).all() and (p[:, 2] >= r).all()
+    q = s.quat.astype(np.float64)
+    np.testing.assert_allclose(np.linalg.norm(q, axis=1), 1.0, atol=1e-6)
+    s4 = sg.config_scene(4, n_envs=400)
+    c = s4.counts()
+    assert c.min() >= 4 and c.max() <= 128 and abs(c.mean() - 24) < 1.0
+    assert set(np.unique(s4.cam_w)) == {64, 128, 256}
+
+
+def test_serving_requests():
+    reqs = sg.serving_requests(duration_s=20.0)
+    assert 800 <= len(reqs) <= 1200
+    ne = np.array([r.n_envs for r in reqs])
+    assert ne.min() >= 16 and ne.max() <= 512
+    assert abs(np.log(ne).mean() - (math.log(16) + math.log(512)) / 2) < 0.15
+    assert all(50 <= r.horizon <= 500 and 8 <= r.n_bodies <= 64 for r in reqs)

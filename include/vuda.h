@@ -1,0 +1,263 @@
+/*
+ * vuda.h -- C ABI of the MI355X co-scheduled physics + render step loop.
+ *
+ * The loop being accelerated is the phased step of a batched embodied-AI
+ * simulator: a physics step (compute) followed by a camera render of every
+ * environment (graphics), which the paper shows leaves one kind of GPU
+ * resource idle in each phase (Background, Workload Characterization).  Its
+ * remedy is to run the two phases spatially side by side on one GPU over a
+ * shared address space with no copy between them (Introduction; System
+ * Mechanisms).  On gfx950 both phases are HIP kernels in one process: the
+ * render kernel reads the physics state buffer in place, and the spatial
+ * partition is a pair of CU-masked HIP streams.
+ *
+ * The entry points mirror the paper's interface table (VUDA Programming
+ * Interface, API Surface, Table 1):
+ *   vuda_cosched(split)        ~ CUstream_bind / CUstream_unbind
+ *   vuda_step / vuda_render    ~ step_async / render_async (enqueue, return)
+ *   vuda_wait(phase)           ~ wait_step / wait_render
+ * and add world creation, result fetch and the serving admission calls.
+ *
+ * Conventions shared by every call:
+ *  - Return value: VUDA_OK (0) or a negative VUDA_E* code; the thread-local
+ *    detail is vuda_last_error_message().  No C++ exception crosses the ABI.
+ *  - Device faults and kernel-detected conditions (non-finite state, contact
+ *    or bin capacity overflow) are asynchronous and surface at the next
+ *    vuda_wait / vuda_fetch of the world.
+ *  - A world is used from one host thread at a time.
+ *  - Host pointers passed in are read during the call only; the library
+ *    copies what it keeps.
+ */
+#ifndef VUDA_H
+#define VUDA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------ */
+#define VUDA_OK         0
+#define VUDA_EINVAL    -1  /* malformed argument or descriptor              */
+#define VUDA_ENOMEM    -2  /* device allocation failed or HBM budget exceeded */
+#define VUDA_EHIP      -3  /* a HIP runtime call failed (code in message)    */
+#define VUDA_ENUMERIC  -4  /* a physics step produced a non-finite state     */
+#define VUDA_EOVERFLOW -5  /* contact-pair or bin capacity exceeded          */
+#define VUDA_EBUSY     -6  /* slots or budget not available right now        */
+
+/* ---- phases (vuda_wait, vuda_get_stream) ------------------------------- */
+#define VUDA_PHASE_STEP   1
+#define VUDA_PHASE_RENDER 2
+#define VUDA_PHASE_ALL    3
+
+/* ---- vuda_fetch selectors ---------------------------------------------- */
+#define VUDA_FETCH_STATE    0 /* float [n_bodies][13]: px py pz vx vy vz qw qx qy qz wx wy wz */
+#define VUDA_FETCH_RGB      1 /* uint8 per camera [H][W][3], cameras in order           */
+#define VUDA_FETCH_DEPTH    2 /* uint32 per camera [H][W] (24-bit unorm; 0xFFFFFFFF = none) */
+#define VUDA_FETCH_CONTACTS 3 /* int32 per env [substeps][1 + 2*pair_cap]: count, then
+                                 (i, j) pairs sorted, ground j = 0xFFFF (debug worlds)   */
+#define VUDA_FETCH_WINNERS  4 /* int32 per camera [H][W]: winning primitive id, -1 none
+                                 (debug worlds)                                        */
+#define VUDA_FETCH_COVERAGE 5 /* int32 per camera [H][W]: covering triangles (debug)    */
+#define VUDA_FETCH_FLAGS    6 /* uint32 per env: bit0 non-finite, bit1 contact overflow,
+                                 bit2 bin overflow                                     */
+
+/* ---- world flags -------------------------------------------------------- */
+#define VUDA_FLAG_DEBUG 1u  /* keep contact sets, winners and coverage for fetch */
+
+typedef struct vuda_world vuda_world;
+
+/* Optional device allocator (e.g. PyTorch's caching allocator).  alloc
+ * returns device memory of at least `bytes` (256-byte aligned) or NULL. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* ptr, void* ctx);
+  void* ctx;
+} vuda_allocator;
+
+/* Physics constants: step dt [s] split in `substeps` substeps of dt/substeps;
+ * penalty contact f = max(0, k*delta - c*v_n); gravity [m/s^2]. */
+typedef struct {
+  float dt;
+  int32_t substeps;
+  float k_contact;
+  float c_damp;
+  float gravity[3];
+} vuda_phys_params;
+
+/* Unit mesh templates and shading constants.  Faces are vertex-index
+ * triples wound counter-clockwise seen from outside; normals are per face. */
+typedef struct {
+  const float* sphere_v; int32_t sphere_nv;   /* [nv][3], nv <= 64         */
+  const int32_t* sphere_f; const float* sphere_n; int32_t sphere_nf; /* nf <= 128 */
+  const float* cube_v; int32_t cube_nv;       /* [nv][3], nv <= 64         */
+  const int32_t* cube_f; const float* cube_n; int32_t cube_nf;
+  const float* ground_v; int32_t ground_nv;   /* world-space ground polygon    */
+  const int32_t* ground_f; int32_t ground_nf;
+  float light[3];        /* unit direction towards the light */
+  float palette[24];     /* 8 RGB albedos, indexed by body albedo index */
+  float ground_albedo;
+  float near_w;          /* triangles with a vertex at clip w < near_w are culled */
+  float guard;           /* ... or with |screen coordinate| > guard (pixels)      */
+} vuda_render_desc;
+
+/*
+ * Per-env content.  Bodies of env e are body_off[e] .. body_off[e+1]-1
+ * (at most 128 per env); cameras cam_off[e] .. cam_off[e+1]-1.
+ * Body arrays: type (0 sphere, 1 cube), size (radius or half-extent),
+ * rbound (bounding-sphere radius), inv_m, inv_I (isotropic), albedo
+ * (palette index 0..7), pos/vel/omega [B][3], quat [B][4] (w,x,y,z).
+ * Cameras: vp [C][16] row-major view-projection (clip = vp * [x y z 1]^T,
+ * depth in [0,1]), w/h in pixels (1..4096).
+ */
+typedef struct {
+  int32_t n_envs;
+  const int32_t* body_off;
+  const uint8_t* type; const float* size; const float* rbound;
+  const float* inv_m; const float* inv_I; const uint8_t* albedo;
+  const float* pos; const float* vel; const float* quat; const float* omega;
+  const int32_t* cam_off; const float* cam_vp; const int32_t* cam_w; const int32_t* cam_h;
+} vuda_env_batch;
+
+/*
+ * World descriptor.  `initial` holds the envs created with the world (may
+ * have n_envs = 0 for a serving world that admits envs later).  The
+ * capacities reserve room for envs admitted later: 0 means "exactly the
+ * initial envs".  hbm_budget (bytes, 0 = unlimited) bounds the device arena.
+ * pair_cap is the per-env, per-substep capacity of the debug contact sets.
+ */
+typedef struct {
+  vuda_phys_params phys;
+  vuda_render_desc render;
+  vuda_env_batch initial;
+  uint32_t flags;          /* VUDA_FLAG_* */
+  int32_t cap_envs;        /* max env slots                  */
+  int64_t cap_bodies;      /* max bodies over all slots      */
+  int32_t cap_cams;        /* max cameras over all slots     */
+  int64_t cap_pixels;      /* max pixels over all cameras    */
+  int32_t pair_cap;        /* debug contact-set capacity (default 1024) */
+  uint64_t hbm_budget;
+} vuda_world_desc;
+
+/* Create a world: validates the descriptor, allocates one device arena
+ * (through `alloc` if non-NULL, else hipMalloc), uploads static data and
+ * the initial state, and creates its streams on the current HIP device.
+ * Errors: VUDA_EINVAL (descriptor), VUDA_ENOMEM (allocation or budget), no
+ * partial world is left behind. */
+int vuda_create_world(const vuda_world_desc* desc, const vuda_allocator* alloc, vuda_world** out);
+
+/* Wait for all work of the world, then free its device memory and streams. */
+int vuda_destroy_world(vuda_world* w);
+
+/*
+ * Co-scheduling switch (the paper's stream bind/unbind).  0 < cu_split < 1:
+ * the step phase runs on a stream restricted to that fraction of the CUs and
+ * the render phase on a stream restricted to the rest (hipExtStreamCreate-
+ * WithCUMask, balanced over the XCDs); cu_split == 2 runs them on two
+ * unmasked streams; cu_split <= 0 or == 1 restores the serialized path (one
+ * stream, every phase in enqueue order).  Changing it only moves work
+ * between CUs: outputs are bit-identical in every mode.  Drains the world
+ * before switching.
+ */
+int vuda_cosched(vuda_world* w, float cu_split);
+
+/*
+ * Enqueue `nsteps` physics steps of envs [env_lo, env_hi) and return (the
+ * paper's step_async).  Step t of an env reads its state buffer t%2 and
+ * writes (t+1)%2.  Dependencies are stream-ordered: the step waits for the
+ * last enqueued step of the world (state read) and the last enqueued render
+ * (which may read the buffer being overwritten).  All envs of the range must
+ * have taken the same number of steps modulo 2 (VUDA_EINVAL otherwise).
+ */
+int vuda_step(vuda_world* w, int32_t env_lo, int32_t env_hi, int32_t nsteps);
+
+/*
+ * Enqueue the render of every camera of envs [env_lo, env_hi) from their
+ * latest enqueued state (the paper's render_async): waits for the last
+ * enqueued step that writes that state; may overlap a later step that only
+ * reads it (inter-step pipelining).  Outputs RGB8 and 24-bit depth.
+ */
+int vuda_render(vuda_world* w, int32_t env_lo, int32_t env_hi);
+
+/* Block until the enqueued work of `phase` (VUDA_PHASE_*) is complete, then
+ * report asynchronous errors (VUDA_ENUMERIC, VUDA_EOVERFLOW, VUDA_EHIP). */
+int vuda_wait(vuda_world* w, int32_t phase);
+
+/*
+ * Copy results of envs [env_lo, env_hi) into dst (`dst_bytes` long; host
+ * memory, or device memory if dst_on_device).  Stream-ordered after all
+ * enqueued work, and synchronous on return.  The layout is given with the
+ * VUDA_FETCH_* selectors; fetch size queries: vuda_fetch_bytes.
+ */
+int vuda_fetch(vuda_world* w, int32_t what, int32_t env_lo, int32_t env_hi, void* dst,
+               size_t dst_bytes, int32_t dst_on_device);
+int vuda_fetch_bytes(vuda_world* w, int32_t what, int32_t env_lo, int32_t env_hi, size_t* bytes);
+
+/* Overwrite the current state of envs [env_lo, env_hi) with `src` (host,
+ * float [n][13] as VUDA_FETCH_STATE); used for checkpoint/resume and for
+ * parity checks from an identical input state. */
+int vuda_load_state(vuda_world* w, int32_t env_lo, int32_t env_hi, const float* src,
+                    size_t src_bytes);
+
+/* The HIP stream (hipStream_t) of a phase, for interop (e.g. an external
+ * stream object in PyTorch).  Valid until the next vuda_cosched call. */
+int vuda_get_stream(vuda_world* w, int32_t phase, void** hip_stream);
+
+/*
+ * Serving: admit the envs of one request into free slots of a world created
+ * with spare capacity.  The request's envs take `batch->n_envs` consecutive
+ * slots starting at *first_env; their state is written to buffer `parity`
+ * (so that they step in lockstep with envs of that parity).  Returns
+ * VUDA_EBUSY if no run of free slots, bodies or pixels is large enough or
+ * the HBM budget would be exceeded; nothing is changed then.
+ */
+int vuda_admit(vuda_world* w, const vuda_env_batch* batch, int32_t parity, int32_t* first_env);
+
+/* Free the slots [first_env, first_env + n_envs) of an admitted request
+ * (stream-ordered after all enqueued work on them). */
+int vuda_release(vuda_world* w, int32_t first_env, int32_t n_envs);
+
+/* World shape queries. */
+int vuda_world_info(vuda_world* w, int32_t* n_envs, int64_t* n_bodies, int32_t* n_cams,
+                    int64_t* n_pixels, uint64_t* arena_bytes);
+
+/*
+ * Launch-shape knobs (the autotuner's search space).  Keys:
+ *   VUDA_TUNE_RASTER_THREADS   raster workgroup size, multiple of 64 (default 256)
+ *   VUDA_TUNE_BIN_MIN          minimum LDS bin entries per raster workgroup (2048)
+ *   VUDA_TUNE_PHYS_PERSISTENT  0: one workgroup per env; n > 0: n resident
+ *                              workgroups pulling envs from a device queue
+ *   VUDA_TUNE_RASTER_PERSISTENT  the same for camera images
+ *   VUDA_TUNE_GRAPHS           1: each (phase, env range, parity) launch is
+ *                              captured once into a hipGraph and replayed
+ * None of them changes any output bit.  Returns VUDA_EINVAL for unknown keys
+ * or out-of-range values.
+ */
+#define VUDA_TUNE_RASTER_THREADS 1
+#define VUDA_TUNE_BIN_MIN 2
+#define VUDA_TUNE_PHYS_PERSISTENT 3
+#define VUDA_TUNE_RASTER_PERSISTENT 4
+#define VUDA_TUNE_GRAPHS 5
+int vuda_set_tuning(vuda_world* w, int32_t key, int32_t value);
+int vuda_get_tuning(vuda_world* w, int32_t key, int32_t* value);
+
+/*
+ * Placement probe: launches n_blocks one-wave workgroups on the stream of
+ * `phase` (VUDA_PHASE_STEP or VUDA_PHASE_RENDER), each spinning for about
+ * spin_us microseconds so that they spread over the CUs the stream may use,
+ * and writes per block the hardware XCC id, shader-engine id and CU id into
+ * out[3*i .. 3*i+2] (host memory, 3*n_blocks int32).  Used to verify the CU
+ * partition of vuda_cosched.  Synchronous.
+ */
+int vuda_probe_placement(vuda_world* w, int32_t phase, int32_t n_blocks, int32_t spin_us,
+                         int32_t* out);
+
+const char* vuda_strerror(int code);
+const char* vuda_last_error_message(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

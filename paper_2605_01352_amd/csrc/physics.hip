@@ -1,0 +1,693 @@
+// Rigid-body physics step for gfx950: one workgroup per env, one lane per body.
+//
+// One launch advances every listed env by one step of `substeps` substeps,
+// reading state buffer `parity` and writing buffer 1 - parity once; the
+// substeps run out of LDS and registers.  Per substep:
+//   1. publish p, v, omega and R(q) of every body to LDS;
+//   2. broadphase on a uniform grid hashed into 2^ceil(log2 2N) buckets
+//      (Teschner et al. 2003 XOR-prime hash).  A bucket is a bitset of
+//      bodies; each body ORs the buckets of its cell and the 13 cells of the
+//      half shell, tests the distance of every body found and records the
+//      pair (i < j) in a per-row bitset;
+//   3. candidate rows are compacted into a pair list sorted by (i, j) with a
+//      workgroup prefix scan of the row popcounts;
+//   4. narrowphase over the list, one pair per lane; contacts are compacted
+//      (wave ballot + prefix) into a contact list that stays sorted, holding
+//      the pair's summed force and both bodies' torques;
+//   5. each body gathers its pairs in sorted order (pairs (i, b) for i < b,
+//      then (b, j), then the ground), so every sum is formed in a fixed
+//      order independent of scheduling;
+//   6. semi-implicit Euler.
+// No floating-point atomics are used; results are bit-reproducible.
+#include "vuda_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace vuda {
+namespace {
+
+struct f3 {
+  float x, y, z;
+};
+__device__ __forceinline__ f3 mk(float x, float y, float z) { return f3{x, y, z}; }
+__device__ __forceinline__ f3 add(f3 a, f3 b) { return mk(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ f3 sub(f3 a, f3 b) { return mk(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ f3 mul(f3 a, float s) { return mk(a.x * s, a.y * s, a.z * s); }
+__device__ __forceinline__ f3 neg(f3 a) { return mk(-a.x, -a.y, -a.z); }
+__device__ __forceinline__ float dot(f3 a, f3 b) { return (a.x * b.x + a.y * b.y) + a.z * b.z; }
+__device__ __forceinline__ f3 cross(f3 a, f3 b) {
+  return mk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+
+struct M3 {
+  float m[9];
+};
+__device__ __forceinline__ f3 rot(const M3& R, f3 v) {
+  return mk((R.m[0] * v.x + R.m[1] * v.y) + R.m[2] * v.z,
+            (R.m[3] * v.x + R.m[4] * v.y) + R.m[5] * v.z,
+            (R.m[6] * v.x + R.m[7] * v.y) + R.m[8] * v.z);
+}
+__device__ __forceinline__ f3 rotT(const M3& R, f3 v) {
+  return mk((R.m[0] * v.x + R.m[3] * v.y) + R.m[6] * v.z,
+            (R.m[1] * v.x + R.m[4] * v.y) + R.m[7] * v.z,
+            (R.m[2] * v.x + R.m[5] * v.y) + R.m[8] * v.z);
+}
+__device__ __forceinline__ M3 quat_to_rot(float w, float x, float y, float z) {
+  const float xx = x * x, yy = y * y, zz = z * z;
+  const float xy = x * y, xz = x * z, yz = y * z;
+  const float wx = w * x, wy = w * y, wz = w * z;
+  M3 R;
+  R.m[0] = 1.0f - 2.0f * (yy + zz);
+  R.m[1] = 2.0f * (xy - wz);
+  R.m[2] = 2.0f * (xz + wy);
+  R.m[3] = 2.0f * (xy + wz);
+  R.m[4] = 1.0f - 2.0f * (xx + zz);
+  R.m[5] = 2.0f * (yz - wx);
+  R.m[6] = 2.0f * (xz - wy);
+  R.m[7] = 2.0f * (yz + wx);
+  R.m[8] = 1.0f - 2.0f * (xx + yy);
+  return R;
+}
+
+// LDS image of one env.  NW = waves per workgroup = 64-body blocks per env.
+template <int NW>
+struct PhysLDS {
+  static constexpr int N = 64 * NW;
+  static constexpr int CAPC = 8 * N;  // candidate pairs
+  static constexpr int CAPK = 4 * N;  // contact pairs
+  float p[3][N];
+  float v[3][N];
+  float w[3][N];
+  float R[9][N];
+  float size[N];
+  float rb[N];
+  int32_t type[N];
+  uint64_t bucket[2 * N][NW];
+  uint64_t rowCand[N][NW];
+  uint64_t rowC[N][NW];
+  uint64_t colC[N][NW];
+  int32_t kstart[N];
+  int32_t gflag[N];
+  uint32_t cand[CAPC];
+  float kres[9][CAPK];  // SF xyz, Ti xyz, Tj xyz of each contact pair
+  int32_t scan[NW + 1];
+  float red[NW];
+  int32_t flag;
+  int32_t work;
+};
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Exclusive prefix sum over the workgroup (thread order); *total gets the sum.
+template <int NW>
+__device__ __forceinline__ int block_excl_scan(int v, int32_t* tmp, int* total) {
+  const int lane = lane_id();
+  int x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (NW == 1) {
+    *total = __shfl(x, 63, 64);
+    return x - v;
+  }
+  const int wv = threadIdx.x >> 6;
+  if (lane == 63) tmp[wv] = x;
+  __syncthreads();
+  int base = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    int t = tmp[k];
+    if (k < wv) base += t;
+    tot += t;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + x - v;
+}
+
+template <int NW>
+__device__ __forceinline__ float block_max(float v, float* tmp) {
+  float x = v;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x = fmaxf(x, __shfl_xor(x, d, 64));
+  if (NW == 1) return x;
+  if (lane_id() == 0) tmp[threadIdx.x >> 6] = x;
+  __syncthreads();
+  float m = tmp[0];
+#pragma unroll
+  for (int k = 1; k < NW; ++k) m = fmaxf(m, tmp[k]);
+  __syncthreads();
+  return m;
+}
+
+__device__ __forceinline__ uint32_t grid_hash(int cx, int cy, int cz, uint32_t mask) {
+  return ((uint32_t)cx * 73856093u ^ (uint32_t)cy * 19349663u ^ (uint32_t)cz * 83492791u) & mask;
+}
+
+struct Point {
+  f3 n;
+  float delta;
+  f3 xc;
+};
+
+template <int NW>
+__device__ __forceinline__ f3 ldsP(const PhysLDS<NW>& s, int b) {
+  return mk(s.p[0][b], s.p[1][b], s.p[2][b]);
+}
+template <int NW>
+__device__ __forceinline__ f3 ldsV(const PhysLDS<NW>& s, int b) {
+  return mk(s.v[0][b], s.v[1][b], s.v[2][b]);
+}
+template <int NW>
+__device__ __forceinline__ f3 ldsW(const PhysLDS<NW>& s, int b) {
+  return mk(s.w[0][b], s.w[1][b], s.w[2][b]);
+}
+template <int NW>
+__device__ __forceinline__ M3 ldsR(const PhysLDS<NW>& s, int b) {
+  M3 R;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) R.m[k] = s.R[k][b];
+  return R;
+}
+
+// Sum of one pair's contact forces, accumulated in point order.
+struct PairAcc {
+  f3 SF, Ti, Tj;
+  int npts;
+};
+
+// Add the force of one contact point; a_first: body A (pushed along +n) is
+// the pair's first body.
+__device__ __forceinline__ void add_point(PairAcc& acc, const Point& pt, bool a_first, f3 pi,
+                                          f3 vi, f3 wi, f3 pj, f3 vj, f3 wj, bool ground,
+                                          const PhysConsts& pc) {
+  const f3 pa = a_first ? pi : pj, va = a_first ? vi : vj, wa = a_first ? wi : wj;
+  const f3 pb = a_first ? pj : pi, vb = a_first ? vj : vi, wb = a_first ? wj : wi;
+  const f3 velA = add(va, cross(wa, sub(pt.xc, pa)));
+  f3 vrel;
+  if (ground) {
+    vrel = velA;
+  } else {
+    const f3 velB = add(vb, cross(wb, sub(pt.xc, pb)));
+    vrel = sub(velA, velB);
+  }
+  const float vn = dot(vrel, pt.n);
+  float f = pc.k * pt.delta - pc.c * vn;
+  if (f < 0.0f) f = 0.0f;
+  const f3 F = mul(pt.n, f);
+  const f3 Fi = a_first ? F : neg(F);
+  acc.SF = add(acc.SF, Fi);
+  acc.Ti = add(acc.Ti, cross(sub(pt.xc, pi), Fi));
+  if (!ground) acc.Tj = add(acc.Tj, cross(sub(pt.xc, pj), neg(Fi)));
+  acc.npts += 1;
+}
+
+__device__ __forceinline__ f3 corner(f3 p, const M3& R, float a, int k) {
+  const f3 w = mk((k & 1) ? a : -a, (k & 2) ? a : -a, (k & 4) ? a : -a);
+  return add(p, rot(R, w));
+}
+
+// argmin over axes of (a - |u_axis|), lowest axis on ties
+__device__ __forceinline__ int min_axis(f3 u, float a, float* depth) {
+  const float d0 = a - fabsf(u.x), d1 = a - fabsf(u.y), d2 = a - fabsf(u.z);
+  int m = 0;
+  float dm = d0;
+  if (d1 < dm) { m = 1; dm = d1; }
+  if (d2 < dm) { m = 2; dm = d2; }
+  *depth = dm;
+  return m;
+}
+
+__device__ __forceinline__ f3 axis_unit(int m, float sgn) {
+  return mk(m == 0 ? sgn : 0.0f, m == 1 ? sgn : 0.0f, m == 2 ? sgn : 0.0f);
+}
+
+__device__ __forceinline__ float pick(f3 u, int m) { return m == 0 ? u.x : (m == 1 ? u.y : u.z); }
+
+// Sphere (centre c, radius r) against cube (p, R, a); normal from the cube to
+// the sphere.  Returns true on contact.
+__device__ __forceinline__ bool sphere_cube(f3 c, float r, f3 p, const M3& R, float a, Point* pt) {
+  const f3 u = rotT(R, sub(c, p));
+  const f3 e = mk(fminf(fmaxf(u.x, -a), a), fminf(fmaxf(u.y, -a), a), fminf(fmaxf(u.z, -a), a));
+  const f3 rv = sub(u, e);
+  const float L2 = dot(rv, rv);
+  if (!(L2 < r * r)) return false;
+  f3 nl;
+  float delta;
+  if (L2 > 0.0f) {
+    const float L = sqrtf(L2);
+    nl = mk(rv.x / L, rv.y / L, rv.z / L);
+    delta = r - L;
+  } else {
+    float dm;
+    const int m = min_axis(u, a, &dm);
+    nl = axis_unit(m, pick(u, m) >= 0.0f ? 1.0f : -1.0f);
+    delta = r + dm;
+  }
+  pt->n = rot(R, nl);
+  pt->delta = delta;
+  pt->xc = add(p, rot(R, e));
+  return true;
+}
+
+// Narrowphase + force sum of body pair (i, j), i < j.
+template <int NW>
+__device__ __noinline__ PairAcc pair_forces(const PhysLDS<NW>& s, int i, int j,
+                                            const PhysConsts& pc) {
+  PairAcc acc;
+  acc.SF = mk(0.0f, 0.0f, 0.0f);
+  acc.Ti = acc.SF;
+  acc.Tj = acc.SF;
+  acc.npts = 0;
+  const f3 pi = ldsP(s, i), pj = ldsP(s, j);
+  const f3 vi = ldsV(s, i), vj = ldsV(s, j);
+  const f3 wi = ldsW(s, i), wj = ldsW(s, j);
+  const int ti = s.type[i], tj = s.type[j];
+  const float si = s.size[i], sj = s.size[j];
+  Point pt;
+  if (ti == 0 && tj == 0) {
+    const f3 d = sub(pi, pj);
+    const float d2 = dot(d, d);
+    const float sr = si + sj;
+    if (d2 < sr * sr) {
+      const float L = sqrtf(d2);
+      pt.n = L > 0.0f ? mk(d.x / L, d.y / L, d.z / L) : mk(0.0f, 0.0f, 1.0f);
+      pt.delta = sr - L;
+      pt.xc = add(pj, mul(pt.n, sj - 0.5f * pt.delta));
+      add_point(acc, pt, true, pi, vi, wi, pj, vj, wj, false, pc);
+    }
+  } else if (ti == 0) {
+    const M3 Rj = ldsR(s, j);
+    if (sphere_cube(pi, si, pj, Rj, sj, &pt)) add_point(acc, pt, true, pi, vi, wi, pj, vj, wj, false, pc);
+  } else if (tj == 0) {
+    const M3 Ri = ldsR(s, i);
+    if (sphere_cube(pj, sj, pi, Ri, si, &pt)) add_point(acc, pt, false, pi, vi, wi, pj, vj, wj, false, pc);
+  } else {
+    const M3 Ri = ldsR(s, i), Rj = ldsR(s, j);
+    // vertices of i inside j (A = i), then vertices of j inside i (A = j)
+#pragma unroll 1
+    for (int side = 0; side < 2; ++side) {
+      const f3 pa = side ? pj : pi, pb = side ? pi : pj;
+      const M3& Ra = side ? Rj : Ri;
+      const M3& Rb = side ? Ri : Rj;
+      const float aa = side ? sj : si, ab = side ? si : sj;
+#pragma unroll 1
+      for (int k = 0; k < 8; ++k) {
+        const f3 vtx = corner(pa, Ra, aa, k);
+        const f3 u = rotT(Rb, sub(vtx, pb));
+        if (fabsf(u.x) < ab && fabsf(u.y) < ab && fabsf(u.z) < ab) {
+          float dm;
+          const int m = min_axis(u, ab, &dm);
+          pt.n = rot(Rb, axis_unit(m, pick(u, m) >= 0.0f ? 1.0f : -1.0f));
+          pt.delta = dm;
+          pt.xc = vtx;
+          add_point(acc, pt, side == 0, pi, vi, wi, pj, vj, wj, false, pc);
+        }
+      }
+    }
+  }
+  return acc;
+}
+
+// Ground contact of one body (its own lane).
+__device__ __forceinline__ PairAcc ground_forces(int type, float a, f3 p, f3 v, f3 w, const M3& R,
+                                                 const PhysConsts& pc) {
+  PairAcc acc;
+  acc.SF = mk(0.0f, 0.0f, 0.0f);
+  acc.Ti = acc.SF;
+  acc.Tj = acc.SF;
+  acc.npts = 0;
+  const f3 z3 = acc.SF;
+  Point pt;
+  pt.n = mk(0.0f, 0.0f, 1.0f);
+  if (type == 0) {
+    if (p.z < a) {
+      pt.delta = a - p.z;
+      pt.xc = mk(p.x, p.y, p.z - a);
+      add_point(acc, pt, true, p, v, w, z3, z3, z3, true, pc);
+    }
+  } else {
+#pragma unroll 1
+    for (int k = 0; k < 8; ++k) {
+      const f3 vtx = corner(p, R, a, k);
+      if (vtx.z < 0.0f) {
+        pt.delta = -vtx.z;
+        pt.xc = vtx;
+        add_point(acc, pt, true, p, v, w, z3, z3, z3, true, pc);
+      }
+    }
+  }
+  return acc;
+}
+
+__device__ __forceinline__ uint64_t below_mask(int b) {
+  return b >= 64 ? ~0ull : ((1ull << b) - 1ull);
+}
+
+template <int NW>
+__device__ __forceinline__ int popc_below(const uint64_t* row, int b) {
+  int c = 0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) c += __popcll(row[k] & below_mask(b - 64 * k < 0 ? 0 : b - 64 * k));
+  return c;
+}
+
+template <int NW>
+__device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc, int env,
+                         int parity) {
+  constexpr int N = PhysLDS<NW>::N;
+  const int tid = threadIdx.x;
+  const EnvDev ed = W.envs[env];
+  const int n = ed.n_bodies;
+  if (n <= 0) return;
+  const int b0 = ed.body_off;
+  const bool own = tid < n;
+  const int64_t cap = W.cap_bodies;
+  const float* in = W.state[parity];
+  float* out = W.state[parity ^ 1];
+  const int gb = b0 + (own ? tid : 0);
+
+  // owned body state in registers
+  f3 p = mk(0, 0, 0), v = p, w = p;
+  float qw = 1.0f, qx = 0.0f, qy = 0.0f, qz = 0.0f;
+  float inv_m = 0.0f, inv_I = 0.0f, a = 0.0f, rbv = 0.0f;
+  int ty = 0;
+  if (own) {
+    p = mk(in[PX * cap + gb], in[PY * cap + gb], in[PZ * cap + gb]);
+    v = mk(in[VX * cap + gb], in[VY * cap + gb], in[VZ * cap + gb]);
+    qw = in[QW * cap + gb]; qx = in[QX * cap + gb]; qy = in[QY * cap + gb]; qz = in[QZ * cap + gb];
+    w = mk(in[WX * cap + gb], in[WY * cap + gb], in[WZ * cap + gb]);
+    inv_m = W.inv_m[gb];
+    inv_I = W.inv_I[gb];
+    a = W.size[gb];
+    rbv = W.rbound[gb];
+    ty = W.type[gb];
+    s.size[tid] = a;
+    s.rb[tid] = rbv;
+    s.type[tid] = ty;
+  }
+  // grid cell edge: a little above the largest bounding diameter
+  const float rmax = block_max<NW>(own ? rbv : 0.0f, s.red);
+  const float inv_c = 1.0f / (2.0f * rmax * 1.000244140625f);
+  int tbits = 1;
+  while ((1 << tbits) < 2 * n) ++tbits;
+  const int T = 1 << tbits;
+  const uint32_t hmask = (uint32_t)(T - 1);
+  const f3 gvec = mk(pc.g[0], pc.g[1], pc.g[2]);
+  bool bad = false;
+
+  for (int sub_i = 0; sub_i < pc.substeps; ++sub_i) {
+    // 1. publish substep-start state
+    M3 R = quat_to_rot(qw, qx, qy, qz);
+    if (own) {
+      s.p[0][tid] = p.x; s.p[1][tid] = p.y; s.p[2][tid] = p.z;
+      s.v[0][tid] = v.x; s.v[1][tid] = v.y; s.v[2][tid] = v.z;
+      s.w[0][tid] = w.x; s.w[1][tid] = w.y; s.w[2][tid] = w.z;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) s.R[k][tid] = R.m[k];
+    }
+    for (int k = tid; k < T; k += N)
+#pragma unroll
+      for (int q = 0; q < NW; ++q) s.bucket[k][q] = 0ull;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      s.rowCand[tid][q] = 0ull;
+      s.rowC[tid][q] = 0ull;
+      s.colC[tid][q] = 0ull;
+    }
+    if (tid == 0) s.flag = 0;
+    // 2. broadphase: cells far from the origin fall back to testing all pairs
+    int cx = 0, cy = 0, cz = 0;
+    if (own) {
+      const float fx = floorf(p.x * inv_c), fy = floorf(p.y * inv_c), fz = floorf(p.z * inv_c);
+      if (!(fabsf(fx) < 1000.0f && fabsf(fy) < 1000.0f && fabsf(fz) < 1000.0f)) s.flag = 1;
+      cx = (int)fx; cy = (int)fy; cz = (int)fz;
+    }
+    __syncthreads();
+    const bool brute = s.flag != 0;
+    if (own && !brute) {
+      const uint32_t h = grid_hash(cx, cy, cz, hmask);
+      atomicOr((unsigned long long*)&s.bucket[h][tid >> 6], 1ull << (tid & 63));
+    }
+    __syncthreads();
+    if (own) {
+      uint64_t M[NW];
+      if (brute) {
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+          const int lo = 64 * q;
+          M[q] = n - lo >= 64 ? ~0ull : (n - lo <= 0 ? 0ull : ((1ull << (n - lo)) - 1ull));
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < NW; ++q) M[q] = 0ull;
+        // own cell and the 13 neighbours of the half shell
+#pragma unroll 1
+        for (int o = 0; o < 14; ++o) {
+          int dx, dy, dz;
+          if (o == 0) { dx = 0; dy = 0; dz = 0; }
+          else if (o <= 9) { dx = 1; dy = (o - 1) / 3 - 1; dz = (o - 1) % 3 - 1; }
+          else if (o <= 12) { dx = 0; dy = 1; dz = o - 11; }
+          else { dx = 0; dy = 0; dz = 1; }
+          const uint32_t h = grid_hash(cx + dx, cy + dy, cz + dz, hmask);
+#pragma unroll
+          for (int q = 0; q < NW; ++q) M[q] |= s.bucket[h][q];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < NW; ++q)
+        if (q == (tid >> 6)) M[q] &= ~(1ull << (tid & 63));
+#pragma unroll
+      for (int q = 0; q < NW; ++q) {
+        uint64_t m = M[q];
+        while (m) {
+          const int j = 64 * q + __ffsll((unsigned long long)m) - 1;
+          m &= m - 1ull;
+          const int lo = tid < j ? tid : j, hi = tid < j ? j : tid;
+          const f3 d = sub(ldsP(s, lo), ldsP(s, hi));
+          const float rs = s.rb[lo] + s.rb[hi];
+          if (dot(d, d) <= rs * rs)
+            atomicOr((unsigned long long*)&s.rowCand[lo][hi >> 6], 1ull << (hi & 63));
+        }
+      }
+    }
+    __syncthreads();
+    // 3. compaction of candidate rows into the sorted pair list
+    int ccount = 0;
+    if (own) {
+#pragma unroll
+      for (int q = 0; q < NW; ++q) ccount += __popcll(s.rowCand[tid][q]);
+    }
+    int ctotal;
+    const int cstart = block_excl_scan<NW>(ccount, s.scan, &ctotal);
+    if (own) {
+      int pos = cstart;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) {
+        uint64_t m = s.rowCand[tid][q];
+        while (m) {
+          const int j = 64 * q + __ffsll((unsigned long long)m) - 1;
+          m &= m - 1ull;
+          if (pos < PhysLDS<NW>::CAPC) s.cand[pos] = (uint32_t)tid | ((uint32_t)j << 16);
+          ++pos;
+        }
+      }
+    }
+    if (ctotal > PhysLDS<NW>::CAPC) bad = true;
+    __syncthreads();
+    // 4. narrowphase, one candidate per lane; contacts compacted in order
+    const int nc = ctotal < PhysLDS<NW>::CAPC ? ctotal : PhysLDS<NW>::CAPC;
+    int kbase = 0;
+    for (int c0 = 0; c0 < nc; c0 += N) {
+      const int k = c0 + tid;
+      bool contact = false;
+      PairAcc acc;
+      int i = 0, j = 0;
+      if (k < nc) {
+        const uint32_t pr = s.cand[k];
+        i = (int)(pr & 0xFFFFu);
+        j = (int)(pr >> 16);
+        acc = pair_forces<NW>(s, i, j, pc);
+        contact = acc.npts > 0;
+      }
+      int ktotal;
+      const int slot = kbase + block_excl_scan<NW>(contact ? 1 : 0, s.scan, &ktotal);
+      if (contact) {
+        if (slot < PhysLDS<NW>::CAPK) {
+          s.kres[0][slot] = acc.SF.x; s.kres[1][slot] = acc.SF.y; s.kres[2][slot] = acc.SF.z;
+          s.kres[3][slot] = acc.Ti.x; s.kres[4][slot] = acc.Ti.y; s.kres[5][slot] = acc.Ti.z;
+          s.kres[6][slot] = acc.Tj.x; s.kres[7][slot] = acc.Tj.y; s.kres[8][slot] = acc.Tj.z;
+        }
+        atomicOr((unsigned long long*)&s.rowC[i][j >> 6], 1ull << (j & 63));
+        atomicOr((unsigned long long*)&s.colC[j][i >> 6], 1ull << (i & 63));
+      }
+      kbase += ktotal;
+    }
+    if (kbase > PhysLDS<NW>::CAPK) bad = true;
+    __syncthreads();
+    // contact-list start of each row
+    int kcount = 0;
+    if (own) {
+#pragma unroll
+      for (int q = 0; q < NW; ++q) kcount += __popcll(s.rowC[tid][q]);
+    }
+    int ktot2;
+    const int kst = block_excl_scan<NW>(kcount, s.scan, &ktot2);
+    s.kstart[tid] = kst;
+    __syncthreads();
+    // 5. gather in sorted pair order, then the ground, then integrate
+    if (own) {
+      f3 F = mk(0.0f, 0.0f, 0.0f), Tq = F;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) {
+        uint64_t m = s.colC[tid][q];
+        while (m) {
+          const int i = 64 * q + __ffsll((unsigned long long)m) - 1;
+          m &= m - 1ull;
+          const int idx = s.kstart[i] + popc_below<NW>(s.rowC[i], tid);
+          if (idx < PhysLDS<NW>::CAPK) {
+            F = sub(F, mk(s.kres[0][idx], s.kres[1][idx], s.kres[2][idx]));
+            Tq = add(Tq, mk(s.kres[6][idx], s.kres[7][idx], s.kres[8][idx]));
+          }
+        }
+      }
+      {
+        int idx = kst;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+          uint64_t m = s.rowC[tid][q];
+          while (m) {
+            m &= m - 1ull;
+            if (idx < PhysLDS<NW>::CAPK) {
+              F = add(F, mk(s.kres[0][idx], s.kres[1][idx], s.kres[2][idx]));
+              Tq = add(Tq, mk(s.kres[3][idx], s.kres[4][idx], s.kres[5][idx]));
+            }
+            ++idx;
+          }
+        }
+      }
+      bool gcontact = false;
+      if (p.z < rbv) {
+        const PairAcc g = ground_forces(ty, a, p, v, w, R, pc);
+        if (g.npts > 0) {
+          gcontact = true;
+          F = add(F, g.SF);
+          Tq = add(Tq, g.Ti);
+        }
+      }
+      // semi-implicit Euler
+      const f3 acc = add(mul(F, inv_m), gvec);
+      v = add(v, mul(acc, pc.h));
+      p = add(p, mul(v, pc.h));
+      w = add(w, mul(mul(Tq, inv_I), pc.h));
+      const float dw = (-w.x * qx - w.y * qy) - w.z * qz;
+      const float dx = (w.x * qw + w.y * qz) - w.z * qy;
+      const float dy = (w.y * qw + w.z * qx) - w.x * qz;
+      const float dz = (w.z * qw + w.x * qy) - w.y * qx;
+      qw = qw + pc.hh * dw;
+      qx = qx + pc.hh * dx;
+      qy = qy + pc.hh * dy;
+      qz = qz + pc.hh * dz;
+      const float n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
+      const float inv = 1.0f / sqrtf(n2);
+      qw = qw * inv; qx = qx * inv; qy = qy * inv; qz = qz * inv;
+      s.gflag[tid] = gcontact ? 1 : 0;
+    }
+    __syncthreads();
+    if (W.contacts) {
+      // pairs of row tid in ascending j, then (tid, ground)
+      int cnt = 0;
+      bool gc = false;
+      if (own) {
+        gc = s.gflag[tid] != 0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) cnt += __popcll(s.rowC[tid][q]);
+        cnt += gc ? 1 : 0;
+      }
+      int tot;
+      const int off = block_excl_scan<NW>(cnt, s.scan, &tot);
+      int32_t* dst = W.contacts + ((int64_t)env * pc.substeps + sub_i) * (1 + 2 * W.pair_cap);
+      if (tid == 0) dst[0] = tot;
+      if (own) {
+        int pos = off;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+          uint64_t m = s.rowC[tid][q];
+          while (m) {
+            const int j = 64 * q + __ffsll((unsigned long long)m) - 1;
+            m &= m - 1ull;
+            if (pos < W.pair_cap) { dst[1 + 2 * pos] = tid; dst[2 + 2 * pos] = j; }
+            ++pos;
+          }
+        }
+        if (gc && pos < W.pair_cap) { dst[1 + 2 * pos] = tid; dst[2 + 2 * pos] = kGroundPair; }
+      }
+    }
+    __syncthreads();
+  }
+  if (own) {
+    out[PX * cap + gb] = p.x; out[PY * cap + gb] = p.y; out[PZ * cap + gb] = p.z;
+    out[VX * cap + gb] = v.x; out[VY * cap + gb] = v.y; out[VZ * cap + gb] = v.z;
+    out[QW * cap + gb] = qw; out[QX * cap + gb] = qx; out[QY * cap + gb] = qy; out[QZ * cap + gb] = qz;
+    out[WX * cap + gb] = w.x; out[WY * cap + gb] = w.y; out[WZ * cap + gb] = w.z;
+    const bool fin = isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(v.x) &&
+                     isfinite(v.y) && isfinite(v.z) && isfinite(w.x) && isfinite(w.y) &&
+                     isfinite(w.z) && isfinite(qw) && isfinite(qx) && isfinite(qy) && isfinite(qz);
+    if (!fin) atomicOr(&W.env_flags[env], kFlagNonFinite);
+  }
+  if (bad && tid == 0) atomicOr(&W.env_flags[env], kFlagContactOverflow);
+}
+
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void physics_kernel(WorldDev W, PhysConsts pc, PhysLaunch L) {
+  __shared__ PhysLDS<NW> s;
+  if (L.persistent == 0) {
+    const int wi = blockIdx.x;
+    if (wi >= L.n_work) return;
+    step_env<NW>(s, W, pc, L.work[wi], L.parity);
+    return;
+  }
+  for (;;) {
+    if (threadIdx.x == 0) s.work = atomicAdd(L.queue, 1);
+    __syncthreads();
+    const int wi = s.work;
+    __syncthreads();
+    if (wi >= L.n_work) return;
+    step_env<NW>(s, W, pc, L.work[wi], L.parity);
+  }
+}
+
+__global__ void reset_queue_kernel(int32_t* q) { *q = 0; }
+
+}  // namespace
+
+hipError_t launch_reset_queue(int32_t* q, hipStream_t s) {
+  hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(1), 0, s, q);
+  return hipGetLastError();
+}
+
+hipError_t launch_physics(const WorldDev& w, const PhysConsts& pc, const PhysLaunch& l,
+                          hipStream_t s) {
+  if (l.n_work <= 0) return hipSuccess;
+  const int nw = l.max_bodies <= 64 ? 1 : 2;
+  for (int t = 0; t < l.nsteps; ++t) {
+    PhysLaunch lt = l;
+    lt.parity = (l.parity + t) & 1;
+    const int grid = l.persistent > 0 ? (l.persistent < l.n_work ? l.persistent : l.n_work) : l.n_work;
+    if (l.persistent > 0) {
+      hipError_t e = launch_reset_queue(l.queue, s);
+      if (e != hipSuccess) return e;
+    }
+    if (nw == 1)
+      hipLaunchKernelGGL(physics_kernel<1>, dim3(grid), dim3(64), 0, s, w, pc, lt);
+    else
+      hipLaunchKernelGGL(physics_kernel<2>, dim3(grid), dim3(128), 0, s, w, pc, lt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace vuda

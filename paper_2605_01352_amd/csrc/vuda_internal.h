@@ -1,0 +1,130 @@
+// Internal layout of a world in device memory, shared by the host runtime and
+// the HIP kernels of libvuda.  Everything here is structure-of-arrays over a
+// global body index (env-major, contiguous per env) so that the lane that
+// owns a body reads and writes its components with coalesced accesses.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vuda {
+
+constexpr int kStateComps = 13;  // px py pz vx vy vz qw qx qy qz wx wy wz
+enum StateComp { PX = 0, PY, PZ, VX, VY, VZ, QW, QX, QY, QZ, WX, WY, WZ };
+
+constexpr int kMaxBodies = 128;     // bodies per env
+constexpr int kMaxTplVerts = 64;    // vertices per template
+constexpr int kMaxTplFaces = 128;   // faces per template
+constexpr int kMaxGroundVerts = 8;
+constexpr int kMaxGroundFaces = 8;
+constexpr int kGroundPair = 0xFFFF;
+constexpr int kTile = 16;           // raster tile edge in pixels
+
+// env flags (device-side, sticky until fetched)
+constexpr uint32_t kFlagNonFinite = 1u;
+constexpr uint32_t kFlagContactOverflow = 2u;
+constexpr uint32_t kFlagBinOverflow = 4u;
+
+struct EnvDev {
+  int32_t body_off;   // first global body id
+  int32_t n_bodies;   // 0 = free slot
+  int32_t cam_off;    // first global camera id
+  int32_t n_cams;
+  int32_t n_verts;    // template vertices of all bodies + ground
+  int32_t n_tris;     // primitives: ground faces + template faces of all bodies
+};
+
+struct CamDev {
+  float vp[16];
+  int32_t w, h;
+  int64_t pix_off;    // first pixel of the image in the image arena
+  int32_t env;
+  int32_t pad;
+};
+
+// Mesh templates and shading constants (device copy of the descriptor).
+struct Templates {
+  float sphere_v[kMaxTplVerts][3];
+  float cube_v[kMaxTplVerts][3];
+  float ground_v[kMaxGroundVerts][3];
+  uint8_t sphere_f[kMaxTplFaces][3];
+  uint8_t cube_f[kMaxTplFaces][3];
+  uint8_t ground_f[kMaxGroundFaces][3];
+  float sphere_n[kMaxTplFaces][3];
+  float cube_n[kMaxTplFaces][3];
+  int32_t sphere_nv, sphere_nf, cube_nv, cube_nf, ground_nv, ground_nf;
+  float light[3];
+  float palette[8][3];
+  float ground_albedo;
+  float near_w;
+  float guard;
+};
+
+struct PhysConsts {
+  float h;        // dt / substeps
+  float hh;       // h / 2
+  float k, c;
+  float g[3];
+  int32_t substeps;
+};
+
+// Pointers into the world arena used by the kernels.
+struct WorldDev {
+  EnvDev* envs;
+  CamDev* cams;
+  // static per body
+  const uint8_t* type;
+  const uint8_t* albedo;
+  const float* size;
+  const float* rbound;
+  const float* inv_m;
+  const float* inv_I;
+  const int32_t* prim_base;  // env-local primitive id of the body's first face
+  const int32_t* vert_base;  // env-local vertex index of the body's first vertex
+  // dynamic state: state[buf][comp * cap_bodies + body]
+  float* state[2];
+  int64_t cap_bodies;
+  // images
+  uint8_t* rgb;
+  uint32_t* depth;
+  int32_t* winners;    // debug only (nullable)
+  int32_t* coverage;   // debug only (nullable)
+  // debug contact sets: per env [substeps][1 + 2*pair_cap]
+  int32_t* contacts;   // nullable
+  int32_t pair_cap;
+  uint32_t* env_flags;
+  const Templates* tpl;
+};
+
+// Host-side launchers (implemented next to the kernels).
+struct PhysLaunch {
+  const int32_t* work;     // env ids, LPT order
+  int32_t n_work;
+  int32_t max_bodies;      // over the listed envs
+  int32_t parity;          // buffer read; writes 1 - parity
+  int32_t nsteps;
+  int32_t persistent;      // 0: one workgroup per env; >0: that many resident workgroups
+  int32_t* queue;          // persistent work counter (one int), nullable otherwise
+};
+
+struct RasterLaunch {
+  const int32_t* work;     // camera ids, LPT order
+  int32_t n_work;
+  int32_t max_verts;       // over the listed cameras' envs
+  int32_t max_tiles;
+  int32_t max_bodies;
+  int32_t parity;          // state buffer rendered
+  int32_t threads;         // workgroup size (multiple of 64)
+  int32_t bin_cap;         // bin entries held in LDS at once
+  int32_t persistent;
+  int32_t* queue;
+};
+
+hipError_t launch_physics(const WorldDev& w, const PhysConsts& pc, const PhysLaunch& l,
+                          hipStream_t s);
+hipError_t launch_raster(const WorldDev& w, const RasterLaunch& l, hipStream_t s);
+size_t raster_lds_bytes(const RasterLaunch& l);
+hipError_t raster_configure(size_t lds_bytes);
+hipError_t launch_reset_queue(int32_t* q, hipStream_t s);
+
+}  // namespace vuda

@@ -1,0 +1,135 @@
+// Host-side state of a world (internal to libvuda).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <set>
+#include <tuple>
+#include <vector>
+
+#include "vuda.h"
+#include "vuda_internal.h"
+
+namespace vuda {
+
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+
+// First-fit allocator of index ranges in [0, cap).
+class RangeAlloc {
+ public:
+  void init(int64_t cap) {
+    free_.clear();
+    if (cap > 0) free_[0] = cap;
+  }
+  int64_t alloc(int64_t n);
+  void release(int64_t start, int64_t n);
+  // mark [start, start + n) as used (it must be free)
+  void take(int64_t start, int64_t n) {
+    if (n <= 0) return;
+    auto it = free_.upper_bound(start);
+    --it;
+    const int64_t s = it->first, e = it->second;
+    free_.erase(it);
+    if (s < start) free_[s] = start;
+    if (start + n < e) free_[start + n] = e;
+  }
+  int64_t free_total() const {
+    int64_t t = 0;
+    for (auto& kv : free_) t += kv.second - kv.first;
+    return t;
+  }
+
+ private:
+  std::map<int64_t, int64_t> free_;  // start -> end
+};
+
+struct WorkList {
+  int32_t* dptr = nullptr;
+  int32_t n = 0;
+  int32_t max_bodies = 0;
+  int32_t max_verts = 0;
+  int32_t max_tris = 0;
+  int32_t max_tiles = 0;
+};
+
+struct Tuning {
+  int32_t raster_threads = 256;
+  int32_t bin_min = 2048;
+  int32_t phys_persistent = 0;
+  int32_t raster_persistent = 0;
+  bool graphs = false;
+};
+
+}  // namespace vuda
+
+struct vuda_world {
+  int device = -1;
+  vuda_phys_params phys{};
+  vuda::PhysConsts pc{};
+  vuda::Templates tpl{};
+  bool debug = false;
+  int32_t pair_cap = 1024;
+  int32_t cap_envs = 0, cap_cams = 0;
+  int64_t cap_bodies = 0, cap_pixels = 0;
+  uint64_t hbm_budget = 0;
+  int32_t n_envs_hi = 0;
+
+  // device arena
+  unsigned char* arena = nullptr;
+  size_t arena_bytes = 0;
+  vuda_allocator allocator{};
+  bool has_allocator = false;
+  struct {
+    size_t envs, cams, type, albedo, size, rbound, inv_m, inv_I, prim_base, vert_base, state0,
+        state1, rgb, depth, flags, tpl, queues, winners, coverage, contacts;
+  } off_{};
+  vuda::WorldDev dev{};
+  int32_t* queues = nullptr;
+
+  // host mirrors
+  std::vector<vuda::EnvDev> env_host;
+  std::vector<uint8_t> env_parity;
+  std::vector<uint8_t> env_active;
+  std::vector<vuda::CamDev> cam_host;
+  vuda::RangeAlloc slots, bodies, camslots, pixels;
+
+  // streams: mode 0 serialized (s_sim == s_render == s_serial), 1 CU-masked,
+  // 2 two unmasked streams
+  hipStream_t s_serial = nullptr, s_sim = nullptr, s_render = nullptr, s_capture = nullptr;
+  int mode = 0;
+  float cu_split = 0.0f;
+
+  // dependency events per env: the last step, and the last render of each buffer
+  std::vector<int64_t> step_ev;
+  std::vector<int64_t> render_ev[2];
+  std::vector<hipEvent_t> evpool;
+  int64_t next_event = 0;
+
+  std::map<std::tuple<int, int32_t, int32_t>, vuda::WorkList> lists;
+  std::map<std::tuple<int, int32_t, int32_t, int>, hipGraphExec_t> graphs;
+  vuda::Tuning tune;
+  size_t lds_configured = 64 * 1024;
+
+  int alloc_arena(const vuda_allocator* a);
+  int upload(const vuda_env_batch& b, int32_t e0, int64_t b0, int32_t c0, int64_t p0, int parity,
+             hipStream_t s);
+  void free_all();
+  int make_streams(float split);
+  void destroy_streams();
+  int drain();
+  int new_event(hipStream_t s, int64_t* id);
+  int wait_events(hipStream_t s, const std::set<int64_t>& ids);
+  void invalidate_lists();
+  int get_list(int phase, int32_t lo, int32_t hi, const vuda::WorkList** out);
+  int range_parity(int32_t lo, int32_t hi, int* parity);
+  int check_range(int32_t lo, int32_t hi);
+  int enqueue_physics(const vuda::WorkList& L, int parity, hipStream_t s);
+  int raster_launch_of(const vuda::WorkList& L, int parity, vuda::RasterLaunch* out);
+  int enqueue_raster(const vuda::WorkList& L, int parity, hipStream_t s);
+  int run_phase(int phase, const vuda::WorkList& L, int parity, int32_t lo, int32_t hi, hipStream_t s);
+  hipStream_t capture_stream();
+  int check_flags();
+};

@@ -1,0 +1,1117 @@
+// Host runtime of libvuda: world arena, env/camera tables, streams and the
+// co-scheduling switch, per-env dependency tracking, fetch and admission.
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <set>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "vuda.h"
+#include "vuda_internal.h"
+#include "vuda_runtime.h"
+
+using namespace vuda;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+static thread_local std::string g_last_error;
+
+int vuda::fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int vuda::hip_fail(hipError_t e, const char* what) {
+  return fail(VUDA_EHIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+#define HIPCHK(x)                                   \
+  do {                                              \
+    hipError_t e__ = (x);                           \
+    if (e__ != hipSuccess) return hip_fail(e__, #x); \
+  } while (0)
+
+extern "C" const char* vuda_strerror(int code) {
+  switch (code) {
+    case VUDA_OK: return "ok";
+    case VUDA_EINVAL: return "invalid argument";
+    case VUDA_ENOMEM: return "out of device memory or over the HBM budget";
+    case VUDA_EHIP: return "HIP runtime error";
+    case VUDA_ENUMERIC: return "non-finite physics state";
+    case VUDA_EOVERFLOW: return "contact or bin capacity exceeded";
+    case VUDA_EBUSY: return "no free slots or budget";
+    default: return "unknown error";
+  }
+}
+
+extern "C" const char* vuda_last_error_message(void) { return g_last_error.c_str(); }
+
+// ---------------------------------------------------------------------------
+// range allocator (first fit over [0, cap))
+// ---------------------------------------------------------------------------
+
+int64_t RangeAlloc::alloc(int64_t n) {
+  if (n == 0) return 0;
+  for (auto it = free_.begin(); it != free_.end(); ++it) {
+    if (it->second - it->first >= n) {
+      const int64_t s = it->first;
+      const int64_t e = it->second;
+      free_.erase(it);
+      if (s + n < e) free_[s + n] = e;
+      return s;
+    }
+  }
+  return -1;
+}
+
+void RangeAlloc::release(int64_t s, int64_t n) {
+  if (n == 0) return;
+  int64_t e = s + n;
+  auto nx = free_.lower_bound(s);
+  if (nx != free_.end() && nx->first == e) {
+    e = nx->second;
+    free_.erase(nx);
+  }
+  auto it = free_.lower_bound(s);
+  if (it != free_.begin()) {
+    auto pv = std::prev(it);
+    if (pv->second == s) {
+      pv->second = e;
+      return;
+    }
+  }
+  free_[s] = e;
+}
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static int validate_batch(const vuda_env_batch& b, const vuda_render_desc& r, int64_t* nb_out,
+                          int32_t* nc_out, int64_t* npix_out) {
+  if (b.n_envs < 0) return fail(VUDA_EINVAL, "n_envs < 0");
+  if (b.n_envs == 0) {
+    *nb_out = 0; *nc_out = 0; *npix_out = 0;
+    return VUDA_OK;
+  }
+  if (!b.body_off || !b.cam_off) return fail(VUDA_EINVAL, "body_off / cam_off missing");
+  if (b.body_off[0] != 0 || b.cam_off[0] != 0) return fail(VUDA_EINVAL, "offsets must start at 0");
+  for (int e = 0; e < b.n_envs; ++e) {
+    const int nb = b.body_off[e + 1] - b.body_off[e];
+    if (nb < 0 || nb > kMaxBodies) return fail(VUDA_EINVAL, "env %d: %d bodies (0..%d)", e, nb, kMaxBodies);
+    const int nc = b.cam_off[e + 1] - b.cam_off[e];
+    if (nc < 0) return fail(VUDA_EINVAL, "env %d: negative camera count", e);
+  }
+  const int64_t nb = b.body_off[b.n_envs];
+  const int32_t nc = b.cam_off[b.n_envs];
+  if (nb > 0 && (!b.type || !b.size || !b.rbound || !b.inv_m || !b.inv_I || !b.albedo || !b.pos ||
+                 !b.vel || !b.quat || !b.omega))
+    return fail(VUDA_EINVAL, "body arrays missing");
+  if (nc > 0 && (!b.cam_vp || !b.cam_w || !b.cam_h)) return fail(VUDA_EINVAL, "camera arrays missing");
+  for (int64_t i = 0; i < nb; ++i) {
+    if (b.type[i] > 1) return fail(VUDA_EINVAL, "body %lld: type %d", (long long)i, (int)b.type[i]);
+    if (b.albedo[i] > 7) return fail(VUDA_EINVAL, "body %lld: albedo %d", (long long)i, (int)b.albedo[i]);
+    if (!(b.size[i] > 0.0f) || !(b.rbound[i] >= b.size[i]))
+      return fail(VUDA_EINVAL, "body %lld: size/rbound", (long long)i);
+  }
+  int64_t npix = 0;
+  for (int32_t c = 0; c < nc; ++c) {
+    if (b.cam_w[c] < 1 || b.cam_h[c] < 1 || b.cam_w[c] > 4096 || b.cam_h[c] > 4096)
+      return fail(VUDA_EINVAL, "camera %d: size %dx%d", c, b.cam_w[c], b.cam_h[c]);
+    npix += (int64_t)b.cam_w[c] * b.cam_h[c];
+  }
+  // primitive ids must fit 16 bits
+  for (int e = 0; e < b.n_envs; ++e) {
+    int64_t tris = r.ground_nf;
+    for (int32_t i = b.body_off[e]; i < b.body_off[e + 1]; ++i) tris += b.type[i] ? r.cube_nf : r.sphere_nf;
+    if (tris > 65535) return fail(VUDA_EINVAL, "env %d: %lld primitives (max 65535)", e, (long long)tris);
+  }
+  *nb_out = nb;
+  *nc_out = nc;
+  *npix_out = npix;
+  return VUDA_OK;
+}
+
+static int validate_render(const vuda_render_desc& r) {
+  if (!r.sphere_v || !r.sphere_f || !r.sphere_n || !r.cube_v || !r.cube_f || !r.cube_n ||
+      !r.ground_v || !r.ground_f)
+    return fail(VUDA_EINVAL, "render templates missing");
+  if (r.sphere_nv < 3 || r.sphere_nv > kMaxTplVerts || r.cube_nv < 3 || r.cube_nv > kMaxTplVerts ||
+      r.ground_nv < 3 || r.ground_nv > kMaxGroundVerts)
+    return fail(VUDA_EINVAL, "template vertex counts");
+  if (r.sphere_nf < 1 || r.sphere_nf > kMaxTplFaces || r.cube_nf < 1 || r.cube_nf > kMaxTplFaces ||
+      r.ground_nf < 1 || r.ground_nf > kMaxGroundFaces)
+    return fail(VUDA_EINVAL, "template face counts");
+  auto chk = [](const int32_t* f, int nf, int nv) {
+    for (int i = 0; i < 3 * nf; ++i)
+      if (f[i] < 0 || f[i] >= nv) return false;
+    return true;
+  };
+  if (!chk(r.sphere_f, r.sphere_nf, r.sphere_nv) || !chk(r.cube_f, r.cube_nf, r.cube_nv) ||
+      !chk(r.ground_f, r.ground_nf, r.ground_nv))
+    return fail(VUDA_EINVAL, "template face index out of range");
+  if (!(r.near_w > 0.0f) || !(r.guard > 0.0f) || r.guard > 65536.0f)
+    return fail(VUDA_EINVAL, "near_w / guard");
+  return VUDA_OK;
+}
+
+static void fill_templates(Templates& t, const vuda_render_desc& r) {
+  memset(&t, 0, sizeof(t));
+  for (int i = 0; i < r.sphere_nv; ++i)
+    for (int k = 0; k < 3; ++k) t.sphere_v[i][k] = r.sphere_v[3 * i + k];
+  for (int i = 0; i < r.cube_nv; ++i)
+    for (int k = 0; k < 3; ++k) t.cube_v[i][k] = r.cube_v[3 * i + k];
+  for (int i = 0; i < r.ground_nv; ++i)
+    for (int k = 0; k < 3; ++k) t.ground_v[i][k] = r.ground_v[3 * i + k];
+  for (int i = 0; i < r.sphere_nf; ++i)
+    for (int k = 0; k < 3; ++k) {
+      t.sphere_f[i][k] = (uint8_t)r.sphere_f[3 * i + k];
+      t.sphere_n[i][k] = r.sphere_n[3 * i + k];
+    }
+  for (int i = 0; i < r.cube_nf; ++i)
+    for (int k = 0; k < 3; ++k) {
+      t.cube_f[i][k] = (uint8_t)r.cube_f[3 * i + k];
+      t.cube_n[i][k] = r.cube_n[3 * i + k];
+    }
+  for (int i = 0; i < r.ground_nf; ++i)
+    for (int k = 0; k < 3; ++k) t.ground_f[i][k] = (uint8_t)r.ground_f[3 * i + k];
+  t.sphere_nv = r.sphere_nv; t.sphere_nf = r.sphere_nf;
+  t.cube_nv = r.cube_nv; t.cube_nf = r.cube_nf;
+  t.ground_nv = r.ground_nv; t.ground_nf = r.ground_nf;
+  for (int k = 0; k < 3; ++k) t.light[k] = r.light[k];
+  for (int i = 0; i < 8; ++i)
+    for (int k = 0; k < 3; ++k) t.palette[i][k] = r.palette[3 * i + k];
+  t.ground_albedo = r.ground_albedo;
+  t.near_w = r.near_w;
+  t.guard = r.guard;
+}
+
+// ---------------------------------------------------------------------------
+// world lifetime
+// ---------------------------------------------------------------------------
+
+int vuda_world::alloc_arena(const vuda_allocator* a) {
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += align256(bytes);
+    return at;
+  };
+  const int64_t B = std::max<int64_t>(cap_bodies, 1);
+  const int64_t P = std::max<int64_t>(cap_pixels, 1);
+  const int64_t E = std::max<int32_t>(cap_envs, 1);
+  const int64_t C = std::max<int32_t>(cap_cams, 1);
+  off_.envs = take(sizeof(EnvDev) * E);
+  off_.cams = take(sizeof(CamDev) * C);
+  off_.type = take(B);
+  off_.albedo = take(B);
+  off_.size = take(4 * B);
+  off_.rbound = take(4 * B);
+  off_.inv_m = take(4 * B);
+  off_.inv_I = take(4 * B);
+  off_.prim_base = take(4 * B);
+  off_.vert_base = take(4 * B);
+  off_.state0 = take(4 * (size_t)kStateComps * B);
+  off_.state1 = take(4 * (size_t)kStateComps * B);
+  off_.rgb = take(3 * P + 16);
+  off_.depth = take(4 * P);
+  off_.flags = take(4 * E + 4);
+  off_.tpl = take(sizeof(Templates));
+  off_.queues = take(64);
+  if (debug) {
+    off_.winners = take(4 * P);
+    off_.coverage = take(4 * P);
+    off_.contacts = take(4 * (size_t)E * phys.substeps * (1 + 2 * (size_t)pair_cap));
+  }
+  arena_bytes = o;
+  if (hbm_budget && arena_bytes > hbm_budget)
+    return fail(VUDA_ENOMEM, "arena of %zu bytes exceeds the HBM budget of %llu", arena_bytes,
+                (unsigned long long)hbm_budget);
+  if (a && a->alloc) {
+    allocator = *a;
+    has_allocator = true;
+    arena = (unsigned char*)a->alloc(arena_bytes, a->ctx);
+    if (!arena) return fail(VUDA_ENOMEM, "allocator returned NULL for %zu bytes", arena_bytes);
+  } else {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, arena_bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(VUDA_ENOMEM, "hipMalloc(%zu): %s", arena_bytes, hipGetErrorString(e));
+    }
+    arena = (unsigned char*)p;
+  }
+  HIPCHK(hipMemset(arena, 0, arena_bytes));
+  dev.envs = (EnvDev*)(arena + off_.envs);
+  dev.cams = (CamDev*)(arena + off_.cams);
+  dev.type = arena + off_.type;
+  dev.albedo = arena + off_.albedo;
+  dev.size = (float*)(arena + off_.size);
+  dev.rbound = (float*)(arena + off_.rbound);
+  dev.inv_m = (float*)(arena + off_.inv_m);
+  dev.inv_I = (float*)(arena + off_.inv_I);
+  dev.prim_base = (int32_t*)(arena + off_.prim_base);
+  dev.vert_base = (int32_t*)(arena + off_.vert_base);
+  dev.state[0] = (float*)(arena + off_.state0);
+  dev.state[1] = (float*)(arena + off_.state1);
+  dev.cap_bodies = B;
+  dev.rgb = arena + off_.rgb;
+  dev.depth = (uint32_t*)(arena + off_.depth);
+  dev.env_flags = (uint32_t*)(arena + off_.flags);
+  dev.tpl = (const Templates*)(arena + off_.tpl);
+  queues = (int32_t*)(arena + off_.queues);
+  dev.winners = debug ? (int32_t*)(arena + off_.winners) : nullptr;
+  dev.coverage = debug ? (int32_t*)(arena + off_.coverage) : nullptr;
+  dev.contacts = debug ? (int32_t*)(arena + off_.contacts) : nullptr;
+  dev.pair_cap = pair_cap;
+  return VUDA_OK;
+}
+
+// Upload a batch of envs into slots [e0, e0 + n), bodies from b0, cameras
+// from c0, pixels from p0; state goes to buffer `parity`.
+int vuda_world::upload(const vuda_env_batch& b, int32_t e0, int64_t b0, int32_t c0, int64_t p0,
+                       int parity, hipStream_t s) {
+  const int64_t nb = b.n_envs ? b.body_off[b.n_envs] : 0;
+  const int32_t nc = b.n_envs ? b.cam_off[b.n_envs] : 0;
+  std::vector<EnvDev> envs(b.n_envs);
+  std::vector<int32_t> pbase(nb), vbase(nb);
+  for (int e = 0; e < b.n_envs; ++e) {
+    EnvDev& d = envs[e];
+    d.body_off = (int32_t)(b0 + b.body_off[e]);
+    d.n_bodies = b.body_off[e + 1] - b.body_off[e];
+    d.cam_off = c0 + b.cam_off[e];
+    d.n_cams = b.cam_off[e + 1] - b.cam_off[e];
+    int32_t pv = tpl.ground_nf, vv = tpl.ground_nv;
+    for (int32_t i = b.body_off[e]; i < b.body_off[e + 1]; ++i) {
+      pbase[i] = pv;
+      vbase[i] = vv;
+      pv += b.type[i] ? tpl.cube_nf : tpl.sphere_nf;
+      vv += b.type[i] ? tpl.cube_nv : tpl.sphere_nv;
+    }
+    d.n_tris = pv;
+    d.n_verts = vv;
+  }
+  std::vector<CamDev> cams(nc);
+  int64_t po = p0;
+  for (int e = 0; e < b.n_envs; ++e)
+    for (int32_t c = b.cam_off[e]; c < b.cam_off[e + 1]; ++c) {
+      CamDev& d = cams[c];
+      memcpy(d.vp, b.cam_vp + 16 * (size_t)c, sizeof(d.vp));
+      d.w = b.cam_w[c];
+      d.h = b.cam_h[c];
+      d.pix_off = po;
+      d.env = e0 + e;
+      d.pad = 0;
+      po += (int64_t)d.w * d.h;
+    }
+  std::vector<float> st((size_t)kStateComps * nb);
+  for (int64_t i = 0; i < nb; ++i) {
+    for (int k = 0; k < 3; ++k) {
+      st[(PX + k) * nb + i] = b.pos[3 * i + k];
+      st[(VX + k) * nb + i] = b.vel[3 * i + k];
+      st[(WX + k) * nb + i] = b.omega[3 * i + k];
+    }
+    for (int k = 0; k < 4; ++k) st[(QW + k) * nb + i] = b.quat[4 * i + k];
+  }
+  auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    if (!bytes) return hipSuccess;
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+  };
+  HIPCHK(up(dev.envs + e0, envs.data(), sizeof(EnvDev) * envs.size()));
+  HIPCHK(up(dev.cams + c0, cams.data(), sizeof(CamDev) * cams.size()));
+  HIPCHK(up((void*)(dev.type + b0), b.type, nb));
+  HIPCHK(up((void*)(dev.albedo + b0), b.albedo, nb));
+  HIPCHK(up((void*)(dev.size + b0), b.size, 4 * nb));
+  HIPCHK(up((void*)(dev.rbound + b0), b.rbound, 4 * nb));
+  HIPCHK(up((void*)(dev.inv_m + b0), b.inv_m, 4 * nb));
+  HIPCHK(up((void*)(dev.inv_I + b0), b.inv_I, 4 * nb));
+  HIPCHK(up((void*)(dev.prim_base + b0), pbase.data(), 4 * nb));
+  HIPCHK(up((void*)(dev.vert_base + b0), vbase.data(), 4 * nb));
+  for (int k = 0; k < kStateComps; ++k)
+    HIPCHK(up(dev.state[parity] + k * dev.cap_bodies + b0, st.data() + k * nb, 4 * nb));
+  // flags of the new envs start clear
+  std::vector<uint32_t> zero(b.n_envs, 0u);
+  HIPCHK(up(dev.env_flags + e0, zero.data(), 4 * zero.size()));
+  // host mirrors
+  for (int e = 0; e < b.n_envs; ++e) {
+    env_host[e0 + e] = envs[e];
+    env_parity[e0 + e] = (uint8_t)parity;
+    env_active[e0 + e] = 1;
+  }
+  for (int32_t c = 0; c < nc; ++c) cam_host[c0 + c] = cams[c];
+  HIPCHK(hipStreamSynchronize(s));  // host vectors die at return
+  invalidate_lists();
+  return VUDA_OK;
+}
+
+extern "C" int vuda_create_world(const vuda_world_desc* d, const vuda_allocator* a, vuda_world** out) {
+  if (!d || !out) return fail(VUDA_EINVAL, "null descriptor or output");
+  *out = nullptr;
+  if (!(d->phys.dt > 0.0f) || d->phys.substeps < 1 || d->phys.substeps > 64 ||
+      !(d->phys.k_contact >= 0.0f) || !(d->phys.c_damp >= 0.0f))
+    return fail(VUDA_EINVAL, "physics parameters");
+  int rc = validate_render(d->render);
+  if (rc) return rc;
+  int64_t nb = 0, npix = 0;
+  int32_t nc = 0;
+  rc = validate_batch(d->initial, d->render, &nb, &nc, &npix);
+  if (rc) return rc;
+  vuda_world* w = new (std::nothrow) vuda_world();
+  if (!w) return fail(VUDA_ENOMEM, "host allocation");
+  HIPCHK(hipGetDevice(&w->device));
+  w->phys = d->phys;
+  w->debug = (d->flags & VUDA_FLAG_DEBUG) != 0;
+  w->pair_cap = d->pair_cap > 0 ? d->pair_cap : 1024;
+  w->cap_envs = std::max(d->cap_envs, d->initial.n_envs);
+  w->cap_bodies = std::max(d->cap_bodies, nb);
+  w->cap_cams = std::max(d->cap_cams, nc);
+  w->cap_pixels = std::max(d->cap_pixels, npix);
+  w->hbm_budget = d->hbm_budget;
+  fill_templates(w->tpl, d->render);
+  w->pc.h = d->phys.dt / (float)d->phys.substeps;
+  w->pc.hh = 0.5f * w->pc.h;
+  w->pc.k = d->phys.k_contact;
+  w->pc.c = d->phys.c_damp;
+  for (int k = 0; k < 3; ++k) w->pc.g[k] = d->phys.gravity[k];
+  w->pc.substeps = d->phys.substeps;
+  rc = w->alloc_arena(a);
+  if (rc) {
+    w->free_all();
+    delete w;
+    return rc;
+  }
+  w->env_host.assign(w->cap_envs, EnvDev{});
+  w->env_parity.assign(w->cap_envs, 0);
+  w->env_active.assign(w->cap_envs, 0);
+  w->cam_host.assign(w->cap_cams, CamDev{});
+  w->step_ev.assign(w->cap_envs, -1);
+  w->render_ev[0].assign(w->cap_envs, -1);
+  w->render_ev[1].assign(w->cap_envs, -1);
+  w->slots.init(w->cap_envs);
+  w->bodies.init(w->cap_bodies);
+  w->camslots.init(w->cap_cams);
+  w->pixels.init(w->cap_pixels);
+  rc = w->make_streams(0.0f);
+  if (rc == VUDA_OK) {
+    hipError_t e = hipMemcpy((void*)w->dev.tpl, &w->tpl, sizeof(Templates), hipMemcpyHostToDevice);
+    if (e != hipSuccess) rc = hip_fail(e, "template upload");
+  }
+  if (rc == VUDA_OK && d->initial.n_envs > 0) {
+    w->slots.take(0, d->initial.n_envs);
+    w->bodies.take(0, nb);
+    w->camslots.take(0, nc);
+    w->pixels.take(0, npix);
+    rc = w->upload(d->initial, 0, 0, 0, 0, 0, w->s_serial);
+    w->n_envs_hi = d->initial.n_envs;
+  }
+  if (rc) {
+    w->free_all();
+    delete w;
+    return rc;
+  }
+  *out = w;
+  return VUDA_OK;
+}
+
+void vuda_world::free_all() {
+  if (device >= 0) (void)hipSetDevice(device);
+  (void)hipDeviceSynchronize();
+  for (auto& kv : lists) {
+    if (kv.second.dptr) (void)hipFree(kv.second.dptr);
+  }
+  lists.clear();
+  for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+  graphs.clear();
+  destroy_streams();
+  if (s_serial) (void)hipStreamDestroy(s_serial);
+  s_serial = nullptr;
+  for (auto& e : evpool) (void)hipEventDestroy(e);
+  evpool.clear();
+  if (arena) {
+    if (has_allocator) allocator.free(arena, allocator.ctx);
+    else (void)hipFree(arena);
+  }
+  arena = nullptr;
+}
+
+extern "C" int vuda_destroy_world(vuda_world* w) {
+  if (!w) return fail(VUDA_EINVAL, "null world");
+  w->free_all();
+  delete w;
+  return VUDA_OK;
+}
+
+extern "C" int vuda_world_info(vuda_world* w, int32_t* n_envs, int64_t* n_bodies, int32_t* n_cams,
+                               int64_t* n_pixels, uint64_t* arena_bytes) {
+  if (!w) return fail(VUDA_EINVAL, "null world");
+  if (n_envs) *n_envs = w->n_envs_hi;
+  if (n_bodies) *n_bodies = w->cap_bodies;
+  if (n_cams) *n_cams = w->cap_cams;
+  if (n_pixels) *n_pixels = w->cap_pixels;
+  if (arena_bytes) *arena_bytes = w->arena_bytes;
+  return VUDA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// streams, CU masks, events
+// ---------------------------------------------------------------------------
+
+void vuda_world::destroy_streams() {
+  if (s_sim && s_sim != s_serial) (void)hipStreamDestroy(s_sim);
+  if (s_render && s_render != s_serial) (void)hipStreamDestroy(s_render);
+  s_sim = s_render = nullptr;
+}
+
+// Bit i of a HIP CU mask selects a CU of XCD (i mod n_xcd), then of shader
+// engine round-robin within it, so a contiguous run of bits spreads evenly
+// over the XCDs and engines; the step phase takes bits [0, k), the render
+// phase [k, n_cu).
+static void cu_masks(int n_cu, float split, std::vector<uint32_t>& sim, std::vector<uint32_t>& ren) {
+  const int words = (n_cu + 31) / 32;
+  sim.assign(words, 0u);
+  ren.assign(words, 0u);
+  int k = (int)(split * (float)n_cu + 0.5f);
+  k = std::max(1, std::min(n_cu - 1, k));
+  for (int i = 0; i < n_cu; ++i) {
+    if (i < k) sim[i / 32] |= 1u << (i % 32);
+    else ren[i / 32] |= 1u << (i % 32);
+  }
+}
+
+int vuda_world::make_streams(float split) {
+  HIPCHK(hipSetDevice(device));
+  if (!s_serial) HIPCHK(hipStreamCreateWithFlags(&s_serial, hipStreamNonBlocking));
+  destroy_streams();
+  mode = 0;
+  cu_split = 0.0f;
+  if (split > 0.0f && split < 1.0f) {
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, device));
+    std::vector<uint32_t> ms, mr;
+    cu_masks(prop.multiProcessorCount, split, ms, mr);
+    HIPCHK(hipExtStreamCreateWithCUMask(&s_sim, (uint32_t)ms.size(), ms.data()));
+    HIPCHK(hipExtStreamCreateWithCUMask(&s_render, (uint32_t)mr.size(), mr.data()));
+    mode = 1;
+    cu_split = split;
+  } else if (split == 2.0f) {
+    HIPCHK(hipStreamCreateWithFlags(&s_sim, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&s_render, hipStreamNonBlocking));
+    mode = 2;
+    cu_split = split;
+  } else {
+    s_sim = s_serial;
+    s_render = s_serial;
+  }
+  return VUDA_OK;
+}
+
+int vuda_world::drain() {
+  HIPCHK(hipSetDevice(device));
+  if (s_sim) HIPCHK(hipStreamSynchronize(s_sim));
+  if (s_render) HIPCHK(hipStreamSynchronize(s_render));
+  if (s_serial) HIPCHK(hipStreamSynchronize(s_serial));
+  return VUDA_OK;
+}
+
+extern "C" int vuda_cosched(vuda_world* w, float cu_split) {
+  if (!w) return fail(VUDA_EINVAL, "null world");
+  if (!(cu_split <= 0.0f || (cu_split > 0.0f && cu_split < 1.0f) || cu_split == 1.0f || cu_split == 2.0f))
+    return fail(VUDA_EINVAL, "cu_split %g: use (0,1), 2, or <=0 / 1", (double)cu_split);
+  int rc = w->drain();
+  if (rc) return rc;
+  for (auto& g : w->graphs) (void)hipGraphExecDestroy(g.second);
+  w->graphs.clear();
+  rc = w->make_streams(cu_split == 1.0f ? 0.0f : cu_split);
+  // every earlier event has completed (drained): forget them
+  std::fill(w->step_ev.begin(), w->step_ev.end(), -1);
+  std::fill(w->render_ev[0].begin(), w->render_ev[0].end(), -1);
+  std::fill(w->render_ev[1].begin(), w->render_ev[1].end(), -1);
+  return rc;
+}
+
+// Event pool: ids grow monotonically; slot id % size is reused after making
+// sure the event it held has completed.
+int vuda_world::new_event(hipStream_t s, int64_t* id) {
+  const size_t kPool = 512;
+  if (evpool.empty()) {
+    evpool.resize(kPool);
+    for (auto& e : evpool) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  const int64_t nid = next_event++;
+  hipEvent_t e = evpool[nid % kPool];
+  if (nid >= (int64_t)kPool) HIPCHK(hipEventSynchronize(e));
+  HIPCHK(hipEventRecord(e, s));
+  *id = nid;
+  return VUDA_OK;
+}
+
+int vuda_world::wait_events(hipStream_t s, const std::set<int64_t>& ids) {
+  const int64_t kPool = (int64_t)evpool.size();
+  for (int64_t id : ids) {
+    if (id < 0 || id < next_event - kPool) continue;  // recycled: already complete
+    HIPCHK(hipStreamWaitEvent(s, evpool[id % kPool], 0));
+  }
+  return VUDA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// work lists (LPT order) cached per range
+// ---------------------------------------------------------------------------
+
+void vuda_world::invalidate_lists() {
+  for (auto& kv : lists)
+    if (kv.second.dptr) (void)hipFree(kv.second.dptr);
+  lists.clear();
+  for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+  graphs.clear();
+}
+
+int vuda_world::get_list(int phase, int32_t lo, int32_t hi, const WorkList** out) {
+  const auto key = std::make_tuple(phase, lo, hi);
+  auto it = lists.find(key);
+  if (it != lists.end()) {
+    *out = &it->second;
+    return VUDA_OK;
+  }
+  WorkList L;
+  std::vector<std::pair<int64_t, int32_t>> items;
+  for (int32_t e = lo; e < hi; ++e) {
+    if (!env_active[e]) continue;
+    const EnvDev& d = env_host[e];
+    if (phase == VUDA_PHASE_STEP) {
+      if (d.n_bodies == 0) continue;
+      items.push_back({(int64_t)d.n_bodies * d.n_bodies + 8 * d.n_bodies, e});
+      L.max_bodies = std::max(L.max_bodies, d.n_bodies);
+    } else {
+      for (int32_t c = d.cam_off; c < d.cam_off + d.n_cams; ++c) {
+        const CamDev& cd = cam_host[c];
+        const int tiles = ((cd.w + kTile - 1) / kTile) * ((cd.h + kTile - 1) / kTile);
+        items.push_back({(int64_t)cd.w * cd.h + 64LL * d.n_tris, c});
+        L.max_bodies = std::max(L.max_bodies, d.n_bodies);
+        L.max_verts = std::max(L.max_verts, d.n_verts);
+        L.max_tris = std::max(L.max_tris, d.n_tris);
+        L.max_tiles = std::max(L.max_tiles, tiles);
+      }
+    }
+  }
+  // longest processing time first; ties by id for a deterministic order
+  std::stable_sort(items.begin(), items.end(), [](const auto& a, const auto& b) {
+    return a.first > b.first || (a.first == b.first && a.second < b.second);
+  });
+  std::vector<int32_t> ids(items.size());
+  for (size_t i = 0; i < items.size(); ++i) ids[i] = items[i].second;
+  L.n = (int32_t)ids.size();
+  if (L.n > 0) {
+    HIPCHK(hipMalloc(&L.dptr, 4 * ids.size()));
+    HIPCHK(hipMemcpy(L.dptr, ids.data(), 4 * ids.size(), hipMemcpyHostToDevice));
+  }
+  auto res = lists.emplace(key, L);
+  *out = &res.first->second;
+  return VUDA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// step / render / wait
+// ---------------------------------------------------------------------------
+
+int vuda_world::range_parity(int32_t lo, int32_t hi, int* parity) {
+  int p = -1;
+  for (int32_t e = lo; e < hi; ++e) {
+    if (!env_active[e]) continue;
+    if (p < 0) p = env_parity[e];
+    else if (p != env_parity[e])
+      return fail(VUDA_EINVAL, "envs %d..%d have different step parity", lo, hi - 1);
+  }
+  *parity = p < 0 ? 0 : p;
+  return VUDA_OK;
+}
+
+int vuda_world::check_range(int32_t lo, int32_t hi) {
+  if (lo < 0 || hi > cap_envs || lo > hi) return fail(VUDA_EINVAL, "env range [%d,%d) of %d", lo, hi, cap_envs);
+  return VUDA_OK;
+}
+
+int vuda_world::enqueue_physics(const WorkList& L, int parity, hipStream_t s) {
+  PhysLaunch pl;
+  pl.work = L.dptr;
+  pl.n_work = L.n;
+  pl.max_bodies = L.max_bodies;
+  pl.parity = parity;
+  pl.nsteps = 1;
+  pl.persistent = tune.phys_persistent;
+  pl.queue = queues;
+  HIPCHK(launch_physics(dev, pc, pl, s));
+  return VUDA_OK;
+}
+
+int vuda_world::raster_launch_of(const WorkList& L, int parity, RasterLaunch* out) {
+  RasterLaunch rl;
+  rl.work = L.dptr;
+  rl.n_work = L.n;
+  rl.max_verts = std::max(L.max_verts, 1);
+  rl.max_tiles = std::max(L.max_tiles, 1);
+  rl.max_bodies = L.max_bodies;
+  rl.parity = parity;
+  rl.threads = tune.raster_threads;
+  // bins: room for every primitive in one tile, at least bin_min entries
+  rl.bin_cap = std::max(L.max_tris, tune.bin_min);
+  rl.persistent = tune.raster_persistent;
+  rl.queue = queues + 1;
+  size_t lds = raster_lds_bytes(rl);
+  const size_t kLdsMax = 160 * 1024;
+  if (lds > kLdsMax) {
+    rl.bin_cap = L.max_tris;
+    lds = raster_lds_bytes(rl);
+    if (lds > kLdsMax)
+      return fail(VUDA_EOVERFLOW, "raster needs %zu bytes of LDS (max %zu)", lds, kLdsMax);
+  }
+  if (lds > lds_configured) {
+    HIPCHK(raster_configure(lds));
+    lds_configured = lds;
+  }
+  *out = rl;
+  return VUDA_OK;
+}
+
+int vuda_world::enqueue_raster(const WorkList& L, int parity, hipStream_t s) {
+  RasterLaunch rl;
+  int rc = raster_launch_of(L, parity, &rl);
+  if (rc) return rc;
+  HIPCHK(launch_raster(dev, rl, s));
+  return VUDA_OK;
+}
+
+// Launch one phase, through a captured graph when graph mode is on.
+int vuda_world::run_phase(int phase, const WorkList& L, int parity, int32_t lo, int32_t hi,
+                          hipStream_t s) {
+  if (!tune.graphs) {
+    return phase == VUDA_PHASE_STEP ? enqueue_physics(L, parity, s) : enqueue_raster(L, parity, s);
+  }
+  const auto key = std::make_tuple(phase, lo, hi, parity);
+  auto it = graphs.find(key);
+  if (it == graphs.end()) {
+    hipStream_t cs = capture_stream();
+    if (!cs) return fail(VUDA_EHIP, "capture stream");
+    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    int rc = phase == VUDA_PHASE_STEP ? enqueue_physics(L, parity, cs) : enqueue_raster(L, parity, cs);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(cs, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    it = graphs.emplace(key, ge).first;
+  }
+  HIPCHK(hipGraphLaunch(it->second, s));
+  return VUDA_OK;
+}
+
+hipStream_t vuda_world::capture_stream() {
+  if (!s_capture) {
+    if (hipStreamCreateWithFlags(&s_capture, hipStreamNonBlocking) != hipSuccess) return nullptr;
+  }
+  return s_capture;
+}
+
+extern "C" int vuda_step(vuda_world* w, int32_t lo, int32_t hi, int32_t nsteps) {
+  if (!w) return fail(VUDA_EINVAL, "null world");
+  int rc = w->check_range(lo, hi);
+  if (rc) return rc;
+  if (nsteps < 0) return fail(VUDA_EINVAL, "nsteps < 0");
+  if (nsteps == 0 || lo == hi) return VUDA_OK;
+  int parity;
+  rc = w->range_parity(lo, hi, &parity);
+  if (rc) return rc;
+  const WorkList* L;
+  rc = w->get_list(VUDA_PHASE_STEP, lo, hi, &L);
+  if (rc) return rc;
+  hipStream_t s = w->s_sim;
+  for (int t = 0; t < nsteps; ++t) {
+    const int p = (parity + t) & 1;
+    if (w->mode != 0) {
+      // RAW on the state read, WAR on the buffer written (renders reading it)
+      std::set<int64_t> ids;
+      for (int32_t e = lo; e < hi; ++e) {
+        if (!w->env_active[e]) continue;
+        ids.insert(w->step_ev[e]);
+        ids.insert(w->render_ev[p ^ 1][e]);
+      }
+      rc = w->wait_events(s, ids);
+      if (rc) return rc;
+    }
+    rc = w->run_phase(VUDA_PHASE_STEP, *L, p, lo, hi, s);
+    if (rc) return rc;
+    int64_t id = -1;
+    if (w->mode != 0) {
+      rc = w->new_event(s, &id);
+      if (rc) return rc;
+    }
+    for (int32_t e = lo; e < hi; ++e) {
+      if (!w->env_active[e]) continue;
+      w->env_parity[e] ^= 1;
+      w->step_ev[e] = id;
+    }
+  }
+  return VUDA_OK;
+}
+
+extern "C" int vuda_render(vuda_world* w, int32_t lo, int32_t hi) {
+  if (!w) return fail(VUDA_EINVAL, "null world");
+  int rc = w->check_range(lo, hi);
+  if (rc) return rc;
+  if (lo == hi) return VUDA_OK;
+  int parity;
+  rc = w->range_parity(lo, hi, &parity);
+  if (rc) return rc;
+  const WorkList* L;
+  rc = w->get_list(VUDA_PHASE_RENDER, lo, hi, &L);
+  if (rc) return rc;
+  hipStream_t s = w->s_render;
+  if (w->mode != 0) {
+    std::set<int64_t> ids;
+    for (int32_t e = lo; e < hi; ++e)
+      if (w->env_active[e]) ids.insert(w->step_ev[e]);  // RAW: the step that wrote the state
+    rc = w->wait_events(s, ids);
+    if (rc) return rc;
+  }
+  rc = w->run_phase(VUDA_PHASE_RENDER, *L, parity, lo, hi, s);
+  if (rc) return rc;
+  if (w->mode != 0) {
+    int64_t id;
+    rc = w->new_event(s, &id);
+    if (rc) return rc;
+    for (int32_t e = lo; e < hi; ++e)
+      if (w->env_active[e]) w->render_ev[parity][e] = id;
+  }
+  return VUDA_OK;
+}
+
+int vuda_world::check_flags() {
+  uint32_t any = 0;
+  std::vector<uint32_t> fl(cap_envs);
+  HIPCHK(hipMemcpy(fl.data(), dev.env_flags, 4 * (size_t)cap_envs, hipMemcpyDeviceToHost));
+  int first = -1;
+  for (int32_t e = 0; e < cap_envs; ++e) {
+    if (fl[e] && first < 0) first = e;
+    any |= fl[e];
+  }
+  if (any & kFlagNonFinite) return fail(VUDA_ENUMERIC, "non-finite state (first env %d)", first);
+  if (any & (kFlagContactOverflow | kFlagBinOverflow))
+    return fail(VUDA_EOVERFLOW, "capacity overflow, flags 0x%x (first env %d)", any, first);
+  return VUDA_OK;
+}
+
+extern "C" int vuda_wait(vuda_world* w, int32_t phase) {
+  if (!w) return fail(VUDA_EINVAL, "null world");
+  if (phase < 1 || phase > 3) return fail(VUDA_EINVAL, "phase %d", phase);
+  HIPCHK(hipSetDevice(w->device));
+  if (phase & VUDA_PHASE_STEP) HIPCHK(hipStreamSynchronize(w->s_sim));
+  if (phase & VUDA_PHASE_RENDER) HIPCHK(hipStreamSynchronize(w->s_render));
+  return w->check_flags();
+}
+
+extern "C" int vuda_get_stream(vuda_world* w, int32_t phase, void** s) {
+  if (!w || !s) return fail(VUDA_EINVAL, "null argument");
+  if (phase == VUDA_PHASE_STEP) *s = (void*)w->s_sim;
+  else if (phase == VUDA_PHASE_RENDER) *s = (void*)w->s_render;
+  else return fail(VUDA_EINVAL, "phase %d", phase);
+  return VUDA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// fetch / load
+// ---------------------------------------------------------------------------
+
+static int env_runs(vuda_world* w, int32_t lo, int32_t hi, int what, std::vector<std::pair<int64_t, int64_t>>& runs,
+                    int64_t* total) {
+  // contiguous element runs [start, count) of the selected data over envs lo..hi
+  runs.clear();
+  *total = 0;
+  for (int32_t e = lo; e < hi; ++e) {
+    if (!w->env_active[e]) continue;
+    const EnvDev& d = w->env_host[e];
+    int64_t s = 0, n = 0;
+    if (what == VUDA_FETCH_STATE) {
+      s = d.body_off;
+      n = d.n_bodies;
+    } else if (what == VUDA_FETCH_CONTACTS || what == VUDA_FETCH_FLAGS) {
+      s = e;
+      n = 1;
+    } else {
+      if (d.n_cams == 0) continue;
+      const CamDev& c0 = w->cam_host[d.cam_off];
+      const CamDev& c1 = w->cam_host[d.cam_off + d.n_cams - 1];
+      s = c0.pix_off;
+      n = c1.pix_off + (int64_t)c1.w * c1.h - s;
+    }
+    if (n == 0) continue;
+    if (!runs.empty() && runs.back().first + runs.back().second == s) runs.back().second += n;
+    else runs.push_back({s, n});
+    *total += n;
+  }
+  return VUDA_OK;
+}
+
+static size_t elem_bytes(vuda_world* w, int what) {
+  switch (what) {
+    case VUDA_FETCH_STATE: return 4 * kStateComps;
+    case VUDA_FETCH_RGB: return 3;
+    case VUDA_FETCH_DEPTH: return 4;
+    case VUDA_FETCH_WINNERS: return 4;
+    case VUDA_FETCH_COVERAGE: return 4;
+    case VUDA_FETCH_CONTACTS: return 4 * (size_t)w->phys.substeps * (1 + 2 * (size_t)w->pair_cap);
+    case VUDA_FETCH_FLAGS: return 4;
+    default: return 0;
+  }
+}
+
+extern "C" int vuda_fetch_bytes(vuda_world* w, int32_t what, int32_t lo, int32_t hi, size_t* bytes) {
+  if (!w || !bytes) return fail(VUDA_EINVAL, "null argument");
+  int rc = w->check_range(lo, hi);
+  if (rc) return rc;
+  if (elem_bytes(w, what) == 0) return fail(VUDA_EINVAL, "fetch selector %d", what);
+  std::vector<std::pair<int64_t, int64_t>> runs;
+  int64_t total;
+  env_runs(w, lo, hi, what, runs, &total);
+  *bytes = (size_t)total * elem_bytes(w, what);
+  return VUDA_OK;
+}
+
+extern "C" int vuda_fetch(vuda_world* w, int32_t what, int32_t lo, int32_t hi, void* dst,
+                          size_t dst_bytes, int32_t on_device) {
+  if (!w) return fail(VUDA_EINVAL, "null world");
+  int rc = w->check_range(lo, hi);
+  if (rc) return rc;
+  const size_t eb = elem_bytes(w, what);
+  if (eb == 0) return fail(VUDA_EINVAL, "fetch selector %d", what);
+  if (!w->debug && (what == VUDA_FETCH_CONTACTS || what == VUDA_FETCH_WINNERS || what == VUDA_FETCH_COVERAGE))
+    return fail(VUDA_EINVAL, "selector %d needs a world created with VUDA_FLAG_DEBUG", what);
+  std::vector<std::pair<int64_t, int64_t>> runs;
+  int64_t total;
+  env_runs(w, lo, hi, what, runs, &total);
+  if ((size_t)total * eb > dst_bytes)
+    return fail(VUDA_EINVAL, "dst holds %zu bytes, need %zu", dst_bytes, (size_t)total * eb);
+  if (total && !dst) return fail(VUDA_EINVAL, "null dst");
+  rc = w->drain();
+  if (rc) return rc;
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  unsigned char* out = (unsigned char*)dst;
+  if (what == VUDA_FETCH_STATE) {
+    // gather [13][B] SoA into [n][13] per env, from each env's current buffer
+    int64_t pos = 0;
+    std::vector<float> tmp;
+    for (int32_t e = lo; e < hi; ++e) {
+      if (!w->env_active[e]) continue;
+      const EnvDev& d = w->env_host[e];
+      if (d.n_bodies == 0) continue;
+      const float* src = w->dev.state[w->env_parity[e]];
+      tmp.resize((size_t)kStateComps * d.n_bodies);
+      for (int k = 0; k < kStateComps; ++k)
+        HIPCHK(hipMemcpy(tmp.data() + (size_t)k * d.n_bodies, src + k * w->dev.cap_bodies + d.body_off,
+                         4 * (size_t)d.n_bodies, hipMemcpyDeviceToHost));
+      std::vector<float> aos((size_t)kStateComps * d.n_bodies);
+      for (int i = 0; i < d.n_bodies; ++i)
+        for (int k = 0; k < kStateComps; ++k) aos[(size_t)i * kStateComps + k] = tmp[(size_t)k * d.n_bodies + i];
+      HIPCHK(hipMemcpy(out + pos * eb, aos.data(), aos.size() * 4,
+                       on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+      pos += d.n_bodies;
+    }
+    return w->check_flags();
+  }
+  const unsigned char* base = nullptr;
+  switch (what) {
+    case VUDA_FETCH_RGB: base = w->dev.rgb; break;
+    case VUDA_FETCH_DEPTH: base = (const unsigned char*)w->dev.depth; break;
+    case VUDA_FETCH_WINNERS: base = (const unsigned char*)w->dev.winners; break;
+    case VUDA_FETCH_COVERAGE: base = (const unsigned char*)w->dev.coverage; break;
+    case VUDA_FETCH_CONTACTS: base = (const unsigned char*)w->dev.contacts; break;
+    case VUDA_FETCH_FLAGS: base = (const unsigned char*)w->dev.env_flags; break;
+  }
+  int64_t pos = 0;
+  for (auto& r : runs) {
+    HIPCHK(hipMemcpy(out + pos * eb, base + r.first * eb, (size_t)r.second * eb, kind));
+    pos += r.second;
+  }
+  if (what == VUDA_FETCH_FLAGS) return VUDA_OK;
+  return w->check_flags();
+}
+
+extern "C" int vuda_load_state(vuda_world* w, int32_t lo, int32_t hi, const float* src, size_t src_bytes) {
+  if (!w) return fail(VUDA_EINVAL, "null world");
+  int rc = w->check_range(lo, hi);
+  if (rc) return rc;
+  int64_t need = 0;
+  for (int32_t e = lo; e < hi; ++e)
+    if (w->env_active[e]) need += w->env_host[e].n_bodies;
+  if ((size_t)need * 4 * kStateComps > src_bytes || (need && !src))
+    return fail(VUDA_EINVAL, "src holds %zu bytes, need %zu", src_bytes, (size_t)need * 4 * kStateComps);
+  rc = w->drain();
+  if (rc) return rc;
+  int64_t pos = 0;
+  for (int32_t e = lo; e < hi; ++e) {
+    if (!w->env_active[e]) continue;
+    const EnvDev& d = w->env_host[e];
+    if (d.n_bodies == 0) continue;
+    std::vector<float> soa((size_t)kStateComps * d.n_bodies);
+    for (int i = 0; i < d.n_bodies; ++i)
+      for (int k = 0; k < kStateComps; ++k)
+        soa[(size_t)k * d.n_bodies + i] = src[(pos + i) * kStateComps + k];
+    float* dstp = w->dev.state[w->env_parity[e]];
+    for (int k = 0; k < kStateComps; ++k)
+      HIPCHK(hipMemcpy(dstp + k * w->dev.cap_bodies + d.body_off, soa.data() + (size_t)k * d.n_bodies,
+                       4 * (size_t)d.n_bodies, hipMemcpyHostToDevice));
+    pos += d.n_bodies;
+  }
+  // clear sticky flags of the reloaded envs
+  std::vector<uint32_t> zero(hi - lo, 0u);
+  if (hi > lo) HIPCHK(hipMemcpy(w->dev.env_flags + lo, zero.data(), 4 * zero.size(), hipMemcpyHostToDevice));
+  return VUDA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// admission (serving)
+// ---------------------------------------------------------------------------
+
+extern "C" int vuda_admit(vuda_world* w, const vuda_env_batch* b, int32_t parity, int32_t* first_env) {
+  if (!w || !b || !first_env) return fail(VUDA_EINVAL, "null argument");
+  if (parity != 0 && parity != 1) return fail(VUDA_EINVAL, "parity %d", parity);
+  vuda_render_desc rd{};
+  rd.ground_nf = w->tpl.ground_nf;
+  rd.sphere_nf = w->tpl.sphere_nf;
+  rd.cube_nf = w->tpl.cube_nf;
+  int64_t nb, npix;
+  int32_t nc;
+  int rc = validate_batch(*b, rd, &nb, &nc, &npix);
+  if (rc) return rc;
+  if (b->n_envs == 0) return fail(VUDA_EINVAL, "empty request");
+  const int64_t e0 = w->slots.alloc(b->n_envs);
+  if (e0 < 0) return fail(VUDA_EBUSY, "no run of %d free env slots", b->n_envs);
+  const int64_t b0 = w->bodies.alloc(nb);
+  const int64_t c0 = b0 < 0 ? -1 : w->camslots.alloc(nc);
+  const int64_t p0 = c0 < 0 ? -1 : w->pixels.alloc(npix);
+  if (b0 < 0 || c0 < 0 || p0 < 0) {
+    w->slots.release(e0, b->n_envs);
+    if (b0 >= 0) w->bodies.release(b0, nb);
+    if (c0 >= 0) w->camslots.release(c0, nc);
+    return fail(VUDA_EBUSY, "no room for %lld bodies / %d cameras / %lld pixels", (long long)nb, nc,
+                (long long)npix);
+  }
+  rc = w->upload(*b, (int32_t)e0, b0, (int32_t)c0, p0, parity, w->s_serial);
+  if (rc) {
+    w->slots.release(e0, b->n_envs);
+    w->bodies.release(b0, nb);
+    w->camslots.release(c0, nc);
+    w->pixels.release(p0, npix);
+    return rc;
+  }
+  for (int e = 0; e < b->n_envs; ++e) {
+    w->step_ev[e0 + e] = -1;
+    w->render_ev[0][e0 + e] = -1;
+    w->render_ev[1][e0 + e] = -1;
+  }
+  w->n_envs_hi = std::max<int32_t>(w->n_envs_hi, (int32_t)(e0 + b->n_envs));
+  *first_env = (int32_t)e0;
+  return VUDA_OK;
+}
+
+extern "C" int vuda_release(vuda_world* w, int32_t first, int32_t n) {
+  if (!w) return fail(VUDA_EINVAL, "null world");
+  if (first < 0 || n <= 0 || first + n > w->cap_envs) return fail(VUDA_EINVAL, "range");
+  for (int32_t e = first; e < first + n; ++e)
+    if (!w->env_active[e]) return fail(VUDA_EINVAL, "env %d is not admitted", e);
+  int rc = w->drain();
+  if (rc) return rc;
+  // the request's bodies, cameras and pixels are contiguous
+  const EnvDev& d0 = w->env_host[first];
+  const EnvDev& d1 = w->env_host[first + n - 1];
+  const int64_t nb = (int64_t)d1.body_off + d1.n_bodies - d0.body_off;
+  const int32_t nc = d1.cam_off + d1.n_cams - d0.cam_off;
+  int64_t p0 = 0, np = 0;
+  if (nc > 0) {
+    const CamDev& c0 = w->cam_host[d0.cam_off];
+    const CamDev& c1 = w->cam_host[d0.cam_off + nc - 1];
+    p0 = c0.pix_off;
+    np = c1.pix_off + (int64_t)c1.w * c1.h - p0;
+  }
+  std::vector<EnvDev> empty(n, EnvDev{});
+  HIPCHK(hipMemcpy(w->dev.envs + first, empty.data(), sizeof(EnvDev) * n, hipMemcpyHostToDevice));
+  w->bodies.release(d0.body_off, nb);
+  w->camslots.release(d0.cam_off, nc);
+  w->pixels.release(p0, np);
+  w->slots.release(first, n);
+  for (int32_t e = first; e < first + n; ++e) {
+    w->env_active[e] = 0;
+    w->env_host[e] = EnvDev{};
+  }
+  w->invalidate_lists();
+  return VUDA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// tuning knobs
+// ---------------------------------------------------------------------------
+
+extern "C" int vuda_set_tuning(vuda_world* w, int32_t key, int32_t value) {
+  if (!w) return fail(VUDA_EINVAL, "null world");
+  switch (key) {
+    case VUDA_TUNE_RASTER_THREADS:
+      if (value < 64 || value > 1024 || value % 64) return fail(VUDA_EINVAL, "raster threads %d", value);
+      w->tune.raster_threads = value;
+      break;
+    case VUDA_TUNE_BIN_MIN:
+      if (value < 0 || value > (1 << 16)) return fail(VUDA_EINVAL, "bin_min %d", value);
+      w->tune.bin_min = value;
+      break;
+    case VUDA_TUNE_PHYS_PERSISTENT:
+      if (value < 0) return fail(VUDA_EINVAL, "persistent %d", value);
+      w->tune.phys_persistent = value;
+      break;
+    case VUDA_TUNE_RASTER_PERSISTENT:
+      if (value < 0) return fail(VUDA_EINVAL, "persistent %d", value);
+      w->tune.raster_persistent = value;
+      break;
+    case VUDA_TUNE_GRAPHS:
+      w->tune.graphs = value != 0;
+      break;
+    default:
+      return fail(VUDA_EINVAL, "tuning key %d", key);
+  }
+  for (auto& g : w->graphs) (void)hipGraphExecDestroy(g.second);
+  w->graphs.clear();
+  return VUDA_OK;
+}
+
+extern "C" int vuda_get_tuning(vuda_world* w, int32_t key, int32_t* value) {
+  if (!w || !value) return fail(VUDA_EINVAL, "null argument");
+  switch (key) {
+    case VUDA_TUNE_RASTER_THREADS: *value = w->tune.raster_threads; break;
+    case VUDA_TUNE_BIN_MIN: *value = w->tune.bin_min; break;
+    case VUDA_TUNE_PHYS_PERSISTENT: *value = w->tune.phys_persistent; break;
+    case VUDA_TUNE_RASTER_PERSISTENT: *value = w->tune.raster_persistent; break;
+    case VUDA_TUNE_GRAPHS: *value = w->tune.graphs ? 1 : 0; break;
+    default: return fail(VUDA_EINVAL, "tuning key %d", key);
+  }
+  return VUDA_OK;
+}

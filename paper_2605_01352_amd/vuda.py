@@ -1,0 +1,331 @@
+"""Python binding of libvuda (the C ABI in include/vuda.h).
+
+Argument marshalling only: every step of the physics and render path runs in
+the library's HIP kernels.  Importing this module does not touch the GPU; the
+first World() loads lib/libvuda.so and raises if it has not been built
+(there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libvuda.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENUMERIC, EOVERFLOW, EBUSY = 0, -1, -2, -3, -4, -5, -6
+PHASE_STEP, PHASE_RENDER, PHASE_ALL = 1, 2, 3
+FETCH_STATE, FETCH_RGB, FETCH_DEPTH, FETCH_CONTACTS, FETCH_WINNERS, FETCH_COVERAGE, FETCH_FLAGS = range(7)
+FLAG_DEBUG = 1
+TUNE_RASTER_THREADS, TUNE_BIN_MIN, TUNE_PHYS_PERSISTENT, TUNE_RASTER_PERSISTENT, TUNE_GRAPHS = 1, 2, 3, 4, 5
+GROUND = 0xFFFF
+
+EXPORTS = [
+    "vuda_create_world", "vuda_destroy_world", "vuda_cosched", "vuda_step", "vuda_render",
+    "vuda_wait", "vuda_fetch", "vuda_fetch_bytes", "vuda_load_state", "vuda_get_stream",
+    "vuda_admit", "vuda_release", "vuda_world_info", "vuda_set_tuning", "vuda_get_tuning",
+    "vuda_probe_placement", "vuda_strerror", "vuda_last_error_message",
+]
+
+
+class VudaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class PhysParams(C.Structure):
+    _fields_ = [("dt", C.c_float), ("substeps", C.c_int32), ("k_contact", C.c_float),
+                ("c_damp", C.c_float), ("gravity", C.c_float * 3)]
+
+
+class RenderDesc(C.Structure):
+    _fields_ = [
+        ("sphere_v", C.c_void_p), ("sphere_nv", C.c_int32), ("sphere_f", C.c_void_p),
+        ("sphere_n", C.c_void_p), ("sphere_nf", C.c_int32),
+        ("cube_v", C.c_void_p), ("cube_nv", C.c_int32), ("cube_f", C.c_void_p),
+        ("cube_n", C.c_void_p), ("cube_nf", C.c_int32),
+        ("ground_v", C.c_void_p), ("ground_nv", C.c_int32), ("ground_f", C.c_void_p),
+        ("ground_nf", C.c_int32),
+        ("light", C.c_float * 3), ("palette", C.c_float * 24), ("ground_albedo", C.c_float),
+        ("near_w", C.c_float), ("guard", C.c_float)]
+
+
+class EnvBatch(C.Structure):
+    _fields_ = [
+        ("n_envs", C.c_int32), ("body_off", C.c_void_p),
+        ("type", C.c_void_p), ("size", C.c_void_p), ("rbound", C.c_void_p),
+        ("inv_m", C.c_void_p), ("inv_I", C.c_void_p), ("albedo", C.c_void_p),
+        ("pos", C.c_void_p), ("vel", C.c_void_p), ("quat", C.c_void_p), ("omega", C.c_void_p),
+        ("cam_off", C.c_void_p), ("cam_vp", C.c_void_p), ("cam_w", C.c_void_p), ("cam_h", C.c_void_p)]
+
+
+class WorldDesc(C.Structure):
+    _fields_ = [("phys", PhysParams), ("render", RenderDesc), ("initial", EnvBatch),
+                ("flags", C.c_uint32), ("cap_envs", C.c_int32), ("cap_bodies", C.c_int64),
+                ("cap_cams", C.c_int32), ("cap_pixels", C.c_int64), ("pair_cap", C.c_int32),
+                ("hbm_budget", C.c_uint64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libvuda.so; raises if it is missing (build it first)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run paper_2605_01352_amd/build.py "
+                               f"(or __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        for name in EXPORTS:
+            getattr(L, name)  # raises AttributeError if missing
+        L.vuda_strerror.restype = C.c_char_p
+        L.vuda_last_error_message.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def check(code: int):
+    if code != 0:
+        L = lib()
+        raise VudaError(code, L.vuda_last_error_message().decode(errors="replace"))
+    return code
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+class _Keep:
+    """Holds contiguous copies of arrays referenced by a ctypes struct."""
+
+    def __init__(self):
+        self.arrs = []
+
+    def __call__(self, a, dtype):
+        a = np.ascontiguousarray(a, dtype=dtype)
+        self.arrs.append(a)
+        return a
+
+
+def render_desc(keep: _Keep, light=None, palette=None, ground_albedo=None, near=None, guard=None):
+    from . import scenegen as sg
+    t = sg.templates()
+    sv, sf, sn = keep(t.sphere_v, np.float32), keep(t.sphere_f, np.int32), keep(t.sphere_n, np.float32)
+    cv, cf, cn = keep(t.cube_v, np.float32), keep(t.cube_f, np.int32), keep(t.cube_n, np.float32)
+    gv, gf = keep(t.ground_v, np.float32), keep(t.ground_f, np.int32)
+    light = sg.LIGHT if light is None else light
+    palette = sg.PALETTE if palette is None else palette
+    return RenderDesc(
+        _p(sv), len(sv), _p(sf), _p(sn), len(sf), _p(cv), len(cv), _p(cf), _p(cn), len(cf),
+        _p(gv), len(gv), _p(gf), len(gf),
+        (C.c_float * 3)(*np.asarray(light, np.float32).tolist()),
+        (C.c_float * 24)(*np.asarray(palette, np.float32).reshape(-1).tolist()),
+        float(sg.GROUND_ALBEDO if ground_albedo is None else ground_albedo),
+        float(sg.NEAR if near is None else near), float(sg.GUARD_BAND if guard is None else guard))
+
+
+def env_batch(keep: _Keep, scene, state: Optional[Dict[str, np.ndarray]] = None) -> EnvBatch:
+    st = scene.state() if state is None else state
+    if scene.n_envs == 0:
+        return EnvBatch(0)
+    return EnvBatch(
+        scene.n_envs, _p(keep(scene.body_off, np.int32)), _p(keep(scene.btype, np.uint8)),
+        _p(keep(scene.size, np.float32)), _p(keep(scene.rbound, np.float32)),
+        _p(keep(scene.inv_m, np.float32)), _p(keep(scene.inv_I, np.float32)),
+        _p(keep(scene.albedo, np.uint8)), _p(keep(st["pos"], np.float32)),
+        _p(keep(st["vel"], np.float32)), _p(keep(st["quat"], np.float32)),
+        _p(keep(st["omega"], np.float32)), _p(keep(scene.cam_off, np.int32)),
+        _p(keep(scene.cam_vp, np.float32)), _p(keep(scene.cam_w, np.int32)),
+        _p(keep(scene.cam_h, np.int32)))
+
+
+def state_to_aos(st: Dict[str, np.ndarray]) -> np.ndarray:
+    return np.concatenate([st["pos"], st["vel"], st["quat"], st["omega"]], axis=1).astype(np.float32)
+
+
+def aos_to_state(a: np.ndarray) -> Dict[str, np.ndarray]:
+    a = np.asarray(a, np.float32).reshape(-1, 13)
+    return dict(pos=a[:, 0:3].copy(), vel=a[:, 3:6].copy(), quat=a[:, 6:10].copy(),
+                omega=a[:, 10:13].copy())
+
+
+class World:
+    """A batch of envs resident on the current HIP device."""
+
+    def __init__(self, scene=None, debug: bool = False, cap_envs: int = 0, cap_bodies: int = 0,
+                 cap_cams: int = 0, cap_pixels: int = 0, pair_cap: int = 1024,
+                 hbm_budget: int = 0, phys=None, render_kw=None):
+        L = lib()
+        keep = _Keep()
+        from . import scenegen as sg
+        ref = scene
+        dt = (ref.dt if ref is not None else 1.0 / 240.0)
+        sub = (ref.substeps if ref is not None else 4)
+        k = (ref.k_contact if ref is not None else 1.0e4)
+        c = (ref.c_damp if ref is not None else 10.0)
+        g = (ref.gravity if ref is not None else (0.0, 0.0, -9.81))
+        if phys:
+            dt, sub, k, c, g = phys.get("dt", dt), phys.get("substeps", sub), phys.get("k", k), \
+                phys.get("c", c), phys.get("g", g)
+        desc = WorldDesc()
+        desc.phys = PhysParams(float(np.float32(dt)), int(sub), float(k), float(c),
+                               (C.c_float * 3)(*[float(x) for x in g]))
+        desc.render = render_desc(keep, **(render_kw or {}))
+        desc.initial = env_batch(keep, scene) if scene is not None else EnvBatch(0)
+        desc.flags = FLAG_DEBUG if debug else 0
+        desc.cap_envs, desc.cap_bodies, desc.cap_cams, desc.cap_pixels = cap_envs, cap_bodies, cap_cams, cap_pixels
+        desc.pair_cap = pair_cap
+        desc.hbm_budget = hbm_budget
+        self._w = C.c_void_p()
+        check(L.vuda_create_world(C.byref(desc), None, C.byref(self._w)))
+        self.scene = scene
+        self.debug = debug
+        self.substeps = int(sub)
+        self.pair_cap = pair_cap
+        self.n_envs = scene.n_envs if scene is not None else 0
+
+    # -- lifetime --------------------------------------------------------
+    def close(self):
+        if self._w:
+            check(lib().vuda_destroy_world(self._w))
+            self._w = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- the loop ---------------------------------------------------------
+    def cosched(self, split: float):
+        check(lib().vuda_cosched(self._w, C.c_float(split)))
+
+    def step(self, lo: int = 0, hi: Optional[int] = None, nsteps: int = 1):
+        hi = self.n_envs if hi is None else hi
+        check(lib().vuda_step(self._w, lo, hi, nsteps))
+
+    def render(self, lo: int = 0, hi: Optional[int] = None):
+        hi = self.n_envs if hi is None else hi
+        check(lib().vuda_render(self._w, lo, hi))
+
+    def wait(self, phase: int = PHASE_ALL):
+        check(lib().vuda_wait(self._w, phase))
+
+    def set_tuning(self, key: int, value: int):
+        check(lib().vuda_set_tuning(self._w, key, int(value)))
+
+    def get_tuning(self, key: int) -> int:
+        v = C.c_int32()
+        check(lib().vuda_get_tuning(self._w, key, C.byref(v)))
+        return v.value
+
+    def stream(self, phase: int) -> int:
+        p = C.c_void_p()
+        check(lib().vuda_get_stream(self._w, phase, C.byref(p)))
+        return p.value or 0
+
+    def probe_placement(self, phase: int, n_blocks: int, spin_us: int = 200) -> np.ndarray:
+        out = np.zeros((n_blocks, 3), np.int32)
+        check(lib().vuda_probe_placement(self._w, phase, n_blocks, spin_us, _p(out)))
+        return out
+
+    # -- results ------------------------------------------------------------
+    def fetch_bytes(self, what: int, lo: int = 0, hi: Optional[int] = None) -> int:
+        hi = self.n_envs if hi is None else hi
+        n = C.c_size_t()
+        check(lib().vuda_fetch_bytes(self._w, what, lo, hi, C.byref(n)))
+        return n.value
+
+    def fetch(self, what: int, lo: int = 0, hi: Optional[int] = None, out=None):
+        """Copy results into a numpy array (or a torch CUDA tensor given as out)."""
+        hi = self.n_envs if hi is None else hi
+        nbytes = self.fetch_bytes(what, lo, hi)
+        if out is not None and hasattr(out, "data_ptr"):
+            if out.numel() * out.element_size() < nbytes:
+                raise ValueError("output tensor too small")
+            check(lib().vuda_fetch(self._w, what, lo, hi, C.c_void_p(out.data_ptr()),
+                                   C.c_size_t(nbytes), 1 if out.is_cuda else 0))
+            return out
+        dt = {FETCH_STATE: np.float32, FETCH_RGB: np.uint8, FETCH_DEPTH: np.uint32,
+              FETCH_CONTACTS: np.int32, FETCH_WINNERS: np.int32, FETCH_COVERAGE: np.int32,
+              FETCH_FLAGS: np.uint32}[what]
+        buf = np.zeros(nbytes // np.dtype(dt).itemsize, dt)
+        check(lib().vuda_fetch(self._w, what, lo, hi, _p(buf), C.c_size_t(nbytes), 0))
+        return buf
+
+    def state(self, lo: int = 0, hi: Optional[int] = None) -> Dict[str, np.ndarray]:
+        return aos_to_state(self.fetch(FETCH_STATE, lo, hi))
+
+    def load_state(self, st: Dict[str, np.ndarray], lo: int = 0, hi: Optional[int] = None):
+        hi = self.n_envs if hi is None else hi
+        a = np.ascontiguousarray(state_to_aos(st))
+        check(lib().vuda_load_state(self._w, lo, hi, _p(a), C.c_size_t(a.nbytes)))
+
+    def images(self, what: int, scene=None, lo: int = 0, hi: Optional[int] = None):
+        """List of per-camera images of envs [lo, hi)."""
+        scene = self.scene if scene is None else scene
+        hi = self.n_envs if hi is None else hi
+        flat = self.fetch(what, lo, hi)
+        out, pos = [], 0
+        for c in range(int(scene.cam_off[lo]), int(scene.cam_off[hi])):
+            w, h = int(scene.cam_w[c]), int(scene.cam_h[c])
+            ch = 3 if what == FETCH_RGB else 1
+            img = flat[pos:pos + w * h * ch]
+            out.append(img.reshape(h, w, 3) if ch == 3 else img.reshape(h, w))
+            pos += w * h * ch
+        return out
+
+    def contacts(self, lo: int = 0, hi: Optional[int] = None):
+        """Per env, per substep: sorted (i, j) pair arrays."""
+        hi = self.n_envs if hi is None else hi
+        flat = self.fetch(FETCH_CONTACTS, lo, hi).reshape(hi - lo, self.substeps, 1 + 2 * self.pair_cap)
+        res = []
+        for e in range(hi - lo):
+            per = []
+            for s in range(self.substeps):
+                n = int(flat[e, s, 0])
+                if n > self.pair_cap:
+                    raise VudaError(EOVERFLOW, f"env {lo + e}: {n} contact pairs > pair_cap")
+                per.append(flat[e, s, 1:1 + 2 * n].reshape(n, 2).copy())
+            res.append(per)
+        return res
+
+    # -- serving -----------------------------------------------------------
+    def admit(self, scene, parity: int = 0) -> int:
+        keep = _Keep()
+        b = env_batch(keep, scene)
+        first = C.c_int32()
+        check(lib().vuda_admit(self._w, C.byref(b), parity, C.byref(first)))
+        self.n_envs = max(self.n_envs, first.value + scene.n_envs)
+        return first.value
+
+    def try_admit(self, scene, parity: int = 0) -> Optional[int]:
+        keep = _Keep()
+        b = env_batch(keep, scene)
+        first = C.c_int32()
+        rc = lib().vuda_admit(self._w, C.byref(b), parity, C.byref(first))
+        if rc == EBUSY:
+            return None
+        check(rc)
+        self.n_envs = max(self.n_envs, first.value + scene.n_envs)
+        return first.value
+
+    def release(self, first: int, n: int):
+        check(lib().vuda_release(self._w, first, n))
+
+    def info(self):
+        ne, nb, nc, npx, ab = C.c_int32(), C.c_int64(), C.c_int32(), C.c_int64(), C.c_uint64()
+        check(lib().vuda_world_info(self._w, C.byref(ne), C.byref(nb), C.byref(nc), C.byref(npx), C.byref(ab)))
+        return dict(n_envs=ne.value, cap_bodies=nb.value, cap_cams=nc.value, cap_pixels=npx.value,
+                    arena_bytes=ab.value)

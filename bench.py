@@ -43,7 +43,9 @@ def enqueue(w, schedule, n_envs, iters):
             raise ValueError(schedule)
 
 
-def timed(torch, w, schedule, n_envs, steps, warmup):
+def timed(torch, w, schedule, n_envs, steps, warmup, st0=None):
+    if st0 is not None:
+        w.load_state(st0)  # every measurement starts from the same scene state
     enqueue(w, schedule, n_envs, warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -54,10 +56,12 @@ def timed(torch, w, schedule, n_envs, steps, warmup):
     return dt
 
 
-def kernel_times(torch, vuda, w, reps=20):
+def kernel_times(torch, vuda, w, st0, reps=20):
     """Average duration of one physics launch and one raster launch, timed
-    with HIP events on the stream the kernels run on (serialized mode)."""
+    with HIP events on the stream the kernels run on (serialized mode),
+    from the initial state."""
     w.cosched(0.0)
+    w.load_state(st0)
     s = torch.cuda.ExternalStream(w.stream(vuda.PHASE_STEP))
     out = {}
     for name in ("physics", "raster"):
@@ -111,6 +115,9 @@ def main():
     ap.add_argument("--envs", type=int, default=None, help="fewer envs (debug only)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--splits", default="0.25,0.375,0.5,0.625,0.75")
+    ap.add_argument("--profile", type=int, default=0,
+                    help="only run this many serialized then co-scheduled steps (for rocprofv3)")
+    ap.add_argument("--tune", default="", help="tuning knobs key=value,... (e.g. raster_threads=512)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the envs are independent and a multi-GPU run would "
@@ -130,29 +137,45 @@ def main():
     log(f"world: {n_envs} envs, {scene.n_bodies} bodies, {scene.n_cams} cameras, "
         f"{w.info()['arena_bytes'] / 2**20:.1f} MiB arena")
 
-    kt = kernel_times(torch, vuda, w)
+    st0 = scene.state()
+    knob_ids = {"raster_threads": vuda.TUNE_RASTER_THREADS, "rec_cap": vuda.TUNE_REC_CAP,
+                "phys_persistent": vuda.TUNE_PHYS_PERSISTENT,
+                "raster_persistent": vuda.TUNE_RASTER_PERSISTENT, "graphs": vuda.TUNE_GRAPHS}
+    for kv in filter(None, args.tune.split(",")):
+        k, v = kv.split("=")
+        w.set_tuning(knob_ids[k], int(v))
+    if args.profile:
+        w.cosched(0.0)
+        dt_s = timed(torch, w, "serial", n_envs, args.profile, 2, st0)
+        w.cosched(2.0)
+        dt_c = timed(torch, w, "interstep", n_envs, args.profile, 2, st0)
+        log(f"profile run: serialized {dt_s / args.profile * 1e6:.1f} us/step, "
+            f"co-scheduled {dt_c / args.profile * 1e6:.1f} us/step")
+        w.close()
+        return
+    kt = kernel_times(torch, vuda, w, st0)
     log(f"kernel times: physics {kt['physics']*1e6:.1f} us, raster {kt['raster']*1e6:.1f} us")
     Ts, Tr = kt["physics"], kt["raster"]
 
     results = {}
     w.cosched(0.0)
-    results["serialized"] = timed(torch, w, "serial", n_envs, args.steps, args.warmup)
+    results["serialized"] = timed(torch, w, "serial", n_envs, args.steps, args.warmup, st0)
     log(f"serialized: {n_envs * args.steps / results['serialized']:.0f} env-steps/s")
     # co-scheduled candidates: unmasked streams and CU splits, both overlap patterns
     cands = [(2.0, sched) for sched in ("interstep", "intertraj")]
     cands += [(float(x), sched) for x in args.splits.split(",") for sched in ("interstep", "intertraj")]
     sweep = {}
-    short = max(20, args.steps // 5)
+    short = args.steps
     for split, sched in cands:
         w.cosched(split)
-        dt = timed(torch, w, sched, n_envs, short, 5)
+        dt = timed(torch, w, sched, n_envs, short, 5, st0)
         sweep[f"{sched}@{split:g}"] = n_envs * short / dt
         log(f"  {sched:9s} split {split:5g}: {n_envs * short / dt:.0f} env-steps/s")
     best = max(sweep, key=sweep.get)
     sched, split = best.split("@")
     split = float(split)
     w.cosched(split)
-    dt = timed(torch, w, sched, n_envs, args.steps, args.warmup)
+    dt = timed(torch, w, sched, n_envs, args.steps, args.warmup, st0)
     value = n_envs * args.steps / dt
     ser = n_envs * args.steps / results["serialized"]
     log(f"co-scheduled ({best}): {value:.0f} env-steps/s, {value / ser:.3f}x serialized, "

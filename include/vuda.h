@@ -226,7 +226,10 @@ int vuda_world_info(vuda_world* w, int32_t* n_envs, int64_t* n_bodies, int32_t* 
 /*
  * Launch-shape knobs (the autotuner's search space).  Keys:
  *   VUDA_TUNE_RASTER_THREADS   raster workgroup size, multiple of 64 (default 256)
- *   VUDA_TUNE_BIN_MIN          minimum LDS bin entries per raster workgroup (2048)
+ *   VUDA_TUNE_REC_CAP          triangle setup records a raster workgroup keeps in
+ *                              LDS (0: automatic, 55% of the largest primitive
+ *                              count); images with more visible triangles take
+ *                              a slower path with the same output
  *   VUDA_TUNE_PHYS_PERSISTENT  0: one workgroup per env; n > 0: n resident
  *                              workgroups pulling envs from a device queue
  *   VUDA_TUNE_RASTER_PERSISTENT  the same for camera images
@@ -236,7 +239,7 @@ int vuda_world_info(vuda_world* w, int32_t* n_envs, int64_t* n_bodies, int32_t* 
  * or out-of-range values.
  */
 #define VUDA_TUNE_RASTER_THREADS 1
-#define VUDA_TUNE_BIN_MIN 2
+#define VUDA_TUNE_REC_CAP 2
 #define VUDA_TUNE_PHYS_PERSISTENT 3
 #define VUDA_TUNE_RASTER_PERSISTENT 4
 #define VUDA_TUNE_GRAPHS 5

@@ -32,7 +32,11 @@ struct EnvDev {
   int32_t n_cams;
   int32_t n_verts;    // template vertices of all bodies + ground
   int32_t n_tris;     // primitives: ground faces + template faces of all bodies
+  int64_t prim_map;   // offset of the env's primitive -> body map
+  int64_t vert_map;   // offset of the env's vertex -> body map
 };
+
+constexpr uint8_t kGroundBody = 0xFF;  // body id of ground primitives in the maps
 
 struct CamDev {
   float vp[16];
@@ -43,7 +47,7 @@ struct CamDev {
 };
 
 // Mesh templates and shading constants (device copy of the descriptor).
-struct Templates {
+struct alignas(16) Templates {
   float sphere_v[kMaxTplVerts][3];
   float cube_v[kMaxTplVerts][3];
   float ground_v[kMaxGroundVerts][3];
@@ -81,6 +85,8 @@ struct WorldDev {
   const float* inv_I;
   const int32_t* prim_base;  // env-local primitive id of the body's first face
   const int32_t* vert_base;  // env-local vertex index of the body's first vertex
+  const uint8_t* prim_body;  // per env: body of each primitive (kGroundBody: ground)
+  const uint8_t* vert_body;  // per env: body of each template vertex
   // dynamic state: state[buf][comp * cap_bodies + body]
   float* state[2];
   int64_t cap_bodies;
@@ -113,9 +119,10 @@ struct RasterLaunch {
   int32_t max_verts;       // over the listed cameras' envs
   int32_t max_tiles;
   int32_t max_bodies;
+  int32_t max_tris;
   int32_t parity;          // state buffer rendered
   int32_t threads;         // workgroup size (multiple of 64)
-  int32_t bin_cap;         // bin entries held in LDS at once
+  int32_t rec_cap;         // triangle setup records held in LDS
   int32_t persistent;
   int32_t* queue;
 };

@@ -57,7 +57,7 @@ struct WorkList {
 
 struct Tuning {
   int32_t raster_threads = 256;
-  int32_t bin_min = 2048;
+  int32_t rec_cap = 0;  // 0: automatic
   int32_t phys_persistent = 0;
   int32_t raster_persistent = 0;
   bool graphs = false;
@@ -83,7 +83,7 @@ struct vuda_world {
   vuda_allocator allocator{};
   bool has_allocator = false;
   struct {
-    size_t envs, cams, type, albedo, size, rbound, inv_m, inv_I, prim_base, vert_base, state0,
+    size_t envs, cams, type, albedo, size, rbound, inv_m, inv_I, prim_base, vert_base, prim_body, vert_body, state0,
         state1, rgb, depth, flags, tpl, queues, winners, coverage, contacts;
   } off_{};
   vuda::WorldDev dev{};
@@ -94,7 +94,8 @@ struct vuda_world {
   std::vector<uint8_t> env_parity;
   std::vector<uint8_t> env_active;
   std::vector<vuda::CamDev> cam_host;
-  vuda::RangeAlloc slots, bodies, camslots, pixels;
+  vuda::RangeAlloc slots, bodies, camslots, pixels, primspace, vertspace;
+  int64_t cap_prims = 0, cap_verts = 0;
 
   // streams: mode 0 serialized (s_sim == s_render == s_serial), 1 CU-masked,
   // 2 two unmasked streams
@@ -114,14 +115,15 @@ struct vuda_world {
   size_t lds_configured = 64 * 1024;
 
   int alloc_arena(const vuda_allocator* a);
-  int upload(const vuda_env_batch& b, int32_t e0, int64_t b0, int32_t c0, int64_t p0, int parity,
-             hipStream_t s);
+  int upload(const vuda_env_batch& b, int32_t e0, int64_t b0, int32_t c0, int64_t p0, int64_t m0,
+             int64_t v0, int parity, hipStream_t s);
+  void map_sizes(const vuda_env_batch& b, int64_t* prims, int64_t* verts) const;
   void free_all();
   int make_streams(float split);
   void destroy_streams();
   int drain();
   int new_event(hipStream_t s, int64_t* id);
-  int wait_events(hipStream_t s, const std::set<int64_t>& ids);
+  int wait_event(hipStream_t s, int64_t id);
   void invalidate_lists();
   int get_list(int phase, int32_t lo, int32_t hi, const vuda::WorkList** out);
   int range_parity(int32_t lo, int32_t hi, int* parity);

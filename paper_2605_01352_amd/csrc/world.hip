@@ -228,6 +228,8 @@ int vuda_world::alloc_arena(const vuda_allocator* a) {
   off_.inv_I = take(4 * B);
   off_.prim_base = take(4 * B);
   off_.vert_base = take(4 * B);
+  off_.prim_body = take(std::max<int64_t>(cap_prims, 1));
+  off_.vert_body = take(std::max<int64_t>(cap_verts, 1));
   off_.state0 = take(4 * (size_t)kStateComps * B);
   off_.state1 = take(4 * (size_t)kStateComps * B);
   off_.rgb = take(3 * P + 16);
@@ -269,6 +271,8 @@ int vuda_world::alloc_arena(const vuda_allocator* a) {
   dev.inv_I = (float*)(arena + off_.inv_I);
   dev.prim_base = (int32_t*)(arena + off_.prim_base);
   dev.vert_base = (int32_t*)(arena + off_.vert_base);
+  dev.prim_body = arena + off_.prim_body;
+  dev.vert_body = arena + off_.vert_body;
   dev.state[0] = (float*)(arena + off_.state0);
   dev.state[1] = (float*)(arena + off_.state1);
   dev.cap_bodies = B;
@@ -286,27 +290,57 @@ int vuda_world::alloc_arena(const vuda_allocator* a) {
 
 // Upload a batch of envs into slots [e0, e0 + n), bodies from b0, cameras
 // from c0, pixels from p0; state goes to buffer `parity`.
+// Per-env primitive and vertex maps start on 16-byte boundaries so that the
+// raster kernel can copy them with 16-byte loads.
+static int64_t map_round(int64_t n) { return (n + 15) & ~(int64_t)15; }
+
+void vuda_world::map_sizes(const vuda_env_batch& b, int64_t* prims, int64_t* verts) const {
+  int64_t np = 0, nv = 0;
+  for (int e = 0; e < b.n_envs; ++e) {
+    int64_t ep = tpl.ground_nf, ev = tpl.ground_nv;
+    for (int32_t i = b.body_off[e]; i < b.body_off[e + 1]; ++i) {
+      ep += b.type[i] ? tpl.cube_nf : tpl.sphere_nf;
+      ev += b.type[i] ? tpl.cube_nv : tpl.sphere_nv;
+    }
+    np += map_round(ep);
+    nv += map_round(ev);
+  }
+  *prims = np;
+  *verts = nv;
+}
+
 int vuda_world::upload(const vuda_env_batch& b, int32_t e0, int64_t b0, int32_t c0, int64_t p0,
-                       int parity, hipStream_t s) {
+                       int64_t m0, int64_t v0, int parity, hipStream_t s) {
   const int64_t nb = b.n_envs ? b.body_off[b.n_envs] : 0;
   const int32_t nc = b.n_envs ? b.cam_off[b.n_envs] : 0;
   std::vector<EnvDev> envs(b.n_envs);
   std::vector<int32_t> pbase(nb), vbase(nb);
+  std::vector<uint8_t> pmap, vmap;
   for (int e = 0; e < b.n_envs; ++e) {
     EnvDev& d = envs[e];
     d.body_off = (int32_t)(b0 + b.body_off[e]);
     d.n_bodies = b.body_off[e + 1] - b.body_off[e];
     d.cam_off = c0 + b.cam_off[e];
     d.n_cams = b.cam_off[e + 1] - b.cam_off[e];
+    d.prim_map = m0 + (int64_t)pmap.size();
+    d.vert_map = v0 + (int64_t)vmap.size();
+    pmap.insert(pmap.end(), tpl.ground_nf, kGroundBody);
+    vmap.insert(vmap.end(), tpl.ground_nv, kGroundBody);
     int32_t pv = tpl.ground_nf, vv = tpl.ground_nv;
     for (int32_t i = b.body_off[e]; i < b.body_off[e + 1]; ++i) {
       pbase[i] = pv;
       vbase[i] = vv;
-      pv += b.type[i] ? tpl.cube_nf : tpl.sphere_nf;
-      vv += b.type[i] ? tpl.cube_nv : tpl.sphere_nv;
+      const int nf = b.type[i] ? tpl.cube_nf : tpl.sphere_nf;
+      const int nvt = b.type[i] ? tpl.cube_nv : tpl.sphere_nv;
+      pmap.insert(pmap.end(), nf, (uint8_t)(i - b.body_off[e]));
+      vmap.insert(vmap.end(), nvt, (uint8_t)(i - b.body_off[e]));
+      pv += nf;
+      vv += nvt;
     }
     d.n_tris = pv;
     d.n_verts = vv;
+    pmap.resize(map_round((int64_t)pmap.size()), kGroundBody);
+    vmap.resize(map_round((int64_t)vmap.size()), kGroundBody);
   }
   std::vector<CamDev> cams(nc);
   int64_t po = p0;
@@ -344,6 +378,8 @@ int vuda_world::upload(const vuda_env_batch& b, int32_t e0, int64_t b0, int32_t 
   HIPCHK(up((void*)(dev.inv_I + b0), b.inv_I, 4 * nb));
   HIPCHK(up((void*)(dev.prim_base + b0), pbase.data(), 4 * nb));
   HIPCHK(up((void*)(dev.vert_base + b0), vbase.data(), 4 * nb));
+  HIPCHK(up((void*)(dev.prim_body + m0), pmap.data(), pmap.size()));
+  HIPCHK(up((void*)(dev.vert_body + v0), vmap.data(), vmap.size()));
   for (int k = 0; k < kStateComps; ++k)
     HIPCHK(up(dev.state[parity] + k * dev.cap_bodies + b0, st.data() + k * nb, 4 * nb));
   // flags of the new envs start clear
@@ -385,6 +421,16 @@ extern "C" int vuda_create_world(const vuda_world_desc* d, const vuda_allocator*
   w->cap_pixels = std::max(d->cap_pixels, npix);
   w->hbm_budget = d->hbm_budget;
   fill_templates(w->tpl, d->render);
+  int64_t init_prims = 0, init_verts = 0;
+  w->map_sizes(d->initial, &init_prims, &init_verts);
+  {
+    // room for the maps of envs admitted later: every body at its largest template
+    const int64_t mf = std::max(w->tpl.sphere_nf, w->tpl.cube_nf);
+    const int64_t mv = std::max(w->tpl.sphere_nv, w->tpl.cube_nv);
+    const int64_t spare_b = w->cap_bodies - nb, spare_e = (int64_t)w->cap_envs - d->initial.n_envs;
+    w->cap_prims = init_prims + spare_b * mf + spare_e * (w->tpl.ground_nf + 15);
+    w->cap_verts = init_verts + spare_b * mv + spare_e * (w->tpl.ground_nv + 15);
+  }
   w->pc.h = d->phys.dt / (float)d->phys.substeps;
   w->pc.hh = 0.5f * w->pc.h;
   w->pc.k = d->phys.k_contact;
@@ -408,6 +454,8 @@ extern "C" int vuda_create_world(const vuda_world_desc* d, const vuda_allocator*
   w->bodies.init(w->cap_bodies);
   w->camslots.init(w->cap_cams);
   w->pixels.init(w->cap_pixels);
+  w->primspace.init(w->cap_prims);
+  w->vertspace.init(w->cap_verts);
   rc = w->make_streams(0.0f);
   if (rc == VUDA_OK) {
     hipError_t e = hipMemcpy((void*)w->dev.tpl, &w->tpl, sizeof(Templates), hipMemcpyHostToDevice);
@@ -418,7 +466,9 @@ extern "C" int vuda_create_world(const vuda_world_desc* d, const vuda_allocator*
     w->bodies.take(0, nb);
     w->camslots.take(0, nc);
     w->pixels.take(0, npix);
-    rc = w->upload(d->initial, 0, 0, 0, 0, 0, w->s_serial);
+    w->primspace.take(0, init_prims);
+    w->vertspace.take(0, init_verts);
+    rc = w->upload(d->initial, 0, 0, 0, 0, 0, 0, 0, w->s_serial);
     w->n_envs_hi = d->initial.n_envs;
   }
   if (rc) {
@@ -562,12 +612,10 @@ int vuda_world::new_event(hipStream_t s, int64_t* id) {
   return VUDA_OK;
 }
 
-int vuda_world::wait_events(hipStream_t s, const std::set<int64_t>& ids) {
+int vuda_world::wait_event(hipStream_t s, int64_t id) {
   const int64_t kPool = (int64_t)evpool.size();
-  for (int64_t id : ids) {
-    if (id < 0 || id < next_event - kPool) continue;  // recycled: already complete
-    HIPCHK(hipStreamWaitEvent(s, evpool[id % kPool], 0));
-  }
+  if (id < 0 || id < next_event - kPool) return VUDA_OK;  // none, or recycled: already complete
+  HIPCHK(hipStreamWaitEvent(s, evpool[id % kPool], 0));
   return VUDA_OK;
 }
 
@@ -668,20 +716,25 @@ int vuda_world::raster_launch_of(const WorkList& L, int parity, RasterLaunch* ou
   rl.max_verts = std::max(L.max_verts, 1);
   rl.max_tiles = std::max(L.max_tiles, 1);
   rl.max_bodies = L.max_bodies;
+  rl.max_tris = std::max(L.max_tris, 1);
   rl.parity = parity;
   rl.threads = tune.raster_threads;
-  // bins: room for every primitive in one tile, at least bin_min entries
-  rl.bin_cap = std::max(L.max_tris, tune.bin_min);
+  // setup records: by default room for 55% of the primitives (front faces of
+  // closed meshes are about half); images with more take the slower path.
+  const int min_rec = L.max_tris / 12 + 1;  // the slower path's bins live in the same space
+  int rec = tune.rec_cap > 0 ? tune.rec_cap : (L.max_tris * 55 + 99) / 100;
+  rec = std::min(std::max(std::max(rec, min_rec), 64), 32767);  // 15-bit record ids in the bins
+  rl.rec_cap = rec;
   rl.persistent = tune.raster_persistent;
   rl.queue = queues + 1;
   size_t lds = raster_lds_bytes(rl);
   const size_t kLdsMax = 160 * 1024;
-  if (lds > kLdsMax) {
-    rl.bin_cap = L.max_tris;
+  while (lds > kLdsMax && rl.rec_cap > min_rec) {
+    rl.rec_cap = std::max(min_rec, rl.rec_cap * 3 / 4);
     lds = raster_lds_bytes(rl);
-    if (lds > kLdsMax)
-      return fail(VUDA_EOVERFLOW, "raster needs %zu bytes of LDS (max %zu)", lds, kLdsMax);
   }
+  if (lds > kLdsMax)
+    return fail(VUDA_EOVERFLOW, "raster needs %zu bytes of LDS (max %zu)", lds, kLdsMax);
   if (lds > lds_configured) {
     HIPCHK(raster_configure(lds));
     lds_configured = lds;
@@ -751,14 +804,13 @@ extern "C" int vuda_step(vuda_world* w, int32_t lo, int32_t hi, int32_t nsteps) 
   for (int t = 0; t < nsteps; ++t) {
     const int p = (parity + t) & 1;
     if (w->mode != 0) {
-      // RAW on the state read, WAR on the buffer written (renders reading it)
-      std::set<int64_t> ids;
-      for (int32_t e = lo; e < hi; ++e) {
-        if (!w->env_active[e]) continue;
-        ids.insert(w->step_ev[e]);
-        ids.insert(w->render_ev[p ^ 1][e]);
-      }
-      rc = w->wait_events(s, ids);
+      // WAR: the renders that read the buffer this step overwrites.  Earlier
+      // steps are on this same stream (RAW is implicit); events of one stream
+      // complete in order, so the latest one covers the others.
+      int64_t last = -1;
+      const int64_t* rev = w->render_ev[p ^ 1].data();
+      for (int32_t e = lo; e < hi; ++e) last = rev[e] > last ? rev[e] : last;
+      rc = w->wait_event(s, last);
       if (rc) return rc;
     }
     rc = w->run_phase(VUDA_PHASE_STEP, *L, p, lo, hi, s);
@@ -790,10 +842,11 @@ extern "C" int vuda_render(vuda_world* w, int32_t lo, int32_t hi) {
   if (rc) return rc;
   hipStream_t s = w->s_render;
   if (w->mode != 0) {
-    std::set<int64_t> ids;
-    for (int32_t e = lo; e < hi; ++e)
-      if (w->env_active[e]) ids.insert(w->step_ev[e]);  // RAW: the step that wrote the state
-    rc = w->wait_events(s, ids);
+    // RAW: the latest step that wrote the state rendered
+    int64_t last = -1;
+    const int64_t* sev = w->step_ev.data();
+    for (int32_t e = lo; e < hi; ++e) last = sev[e] > last ? sev[e] : last;
+    rc = w->wait_event(s, last);
     if (rc) return rc;
   }
   rc = w->run_phase(VUDA_PHASE_RENDER, *L, parity, lo, hi, s);
@@ -1008,22 +1061,30 @@ extern "C" int vuda_admit(vuda_world* w, const vuda_env_batch* b, int32_t parity
   if (b->n_envs == 0) return fail(VUDA_EINVAL, "empty request");
   const int64_t e0 = w->slots.alloc(b->n_envs);
   if (e0 < 0) return fail(VUDA_EBUSY, "no run of %d free env slots", b->n_envs);
+  int64_t nprim, nvert;
+  w->map_sizes(*b, &nprim, &nvert);
   const int64_t b0 = w->bodies.alloc(nb);
   const int64_t c0 = b0 < 0 ? -1 : w->camslots.alloc(nc);
   const int64_t p0 = c0 < 0 ? -1 : w->pixels.alloc(npix);
-  if (b0 < 0 || c0 < 0 || p0 < 0) {
+  const int64_t m0 = p0 < 0 ? -1 : w->primspace.alloc(nprim);
+  const int64_t v0 = m0 < 0 ? -1 : w->vertspace.alloc(nvert);
+  if (v0 < 0) {
     w->slots.release(e0, b->n_envs);
     if (b0 >= 0) w->bodies.release(b0, nb);
     if (c0 >= 0) w->camslots.release(c0, nc);
+    if (p0 >= 0) w->pixels.release(p0, npix);
+    if (m0 >= 0) w->primspace.release(m0, nprim);
     return fail(VUDA_EBUSY, "no room for %lld bodies / %d cameras / %lld pixels", (long long)nb, nc,
                 (long long)npix);
   }
-  rc = w->upload(*b, (int32_t)e0, b0, (int32_t)c0, p0, parity, w->s_serial);
+  rc = w->upload(*b, (int32_t)e0, b0, (int32_t)c0, p0, m0, v0, parity, w->s_serial);
   if (rc) {
     w->slots.release(e0, b->n_envs);
     w->bodies.release(b0, nb);
     w->camslots.release(c0, nc);
     w->pixels.release(p0, npix);
+    w->primspace.release(m0, nprim);
+    w->vertspace.release(v0, nvert);
     return rc;
   }
   for (int e = 0; e < b->n_envs; ++e) {
@@ -1060,6 +1121,8 @@ extern "C" int vuda_release(vuda_world* w, int32_t first, int32_t n) {
   w->bodies.release(d0.body_off, nb);
   w->camslots.release(d0.cam_off, nc);
   w->pixels.release(p0, np);
+  w->primspace.release(d0.prim_map, d1.prim_map + d1.n_tris - d0.prim_map);
+  w->vertspace.release(d0.vert_map, d1.vert_map + d1.n_verts - d0.vert_map);
   w->slots.release(first, n);
   for (int32_t e = first; e < first + n; ++e) {
     w->env_active[e] = 0;
@@ -1080,9 +1143,9 @@ extern "C" int vuda_set_tuning(vuda_world* w, int32_t key, int32_t value) {
       if (value < 64 || value > 1024 || value % 64) return fail(VUDA_EINVAL, "raster threads %d", value);
       w->tune.raster_threads = value;
       break;
-    case VUDA_TUNE_BIN_MIN:
-      if (value < 0 || value > (1 << 16)) return fail(VUDA_EINVAL, "bin_min %d", value);
-      w->tune.bin_min = value;
+    case VUDA_TUNE_REC_CAP:
+      if (value < 0 || value > 32767) return fail(VUDA_EINVAL, "rec_cap %d", value);
+      w->tune.rec_cap = value;
       break;
     case VUDA_TUNE_PHYS_PERSISTENT:
       if (value < 0) return fail(VUDA_EINVAL, "persistent %d", value);
@@ -1107,7 +1170,7 @@ extern "C" int vuda_get_tuning(vuda_world* w, int32_t key, int32_t* value) {
   if (!w || !value) return fail(VUDA_EINVAL, "null argument");
   switch (key) {
     case VUDA_TUNE_RASTER_THREADS: *value = w->tune.raster_threads; break;
-    case VUDA_TUNE_BIN_MIN: *value = w->tune.bin_min; break;
+    case VUDA_TUNE_REC_CAP: *value = w->tune.rec_cap; break;
     case VUDA_TUNE_PHYS_PERSISTENT: *value = w->tune.phys_persistent; break;
     case VUDA_TUNE_RASTER_PERSISTENT: *value = w->tune.raster_persistent; break;
     case VUDA_TUNE_GRAPHS: *value = w->tune.graphs ? 1 : 0; break;

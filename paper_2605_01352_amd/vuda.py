@@ -20,7 +20,7 @@ OK, EINVAL, ENOMEM, EHIP, ENUMERIC, EOVERFLOW, EBUSY = 0, -1, -2, -3, -4, -5, -6
 PHASE_STEP, PHASE_RENDER, PHASE_ALL = 1, 2, 3
 FETCH_STATE, FETCH_RGB, FETCH_DEPTH, FETCH_CONTACTS, FETCH_WINNERS, FETCH_COVERAGE, FETCH_FLAGS = range(7)
 FLAG_DEBUG = 1
-TUNE_RASTER_THREADS, TUNE_BIN_MIN, TUNE_PHYS_PERSISTENT, TUNE_RASTER_PERSISTENT, TUNE_GRAPHS = 1, 2, 3, 4, 5
+TUNE_RASTER_THREADS, TUNE_REC_CAP, TUNE_PHYS_PERSISTENT, TUNE_RASTER_PERSISTENT, TUNE_GRAPHS = 1, 2, 3, 4, 5
 GROUND = 0xFFFF
 
 EXPORTS = [

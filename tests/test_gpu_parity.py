@@ -112,7 +112,7 @@ def test_tuning_knobs_do_not_change_outputs():
     s = sg.config_scene(4, n_envs=24)
     ref = None
     for knobs in ({}, {vuda.TUNE_RASTER_THREADS: 64}, {vuda.TUNE_RASTER_THREADS: 1024},
-                  {vuda.TUNE_BIN_MIN: 0}, {vuda.TUNE_PHYS_PERSISTENT: 7, vuda.TUNE_RASTER_PERSISTENT: 5},
+                  {vuda.TUNE_REC_CAP: 64}, {vuda.TUNE_REC_CAP: 5000}, {vuda.TUNE_PHYS_PERSISTENT: 7, vuda.TUNE_RASTER_PERSISTENT: 5},
                   {vuda.TUNE_GRAPHS: 1}):
         with vuda.World(s) as w:
             for k, v in knobs.items():

@@ -140,7 +140,8 @@ def main():
     st0 = scene.state()
     knob_ids = {"raster_threads": vuda.TUNE_RASTER_THREADS, "rec_cap": vuda.TUNE_REC_CAP,
                 "phys_persistent": vuda.TUNE_PHYS_PERSISTENT,
-                "raster_persistent": vuda.TUNE_RASTER_PERSISTENT, "graphs": vuda.TUNE_GRAPHS}
+                "raster_persistent": vuda.TUNE_RASTER_PERSISTENT, "graphs": vuda.TUNE_GRAPHS,
+                "phys_prio": vuda.TUNE_PHYS_PRIORITY, "broadphase": vuda.TUNE_BROADPHASE}
     for kv in filter(None, args.tune.split(",")):
         k, v = kv.split("=")
         w.set_tuning(knob_ids[k], int(v))

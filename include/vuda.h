@@ -235,6 +235,11 @@ int vuda_world_info(vuda_world* w, int32_t* n_envs, int64_t* n_bodies, int32_t* 
  *   VUDA_TUNE_RASTER_PERSISTENT  the same for camera images
  *   VUDA_TUNE_GRAPHS           1: each (phase, env range, parity) launch is
  *                              captured once into a hipGraph and replayed
+ *   VUDA_TUNE_PHYS_PRIORITY    0..3: instruction-issue priority of the physics
+ *                              waves relative to render waves on shared CUs
+ *   VUDA_TUNE_BROADPHASE       0 automatic (all pairs up to 64 bodies, uniform
+ *                              grid hash above), 1 grid hash, 2 all pairs;
+ *                              both give the same candidate set
  * None of them changes any output bit.  Returns VUDA_EINVAL for unknown keys
  * or out-of-range values.
  */
@@ -243,6 +248,8 @@ int vuda_world_info(vuda_world* w, int32_t* n_envs, int64_t* n_bodies, int32_t* 
 #define VUDA_TUNE_PHYS_PERSISTENT 3
 #define VUDA_TUNE_RASTER_PERSISTENT 4
 #define VUDA_TUNE_GRAPHS 5
+#define VUDA_TUNE_PHYS_PRIORITY 6
+#define VUDA_TUNE_BROADPHASE 7
 int vuda_set_tuning(vuda_world* w, int32_t key, int32_t value);
 int vuda_get_tuning(vuda_world* w, int32_t key, int32_t* value);
 

@@ -75,6 +75,7 @@ struct PhysLDS {
   static constexpr int N = 64 * NW;
   static constexpr int CAPC = 8 * N;  // candidate pairs
   static constexpr int CAPK = 4 * N;  // contact pairs
+  float4 pr[N];  // position and bounding radius, for the all-pairs broadphase
   float p[3][N];
   float v[3][N];
   float w[3][N];
@@ -99,21 +100,29 @@ struct PhysLDS {
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 // Exclusive prefix sum over the workgroup (thread order); *total gets the sum.
+// Inclusive wave64 prefix sum with DPP row shifts and row broadcasts (VALU
+// only); lanes reading outside their row take 0.
+__device__ __forceinline__ int wave_incl_add(int x) {
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return x;
+}
+
 template <int NW>
 __device__ __forceinline__ int block_excl_scan(int v, int32_t* tmp, int* total) {
   const int lane = lane_id();
-  int x = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    int y = __shfl_up(x, d, 64);
-    if (lane >= d) x += y;
-  }
+  const int x = wave_incl_add(v);
   if (NW == 1) {
-    *total = __shfl(x, 63, 64);
+    *total = __builtin_amdgcn_readlane(x, 63);
     return x - v;
   }
   const int wv = threadIdx.x >> 6;
   if (lane == 63) tmp[wv] = x;
+  (void)lane;
   __syncthreads();
   int base = 0, tot = 0;
 #pragma unroll
@@ -356,7 +365,7 @@ __device__ __forceinline__ int popc_below(const uint64_t* row, int b) {
 
 template <int NW>
 __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc, int env,
-                         int parity) {
+                         int parity, int broadphase) {
   constexpr int N = PhysLDS<NW>::N;
   const int tid = threadIdx.x;
   const EnvDev ed = W.envs[env];
@@ -397,12 +406,15 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
   const uint32_t hmask = (uint32_t)(T - 1);
   const f3 gvec = mk(pc.g[0], pc.g[1], pc.g[2]);
   bool bad = false;
+  // broadphase choice: 0 auto (grid above 64 bodies), 1 grid, 2 all-pairs
+  const bool use_grid = broadphase == 1 || (broadphase == 0 && n > 64);
 
   for (int sub_i = 0; sub_i < pc.substeps; ++sub_i) {
     // 1. publish substep-start state
     M3 R = quat_to_rot(qw, qx, qy, qz);
     if (own) {
       s.p[0][tid] = p.x; s.p[1][tid] = p.y; s.p[2][tid] = p.z;
+      s.pr[tid] = make_float4(p.x, p.y, p.z, rbv);
       s.v[0][tid] = v.x; s.v[1][tid] = v.y; s.v[2][tid] = v.z;
       s.w[0][tid] = w.x; s.w[1][tid] = w.y; s.w[2][tid] = w.z;
 #pragma unroll
@@ -418,33 +430,67 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
       s.colC[tid][q] = 0ull;
     }
     if (tid == 0) s.flag = 0;
-    // 2. broadphase: cells far from the origin fall back to testing all pairs
+    // 2. broadphase.  The candidate set is exactly {(i, j): i < j,
+    // |p_i - p_j|^2 <= (R_i + R_j)^2}; two ways produce it.  All-pairs: every
+    // lane tests every body, reading it with one broadcast LDS load (no
+    // divergence) -- the faster choice for one wave.  Grid: bodies hashed into
+    // bitset buckets by cell, each lane ORs its own and the 13 half-shell
+    // neighbour buckets and tests only the bodies found.  Cells far from the
+    // origin fall back to all-pairs.
     int cx = 0, cy = 0, cz = 0;
-    if (own) {
+    if (use_grid && own) {
       const float fx = floorf(p.x * inv_c), fy = floorf(p.y * inv_c), fz = floorf(p.z * inv_c);
       if (!(fabsf(fx) < 1000.0f && fabsf(fy) < 1000.0f && fabsf(fz) < 1000.0f)) s.flag = 1;
       cx = (int)fx; cy = (int)fy; cz = (int)fz;
     }
     __syncthreads();
-    const bool brute = s.flag != 0;
-    if (own && !brute) {
-      const uint32_t h = grid_hash(cx, cy, cz, hmask);
-      atomicOr((unsigned long long*)&s.bucket[h][tid >> 6], 1ull << (tid & 63));
-    }
-    __syncthreads();
-    if (own) {
-      uint64_t M[NW];
-      if (brute) {
+    const bool grid = use_grid && s.flag == 0;
+    if (!grid && NW == 1) {
+      // one wave: body j's position is broadcast from lane j's registers
+      uint64_t row = 0ull;
+      for (int j = 0; j < n; ++j) {
+        const float bx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.x), j));
+        const float by = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.y), j));
+        const float bz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.z), j));
+        const float br = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rbv), j));
+        const f3 d = mk(p.x - bx, p.y - by, p.z - bz);
+        const float rs = rbv + br;
+        if (j > tid && dot(d, d) <= rs * rs) row |= 1ull << j;
+      }
+      if (own) s.rowCand[tid][0] = row;
+    } else if (!grid) {
+      if (own) {
+        uint64_t row[NW];
 #pragma unroll
-        for (int q = 0; q < NW; ++q) {
-          const int lo = 64 * q;
-          M[q] = n - lo >= 64 ? ~0ull : (n - lo <= 0 ? 0ull : ((1ull << (n - lo)) - 1ull));
+        for (int q = 0; q < NW; ++q) row[q] = 0ull;
+        const float4 me = s.pr[tid];
+        // j is the same in every lane: s.pr[j] is one broadcast load
+#pragma unroll 4
+        for (int j = 0; j < n; ++j) {
+          const float4 o = s.pr[j];
+          const f3 d = mk(me.x - o.x, me.y - o.y, me.z - o.z);
+          const float rs = me.w + o.w;
+          if (j > tid && dot(d, d) <= rs * rs) {
+#pragma unroll
+            for (int q = 0; q < NW; ++q)
+              if (q == (j >> 6)) row[q] |= 1ull << (j & 63);
+          }
         }
-      } else {
+#pragma unroll
+        for (int q = 0; q < NW; ++q) s.rowCand[tid][q] = row[q];
+      }
+    } else {
+      if (own) {
+        const uint32_t h = grid_hash(cx, cy, cz, hmask);
+        atomicOr((unsigned long long*)&s.bucket[h][tid >> 6], 1ull << (tid & 63));
+      }
+      __syncthreads();
+      if (own) {
+        uint64_t M[NW];
 #pragma unroll
         for (int q = 0; q < NW; ++q) M[q] = 0ull;
         // own cell and the 13 neighbours of the half shell
-#pragma unroll 1
+#pragma unroll
         for (int o = 0; o < 14; ++o) {
           int dx, dy, dz;
           if (o == 0) { dx = 0; dy = 0; dz = 0; }
@@ -455,21 +501,22 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
 #pragma unroll
           for (int q = 0; q < NW; ++q) M[q] |= s.bucket[h][q];
         }
-      }
 #pragma unroll
-      for (int q = 0; q < NW; ++q)
-        if (q == (tid >> 6)) M[q] &= ~(1ull << (tid & 63));
+        for (int q = 0; q < NW; ++q)
+          if (q == (tid >> 6)) M[q] &= ~(1ull << (tid & 63));
 #pragma unroll
-      for (int q = 0; q < NW; ++q) {
-        uint64_t m = M[q];
-        while (m) {
-          const int j = 64 * q + __ffsll((unsigned long long)m) - 1;
-          m &= m - 1ull;
-          const int lo = tid < j ? tid : j, hi = tid < j ? j : tid;
-          const f3 d = sub(ldsP(s, lo), ldsP(s, hi));
-          const float rs = s.rb[lo] + s.rb[hi];
-          if (dot(d, d) <= rs * rs)
-            atomicOr((unsigned long long*)&s.rowCand[lo][hi >> 6], 1ull << (hi & 63));
+        for (int q = 0; q < NW; ++q) {
+          uint64_t m = M[q];
+          while (m) {
+            const int j = 64 * q + __ffsll((unsigned long long)m) - 1;
+            m &= m - 1ull;
+            const int lo = tid < j ? tid : j, hi = tid < j ? j : tid;
+            const float4 a4 = s.pr[lo], b4 = s.pr[hi];
+            const f3 d = mk(a4.x - b4.x, a4.y - b4.y, a4.z - b4.z);
+            const float rs = a4.w + b4.w;
+            if (dot(d, d) <= rs * rs)
+              atomicOr((unsigned long long*)&s.rowCand[lo][hi >> 6], 1ull << (hi & 63));
+          }
         }
       }
     }
@@ -643,10 +690,18 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
 template <int NW>
 __global__ __launch_bounds__(64 * NW) void physics_kernel(WorldDev W, PhysConsts pc, PhysLaunch L) {
   __shared__ PhysLDS<NW> s;
+  // The step is latency-bound; a higher issue priority shortens it when it
+  // shares CUs with the render phase.
+  switch (L.prio) {
+    case 1: __builtin_amdgcn_s_setprio(1); break;
+    case 2: __builtin_amdgcn_s_setprio(2); break;
+    case 3: __builtin_amdgcn_s_setprio(3); break;
+    default: break;
+  }
   if (L.persistent == 0) {
     const int wi = blockIdx.x;
     if (wi >= L.n_work) return;
-    step_env<NW>(s, W, pc, L.work[wi], L.parity);
+    step_env<NW>(s, W, pc, L.work[wi], L.parity, L.broadphase);
     return;
   }
   for (;;) {
@@ -655,7 +710,7 @@ __global__ __launch_bounds__(64 * NW) void physics_kernel(WorldDev W, PhysConsts
     const int wi = s.work;
     __syncthreads();
     if (wi >= L.n_work) return;
-    step_env<NW>(s, W, pc, L.work[wi], L.parity);
+    step_env<NW>(s, W, pc, L.work[wi], L.parity, L.broadphase);
   }
 }
 

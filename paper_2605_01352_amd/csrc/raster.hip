@@ -27,6 +27,8 @@
 // Images whose records or bins do not fit the LDS budget take a slower path
 // that re-derives each triangle from the vertex cache per tile and bins
 // tiles in groups that fit; both paths produce identical bits.
+#include <cstddef>
+
 #include "vuda_internal.h"
 
 #pragma clang fp contract(off)
@@ -39,10 +41,21 @@ constexpr int kRecWords = 12;  // X0 Y0 X1 Y1 | X2 Y2 key z0 | z1 z2 invA rgb
 // per wave: tile z-buffer (256 x u64), coverage counts (256 x i32), fragment owners (64 x i32)
 constexpr int kWaveBytes = 256 * 8 + 256 * 4 + 64 * 4;
 
-// The whole template/shading struct is copied into LDS per workgroup.
-constexpr int kTplBytes = (int)sizeof(Templates);
-static_assert(kTplBytes % 16 == 0, "template copy in 16-byte words");
-typedef Templates TplLDS;
+// The template vertex and face tables (the leading members of Templates)
+// are copied into LDS per workgroup; normals and shading constants, used once
+// per visible triangle, stay in global memory.
+struct TplLDS {
+  float sphere_v[kMaxTplVerts][3];
+  float cube_v[kMaxTplVerts][3];
+  float ground_v[kMaxGroundVerts][3];
+  uint8_t sphere_f[kMaxTplFaces][3];
+  uint8_t cube_f[kMaxTplFaces][3];
+  uint8_t ground_f[kMaxGroundFaces][3];
+};
+constexpr int kTplBytes = ((int)sizeof(TplLDS) + 15) & ~15;
+static_assert(offsetof(Templates, sphere_v) == offsetof(TplLDS, sphere_v) &&
+              offsetof(Templates, ground_f) == offsetof(TplLDS, ground_f) &&
+              kTplBytes <= (int)sizeof(Templates), "template tables lead Templates");
 
 struct RasterLayout {
   // byte offsets into dynamic LDS
@@ -481,7 +494,7 @@ __device__ void raster_slow(unsigned char* lds, const RasterLayout& Lo, const Wo
                             const ImageCtx& im, bool* overflow) {
   const int tid = threadIdx.x;
   const int nthr = blockDim.x;
-  const Templates* tp = T;  // the workgroup's LDS copy
+  const Templates* tp = W.tpl;
   const int32_t* VX = (const int32_t*)(lds + Lo.verts);
   const int32_t* VY = VX + Lo.vmax;
   const float* VZ = (const float*)(VY + Lo.vmax);
@@ -635,7 +648,7 @@ __device__ void raster_image(unsigned char* lds, const RasterLayout& Lo, const W
   im.env = cam.env;
 
   TplLDS* T = (TplLDS*)(lds + Lo.tpl);
-  const Templates* tp = T;
+  const Templates* tp = W.tpl;
   uint8_t* pmap = lds + Lo.maps;
   uint8_t* vmap = pmap + align16(L.max_tris);
   BodyLDS B;

@@ -111,6 +111,8 @@ struct PhysLaunch {
   int32_t nsteps;
   int32_t persistent;      // 0: one workgroup per env; >0: that many resident workgroups
   int32_t* queue;          // persistent work counter (one int), nullable otherwise
+  int32_t prio;            // wave issue priority 0..3 (s_setprio) of the physics waves
+  int32_t broadphase;      // 0 auto, 1 uniform grid hash, 2 all pairs
 };
 
 struct RasterLaunch {

@@ -61,6 +61,8 @@ struct Tuning {
   int32_t phys_persistent = 0;
   int32_t raster_persistent = 0;
   bool graphs = false;
+  int32_t phys_prio = 0;
+  int32_t broadphase = 0;
 };
 
 }  // namespace vuda

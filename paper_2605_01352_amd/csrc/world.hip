@@ -705,6 +705,8 @@ int vuda_world::enqueue_physics(const WorkList& L, int parity, hipStream_t s) {
   pl.nsteps = 1;
   pl.persistent = tune.phys_persistent;
   pl.queue = queues;
+  pl.prio = tune.phys_prio;
+  pl.broadphase = tune.broadphase;
   HIPCHK(launch_physics(dev, pc, pl, s));
   return VUDA_OK;
 }
@@ -1158,6 +1160,14 @@ extern "C" int vuda_set_tuning(vuda_world* w, int32_t key, int32_t value) {
     case VUDA_TUNE_GRAPHS:
       w->tune.graphs = value != 0;
       break;
+    case VUDA_TUNE_PHYS_PRIORITY:
+      if (value < 0 || value > 3) return fail(VUDA_EINVAL, "priority %d", value);
+      w->tune.phys_prio = value;
+      break;
+    case VUDA_TUNE_BROADPHASE:
+      if (value < 0 || value > 2) return fail(VUDA_EINVAL, "broadphase %d", value);
+      w->tune.broadphase = value;
+      break;
     default:
       return fail(VUDA_EINVAL, "tuning key %d", key);
   }
@@ -1174,6 +1184,8 @@ extern "C" int vuda_get_tuning(vuda_world* w, int32_t key, int32_t* value) {
     case VUDA_TUNE_PHYS_PERSISTENT: *value = w->tune.phys_persistent; break;
     case VUDA_TUNE_RASTER_PERSISTENT: *value = w->tune.raster_persistent; break;
     case VUDA_TUNE_GRAPHS: *value = w->tune.graphs ? 1 : 0; break;
+    case VUDA_TUNE_PHYS_PRIORITY: *value = w->tune.phys_prio; break;
+    case VUDA_TUNE_BROADPHASE: *value = w->tune.broadphase; break;
     default: return fail(VUDA_EINVAL, "tuning key %d", key);
   }
   return VUDA_OK;

@@ -21,6 +21,8 @@ PHASE_STEP, PHASE_RENDER, PHASE_ALL = 1, 2, 3
 FETCH_STATE, FETCH_RGB, FETCH_DEPTH, FETCH_CONTACTS, FETCH_WINNERS, FETCH_COVERAGE, FETCH_FLAGS = range(7)
 FLAG_DEBUG = 1
 TUNE_RASTER_THREADS, TUNE_REC_CAP, TUNE_PHYS_PERSISTENT, TUNE_RASTER_PERSISTENT, TUNE_GRAPHS = 1, 2, 3, 4, 5
+TUNE_PHYS_PRIORITY = 6
+TUNE_BROADPHASE = 7
 GROUND = 0xFFFF
 
 EXPORTS = [

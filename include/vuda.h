@@ -264,6 +264,80 @@ int vuda_get_tuning(vuda_world* w, int32_t key, int32_t* value);
 int vuda_probe_placement(vuda_world* w, int32_t phase, int32_t n_blocks, int32_t spin_us,
                          int32_t* out);
 
+/* ---- schedules (vuda_run, autotuner, serving) -------------------------- */
+#define VUDA_SCHED_SERIAL    0  /* step then render, one stream                    */
+#define VUDA_SCHED_INTERSTEP 1  /* render S_t beside step S_t -> S_t+1 (double
+                                   buffered), the paper's inter-step pipelining     */
+#define VUDA_SCHED_INTERTRAJ 2  /* envs split in two halves: step(A) beside
+                                   render(B), then step(B) beside render(A), the
+                                   paper's inter-trajectory parallelism             */
+
+/*
+ * Enqueue `iters` iterations of a schedule over every active env: each
+ * iteration advances every env one step and renders it once (Parallelism
+ * Patterns: inter-step and inter-trajectory overlap).  Uses the current
+ * co-scheduling mode; with VUDA_SCHED_SERIAL the phases follow each other.
+ * All active envs must have the same step parity.
+ */
+int vuda_run(vuda_world* w, int32_t schedule, int32_t iters);
+
+/*
+ * Autotuner: searches the launch shapes (schedule, CU split, physics and
+ * raster workgroup shapes, physics priority, broadphase) for the highest
+ * co-scheduled env-steps/s on this world, timing `steps_per_trial`
+ * iterations per candidate from the current state (the state is saved before
+ * and restored after, so results are unchanged), applies the best, and
+ * records it in the text file `cache_path` (may be NULL) keyed by the GPU
+ * architecture and the world's shape; a later call with the same key applies
+ * the cached choice without trials.  Also reports the best serialized rate.
+ */
+typedef struct {
+  float cu_split;            /* chosen split: (0,1) CU-masked, 2 unmasked streams */
+  int32_t schedule;          /* VUDA_SCHED_* */
+  int32_t raster_threads, rec_cap, phys_persistent, raster_persistent, phys_priority, broadphase;
+  double cosched_env_steps_per_s;
+  double serial_env_steps_per_s;
+  int32_t serial_raster_threads, serial_phys_persistent;
+  int32_t trials;            /* 0 when taken from the cache */
+} vuda_tune_result;
+int vuda_autotune(vuda_world* w, int32_t steps_per_trial, const char* cache_path, vuda_tune_result* out);
+
+/*
+ * Serving with continuous batching.  A server owns a world created with spare
+ * capacity (desc->initial may be empty).  Requests (envs + horizon) are
+ * queued by vuda_serve_submit; each vuda_serve_tick admits queued requests in
+ * FIFO order while env slots, bodies, cameras and pixels are free and the
+ * reserved bytes stay within desc->hbm_budget, runs one co-scheduled
+ * iteration (every active env steps once and is rendered), and completes the
+ * requests that reached their horizon: their final state and a frame of it
+ * are kept (if keep_results) and their slots are released.  Latency is
+ * completion time minus submit time (host monotonic clock).
+ */
+typedef struct vuda_server vuda_server;
+typedef struct {
+  int64_t submitted, admitted, completed, queued, active_requests, active_envs;
+  int64_t env_steps;             /* env-steps served so far                    */
+  int64_t ticks;
+  double busy_s;                 /* time inside vuda_serve_tick               */
+  double latency_p50_s, latency_p99_s, latency_max_s, latency_mean_s;
+  double queue_p50_s, queue_p99_s; /* submit -> admission                     */
+  uint64_t reserved_bytes, peak_reserved_bytes;
+} vuda_serve_stats_t;
+int vuda_serve_create(const vuda_world_desc* desc, float cu_split, int32_t schedule,
+                      int32_t keep_results, vuda_server** out);
+int vuda_serve_destroy(vuda_server* s);
+int vuda_serve_submit(vuda_server* s, int64_t request_id, const vuda_env_batch* envs, int32_t horizon);
+int vuda_serve_tick(vuda_server* s, int32_t* n_completed);
+/* Pop up to cap completed request ids (and their latencies, seconds). */
+int vuda_serve_completed(vuda_server* s, int64_t* ids, double* latency_s, int32_t cap, int32_t* n);
+/* Kept result of a completed request: what = VUDA_FETCH_STATE, _RGB or _DEPTH;
+ * *need receives the size; dst may be NULL to query it. */
+int vuda_serve_result(vuda_server* s, int64_t request_id, int32_t what, void* dst, size_t bytes,
+                      size_t* need);
+int vuda_serve_stats(vuda_server* s, vuda_serve_stats_t* out);
+/* The server's world (for tuning knobs and the autotuner). */
+int vuda_serve_world(vuda_server* s, vuda_world** w);
+
 const char* vuda_strerror(int code);
 const char* vuda_last_error_message(void);
 

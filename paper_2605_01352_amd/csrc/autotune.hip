@@ -1,0 +1,260 @@
+// Autotuner: picks the schedule, CU split and launch shapes with the highest
+// measured co-scheduled throughput on a world, by coordinate descent over a
+// small candidate set, timing real iterations from a saved state.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "vuda.h"
+#include "vuda_runtime.h"
+
+using namespace vuda;
+
+namespace {
+
+struct Cand {
+  float split = 2.0f;
+  int32_t sched = VUDA_SCHED_INTERSTEP;
+  Tuning tune;
+};
+
+std::string signature(vuda_world* w) {
+  int32_t envs = 0, cams = 0, maxb = 0, maxt = 0;
+  int64_t bodies = 0, pixels = 0;
+  for (int32_t e = 0; e < w->n_envs_hi; ++e) {
+    if (!w->env_active[e]) continue;
+    const EnvDev& d = w->env_host[e];
+    ++envs;
+    bodies += d.n_bodies;
+    cams += d.n_cams;
+    maxb = std::max(maxb, d.n_bodies);
+    maxt = std::max(maxt, d.n_tris);
+    for (int32_t c = d.cam_off; c < d.cam_off + d.n_cams; ++c)
+      pixels += (int64_t)w->cam_host[c].w * w->cam_host[c].h;
+  }
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, w->device) == hipSuccess) arch = prop.gcnArchName;
+  std::ostringstream os;
+  os << arch << "|cu" << prop.multiProcessorCount << "|envs" << envs << "|bodies" << bodies << "|cams"
+     << cams << "|px" << pixels << "|maxb" << maxb << "|maxt" << maxt << "|sub" << w->phys.substeps;
+  return os.str();
+}
+
+// State of the world saved before the trials and restored after each one.
+struct Snapshot {
+  void* dev = nullptr;
+  size_t bytes = 0;
+  std::vector<uint8_t> parity;
+  std::vector<int64_t> step_ev, render_ev0, render_ev1;
+};
+
+int take_snapshot(vuda_world* w, Snapshot* s) {
+  const size_t st = 4 * (size_t)kStateComps * w->dev.cap_bodies;
+  const size_t fl = 4 * (size_t)w->cap_envs;
+  s->bytes = 2 * st + fl;
+  hipError_t e = hipMalloc(&s->dev, s->bytes);
+  if (e != hipSuccess) return hip_fail(e, "snapshot allocation");
+  char* d = (char*)s->dev;
+  e = hipMemcpy(d, w->dev.state[0], st, hipMemcpyDeviceToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d + st, w->dev.state[1], st, hipMemcpyDeviceToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d + 2 * st, w->dev.env_flags, fl, hipMemcpyDeviceToDevice);
+  if (e != hipSuccess) return hip_fail(e, "snapshot copy");
+  s->parity = w->env_parity;
+  return VUDA_OK;
+}
+
+int restore_snapshot(vuda_world* w, const Snapshot& s) {
+  int rc = w->drain();
+  if (rc) return rc;
+  const size_t st = 4 * (size_t)kStateComps * w->dev.cap_bodies;
+  const size_t fl = 4 * (size_t)w->cap_envs;
+  const char* d = (const char*)s.dev;
+  hipError_t e = hipMemcpy(w->dev.state[0], d, st, hipMemcpyDeviceToDevice);
+  if (e == hipSuccess) e = hipMemcpy(w->dev.state[1], d + st, st, hipMemcpyDeviceToDevice);
+  if (e == hipSuccess) e = hipMemcpy(w->dev.env_flags, d + 2 * st, fl, hipMemcpyDeviceToDevice);
+  if (e != hipSuccess) return hip_fail(e, "snapshot restore");
+  w->env_parity = s.parity;
+  std::fill(w->step_ev.begin(), w->step_ev.end(), -1);
+  std::fill(w->render_ev[0].begin(), w->render_ev[0].end(), -1);
+  std::fill(w->render_ev[1].begin(), w->render_ev[1].end(), -1);
+  return VUDA_OK;
+}
+
+int apply(vuda_world* w, const Cand& c) {
+  w->tune = c.tune;
+  for (auto& g : w->graphs) (void)hipGraphExecDestroy(g.second);
+  w->graphs.clear();
+  return vuda_cosched(w, c.split);
+}
+
+// env-steps/s of `steps` iterations of candidate c from the snapshot
+int trial(vuda_world* w, const Snapshot& snap, const Cand& c, int32_t steps, int32_t envs,
+          double* rate) {
+  int rc = restore_snapshot(w, snap);
+  if (!rc) rc = apply(w, c);
+  if (!rc) rc = vuda_run(w, c.sched, 3);
+  if (!rc) rc = w->drain();
+  if (rc) return rc;
+  const auto t0 = std::chrono::steady_clock::now();
+  rc = vuda_run(w, c.sched, steps);
+  if (!rc) rc = w->drain();
+  if (rc) return rc;
+  const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  *rate = dt > 0 ? (double)envs * steps / dt : 0.0;
+  return VUDA_OK;
+}
+
+void to_result(const Cand& c, vuda_tune_result* r) {
+  r->cu_split = c.split;
+  r->schedule = c.sched;
+  r->raster_threads = c.tune.raster_threads;
+  r->rec_cap = c.tune.rec_cap;
+  r->phys_persistent = c.tune.phys_persistent;
+  r->raster_persistent = c.tune.raster_persistent;
+  r->phys_priority = c.tune.phys_prio;
+  r->broadphase = c.tune.broadphase;
+}
+
+bool cache_lookup(const char* path, const std::string& key, vuda_tune_result* r) {
+  if (!path) return false;
+  std::ifstream f(path);
+  std::string line;
+  bool found = false;
+  while (std::getline(f, line)) {
+    std::istringstream is(line);
+    std::string k;
+    if (!(is >> k) || k != key) continue;
+    vuda_tune_result t{};
+    if (is >> t.cu_split >> t.schedule >> t.raster_threads >> t.rec_cap >> t.phys_persistent >>
+        t.raster_persistent >> t.phys_priority >> t.broadphase >> t.cosched_env_steps_per_s >>
+        t.serial_env_steps_per_s >> t.serial_raster_threads >> t.serial_phys_persistent) {
+      *r = t;  // the last matching line wins
+      found = true;
+    }
+  }
+  return found;
+}
+
+void cache_store(const char* path, const std::string& key, const vuda_tune_result& r) {
+  if (!path) return;
+  std::ofstream f(path, std::ios::app);
+  f << key << " " << r.cu_split << " " << r.schedule << " " << r.raster_threads << " " << r.rec_cap
+    << " " << r.phys_persistent << " " << r.raster_persistent << " " << r.phys_priority << " "
+    << r.broadphase << " " << r.cosched_env_steps_per_s << " " << r.serial_env_steps_per_s << " "
+    << r.serial_raster_threads << " " << r.serial_phys_persistent << "\n";
+}
+
+}  // namespace
+
+extern "C" int vuda_autotune(vuda_world* w, int32_t steps, const char* cache_path,
+                             vuda_tune_result* out) {
+  if (!w || !out) return fail(VUDA_EINVAL, "null argument");
+  if (steps < 1 || steps > 100000) return fail(VUDA_EINVAL, "steps_per_trial %d", steps);
+  int parity;
+  int rc = w->range_parity(0, w->n_envs_hi, &parity);
+  if (rc) return rc;
+  int32_t envs = 0;
+  for (int32_t e = 0; e < w->n_envs_hi; ++e) envs += w->env_active[e];
+  if (envs == 0) return fail(VUDA_EINVAL, "no active envs to tune on");
+  const std::string key = signature(w);
+  memset(out, 0, sizeof(*out));
+  if (cache_lookup(cache_path, key, out)) {
+    Cand c;
+    c.split = out->cu_split;
+    c.sched = out->schedule;
+    c.tune.raster_threads = out->raster_threads;
+    c.tune.rec_cap = out->rec_cap;
+    c.tune.phys_persistent = out->phys_persistent;
+    c.tune.raster_persistent = out->raster_persistent;
+    c.tune.phys_prio = out->phys_priority;
+    c.tune.broadphase = out->broadphase;
+    out->trials = 0;
+    return apply(w, c);
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, w->device) != hipSuccess) return fail(VUDA_EHIP, "device properties");
+  const int ncu = prop.multiProcessorCount;
+  const Tuning saved = w->tune;
+  const float saved_split = w->mode == 0 ? 0.0f : w->cu_split;
+  Snapshot snap;
+  rc = take_snapshot(w, &snap);
+  if (rc) {
+    if (snap.dev) (void)hipFree(snap.dev);
+    return rc;
+  }
+  int trials = 0;
+  auto run = [&](const Cand& c, double* r) {
+    ++trials;
+    return trial(w, snap, c, steps, envs, r);
+  };
+
+  // serialized baseline: its own best workgroup shapes
+  Cand bs;
+  bs.split = 0.0f;
+  bs.sched = VUDA_SCHED_SERIAL;
+  bs.tune = saved;
+  double best_serial = -1.0;
+  for (int rt : {256, 512}) {
+    Cand c = bs;
+    c.tune.raster_threads = rt;
+    c.tune.phys_persistent = 0;
+    double r;
+    if ((rc = run(c, &r))) break;
+    if (r > best_serial) { best_serial = r; bs = c; }
+  }
+  // co-scheduled: coordinate descent
+  Cand best = bs;
+  best.tune = bs.tune;
+  double best_rate = -1.0;
+  if (!rc) {
+    const float splits[] = {2.0f, 0.25f, 0.375f, 0.5f, 0.625f, 0.75f};
+    for (int sched : {VUDA_SCHED_INTERSTEP, VUDA_SCHED_INTERTRAJ})
+      for (float sp : splits) {
+        Cand c = best;
+        c.sched = sched;
+        c.split = sp;
+        double r;
+        if ((rc = run(c, &r))) break;
+        if (r > best_rate) { best_rate = r; best.sched = sched; best.split = sp; }
+      }
+  }
+  auto stage = [&](auto set, std::initializer_list<int> vals) {
+    for (int v : vals) {
+      if (rc) return;
+      Cand c = best;
+      set(c, v);
+      double r;
+      if ((rc = run(c, &r))) return;
+      if (r > best_rate) { best_rate = r; best = c; }
+    }
+  };
+  stage([](Cand& c, int v) { c.tune.phys_persistent = v; }, {0, ncu, 2 * ncu, 3 * ncu});
+  stage([](Cand& c, int v) { c.tune.raster_threads = v; }, {256, 512});
+  stage([](Cand& c, int v) { c.tune.phys_prio = v; }, {0, 3});
+  stage([](Cand& c, int v) { c.tune.broadphase = v; }, {0, 1});
+  const int rc_trials = rc;
+  rc = restore_snapshot(w, snap);
+  (void)hipFree(snap.dev);
+  if (rc_trials) {
+    w->tune = saved;
+    (void)vuda_cosched(w, saved_split);
+    return rc_trials;
+  }
+  if (rc) return rc;
+  to_result(best, out);
+  out->cosched_env_steps_per_s = best_rate;
+  out->serial_env_steps_per_s = best_serial;
+  out->serial_raster_threads = bs.tune.raster_threads;
+  out->serial_phys_persistent = bs.tune.phys_persistent;
+  out->trials = trials;
+  cache_store(cache_path, key, *out);
+  return apply(w, best);
+}

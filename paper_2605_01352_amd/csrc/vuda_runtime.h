@@ -48,6 +48,8 @@ class RangeAlloc {
 
 struct WorkList {
   int32_t* dptr = nullptr;
+  int32_t cap = 0;     // entries dptr holds
+  bool dirty = true;   // rebuild before the next use
   int32_t n = 0;
   int32_t max_bodies = 0;
   int32_t max_verts = 0;
@@ -136,4 +138,5 @@ struct vuda_world {
   int run_phase(int phase, const vuda::WorkList& L, int parity, int32_t lo, int32_t hi, hipStream_t s);
   hipStream_t capture_stream();
   int check_flags();
+  int32_t active_midpoint();
 };

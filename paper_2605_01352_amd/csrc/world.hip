@@ -623,22 +623,21 @@ int vuda_world::wait_event(hipStream_t s, int64_t id) {
 // work lists (LPT order) cached per range
 // ---------------------------------------------------------------------------
 
+// Mark every cached work list for a rebuild (after admission or release,
+// which drain the world first, so no kernel still reads a list).
 void vuda_world::invalidate_lists() {
-  for (auto& kv : lists)
-    if (kv.second.dptr) (void)hipFree(kv.second.dptr);
-  lists.clear();
+  for (auto& kv : lists) kv.second.dirty = true;
   for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
   graphs.clear();
 }
 
 int vuda_world::get_list(int phase, int32_t lo, int32_t hi, const WorkList** out) {
   const auto key = std::make_tuple(phase, lo, hi);
-  auto it = lists.find(key);
-  if (it != lists.end()) {
-    *out = &it->second;
-    return VUDA_OK;
-  }
-  WorkList L;
+  WorkList& L = lists[key];
+  *out = &L;
+  if (!L.dirty) return VUDA_OK;
+  L.n = 0;
+  L.max_bodies = L.max_verts = L.max_tris = L.max_tiles = 0;
   std::vector<std::pair<int64_t, int32_t>> items;
   for (int32_t e = lo; e < hi; ++e) {
     if (!env_active[e]) continue;
@@ -665,13 +664,17 @@ int vuda_world::get_list(int phase, int32_t lo, int32_t hi, const WorkList** out
   });
   std::vector<int32_t> ids(items.size());
   for (size_t i = 0; i < items.size(); ++i) ids[i] = items[i].second;
-  L.n = (int32_t)ids.size();
-  if (L.n > 0) {
-    HIPCHK(hipMalloc(&L.dptr, 4 * ids.size()));
-    HIPCHK(hipMemcpy(L.dptr, ids.data(), 4 * ids.size(), hipMemcpyHostToDevice));
+  if ((int32_t)ids.size() > L.cap) {
+    if (L.dptr) HIPCHK(hipFree(L.dptr));
+    L.dptr = nullptr;
+    L.cap = 0;
+    const int32_t want = std::max<int32_t>((int32_t)ids.size(), 64);
+    HIPCHK(hipMalloc(&L.dptr, 4 * (size_t)want));
+    L.cap = want;
   }
-  auto res = lists.emplace(key, L);
-  *out = &res.first->second;
+  if (!ids.empty()) HIPCHK(hipMemcpy(L.dptr, ids.data(), 4 * ids.size(), hipMemcpyHostToDevice));
+  L.n = (int32_t)ids.size();
+  L.dirty = false;
   return VUDA_OK;
 }
 
@@ -1061,6 +1064,8 @@ extern "C" int vuda_admit(vuda_world* w, const vuda_env_batch* b, int32_t parity
   int rc = validate_batch(*b, rd, &nb, &nc, &npix);
   if (rc) return rc;
   if (b->n_envs == 0) return fail(VUDA_EINVAL, "empty request");
+  rc = w->drain();  // work lists and tables change below
+  if (rc) return rc;
   const int64_t e0 = w->slots.alloc(b->n_envs);
   if (e0 < 0) return fail(VUDA_EBUSY, "no run of %d free env slots", b->n_envs);
   int64_t nprim, nvert;
@@ -1123,8 +1128,9 @@ extern "C" int vuda_release(vuda_world* w, int32_t first, int32_t n) {
   w->bodies.release(d0.body_off, nb);
   w->camslots.release(d0.cam_off, nc);
   w->pixels.release(p0, np);
-  w->primspace.release(d0.prim_map, d1.prim_map + d1.n_tris - d0.prim_map);
-  w->vertspace.release(d0.vert_map, d1.vert_map + d1.n_verts - d0.vert_map);
+  // each env's maps were allocated rounded up to 16 bytes
+  w->primspace.release(d0.prim_map, d1.prim_map + map_round(d1.n_tris) - d0.prim_map);
+  w->vertspace.release(d0.vert_map, d1.vert_map + map_round(d1.n_verts) - d0.vert_map);
   w->slots.release(first, n);
   for (int32_t e = first; e < first + n; ++e) {
     w->env_active[e] = 0;
@@ -1187,6 +1193,51 @@ extern "C" int vuda_get_tuning(vuda_world* w, int32_t key, int32_t* value) {
     case VUDA_TUNE_PHYS_PRIORITY: *value = w->tune.phys_prio; break;
     case VUDA_TUNE_BROADPHASE: *value = w->tune.broadphase; break;
     default: return fail(VUDA_EINVAL, "tuning key %d", key);
+  }
+  return VUDA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// schedules over every active env
+// ---------------------------------------------------------------------------
+
+// Slot index splitting the active envs into two halves of equal count.
+int32_t vuda_world::active_midpoint() {
+  int32_t total = 0;
+  for (int32_t e = 0; e < n_envs_hi; ++e) total += env_active[e];
+  int32_t seen = 0;
+  for (int32_t e = 0; e < n_envs_hi; ++e) {
+    if (seen * 2 >= total) return e;
+    seen += env_active[e];
+  }
+  return n_envs_hi;
+}
+
+extern "C" int vuda_run(vuda_world* w, int32_t schedule, int32_t iters) {
+  if (!w) return fail(VUDA_EINVAL, "null world");
+  if (iters < 0 || schedule < VUDA_SCHED_SERIAL || schedule > VUDA_SCHED_INTERTRAJ)
+    return fail(VUDA_EINVAL, "schedule %d / iters %d", schedule, iters);
+  const int32_t hi = w->n_envs_hi;
+  const int32_t mid = schedule == VUDA_SCHED_INTERTRAJ ? w->active_midpoint() : 0;
+  for (int32_t t = 0; t < iters; ++t) {
+    int rc = VUDA_OK;
+    switch (schedule) {
+      case VUDA_SCHED_SERIAL:
+        rc = vuda_step(w, 0, hi, 1);
+        if (!rc) rc = vuda_render(w, 0, hi);
+        break;
+      case VUDA_SCHED_INTERSTEP:  // render S_t while S_t -> S_t+1 runs beside it
+        rc = vuda_render(w, 0, hi);
+        if (!rc) rc = vuda_step(w, 0, hi, 1);
+        break;
+      case VUDA_SCHED_INTERTRAJ:  // step(A) | render(B), then step(B) | render(A)
+        rc = vuda_step(w, 0, mid, 1);
+        if (!rc) rc = vuda_render(w, mid, hi);
+        if (!rc) rc = vuda_step(w, mid, hi, 1);
+        if (!rc) rc = vuda_render(w, 0, mid);
+        break;
+    }
+    if (rc) return rc;
   }
   return VUDA_OK;
 }

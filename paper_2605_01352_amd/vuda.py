@@ -29,8 +29,13 @@ EXPORTS = [
     "vuda_create_world", "vuda_destroy_world", "vuda_cosched", "vuda_step", "vuda_render",
     "vuda_wait", "vuda_fetch", "vuda_fetch_bytes", "vuda_load_state", "vuda_get_stream",
     "vuda_admit", "vuda_release", "vuda_world_info", "vuda_set_tuning", "vuda_get_tuning",
-    "vuda_probe_placement", "vuda_strerror", "vuda_last_error_message",
+    "vuda_probe_placement", "vuda_strerror", "vuda_last_error_message", "vuda_run",
+    "vuda_autotune", "vuda_serve_create", "vuda_serve_destroy", "vuda_serve_submit",
+    "vuda_serve_tick", "vuda_serve_completed", "vuda_serve_result", "vuda_serve_stats",
+    "vuda_serve_world",
 ]
+SCHED_SERIAL, SCHED_INTERSTEP, SCHED_INTERTRAJ = 0, 1, 2
+SCHED_NAMES = {SCHED_SERIAL: "serial", SCHED_INTERSTEP: "interstep", SCHED_INTERTRAJ: "intertraj"}
 
 
 class VudaError(RuntimeError):
@@ -72,6 +77,31 @@ class WorldDesc(C.Structure):
                 ("hbm_budget", C.c_uint64)]
 
 
+class TuneResult(C.Structure):
+    _fields_ = [("cu_split", C.c_float), ("schedule", C.c_int32), ("raster_threads", C.c_int32),
+                ("rec_cap", C.c_int32), ("phys_persistent", C.c_int32),
+                ("raster_persistent", C.c_int32), ("phys_priority", C.c_int32),
+                ("broadphase", C.c_int32), ("cosched_env_steps_per_s", C.c_double),
+                ("serial_env_steps_per_s", C.c_double), ("serial_raster_threads", C.c_int32),
+                ("serial_phys_persistent", C.c_int32), ("trials", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServeStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
+                ("queued", C.c_int64), ("active_requests", C.c_int64), ("active_envs", C.c_int64),
+                ("env_steps", C.c_int64), ("ticks", C.c_int64), ("busy_s", C.c_double),
+                ("latency_p50_s", C.c_double), ("latency_p99_s", C.c_double),
+                ("latency_max_s", C.c_double), ("latency_mean_s", C.c_double),
+                ("queue_p50_s", C.c_double), ("queue_p99_s", C.c_double),
+                ("reserved_bytes", C.c_uint64), ("peak_reserved_bytes", C.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -82,10 +112,20 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run paper_2605_01352_amd/build.py "
                                f"(or __graft_entry__.build())")
+        # PyTorch ships its own HIP runtime and loads it under another name; it
+        # has to be loaded first so that libvuda binds to that same runtime and
+        # the process holds one (streams and events are then shared with it).
+        try:
+            import torch  # noqa: F401
+        except Exception:
+            pass
         L = C.CDLL(LIB_PATH)
         for name in EXPORTS:
             getattr(L, name)  # raises AttributeError if missing
         L.vuda_strerror.restype = C.c_char_p
+        L.vuda_serve_submit.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int32]
+        L.vuda_serve_result.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_size_t,
+                                        C.c_void_p]
         L.vuda_last_error_message.restype = C.c_char_p
         _lib = L
     return _lib
@@ -224,6 +264,15 @@ class World:
     def wait(self, phase: int = PHASE_ALL):
         check(lib().vuda_wait(self._w, phase))
 
+    def run(self, schedule: int = SCHED_INTERSTEP, iters: int = 1):
+        """Enqueue iterations of a schedule over every active env."""
+        check(lib().vuda_run(self._w, schedule, iters))
+
+    def autotune(self, steps: int = 30, cache: Optional[str] = None) -> Dict:
+        r = TuneResult()
+        check(lib().vuda_autotune(self._w, steps, cache.encode() if cache else None, C.byref(r)))
+        return r.as_dict()
+
     def set_tuning(self, key: int, value: int):
         check(lib().vuda_set_tuning(self._w, key, int(value)))
 
@@ -331,3 +380,95 @@ class World:
         check(lib().vuda_world_info(self._w, C.byref(ne), C.byref(nb), C.byref(nc), C.byref(npx), C.byref(ab)))
         return dict(n_envs=ne.value, cap_bodies=nb.value, cap_cams=nc.value, cap_pixels=npx.value,
                     arena_bytes=ab.value)
+
+
+def world_desc(keep: _Keep, scene=None, debug: bool = False, cap_envs: int = 0, cap_bodies: int = 0,
+               cap_cams: int = 0, cap_pixels: int = 0, pair_cap: int = 1024, hbm_budget: int = 0,
+               phys=None) -> WorldDesc:
+    dt, sub, k, c, g = 1.0 / 240.0, 4, 1.0e4, 10.0, (0.0, 0.0, -9.81)
+    if scene is not None:
+        dt, sub, k, c, g = scene.dt, scene.substeps, scene.k_contact, scene.c_damp, scene.gravity
+    if phys:
+        dt, sub, k, c, g = phys.get("dt", dt), phys.get("substeps", sub), phys.get("k", k), \
+            phys.get("c", c), phys.get("g", g)
+    d = WorldDesc()
+    d.phys = PhysParams(float(np.float32(dt)), int(sub), float(k), float(c),
+                        (C.c_float * 3)(*[float(x) for x in g]))
+    d.render = render_desc(keep)
+    d.initial = env_batch(keep, scene) if scene is not None else EnvBatch(0)
+    d.flags = FLAG_DEBUG if debug else 0
+    d.cap_envs, d.cap_bodies, d.cap_cams, d.cap_pixels = cap_envs, cap_bodies, cap_cams, cap_pixels
+    d.pair_cap = pair_cap
+    d.hbm_budget = hbm_budget
+    return d
+
+
+class Server:
+    """Serving loop with continuous batching (vuda_serve_*)."""
+
+    def __init__(self, cap_envs: int, cap_bodies: int, cap_cams: int, cap_pixels: int,
+                 hbm_budget: int = 0, cu_split: float = 2.0, schedule: int = SCHED_INTERSTEP,
+                 keep_results: bool = False):
+        L = lib()
+        keep = _Keep()
+        d = world_desc(keep, None, cap_envs=cap_envs, cap_bodies=cap_bodies, cap_cams=cap_cams,
+                       cap_pixels=cap_pixels, hbm_budget=hbm_budget)
+        self._s = C.c_void_p()
+        check(L.vuda_serve_create(C.byref(d), C.c_float(cu_split), schedule, int(keep_results),
+                                  C.byref(self._s)))
+
+    def close(self):
+        if self._s:
+            check(lib().vuda_serve_destroy(self._s))
+            self._s = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def world_handle(self):
+        w = C.c_void_p()
+        check(lib().vuda_serve_world(self._s, C.byref(w)))
+        return w
+
+    def set_tuning(self, key: int, value: int):
+        check(lib().vuda_set_tuning(self.world_handle(), key, int(value)))
+
+    def submit(self, request_id: int, scene, horizon: int):
+        keep = _Keep()
+        b = env_batch(keep, scene)
+        check(lib().vuda_serve_submit(self._s, int(request_id), C.byref(b), int(horizon)))
+
+    def tick(self) -> int:
+        n = C.c_int32()
+        check(lib().vuda_serve_tick(self._s, C.byref(n)))
+        return n.value
+
+    def completed(self, cap: int = 4096):
+        ids = np.zeros(cap, np.int64)
+        lat = np.zeros(cap, np.float64)
+        n = C.c_int32()
+        check(lib().vuda_serve_completed(self._s, _p(ids), _p(lat), cap, C.byref(n)))
+        return list(zip(ids[:n.value].tolist(), lat[:n.value].tolist()))
+
+    def result(self, request_id: int, what: int) -> np.ndarray:
+        need = C.c_size_t()
+        check(lib().vuda_serve_result(self._s, int(request_id), what, None, 0, C.byref(need)))
+        dt = {FETCH_STATE: np.float32, FETCH_RGB: np.uint8, FETCH_DEPTH: np.uint32}[what]
+        out = np.zeros(need.value // np.dtype(dt).itemsize, dt)
+        check(lib().vuda_serve_result(self._s, int(request_id), what, _p(out), C.c_size_t(need.value),
+                                      C.byref(need)))
+        return out
+
+    def stats(self) -> Dict:
+        st = ServeStats()
+        check(lib().vuda_serve_stats(self._s, C.byref(st)))
+        return st.as_dict()

@@ -1,0 +1,104 @@
+"""Serving with continuous batching on the GPU: a request's result is the same
+alone and in a mix of requests admitted at other times; admission respects
+the HBM budget; latency statistics are reported."""
+import numpy as np
+import pytest
+
+from paper_2605_01352_amd import scenegen as sg
+from paper_2605_01352_amd import vuda
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+def small_requests():
+    specs = [sg.RequestSpec(0, 0.0, 5, 12, 64, 7), sg.RequestSpec(1, 0.0, 9, 20, 128, 11),
+             sg.RequestSpec(2, 0.0, 4, 8, 64, 5), sg.RequestSpec(3, 0.0, 6, 30, 64, 9)]
+    return specs, [sg.request_scene(r) for r in specs]
+
+
+def server(**kw):
+    args = dict(cap_envs=64, cap_bodies=1024, cap_cams=64, cap_pixels=64 * 128 * 128, keep_results=True)
+    args.update(kw)
+    return vuda.Server(**args)
+
+
+def run_until_done(srv, n, max_ticks=500):
+    done = {}
+    for _ in range(max_ticks):
+        srv.tick()
+        for rid, lat in srv.completed():
+            done[rid] = lat
+        if len(done) >= n:
+            return done
+    raise AssertionError(f"only {len(done)} of {n} requests completed")
+
+
+@pytest.mark.parametrize("schedule,split", [(vuda.SCHED_INTERSTEP, 2.0), (vuda.SCHED_INTERTRAJ, 0.5),
+                                            (vuda.SCHED_SERIAL, 0.0)])
+def test_request_same_alone_and_in_mix(schedule, split):
+    specs, scenes = small_requests()
+    with server(schedule=schedule, cu_split=split) as a:
+        a.submit(0, scenes[0], specs[0].horizon)
+        run_until_done(a, 1)
+        alone = [a.result(0, k) for k in (vuda.FETCH_STATE, vuda.FETCH_RGB, vuda.FETCH_DEPTH)]
+    with server(schedule=schedule, cu_split=split) as b:
+        b.submit(1, scenes[1], specs[1].horizon)
+        b.tick()
+        b.tick()
+        b.submit(0, scenes[0], specs[0].horizon)   # joins while request 1 is running
+        b.tick()
+        b.submit(2, scenes[2], specs[2].horizon)
+        b.submit(3, scenes[3], specs[3].horizon)
+        run_until_done(b, 4)
+        mixed = [b.result(0, k) for k in (vuda.FETCH_STATE, vuda.FETCH_RGB, vuda.FETCH_DEPTH)]
+        st = b.stats()
+    for x, y in zip(alone, mixed):
+        assert np.array_equal(x, y)
+    assert st["completed"] == 4 and st["queued"] == 0 and st["active_requests"] == 0
+    assert st["env_steps"] == sum(r.n_envs * r.horizon for r in specs)
+
+
+def test_result_matches_a_plain_world():
+    specs, scenes = small_requests()
+    r = specs[1]
+    with server() as srv:
+        srv.submit(7, scenes[1], r.horizon)
+        run_until_done(srv, 1)
+        got = srv.result(7, vuda.FETCH_STATE)
+    with vuda.World(scenes[1]) as w:
+        for _ in range(r.horizon):
+            w.step()
+        w.wait()
+        assert np.array_equal(w.fetch(vuda.FETCH_STATE), got)
+
+
+def test_admission_waits_for_budget():
+    specs, scenes = small_requests()
+    # a budget that holds request 1 (the largest) but not two of them at once
+    with server(hbm_budget=1, keep_results=False) as tiny:
+        with pytest.raises(vuda.VudaError):
+            tiny.submit(1, scenes[1], specs[1].horizon)  # can never fit
+    budget = 9 * (20 * 130 + 128 * 128 * 7) + 9 * 4000
+    with server(hbm_budget=budget, keep_results=False) as srv:
+        for k in range(3):
+            srv.submit(10 + k, scenes[1], specs[1].horizon)
+        srv.tick()
+        st = srv.stats()
+        assert st["active_requests"] == 1 and st["queued"] == 2
+        done = run_until_done(srv, 3)
+        st = srv.stats()
+        assert st["peak_reserved_bytes"] <= budget
+        assert st["queue_p99_s"] > 0 and st["latency_p99_s"] >= st["latency_p50_s"] > 0
+        say(f"budget-limited serving: {st}")
+        assert sorted(done) == [10, 11, 12]
+
+
+def test_slots_are_reused():
+    specs, scenes = small_requests()
+    with server(cap_envs=10, cap_bodies=200, cap_cams=10, cap_pixels=10 * 128 * 128,
+                keep_results=False) as srv:
+        for k in range(6):
+            srv.submit(k, scenes[1], specs[1].horizon)  # 9 envs each: one at a time
+        done = run_until_done(srv, 6, max_ticks=200)
+        assert len(done) == 6

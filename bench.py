@@ -19,6 +19,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "env-steps/s (sim+render) co-scheduled vs serialized; p99 rollout latency"
 HBM_PEAK_GBS = 8000.0
+CSRC = os.path.join(ROOT, "paper_2605_01352_amd", "csrc")
+KERNEL_SOURCES = {"raster": ["raster.hip", "vuda_internal.h"], "physics": ["physics.hip", "vuda_internal.h"]}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.md")
 
 
 def log(*a):
@@ -43,11 +46,13 @@ def enqueue(w, schedule, n_envs, iters):
             raise ValueError(schedule)
 
 
-def timed(torch, w, schedule, n_envs, steps, warmup, st0=None):
+def timed(torch, w, schedule, n_envs, steps, warmup, st0=None, after_warmup=None):
     if st0 is not None:
         w.load_state(st0)  # every measurement starts from the same scene state
     enqueue(w, schedule, n_envs, warmup)
     torch.cuda.synchronize()
+    if after_warmup is not None:
+        after_warmup()
     t0 = time.perf_counter()
     enqueue(w, schedule, n_envs, steps)
     torch.cuda.synchronize()
@@ -56,27 +61,60 @@ def timed(torch, w, schedule, n_envs, steps, warmup, st0=None):
     return dt
 
 
-def kernel_times(torch, vuda, w, st0, reps=20):
-    """Average duration of one physics launch and one raster launch, timed
-    with HIP events on the stream the kernels run on (serialized mode),
-    from the initial state."""
-    w.cosched(0.0)
-    w.load_state(st0)
-    s = torch.cuda.ExternalStream(w.stream(vuda.PHASE_STEP))
+def launch_stats(vuda, w):
+    """Average launch duration (s) and launch count per phase since the last
+    read, from the HIP events the library records around each launch on the
+    stream the kernel runs on."""
     out = {}
-    for name in ("physics", "raster"):
-        fn = w.step if name == "physics" else w.render
-        for _ in range(3):
-            fn()
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
-        for a, b in ev:
-            a.record(s)
-            fn()
-            b.record(s)
-        torch.cuda.synchronize()
-        out[name] = sum(a.elapsed_time(b) for a, b in ev) / reps * 1e-3  # seconds
-    w.wait()
+    for name, ph in (("physics", vuda.PHASE_STEP), ("raster", vuda.PHASE_RENDER)):
+        t = w.phase_times(ph)
+        out[name] = {"launches": t["launches"],
+                     "avg_s": t["total_ms"] * 1e-3 / max(1, t["launches"]),
+                     "max_s": t["max_ms"] * 1e-3}
     return out
+
+
+def source_hash(kernel):
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:12]
+
+
+def measured_traffic(kernel, config):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current source of the kernel (else None).  Lines read:
+    `traffic <kernel> c<config> src=<hash> fetch_kib=<f> write_kib=<w>
+    fetch_factor=<a> write_factor=<b>`; bytes = 1024 (f a + w b)."""
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    want = source_hash(kernel)
+    for line in lines:
+        tok = line.strip().strip("`").split()
+        if len(tok) < 3 or tok[0] != "traffic" or tok[1] != kernel or tok[2] != f"c{config}":
+            continue
+        kv = dict(t.split("=", 1) for t in tok[3:] if "=" in t)
+        if kv.get("src") != want:
+            return None
+        return int(1024 * (float(kv["fetch_kib"]) * float(kv["fetch_factor"]) +
+                           float(kv["write_kib"]) * float(kv["write_factor"])))
+    return None
+
+
+def copy_calibration(torch, mib):
+    """A plain device copy of `mib` MiB (read + write of that many bytes), for
+    scaling the HBM byte counters of a profiled run."""
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
 
 
 def cpu_baseline(scene_fn, n_envs, steps):
@@ -114,9 +152,15 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--envs", type=int, default=None, help="fewer envs (debug only)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="length of the continuous-batching serving run (0: skip)")
     ap.add_argument("--splits", default="0.25,0.375,0.5,0.625,0.75")
     ap.add_argument("--profile", type=int, default=0,
                     help="only run this many serialized then co-scheduled steps (for rocprofv3)")
+    ap.add_argument("--only", default="",
+                    help="skip the sweep and time this co-scheduled mode, e.g. interstep@2")
+    ap.add_argument("--copy-calib", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--tune", default="", help="tuning knobs key=value,... (e.g. raster_threads=512)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -129,6 +173,8 @@ def main():
     from paper_2605_01352_amd import vuda
 
     torch.cuda.init()
+    if args.copy_calib:
+        copy_calibration(torch, args.copy_calib)
     cfg = args.config
     log(f"building scene c{cfg}")
     scene = sg.config_scene(cfg, n_envs=args.envs)
@@ -154,56 +200,73 @@ def main():
             f"co-scheduled {dt_c / args.profile * 1e6:.1f} us/step")
         w.close()
         return
-    kt = kernel_times(torch, vuda, w, st0)
-    log(f"kernel times: physics {kt['physics']*1e6:.1f} us, raster {kt['raster']*1e6:.1f} us")
-    Ts, Tr = kt["physics"], kt["raster"]
-
+    w.set_tuning(vuda.TUNE_TIMING, 1)
     results = {}
     w.cosched(0.0)
-    results["serialized"] = timed(torch, w, "serial", n_envs, args.steps, args.warmup, st0)
-    log(f"serialized: {n_envs * args.steps / results['serialized']:.0f} env-steps/s")
+    results["serialized"] = timed(torch, w, "serial", n_envs, args.steps, args.warmup, st0,
+                                  after_warmup=lambda: launch_stats(vuda, w))
+    alone = launch_stats(vuda, w)  # launches of the timed region
+    Ts, Tr = alone["physics"]["avg_s"], alone["raster"]["avg_s"]
+    ser = n_envs * args.steps / results["serialized"]
+    log(f"serialized: {ser:.0f} env-steps/s; launches alone: physics {Ts*1e6:.1f} us, "
+        f"raster {Tr*1e6:.1f} us, bound {(Ts + Tr) / max(Ts, Tr):.3f}x")
     # co-scheduled candidates: unmasked streams and CU splits, both overlap patterns
     cands = [(2.0, sched) for sched in ("interstep", "intertraj")]
     cands += [(float(x), sched) for x in args.splits.split(",") for sched in ("interstep", "intertraj")]
+    if args.only:
+        cands = []
     sweep = {}
-    short = args.steps
     for split, sched in cands:
         w.cosched(split)
-        dt = timed(torch, w, sched, n_envs, short, 5, st0)
-        sweep[f"{sched}@{split:g}"] = n_envs * short / dt
-        log(f"  {sched:9s} split {split:5g}: {n_envs * short / dt:.0f} env-steps/s")
-    best = max(sweep, key=sweep.get)
+        dt = timed(torch, w, sched, n_envs, args.steps, 5, st0)
+        sweep[f"{sched}@{split:g}"] = n_envs * args.steps / dt
+        log(f"  {sched:9s} split {split:5g}: {n_envs * args.steps / dt:.0f} env-steps/s")
+    best = args.only or max(sweep, key=sweep.get)
     sched, split = best.split("@")
     split = float(split)
     w.cosched(split)
-    dt = timed(torch, w, sched, n_envs, args.steps, args.warmup, st0)
+    dt = timed(torch, w, sched, n_envs, args.steps, args.warmup, st0,
+               after_warmup=lambda: launch_stats(vuda, w))
+    live = launch_stats(vuda, w)  # launches of the timed region
     value = n_envs * args.steps / dt
-    ser = n_envs * args.steps / results["serialized"]
-    log(f"co-scheduled ({best}): {value:.0f} env-steps/s, {value / ser:.3f}x serialized, "
-        f"bound {(Ts + Tr) / max(Ts, Tr):.3f}x")
+    log(f"co-scheduled ({best}): {value:.0f} env-steps/s, {value / ser:.3f}x serialized")
 
-    # roofline of the dominant kernel (algorithmic bytes per launch / duration)
+    # roofline of the dominant kernel: algorithmic bytes per launch over its
+    # average duration in the timed region
     px = int((scene.cam_w.astype("int64") * scene.cam_h).sum())
-    raster_bytes = 7 * px + 28 * int(sum(scene.counts()[e] * (scene.cam_off[e + 1] - scene.cam_off[e])
-                                         for e in range(n_envs)))
-    phys_bytes = 120 * scene.n_bodies
-    if Tr >= Ts:
-        dom, tb, td = "raster", raster_bytes, Tr
-    else:
-        dom, tb, td = "physics", phys_bytes, Ts
-    ach = tb / td / 1e9
-    roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None,
-            "bytes_per_launch": tb, "launch_us": round(td * 1e6, 2),
-            "physics": {"launch_us": round(Ts * 1e6, 2), "bytes": phys_bytes,
-                        "GBs": round(phys_bytes / Ts / 1e9, 2)},
-            "raster": {"launch_us": round(Tr * 1e6, 2), "bytes": raster_bytes,
-                       "GBs": round(raster_bytes / Tr / 1e9, 2)}}
+    body_cams = int(sum(scene.counts()[e] * (scene.cam_off[e + 1] - scene.cam_off[e]) for e in range(n_envs)))
+    raster_step_bytes = 7 * px + 28 * body_cams
+    phys_step_bytes = 120 * scene.n_bodies
+    per_step = {"physics": live["physics"]["launches"] / args.steps,
+                "raster": live["raster"]["launches"] / args.steps}
+    kinds = {}
+    for name, step_bytes in (("physics", phys_step_bytes), ("raster", raster_step_bytes)):
+        lb = step_bytes / per_step[name]  # launches split the env range evenly
+        t = live[name]["avg_s"]
+        kinds[name] = {"launch_us": round(t * 1e6, 2), "bytes_per_launch": int(lb),
+                       "launches_per_step": per_step[name], "GBs": round(lb / t / 1e9, 2),
+                       "alone_launch_us": round(alone[name]["avg_s"] * 1e6, 2)}
+    dom = max(kinds, key=lambda k: kinds[k]["launch_us"] * per_step[k])
+    ach = kinds[dom]["GBs"]
+    tr = measured_traffic(dom, cfg)
+    roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": tr,
+            "bytes_per_launch": kinds[dom]["bytes_per_launch"], "launch_us": kinds[dom]["launch_us"],
+            "physics": kinds["physics"], "raster": kinds["raster"]}
+
+    serving = None
+    if args.serve_seconds > 0:
+        from paper_2605_01352_amd import serving as srv
+        log(f"serving: {args.serve_seconds:g} s of Poisson(50/s) requests ...")
+        serving = srv.run(duration=args.serve_seconds, rate=50.0, log=log)
+        log(f"serving: {serving}")
 
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(lambda n: sg.config_scene(cfg, n_envs=n), min(512, n_envs), 100 if cfg <= 2 else 10)
+        n_cpu = min(1024, n_envs)
+        cpu = cpu_baseline(lambda n: scene if n == n_envs else scene.subset(range(n)), n_cpu,
+                           50 if cfg <= 2 else 10)
         log(f"cpu baseline: {cpu['value']:.0f} env-steps/s on {cpu['cores']} threads")
     w.close()
 
@@ -223,9 +286,11 @@ def main():
         "serialized": {"value": round(ser, 1), "ms_per_step": round(results["serialized"] / args.steps * 1e3, 4)},
         "speedup_vs_serialized": round(value / ser, 4),
         "overlap_bound": round((Ts + Tr) / max(Ts, Tr), 4),
+        "phase_alone_us": {"physics": round(Ts * 1e6, 2), "raster": round(Tr * 1e6, 2)},
         "sweep": {k: round(v, 1) for k, v in sweep.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
 

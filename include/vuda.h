@@ -240,6 +240,9 @@ int vuda_world_info(vuda_world* w, int32_t* n_envs, int64_t* n_bodies, int32_t* 
  *   VUDA_TUNE_BROADPHASE       0 automatic (all pairs up to 64 bodies, uniform
  *                              grid hash above), 1 grid hash, 2 all pairs;
  *                              both give the same candidate set
+ *   VUDA_TUNE_TIMING           1: record a HIP event pair around every phase
+ *                              launch on the stream it runs on (read with
+ *                              vuda_phase_times); 0: off (default)
  * None of them changes any output bit.  Returns VUDA_EINVAL for unknown keys
  * or out-of-range values.
  */
@@ -250,8 +253,22 @@ int vuda_world_info(vuda_world* w, int32_t* n_envs, int64_t* n_bodies, int32_t* 
 #define VUDA_TUNE_GRAPHS 5
 #define VUDA_TUNE_PHYS_PRIORITY 6
 #define VUDA_TUNE_BROADPHASE 7
+#define VUDA_TUNE_TIMING 8
 int vuda_set_tuning(vuda_world* w, int32_t key, int32_t value);
 int vuda_get_tuning(vuda_world* w, int32_t key, int32_t* value);
+
+/*
+ * Launch durations recorded while VUDA_TUNE_TIMING is on: for `phase`
+ * (VUDA_PHASE_STEP or VUDA_PHASE_RENDER), waits for the last recorded launch,
+ * then returns the number of launches since the previous call and the sum and
+ * maximum of their durations in milliseconds (GPU time between the event
+ * recorded after the launch's stream waits were satisfied and the event after
+ * its kernels), and starts a new count.  A launch is one physics or raster
+ * kernel over the enqueued env range (with its queue reset when persistent).
+ * Any output pointer may be NULL.
+ */
+int vuda_phase_times(vuda_world* w, int32_t phase, int64_t* launches, double* total_ms,
+                     double* max_ms);
 
 /*
  * Placement probe: launches n_blocks one-wave workgroups on the stream of

@@ -65,6 +65,7 @@ struct Tuning {
   bool graphs = false;
   int32_t phys_prio = 0;
   int32_t broadphase = 0;
+  bool timing = false;
 };
 
 }  // namespace vuda
@@ -113,6 +114,11 @@ struct vuda_world {
   std::vector<hipEvent_t> evpool;
   int64_t next_event = 0;
 
+  // launch timing: start/stop event pairs per phase (index 0 step, 1 render),
+  // tev_used[k] pairs recorded since the last read
+  std::vector<hipEvent_t> tev[2];
+  size_t tev_used[2] = {0, 0};
+
   std::map<std::tuple<int, int32_t, int32_t>, vuda::WorkList> lists;
   std::map<std::tuple<int, int32_t, int32_t, int>, hipGraphExec_t> graphs;
   vuda::Tuning tune;
@@ -136,6 +142,7 @@ struct vuda_world {
   int raster_launch_of(const vuda::WorkList& L, int parity, vuda::RasterLaunch* out);
   int enqueue_raster(const vuda::WorkList& L, int parity, hipStream_t s);
   int run_phase(int phase, const vuda::WorkList& L, int parity, int32_t lo, int32_t hi, hipStream_t s);
+  int launch_phase(int phase, const vuda::WorkList& L, int parity, int32_t lo, int32_t hi, hipStream_t s);
   hipStream_t capture_stream();
   int check_flags();
   int32_t active_midpoint();

@@ -494,6 +494,10 @@ void vuda_world::free_all() {
   s_serial = nullptr;
   for (auto& e : evpool) (void)hipEventDestroy(e);
   evpool.clear();
+  for (auto& v : tev) {
+    for (auto& e : v) (void)hipEventDestroy(e);
+    v.clear();
+  }
   if (arena) {
     if (has_allocator) allocator.free(arena, allocator.ctx);
     else (void)hipFree(arena);
@@ -756,9 +760,29 @@ int vuda_world::enqueue_raster(const WorkList& L, int parity, hipStream_t s) {
   return VUDA_OK;
 }
 
-// Launch one phase, through a captured graph when graph mode is on.
+// Launch one phase, through a captured graph when graph mode is on, between
+// a pair of timing events when timing is on.
 int vuda_world::run_phase(int phase, const WorkList& L, int parity, int32_t lo, int32_t hi,
                           hipStream_t s) {
+  if (!tune.timing) return launch_phase(phase, L, parity, lo, hi, s);
+  const int k = phase == VUDA_PHASE_STEP ? 0 : 1;
+  std::vector<hipEvent_t>& ev = tev[k];
+  const size_t i = 2 * tev_used[k];
+  while (ev.size() < i + 2) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    ev.push_back(e);
+  }
+  HIPCHK(hipEventRecord(ev[i], s));
+  int rc = launch_phase(phase, L, parity, lo, hi, s);
+  if (rc) return rc;
+  HIPCHK(hipEventRecord(ev[i + 1], s));
+  ++tev_used[k];
+  return VUDA_OK;
+}
+
+int vuda_world::launch_phase(int phase, const WorkList& L, int parity, int32_t lo, int32_t hi,
+                             hipStream_t s) {
   if (!tune.graphs) {
     return phase == VUDA_PHASE_STEP ? enqueue_physics(L, parity, s) : enqueue_raster(L, parity, s);
   }
@@ -957,6 +981,26 @@ extern "C" int vuda_fetch_bytes(vuda_world* w, int32_t what, int32_t lo, int32_t
   return VUDA_OK;
 }
 
+// Maximal runs of active envs in [lo, hi) whose bodies are contiguous and
+// whose state sits in the same buffer: {parity, first body, body count}.
+struct StateRun {
+  int parity;
+  int64_t b0, nb;
+};
+static void state_runs(const vuda_world* w, int32_t lo, int32_t hi, std::vector<StateRun>& runs) {
+  runs.clear();
+  for (int32_t e = lo; e < hi; ++e) {
+    if (!w->env_active[e]) continue;
+    const EnvDev& d = w->env_host[e];
+    if (d.n_bodies == 0) continue;
+    const int par = w->env_parity[e];
+    if (!runs.empty() && runs.back().parity == par && runs.back().b0 + runs.back().nb == d.body_off)
+      runs.back().nb += d.n_bodies;
+    else
+      runs.push_back({par, d.body_off, d.n_bodies});
+  }
+}
+
 extern "C" int vuda_fetch(vuda_world* w, int32_t what, int32_t lo, int32_t hi, void* dst,
                           size_t dst_bytes, int32_t on_device) {
   if (!w) return fail(VUDA_EINVAL, "null world");
@@ -977,24 +1021,23 @@ extern "C" int vuda_fetch(vuda_world* w, int32_t what, int32_t lo, int32_t hi, v
   const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   unsigned char* out = (unsigned char*)dst;
   if (what == VUDA_FETCH_STATE) {
-    // gather [13][B] SoA into [n][13] per env, from each env's current buffer
+    // gather [13][B] SoA into [n][13], from each env's current buffer
+    std::vector<StateRun> sr;
+    state_runs(w, lo, hi, sr);
     int64_t pos = 0;
-    std::vector<float> tmp;
-    for (int32_t e = lo; e < hi; ++e) {
-      if (!w->env_active[e]) continue;
-      const EnvDev& d = w->env_host[e];
-      if (d.n_bodies == 0) continue;
-      const float* src = w->dev.state[w->env_parity[e]];
-      tmp.resize((size_t)kStateComps * d.n_bodies);
+    std::vector<float> tmp, aos;
+    for (const StateRun& r : sr) {
+      const float* src = w->dev.state[r.parity];
+      tmp.resize((size_t)kStateComps * r.nb);
       for (int k = 0; k < kStateComps; ++k)
-        HIPCHK(hipMemcpy(tmp.data() + (size_t)k * d.n_bodies, src + k * w->dev.cap_bodies + d.body_off,
-                         4 * (size_t)d.n_bodies, hipMemcpyDeviceToHost));
-      std::vector<float> aos((size_t)kStateComps * d.n_bodies);
-      for (int i = 0; i < d.n_bodies; ++i)
-        for (int k = 0; k < kStateComps; ++k) aos[(size_t)i * kStateComps + k] = tmp[(size_t)k * d.n_bodies + i];
+        HIPCHK(hipMemcpy(tmp.data() + (size_t)k * r.nb, src + k * w->dev.cap_bodies + r.b0, 4 * (size_t)r.nb,
+                         hipMemcpyDeviceToHost));
+      aos.resize((size_t)kStateComps * r.nb);
+      for (int64_t i = 0; i < r.nb; ++i)
+        for (int k = 0; k < kStateComps; ++k) aos[(size_t)i * kStateComps + k] = tmp[(size_t)k * r.nb + i];
       HIPCHK(hipMemcpy(out + pos * eb, aos.data(), aos.size() * 4,
                        on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
-      pos += d.n_bodies;
+      pos += r.nb;
     }
     return w->check_flags();
   }
@@ -1027,20 +1070,21 @@ extern "C" int vuda_load_state(vuda_world* w, int32_t lo, int32_t hi, const floa
     return fail(VUDA_EINVAL, "src holds %zu bytes, need %zu", src_bytes, (size_t)need * 4 * kStateComps);
   rc = w->drain();
   if (rc) return rc;
+  // one copy per state component for each run of contiguous envs
+  std::vector<StateRun> sr;
+  state_runs(w, lo, hi, sr);
   int64_t pos = 0;
-  for (int32_t e = lo; e < hi; ++e) {
-    if (!w->env_active[e]) continue;
-    const EnvDev& d = w->env_host[e];
-    if (d.n_bodies == 0) continue;
-    std::vector<float> soa((size_t)kStateComps * d.n_bodies);
-    for (int i = 0; i < d.n_bodies; ++i)
+  std::vector<float> soa;
+  for (const StateRun& r : sr) {
+    soa.resize((size_t)kStateComps * r.nb);
+    for (int64_t i = 0; i < r.nb; ++i)
       for (int k = 0; k < kStateComps; ++k)
-        soa[(size_t)k * d.n_bodies + i] = src[(pos + i) * kStateComps + k];
-    float* dstp = w->dev.state[w->env_parity[e]];
+        soa[(size_t)k * r.nb + i] = src[(pos + i) * kStateComps + k];
+    float* dstp = w->dev.state[r.parity];
     for (int k = 0; k < kStateComps; ++k)
-      HIPCHK(hipMemcpy(dstp + k * w->dev.cap_bodies + d.body_off, soa.data() + (size_t)k * d.n_bodies,
-                       4 * (size_t)d.n_bodies, hipMemcpyHostToDevice));
-    pos += d.n_bodies;
+      HIPCHK(hipMemcpy(dstp + k * w->dev.cap_bodies + r.b0, soa.data() + (size_t)k * r.nb, 4 * (size_t)r.nb,
+                       hipMemcpyHostToDevice));
+    pos += r.nb;
   }
   // clear sticky flags of the reloaded envs
   std::vector<uint32_t> zero(hi - lo, 0u);
@@ -1174,6 +1218,10 @@ extern "C" int vuda_set_tuning(vuda_world* w, int32_t key, int32_t value) {
       if (value < 0 || value > 2) return fail(VUDA_EINVAL, "broadphase %d", value);
       w->tune.broadphase = value;
       break;
+    case VUDA_TUNE_TIMING:
+      if (value < 0 || value > 1) return fail(VUDA_EINVAL, "timing %d", value);
+      w->tune.timing = value != 0;
+      return VUDA_OK;  // placement of the events only: graphs stay valid
     default:
       return fail(VUDA_EINVAL, "tuning key %d", key);
   }
@@ -1192,8 +1240,33 @@ extern "C" int vuda_get_tuning(vuda_world* w, int32_t key, int32_t* value) {
     case VUDA_TUNE_GRAPHS: *value = w->tune.graphs ? 1 : 0; break;
     case VUDA_TUNE_PHYS_PRIORITY: *value = w->tune.phys_prio; break;
     case VUDA_TUNE_BROADPHASE: *value = w->tune.broadphase; break;
+    case VUDA_TUNE_TIMING: *value = w->tune.timing ? 1 : 0; break;
     default: return fail(VUDA_EINVAL, "tuning key %d", key);
   }
+  return VUDA_OK;
+}
+
+extern "C" int vuda_phase_times(vuda_world* w, int32_t phase, int64_t* launches, double* total_ms,
+                                double* max_ms) {
+  if (!w) return fail(VUDA_EINVAL, "null world");
+  if (phase != VUDA_PHASE_STEP && phase != VUDA_PHASE_RENDER) return fail(VUDA_EINVAL, "phase %d", phase);
+  const int k = phase == VUDA_PHASE_STEP ? 0 : 1;
+  const size_t n = w->tev_used[k];
+  double sum = 0.0, mx = 0.0;
+  if (n) {
+    HIPCHK(hipSetDevice(w->device));
+    HIPCHK(hipEventSynchronize(w->tev[k][2 * n - 1]));
+    for (size_t i = 0; i < n; ++i) {
+      float ms = 0.0f;
+      HIPCHK(hipEventElapsedTime(&ms, w->tev[k][2 * i], w->tev[k][2 * i + 1]));
+      sum += ms;
+      mx = ms > mx ? ms : mx;
+    }
+  }
+  w->tev_used[k] = 0;
+  if (launches) *launches = (int64_t)n;
+  if (total_ms) *total_ms = sum;
+  if (max_ms) *max_ms = mx;
   return VUDA_OK;
 }
 

@@ -23,6 +23,7 @@ FLAG_DEBUG = 1
 TUNE_RASTER_THREADS, TUNE_REC_CAP, TUNE_PHYS_PERSISTENT, TUNE_RASTER_PERSISTENT, TUNE_GRAPHS = 1, 2, 3, 4, 5
 TUNE_PHYS_PRIORITY = 6
 TUNE_BROADPHASE = 7
+TUNE_TIMING = 8
 GROUND = 0xFFFF
 
 EXPORTS = [
@@ -32,7 +33,7 @@ EXPORTS = [
     "vuda_probe_placement", "vuda_strerror", "vuda_last_error_message", "vuda_run",
     "vuda_autotune", "vuda_serve_create", "vuda_serve_destroy", "vuda_serve_submit",
     "vuda_serve_tick", "vuda_serve_completed", "vuda_serve_result", "vuda_serve_stats",
-    "vuda_serve_world",
+    "vuda_serve_world", "vuda_phase_times",
 ]
 SCHED_SERIAL, SCHED_INTERSTEP, SCHED_INTERTRAJ = 0, 1, 2
 SCHED_NAMES = {SCHED_SERIAL: "serial", SCHED_INTERSTEP: "interstep", SCHED_INTERTRAJ: "intertraj"}
@@ -280,6 +281,13 @@ class World:
         v = C.c_int32()
         check(lib().vuda_get_tuning(self._w, key, C.byref(v)))
         return v.value
+
+    def phase_times(self, phase: int) -> Dict:
+        """Launch count, total and max duration (ms) recorded with TUNE_TIMING
+        on since the previous call for this phase."""
+        n, tot, mx = C.c_int64(), C.c_double(), C.c_double()
+        check(lib().vuda_phase_times(self._w, phase, C.byref(n), C.byref(tot), C.byref(mx)))
+        return {"launches": n.value, "total_ms": tot.value, "max_ms": mx.value}
 
     def stream(self, phase: int) -> int:
         p = C.c_void_p()

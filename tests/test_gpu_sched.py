@@ -198,3 +198,23 @@ def test_invalid_calls():
         w.step(0, 1)
         with pytest.raises(vuda.VudaError):
             w.step(0, 2)
+
+
+def test_launch_timing_counts_and_leaves_results_unchanged():
+    s = sg.config_scene(2, n_envs=64)
+    ref = reference(s, 6)
+    with vuda.World(s) as w:
+        w.set_tuning(vuda.TUNE_TIMING, 1)
+        w.cosched(0.5)
+        for _ in range(6):
+            w.step()
+            w.render()
+        w.wait()
+        ts, tr = w.phase_times(vuda.PHASE_STEP), w.phase_times(vuda.PHASE_RENDER)
+        say(f"timing: step {ts}, render {tr}")
+        assert ts["launches"] == 6 and tr["launches"] == 6
+        for t in (ts, tr):
+            assert 0 < t["max_ms"] <= t["total_ms"] < 1e4
+        assert w.phase_times(vuda.PHASE_STEP)["launches"] == 0  # read resets the count
+        w.set_tuning(vuda.TUNE_TIMING, 0)
+        assert_same(ref, outputs(w))

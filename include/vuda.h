@@ -226,10 +226,11 @@ int vuda_world_info(vuda_world* w, int32_t* n_envs, int64_t* n_bodies, int32_t* 
 /*
  * Launch-shape knobs (the autotuner's search space).  Keys:
  *   VUDA_TUNE_RASTER_THREADS   raster workgroup size, multiple of 64 (default 256)
- *   VUDA_TUNE_REC_CAP          triangle setup records a raster workgroup keeps in
- *                              LDS (0: automatic, 55% of the largest primitive
- *                              count); images with more visible triangles take
- *                              a slower path with the same output
+ *   VUDA_TUNE_REC_CAP          tile-bin entries an image may use (0: its whole
+ *                              capacity, 4 per primitive of its env); an image
+ *                              needing more is rendered without bins, each
+ *                              tile testing every visible triangle (slower,
+ *                              same output)
  *   VUDA_TUNE_PHYS_PERSISTENT  0: one workgroup per env; n > 0: n resident
  *                              workgroups pulling envs from a device queue
  *   VUDA_TUNE_RASTER_PERSISTENT  the same for camera images
@@ -260,14 +261,18 @@ int vuda_get_tuning(vuda_world* w, int32_t key, int32_t* value);
 /*
  * Launch durations recorded while VUDA_TUNE_TIMING is on: for `phase`
  * (VUDA_PHASE_STEP or VUDA_PHASE_RENDER), waits for the last recorded launch,
- * then returns the number of launches since the previous call and the sum and
- * maximum of their durations in milliseconds (GPU time between the event
- * recorded after the launch's stream waits were satisfied and the event after
- * its kernels), and starts a new count.  A launch is one physics or raster
- * kernel over the enqueued env range (with its queue reset when persistent).
- * Any output pointer may be NULL.
+ * then returns the number of launches since the last read of part 0 and the
+ * sum and maximum of their durations in milliseconds; a read of part 0 starts
+ * a new count.  A launch is the phase's work over one enqueued env range:
+ * the physics kernel, or the raster setup kernel followed by the raster tile
+ * kernel (each with its queue reset when persistent).  Durations are GPU time
+ * between events on the launch's stream, the first recorded after the
+ * launch's stream waits were satisfied.  `part` selects 0 the whole launch,
+ * 1 its first kernel, 2 the raster tile kernel (VUDA_PHASE_RENDER only; with
+ * VUDA_TUNE_GRAPHS on, the launch is one graph and part 2 reads 0).  Any
+ * output pointer may be NULL.
  */
-int vuda_phase_times(vuda_world* w, int32_t phase, int64_t* launches, double* total_ms,
+int vuda_phase_times(vuda_world* w, int32_t phase, int32_t part, int64_t* launches, double* total_ms,
                      double* max_ms);
 
 /*

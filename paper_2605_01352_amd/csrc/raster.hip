@@ -1,32 +1,37 @@
-// Tiled software rasterizer for gfx950: one workgroup per camera image.
+// Tiled software rasterizer for gfx950: two kernels per render launch.
 //
-// Per image:
-//   1. bodies: pose from the physics state buffer (read in place, no copy)
-//      and R(q) into LDS; template vertex and face tables into LDS;
-//   2. vertices: every template vertex of every body (and the ground) is
-//      transformed once -- world = p + R (s v), clip = VP world, perspective
-//      divide, viewport, snap to 24.8 fixed point -- and cached in LDS;
+// raster_setup_kernel, one workgroup per camera image:
+//   1. body poses, read in place from the physics state buffer, with R(q),
+//      and the mesh templates go to LDS;
+//   2. every template vertex of every body (and the ground) is transformed
+//      once -- world = p + R (s v), clip = VP world, perspective divide,
+//      viewport, snap to 24.8 fixed point -- into an LDS vertex cache;
 //   3. triangle setup: a triangle is culled if a vertex is behind the near
 //      plane or outside the guard band, if it is back-facing or degenerate
-//      (integer area <= 0), or if its bounding box holds no pixel centre;
-//      survivors get a setup record in LDS (snapped vertices in edge order,
-//      depths, 1/area, primitive key and its flat Lambert colour) and are
-//      binned into 16x16-pixel tiles with LDS atomics, a workgroup prefix
-//      scan of the tile counts and a scatter;
-//   4. tiles: each wave takes one tile at a time and keeps the tile's
-//      z-buffer of 64-bit keys (depth << 32 | primitive << 16 | record) in
-//      LDS.  Small triangles (box within the tile <= 64 pixels) are packed as
-//      fragments, one pixel per lane across several triangles; large ones run
-//      one lane per four pixels.  Edge functions are exact (integer values
-//      carried in fp64, which represents them without rounding); a pixel is
-//      covered if every edge value is > 0, or == 0 on a top-left edge.  Depth
-//      is interpolated in fp32 and quantised to 24 bits; the minimum key wins,
-//      so the result does not depend on bin order or on which lane tests
-//      which pixel;
-//   5. the winner's colour from its record, RGB8 + u32 depth stores.
-// Images whose records or bins do not fit the LDS budget take a slower path
-// that re-derives each triangle from the vertex cache per tile and bins
-// tiles in groups that fit; both paths produce identical bits.
+//      (integer area <= 0), or if its bounding box holds no pixel centre.  A
+//      survivor gets a setup record in the image's raster scratch (snapped
+//      vertices in edge order, depths, 1/area, key and flat Lambert colour)
+//      and the tiles of its box are counted with LDS atomics;
+//   4. a workgroup prefix scan of the counts places each 16x16 tile's bin; a
+//      scatter pass classifies each triangle against every tile of its box
+//      (exact corner test of the edge functions) and appends its record id,
+//      flagged when the triangle covers the whole tile.
+// raster_tile_kernel, one wave per tile and four tiles per workgroup; a lane
+//   owns four horizontally adjacent pixels.  The bin is read in batches of 64
+//   records.  Small triangles (at most 64 pixels of their box in the tile)
+//   are expanded into fragments, one pixel per lane across several
+//   triangles, whose keys meet in an LDS z-buffer through atomic minimum;
+//   large ones are tested by every lane on its own four pixels, keeping the
+//   minimum in registers.  Edge functions are exact (integer values carried
+//   in fp64); a pixel centre is covered if every edge value is > 0, or == 0
+//   on a top-left edge.  Depth is interpolated in fp32 and quantised to 24
+//   bits, and the minimum key (depth << 32 | primitive << 16 | record) wins,
+//   so the result depends neither on bin order nor on which lane tests which
+//   pixel.  The winner's colour comes from its record; depth and RGB8 leave
+//   in 16- and 4-byte stores.
+// An image whose bins exceed their capacity, or whose tile table does not fit
+// the setup kernel's LDS, is marked unbinned: each of its tiles then tests
+// every record of the image -- slower, with the same output.
 #include <cstddef>
 
 #include "vuda_internal.h"
@@ -36,56 +41,33 @@
 namespace vuda {
 namespace {
 
-constexpr int kMaxTileWindow = 1024;
-constexpr int kRecWords = 12;  // X0 Y0 X1 Y1 | X2 Y2 key z0 | z1 z2 invA rgb
-// per wave: tile z-buffer (256 x u64), coverage counts (256 x i32), fragment owners (64 x i32)
-constexpr int kWaveBytes = 256 * 8 + 256 * 4 + 64 * 4;
-
-// The template vertex and face tables (the leading members of Templates)
-// are copied into LDS per workgroup; normals and shading constants, used once
-// per visible triangle, stay in global memory.
-struct TplLDS {
-  float sphere_v[kMaxTplVerts][3];
-  float cube_v[kMaxTplVerts][3];
-  float ground_v[kMaxGroundVerts][3];
-  uint8_t sphere_f[kMaxTplFaces][3];
-  uint8_t cube_f[kMaxTplFaces][3];
-  uint8_t ground_f[kMaxGroundFaces][3];
-};
-constexpr int kTplBytes = ((int)sizeof(TplLDS) + 15) & ~15;
-static_assert(offsetof(Templates, sphere_v) == offsetof(TplLDS, sphere_v) &&
-              offsetof(Templates, ground_f) == offsetof(TplLDS, ground_f) &&
-              kTplBytes <= (int)sizeof(Templates), "template tables lead Templates");
-
-struct RasterLayout {
-  // byte offsets into dynamic LDS
-  int tpl, maps, body, verts, recs, tiles, waves, misc, total;
-  int nmax, vmax, tw, rec_cap, bin_cap_fast, bin_cap_slow, nwaves;
-};
+constexpr int kMaxLdsTiles = 4096;  // tile table held in the setup kernel's LDS
+constexpr int kSmallMax = 64;       // box pixels in the tile of a fragment-packed triangle
+constexpr int kTileWaves = 4;       // tiles (one per wave) per tile-kernel workgroup
+constexpr int kWide = 8;            // triangles over more tiles are binned by their whole wave
+constexpr int kTplBytes = (int)((sizeof(Templates) + 15) & ~(size_t)15);
 
 __host__ __device__ inline int align16(int x) { return (x + 15) & ~15; }
 
-__host__ __device__ inline RasterLayout make_layout(int max_bodies, int max_verts, int max_tiles,
-                                                    int max_tris, int rec_cap, int threads) {
-  RasterLayout L;
+struct SetupLayout {
+  // byte offsets into the setup kernel's dynamic LDS
+  int tpl, body, verts, vis, tiles, misc, total;
+  int nmax, vmax, tw;
+};
+
+__host__ __device__ inline SetupLayout setup_layout(int max_bodies, int max_verts, int max_tiles,
+                                                    int max_tris) {
+  SetupLayout L;
   L.nmax = max_bodies + 1;
   L.vmax = max_verts;
-  L.tw = max_tiles < kMaxTileWindow ? max_tiles : kMaxTileWindow;
-  L.rec_cap = rec_cap;
-  L.nwaves = threads / 64;
-  const int vb = align16(12 * L.vmax), bb = align16(8 * rec_cap);
-  const int vbytes = vb > bb ? vb : bb;
-  L.bin_cap_fast = vbytes / 2;                // u16 record ids in the vertex region
-  L.bin_cap_slow = kRecWords * rec_cap;       // u32 entries in the record region
+  L.tw = max_tiles < kMaxLdsTiles ? max_tiles : kMaxLdsTiles;
   int o = 0;
-  L.tpl = o;    o += align16(kTplBytes);
-  L.maps = o;   o += align16(max_tris) + align16(max_verts);  // prim and vertex -> body
-  L.body = o;   o += align16(4 * 18 * L.nmax);
-  L.verts = o;  o += vbytes;
-  L.recs = o;   o += align16(4 * kRecWords * rec_cap);
+  L.tpl = o;    o += kTplBytes;
+  L.body = o;   o += align16(4 * 17 * L.nmax);
+  L.verts = o;  o += align16(12 * L.vmax);
+  L.vis = o;    o += align16(2 * max_tris);
   L.tiles = o;  o += align16(4 * (3 * L.tw + 1));
-  L.waves = o;  o += L.nwaves * kWaveBytes;
-  L.misc = o;   o += 128;  // scalars [0, 8), per-wave scan totals [8, 24)
+  L.misc = o;   o += 128;  // [2] record count, [4] queue slot, [8, 24) scan totals
   L.total = o;
   return L;
 }
@@ -95,8 +77,8 @@ struct BodyLDS {
   float* R;       // [9][nmax]
   float* s;       // [nmax]
   int32_t* type;  // [nmax]
-  int32_t* vb;    // [nmax] vertex base (env-local), vb[n] = total verts
-  int32_t* pb;    // [nmax] primitive base, pb[n] = total prims
+  int32_t* vb;    // [nmax] vertex base (env-local)
+  int32_t* pb;    // [nmax] primitive base
   int32_t* alb;   // [nmax]
 };
 
@@ -124,10 +106,10 @@ struct Tri {
   bool ok;
 };
 
-// vertex indices (env-local) of primitive `prim`; body = -1 for the ground
-__device__ __forceinline__ void prim_vertices(const TplLDS* T, const BodyLDS& B, const uint8_t* pmap,
-                                              int prim, int* body, int vid[3]) {
-  const int b = pmap[prim];
+// vertex indices (env-local) of primitive `prim` whose body (from the map) is
+// b; *body = -1 for the ground
+__device__ __forceinline__ void prim_vertices(const Templates* T, const BodyLDS& B, int b, int prim,
+                                              int* body, int vid[3]) {
   if (b == kGroundBody) {
     *body = -1;
 #pragma unroll
@@ -179,9 +161,9 @@ __device__ __forceinline__ bool top_left(int32_t dx, int32_t dy) {
   return dy < 0 || (dy == 0 && dx > 0);
 }
 
-// Classify the pixel centres of the tile block [x0..x1] x [y0..y1] against
-// the edges of a snapped triangle (edge order): 0 none can be covered, 1 some
-// may be, 2 all are.  Edge values are affine in the pixel centre, so their
+// Classify the pixel centres of the block [x0..x1] x [y0..y1] against the
+// edges of a snapped triangle (edge order): 0 none can be covered, 1 some may
+// be, 2 all are.  Edge values are affine in the pixel centre, so their
 // extremes over the block are at its corners; all values are exact in fp64.
 __device__ __forceinline__ int tile_class(const int32_t* X, const int32_t* Y, int x0, int x1, int y0,
                                           int y1) {
@@ -232,59 +214,6 @@ __device__ __forceinline__ uint32_t face_color(const Templates* tp, const BodyLD
   return rgb;
 }
 
-__device__ __forceinline__ void store_pixel(const WorldDev& W, int64_t pix, uint32_t rgb, uint32_t D,
-                                            int32_t win, int cover) {
-  W.rgb[3 * pix] = (uint8_t)(rgb & 0xFF);
-  W.rgb[3 * pix + 1] = (uint8_t)((rgb >> 8) & 0xFF);
-  W.rgb[3 * pix + 2] = (uint8_t)((rgb >> 16) & 0xFF);
-  W.depth[pix] = D;
-  if (W.winners) W.winners[pix] = win;
-  if (W.coverage) W.coverage[pix] = cover;
-}
-
-struct Rec {
-  int32_t X[3], Y[3];
-  uint32_t key;
-  float z[3];
-  float invA;
-};
-
-__device__ __forceinline__ Rec load_rec(const int32_t* recs, int r) {
-  const int4* p = (const int4*)(recs + kRecWords * r);
-  const int4 a = p[0], b = p[1], c = p[2];
-  Rec R;
-  R.X[0] = a.x; R.Y[0] = a.y; R.X[1] = a.z; R.Y[1] = a.w;
-  R.X[2] = b.x; R.Y[2] = b.y; R.key = (uint32_t)b.z; R.z[0] = __int_as_float(b.w);
-  R.z[1] = __int_as_float(c.x); R.z[2] = __int_as_float(c.y); R.invA = __int_as_float(c.z);
-  return R;
-}
-
-__device__ __forceinline__ void store_rec(int32_t* recs, int r, const Tri& t, uint32_t key, float invA,
-                                          uint32_t rgb) {
-  int4* p = (int4*)(recs + kRecWords * r);
-  p[0] = make_int4(t.X[0], t.Y[0], t.X[1], t.Y[1]);
-  p[1] = make_int4(t.X[2], t.Y[2], (int32_t)key, __float_as_int(t.z[0]));
-  p[2] = make_int4(__float_as_int(t.z[1]), __float_as_int(t.z[2]), __float_as_int(invA), (int32_t)rgb);
-}
-
-// Coverage and key of one pixel centre (Px, Py in 24.8 units) for a record.
-__device__ __forceinline__ bool pixel_key(const Rec& R, int Px, int Py, uint64_t* key) {
-  double E[3];
-  bool in = true;
-#pragma unroll
-  for (int e = 0; e < 3; ++e) {
-    const int a = (e + 1) % 3, b = (e + 2) % 3;
-    const int32_t dx = R.X[b] - R.X[a], dy = R.Y[b] - R.Y[a];
-    E[e] = (double)dx * (double)(Py - R.Y[a]) - (double)dy * (double)(Px - R.X[a]);
-    in = in && (E[e] > 0.0 || (E[e] == 0.0 && top_left(dx, dy)));
-  }
-  if (!in) return false;
-  const float zz = (((float)E[0] * R.z[0] + (float)E[1] * R.z[1]) + (float)E[2] * R.z[2]) * R.invA;
-  const uint32_t D = (uint32_t)rintf(fminf(fmaxf(zz, 0.0f), 1.0f) * 16777215.0f);
-  *key = ((uint64_t)D << 32) | R.key;
-  return true;
-}
-
 // Inclusive wave64 scans with DPP row shifts and row broadcasts: each step is
 // a VALU operation reading a neighbour lane, with no LDS round trip.  Lanes
 // whose source is outside the row read the identity (0; values are >= 0).
@@ -307,21 +236,10 @@ __device__ __forceinline__ int wave_incl_max(int x) {
   return x;
 }
 
-struct ImageCtx {
-  int Wd, Ht, ntx, nty, ntiles;
-  int64_t pix_off;
-  int env;
-};
-
 // Exclusive prefix sum over the workgroup of one value per thread.
 __device__ __forceinline__ int wg_excl_scan(int v, int32_t* tmp, int* total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  int x = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int y = __shfl_up(x, d, 64);
-    if (lane >= d) x += y;
-  }
+  const int x = wave_incl_add(v);
   if (lane == 63) tmp[wave] = x;
   __syncthreads();
   int base = 0, tot = 0;
@@ -353,304 +271,59 @@ __device__ __forceinline__ int tile_scan(const int32_t* cnt, int32_t* toff, int 
   return total;
 }
 
-// Fast path, step 4: one tile by one wave, from setup records.
-__device__ void raster_tile_fast(const WorldDev& W, const ImageCtx& im, const int32_t* recs,
-                                 const uint16_t* bins, int k0, int k1, int tile, uint64_t* zb,
-                                 int32_t* cov) {
-  int32_t* own = cov + 256;  // 64 fragment-owner marks of this wave
-  const int lane = threadIdx.x & 63;
-  const int tx = tile % im.ntx, ty = tile / im.ntx;
-  const int tx0 = tx * kTile, ty0 = ty * kTile;
-  const int tx1 = min(tx0 + kTile - 1, im.Wd - 1), ty1 = min(ty0 + kTile - 1, im.Ht - 1);
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    zb[lane + 64 * r] = ~0ull;
-    cov[lane + 64 * r] = 0;
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  // this lane's four pixels for the large-triangle path
-  const int px = tx0 + (lane & 15);
-  const int py0 = ty0 + (lane >> 4);
-  uint64_t kreg[4];
-  int creg[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) { kreg[r] = ~0ull; creg[r] = 0; }
-
-  for (int kb = k0; kb < k1; kb += 64) {
-    const int k = kb + lane;
-    int rec = 0, fx0 = 0, fy0 = 0, bw = 1, area = 0, full = 0;
-    if (k < k1) {
-      const int entry = bins[k];
-      rec = entry & 0x7FFF;
-      full = entry >> 15;
-      const Rec R = load_rec(recs, rec);
-      int x0, x1, y0, y1;
-      tri_pixels(R.X, R.Y, im.Wd, im.Ht, &x0, &x1, &y0, &y1);
-      fx0 = max(x0, tx0);
-      fy0 = max(y0, ty0);
-      bw = min(x1, tx1) - fx0 + 1;
-      const int bh = min(y1, ty1) - fy0 + 1;
-      area = (bw > 0 && bh > 0) ? bw * bh : 0;
-      if (bw < 1) bw = 1;
-    }
-    const bool big = area > 64;
-    // small triangles: fragments packed over lanes.  Fragment f belongs to
-    // the lane j with off_j <= f < off_j + a_j; per window of 64 fragments
-    // each owner marks where its range starts and a max-scan spreads it.
-    const int a = big ? 0 : area;
-    const int incl = wave_incl_add(a);
-    const int F = __builtin_amdgcn_readlane(incl, 63);
-    const int off = incl - a;
-    int carry = 0;  // owner + 1 of the fragment before the window
-    for (int f0 = 0; f0 < F; f0 += 64) {
-      own[lane] = 0;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      if (a > 0 && off >= f0 && off < f0 + 64) own[off - f0] = lane + 1;
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      int o = own[lane];
-      if (lane == 0) o = max(o, carry);
-      o = wave_incl_max(o);
-      carry = __builtin_amdgcn_readlane(o, 63);
-      const int j = o - 1;  // >= 0 for every fragment below F
-      const int f = f0 + lane;
-      const int jrec = __shfl(rec, j, 64);
-      const int jx0 = __shfl(fx0, j, 64), jy0 = __shfl(fy0, j, 64);
-      const int jbw = __shfl(bw, j, 64), joff = __shfl(off, j, 64);
-      if (f < F) {
-        const int rr = f - joff;
-        // rr / jbw exactly: rr < 64 and jbw <= 16 leave a margin far above the rounding
-        const int qy = (int)(((float)rr + 0.5f) * (1.0f / (float)jbw));
-        const int qx = rr - qy * jbw;
-        const int ppx = jx0 + qx, ppy = jy0 + qy;
-        const int p = (ppy - ty0) * kTile + (ppx - tx0);
-        const Rec R = load_rec(recs, jrec);
-        uint64_t kk;
-        if (p >= 0 && p < 256 && pixel_key(R, 256 * ppx + 128, 256 * ppy + 128, &kk)) {
-          atomicMin((unsigned long long*)&zb[p], (unsigned long long)kk);
-          atomicAdd(&cov[p], 1);
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    }
-    // large triangles: one lane per four pixels, the record uniform
-    uint64_t m = __ballot(big);
-    while (m) {
-      const int j = __ffsll((unsigned long long)m) - 1;
-      m &= m - 1ull;
-      const int jrec = __builtin_amdgcn_readfirstlane(__shfl(rec, j, 64));
-      const bool jfull = __builtin_amdgcn_readfirstlane(__shfl(full, j, 64)) != 0;
-      const Rec R = load_rec(recs, jrec);
-      // E is an integer held exactly in fp64; inside the edge means E > 0, or
-      // E == 0 on a top-left edge, i.e. E + tl > 0 with tl in {0, 1}.
-      double ea[3], E[3], tb[3];
-#pragma unroll
-      for (int e = 0; e < 3; ++e) {
-        const int a0 = (e + 1) % 3, b0 = (e + 2) % 3;
-        const int32_t dx = R.X[b0] - R.X[a0], dy = R.Y[b0] - R.Y[a0];
-        ea[e] = (double)dx * 1024.0;  // 4 pixel rows down
-        tb[e] = top_left(dx, dy) ? 1.0 : 0.0;
-        E[e] = (double)dx * (double)(256 * py0 + 128 - R.Y[a0]) - (double)dy * (double)(256 * px + 128 - R.X[a0]);
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const double m = fmin(fmin(E[0] + tb[0], E[1] + tb[1]), E[2] + tb[2]);
-        const float zz = (((float)E[0] * R.z[0] + (float)E[1] * R.z[1]) + (float)E[2] * R.z[2]) * R.invA;
-        const uint32_t D = (uint32_t)rintf(fminf(fmaxf(zz, 0.0f), 1.0f) * 16777215.0f);
-        const uint64_t kk = ((uint64_t)D << 32) | R.key;
-        const bool in = jfull || m > 0.0;
-        creg[r] += in ? 1 : 0;
-        kreg[r] = (in && kk < kreg[r]) ? kk : kreg[r];
-#pragma unroll
-        for (int e = 0; e < 3; ++e) E[e] += ea[e];
-      }
-    }
-  }
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int py = py0 + 4 * r;
-    if (px > tx1 || py > ty1) continue;
-    const int p = lane + 64 * r;
-    const uint64_t z = zb[p];
-    const uint64_t key = z < kreg[r] ? z : kreg[r];
-    const int64_t pix = im.pix_off + (int64_t)py * im.Wd + px;
-    uint32_t rgb = 0, D = 0xFFFFFFFFu;
-    int32_t win = -1;
-    if (key != ~0ull) {
-      const uint32_t lo = (uint32_t)key;
-      D = (uint32_t)(key >> 32);
-      win = (int32_t)(lo >> 16);
-      rgb = (uint32_t)recs[kRecWords * (lo & 0xFFFFu) + 11];
-    }
-    store_pixel(W, pix, rgb, D, win, cov[p] + creg[r]);
-  }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+__device__ __forceinline__ void store_rec(int4* recs, int r, const Tri& t, uint32_t key, float invA,
+                                          uint32_t rgb) {
+  int4* p = recs + 3 * r;
+  p[0] = make_int4(t.X[0], t.Y[0], t.X[1], t.Y[1]);
+  p[1] = make_int4(t.X[2], t.Y[2], (int32_t)key, __float_as_int(t.z[0]));
+  p[2] = make_int4(__float_as_int(t.z[1]), __float_as_int(t.z[2]), __float_as_int(invA), (int32_t)rgb);
 }
 
-// Slow path: re-derive triangles from the vertex cache, tiles in groups whose
-// bins fit the record region.  Keys: depth << 32 | (body + 1) << 16 | prim.
-__device__ void raster_slow(unsigned char* lds, const RasterLayout& Lo, const WorldDev& W,
-                            const TplLDS* T, const BodyLDS& B, const uint8_t* pmap, int ntris,
-                            const ImageCtx& im, bool* overflow) {
-  const int tid = threadIdx.x;
-  const int nthr = blockDim.x;
-  const Templates* tp = W.tpl;
-  const int32_t* VX = (const int32_t*)(lds + Lo.verts);
-  const int32_t* VY = VX + Lo.vmax;
-  const float* VZ = (const float*)(VY + Lo.vmax);
-  int32_t* tcount = (int32_t*)(lds + Lo.tiles);
-  int32_t* toff = tcount + Lo.tw;
-  int32_t* tfill = toff + Lo.tw + 1;
-  uint32_t* bins = (uint32_t*)(lds + Lo.recs);
-  int32_t* misc = (int32_t*)(lds + Lo.misc);
-  const int bin_cap = Lo.bin_cap_slow;
-  const int nwaves = nthr >> 6;
-  const int wave = tid >> 6, lane = tid & 63;
-
-  for (int w0 = 0; w0 < im.ntiles; w0 += Lo.tw) {
-    const int w1 = min(im.ntiles, w0 + Lo.tw);
-    for (int t = tid; t < w1 - w0; t += nthr) tcount[t] = 0;
-    __syncthreads();
-    for (int pr = tid; pr < ntris; pr += nthr) {
-      int body, vid[3];
-      prim_vertices(T, B, pmap, pr, &body, vid);
-      const Tri t = load_tri(VX, VY, VZ, vid);
-      if (!t.ok || tri_area(t.X, t.Y) <= 0) continue;
-      int x0, x1, y0, y1;
-      if (!tri_pixels(t.X, t.Y, im.Wd, im.Ht, &x0, &x1, &y0, &y1)) continue;
-      for (int ty = y0 >> 4; ty <= (y1 >> 4); ++ty)
-        for (int tx = x0 >> 4; tx <= (x1 >> 4); ++tx) {
-          const int ti = ty * im.ntx + tx - w0;
-          if (ti >= 0 && ti < w1 - w0) atomicAdd(&tcount[ti], 1);
-        }
-    }
-    __syncthreads();
-    tile_scan(tcount, toff, w1 - w0, misc + 8);
-    int g0 = 0;
-    while (g0 < w1 - w0) {
-      if (tid == 0) {
-        int g1 = g0 + 1;
-        while (g1 < w1 - w0 && toff[g1 + 1] - toff[g0] <= bin_cap) ++g1;
-        misc[0] = g1;
-        misc[1] = toff[g1] - toff[g0] > bin_cap ? 1 : 0;
-      }
-      __syncthreads();
-      const int g1 = misc[0];
-      if (misc[1]) *overflow = true;
-      const int base = toff[g0];
-      for (int t = g0 + tid; t < g1; t += nthr) tfill[t] = 0;
-      __syncthreads();
-      for (int pr = tid; pr < ntris; pr += nthr) {
-        int body, vid[3];
-        prim_vertices(T, B, pmap, pr, &body, vid);
-        const Tri t = load_tri(VX, VY, VZ, vid);
-        if (!t.ok || tri_area(t.X, t.Y) <= 0) continue;
-        int x0, x1, y0, y1;
-        if (!tri_pixels(t.X, t.Y, im.Wd, im.Ht, &x0, &x1, &y0, &y1)) continue;
-        const uint32_t entry = (uint32_t)pr | ((uint32_t)(body + 1) << 16);
-        for (int ty = y0 >> 4; ty <= (y1 >> 4); ++ty)
-          for (int tx = x0 >> 4; tx <= (x1 >> 4); ++tx) {
-            const int ti = ty * im.ntx + tx - w0;
-            if (ti >= g0 && ti < g1) {
-              const int slot = toff[ti] - base + atomicAdd(&tfill[ti], 1);
-              if (slot < bin_cap) bins[slot] = entry;
-            }
-          }
-      }
-      __syncthreads();
-      for (int ti = g0 + wave; ti < g1; ti += nwaves) {
-        const int tile = w0 + ti;
-        const int tx = tile % im.ntx, ty = tile / im.ntx;
-        const int px = tx * kTile + (lane & 15);
-        const int py0 = ty * kTile + (lane >> 4);
-        uint64_t key[4];
-        int cover[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) { key[r] = ~0ull; cover[r] = 0; }
-        const int k0 = toff[ti] - base, k1 = min(toff[ti + 1] - base, bin_cap);
-        for (int k = k0; k < k1; ++k) {
-          const uint32_t entry = __builtin_amdgcn_readfirstlane(bins[k]);
-          int body, vid[3];
-          prim_vertices(T, B, pmap, (int)(entry & 0xFFFFu), &body, vid);
-          const Tri t = load_tri(VX, VY, VZ, vid);
-          Rec R;
-#pragma unroll
-          for (int q = 0; q < 3; ++q) { R.X[q] = t.X[q]; R.Y[q] = t.Y[q]; R.z[q] = t.z[q]; }
-          R.key = entry;
-          R.invA = 1.0f / (float)(double)tri_area(t.X, t.Y);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            uint64_t kk;
-            if (pixel_key(R, 256 * px + 128, 256 * (py0 + 4 * r) + 128, &kk)) {
-              cover[r] += 1;
-              if (kk < key[r]) key[r] = kk;
-            }
-          }
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int py = py0 + 4 * r;
-          if (px >= im.Wd || py >= im.Ht) continue;
-          uint32_t rgb = 0, D = 0xFFFFFFFFu;
-          int32_t win = -1;
-          if (key[r] != ~0ull) {
-            const uint32_t e = (uint32_t)key[r];
-            D = (uint32_t)(key[r] >> 32);
-            win = (int32_t)(e & 0xFFFFu);
-            const int body = (int)(e >> 16) - 1;
-            rgb = face_color(tp, B, Lo.nmax, body, body < 0 ? win : win - B.pb[body]);
-          }
-          store_pixel(W, im.pix_off + (int64_t)py * im.Wd + px, rgb, D, win, cover[r]);
-        }
-      }
-      __syncthreads();
-      g0 = g1;
-    }
-  }
-}
-
-constexpr int kWide = 8;
-
-// Bin record r into tile (tx, ty) unless its edges miss the tile; flag the
-// entry when the triangle covers every pixel of the tile.
-__device__ __forceinline__ void bin_tile(const Rec& R, int r, int tx, int ty, int x0, int x1, int y0,
-                                         int y1, bool classify, const ImageCtx& im, const int32_t* toff,
-                                         int32_t* tfill, uint16_t* bins) {
+// Append record r to the bin of tile (tx, ty) unless its edges miss the tile;
+// flag the entry when the triangle covers every pixel of the tile.
+__device__ __forceinline__ void bin_tile(const Tri& t, int r, int tx, int ty, int x0, int x1, int y0,
+                                         int y1, bool classify, int Wd, int Ht, int ntx,
+                                         const int32_t* toff, int32_t* tfill, uint16_t* bins) {
   const int bx0 = max(x0, tx * kTile), bx1 = min(x1, tx * kTile + kTile - 1);
   const int by0 = max(y0, ty * kTile), by1 = min(y1, ty * kTile + kTile - 1);
-  const int cls = classify ? tile_class(R.X, R.Y, bx0, bx1, by0, by1) : 1;
+  const int cls = classify ? tile_class(t.X, t.Y, bx0, bx1, by0, by1) : 1;
   if (cls == 0) return;
   const bool whole = bx0 == tx * kTile && by0 == ty * kTile &&
-                     bx1 == min(im.Wd - 1, tx * kTile + kTile - 1) &&
-                     by1 == min(im.Ht - 1, ty * kTile + kTile - 1);
-  const int ti = ty * im.ntx + tx;
+                     bx1 == min(Wd - 1, tx * kTile + kTile - 1) &&
+                     by1 == min(Ht - 1, ty * kTile + kTile - 1);
+  const int ti = ty * ntx + tx;
   bins[toff[ti] + atomicAdd(&tfill[ti], 1)] = (uint16_t)(r | ((cls == 2 && whole) ? 0x8000 : 0));
 }
 
-__device__ void raster_image(unsigned char* lds, const RasterLayout& Lo, const WorldDev& W,
-                             const RasterLaunch& L, int cam_id) {
+// ---------------------------------------------------------------------------
+// setup kernel
+// ---------------------------------------------------------------------------
+
+__device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const WorldDev& W,
+                            const RasterLaunch& L, int cam_id) {
   const int tid = threadIdx.x;
   const int nthr = blockDim.x;
+  const int lane = tid & 63;
   const CamDev cam = W.cams[cam_id];
   const EnvDev ed = W.envs[cam.env];
   const int n = ed.n_bodies;
+  const int ntris = ed.n_tris;
   const int64_t cap = W.cap_bodies;
   const float* st = W.state[L.parity];
   const uint8_t* gpmap = W.prim_body + ed.prim_map;
   const uint8_t* gvmap = W.vert_body + ed.vert_map;
-  ImageCtx im;
-  im.Wd = cam.w;
-  im.Ht = cam.h;
-  im.ntx = (im.Wd + kTile - 1) / kTile;
-  im.nty = (im.Ht + kTile - 1) / kTile;
-  im.ntiles = im.ntx * im.nty;
-  im.pix_off = cam.pix_off;
-  im.env = cam.env;
+  const int Wd = cam.w, Ht = cam.h;
+  const int ntx = (Wd + kTile - 1) / kTile;
+  const int ntiles = tiles_of(Wd, Ht);
+  const RsLayout RL = rs_layout(cam.n_tris, ntiles);
+  unsigned char* rs = W.rscratch + cam.rs_off;
+  int32_t* hdr = (int32_t*)rs;
+  int32_t* ttab = (int32_t*)(rs + RL.tiles);
+  int4* grec = (int4*)(rs + RL.recs);
+  uint16_t* bins = (uint16_t*)(rs + RL.bins);
+  const int bin_cap = (L.bin_limit > 0 && L.bin_limit < RL.bin_cap) ? L.bin_limit : RL.bin_cap;
 
-  TplLDS* T = (TplLDS*)(lds + Lo.tpl);
-  const Templates* tp = W.tpl;
-  uint8_t* pmap = lds + Lo.maps;
-  uint8_t* vmap = pmap + align16(L.max_tris);
+  Templates* T = (Templates*)(lds + Lo.tpl);
   BodyLDS B;
   float* bf = (float*)(lds + Lo.body);
   B.p = bf;
@@ -663,19 +336,17 @@ __device__ void raster_image(unsigned char* lds, const RasterLayout& Lo, const W
   int32_t* VX = (int32_t*)(lds + Lo.verts);
   int32_t* VY = VX + Lo.vmax;
   float* VZ = (float*)(VY + Lo.vmax);
-  int32_t* recs = (int32_t*)(lds + Lo.recs);
+  uint16_t* vis = (uint16_t*)(lds + Lo.vis);
   int32_t* tcount = (int32_t*)(lds + Lo.tiles);
   int32_t* toff = tcount + Lo.tw;
   int32_t* tfill = toff + Lo.tw + 1;
   int32_t* misc = (int32_t*)(lds + Lo.misc);
 
-  // 1. bodies and templates
+  // 1. templates and bodies
   {
     const int4* src = (const int4*)W.tpl;
     int4* dst = (int4*)T;
     for (int i = tid; i < kTplBytes / 16; i += nthr) dst[i] = src[i];
-    for (int i = tid; i < (ed.n_tris + 15) / 16; i += nthr) ((int4*)pmap)[i] = ((const int4*)gpmap)[i];
-    for (int i = tid; i < (ed.n_verts + 15) / 16; i += nthr) ((int4*)vmap)[i] = ((const int4*)gvmap)[i];
   }
   for (int b = tid; b < n; b += nthr) {
     const int g = ed.body_off + b;
@@ -692,18 +363,18 @@ __device__ void raster_image(unsigned char* lds, const RasterLayout& Lo, const W
     B.pb[b] = W.prim_base[g];
     B.alb[b] = W.albedo[g];
   }
-  if (tid == 0) misc[2] = 0;  // records
-  const bool fast_tiles = im.ntiles <= Lo.tw;
-  if (fast_tiles)
-    for (int t = tid; t < im.ntiles; t += nthr) tcount[t] = 0;
+  const bool tiled = ntiles <= Lo.tw;
+  if (tid == 0) misc[2] = 0;
+  if (tiled)
+    for (int t = tid; t < ntiles; t += nthr) tcount[t] = 0;
   __syncthreads();
 
   // 2. vertices
   const float* vp = cam.vp;
-  const float fW = (float)im.Wd, fH = (float)im.Ht;
+  const float fW = (float)Wd, fH = (float)Ht;
   for (int vi = tid; vi < ed.n_verts; vi += nthr) {
     float wx, wy, wz;
-    const int b = vmap[vi];
+    const int b = gvmap[vi];
     if (b == kGroundBody) {
       wx = T->ground_v[vi][0];
       wy = T->ground_v[vi][1];
@@ -725,11 +396,11 @@ __device__ void raster_image(unsigned char* lds, const RasterLayout& Lo, const W
     const float cw = ((vp[12] * wx + vp[13] * wy) + vp[14] * wz) + vp[15];
     int32_t X = kInvalid, Y = kInvalid;
     float z = 0.0f;
-    if (!(cw < tp->near_w)) {
+    if (!(cw < T->near_w)) {
       const float nx = cx / cw, ny = cy / cw, nz = cz / cw;
       const float px = (nx * 0.5f + 0.5f) * fW;
       const float py = (0.5f - ny * 0.5f) * fH;
-      if (!(fabsf(px) > tp->guard || fabsf(py) > tp->guard)) {
+      if (!(fabsf(px) > T->guard || fabsf(py) > T->guard)) {
         X = (int32_t)rintf(px * 256.0f);
         Y = (int32_t)rintf(py * 256.0f);
         z = nz;
@@ -742,26 +413,23 @@ __device__ void raster_image(unsigned char* lds, const RasterLayout& Lo, const W
   __syncthreads();
 
   // 3. setup records (with the face colour) and tile counts.  A triangle
-  // whose box spans more than kWide tiles is binned by its whole wave, one
+  // whose box spans more than kWide tiles is counted by its whole wave, one
   // tile per lane, so that one lane never walks a long tile list alone.
-  const int ntris = ed.n_tris;
-  const int lane = tid & 63;
   for (int base = 0; base < ntris; base += nthr) {
     const int pr = base + tid;
     int tx0 = 0, ty0 = 0, nx = 0, ntl = 0;
     if (pr < ntris) {
       int body, vid[3];
-      prim_vertices(T, B, pmap, pr, &body, vid);
+      prim_vertices(T, B, gpmap[pr], pr, &body, vid);
       const Tri t = load_tri(VX, VY, VZ, vid);
       int x0, x1, y0, y1;
       if (t.ok) {
         const int64_t A = tri_area(t.X, t.Y);
-        if (A > 0 && tri_pixels(t.X, t.Y, im.Wd, im.Ht, &x0, &x1, &y0, &y1)) {
+        if (A > 0 && tri_pixels(t.X, t.Y, Wd, Ht, &x0, &x1, &y0, &y1)) {
           const int slot = atomicAdd(&misc[2], 1);
-          if (slot < Lo.rec_cap) {
-            const uint32_t rgb = face_color(tp, B, Lo.nmax, body, body < 0 ? pr : pr - B.pb[body]);
-            store_rec(recs, slot, t, ((uint32_t)pr << 16) | (uint32_t)slot, 1.0f / (float)(double)A, rgb);
-          }
+          const uint32_t rgb = face_color(T, B, Lo.nmax, body, body < 0 ? pr : pr - B.pb[body]);
+          store_rec(grec, slot, t, ((uint32_t)pr << 16) | (uint32_t)slot, 1.0f / (float)(double)A, rgb);
+          vis[slot] = (uint16_t)pr;
           tx0 = x0 >> 4;
           ty0 = y0 >> 4;
           nx = (x1 >> 4) - tx0 + 1;
@@ -769,11 +437,11 @@ __device__ void raster_image(unsigned char* lds, const RasterLayout& Lo, const W
         }
       }
     }
-    if (!fast_tiles) continue;
+    if (!tiled) continue;
     if (ntl <= kWide)
       for (int q = 0; q < ntl; ++q) {
         const int qy = q / nx;
-        atomicAdd(&tcount[(ty0 + qy) * im.ntx + tx0 + (q - qy * nx)], 1);
+        atomicAdd(&tcount[(ty0 + qy) * ntx + tx0 + (q - qy * nx)], 1);
       }
     uint64_t m = __ballot(ntl > kWide);
     while (m) {
@@ -783,75 +451,80 @@ __device__ void raster_image(unsigned char* lds, const RasterLayout& Lo, const W
       const int jnx = __shfl(nx, j, 64), jn = __shfl(ntl, j, 64);
       for (int q = lane; q < jn; q += 64) {
         const int qy = q / jnx;
-        atomicAdd(&tcount[(jy0 + qy) * im.ntx + jx0 + (q - qy * jnx)], 1);
+        atomicAdd(&tcount[(jy0 + qy) * ntx + jx0 + (q - qy * jnx)], 1);
       }
     }
   }
   __syncthreads();
   const int nrec = misc[2];
-  bool fast = fast_tiles && nrec <= Lo.rec_cap;
-  if (fast) {
-    const int total = tile_scan(tcount, toff, im.ntiles, misc + 8);
-    if (total > Lo.bin_cap_fast) fast = false;
+  // bin entries hold 15-bit record ids
+  bool binned = tiled && nrec <= 32768;
+  if (binned) {
+    const int total = tile_scan(tcount, toff, ntiles, misc + 8);
+    if (total > bin_cap) binned = false;
   }
 
-  bool overflow = false;
-  if (fast) {
-    // scatter record ids into the bins (the vertex cache is no longer needed)
-    uint16_t* bins = (uint16_t*)(lds + Lo.verts);
-    for (int t = tid; t < im.ntiles; t += nthr) tfill[t] = 0;
+  // 4. scatter record ids into the bins, from the vertex cache
+  if (binned) {
+    for (int t = tid; t < ntiles; t += nthr) tfill[t] = 0;
     __syncthreads();
     for (int base = 0; base < nrec; base += nthr) {
       const int r = base + tid;
       int x0 = 0, x1 = 0, y0 = 0, y1 = 0, nx = 0, ntl = 0;
-      Rec R;
+      Tri t{};
       if (r < nrec) {
-        R = load_rec(recs, r);
-        tri_pixels(R.X, R.Y, im.Wd, im.Ht, &x0, &x1, &y0, &y1);
+        const int pr = vis[r];
+        int body, vid[3];
+        prim_vertices(T, B, gpmap[pr], pr, &body, vid);
+        t = load_tri(VX, VY, VZ, vid);
+        tri_pixels(t.X, t.Y, Wd, Ht, &x0, &x1, &y0, &y1);
         nx = (x1 >> 4) - (x0 >> 4) + 1;
         ntl = nx * ((y1 >> 4) - (y0 >> 4) + 1);
       }
       if (ntl <= kWide)
         for (int q = 0; q < ntl; ++q) {
           const int qy = q / nx;
-          bin_tile(R, r, (x0 >> 4) + (q - qy * nx), (y0 >> 4) + qy, x0, x1, y0, y1, ntl > 1, im, toff,
-                   tfill, bins);
+          bin_tile(t, r, (x0 >> 4) + (q - qy * nx), (y0 >> 4) + qy, x0, x1, y0, y1, ntl > 1, Wd, Ht, ntx,
+                   toff, tfill, bins);
         }
       uint64_t m = __ballot(ntl > kWide);
       while (m) {
         const int j = __ffsll((unsigned long long)m) - 1;
         m &= m - 1ull;
         const int jr = __builtin_amdgcn_readfirstlane(__shfl(r, j, 64));
-        const Rec J = load_rec(recs, jr);
+        const int jp = vis[jr];
+        int jbody, jvid[3];
+        prim_vertices(T, B, gpmap[jp], jp, &jbody, jvid);
+        const Tri J = load_tri(VX, VY, VZ, jvid);
         int jx0, jx1, jy0, jy1;
-        tri_pixels(J.X, J.Y, im.Wd, im.Ht, &jx0, &jx1, &jy0, &jy1);
+        tri_pixels(J.X, J.Y, Wd, Ht, &jx0, &jx1, &jy0, &jy1);
         const int jnx = (jx1 >> 4) - (jx0 >> 4) + 1;
         const int jn = jnx * ((jy1 >> 4) - (jy0 >> 4) + 1);
         for (int q = lane; q < jn; q += 64) {
           const int qy = q / jnx;
-          bin_tile(J, jr, (jx0 >> 4) + (q - qy * jnx), (jy0 >> 4) + qy, jx0, jx1, jy0, jy1, true, im,
-                   toff, tfill, bins);
+          bin_tile(J, jr, (jx0 >> 4) + (q - qy * jnx), (jy0 >> 4) + qy, jx0, jx1, jy0, jy1, true, Wd, Ht,
+                   ntx, toff, tfill, bins);
         }
       }
     }
     __syncthreads();
-    const int wave = tid >> 6;
-    uint64_t* zb = (uint64_t*)(lds + Lo.waves + wave * kWaveBytes);
-    int32_t* cov = (int32_t*)(zb + 256);
-    for (int ti = wave; ti < im.ntiles; ti += Lo.nwaves)
-      raster_tile_fast(W, im, recs, bins, toff[ti], toff[ti] + tfill[ti], ti, zb, cov);
-  } else {
-    raster_slow(lds, Lo, W, T, B, pmap, ntris, im, &overflow);
+    for (int t = tid; t < ntiles; t += nthr) {
+      ttab[2 * t] = toff[t];
+      ttab[2 * t + 1] = tfill[t];
+    }
   }
-  if (overflow && tid == 0) atomicOr(&W.env_flags[cam.env], kFlagBinOverflow);
+  if (tid == 0) {
+    hdr[0] = nrec;
+    hdr[1] = binned ? 1 : 0;
+  }
 }
 
-__global__ void raster_kernel(WorldDev W, RasterLaunch L) {
+__global__ void raster_setup_kernel(WorldDev W, RasterLaunch L) {
   extern __shared__ __align__(16) unsigned char lds[];
-  const RasterLayout Lo = make_layout(L.max_bodies, L.max_verts, L.max_tiles, L.max_tris, L.rec_cap, blockDim.x);
+  const SetupLayout Lo = setup_layout(L.max_bodies, L.max_verts, L.max_tiles, L.max_tris);
   if (L.persistent == 0) {
     if ((int)blockIdx.x >= L.n_work) return;
-    raster_image(lds, Lo, W, L, L.work[blockIdx.x]);
+    setup_image(lds, Lo, W, L, L.work[blockIdx.x]);
     return;
   }
   int32_t* slot = (int32_t*)(lds + Lo.misc) + 4;
@@ -861,22 +534,255 @@ __global__ void raster_kernel(WorldDev W, RasterLaunch L) {
     __syncthreads();
     const int wi = *slot;
     if (wi >= L.n_work) return;
-    raster_image(lds, Lo, W, L, L.work[wi]);
+    setup_image(lds, Lo, W, L, L.work[wi]);
   }
+}
+
+// ---------------------------------------------------------------------------
+// tile kernel
+// ---------------------------------------------------------------------------
+
+struct TileWaveLDS {
+  uint64_t zb[256];     // z-buffer of the small-triangle fragments
+  int4 rec[64][3];      // the batch's setup records
+  int2 meta[64];        // (x0 | y0 << 16, fragment offset | box width << 16)
+  int32_t own[64];      // fragment owner marks
+};
+
+// Covered test and key of one pixel centre for a record (fragment path).
+__device__ __forceinline__ bool frag_key(const int4& ra, const int4& rb, const int4& rc, int ppx, int ppy,
+                                         uint64_t* key) {
+  const int32_t X[3] = {ra.x, ra.z, rb.x}, Y[3] = {ra.y, ra.w, rb.y};
+  const int Px = 256 * ppx + 128, Py = 256 * ppy + 128;
+  double E[3];
+  bool in = true;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const int a = (e + 1) % 3, b = (e + 2) % 3;
+    const int32_t dx = X[b] - X[a], dy = Y[b] - Y[a];
+    // both products and the sum are integers below 2^53: exact
+    E[e] = fma(-(double)dy, (double)(Px - X[a]), (double)dx * (double)(Py - Y[a]));
+    // integer-valued E: (E > 0 or E == 0 on a top-left edge) == (E >= threshold)
+    in = in && E[e] >= (top_left(dx, dy) ? 0.0 : 1.0);
+  }
+  if (!in) return false;
+  const float zz = (((float)E[0] * __int_as_float(rb.w) + (float)E[1] * __int_as_float(rc.x)) +
+                    (float)E[2] * __int_as_float(rc.y)) *
+                   __int_as_float(rc.z);
+  // the interpolated depth is finite, so the median equals the clamp to [0, 1]
+  const uint32_t D = (uint32_t)rintf(__builtin_amdgcn_fmed3f(zz, 0.0f, 1.0f) * 16777215.0f);
+  *key = ((uint64_t)D << 32) | (uint32_t)rb.z;
+  return true;
+}
+
+template <bool DBG>
+__device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam, int ntx, int ntiles,
+                                            int tile, TileWaveLDS& S, int32_t* cov) {
+  const int lane = threadIdx.x & 63;
+  const int Wd = cam.w, Ht = cam.h;
+  const RsLayout RL = rs_layout(cam.n_tris, ntiles);
+  const unsigned char* rs = W.rscratch + cam.rs_off;
+  const int32_t* hdr = (const int32_t*)rs;
+  const int nrec = hdr[0];
+  const bool binned = hdr[1] != 0;
+  const int4* grec = (const int4*)(rs + RL.recs);
+  const uint16_t* bins = (const uint16_t*)(rs + RL.bins);
+  int k0 = 0, k1 = nrec;
+  if (binned) {
+    const int32_t* tt = (const int32_t*)(rs + RL.tiles) + 2 * tile;
+    k0 = tt[0];
+    k1 = k0 + tt[1];
+  }
+  const int tx0 = (tile % ntx) * kTile, ty0 = (tile / ntx) * kTile;
+  const int tx1 = min(tx0 + kTile - 1, Wd - 1), ty1 = min(ty0 + kTile - 1, Ht - 1);
+  // this lane's pixels: (px0 + i, py) for i < 4, z-buffer entries 4 lane + i
+  const int py = ty0 + (lane >> 2), px0 = tx0 + 4 * (lane & 3);
+  uint64_t* zb = S.zb;
+  {
+    ulonglong2* z2 = (ulonglong2*)(zb + 4 * lane);
+    z2[0] = make_ulonglong2(~0ull, ~0ull);
+    z2[1] = make_ulonglong2(~0ull, ~0ull);
+    if (DBG) *(int4*)(cov + 4 * lane) = make_int4(0, 0, 0, 0);
+  }
+  uint64_t kreg[4] = {~0ull, ~0ull, ~0ull, ~0ull};
+  int creg[4] = {0, 0, 0, 0};
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+
+  for (int kb = k0; kb < k1; kb += 64) {
+    const int k = kb + lane;
+    int full = 0, area = 0, fx0 = 0, fy0 = 0, bw = 1;
+    if (k < k1) {
+      int rec = k;
+      if (binned) {
+        const int e = bins[k];
+        rec = e & 0x7FFF;
+        full = e >> 15;
+      }
+      const int4 ra = grec[3 * rec], rb = grec[3 * rec + 1], rc = grec[3 * rec + 2];
+      S.rec[lane][0] = ra;
+      S.rec[lane][1] = rb;
+      S.rec[lane][2] = rc;
+      const int32_t X[3] = {ra.x, ra.z, rb.x}, Y[3] = {ra.y, ra.w, rb.y};
+      int x0, x1, y0, y1;
+      if (tri_pixels(X, Y, Wd, Ht, &x0, &x1, &y0, &y1)) {
+        fx0 = max(x0, tx0);
+        fy0 = max(y0, ty0);
+        bw = min(x1, tx1) - fx0 + 1;
+        const int bh = min(y1, ty1) - fy0 + 1;
+        area = (bw > 0 && bh > 0) ? bw * bh : 0;
+        if (bw < 1) bw = 1;
+      }
+    }
+    const bool big = area > kSmallMax;
+    // small triangles: fragments packed over lanes.  Fragment f belongs to
+    // the lane j with off_j <= f < off_j + a_j; per window of 64 fragments
+    // each owner marks where its range starts and a max-scan spreads it.
+    const int a = big ? 0 : area;
+    const int incl = wave_incl_add(a);
+    const int F = __builtin_amdgcn_readlane(incl, 63);
+    const int off = incl - a;
+    S.meta[lane] = make_int2(fx0 | (fy0 << 16), off | (bw << 16));
+    int carry = 0;  // owner + 1 of the fragment before the window
+    for (int f0 = 0; f0 < F; f0 += 64) {
+      S.own[lane] = 0;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      if (a > 0 && off >= f0 && off < f0 + 64) S.own[off - f0] = lane + 1;
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      int o = S.own[lane];
+      if (lane == 0) o = max(o, carry);
+      o = wave_incl_max(o);
+      carry = __builtin_amdgcn_readlane(o, 63);
+      const int f = f0 + lane;
+      if (f < F) {
+        const int j = o - 1;  // >= 0 for every fragment below F
+        const int2 m = S.meta[j];
+        const int rr = f - (m.y & 0xFFFF), jbw = m.y >> 16;
+        // rr / jbw exactly: rr < 64 and jbw <= 16 keep the quotient's
+        // fraction at least 1/32 away from an integer
+        const int qy = (int)(((float)rr + 0.5f) * __builtin_amdgcn_rcpf((float)jbw));
+        const int ppx = (m.x & 0xFFFF) + (rr - qy * jbw), ppy = (m.x >> 16) + qy;
+        uint64_t kk;
+        if (frag_key(S.rec[j][0], S.rec[j][1], S.rec[j][2], ppx, ppy, &kk)) {
+          const int p = (ppy - ty0) * kTile + (ppx - tx0);
+          atomicMin((unsigned long long*)&zb[p], (unsigned long long)kk);
+          if (DBG) atomicAdd(&cov[p], 1);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    }
+    // large triangles: every lane on its four pixels, the record uniform
+    uint64_t m = __ballot(big);
+    while (m) {
+      const int j = __ffsll((unsigned long long)m) - 1;
+      m &= m - 1ull;
+      const bool jfull = __builtin_amdgcn_readlane(full, j) != 0;
+      const int4 ra = S.rec[j][0], rb = S.rec[j][1], rc = S.rec[j][2];
+      const int32_t X[3] = {ra.x, ra.z, rb.x}, Y[3] = {ra.y, ra.w, rb.y};
+      const float z0 = __int_as_float(rb.w), z1 = __int_as_float(rc.x), z2 = __int_as_float(rc.y);
+      const float invA = __int_as_float(rc.z);
+      const uint32_t key = (uint32_t)rb.z;
+      double E[3], step[3], thr[3];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        const int a0 = (e + 1) % 3, b0 = (e + 2) % 3;
+        const int32_t dx = X[b0] - X[a0], dy = Y[b0] - Y[a0];
+        E[e] = fma(-(double)dy, (double)(256 * px0 + 128 - X[a0]), (double)dx * (double)(256 * py + 128 - Y[a0]));
+        step[e] = -(double)dy * 256.0;  // one pixel right
+        thr[e] = top_left(dx, dy) ? 0.0 : 1.0;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const bool in = jfull || (E[0] >= thr[0] && E[1] >= thr[1] && E[2] >= thr[2]);
+        const float zz = (((float)E[0] * z0 + (float)E[1] * z1) + (float)E[2] * z2) * invA;
+        const uint32_t D = (uint32_t)rintf(__builtin_amdgcn_fmed3f(zz, 0.0f, 1.0f) * 16777215.0f);
+        const uint64_t kk = ((uint64_t)D << 32) | key;
+        kreg[i] = (in && kk < kreg[i]) ? kk : kreg[i];
+        if (DBG) creg[i] += in ? 1 : 0;
+#pragma unroll
+        for (int e = 0; e < 3; ++e) E[e] += step[e];
+      }
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+  // resolve: the fragment z-buffer against the registers, then the winners'
+  // colours and the stores
+  const ulonglong2 za = ((const ulonglong2*)(zb + 4 * lane))[0];
+  const ulonglong2 zc = ((const ulonglong2*)(zb + 4 * lane))[1];
+  const uint64_t zk[4] = {za.x, za.y, zc.x, zc.y};
+  uint32_t D[4], rgb[4];
+  int32_t win[4];
+  const int32_t* gw = (const int32_t*)grec;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint64_t key = zk[i] < kreg[i] ? zk[i] : kreg[i];
+    D[i] = 0xFFFFFFFFu;
+    rgb[i] = 0;
+    win[i] = -1;
+    if (key != ~0ull) {
+      const uint32_t lo = (uint32_t)key;
+      D[i] = (uint32_t)(key >> 32);
+      win[i] = (int32_t)(lo >> 16);
+      rgb[i] = (uint32_t)gw[kRecWords * (lo & 0xFFFFu) + 11];
+    }
+  }
+  if (py <= ty1) {
+    const int64_t pix = cam.pix_off + (int64_t)py * Wd + px0;
+    if (px0 + 3 <= tx1 && (pix & 3) == 0) {
+      *(uint4*)(W.depth + pix) = make_uint4(D[0], D[1], D[2], D[3]);
+      uint32_t* c = (uint32_t*)(W.rgb + 3 * pix);  // 3 pix is a multiple of 12
+      c[0] = rgb[0] | (rgb[1] << 24);
+      c[1] = (rgb[1] >> 8) | (rgb[2] << 16);
+      c[2] = (rgb[2] >> 16) | (rgb[3] << 8);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (px0 + i > tx1) continue;
+        W.depth[pix + i] = D[i];
+        W.rgb[3 * (pix + i)] = (uint8_t)(rgb[i] & 0xFF);
+        W.rgb[3 * (pix + i) + 1] = (uint8_t)((rgb[i] >> 8) & 0xFF);
+        W.rgb[3 * (pix + i) + 2] = (uint8_t)((rgb[i] >> 16) & 0xFF);
+      }
+    }
+    if (DBG) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (px0 + i > tx1) continue;
+        W.winners[pix + i] = win[i];
+        W.coverage[pix + i] = cov[4 * lane + i] + creg[i];
+      }
+    }
+  }
+}
+
+template <bool DBG>
+__global__ void __launch_bounds__(64 * kTileWaves) raster_tile_kernel(WorldDev W, RasterLaunch L) {
+  __shared__ TileWaveLDS S[kTileWaves];
+  __shared__ int32_t C[DBG ? kTileWaves : 1][DBG ? 256 : 1];
+  const int2 job = L.tiles[blockIdx.x];
+  if (job.x < 0) return;
+  const int wave = threadIdx.x >> 6;
+  const CamDev cam = W.cams[job.x];
+  const int ntx = (cam.w + kTile - 1) / kTile;
+  const int ntiles = tiles_of(cam.w, cam.h);
+  const int tile = job.y + wave;
+  if (tile >= ntiles) return;  // no workgroup barrier follows
+  raster_tile<DBG>(W, cam, ntx, ntiles, tile, S[wave], DBG ? C[wave] : nullptr);
 }
 
 }  // namespace
 
 size_t raster_lds_bytes(const RasterLaunch& l) {
-  return (size_t)make_layout(l.max_bodies, l.max_verts, l.max_tiles, l.max_tris, l.rec_cap, l.threads).total;
+  return (size_t)setup_layout(l.max_bodies, l.max_verts, l.max_tiles, l.max_tris).total;
 }
 
 hipError_t raster_configure(size_t lds_bytes) {
-  return hipFuncSetAttribute((const void*)raster_kernel,
+  return hipFuncSetAttribute((const void*)raster_setup_kernel,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
 }
 
-hipError_t launch_raster(const WorldDev& w, const RasterLaunch& l, hipStream_t s) {
+hipError_t launch_raster(const WorldDev& w, const RasterLaunch& l, hipStream_t s, phase_mark_fn mark,
+                         void* mark_ctx) {
   if (l.n_work <= 0) return hipSuccess;
   const size_t lds = raster_lds_bytes(l);
   const int grid = l.persistent > 0 ? (l.persistent < l.n_work ? l.persistent : l.n_work) : l.n_work;
@@ -884,7 +790,19 @@ hipError_t launch_raster(const WorldDev& w, const RasterLaunch& l, hipStream_t s
     hipError_t e = launch_reset_queue(l.queue, s);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(raster_kernel, dim3(grid), dim3(l.threads), lds, s, w, l);
+  hipLaunchKernelGGL(raster_setup_kernel, dim3(grid), dim3(l.threads), lds, s, w, l);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (mark) {
+    e = mark(mark_ctx, s);
+    if (e != hipSuccess) return e;
+  }
+  if (l.n_tile_groups > 0) {
+    if (w.winners)
+      hipLaunchKernelGGL(raster_tile_kernel<true>, dim3(l.n_tile_groups), dim3(64 * kTileWaves), 0, s, w, l);
+    else
+      hipLaunchKernelGGL(raster_tile_kernel<false>, dim3(l.n_tile_groups), dim3(64 * kTileWaves), 0, s, w, l);
+  }
   return hipGetLastError();
 }
 

@@ -110,7 +110,8 @@ struct vuda_server {
   double busy = 0.0;
 
   // Device bytes a request holds while resident: both state buffers and the
-  // static arrays per body, the primitive/vertex maps, and the RGB-D images.
+  // static arrays per body, the primitive/vertex maps, the RGB-D images and
+  // the raster scratch of its cameras.
   uint64_t request_bytes(const Batch& b) const {
     const int64_t nb = b.bodies();
     int64_t maps = 0;
@@ -120,7 +121,8 @@ struct vuda_server {
         maps += b.type[i] ? w->tpl.cube_nf + w->tpl.cube_nv : w->tpl.sphere_nf + w->tpl.sphere_nv;
     }
     return (uint64_t)nb * (2 * 4 * kStateComps + 26) + (uint64_t)maps + (uint64_t)b.pixels() * 7 +
-           (uint64_t)b.n_envs * sizeof(EnvDev) + b.cam_w.size() * sizeof(CamDev);
+           (uint64_t)b.n_envs * sizeof(EnvDev) + b.cam_w.size() * sizeof(CamDev) +
+           256 * (uint64_t)w->rs_units(b.view());
   }
 };
 

@@ -43,8 +43,39 @@ struct CamDev {
   int32_t w, h;
   int64_t pix_off;    // first pixel of the image in the image arena
   int32_t env;
-  int32_t pad;
+  int32_t n_tris;     // primitives of the env (sizes the raster scratch)
+  int64_t rs_off;     // byte offset of the image's raster scratch
 };
+
+// Raster scratch of one camera image, written by the setup kernel and read by
+// the tile kernel: a header (record count, binned flag), the tile table
+// (bin offset, bin count per 16x16 tile), the setup records (kRecBytes each,
+// room for every primitive of the env) and the bins (u16 record ids, bit 15
+// set when the triangle covers the whole tile).
+constexpr int kRecWords = 12;  // X0 Y0 X1 Y1 | X2 Y2 key z0 | z1 z2 invA rgb
+constexpr int kRecBytes = 4 * kRecWords;
+constexpr int kBinsPerTri = 4;  // bin capacity of an image, per primitive
+
+struct RsLayout {
+  int64_t tiles, recs, bins, total;
+  int32_t bin_cap;
+};
+
+__host__ __device__ inline int64_t rs_align(int64_t x) { return (x + 255) & ~(int64_t)255; }
+
+__host__ __device__ inline RsLayout rs_layout(int32_t ntris, int32_t ntiles) {
+  RsLayout r;
+  r.tiles = 64;
+  r.recs = rs_align(64 + 8 * (int64_t)ntiles);
+  r.bins = r.recs + rs_align((int64_t)kRecBytes * ntris);
+  r.bin_cap = kBinsPerTri * ntris;
+  r.total = r.bins + rs_align(2 * (int64_t)r.bin_cap);
+  return r;
+}
+
+__host__ __device__ inline int32_t tiles_of(int32_t w, int32_t h) {
+  return ((w + kTile - 1) / kTile) * ((h + kTile - 1) / kTile);
+}
 
 // Mesh templates and shading constants (device copy of the descriptor).
 struct alignas(16) Templates {
@@ -100,6 +131,7 @@ struct WorldDev {
   int32_t pair_cap;
   uint32_t* env_flags;
   const Templates* tpl;
+  unsigned char* rscratch;  // raster scratch of every camera (CamDev::rs_off)
 };
 
 // Host-side launchers (implemented next to the kernels).
@@ -116,22 +148,29 @@ struct PhysLaunch {
 };
 
 struct RasterLaunch {
-  const int32_t* work;     // camera ids, LPT order
+  const int32_t* work;     // camera ids, LPT order (setup kernel, one workgroup each)
   int32_t n_work;
+  const int2* tiles;       // tile kernel: per workgroup (camera, first of its 4 tiles);
+                           // camera -1 for padding entries
+  int32_t n_tile_groups;
   int32_t max_verts;       // over the listed cameras' envs
   int32_t max_tiles;
   int32_t max_bodies;
   int32_t max_tris;
   int32_t parity;          // state buffer rendered
-  int32_t threads;         // workgroup size (multiple of 64)
-  int32_t rec_cap;         // triangle setup records held in LDS
-  int32_t persistent;
+  int32_t threads;         // setup workgroup size (multiple of 64)
+  int32_t bin_limit;       // bin entries an image may use (0: its whole capacity)
+  int32_t persistent;      // setup kernel: resident workgroups pulling images
   int32_t* queue;
 };
 
+// Timing hook: called between the kernels of a phase (nullable).
+typedef hipError_t (*phase_mark_fn)(void* ctx, hipStream_t s);
+
 hipError_t launch_physics(const WorldDev& w, const PhysConsts& pc, const PhysLaunch& l,
                           hipStream_t s);
-hipError_t launch_raster(const WorldDev& w, const RasterLaunch& l, hipStream_t s);
+hipError_t launch_raster(const WorldDev& w, const RasterLaunch& l, hipStream_t s, phase_mark_fn mark,
+                         void* mark_ctx);
 size_t raster_lds_bytes(const RasterLaunch& l);
 hipError_t raster_configure(size_t lds_bytes);
 hipError_t launch_reset_queue(int32_t* q, hipStream_t s);

@@ -49,6 +49,9 @@ class RangeAlloc {
 struct WorkList {
   int32_t* dptr = nullptr;
   int32_t cap = 0;     // entries dptr holds
+  int2* tptr = nullptr;  // render: tile-kernel jobs (camera, first tile)
+  int32_t tcap = 0;
+  int32_t n_groups = 0;
   bool dirty = true;   // rebuild before the next use
   int32_t n = 0;
   int32_t max_bodies = 0;
@@ -59,7 +62,7 @@ struct WorkList {
 
 struct Tuning {
   int32_t raster_threads = 256;
-  int32_t rec_cap = 0;  // 0: automatic
+  int32_t rec_cap = 0;  // bin entries an image may use (0: its whole capacity)
   int32_t phys_persistent = 0;
   int32_t raster_persistent = 0;
   bool graphs = false;
@@ -89,7 +92,7 @@ struct vuda_world {
   bool has_allocator = false;
   struct {
     size_t envs, cams, type, albedo, size, rbound, inv_m, inv_I, prim_base, vert_base, prim_body, vert_body, state0,
-        state1, rgb, depth, flags, tpl, queues, winners, coverage, contacts;
+        state1, rgb, depth, flags, tpl, queues, winners, coverage, contacts, rs;
   } off_{};
   vuda::WorldDev dev{};
   int32_t* queues = nullptr;
@@ -100,7 +103,8 @@ struct vuda_world {
   std::vector<uint8_t> env_active;
   std::vector<vuda::CamDev> cam_host;
   vuda::RangeAlloc slots, bodies, camslots, pixels, primspace, vertspace;
-  int64_t cap_prims = 0, cap_verts = 0;
+  vuda::RangeAlloc rsspace;  // raster scratch, in 256-byte units
+  int64_t cap_prims = 0, cap_verts = 0, cap_rs = 0;
 
   // streams: mode 0 serialized (s_sim == s_render == s_serial), 1 CU-masked,
   // 2 two unmasked streams
@@ -114,8 +118,9 @@ struct vuda_world {
   std::vector<hipEvent_t> evpool;
   int64_t next_event = 0;
 
-  // launch timing: start/stop event pairs per phase (index 0 step, 1 render),
-  // tev_used[k] pairs recorded since the last read
+  // launch timing: per phase (index 0 step, 1 render) and launch, events at
+  // the start, between the phase's kernels and at the end; tev_used[k]
+  // launches recorded since the last read
   std::vector<hipEvent_t> tev[2];
   size_t tev_used[2] = {0, 0};
 
@@ -126,8 +131,10 @@ struct vuda_world {
 
   int alloc_arena(const vuda_allocator* a);
   int upload(const vuda_env_batch& b, int32_t e0, int64_t b0, int32_t c0, int64_t p0, int64_t m0,
-             int64_t v0, int parity, hipStream_t s);
+             int64_t v0, int64_t r0, int parity, hipStream_t s);
   void map_sizes(const vuda_env_batch& b, int64_t* prims, int64_t* verts) const;
+  int64_t rs_units(const vuda_env_batch& b) const;
+  int32_t env_tris(const vuda_env_batch& b, int32_t e) const;
   void free_all();
   int make_streams(float split);
   void destroy_streams();
@@ -140,9 +147,10 @@ struct vuda_world {
   int check_range(int32_t lo, int32_t hi);
   int enqueue_physics(const vuda::WorkList& L, int parity, hipStream_t s);
   int raster_launch_of(const vuda::WorkList& L, int parity, vuda::RasterLaunch* out);
-  int enqueue_raster(const vuda::WorkList& L, int parity, hipStream_t s);
+  int enqueue_raster(const vuda::WorkList& L, int parity, hipStream_t s, hipEvent_t mid);
   int run_phase(int phase, const vuda::WorkList& L, int parity, int32_t lo, int32_t hi, hipStream_t s);
-  int launch_phase(int phase, const vuda::WorkList& L, int parity, int32_t lo, int32_t hi, hipStream_t s);
+  int launch_phase(int phase, const vuda::WorkList& L, int parity, int32_t lo, int32_t hi, hipStream_t s,
+                   hipEvent_t mid);
   hipStream_t capture_stream();
   int check_flags();
   int32_t active_midpoint();

@@ -237,6 +237,7 @@ int vuda_world::alloc_arena(const vuda_allocator* a) {
   off_.flags = take(4 * E + 4);
   off_.tpl = take(sizeof(Templates));
   off_.queues = take(64);
+  off_.rs = take(256 * (size_t)std::max<int64_t>(cap_rs, 1));
   if (debug) {
     off_.winners = take(4 * P);
     off_.coverage = take(4 * P);
@@ -280,6 +281,7 @@ int vuda_world::alloc_arena(const vuda_allocator* a) {
   dev.depth = (uint32_t*)(arena + off_.depth);
   dev.env_flags = (uint32_t*)(arena + off_.flags);
   dev.tpl = (const Templates*)(arena + off_.tpl);
+  dev.rscratch = arena + off_.rs;
   queues = (int32_t*)(arena + off_.queues);
   dev.winners = debug ? (int32_t*)(arena + off_.winners) : nullptr;
   dev.coverage = debug ? (int32_t*)(arena + off_.coverage) : nullptr;
@@ -309,8 +311,25 @@ void vuda_world::map_sizes(const vuda_env_batch& b, int64_t* prims, int64_t* ver
   *verts = nv;
 }
 
+int32_t vuda_world::env_tris(const vuda_env_batch& b, int32_t e) const {
+  int32_t n = tpl.ground_nf;
+  for (int32_t i = b.body_off[e]; i < b.body_off[e + 1]; ++i) n += b.type[i] ? tpl.cube_nf : tpl.sphere_nf;
+  return n;
+}
+
+// Raster scratch of a batch's cameras, in 256-byte units.
+int64_t vuda_world::rs_units(const vuda_env_batch& b) const {
+  int64_t u = 0;
+  for (int32_t e = 0; e < b.n_envs; ++e) {
+    const int32_t nt = env_tris(b, e);
+    for (int32_t c = b.cam_off[e]; c < b.cam_off[e + 1]; ++c)
+      u += rs_layout(nt, tiles_of(b.cam_w[c], b.cam_h[c])).total / 256;
+  }
+  return u;
+}
+
 int vuda_world::upload(const vuda_env_batch& b, int32_t e0, int64_t b0, int32_t c0, int64_t p0,
-                       int64_t m0, int64_t v0, int parity, hipStream_t s) {
+                       int64_t m0, int64_t v0, int64_t r0, int parity, hipStream_t s) {
   const int64_t nb = b.n_envs ? b.body_off[b.n_envs] : 0;
   const int32_t nc = b.n_envs ? b.cam_off[b.n_envs] : 0;
   std::vector<EnvDev> envs(b.n_envs);
@@ -343,8 +362,9 @@ int vuda_world::upload(const vuda_env_batch& b, int32_t e0, int64_t b0, int32_t 
     vmap.resize(map_round((int64_t)vmap.size()), kGroundBody);
   }
   std::vector<CamDev> cams(nc);
-  int64_t po = p0;
-  for (int e = 0; e < b.n_envs; ++e)
+  int64_t po = p0, ro = 256 * r0;
+  for (int e = 0; e < b.n_envs; ++e) {
+    const int32_t nt = envs[e].n_tris;
     for (int32_t c = b.cam_off[e]; c < b.cam_off[e + 1]; ++c) {
       CamDev& d = cams[c];
       memcpy(d.vp, b.cam_vp + 16 * (size_t)c, sizeof(d.vp));
@@ -352,9 +372,12 @@ int vuda_world::upload(const vuda_env_batch& b, int32_t e0, int64_t b0, int32_t 
       d.h = b.cam_h[c];
       d.pix_off = po;
       d.env = e0 + e;
-      d.pad = 0;
+      d.n_tris = nt;
+      d.rs_off = ro;
       po += (int64_t)d.w * d.h;
+      ro += rs_layout(nt, tiles_of(d.w, d.h)).total;
     }
+  }
   std::vector<float> st((size_t)kStateComps * nb);
   for (int64_t i = 0; i < nb; ++i) {
     for (int k = 0; k < 3; ++k) {
@@ -430,6 +453,17 @@ extern "C" int vuda_create_world(const vuda_world_desc* d, const vuda_allocator*
     const int64_t spare_b = w->cap_bodies - nb, spare_e = (int64_t)w->cap_envs - d->initial.n_envs;
     w->cap_prims = init_prims + spare_b * mf + spare_e * (w->tpl.ground_nf + 15);
     w->cap_verts = init_verts + spare_b * mv + spare_e * (w->tpl.ground_nv + 15);
+    // raster scratch of cameras admitted later.  Per camera it is at most
+    // (kRecBytes + 2 kBinsPerTri) n_tris + 8 tiles + 829 bytes, and a camera
+    // of W x H pixels has at most W H / 256 + 513 tiles; envs are assumed to
+    // carry no more cameras each than the initial batch's most (at least 1).
+    int32_t kcam = 1;
+    for (int32_t e = 0; e < d->initial.n_envs; ++e)
+      kcam = std::max(kcam, d->initial.cam_off[e + 1] - d->initial.cam_off[e]);
+    const int64_t spare_c = (int64_t)w->cap_cams - nc, spare_p = w->cap_pixels - npix;
+    const int64_t spare_bytes = (int64_t)(kRecBytes + 2 * kBinsPerTri) * kcam * (w->cap_prims - init_prims) +
+                                spare_p / 32 + (829 + 8 * 513) * spare_c;
+    w->cap_rs = w->rs_units(d->initial) + (spare_bytes + 255) / 256;
   }
   w->pc.h = d->phys.dt / (float)d->phys.substeps;
   w->pc.hh = 0.5f * w->pc.h;
@@ -456,6 +490,7 @@ extern "C" int vuda_create_world(const vuda_world_desc* d, const vuda_allocator*
   w->pixels.init(w->cap_pixels);
   w->primspace.init(w->cap_prims);
   w->vertspace.init(w->cap_verts);
+  w->rsspace.init(w->cap_rs);
   rc = w->make_streams(0.0f);
   if (rc == VUDA_OK) {
     hipError_t e = hipMemcpy((void*)w->dev.tpl, &w->tpl, sizeof(Templates), hipMemcpyHostToDevice);
@@ -468,7 +503,8 @@ extern "C" int vuda_create_world(const vuda_world_desc* d, const vuda_allocator*
     w->pixels.take(0, npix);
     w->primspace.take(0, init_prims);
     w->vertspace.take(0, init_verts);
-    rc = w->upload(d->initial, 0, 0, 0, 0, 0, 0, 0, w->s_serial);
+    w->rsspace.take(0, w->rs_units(d->initial));
+    rc = w->upload(d->initial, 0, 0, 0, 0, 0, 0, 0, 0, w->s_serial);
     w->n_envs_hi = d->initial.n_envs;
   }
   if (rc) {
@@ -485,6 +521,7 @@ void vuda_world::free_all() {
   (void)hipDeviceSynchronize();
   for (auto& kv : lists) {
     if (kv.second.dptr) (void)hipFree(kv.second.dptr);
+    if (kv.second.tptr) (void)hipFree(kv.second.tptr);
   }
   lists.clear();
   for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
@@ -678,6 +715,35 @@ int vuda_world::get_list(int phase, int32_t lo, int32_t hi, const WorkList** out
   }
   if (!ids.empty()) HIPCHK(hipMemcpy(L.dptr, ids.data(), 4 * ids.size(), hipMemcpyHostToDevice));
   L.n = (int32_t)ids.size();
+  L.n_groups = 0;
+  if (phase == VUDA_PHASE_RENDER && !ids.empty()) {
+    // Tile-kernel jobs of 4 tiles.  Workgroups are handed to the 8 XCDs
+    // round-robin, so the setup workgroup of image i runs on XCD i mod 8;
+    // its tiles get job indices of the same residue, where that XCD's L2
+    // still holds the image's records and bins.
+    constexpr int kXcd = 8;
+    std::vector<std::vector<int2>> per(kXcd);
+    for (size_t i = 0; i < ids.size(); ++i) {
+      const CamDev& cd = cam_host[ids[i]];
+      const int32_t nt = tiles_of(cd.w, cd.h);
+      for (int32_t t = 0; t < nt; t += 4) per[i % kXcd].push_back(make_int2(ids[i], t));
+    }
+    size_t len = 0;
+    for (auto& v : per) len = std::max(len, v.size());
+    std::vector<int2> jobs(kXcd * len, make_int2(-1, 0));
+    for (int x = 0; x < kXcd; ++x)
+      for (size_t q = 0; q < per[x].size(); ++q) jobs[kXcd * q + x] = per[x][q];
+    if ((int64_t)jobs.size() > L.tcap) {
+      if (L.tptr) HIPCHK(hipFree(L.tptr));
+      L.tptr = nullptr;
+      L.tcap = 0;
+      const int32_t want = std::max<int32_t>((int32_t)jobs.size(), 64);
+      HIPCHK(hipMalloc(&L.tptr, sizeof(int2) * (size_t)want));
+      L.tcap = want;
+    }
+    HIPCHK(hipMemcpy(L.tptr, jobs.data(), sizeof(int2) * jobs.size(), hipMemcpyHostToDevice));
+    L.n_groups = (int32_t)jobs.size();
+  }
   L.dirty = false;
   return VUDA_OK;
 }
@@ -722,28 +788,21 @@ int vuda_world::raster_launch_of(const WorkList& L, int parity, RasterLaunch* ou
   RasterLaunch rl;
   rl.work = L.dptr;
   rl.n_work = L.n;
+  rl.tiles = L.tptr;
+  rl.n_tile_groups = L.n_groups;
   rl.max_verts = std::max(L.max_verts, 1);
   rl.max_tiles = std::max(L.max_tiles, 1);
   rl.max_bodies = L.max_bodies;
   rl.max_tris = std::max(L.max_tris, 1);
   rl.parity = parity;
   rl.threads = tune.raster_threads;
-  // setup records: by default room for 55% of the primitives (front faces of
-  // closed meshes are about half); images with more take the slower path.
-  const int min_rec = L.max_tris / 12 + 1;  // the slower path's bins live in the same space
-  int rec = tune.rec_cap > 0 ? tune.rec_cap : (L.max_tris * 55 + 99) / 100;
-  rec = std::min(std::max(std::max(rec, min_rec), 64), 32767);  // 15-bit record ids in the bins
-  rl.rec_cap = rec;
+  rl.bin_limit = tune.rec_cap;
   rl.persistent = tune.raster_persistent;
   rl.queue = queues + 1;
-  size_t lds = raster_lds_bytes(rl);
+  const size_t lds = raster_lds_bytes(rl);
   const size_t kLdsMax = 160 * 1024;
-  while (lds > kLdsMax && rl.rec_cap > min_rec) {
-    rl.rec_cap = std::max(min_rec, rl.rec_cap * 3 / 4);
-    lds = raster_lds_bytes(rl);
-  }
   if (lds > kLdsMax)
-    return fail(VUDA_EOVERFLOW, "raster needs %zu bytes of LDS (max %zu)", lds, kLdsMax);
+    return fail(VUDA_EOVERFLOW, "raster setup needs %zu bytes of LDS (max %zu)", lds, kLdsMax);
   if (lds > lds_configured) {
     HIPCHK(raster_configure(lds));
     lds_configured = lds;
@@ -752,39 +811,44 @@ int vuda_world::raster_launch_of(const WorkList& L, int parity, RasterLaunch* ou
   return VUDA_OK;
 }
 
-int vuda_world::enqueue_raster(const WorkList& L, int parity, hipStream_t s) {
+static hipError_t record_mark(void* ev, hipStream_t s) { return hipEventRecord((hipEvent_t)ev, s); }
+
+int vuda_world::enqueue_raster(const WorkList& L, int parity, hipStream_t s, hipEvent_t mid) {
   RasterLaunch rl;
   int rc = raster_launch_of(L, parity, &rl);
   if (rc) return rc;
-  HIPCHK(launch_raster(dev, rl, s));
+  HIPCHK(launch_raster(dev, rl, s, mid ? record_mark : nullptr, (void*)mid));
   return VUDA_OK;
 }
 
 // Launch one phase, through a captured graph when graph mode is on, between
-// a pair of timing events when timing is on.
+// timing events when timing is on.
 int vuda_world::run_phase(int phase, const WorkList& L, int parity, int32_t lo, int32_t hi,
                           hipStream_t s) {
-  if (!tune.timing) return launch_phase(phase, L, parity, lo, hi, s);
+  if (!tune.timing) return launch_phase(phase, L, parity, lo, hi, s, nullptr);
   const int k = phase == VUDA_PHASE_STEP ? 0 : 1;
   std::vector<hipEvent_t>& ev = tev[k];
-  const size_t i = 2 * tev_used[k];
-  while (ev.size() < i + 2) {
+  const size_t i = 3 * tev_used[k];
+  while (ev.size() < i + 3) {
     hipEvent_t e;
     HIPCHK(hipEventCreate(&e));
     ev.push_back(e);
   }
+  // the mark between a render's two kernels; otherwise it coincides with the end
+  const bool mid = phase == VUDA_PHASE_RENDER && !tune.graphs;
   HIPCHK(hipEventRecord(ev[i], s));
-  int rc = launch_phase(phase, L, parity, lo, hi, s);
+  int rc = launch_phase(phase, L, parity, lo, hi, s, mid ? ev[i + 1] : nullptr);
   if (rc) return rc;
-  HIPCHK(hipEventRecord(ev[i + 1], s));
+  if (!mid) HIPCHK(hipEventRecord(ev[i + 1], s));
+  HIPCHK(hipEventRecord(ev[i + 2], s));
   ++tev_used[k];
   return VUDA_OK;
 }
 
 int vuda_world::launch_phase(int phase, const WorkList& L, int parity, int32_t lo, int32_t hi,
-                             hipStream_t s) {
+                             hipStream_t s, hipEvent_t mid) {
   if (!tune.graphs) {
-    return phase == VUDA_PHASE_STEP ? enqueue_physics(L, parity, s) : enqueue_raster(L, parity, s);
+    return phase == VUDA_PHASE_STEP ? enqueue_physics(L, parity, s) : enqueue_raster(L, parity, s, mid);
   }
   const auto key = std::make_tuple(phase, lo, hi, parity);
   auto it = graphs.find(key);
@@ -792,7 +856,7 @@ int vuda_world::launch_phase(int phase, const WorkList& L, int parity, int32_t l
     hipStream_t cs = capture_stream();
     if (!cs) return fail(VUDA_EHIP, "capture stream");
     HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    int rc = phase == VUDA_PHASE_STEP ? enqueue_physics(L, parity, cs) : enqueue_raster(L, parity, cs);
+    int rc = phase == VUDA_PHASE_STEP ? enqueue_physics(L, parity, cs) : enqueue_raster(L, parity, cs, nullptr);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(cs, &g);
     if (rc) {
@@ -1119,16 +1183,19 @@ extern "C" int vuda_admit(vuda_world* w, const vuda_env_batch* b, int32_t parity
   const int64_t p0 = c0 < 0 ? -1 : w->pixels.alloc(npix);
   const int64_t m0 = p0 < 0 ? -1 : w->primspace.alloc(nprim);
   const int64_t v0 = m0 < 0 ? -1 : w->vertspace.alloc(nvert);
-  if (v0 < 0) {
+  const int64_t nrs = w->rs_units(*b);
+  const int64_t r0 = v0 < 0 ? -1 : w->rsspace.alloc(nrs);
+  if (r0 < 0) {
     w->slots.release(e0, b->n_envs);
     if (b0 >= 0) w->bodies.release(b0, nb);
     if (c0 >= 0) w->camslots.release(c0, nc);
     if (p0 >= 0) w->pixels.release(p0, npix);
     if (m0 >= 0) w->primspace.release(m0, nprim);
+    if (v0 >= 0) w->vertspace.release(v0, nvert);
     return fail(VUDA_EBUSY, "no room for %lld bodies / %d cameras / %lld pixels", (long long)nb, nc,
                 (long long)npix);
   }
-  rc = w->upload(*b, (int32_t)e0, b0, (int32_t)c0, p0, m0, v0, parity, w->s_serial);
+  rc = w->upload(*b, (int32_t)e0, b0, (int32_t)c0, p0, m0, v0, r0, parity, w->s_serial);
   if (rc) {
     w->slots.release(e0, b->n_envs);
     w->bodies.release(b0, nb);
@@ -1136,6 +1203,7 @@ extern "C" int vuda_admit(vuda_world* w, const vuda_env_batch* b, int32_t parity
     w->pixels.release(p0, npix);
     w->primspace.release(m0, nprim);
     w->vertspace.release(v0, nvert);
+    w->rsspace.release(r0, nrs);
     return rc;
   }
   for (int e = 0; e < b->n_envs; ++e) {
@@ -1160,18 +1228,21 @@ extern "C" int vuda_release(vuda_world* w, int32_t first, int32_t n) {
   const EnvDev& d1 = w->env_host[first + n - 1];
   const int64_t nb = (int64_t)d1.body_off + d1.n_bodies - d0.body_off;
   const int32_t nc = d1.cam_off + d1.n_cams - d0.cam_off;
-  int64_t p0 = 0, np = 0;
+  int64_t p0 = 0, np = 0, r0 = 0, nr = 0;
   if (nc > 0) {
     const CamDev& c0 = w->cam_host[d0.cam_off];
     const CamDev& c1 = w->cam_host[d0.cam_off + nc - 1];
     p0 = c0.pix_off;
     np = c1.pix_off + (int64_t)c1.w * c1.h - p0;
+    r0 = c0.rs_off / 256;
+    nr = (c1.rs_off + rs_layout(c1.n_tris, tiles_of(c1.w, c1.h)).total) / 256 - r0;
   }
   std::vector<EnvDev> empty(n, EnvDev{});
   HIPCHK(hipMemcpy(w->dev.envs + first, empty.data(), sizeof(EnvDev) * n, hipMemcpyHostToDevice));
   w->bodies.release(d0.body_off, nb);
   w->camslots.release(d0.cam_off, nc);
   w->pixels.release(p0, np);
+  w->rsspace.release(r0, nr);
   // each env's maps were allocated rounded up to 16 bytes
   w->primspace.release(d0.prim_map, d1.prim_map + map_round(d1.n_tris) - d0.prim_map);
   w->vertspace.release(d0.vert_map, d1.vert_map + map_round(d1.n_verts) - d0.vert_map);
@@ -1196,7 +1267,7 @@ extern "C" int vuda_set_tuning(vuda_world* w, int32_t key, int32_t value) {
       w->tune.raster_threads = value;
       break;
     case VUDA_TUNE_REC_CAP:
-      if (value < 0 || value > 32767) return fail(VUDA_EINVAL, "rec_cap %d", value);
+      if (value < 0) return fail(VUDA_EINVAL, "bin limit %d", value);
       w->tune.rec_cap = value;
       break;
     case VUDA_TUNE_PHYS_PERSISTENT:
@@ -1246,24 +1317,27 @@ extern "C" int vuda_get_tuning(vuda_world* w, int32_t key, int32_t* value) {
   return VUDA_OK;
 }
 
-extern "C" int vuda_phase_times(vuda_world* w, int32_t phase, int64_t* launches, double* total_ms,
-                                double* max_ms) {
+extern "C" int vuda_phase_times(vuda_world* w, int32_t phase, int32_t part, int64_t* launches,
+                                double* total_ms, double* max_ms) {
   if (!w) return fail(VUDA_EINVAL, "null world");
   if (phase != VUDA_PHASE_STEP && phase != VUDA_PHASE_RENDER) return fail(VUDA_EINVAL, "phase %d", phase);
+  if (part < 0 || part > 2 || (phase == VUDA_PHASE_STEP && part == 2))
+    return fail(VUDA_EINVAL, "part %d of phase %d", part, phase);
   const int k = phase == VUDA_PHASE_STEP ? 0 : 1;
   const size_t n = w->tev_used[k];
+  const int a = part == 2 ? 1 : 0, b = part == 1 ? 1 : 2;
   double sum = 0.0, mx = 0.0;
   if (n) {
     HIPCHK(hipSetDevice(w->device));
-    HIPCHK(hipEventSynchronize(w->tev[k][2 * n - 1]));
+    HIPCHK(hipEventSynchronize(w->tev[k][3 * n - 1]));
     for (size_t i = 0; i < n; ++i) {
       float ms = 0.0f;
-      HIPCHK(hipEventElapsedTime(&ms, w->tev[k][2 * i], w->tev[k][2 * i + 1]));
+      HIPCHK(hipEventElapsedTime(&ms, w->tev[k][3 * i + a], w->tev[k][3 * i + b]));
       sum += ms;
       mx = ms > mx ? ms : mx;
     }
   }
-  w->tev_used[k] = 0;
+  if (part == 0) w->tev_used[k] = 0;
   if (launches) *launches = (int64_t)n;
   if (total_ms) *total_ms = sum;
   if (max_ms) *max_ms = mx;

@@ -284,10 +284,16 @@ class World:
 
     def phase_times(self, phase: int) -> Dict:
         """Launch count, total and max duration (ms) recorded with TUNE_TIMING
-        on since the previous call for this phase."""
-        n, tot, mx = C.c_int64(), C.c_double(), C.c_double()
-        check(lib().vuda_phase_times(self._w, phase, C.byref(n), C.byref(tot), C.byref(mx)))
-        return {"launches": n.value, "total_ms": tot.value, "max_ms": mx.value}
+        on since the previous call for this phase: the whole launch, and per
+        kernel ("parts": first kernel, raster tile kernel)."""
+        out = {}
+        parts = (0, 1, 2) if phase == PHASE_RENDER else (0, 1)
+        # part 0 last: its read starts a new count
+        for part in reversed(parts):
+            n, tot, mx = C.c_int64(), C.c_double(), C.c_double()
+            check(lib().vuda_phase_times(self._w, phase, part, C.byref(n), C.byref(tot), C.byref(mx)))
+            out[part] = {"launches": n.value, "total_ms": tot.value, "max_ms": mx.value}
+        return {**out[0], "parts": [out[p] for p in parts[1:]]}
 
     def stream(self, phase: int) -> int:
         p = C.c_void_p()

@@ -93,6 +93,18 @@ def test_edge_cases():
     run_parity(full, 4, render_every=2, label="edge")
 
 
+def test_unbinned_images_parity():
+    """Images whose tile bins exceed the allowed entries are rendered with
+    every tile testing every visible triangle; same bits as the oracle."""
+    s = sg.config_scene(4, n_envs=12)
+    with vuda.World(s, debug=True) as w:
+        w.set_tuning(vuda.TUNE_REC_CAP, 1)
+        compare_render(w, s)
+        for _ in range(3):
+            w.step()
+        compare_render(w, s)
+
+
 def test_bit_exact_and_deterministic():
     """Two runs give identical bits; GPU equals oracle bit for bit on c1."""
     s = sg.config_scene(1)

@@ -213,8 +213,11 @@ def test_launch_timing_counts_and_leaves_results_unchanged():
         ts, tr = w.phase_times(vuda.PHASE_STEP), w.phase_times(vuda.PHASE_RENDER)
         say(f"timing: step {ts}, render {tr}")
         assert ts["launches"] == 6 and tr["launches"] == 6
-        for t in (ts, tr):
+        for t in (ts, tr, *tr["parts"]):
             assert 0 < t["max_ms"] <= t["total_ms"] < 1e4
+        setup, tiles = tr["parts"]
+        assert setup["launches"] == tiles["launches"] == 6
+        assert setup["total_ms"] + tiles["total_ms"] <= tr["total_ms"] * 1.0001
         assert w.phase_times(vuda.PHASE_STEP)["launches"] == 0  # read resets the count
         w.set_tuning(vuda.TUNE_TIMING, 0)
         assert_same(ref, outputs(w))

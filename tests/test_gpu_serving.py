@@ -79,7 +79,12 @@ def test_admission_waits_for_budget():
     with server(hbm_budget=1, keep_results=False) as tiny:
         with pytest.raises(vuda.VudaError):
             tiny.submit(1, scenes[1], specs[1].horizon)  # can never fit
-    budget = 9 * (20 * 130 + 128 * 128 * 7) + 9 * 4000
+    with server(keep_results=False) as one:
+        one.submit(10, scenes[1], specs[1].horizon)
+        one.tick()
+        need = one.stats()["reserved_bytes"]  # what one such request holds
+    assert need > 9 * 128 * 128 * 7
+    budget = need + need // 2
     with server(hbm_budget=budget, keep_results=False) as srv:
         for k in range(3):
             srv.submit(10 + k, scenes[1], specs[1].horizon)

@@ -213,9 +213,24 @@ __device__ __forceinline__ void add_point(PairAcc& acc, const Point& pt, bool a_
   acc.npts += 1;
 }
 
-__device__ __forceinline__ f3 corner(f3 p, const M3& R, float a, int k) {
-  const f3 w = mk((k & 1) ? a : -a, (k & 2) ? a : -a, (k & 4) ? a : -a);
-  return add(p, rot(R, w));
+// Corner k of a cube (sign + on axis t iff bit t of k is set): p + R (+-a,
+// +-a, +-a), from the products R[k] * a computed once per cube.  The product
+// with -a is the negated product with a, so each corner is bit-identical to
+// evaluating R w with w = (+-a, +-a, +-a) row by row.
+struct CubeProducts {
+  float m[9];
+};
+__device__ __forceinline__ CubeProducts cube_products(const M3& R, float a) {
+  CubeProducts c;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) c.m[k] = R.m[k] * a;
+  return c;
+}
+__device__ __forceinline__ f3 corner_of(f3 p, const CubeProducts& c, int k) {
+  const float sx = (k & 1) ? 1.0f : -1.0f, sy = (k & 2) ? 1.0f : -1.0f, sz = (k & 4) ? 1.0f : -1.0f;
+  const f3 r = mk((sx * c.m[0] + sy * c.m[1]) + sz * c.m[2], (sx * c.m[3] + sy * c.m[4]) + sz * c.m[5],
+                  (sx * c.m[6] + sy * c.m[7]) + sz * c.m[8]);
+  return add(p, r);
 }
 
 // argmin over axes of (a - |u_axis|), lowest axis on ties
@@ -302,9 +317,10 @@ __device__ __noinline__ PairAcc pair_forces(const PhysLDS<NW>& s, int i, int j,
       const M3& Ra = side ? Rj : Ri;
       const M3& Rb = side ? Ri : Rj;
       const float aa = side ? sj : si, ab = side ? si : sj;
-#pragma unroll 1
+      const CubeProducts ca = cube_products(Ra, aa);
+#pragma unroll
       for (int k = 0; k < 8; ++k) {
-        const f3 vtx = corner(pa, Ra, aa, k);
+        const f3 vtx = corner_of(pa, ca, k);
         const f3 u = rotT(Rb, sub(vtx, pb));
         if (fabsf(u.x) < ab && fabsf(u.y) < ab && fabsf(u.z) < ab) {
           float dm;
@@ -338,9 +354,10 @@ __device__ __forceinline__ PairAcc ground_forces(int type, float a, f3 p, f3 v, 
       add_point(acc, pt, true, p, v, w, z3, z3, z3, true, pc);
     }
   } else {
-#pragma unroll 1
+    const CubeProducts c = cube_products(R, a);
+#pragma unroll
     for (int k = 0; k < 8; ++k) {
-      const f3 vtx = corner(p, R, a, k);
+      const f3 vtx = corner_of(p, c, k);
       if (vtx.z < 0.0f) {
         pt.delta = -vtx.z;
         pt.xc = vtx;
@@ -446,18 +463,30 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
     __syncthreads();
     const bool grid = use_grid && s.flag == 0;
     if (!grid && NW == 1) {
-      // one wave: body j's position is broadcast from lane j's registers
-      uint64_t row = 0ull;
-      for (int j = 0; j < n; ++j) {
-        const float bx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.x), j));
-        const float by = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.y), j));
-        const float bz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.z), j));
-        const float br = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rbv), j));
-        const f3 d = mk(p.x - bx, p.y - by, p.z - bz);
-        const float rs = rbv + br;
-        if (j > tid && dot(d, d) <= rs * rs) row |= 1ull << j;
+      // one wave: lane l tests body i against body (i + r) mod n for its
+      // share of the rotations r = 1 .. n/2 (two groups of 32 lanes when
+      // n <= 32).  Every unordered pair is one rotation away from one of its
+      // bodies; at r = n/2 (n even) both see it and the lower one keeps it.
+      // The test is symmetric in the two bodies, bit for bit.
+      const int groups = n <= 32 ? 2 : 1;
+      const int i = n <= 32 ? (tid & 31) : tid;
+      const int g = n <= 32 ? (tid >> 5) : 0;
+      const int R = n / 2;
+      if (i < n) {
+        const float4 me = s.pr[i];
+        for (int r = 1 + g; r <= R; r += groups) {
+          int j = i + r;
+          if (j >= n) j -= n;
+          if (2 * r == n && i > j) continue;
+          const float4 o = s.pr[j];
+          const f3 d = mk(me.x - o.x, me.y - o.y, me.z - o.z);
+          const float rs = me.w + o.w;
+          if (dot(d, d) <= rs * rs) {
+            const int lo = i < j ? i : j, hi = i < j ? j : i;
+            atomicOr((unsigned long long*)&s.rowCand[lo][0], 1ull << hi);
+          }
+        }
       }
-      if (own) s.rowCand[tid][0] = row;
     } else if (!grid) {
       if (own) {
         uint64_t row[NW];

@@ -761,7 +761,8 @@ __global__ void __launch_bounds__(64 * kTileWaves) raster_tile_kernel(WorldDev W
   __shared__ int32_t C[DBG ? kTileWaves : 1][DBG ? 256 : 1];
   const int2 job = L.tiles[blockIdx.x];
   if (job.x < 0) return;
-  const int wave = threadIdx.x >> 6;
+  // uniform per wave: tile bookkeeping stays in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const CamDev cam = W.cams[job.x];
   const int ntx = (cam.w + kTile - 1) / kTile;
   const int ntiles = tiles_of(cam.w, cam.h);

@@ -63,19 +63,25 @@ def timed(torch, w, schedule, n_envs, steps, warmup, st0=None, after_warmup=None
 
 
 def launch_stats(vuda, w):
-    """Average launch duration (s) and launch count per phase since the last
+    """Average launch duration (s) and launch count per kernel since the last
     read, from the HIP events the library records around each launch on the
     stream the kernel runs on."""
     out = {}
-    for name, ph in (("physics", vuda.PHASE_STEP), ("raster", vuda.PHASE_RENDER)):
-        t = w.phase_times(ph)
+    for name, k in (("physics", vuda.KERNEL_PHYSICS), ("raster_setup", vuda.KERNEL_RASTER_SETUP),
+                    ("raster_tiles", vuda.KERNEL_RASTER_TILES)):
+        t = w.kernel_times(k)
         n = max(1, t["launches"])
-        out[name] = {"launches": t["launches"], "avg_s": t["total_ms"] * 1e-3 / n,
-                     "max_s": t["max_ms"] * 1e-3}
-        if ph == vuda.PHASE_RENDER:
-            out["raster_setup"] = {"launches": t["launches"], "avg_s": t["parts"][0]["total_ms"] * 1e-3 / n}
-            out["raster_tiles"] = {"launches": t["launches"], "avg_s": t["parts"][1]["total_ms"] * 1e-3 / n}
+        out[name] = {"launches": t["launches"], "avg_s": t["total_ms"] * 1e-3 / n, "max_s": t["max_ms"] * 1e-3}
     return out
+
+
+def phase_seconds(st, steps, presetup):
+    """Per-step GPU time of the step phase and of the render phase: the
+    raster setup belongs to the step with presetup, to the render without."""
+    per = {k: v["avg_s"] * v["launches"] / steps for k, v in st.items()}
+    if presetup:
+        return per["physics"] + per["raster_setup"], per["raster_tiles"]
+    return per["physics"], per["raster_setup"] + per["raster_tiles"]
 
 
 def source_hash(kernel):
@@ -191,7 +197,8 @@ def main():
     knob_ids = {"raster_threads": vuda.TUNE_RASTER_THREADS, "rec_cap": vuda.TUNE_REC_CAP,
                 "phys_persistent": vuda.TUNE_PHYS_PERSISTENT,
                 "raster_persistent": vuda.TUNE_RASTER_PERSISTENT, "graphs": vuda.TUNE_GRAPHS,
-                "phys_prio": vuda.TUNE_PHYS_PRIORITY, "broadphase": vuda.TUNE_BROADPHASE}
+                "phys_prio": vuda.TUNE_PHYS_PRIORITY, "broadphase": vuda.TUNE_BROADPHASE,
+                "presetup": vuda.TUNE_PRESETUP}
     for kv in filter(None, args.tune.split(",")):
         k, v = kv.split("=")
         w.set_tuning(knob_ids[k], int(v))
@@ -210,10 +217,13 @@ def main():
     results["serialized"] = timed(torch, w, "serial", n_envs, args.steps, args.warmup, st0,
                                   after_warmup=lambda: launch_stats(vuda, w))
     alone = launch_stats(vuda, w)  # launches of the timed region
-    Ts, Tr = alone["physics"]["avg_s"], alone["raster"]["avg_s"]
+    presetup = w.get_tuning(vuda.TUNE_PRESETUP) != 0
+    Ts, Tr = phase_seconds(alone, args.steps, presetup)
     ser = n_envs * args.steps / results["serialized"]
-    log(f"serialized: {ser:.0f} env-steps/s; launches alone: physics {Ts*1e6:.1f} us, "
-        f"raster {Tr*1e6:.1f} us, bound {(Ts + Tr) / max(Ts, Tr):.3f}x")
+    log(f"serialized: {ser:.0f} env-steps/s; per step alone: step phase {Ts*1e6:.1f} us, "
+        f"render phase {Tr*1e6:.1f} us, bound {(Ts + Tr) / max(Ts, Tr):.3f}x "
+        f"(physics {alone['physics']['avg_s']*1e6:.1f}, setup {alone['raster_setup']['avg_s']*1e6:.1f}, "
+        f"tiles {alone['raster_tiles']['avg_s']*1e6:.1f} us per launch)")
     # co-scheduled candidates: unmasked streams and CU splits, both overlap patterns
     cands = [(2.0, sched) for sched in ("interstep", "intertraj")]
     cands += [(float(x), sched) for x in args.splits.split(",") for sched in ("interstep", "intertraj")]
@@ -239,20 +249,18 @@ def main():
     # average duration in the timed region
     px = int((scene.cam_w.astype("int64") * scene.cam_h).sum())
     body_cams = int(sum(scene.counts()[e] * (scene.cam_off[e + 1] - scene.cam_off[e]) for e in range(n_envs)))
-    # algorithmic bytes: the render phase reads 28 B of pose per body and
-    # camera (setup kernel) and writes 7 B per pixel (tile kernel)
-    step_bytes = {"physics": 120 * scene.n_bodies, "raster": 7 * px + 28 * body_cams,
-                  "raster_setup": 28 * body_cams, "raster_tiles": 7 * px}
+    # algorithmic bytes: the raster setup reads 28 B of pose per body and
+    # camera, the tile kernel writes 7 B per pixel
+    step_bytes = {"physics": 120 * scene.n_bodies, "raster_setup": 28 * body_cams, "raster_tiles": 7 * px}
     per_step = {k: live[k]["launches"] / args.steps for k in step_bytes}
     kinds = {}
     for name in step_bytes:
-        lb = step_bytes[name] / per_step[name]  # launches split the env range evenly
+        lb = step_bytes[name] / max(per_step[name], 1e-9)  # launches split the env range evenly
         t = live[name]["avg_s"]
         kinds[name] = {"launch_us": round(t * 1e6, 2), "bytes_per_launch": int(lb),
-                       "launches_per_step": per_step[name], "GBs": round(lb / t / 1e9, 2),
+                       "launches_per_step": per_step[name], "GBs": round(lb / t / 1e9, 2) if t else None,
                        "alone_launch_us": round(alone[name]["avg_s"] * 1e6, 2)}
-    # the dominant kernel (the render phase is two kernels)
-    dom = max(("physics", "raster_setup", "raster_tiles"), key=lambda k: kinds[k]["launch_us"] * per_step[k])
+    dom = max(step_bytes, key=lambda k: kinds[k]["launch_us"] * per_step[k])
     ach = kinds[dom]["GBs"]
     tr = measured_traffic(dom, cfg)
     roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -292,7 +300,7 @@ def main():
         "serialized": {"value": round(ser, 1), "ms_per_step": round(results["serialized"] / args.steps * 1e3, 4)},
         "speedup_vs_serialized": round(value / ser, 4),
         "overlap_bound": round((Ts + Tr) / max(Ts, Tr), 4),
-        "phase_alone_us": {"physics": round(Ts * 1e6, 2), "raster": round(Tr * 1e6, 2)},
+        "phase_alone_us": {"step": round(Ts * 1e6, 2), "render": round(Tr * 1e6, 2), "presetup": presetup},
         "sweep": {k: round(v, 1) for k, v in sweep.items()},
         "roofline": roof,
         "cpu_baseline": cpu,

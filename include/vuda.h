@@ -241,9 +241,15 @@ int vuda_world_info(vuda_world* w, int32_t* n_envs, int64_t* n_bodies, int32_t* 
  *   VUDA_TUNE_BROADPHASE       0 automatic (all pairs up to 64 bodies, uniform
  *                              grid hash above), 1 grid hash, 2 all pairs;
  *                              both give the same candidate set
- *   VUDA_TUNE_TIMING           1: record a HIP event pair around every phase
+ *   VUDA_TUNE_TIMING           1: record a HIP event pair around every kernel
  *                              launch on the stream it runs on (read with
- *                              vuda_phase_times); 0: off (default)
+ *                              vuda_kernel_times); 0: off (default)
+ *   VUDA_TUNE_PRESETUP         1 (default): vuda_step ends with the raster
+ *                              setup of the state it produced, on the step
+ *                              stream, so that vuda_render only rasterizes;
+ *                              0: vuda_render does both.  A render of a state
+ *                              without setup (after creation, vuda_load_state
+ *                              or a step with this off) does its own setup
  * None of them changes any output bit.  Returns VUDA_EINVAL for unknown keys
  * or out-of-range values.
  */
@@ -255,25 +261,28 @@ int vuda_world_info(vuda_world* w, int32_t* n_envs, int64_t* n_bodies, int32_t* 
 #define VUDA_TUNE_PHYS_PRIORITY 6
 #define VUDA_TUNE_BROADPHASE 7
 #define VUDA_TUNE_TIMING 8
+#define VUDA_TUNE_PRESETUP 9
 int vuda_set_tuning(vuda_world* w, int32_t key, int32_t value);
 int vuda_get_tuning(vuda_world* w, int32_t key, int32_t* value);
 
 /*
- * Launch durations recorded while VUDA_TUNE_TIMING is on: for `phase`
- * (VUDA_PHASE_STEP or VUDA_PHASE_RENDER), waits for the last recorded launch,
- * then returns the number of launches since the last read of part 0 and the
- * sum and maximum of their durations in milliseconds; a read of part 0 starts
- * a new count.  A launch is the phase's work over one enqueued env range:
- * the physics kernel, or the raster setup kernel followed by the raster tile
- * kernel (each with its queue reset when persistent).  Durations are GPU time
- * between events on the launch's stream, the first recorded after the
- * launch's stream waits were satisfied.  `part` selects 0 the whole launch,
- * 1 its first kernel, 2 the raster tile kernel (VUDA_PHASE_RENDER only; with
- * VUDA_TUNE_GRAPHS on, the launch is one graph and part 2 reads 0).  Any
- * output pointer may be NULL.
+ * Kernel durations recorded while VUDA_TUNE_TIMING is on.  `kernel` is
+ * VUDA_KERNEL_PHYSICS (the step), VUDA_KERNEL_RASTER_SETUP (vertex
+ * transform, triangle setup and tile binning of a state; part of the step
+ * with VUDA_TUNE_PRESETUP, else of the render) or VUDA_KERNEL_RASTER_TILES
+ * (the pixels, part of the render).  Waits for the last recorded launch of
+ * that kernel, then returns the number of launches since the previous call
+ * for it and the sum and maximum of their durations in milliseconds -- GPU
+ * time between an event recorded on the launch's stream just before the
+ * kernel (after the stream's waits were satisfied) and one just after it
+ * (including its queue reset when persistent) -- and starts a new count.
+ * Any output pointer may be NULL.
  */
-int vuda_phase_times(vuda_world* w, int32_t phase, int32_t part, int64_t* launches, double* total_ms,
-                     double* max_ms);
+#define VUDA_KERNEL_PHYSICS 1
+#define VUDA_KERNEL_RASTER_SETUP 2
+#define VUDA_KERNEL_RASTER_TILES 3
+int vuda_kernel_times(vuda_world* w, int32_t kernel, int64_t* launches, double* total_ms,
+                      double* max_ms);
 
 /*
  * Placement probe: launches n_blocks one-wave workgroups on the stream of
@@ -305,7 +314,7 @@ int vuda_run(vuda_world* w, int32_t schedule, int32_t iters);
 
 /*
  * Autotuner: searches the launch shapes (schedule, CU split, physics and
- * raster workgroup shapes, physics priority, broadphase) for the highest
+ * raster workgroup shapes, physics priority, broadphase, presetup) for the highest
  * co-scheduled env-steps/s on this world, timing `steps_per_trial`
  * iterations per candidate from the current state (the state is saved before
  * and restored after, so results are unchanged), applies the best, and
@@ -321,6 +330,7 @@ typedef struct {
   double serial_env_steps_per_s;
   int32_t serial_raster_threads, serial_phys_persistent;
   int32_t trials;            /* 0 when taken from the cache */
+  int32_t presetup;          /* VUDA_TUNE_PRESETUP chosen */
 } vuda_tune_result;
 int vuda_autotune(vuda_world* w, int32_t steps_per_trial, const char* cache_path, vuda_tune_result* out);
 

@@ -82,6 +82,7 @@ int restore_snapshot(vuda_world* w, const Snapshot& s) {
   if (e == hipSuccess) e = hipMemcpy(w->dev.env_flags, d + 2 * st, fl, hipMemcpyDeviceToDevice);
   if (e != hipSuccess) return hip_fail(e, "snapshot restore");
   w->env_parity = s.parity;
+  std::fill(w->setup_ok.begin(), w->setup_ok.end(), 0);  // the scratch may hold another state's setup
   std::fill(w->step_ev.begin(), w->step_ev.end(), -1);
   std::fill(w->render_ev[0].begin(), w->render_ev[0].end(), -1);
   std::fill(w->render_ev[1].begin(), w->render_ev[1].end(), -1);
@@ -121,6 +122,7 @@ void to_result(const Cand& c, vuda_tune_result* r) {
   r->raster_persistent = c.tune.raster_persistent;
   r->phys_priority = c.tune.phys_prio;
   r->broadphase = c.tune.broadphase;
+  r->presetup = c.tune.presetup ? 1 : 0;
 }
 
 bool cache_lookup(const char* path, const std::string& key, vuda_tune_result* r) {
@@ -135,7 +137,7 @@ bool cache_lookup(const char* path, const std::string& key, vuda_tune_result* r)
     vuda_tune_result t{};
     if (is >> t.cu_split >> t.schedule >> t.raster_threads >> t.rec_cap >> t.phys_persistent >>
         t.raster_persistent >> t.phys_priority >> t.broadphase >> t.cosched_env_steps_per_s >>
-        t.serial_env_steps_per_s >> t.serial_raster_threads >> t.serial_phys_persistent) {
+        t.serial_env_steps_per_s >> t.serial_raster_threads >> t.serial_phys_persistent >> t.presetup) {
       *r = t;  // the last matching line wins
       found = true;
     }
@@ -149,7 +151,7 @@ void cache_store(const char* path, const std::string& key, const vuda_tune_resul
   f << key << " " << r.cu_split << " " << r.schedule << " " << r.raster_threads << " " << r.rec_cap
     << " " << r.phys_persistent << " " << r.raster_persistent << " " << r.phys_priority << " "
     << r.broadphase << " " << r.cosched_env_steps_per_s << " " << r.serial_env_steps_per_s << " "
-    << r.serial_raster_threads << " " << r.serial_phys_persistent << "\n";
+    << r.serial_raster_threads << " " << r.serial_phys_persistent << " " << r.presetup << "\n";
 }
 
 }  // namespace
@@ -176,6 +178,7 @@ extern "C" int vuda_autotune(vuda_world* w, int32_t steps, const char* cache_pat
     c.tune.raster_persistent = out->raster_persistent;
     c.tune.phys_prio = out->phys_priority;
     c.tune.broadphase = out->broadphase;
+    c.tune.presetup = out->presetup != 0;
     out->trials = 0;
     return apply(w, c);
   }
@@ -240,6 +243,7 @@ extern "C" int vuda_autotune(vuda_world* w, int32_t steps, const char* cache_pat
   stage([](Cand& c, int v) { c.tune.raster_threads = v; }, {256, 512});
   stage([](Cand& c, int v) { c.tune.phys_prio = v; }, {0, 3});
   stage([](Cand& c, int v) { c.tune.broadphase = v; }, {0, 1});
+  stage([](Cand& c, int v) { c.tune.presetup = v != 0; }, {1, 0});
   const int rc_trials = rc;
   rc = restore_snapshot(w, snap);
   (void)hipFree(snap.dev);

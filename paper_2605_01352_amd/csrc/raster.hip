@@ -6,13 +6,14 @@
 //   2. every template vertex of every body (and the ground) is transformed
 //      once -- world = p + R (s v), clip = VP world, perspective divide,
 //      viewport, snap to 24.8 fixed point -- into an LDS vertex cache;
-//   3. triangle setup: a triangle is culled if a vertex is behind the near
-//      plane or outside the guard band, if it is back-facing or degenerate
-//      (integer area <= 0), or if its bounding box holds no pixel centre.  A
-//      survivor gets a setup record in the image's raster scratch (snapped
-//      vertices in edge order, depths, 1/area, key and flat Lambert colour)
-//      and the tiles of its box are counted with LDS atomics;
-//   4. a workgroup prefix scan of the counts places each 16x16 tile's bin; a
+//   3. culling: a triangle is dropped if a vertex is behind the near plane
+//      or outside the guard band, if it is back-facing or degenerate (integer
+//      area <= 0), or if its bounding box holds no pixel centre; survivors
+//      are compacted into a list;
+//   4. each survivor gets a setup record in the image's raster scratch
+//      (snapped vertices in edge order, depths, 1/area, key and flat Lambert
+//      colour) and the tiles of its box are counted with LDS atomics;
+//   5. a workgroup prefix scan of the counts places each 16x16 tile's bin; a
 //      scatter pass classifies each triangle against every tile of its box
 //      (exact corner test of the edge functions) and appends its record id,
 //      flagged when the triangle covers the whole tile.
@@ -316,7 +317,7 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
   const int ntx = (Wd + kTile - 1) / kTile;
   const int ntiles = tiles_of(Wd, Ht);
   const RsLayout RL = rs_layout(cam.n_tris, ntiles);
-  unsigned char* rs = W.rscratch + cam.rs_off;
+  unsigned char* rs = W.rscratch + cam.rs_off + L.parity * RL.total;  // one scratch per state buffer
   int32_t* hdr = (int32_t*)rs;
   int32_t* ttab = (int32_t*)(rs + RL.tiles);
   int4* grec = (int4*)(rs + RL.recs);
@@ -412,43 +413,65 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
   }
   __syncthreads();
 
-  // 3. setup records (with the face colour) and tile counts.  A triangle
-  // whose box spans more than kWide tiles is counted by its whole wave, one
-  // tile per lane, so that one lane never walks a long tile list alone.
+  // 3. visibility.  A triangle survives if every vertex is in front of the
+  // near plane and inside the guard band, its integer area is > 0 (front
+  // facing, not degenerate) and its box holds a pixel centre.  Survivors are
+  // compacted into vis (a wave ballot and one atomic per wave), so that the
+  // costlier steps below run on full waves.
   for (int base = 0; base < ntris; base += nthr) {
     const int pr = base + tid;
-    int tx0 = 0, ty0 = 0, nx = 0, ntl = 0;
+    bool keep = false;
     if (pr < ntris) {
       int body, vid[3];
       prim_vertices(T, B, gpmap[pr], pr, &body, vid);
       const Tri t = load_tri(VX, VY, VZ, vid);
       int x0, x1, y0, y1;
-      if (t.ok) {
-        const int64_t A = tri_area(t.X, t.Y);
-        if (A > 0 && tri_pixels(t.X, t.Y, Wd, Ht, &x0, &x1, &y0, &y1)) {
-          const int slot = atomicAdd(&misc[2], 1);
-          const uint32_t rgb = face_color(T, B, Lo.nmax, body, body < 0 ? pr : pr - B.pb[body]);
-          store_rec(grec, slot, t, ((uint32_t)pr << 16) | (uint32_t)slot, 1.0f / (float)(double)A, rgb);
-          vis[slot] = (uint16_t)pr;
-          tx0 = x0 >> 4;
-          ty0 = y0 >> 4;
-          nx = (x1 >> 4) - tx0 + 1;
-          ntl = nx * ((y1 >> 4) - ty0 + 1);
-        }
-      }
+      keep = t.ok && tri_area(t.X, t.Y) > 0 && tri_pixels(t.X, t.Y, Wd, Ht, &x0, &x1, &y0, &y1);
+    }
+    const uint64_t m = __ballot(keep);
+    int wbase = 0;
+    if (lane == 0 && m) wbase = atomicAdd(&misc[2], __popcll(m));
+    wbase = __builtin_amdgcn_readfirstlane(wbase);
+    const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+    if (keep) vis[wbase + below] = (uint16_t)pr;
+  }
+  __syncthreads();
+  const int nrec = misc[2];
+
+  // 4. setup records (with the face colour) and tile counts, one surviving
+  // triangle per lane.  A triangle whose box spans more than kWide tiles is
+  // counted by its whole wave, one tile per lane, so that one lane never
+  // walks a long tile list alone.  Record slots differ from run to run; keys
+  // order by depth, then primitive, so the slot never decides a winner.
+  for (int base = 0; base < nrec; base += nthr) {
+    const int r = base + tid;
+    int tx0 = 0, ty0 = 0, nx = 0, ny = 0;
+    if (r < nrec) {
+      const int pr = vis[r];
+      int body, vid[3];
+      prim_vertices(T, B, gpmap[pr], pr, &body, vid);
+      const Tri t = load_tri(VX, VY, VZ, vid);
+      int x0, x1, y0, y1;
+      tri_pixels(t.X, t.Y, Wd, Ht, &x0, &x1, &y0, &y1);
+      const int64_t A = tri_area(t.X, t.Y);
+      const uint32_t rgb = face_color(T, B, Lo.nmax, body, body < 0 ? pr : pr - B.pb[body]);
+      store_rec(grec, r, t, ((uint32_t)pr << 16) | (uint32_t)r, 1.0f / (float)(double)A, rgb);
+      tx0 = x0 >> 4;
+      ty0 = y0 >> 4;
+      nx = (x1 >> 4) - tx0 + 1;
+      ny = (y1 >> 4) - ty0 + 1;
     }
     if (!tiled) continue;
-    if (ntl <= kWide)
-      for (int q = 0; q < ntl; ++q) {
-        const int qy = q / nx;
-        atomicAdd(&tcount[(ty0 + qy) * ntx + tx0 + (q - qy * nx)], 1);
-      }
-    uint64_t m = __ballot(ntl > kWide);
+    const bool wide = nx * ny > kWide;
+    if (!wide)
+      for (int qy = 0; qy < ny; ++qy)
+        for (int qx = 0; qx < nx; ++qx) atomicAdd(&tcount[(ty0 + qy) * ntx + tx0 + qx], 1);
+    uint64_t m = __ballot(wide);
     while (m) {
       const int j = __ffsll((unsigned long long)m) - 1;
       m &= m - 1ull;
       const int jx0 = __shfl(tx0, j, 64), jy0 = __shfl(ty0, j, 64);
-      const int jnx = __shfl(nx, j, 64), jn = __shfl(ntl, j, 64);
+      const int jnx = __shfl(nx, j, 64), jn = jnx * __shfl(ny, j, 64);
       for (int q = lane; q < jn; q += 64) {
         const int qy = q / jnx;
         atomicAdd(&tcount[(jy0 + qy) * ntx + jx0 + (q - qy * jnx)], 1);
@@ -456,7 +479,6 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
     }
   }
   __syncthreads();
-  const int nrec = misc[2];
   // bin entries hold 15-bit record ids
   bool binned = tiled && nrec <= 32768;
   if (binned) {
@@ -464,13 +486,13 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
     if (total > bin_cap) binned = false;
   }
 
-  // 4. scatter record ids into the bins, from the vertex cache
+  // 5. scatter record ids into the bins, from the vertex cache
   if (binned) {
     for (int t = tid; t < ntiles; t += nthr) tfill[t] = 0;
     __syncthreads();
     for (int base = 0; base < nrec; base += nthr) {
       const int r = base + tid;
-      int x0 = 0, x1 = 0, y0 = 0, y1 = 0, nx = 0, ntl = 0;
+      int x0 = 0, x1 = 0, y0 = 0, y1 = 0, nx = 0, ny = 0;
       Tri t{};
       if (r < nrec) {
         const int pr = vis[r];
@@ -479,15 +501,15 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
         t = load_tri(VX, VY, VZ, vid);
         tri_pixels(t.X, t.Y, Wd, Ht, &x0, &x1, &y0, &y1);
         nx = (x1 >> 4) - (x0 >> 4) + 1;
-        ntl = nx * ((y1 >> 4) - (y0 >> 4) + 1);
+        ny = (y1 >> 4) - (y0 >> 4) + 1;
       }
-      if (ntl <= kWide)
-        for (int q = 0; q < ntl; ++q) {
-          const int qy = q / nx;
-          bin_tile(t, r, (x0 >> 4) + (q - qy * nx), (y0 >> 4) + qy, x0, x1, y0, y1, ntl > 1, Wd, Ht, ntx,
-                   toff, tfill, bins);
-        }
-      uint64_t m = __ballot(ntl > kWide);
+      const bool wide = nx * ny > kWide;
+      if (!wide)
+        for (int qy = 0; qy < ny; ++qy)
+          for (int qx = 0; qx < nx; ++qx)
+            bin_tile(t, r, (x0 >> 4) + qx, (y0 >> 4) + qy, x0, x1, y0, y1, nx * ny > 1, Wd, Ht, ntx, toff,
+                     tfill, bins);
+      uint64_t m = __ballot(wide);
       while (m) {
         const int j = __ffsll((unsigned long long)m) - 1;
         m &= m - 1ull;
@@ -542,58 +564,50 @@ __global__ void raster_setup_kernel(WorldDev W, RasterLaunch L) {
 // tile kernel
 // ---------------------------------------------------------------------------
 
+// A small triangle's edge values over its box, in 32-bit integers: when the
+// triangle spans at most kNarrow units (120 pixels) on both axes, every edge
+// value at a pixel centre in its box is at most 2 kNarrow^2 < 2^31 in
+// magnitude and the steps per pixel, 256 dx and 256 dy, stay below 2^23, so
+// 24-bit multiply-adds are exact.
+constexpr int kNarrow = 120 * 256;
+
 struct TileWaveLDS {
   uint64_t zb[256];     // z-buffer of the small-triangle fragments
-  int4 rec[64][3];      // the batch's setup records
+  // per batch lane: a small triangle's (E0 at its box origin, key), (step
+  // per row, thr0), (step per column, thr1), (z0, z1, z2, 1/area), (thr2);
+  // a large one's setup record in the first three
+  int4 q[64][5];
   int2 meta[64];        // (x0 | y0 << 16, fragment offset | box width << 16)
   int32_t own[64];      // fragment owner marks
 };
 
-// Covered test and key of one pixel centre for a record (fragment path).
-__device__ __forceinline__ bool frag_key(const int4& ra, const int4& rb, const int4& rc, int ppx, int ppy,
-                                         uint64_t* key) {
-  const int32_t X[3] = {ra.x, ra.z, rb.x}, Y[3] = {ra.y, ra.w, rb.y};
-  const int Px = 256 * ppx + 128, Py = 256 * ppy + 128;
-  double E[3];
-  bool in = true;
-#pragma unroll
-  for (int e = 0; e < 3; ++e) {
-    const int a = (e + 1) % 3, b = (e + 2) % 3;
-    const int32_t dx = X[b] - X[a], dy = Y[b] - Y[a];
-    // both products and the sum are integers below 2^53: exact
-    E[e] = fma(-(double)dy, (double)(Px - X[a]), (double)dx * (double)(Py - Y[a]));
-    // integer-valued E: (E > 0 or E == 0 on a top-left edge) == (E >= threshold)
-    in = in && E[e] >= (top_left(dx, dy) ? 0.0 : 1.0);
-  }
-  if (!in) return false;
-  const float zz = (((float)E[0] * __int_as_float(rb.w) + (float)E[1] * __int_as_float(rc.x)) +
-                    (float)E[2] * __int_as_float(rc.y)) *
-                   __int_as_float(rc.z);
+// Quantised depth key of a covered pixel from its three edge values.
+__device__ __forceinline__ uint64_t depth_key(float e0, float e1, float e2, float z0, float z1, float z2,
+                                              float invA, uint32_t key) {
+  const float zz = ((e0 * z0 + e1 * z1) + e2 * z2) * invA;
   // the interpolated depth is finite, so the median equals the clamp to [0, 1]
   const uint32_t D = (uint32_t)rintf(__builtin_amdgcn_fmed3f(zz, 0.0f, 1.0f) * 16777215.0f);
-  *key = ((uint64_t)D << 32) | (uint32_t)rb.z;
-  return true;
+  return ((uint64_t)D << 32) | key;
 }
 
 template <bool DBG>
-__device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam, int ntx, int ntiles,
-                                            int tile, TileWaveLDS& S, int32_t* cov) {
+__device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam, int parity, int ntx,
+                                            int tx, int ty, TileWaveLDS& S, int32_t* cov) {
   const int lane = threadIdx.x & 63;
   const int Wd = cam.w, Ht = cam.h;
-  const RsLayout RL = rs_layout(cam.n_tris, ntiles);
-  const unsigned char* rs = W.rscratch + cam.rs_off;
+  const unsigned char* rs = W.rscratch + cam.rs_off + (int64_t)parity * cam.rs_total;
   const int32_t* hdr = (const int32_t*)rs;
   const int nrec = hdr[0];
   const bool binned = hdr[1] != 0;
-  const int4* grec = (const int4*)(rs + RL.recs);
-  const uint16_t* bins = (const uint16_t*)(rs + RL.bins);
+  const int4* grec = (const int4*)(rs + cam.rs_recs);
+  const uint16_t* bins = (const uint16_t*)(rs + cam.rs_bins);
   int k0 = 0, k1 = nrec;
   if (binned) {
-    const int32_t* tt = (const int32_t*)(rs + RL.tiles) + 2 * tile;
+    const int32_t* tt = (const int32_t*)(rs + 64) + 2 * (ty * ntx + tx);
     k0 = tt[0];
     k1 = k0 + tt[1];
   }
-  const int tx0 = (tile % ntx) * kTile, ty0 = (tile / ntx) * kTile;
+  const int tx0 = tx * kTile, ty0 = ty * kTile;
   const int tx1 = min(tx0 + kTile - 1, Wd - 1), ty1 = min(ty0 + kTile - 1, Ht - 1);
   // this lane's pixels: (px0 + i, py) for i < 4, z-buffer entries 4 lane + i
   const int py = ty0 + (lane >> 2), px0 = tx0 + 4 * (lane & 3);
@@ -611,6 +625,7 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
   for (int kb = k0; kb < k1; kb += 64) {
     const int k = kb + lane;
     int full = 0, area = 0, fx0 = 0, fy0 = 0, bw = 1;
+    bool big = false;
     if (k < k1) {
       int rec = k;
       if (binned) {
@@ -619,9 +634,6 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
         full = e >> 15;
       }
       const int4 ra = grec[3 * rec], rb = grec[3 * rec + 1], rc = grec[3 * rec + 2];
-      S.rec[lane][0] = ra;
-      S.rec[lane][1] = rb;
-      S.rec[lane][2] = rc;
       const int32_t X[3] = {ra.x, ra.z, rb.x}, Y[3] = {ra.y, ra.w, rb.y};
       int x0, x1, y0, y1;
       if (tri_pixels(X, Y, Wd, Ht, &x0, &x1, &y0, &y1)) {
@@ -632,8 +644,34 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
         area = (bw > 0 && bh > 0) ? bw * bh : 0;
         if (bw < 1) bw = 1;
       }
+      const bool narrow = max(X[0], max(X[1], X[2])) - min(X[0], min(X[1], X[2])) <= kNarrow &&
+                          max(Y[0], max(Y[1], Y[2])) - min(Y[0], min(Y[1], Y[2])) <= kNarrow;
+      big = area > kSmallMax || (area > 0 && !narrow);
+      if (big) {
+        S.q[lane][0] = ra;
+        S.q[lane][1] = rb;
+        S.q[lane][2] = rc;
+      } else if (area > 0) {
+        // edge values at the centre of pixel (fx0, fy0), steps per row and column
+        const int Px = 256 * fx0 + 128, Py = 256 * fy0 + 128;
+        int E0[3], sr[3], sc[3], thr[3];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+          const int a0 = (e + 1) % 3, b0 = (e + 2) % 3;
+          const int32_t dx = X[b0] - X[a0], dy = Y[b0] - Y[a0];
+          E0[e] = __mul24(dx, Py - Y[a0]) - __mul24(dy, Px - X[a0]);
+          sr[e] = 256 * dx;
+          sc[e] = -256 * dy;
+          // (E > 0 or E == 0 on a top-left edge) == (E >= threshold) for integer E
+          thr[e] = top_left(dx, dy) ? 0 : 1;
+        }
+        S.q[lane][0] = make_int4(E0[0], E0[1], E0[2], rb.z);
+        S.q[lane][1] = make_int4(sr[0], sr[1], sr[2], thr[0]);
+        S.q[lane][2] = make_int4(sc[0], sc[1], sc[2], thr[1]);
+        S.q[lane][3] = make_int4(rb.w, rc.x, rc.y, rc.z);
+        S.q[lane][4].x = thr[2];
+      }
     }
-    const bool big = area > kSmallMax;
     // small triangles: fragments packed over lanes.  Fragment f belongs to
     // the lane j with off_j <= f < off_j + a_j; per window of 64 fragments
     // each owner marks where its range starts and a max-scan spreads it.
@@ -660,12 +698,20 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
         // rr / jbw exactly: rr < 64 and jbw <= 16 keep the quotient's
         // fraction at least 1/32 away from an integer
         const int qy = (int)(((float)rr + 0.5f) * __builtin_amdgcn_rcpf((float)jbw));
-        const int ppx = (m.x & 0xFFFF) + (rr - qy * jbw), ppy = (m.x >> 16) + qy;
-        uint64_t kk;
-        if (frag_key(S.rec[j][0], S.rec[j][1], S.rec[j][2], ppx, ppy, &kk)) {
-          const int p = (ppy - ty0) * kTile + (ppx - tx0);
-          atomicMin((unsigned long long*)&zb[p], (unsigned long long)kk);
-          if (DBG) atomicAdd(&cov[p], 1);
+        const int qx = rr - qy * jbw;
+        const int4 q0 = S.q[j][0], q1 = S.q[j][1], q2 = S.q[j][2];
+        const int e0 = q0.x + __mul24(q1.x, qy) + __mul24(q2.x, qx);
+        const int e1 = q0.y + __mul24(q1.y, qy) + __mul24(q2.y, qx);
+        const int e2 = q0.z + __mul24(q1.z, qy) + __mul24(q2.z, qx);
+        if ((e0 >= q1.w) & (e1 >= q2.w) & (e2 >= S.q[j][4].x)) {
+          const int4 q3 = S.q[j][3];
+          const uint64_t kk = depth_key((float)e0, (float)e1, (float)e2, __int_as_float(q3.x),
+                                        __int_as_float(q3.y), __int_as_float(q3.z), __int_as_float(q3.w),
+                                        (uint32_t)q0.w);
+          const int p = (m.x >> 16) + qy - ty0;  // row in the tile
+          const int pp = p * kTile + (m.x & 0xFFFF) + qx - tx0;
+          atomicMin((unsigned long long*)&zb[pp], (unsigned long long)kk);
+          if (DBG) atomicAdd(&cov[pp], 1);
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -675,8 +721,8 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
     while (m) {
       const int j = __ffsll((unsigned long long)m) - 1;
       m &= m - 1ull;
-      const bool jfull = __builtin_amdgcn_readlane(full, j) != 0;
-      const int4 ra = S.rec[j][0], rb = S.rec[j][1], rc = S.rec[j][2];
+      const bool jfull = __builtin_amdgcn_readlane(full, j) != 0;  // uniform
+      const int4 ra = S.q[j][0], rb = S.q[j][1], rc = S.q[j][2];
       const int32_t X[3] = {ra.x, ra.z, rb.x}, Y[3] = {ra.y, ra.w, rb.y};
       const float z0 = __int_as_float(rb.w), z1 = __int_as_float(rc.x), z2 = __int_as_float(rc.y);
       const float invA = __int_as_float(rc.z);
@@ -690,16 +736,26 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
         step[e] = -(double)dy * 256.0;  // one pixel right
         thr[e] = top_left(dx, dy) ? 0.0 : 1.0;
       }
+      if (jfull) {
+        // every pixel of the tile is covered
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const bool in = jfull || (E[0] >= thr[0] && E[1] >= thr[1] && E[2] >= thr[2]);
-        const float zz = (((float)E[0] * z0 + (float)E[1] * z1) + (float)E[2] * z2) * invA;
-        const uint32_t D = (uint32_t)rintf(__builtin_amdgcn_fmed3f(zz, 0.0f, 1.0f) * 16777215.0f);
-        const uint64_t kk = ((uint64_t)D << 32) | key;
-        kreg[i] = (in && kk < kreg[i]) ? kk : kreg[i];
-        if (DBG) creg[i] += in ? 1 : 0;
+        for (int i = 0; i < 4; ++i) {
+          const uint64_t kk = depth_key((float)E[0], (float)E[1], (float)E[2], z0, z1, z2, invA, key);
+          kreg[i] = kk < kreg[i] ? kk : kreg[i];
+          if (DBG) creg[i] += 1;
 #pragma unroll
-        for (int e = 0; e < 3; ++e) E[e] += step[e];
+          for (int e = 0; e < 3; ++e) E[e] += step[e];
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const bool in = (E[0] >= thr[0]) & (E[1] >= thr[1]) & (E[2] >= thr[2]);
+          const uint64_t kk = depth_key((float)E[0], (float)E[1], (float)E[2], z0, z1, z2, invA, key);
+          kreg[i] = (in & (kk < kreg[i])) ? kk : kreg[i];
+          if (DBG) creg[i] += in ? 1 : 0;
+#pragma unroll
+          for (int e = 0; e < 3; ++e) E[e] += step[e];
+        }
       }
     }
   }
@@ -765,10 +821,9 @@ __global__ void __launch_bounds__(64 * kTileWaves) raster_tile_kernel(WorldDev W
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const CamDev cam = W.cams[job.x];
   const int ntx = (cam.w + kTile - 1) / kTile;
-  const int ntiles = tiles_of(cam.w, cam.h);
-  const int tile = job.y + wave;
-  if (tile >= ntiles) return;  // no workgroup barrier follows
-  raster_tile<DBG>(W, cam, ntx, ntiles, tile, S[wave], DBG ? C[wave] : nullptr);
+  const int tx = (job.y & 0xFFFF) + wave, ty = job.y >> 16;
+  if (tx >= ntx) return;  // no workgroup barrier follows
+  raster_tile<DBG>(W, cam, L.parity, ntx, tx, ty, S[wave], DBG ? C[wave] : nullptr);
 }
 
 }  // namespace
@@ -782,8 +837,7 @@ hipError_t raster_configure(size_t lds_bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
 }
 
-hipError_t launch_raster(const WorldDev& w, const RasterLaunch& l, hipStream_t s, phase_mark_fn mark,
-                         void* mark_ctx) {
+hipError_t launch_raster_setup(const WorldDev& w, const RasterLaunch& l, hipStream_t s) {
   if (l.n_work <= 0) return hipSuccess;
   const size_t lds = raster_lds_bytes(l);
   const int grid = l.persistent > 0 ? (l.persistent < l.n_work ? l.persistent : l.n_work) : l.n_work;
@@ -792,18 +846,15 @@ hipError_t launch_raster(const WorldDev& w, const RasterLaunch& l, hipStream_t s
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(raster_setup_kernel, dim3(grid), dim3(l.threads), lds, s, w, l);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  if (mark) {
-    e = mark(mark_ctx, s);
-    if (e != hipSuccess) return e;
-  }
-  if (l.n_tile_groups > 0) {
-    if (w.winners)
-      hipLaunchKernelGGL(raster_tile_kernel<true>, dim3(l.n_tile_groups), dim3(64 * kTileWaves), 0, s, w, l);
-    else
-      hipLaunchKernelGGL(raster_tile_kernel<false>, dim3(l.n_tile_groups), dim3(64 * kTileWaves), 0, s, w, l);
-  }
+  return hipGetLastError();
+}
+
+hipError_t launch_raster_tiles(const WorldDev& w, const RasterLaunch& l, hipStream_t s) {
+  if (l.n_tile_groups <= 0) return hipSuccess;
+  if (w.winners)
+    hipLaunchKernelGGL(raster_tile_kernel<true>, dim3(l.n_tile_groups), dim3(64 * kTileWaves), 0, s, w, l);
+  else
+    hipLaunchKernelGGL(raster_tile_kernel<false>, dim3(l.n_tile_groups), dim3(64 * kTileWaves), 0, s, w, l);
   return hipGetLastError();
 }
 

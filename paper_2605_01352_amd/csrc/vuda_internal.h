@@ -44,11 +44,14 @@ struct CamDev {
   int64_t pix_off;    // first pixel of the image in the image arena
   int32_t env;
   int32_t n_tris;     // primitives of the env (sizes the raster scratch)
-  int64_t rs_off;     // byte offset of the image's raster scratch
+  int64_t rs_off;     // byte offset of the image's raster scratch (two layouts, one per state buffer)
+  int32_t rs_recs, rs_bins, rs_total;  // rs_layout(n_tris, tiles): offsets and size of one layout
+  int32_t pad;
 };
 
-// Raster scratch of one camera image, written by the setup kernel and read by
-// the tile kernel: a header (record count, binned flag), the tile table
+// Raster scratch of one camera image and state buffer (two per camera, one
+// for each state buffer), written by the setup kernel and read by the tile
+// kernel: a header (record count, binned flag), the tile table
 // (bin offset, bin count per 16x16 tile), the setup records (kRecBytes each,
 // room for every primitive of the env) and the bins (u16 record ids, bit 15
 // set when the triangle covers the whole tile).
@@ -150,8 +153,8 @@ struct PhysLaunch {
 struct RasterLaunch {
   const int32_t* work;     // camera ids, LPT order (setup kernel, one workgroup each)
   int32_t n_work;
-  const int2* tiles;       // tile kernel: per workgroup (camera, first of its 4 tiles);
-                           // camera -1 for padding entries
+  const int2* tiles;       // tile kernel: per workgroup (camera, tx | ty << 16): the tiles
+                           // tx .. tx + 3 of tile row ty; camera -1 for padding entries
   int32_t n_tile_groups;
   int32_t max_verts;       // over the listed cameras' envs
   int32_t max_tiles;
@@ -164,13 +167,12 @@ struct RasterLaunch {
   int32_t* queue;
 };
 
-// Timing hook: called between the kernels of a phase (nullable).
-typedef hipError_t (*phase_mark_fn)(void* ctx, hipStream_t s);
-
 hipError_t launch_physics(const WorldDev& w, const PhysConsts& pc, const PhysLaunch& l,
                           hipStream_t s);
-hipError_t launch_raster(const WorldDev& w, const RasterLaunch& l, hipStream_t s, phase_mark_fn mark,
-                         void* mark_ctx);
+// The render work of a state buffer: setup (geometry, records, bins) into the
+// cameras' scratch of that buffer, then the tiles (pixels) from it.
+hipError_t launch_raster_setup(const WorldDev& w, const RasterLaunch& l, hipStream_t s);
+hipError_t launch_raster_tiles(const WorldDev& w, const RasterLaunch& l, hipStream_t s);
 size_t raster_lds_bytes(const RasterLaunch& l);
 hipError_t raster_configure(size_t lds_bytes);
 hipError_t launch_reset_queue(int32_t* q, hipStream_t s);

@@ -69,7 +69,11 @@ struct Tuning {
   int32_t phys_prio = 0;
   int32_t broadphase = 0;
   bool timing = false;
+  bool presetup = true;
 };
+
+// kernels of the step loop (index of their timing events)
+constexpr int kKernelPhysics = 0, kKernelSetup = 1, kKernelTiles = 2;
 
 }  // namespace vuda
 
@@ -118,11 +122,13 @@ struct vuda_world {
   std::vector<hipEvent_t> evpool;
   int64_t next_event = 0;
 
-  // launch timing: per phase (index 0 step, 1 render) and launch, events at
-  // the start, between the phase's kernels and at the end; tev_used[k]
-  // launches recorded since the last read
-  std::vector<hipEvent_t> tev[2];
-  size_t tev_used[2] = {0, 0};
+  // launch timing: per kernel (kKernel*) and launch, an event before and one
+  // after; tev_used[k] launches recorded since the last read
+  std::vector<hipEvent_t> tev[3];
+  size_t tev_used[3] = {0, 0, 0};
+  // per env: the raster scratch of its current state buffer holds that
+  // state's setup
+  std::vector<uint8_t> setup_ok;
 
   std::map<std::tuple<int, int32_t, int32_t>, vuda::WorkList> lists;
   std::map<std::tuple<int, int32_t, int32_t, int>, hipGraphExec_t> graphs;
@@ -146,11 +152,10 @@ struct vuda_world {
   int range_parity(int32_t lo, int32_t hi, int* parity);
   int check_range(int32_t lo, int32_t hi);
   int enqueue_physics(const vuda::WorkList& L, int parity, hipStream_t s);
-  int raster_launch_of(const vuda::WorkList& L, int parity, vuda::RasterLaunch* out);
-  int enqueue_raster(const vuda::WorkList& L, int parity, hipStream_t s, hipEvent_t mid);
-  int run_phase(int phase, const vuda::WorkList& L, int parity, int32_t lo, int32_t hi, hipStream_t s);
-  int launch_phase(int phase, const vuda::WorkList& L, int parity, int32_t lo, int32_t hi, hipStream_t s,
-                   hipEvent_t mid);
+  int raster_launch_of(const vuda::WorkList& L, int parity, int32_t* queue, vuda::RasterLaunch* out);
+  int enqueue_kernel(int kind, const vuda::WorkList& L, int parity, hipStream_t s, int32_t* queue);
+  int run_kernel(int kind, const vuda::WorkList& L, int parity, int32_t lo, int32_t hi, hipStream_t s,
+                 int32_t* queue);
   hipStream_t capture_stream();
   int check_flags();
   int32_t active_midpoint();

@@ -323,7 +323,7 @@ int64_t vuda_world::rs_units(const vuda_env_batch& b) const {
   for (int32_t e = 0; e < b.n_envs; ++e) {
     const int32_t nt = env_tris(b, e);
     for (int32_t c = b.cam_off[e]; c < b.cam_off[e + 1]; ++c)
-      u += rs_layout(nt, tiles_of(b.cam_w[c], b.cam_h[c])).total / 256;
+      u += 2 * (rs_layout(nt, tiles_of(b.cam_w[c], b.cam_h[c])).total / 256);
   }
   return u;
 }
@@ -374,8 +374,13 @@ int vuda_world::upload(const vuda_env_batch& b, int32_t e0, int64_t b0, int32_t 
       d.env = e0 + e;
       d.n_tris = nt;
       d.rs_off = ro;
+      const RsLayout rl = rs_layout(nt, tiles_of(d.w, d.h));
+      d.rs_recs = (int32_t)rl.recs;
+      d.rs_bins = (int32_t)rl.bins;
+      d.rs_total = (int32_t)rl.total;
+      d.pad = 0;
       po += (int64_t)d.w * d.h;
-      ro += rs_layout(nt, tiles_of(d.w, d.h)).total;
+      ro += 2 * rl.total;
     }
   }
   std::vector<float> st((size_t)kStateComps * nb);
@@ -453,7 +458,7 @@ extern "C" int vuda_create_world(const vuda_world_desc* d, const vuda_allocator*
     const int64_t spare_b = w->cap_bodies - nb, spare_e = (int64_t)w->cap_envs - d->initial.n_envs;
     w->cap_prims = init_prims + spare_b * mf + spare_e * (w->tpl.ground_nf + 15);
     w->cap_verts = init_verts + spare_b * mv + spare_e * (w->tpl.ground_nv + 15);
-    // raster scratch of cameras admitted later.  Per camera it is at most
+    // raster scratch of cameras admitted later.  Per camera and state buffer it is at most
     // (kRecBytes + 2 kBinsPerTri) n_tris + 8 tiles + 829 bytes, and a camera
     // of W x H pixels has at most W H / 256 + 513 tiles; envs are assumed to
     // carry no more cameras each than the initial batch's most (at least 1).
@@ -461,8 +466,8 @@ extern "C" int vuda_create_world(const vuda_world_desc* d, const vuda_allocator*
     for (int32_t e = 0; e < d->initial.n_envs; ++e)
       kcam = std::max(kcam, d->initial.cam_off[e + 1] - d->initial.cam_off[e]);
     const int64_t spare_c = (int64_t)w->cap_cams - nc, spare_p = w->cap_pixels - npix;
-    const int64_t spare_bytes = (int64_t)(kRecBytes + 2 * kBinsPerTri) * kcam * (w->cap_prims - init_prims) +
-                                spare_p / 32 + (829 + 8 * 513) * spare_c;
+    const int64_t spare_bytes = 2 * ((int64_t)(kRecBytes + 2 * kBinsPerTri) * kcam * (w->cap_prims - init_prims) +
+                                     spare_p / 32 + (829 + 8 * 513) * spare_c);
     w->cap_rs = w->rs_units(d->initial) + (spare_bytes + 255) / 256;
   }
   w->pc.h = d->phys.dt / (float)d->phys.substeps;
@@ -482,6 +487,7 @@ extern "C" int vuda_create_world(const vuda_world_desc* d, const vuda_allocator*
   w->env_active.assign(w->cap_envs, 0);
   w->cam_host.assign(w->cap_cams, CamDev{});
   w->step_ev.assign(w->cap_envs, -1);
+  w->setup_ok.assign(w->cap_envs, 0);
   w->render_ev[0].assign(w->cap_envs, -1);
   w->render_ev[1].assign(w->cap_envs, -1);
   w->slots.init(w->cap_envs);
@@ -717,7 +723,7 @@ int vuda_world::get_list(int phase, int32_t lo, int32_t hi, const WorkList** out
   L.n = (int32_t)ids.size();
   L.n_groups = 0;
   if (phase == VUDA_PHASE_RENDER && !ids.empty()) {
-    // Tile-kernel jobs of 4 tiles.  Workgroups are handed to the 8 XCDs
+    // Tile-kernel jobs of 4 tiles of a row.  Workgroups are handed to the 8 XCDs
     // round-robin, so the setup workgroup of image i runs on XCD i mod 8;
     // its tiles get job indices of the same residue, where that XCD's L2
     // still holds the image's records and bins.
@@ -725,8 +731,9 @@ int vuda_world::get_list(int phase, int32_t lo, int32_t hi, const WorkList** out
     std::vector<std::vector<int2>> per(kXcd);
     for (size_t i = 0; i < ids.size(); ++i) {
       const CamDev& cd = cam_host[ids[i]];
-      const int32_t nt = tiles_of(cd.w, cd.h);
-      for (int32_t t = 0; t < nt; t += 4) per[i % kXcd].push_back(make_int2(ids[i], t));
+      const int32_t ntx = (cd.w + kTile - 1) / kTile, nty = (cd.h + kTile - 1) / kTile;
+      for (int32_t ty = 0; ty < nty; ++ty)
+        for (int32_t tx = 0; tx < ntx; tx += 4) per[i % kXcd].push_back(make_int2(ids[i], tx | (ty << 16)));
     }
     size_t len = 0;
     for (auto& v : per) len = std::max(len, v.size());
@@ -784,7 +791,7 @@ int vuda_world::enqueue_physics(const WorkList& L, int parity, hipStream_t s) {
   return VUDA_OK;
 }
 
-int vuda_world::raster_launch_of(const WorkList& L, int parity, RasterLaunch* out) {
+int vuda_world::raster_launch_of(const WorkList& L, int parity, int32_t* queue, RasterLaunch* out) {
   RasterLaunch rl;
   rl.work = L.dptr;
   rl.n_work = L.n;
@@ -798,7 +805,7 @@ int vuda_world::raster_launch_of(const WorkList& L, int parity, RasterLaunch* ou
   rl.threads = tune.raster_threads;
   rl.bin_limit = tune.rec_cap;
   rl.persistent = tune.raster_persistent;
-  rl.queue = queues + 1;
+  rl.queue = queue;
   const size_t lds = raster_lds_bytes(rl);
   const size_t kLdsMax = 160 * 1024;
   if (lds > kLdsMax)
@@ -811,66 +818,66 @@ int vuda_world::raster_launch_of(const WorkList& L, int parity, RasterLaunch* ou
   return VUDA_OK;
 }
 
-static hipError_t record_mark(void* ev, hipStream_t s) { return hipEventRecord((hipEvent_t)ev, s); }
-
-int vuda_world::enqueue_raster(const WorkList& L, int parity, hipStream_t s, hipEvent_t mid) {
+int vuda_world::enqueue_kernel(int kind, const WorkList& L, int parity, hipStream_t s, int32_t* queue) {
+  if (kind == kKernelPhysics) return enqueue_physics(L, parity, s);
   RasterLaunch rl;
-  int rc = raster_launch_of(L, parity, &rl);
+  int rc = raster_launch_of(L, parity, queue, &rl);
   if (rc) return rc;
-  HIPCHK(launch_raster(dev, rl, s, mid ? record_mark : nullptr, (void*)mid));
+  if (kind == kKernelSetup) HIPCHK(launch_raster_setup(dev, rl, s));
+  else HIPCHK(launch_raster_tiles(dev, rl, s));
   return VUDA_OK;
 }
 
-// Launch one phase, through a captured graph when graph mode is on, between
-// timing events when timing is on.
-int vuda_world::run_phase(int phase, const WorkList& L, int parity, int32_t lo, int32_t hi,
-                          hipStream_t s) {
-  if (!tune.timing) return launch_phase(phase, L, parity, lo, hi, s, nullptr);
-  const int k = phase == VUDA_PHASE_STEP ? 0 : 1;
-  std::vector<hipEvent_t>& ev = tev[k];
-  const size_t i = 3 * tev_used[k];
-  while (ev.size() < i + 3) {
-    hipEvent_t e;
-    HIPCHK(hipEventCreate(&e));
-    ev.push_back(e);
-  }
-  // the mark between a render's two kernels; otherwise it coincides with the end
-  const bool mid = phase == VUDA_PHASE_RENDER && !tune.graphs;
-  HIPCHK(hipEventRecord(ev[i], s));
-  int rc = launch_phase(phase, L, parity, lo, hi, s, mid ? ev[i + 1] : nullptr);
-  if (rc) return rc;
-  if (!mid) HIPCHK(hipEventRecord(ev[i + 1], s));
-  HIPCHK(hipEventRecord(ev[i + 2], s));
-  ++tev_used[k];
-  return VUDA_OK;
-}
-
-int vuda_world::launch_phase(int phase, const WorkList& L, int parity, int32_t lo, int32_t hi,
-                             hipStream_t s, hipEvent_t mid) {
-  if (!tune.graphs) {
-    return phase == VUDA_PHASE_STEP ? enqueue_physics(L, parity, s) : enqueue_raster(L, parity, s, mid);
-  }
-  const auto key = std::make_tuple(phase, lo, hi, parity);
-  auto it = graphs.find(key);
-  if (it == graphs.end()) {
-    hipStream_t cs = capture_stream();
-    if (!cs) return fail(VUDA_EHIP, "capture stream");
-    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    int rc = phase == VUDA_PHASE_STEP ? enqueue_physics(L, parity, cs) : enqueue_raster(L, parity, cs, nullptr);
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(cs, &g);
-    if (rc) {
-      if (g) (void)hipGraphDestroy(g);
-      return rc;
+// Launch one kernel over a work list, through a captured graph when graph mode
+// is on, between timing events when timing is on.
+int vuda_world::run_kernel(int kind, const WorkList& L, int parity, int32_t lo, int32_t hi, hipStream_t s,
+                           int32_t* queue) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (tune.timing) {
+    std::vector<hipEvent_t>& ev = tev[kind];
+    const size_t i = 2 * tev_used[kind];
+    while (ev.size() < i + 2) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      ev.push_back(e);
     }
-    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-    hipGraphExec_t ge = nullptr;
-    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
-    it = graphs.emplace(key, ge).first;
+    e0 = ev[i];
+    e1 = ev[i + 1];
+    HIPCHK(hipEventRecord(e0, s));
   }
-  HIPCHK(hipGraphLaunch(it->second, s));
+  int rc = VUDA_OK;
+  if (!tune.graphs) {
+    rc = enqueue_kernel(kind, L, parity, s, queue);
+  } else {
+    // the queue slot is part of the launch: it tells the two setup launch sites apart
+    const int slot = queue ? (int)(queue - queues) : 0;
+    const auto key = std::make_tuple(4 * kind + slot, lo, hi, parity);
+    auto it = graphs.find(key);
+    if (it == graphs.end()) {
+      hipStream_t cs = capture_stream();
+      if (!cs) return fail(VUDA_EHIP, "capture stream");
+      HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      rc = enqueue_kernel(kind, L, parity, cs, queue);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(cs, &g);
+      if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+      hipGraphExec_t ge = nullptr;
+      e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+      it = graphs.emplace(key, ge).first;
+    }
+    HIPCHK(hipGraphLaunch(it->second, s));
+  }
+  if (rc) return rc;
+  if (e1) {
+    HIPCHK(hipEventRecord(e1, s));
+    ++tev_used[kind];
+  }
   return VUDA_OK;
 }
 
@@ -893,21 +900,34 @@ extern "C" int vuda_step(vuda_world* w, int32_t lo, int32_t hi, int32_t nsteps) 
   const WorkList* L;
   rc = w->get_list(VUDA_PHASE_STEP, lo, hi, &L);
   if (rc) return rc;
+  // With presetup the raster setup of the new state (vertex transform,
+  // triangle setup, binning -- it reads nothing but that state) follows the
+  // last physics step on this stream, and the render phase keeps the pixels.
+  const WorkList* LR = nullptr;
+  if (w->tune.presetup) {
+    rc = w->get_list(VUDA_PHASE_RENDER, lo, hi, &LR);
+    if (rc) return rc;
+  }
   hipStream_t s = w->s_sim;
   for (int t = 0; t < nsteps; ++t) {
     const int p = (parity + t) & 1;
     if (w->mode != 0) {
-      // WAR: the renders that read the buffer this step overwrites.  Earlier
-      // steps are on this same stream (RAW is implicit); events of one stream
-      // complete in order, so the latest one covers the others.
+      // WAR: the renders that read the state buffer (and raster scratch)
+      // this step overwrites.  Earlier steps are on this same stream (RAW is
+      // implicit); events of one stream complete in order, so the latest one
+      // covers the others.
       int64_t last = -1;
       const int64_t* rev = w->render_ev[p ^ 1].data();
       for (int32_t e = lo; e < hi; ++e) last = rev[e] > last ? rev[e] : last;
       rc = w->wait_event(s, last);
       if (rc) return rc;
     }
-    rc = w->run_phase(VUDA_PHASE_STEP, *L, p, lo, hi, s);
+    rc = w->run_kernel(kKernelPhysics, *L, p, lo, hi, s, w->queues);
     if (rc) return rc;
+    if (LR && t == nsteps - 1) {
+      rc = w->run_kernel(kKernelSetup, *LR, p ^ 1, lo, hi, s, w->queues + 1);
+      if (rc) return rc;
+    }
     int64_t id = -1;
     if (w->mode != 0) {
       rc = w->new_event(s, &id);
@@ -919,6 +939,7 @@ extern "C" int vuda_step(vuda_world* w, int32_t lo, int32_t hi, int32_t nsteps) 
       w->step_ev[e] = id;
     }
   }
+  for (int32_t e = lo; e < hi; ++e) w->setup_ok[e] = LR ? 1 : 0;
   return VUDA_OK;
 }
 
@@ -935,14 +956,21 @@ extern "C" int vuda_render(vuda_world* w, int32_t lo, int32_t hi) {
   if (rc) return rc;
   hipStream_t s = w->s_render;
   if (w->mode != 0) {
-    // RAW: the latest step that wrote the state rendered
+    // RAW: the latest step that wrote the state rendered (and its setup)
     int64_t last = -1;
     const int64_t* sev = w->step_ev.data();
     for (int32_t e = lo; e < hi; ++e) last = sev[e] > last ? sev[e] : last;
     rc = w->wait_event(s, last);
     if (rc) return rc;
   }
-  rc = w->run_phase(VUDA_PHASE_RENDER, *L, parity, lo, hi, s);
+  bool need_setup = false;
+  for (int32_t e = lo; e < hi; ++e) need_setup |= w->env_active[e] && !w->setup_ok[e];
+  if (need_setup) {
+    rc = w->run_kernel(kKernelSetup, *L, parity, lo, hi, s, w->queues + 2);
+    if (rc) return rc;
+    for (int32_t e = lo; e < hi; ++e) w->setup_ok[e] = 1;
+  }
+  rc = w->run_kernel(kKernelTiles, *L, parity, lo, hi, s, nullptr);
   if (rc) return rc;
   if (w->mode != 0) {
     int64_t id;
@@ -1150,6 +1178,8 @@ extern "C" int vuda_load_state(vuda_world* w, int32_t lo, int32_t hi, const floa
                        hipMemcpyHostToDevice));
     pos += r.nb;
   }
+  // the reloaded state has no raster setup yet
+  for (int32_t e = lo; e < hi; ++e) w->setup_ok[e] = 0;
   // clear sticky flags of the reloaded envs
   std::vector<uint32_t> zero(hi - lo, 0u);
   if (hi > lo) HIPCHK(hipMemcpy(w->dev.env_flags + lo, zero.data(), 4 * zero.size(), hipMemcpyHostToDevice));
@@ -1207,6 +1237,7 @@ extern "C" int vuda_admit(vuda_world* w, const vuda_env_batch* b, int32_t parity
     return rc;
   }
   for (int e = 0; e < b->n_envs; ++e) {
+    w->setup_ok[e0 + e] = 0;
     w->step_ev[e0 + e] = -1;
     w->render_ev[0][e0 + e] = -1;
     w->render_ev[1][e0 + e] = -1;
@@ -1235,7 +1266,7 @@ extern "C" int vuda_release(vuda_world* w, int32_t first, int32_t n) {
     p0 = c0.pix_off;
     np = c1.pix_off + (int64_t)c1.w * c1.h - p0;
     r0 = c0.rs_off / 256;
-    nr = (c1.rs_off + rs_layout(c1.n_tris, tiles_of(c1.w, c1.h)).total) / 256 - r0;
+    nr = (c1.rs_off + 2 * rs_layout(c1.n_tris, tiles_of(c1.w, c1.h)).total) / 256 - r0;
   }
   std::vector<EnvDev> empty(n, EnvDev{});
   HIPCHK(hipMemcpy(w->dev.envs + first, empty.data(), sizeof(EnvDev) * n, hipMemcpyHostToDevice));
@@ -1248,6 +1279,7 @@ extern "C" int vuda_release(vuda_world* w, int32_t first, int32_t n) {
   w->vertspace.release(d0.vert_map, d1.vert_map + map_round(d1.n_verts) - d0.vert_map);
   w->slots.release(first, n);
   for (int32_t e = first; e < first + n; ++e) {
+    w->setup_ok[e] = 0;
     w->env_active[e] = 0;
     w->env_host[e] = EnvDev{};
   }
@@ -1293,6 +1325,10 @@ extern "C" int vuda_set_tuning(vuda_world* w, int32_t key, int32_t value) {
       if (value < 0 || value > 1) return fail(VUDA_EINVAL, "timing %d", value);
       w->tune.timing = value != 0;
       return VUDA_OK;  // placement of the events only: graphs stay valid
+    case VUDA_TUNE_PRESETUP:
+      if (value < 0 || value > 1) return fail(VUDA_EINVAL, "presetup %d", value);
+      w->tune.presetup = value != 0;
+      return VUDA_OK;
     default:
       return fail(VUDA_EINVAL, "tuning key %d", key);
   }
@@ -1312,32 +1348,30 @@ extern "C" int vuda_get_tuning(vuda_world* w, int32_t key, int32_t* value) {
     case VUDA_TUNE_PHYS_PRIORITY: *value = w->tune.phys_prio; break;
     case VUDA_TUNE_BROADPHASE: *value = w->tune.broadphase; break;
     case VUDA_TUNE_TIMING: *value = w->tune.timing ? 1 : 0; break;
+    case VUDA_TUNE_PRESETUP: *value = w->tune.presetup ? 1 : 0; break;
     default: return fail(VUDA_EINVAL, "tuning key %d", key);
   }
   return VUDA_OK;
 }
 
-extern "C" int vuda_phase_times(vuda_world* w, int32_t phase, int32_t part, int64_t* launches,
-                                double* total_ms, double* max_ms) {
+extern "C" int vuda_kernel_times(vuda_world* w, int32_t kernel, int64_t* launches, double* total_ms,
+                                 double* max_ms) {
   if (!w) return fail(VUDA_EINVAL, "null world");
-  if (phase != VUDA_PHASE_STEP && phase != VUDA_PHASE_RENDER) return fail(VUDA_EINVAL, "phase %d", phase);
-  if (part < 0 || part > 2 || (phase == VUDA_PHASE_STEP && part == 2))
-    return fail(VUDA_EINVAL, "part %d of phase %d", part, phase);
-  const int k = phase == VUDA_PHASE_STEP ? 0 : 1;
+  if (kernel < VUDA_KERNEL_PHYSICS || kernel > VUDA_KERNEL_RASTER_TILES) return fail(VUDA_EINVAL, "kernel %d", kernel);
+  const int k = kernel - VUDA_KERNEL_PHYSICS;
   const size_t n = w->tev_used[k];
-  const int a = part == 2 ? 1 : 0, b = part == 1 ? 1 : 2;
   double sum = 0.0, mx = 0.0;
   if (n) {
     HIPCHK(hipSetDevice(w->device));
-    HIPCHK(hipEventSynchronize(w->tev[k][3 * n - 1]));
+    HIPCHK(hipEventSynchronize(w->tev[k][2 * n - 1]));
     for (size_t i = 0; i < n; ++i) {
       float ms = 0.0f;
-      HIPCHK(hipEventElapsedTime(&ms, w->tev[k][3 * i + a], w->tev[k][3 * i + b]));
+      HIPCHK(hipEventElapsedTime(&ms, w->tev[k][2 * i], w->tev[k][2 * i + 1]));
       sum += ms;
       mx = ms > mx ? ms : mx;
     }
   }
-  if (part == 0) w->tev_used[k] = 0;
+  w->tev_used[k] = 0;
   if (launches) *launches = (int64_t)n;
   if (total_ms) *total_ms = sum;
   if (max_ms) *max_ms = mx;

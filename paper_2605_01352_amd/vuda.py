@@ -24,6 +24,8 @@ TUNE_RASTER_THREADS, TUNE_REC_CAP, TUNE_PHYS_PERSISTENT, TUNE_RASTER_PERSISTENT,
 TUNE_PHYS_PRIORITY = 6
 TUNE_BROADPHASE = 7
 TUNE_TIMING = 8
+TUNE_PRESETUP = 9
+KERNEL_PHYSICS, KERNEL_RASTER_SETUP, KERNEL_RASTER_TILES = 1, 2, 3
 GROUND = 0xFFFF
 
 EXPORTS = [
@@ -33,7 +35,7 @@ EXPORTS = [
     "vuda_probe_placement", "vuda_strerror", "vuda_last_error_message", "vuda_run",
     "vuda_autotune", "vuda_serve_create", "vuda_serve_destroy", "vuda_serve_submit",
     "vuda_serve_tick", "vuda_serve_completed", "vuda_serve_result", "vuda_serve_stats",
-    "vuda_serve_world", "vuda_phase_times",
+    "vuda_serve_world", "vuda_kernel_times",
 ]
 SCHED_SERIAL, SCHED_INTERSTEP, SCHED_INTERTRAJ = 0, 1, 2
 SCHED_NAMES = {SCHED_SERIAL: "serial", SCHED_INTERSTEP: "interstep", SCHED_INTERTRAJ: "intertraj"}
@@ -84,7 +86,7 @@ class TuneResult(C.Structure):
                 ("raster_persistent", C.c_int32), ("phys_priority", C.c_int32),
                 ("broadphase", C.c_int32), ("cosched_env_steps_per_s", C.c_double),
                 ("serial_env_steps_per_s", C.c_double), ("serial_raster_threads", C.c_int32),
-                ("serial_phys_persistent", C.c_int32), ("trials", C.c_int32)]
+                ("serial_phys_persistent", C.c_int32), ("trials", C.c_int32), ("presetup", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -282,18 +284,12 @@ class World:
         check(lib().vuda_get_tuning(self._w, key, C.byref(v)))
         return v.value
 
-    def phase_times(self, phase: int) -> Dict:
-        """Launch count, total and max duration (ms) recorded with TUNE_TIMING
-        on since the previous call for this phase: the whole launch, and per
-        kernel ("parts": first kernel, raster tile kernel)."""
-        out = {}
-        parts = (0, 1, 2) if phase == PHASE_RENDER else (0, 1)
-        # part 0 last: its read starts a new count
-        for part in reversed(parts):
-            n, tot, mx = C.c_int64(), C.c_double(), C.c_double()
-            check(lib().vuda_phase_times(self._w, phase, part, C.byref(n), C.byref(tot), C.byref(mx)))
-            out[part] = {"launches": n.value, "total_ms": tot.value, "max_ms": mx.value}
-        return {**out[0], "parts": [out[p] for p in parts[1:]]}
+    def kernel_times(self, kernel: int) -> Dict:
+        """Launch count, total and max duration (ms) of a kernel (KERNEL_*)
+        recorded with TUNE_TIMING on since the previous call for it."""
+        n, tot, mx = C.c_int64(), C.c_double(), C.c_double()
+        check(lib().vuda_kernel_times(self._w, kernel, C.byref(n), C.byref(tot), C.byref(mx)))
+        return {"launches": n.value, "total_ms": tot.value, "max_ms": mx.value}
 
     def stream(self, phase: int) -> int:
         p = C.c_void_p()

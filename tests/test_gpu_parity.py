@@ -126,7 +126,8 @@ def test_tuning_knobs_do_not_change_outputs():
     for knobs in ({}, {vuda.TUNE_RASTER_THREADS: 64}, {vuda.TUNE_RASTER_THREADS: 1024},
                   {vuda.TUNE_REC_CAP: 64}, {vuda.TUNE_REC_CAP: 5000}, {vuda.TUNE_PHYS_PERSISTENT: 7, vuda.TUNE_RASTER_PERSISTENT: 5},
                   {vuda.TUNE_GRAPHS: 1}, {vuda.TUNE_BROADPHASE: 1}, {vuda.TUNE_BROADPHASE: 2},
-                  {vuda.TUNE_PHYS_PRIORITY: 3}):
+                  {vuda.TUNE_PHYS_PRIORITY: 3}, {vuda.TUNE_PRESETUP: 0},
+                  {vuda.TUNE_PRESETUP: 0, vuda.TUNE_GRAPHS: 1}, {vuda.TUNE_RASTER_PERSISTENT: 3}):
         with vuda.World(s) as w:
             for k, v in knobs.items():
                 w.set_tuning(k, v)

@@ -14,9 +14,10 @@
 //      (snapped vertices in edge order, depths, 1/area, key and flat Lambert
 //      colour) and the tiles of its box are counted with LDS atomics;
 //   5. a workgroup prefix scan of the counts places each 16x16 tile's bin; a
-//      scatter pass classifies each triangle against every tile of its box
-//      (exact corner test of the edge functions) and appends its record id,
-//      flagged when the triangle covers the whole tile.
+//      scatter pass appends each triangle's record id to the bins of the
+//      tiles of its box, after an exact corner test of the edge functions
+//      where its box in the tile is large, flagged when the triangle covers
+//      the whole tile.
 // raster_tile_kernel, one wave per tile and four tiles per workgroup; a lane
 //   owns four horizontally adjacent pixels.  The bin is read in batches of 64
 //   records.  Small triangles (at most 64 pixels of their box in the tile)
@@ -281,13 +282,18 @@ __device__ __forceinline__ void store_rec(int4* recs, int r, const Tri& t, uint3
 }
 
 // Append record r to the bin of tile (tx, ty) unless its edges miss the tile;
-// flag the entry when the triangle covers every pixel of the tile.
+// flag the entry when the triangle covers every pixel of the tile.  Only a
+// box of more than kSmallMax pixels in the tile is classified (the tile
+// kernel rasterizes it pixel by pixel over the whole tile, where the flag and
+// the rejection pay); a smaller one is expanded into its box's pixels there
+// anyway.
 __device__ __forceinline__ void bin_tile(const Tri& t, int r, int tx, int ty, int x0, int x1, int y0,
                                          int y1, bool classify, int Wd, int Ht, int ntx,
                                          const int32_t* toff, int32_t* tfill, uint16_t* bins) {
   const int bx0 = max(x0, tx * kTile), bx1 = min(x1, tx * kTile + kTile - 1);
   const int by0 = max(y0, ty * kTile), by1 = min(y1, ty * kTile + kTile - 1);
-  const int cls = classify ? tile_class(t.X, t.Y, bx0, bx1, by0, by1) : 1;
+  const bool large = (bx1 - bx0 + 1) * (by1 - by0 + 1) > kSmallMax;
+  const int cls = (classify && large) ? tile_class(t.X, t.Y, bx0, bx1, by0, by1) : 1;
   if (cls == 0) return;
   const bool whole = bx0 == tx * kTile && by0 == ty * kTile &&
                      bx1 == min(Wd - 1, tx * kTile + kTile - 1) &&

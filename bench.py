@@ -211,12 +211,23 @@ def main():
             f"co-scheduled {dt_c / args.profile * 1e6:.1f} us/step")
         w.close()
         return
-    w.set_tuning(vuda.TUNE_TIMING, 1)
+    def kernel_run(sched):
+        """The same timed region again with a HIP event pair around every
+        launch: the per-kernel launch durations of that region.  The events
+        cost throughput of their own, so the headline figures come from the
+        runs without them."""
+        w.set_tuning(vuda.TUNE_TIMING, 1)
+        timed(torch, w, sched, n_envs, args.steps, args.warmup, st0,
+              after_warmup=lambda: launch_stats(vuda, w))
+        st = launch_stats(vuda, w)  # launches of the timed region
+        w.set_tuning(vuda.TUNE_TIMING, 0)
+        return st
+
+    w.set_tuning(vuda.TUNE_TIMING, 0)
     results = {}
     w.cosched(0.0)
-    results["serialized"] = timed(torch, w, "serial", n_envs, args.steps, args.warmup, st0,
-                                  after_warmup=lambda: launch_stats(vuda, w))
-    alone = launch_stats(vuda, w)  # launches of the timed region
+    results["serialized"] = timed(torch, w, "serial", n_envs, args.steps, args.warmup, st0)
+    alone = kernel_run("serial")
     presetup = w.get_tuning(vuda.TUNE_PRESETUP) != 0
     Ts, Tr = phase_seconds(alone, args.steps, presetup)
     ser = n_envs * args.steps / results["serialized"]
@@ -239,10 +250,9 @@ def main():
     sched, split = best.split("@")
     split = float(split)
     w.cosched(split)
-    dt = timed(torch, w, sched, n_envs, args.steps, args.warmup, st0,
-               after_warmup=lambda: launch_stats(vuda, w))
-    live = launch_stats(vuda, w)  # launches of the timed region
+    dt = timed(torch, w, sched, n_envs, args.steps, args.warmup, st0)
     value = n_envs * args.steps / dt
+    live = kernel_run(sched)
     log(f"co-scheduled ({best}): {value:.0f} env-steps/s, {value / ser:.3f}x serialized")
 
     # roofline of the dominant kernel: algorithmic bytes per launch over its

@@ -11,9 +11,11 @@
 //      pair (i < j) in a per-row bitset;
 //   3. candidate rows are compacted into a pair list sorted by (i, j) with a
 //      workgroup prefix scan of the row popcounts;
-//   4. narrowphase over the list, one pair per lane; contacts are compacted
-//      (wave ballot + prefix) into a contact list that stays sorted, holding
-//      the pair's summed force and both bodies' torques;
+//   4. narrowphase: a pair with a sphere (one contact point at most) on one
+//      lane; a cube-cube pair's 16 vertex-in-box tests on 16 lanes, then its
+//      point terms summed in point order, one component per lane; likewise
+//      the 8 corners of a cube near the ground.  A pair in contact gets a
+//      slot holding its summed force and both bodies' torques;
 //   5. each body gathers its pairs in sorted order (pairs (i, b) for i < b,
 //      then (b, j), then the ground), so every sum is formed in a fixed
 //      order independent of scheduling;
@@ -74,7 +76,8 @@ template <int NW>
 struct PhysLDS {
   static constexpr int N = 64 * NW;
   static constexpr int CAPC = 8 * N;  // candidate pairs
-  static constexpr int CAPK = 4 * N;  // contact pairs
+  static_assert(CAPC <= 1024 && N <= 2048, "cube-cube queue packing");
+  static constexpr int CAPK = 4 * N;  // pairs in contact
   float4 pr[N];  // position and bounding radius, for the all-pairs broadphase
   float p[3][N];
   float v[3][N];
@@ -87,14 +90,20 @@ struct PhysLDS {
   uint64_t rowCand[N][NW];
   uint64_t rowC[N][NW];
   uint64_t colC[N][NW];
-  int32_t kstart[N];
-  int32_t gflag[N];
-  uint32_t cand[CAPC];
-  float kres[9][CAPK];  // SF xyz, Ti xyz, Tj xyz of each contact pair
+  int32_t cstart[N];      // candidate-list start of each row
+  int32_t gflag[N];       // body touches the ground
+  uint32_t cand[CAPC];    // candidate pairs i | j << 16, sorted
+  uint16_t kslot[CAPC];   // slot of each candidate in contact
+  uint32_t ccl[CAPC];     // candidates whose bodies are both cubes: k | i << 10 | j << 21
+  int32_t gcl[N];         // cubes closer to the ground than their bounding radius
+  float kres[9][CAPK];    // SF xyz, Ti xyz, Tj xyz of each pair in contact
+  alignas(16) float stage[9][N];  // one contact point's terms per lane, before the ordered sum
+  float gres[6][N];       // ground force and torque of each body
   int32_t scan[NW + 1];
   float red[NW];
   int32_t flag;
   int32_t work;
+  int32_t kcnt, ncc, ngc;
 };
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
@@ -187,11 +196,15 @@ struct PairAcc {
   int npts;
 };
 
-// Add the force of one contact point; a_first: body A (pushed along +n) is
-// the pair's first body.
-__device__ __forceinline__ void add_point(PairAcc& acc, const Point& pt, bool a_first, f3 pi,
-                                          f3 vi, f3 wi, f3 pj, f3 vj, f3 wj, bool ground,
-                                          const PhysConsts& pc) {
+// Force of one contact point on the pair's first body and the torques it
+// exerts on both bodies; a_first: body A (pushed along +n) is the pair's
+// first body.
+struct PointTerms {
+  f3 Fi, ti, tj;
+};
+__device__ __forceinline__ PointTerms point_terms(const Point& pt, bool a_first, f3 pi, f3 vi, f3 wi,
+                                                  f3 pj, f3 vj, f3 wj, bool ground,
+                                                  const PhysConsts& pc) {
   const f3 pa = a_first ? pi : pj, va = a_first ? vi : vj, wa = a_first ? wi : wj;
   const f3 pb = a_first ? pj : pi, vb = a_first ? vj : vi, wb = a_first ? wj : wi;
   const f3 velA = add(va, cross(wa, sub(pt.xc, pa)));
@@ -206,31 +219,28 @@ __device__ __forceinline__ void add_point(PairAcc& acc, const Point& pt, bool a_
   float f = pc.k * pt.delta - pc.c * vn;
   if (f < 0.0f) f = 0.0f;
   const f3 F = mul(pt.n, f);
-  const f3 Fi = a_first ? F : neg(F);
-  acc.SF = add(acc.SF, Fi);
-  acc.Ti = add(acc.Ti, cross(sub(pt.xc, pi), Fi));
-  if (!ground) acc.Tj = add(acc.Tj, cross(sub(pt.xc, pj), neg(Fi)));
+  PointTerms r;
+  r.Fi = a_first ? F : neg(F);
+  r.ti = cross(sub(pt.xc, pi), r.Fi);
+  r.tj = ground ? mk(0.0f, 0.0f, 0.0f) : cross(sub(pt.xc, pj), neg(r.Fi));
+  return r;
+}
+
+// Add the force of one contact point to its pair's sums.
+__device__ __forceinline__ void add_point(PairAcc& acc, const Point& pt, bool a_first, f3 pi,
+                                          f3 vi, f3 wi, f3 pj, f3 vj, f3 wj, bool ground,
+                                          const PhysConsts& pc) {
+  const PointTerms t = point_terms(pt, a_first, pi, vi, wi, pj, vj, wj, ground, pc);
+  acc.SF = add(acc.SF, t.Fi);
+  acc.Ti = add(acc.Ti, t.ti);
+  if (!ground) acc.Tj = add(acc.Tj, t.tj);
   acc.npts += 1;
 }
 
-// Corner k of a cube (sign + on axis t iff bit t of k is set): p + R (+-a,
-// +-a, +-a), from the products R[k] * a computed once per cube.  The product
-// with -a is the negated product with a, so each corner is bit-identical to
-// evaluating R w with w = (+-a, +-a, +-a) row by row.
-struct CubeProducts {
-  float m[9];
-};
-__device__ __forceinline__ CubeProducts cube_products(const M3& R, float a) {
-  CubeProducts c;
-#pragma unroll
-  for (int k = 0; k < 9; ++k) c.m[k] = R.m[k] * a;
-  return c;
-}
-__device__ __forceinline__ f3 corner_of(f3 p, const CubeProducts& c, int k) {
-  const float sx = (k & 1) ? 1.0f : -1.0f, sy = (k & 2) ? 1.0f : -1.0f, sz = (k & 4) ? 1.0f : -1.0f;
-  const f3 r = mk((sx * c.m[0] + sy * c.m[1]) + sz * c.m[2], (sx * c.m[3] + sy * c.m[4]) + sz * c.m[5],
-                  (sx * c.m[6] + sy * c.m[7]) + sz * c.m[8]);
-  return add(p, r);
+// Corner k of a cube (sign + on axis t iff bit t of k is set): p + R w with
+// w = (+-a, +-a, +-a).
+__device__ __forceinline__ f3 corner_vertex(f3 p, const M3& R, float a, int k) {
+  return add(p, rot(R, mk((k & 1) ? a : -a, (k & 2) ? a : -a, (k & 4) ? a : -a)));
 }
 
 // argmin over axes of (a - |u_axis|), lowest axis on ties
@@ -276,7 +286,7 @@ __device__ __forceinline__ bool sphere_cube(f3 c, float r, f3 p, const M3& R, fl
   return true;
 }
 
-// Narrowphase + force sum of body pair (i, j), i < j.
+// Narrowphase + force sum of body pair (i, j), i < j, one of them a sphere.
 template <int NW>
 __device__ __noinline__ PairAcc pair_forces(const PhysLDS<NW>& s, int i, int j,
                                             const PhysConsts& pc) {
@@ -308,63 +318,46 @@ __device__ __noinline__ PairAcc pair_forces(const PhysLDS<NW>& s, int i, int j,
   } else if (tj == 0) {
     const M3 Ri = ldsR(s, i);
     if (sphere_cube(pj, sj, pi, Ri, si, &pt)) add_point(acc, pt, false, pi, vi, wi, pj, vj, wj, false, pc);
-  } else {
-    const M3 Ri = ldsR(s, i), Rj = ldsR(s, j);
-    // vertices of i inside j (A = i), then vertices of j inside i (A = j)
-#pragma unroll 1
-    for (int side = 0; side < 2; ++side) {
-      const f3 pa = side ? pj : pi, pb = side ? pi : pj;
-      const M3& Ra = side ? Rj : Ri;
-      const M3& Rb = side ? Ri : Rj;
-      const float aa = side ? sj : si, ab = side ? si : sj;
-      const CubeProducts ca = cube_products(Ra, aa);
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const f3 vtx = corner_of(pa, ca, k);
-        const f3 u = rotT(Rb, sub(vtx, pb));
-        if (fabsf(u.x) < ab && fabsf(u.y) < ab && fabsf(u.z) < ab) {
-          float dm;
-          const int m = min_axis(u, ab, &dm);
-          pt.n = rot(Rb, axis_unit(m, pick(u, m) >= 0.0f ? 1.0f : -1.0f));
-          pt.delta = dm;
-          pt.xc = vtx;
-          add_point(acc, pt, side == 0, pi, vi, wi, pj, vj, wj, false, pc);
-        }
-      }
-    }
   }
   return acc;
 }
 
-// Ground contact of one body (its own lane).
-__device__ __forceinline__ PairAcc ground_forces(int type, float a, f3 p, f3 v, f3 w, const M3& R,
-                                                 const PhysConsts& pc) {
-  PairAcc acc;
-  acc.SF = mk(0.0f, 0.0f, 0.0f);
-  acc.Ti = acc.SF;
-  acc.Tj = acc.SF;
-  acc.npts = 0;
-  const f3 z3 = acc.SF;
-  Point pt;
-  pt.n = mk(0.0f, 0.0f, 1.0f);
-  if (type == 0) {
-    if (p.z < a) {
-      pt.delta = a - p.z;
-      pt.xc = mk(p.x, p.y, p.z - a);
-      add_point(acc, pt, true, p, v, w, z3, z3, z3, true, pc);
-    }
-  } else {
-    const CubeProducts c = cube_products(R, a);
+// Corner k of cube A strictly inside cube B: the contact point, pushed out
+// of B along the normal of B's nearest face.
+__device__ __forceinline__ bool corner_in_box(f3 pa, const M3& Ra, float aa, int k, f3 pb, const M3& Rb,
+                                              float ab, Point* pt) {
+  const f3 vtx = corner_vertex(pa, Ra, aa, k);
+  const f3 u = rotT(Rb, sub(vtx, pb));
+  if (!(fabsf(u.x) < ab && fabsf(u.y) < ab && fabsf(u.z) < ab)) return false;
+  float dm;
+  const int m = min_axis(u, ab, &dm);
+  pt->n = rot(Rb, axis_unit(m, pick(u, m) >= 0.0f ? 1.0f : -1.0f));
+  pt->delta = dm;
+  pt->xc = vtx;
+  return true;
+}
+
+// Lanes of this wave below the calling lane whose bit is set in m.
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Ordered sum, over the set bits l of the group mask gm (ascending), of
+// stage[c][base + l] for l < G: the terms of one pair's contact points in
+// point order.  The G values are loaded first, then added where selected.
+template <int G, int NW>
+__device__ __forceinline__ float ordered_sum(const PhysLDS<NW>& s, int c, int base, uint32_t gm) {
+  float v[G];
+  const float4* src = (const float4*)&s.stage[c][base];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const f3 vtx = corner_of(p, c, k);
-      if (vtx.z < 0.0f) {
-        pt.delta = -vtx.z;
-        pt.xc = vtx;
-        add_point(acc, pt, true, p, v, w, z3, z3, z3, true, pc);
-      }
-    }
+  for (int l = 0; l < G / 4; ++l) {
+    const float4 x = src[l];
+    v[4 * l] = x.x; v[4 * l + 1] = x.y; v[4 * l + 2] = x.z; v[4 * l + 3] = x.w;
   }
+  float acc = 0.0f;
+#pragma unroll
+  for (int l = 0; l < G; ++l)
+    if ((gm >> l) & 1u) acc = acc + v[l];
   return acc;
 }
 
@@ -446,7 +439,12 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
       s.rowC[tid][q] = 0ull;
       s.colC[tid][q] = 0ull;
     }
-    if (tid == 0) s.flag = 0;
+    if (tid == 0) {
+      s.flag = 0;
+      s.kcnt = 0;
+      s.ncc = 0;
+      s.ngc = 0;
+    }
     // 2. broadphase.  The candidate set is exactly {(i, j): i < j,
     // |p_i - p_j|^2 <= (R_i + R_j)^2}; two ways produce it.  All-pairs: every
     // lane tests every body, reading it with one broadcast LDS load (no
@@ -468,22 +466,33 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
       // n <= 32).  Every unordered pair is one rotation away from one of its
       // bodies; at r = n/2 (n even) both see it and the lower one keeps it.
       // The test is symmetric in the two bodies, bit for bit.
+      // Eight rotations per batch: their loads issue back to back.
       const int groups = n <= 32 ? 2 : 1;
       const int i = n <= 32 ? (tid & 31) : tid;
       const int g = n <= 32 ? (tid >> 5) : 0;
       const int R = n / 2;
       if (i < n) {
         const float4 me = s.pr[i];
-        for (int r = 1 + g; r <= R; r += groups) {
-          int j = i + r;
-          if (j >= n) j -= n;
-          if (2 * r == n && i > j) continue;
-          const float4 o = s.pr[j];
-          const f3 d = mk(me.x - o.x, me.y - o.y, me.z - o.z);
-          const float rs = me.w + o.w;
-          if (dot(d, d) <= rs * rs) {
-            const int lo = i < j ? i : j, hi = i < j ? j : i;
-            atomicOr((unsigned long long*)&s.rowCand[lo][0], 1ull << hi);
+        for (int r0 = 1 + g; r0 <= R; r0 += 8 * groups) {
+          float4 o[8];
+          int jj[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int r = r0 + u * groups;
+            int j = i + r;
+            if (j >= n) j -= n;
+            jj[u] = r <= R ? j : i;
+            o[u] = s.pr[jj[u]];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int r = r0 + u * groups, j = jj[u];
+            const f3 d = mk(me.x - o[u].x, me.y - o[u].y, me.z - o[u].z);
+            const float rs = me.w + o[u].w;
+            if ((r <= R) & !((2 * r == n) & (i > j)) & (dot(d, d) <= rs * rs)) {
+              const int lo = i < j ? i : j, hi = i < j ? j : i;
+              atomicOr((unsigned long long*)&s.rowCand[lo][0], 1ull << hi);
+            }
           }
         }
       }
@@ -558,6 +567,7 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
     }
     int ctotal;
     const int cstart = block_excl_scan<NW>(ccount, s.scan, &ctotal);
+    s.cstart[tid] = cstart;
     if (own) {
       int pos = cstart;
 #pragma unroll
@@ -573,24 +583,37 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
     }
     if (ctotal > PhysLDS<NW>::CAPC) bad = true;
     __syncthreads();
-    // 4. narrowphase, one candidate per lane; contacts compacted in order
+    // 4a. narrowphase of the pairs with a sphere, one candidate per lane;
+    // cube-cube pairs are queued.  A pair in contact takes the next free
+    // slot (handed out per wave) and its candidate remembers it, so the
+    // order of the slots affects no sum.
     const int nc = ctotal < PhysLDS<NW>::CAPC ? ctotal : PhysLDS<NW>::CAPC;
-    int kbase = 0;
     for (int c0 = 0; c0 < nc; c0 += N) {
       const int k = c0 + tid;
-      bool contact = false;
+      bool contact = false, cc = false;
       PairAcc acc;
       int i = 0, j = 0;
       if (k < nc) {
         const uint32_t pr = s.cand[k];
         i = (int)(pr & 0xFFFFu);
         j = (int)(pr >> 16);
-        acc = pair_forces<NW>(s, i, j, pc);
-        contact = acc.npts > 0;
+        cc = (s.type[i] != 0) & (s.type[j] != 0);
+        if (!cc) {
+          acc = pair_forces<NW>(s, i, j, pc);
+          contact = acc.npts > 0;
+        }
       }
-      int ktotal;
-      const int slot = kbase + block_excl_scan<NW>(contact ? 1 : 0, s.scan, &ktotal);
+      const uint64_t cm = __ballot(contact), qm = __ballot(cc);
+      int kb = 0, qb = 0;
+      if (lane_id() == 0) {
+        if (cm) kb = atomicAdd(&s.kcnt, __popcll(cm));
+        if (qm) qb = atomicAdd(&s.ncc, __popcll(qm));
+      }
+      kb = __shfl(kb, 0, 64);
+      qb = __shfl(qb, 0, 64);
       if (contact) {
+        const int slot = kb + lanes_below(cm);
+        s.kslot[k] = (uint16_t)slot;
         if (slot < PhysLDS<NW>::CAPK) {
           s.kres[0][slot] = acc.SF.x; s.kres[1][slot] = acc.SF.y; s.kres[2][slot] = acc.SF.z;
           s.kres[3][slot] = acc.Ti.x; s.kres[4][slot] = acc.Ti.y; s.kres[5][slot] = acc.Ti.z;
@@ -599,59 +622,210 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
         atomicOr((unsigned long long*)&s.rowC[i][j >> 6], 1ull << (j & 63));
         atomicOr((unsigned long long*)&s.colC[j][i >> 6], 1ull << (i & 63));
       }
-      kbase += ktotal;
+      if (cc) s.ccl[qb + lanes_below(qm)] = (uint32_t)k | ((uint32_t)i << 10) | ((uint32_t)j << 21);
     }
-    if (kbase > PhysLDS<NW>::CAPK) bad = true;
-    __syncthreads();
-    // contact-list start of each row
-    int kcount = 0;
-    if (own) {
-#pragma unroll
-      for (int q = 0; q < NW; ++q) kcount += __popcll(s.rowC[tid][q]);
+    // ground: a sphere's single point on its own lane; cubes are queued
+    bool gsph = false;
+    PairAcc gs;
+    if (own && p.z < rbv && ty == 0) {
+      const f3 z3 = mk(0.0f, 0.0f, 0.0f);
+      Point pt;
+      gs.SF = z3;
+      gs.Ti = z3;
+      gs.Tj = z3;
+      gs.npts = 0;
+      if (p.z < a) {
+        pt.n = mk(0.0f, 0.0f, 1.0f);
+        pt.delta = a - p.z;
+        pt.xc = mk(p.x, p.y, p.z - a);
+        add_point(gs, pt, true, p, v, w, z3, z3, z3, true, pc);
+        gsph = true;
+      }
     }
-    int ktot2;
-    const int kst = block_excl_scan<NW>(kcount, s.scan, &ktot2);
-    s.kstart[tid] = kst;
+    {
+      const bool gq = own && p.z < rbv && ty != 0;
+      const uint64_t gm = __ballot(gq);
+      int gb = 0;
+      if (lane_id() == 0 && gm) gb = atomicAdd(&s.ngc, __popcll(gm));
+      gb = __shfl(gb, 0, 64);
+      if (gq) s.gcl[gb + lanes_below(gm)] = tid;
+      s.gflag[tid] = gsph ? 1 : 0;
+      if (gsph) {
+        s.gres[0][tid] = gs.SF.x; s.gres[1][tid] = gs.SF.y; s.gres[2][tid] = gs.SF.z;
+        s.gres[3][tid] = gs.Ti.x; s.gres[4][tid] = gs.Ti.y; s.gres[5][tid] = gs.Ti.z;
+      }
+    }
     __syncthreads();
-    // 5. gather in sorted pair order, then the ground, then integrate
+    // 4b. cube-cube pairs, 16 lanes each: lane r of a group tests corner
+    // r & 7 of cube i inside cube j (r < 8), then of j inside i -- the
+    // oracle's point order -- and lanes 0..8 of the group then sum one
+    // component each over the points found, in that order.
+    const int ncc = s.ncc;
+    const int lane = lane_id();
+    for (int t0 = 0; t0 < 16 * ncc; t0 += N) {
+      const int t = t0 + tid;
+      const int r = lane & 15;
+      bool hit = false;
+      int k = 0, i = 0, j = 0;
+      if (t < 16 * ncc) {
+        const uint32_t e = s.ccl[t >> 4];
+        k = (int)(e & 0x3FFu);
+        i = (int)((e >> 10) & 0x7FFu);
+        j = (int)(e >> 21);
+        const int A = r < 8 ? i : j, B = r < 8 ? j : i;
+        const f3 pA = ldsP(s, A), pB = ldsP(s, B);
+        const M3 RA = ldsR(s, A), RB = ldsR(s, B);
+        const float aA = s.size[A], aB = s.size[B];
+        const f3 vi = ldsV(s, i), wi = ldsW(s, i), vj = ldsV(s, j), wj = ldsW(s, j);
+        Point pt;
+        hit = corner_in_box(pA, RA, aA, r & 7, pB, RB, aB, &pt);
+        if (hit) {
+          const f3 pi = r < 8 ? pA : pB, pj = r < 8 ? pB : pA;
+          const PointTerms pq = point_terms(pt, r < 8, pi, vi, wi, pj, vj, wj, false, pc);
+          s.stage[0][tid] = pq.Fi.x; s.stage[1][tid] = pq.Fi.y; s.stage[2][tid] = pq.Fi.z;
+          s.stage[3][tid] = pq.ti.x; s.stage[4][tid] = pq.ti.y; s.stage[5][tid] = pq.ti.z;
+          s.stage[6][tid] = pq.tj.x; s.stage[7][tid] = pq.tj.y; s.stage[8][tid] = pq.tj.z;
+        }
+      }
+      const uint64_t hm = __ballot(hit);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      const int g0 = lane & 48;  // the group's first lane in the wave
+      const uint32_t gm = (uint32_t)(hm >> g0) & 0xFFFFu;
+      float sum = 0.0f;
+      if (r < 9) sum = ordered_sum<16, NW>(s, r, tid - r, gm);
+      const uint64_t lead = __ballot(r == 0 && gm != 0);
+      int kb = 0;
+      if (lane == 0 && lead) kb = atomicAdd(&s.kcnt, __popcll(lead));
+      kb = __shfl(kb, 0, 64);
+      if (gm != 0) {
+        const int slot = kb + __popcll(lead & ((1ull << g0) - 1ull));
+        if (r < 9 && slot < PhysLDS<NW>::CAPK) s.kres[r][slot] = sum;
+        if (r == 0) {
+          s.kslot[k] = (uint16_t)slot;
+          atomicOr((unsigned long long*)&s.rowC[i][j >> 6], 1ull << (j & 63));
+          atomicOr((unsigned long long*)&s.colC[j][i >> 6], 1ull << (i & 63));
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    }
+    // 4c. cubes near the ground, 8 lanes each: lane r tests corner r, and
+    // lanes 0..5 sum the force and torque components in corner order
+    const int ngc = s.ngc;
+    for (int t0 = 0; t0 < 8 * ngc; t0 += N) {
+      const int t = t0 + tid;
+      const int r = lane & 7;
+      bool hit = false;
+      int b = 0;
+      if (t < 8 * ngc) {
+        b = s.gcl[t >> 3];
+        const f3 pb = ldsP(s, b), vb = ldsV(s, b), wb = ldsW(s, b);
+        const f3 vtx = corner_vertex(pb, ldsR(s, b), s.size[b], r);
+        if (vtx.z < 0.0f) {
+          hit = true;
+          const f3 z3 = mk(0.0f, 0.0f, 0.0f);
+          Point pt;
+          pt.n = mk(0.0f, 0.0f, 1.0f);
+          pt.delta = -vtx.z;
+          pt.xc = vtx;
+          const PointTerms pq = point_terms(pt, true, pb, vb, wb, z3, z3, z3, true, pc);
+          s.stage[0][tid] = pq.Fi.x; s.stage[1][tid] = pq.Fi.y; s.stage[2][tid] = pq.Fi.z;
+          s.stage[3][tid] = pq.ti.x; s.stage[4][tid] = pq.ti.y; s.stage[5][tid] = pq.ti.z;
+        }
+      }
+      const uint64_t hm = __ballot(hit);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      const uint32_t gm = (uint32_t)(hm >> (lane & 56)) & 0xFFu;
+      if (gm != 0 && r < 6) {
+        s.gres[r][b] = ordered_sum<8, NW>(s, r, tid - r, gm);
+        if (r == 0) s.gflag[b] = 1;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    }
+    __syncthreads();
+    if (s.kcnt > PhysLDS<NW>::CAPK) bad = true;
+    // 5. gather in sorted pair order, then the ground, then integrate.
+    // Contacts are taken four at a time so that each level of lookups
+    // (candidate index, slot, sums) issues its loads together.
     if (own) {
       f3 F = mk(0.0f, 0.0f, 0.0f), Tq = F;
 #pragma unroll
       for (int q = 0; q < NW; ++q) {
+        // pairs (i, tid), i ascending: the candidate index of (i, tid) is
+        // the start of row i plus the rank of tid in that row
         uint64_t m = s.colC[tid][q];
         while (m) {
-          const int i = 64 * q + __ffsll((unsigned long long)m) - 1;
-          m &= m - 1ull;
-          const int idx = s.kstart[i] + popc_below<NW>(s.rowC[i], tid);
-          if (idx < PhysLDS<NW>::CAPK) {
-            F = sub(F, mk(s.kres[0][idx], s.kres[1][idx], s.kres[2][idx]));
-            Tq = add(Tq, mk(s.kres[6][idx], s.kres[7][idx], s.kres[8][idx]));
+          int ii[4], idx[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            ii[u] = m ? 64 * q + __ffsll((unsigned long long)m) - 1 : -1;
+            m &= m - 1ull;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int i = ii[u] < 0 ? 0 : ii[u];
+            idx[u] = s.kslot[s.cstart[i] + popc_below<NW>(s.rowCand[i], tid)];
+            if (ii[u] < 0 || idx[u] >= PhysLDS<NW>::CAPK) idx[u] = -1;
+          }
+          float kv[4][6];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int x = idx[u] < 0 ? 0 : idx[u];
+            kv[u][0] = s.kres[0][x]; kv[u][1] = s.kres[1][x]; kv[u][2] = s.kres[2][x];
+            kv[u][3] = s.kres[6][x]; kv[u][4] = s.kres[7][x]; kv[u][5] = s.kres[8][x];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (idx[u] >= 0) {
+              F = sub(F, mk(kv[u][0], kv[u][1], kv[u][2]));
+              Tq = add(Tq, mk(kv[u][3], kv[u][4], kv[u][5]));
+            }
           }
         }
       }
       {
-        int idx = kst;
+        // pairs (tid, j), j ascending: candidates of row tid in contact
+        int c = cstart;
 #pragma unroll
         for (int q = 0; q < NW; ++q) {
-          uint64_t m = s.rowC[tid][q];
-          while (m) {
-            m &= m - 1ull;
-            if (idx < PhysLDS<NW>::CAPK) {
-              F = add(F, mk(s.kres[0][idx], s.kres[1][idx], s.kres[2][idx]));
-              Tq = add(Tq, mk(s.kres[3][idx], s.kres[4][idx], s.kres[5][idx]));
+          uint64_t m = s.rowCand[tid][q];
+          const uint64_t mc = s.rowC[tid][q];
+          uint64_t mk_ = mc;
+          while (mk_) {
+            // candidate index of each of the next four contacts: the row
+            // start plus its rank among the row's candidates
+            int idx[4];
+            bool ok[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              ok[u] = mk_ != 0ull;
+              const int j = ok[u] ? __ffsll((unsigned long long)mk_) - 1 : 0;
+              mk_ &= mk_ - 1ull;
+              idx[u] = s.kslot[c + __popcll(m & below_mask(j))];
             }
-            ++idx;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              if (!ok[u] || idx[u] >= PhysLDS<NW>::CAPK) idx[u] = -1;
+            float kv[4][6];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int x = idx[u] < 0 ? 0 : idx[u];
+              kv[u][0] = s.kres[0][x]; kv[u][1] = s.kres[1][x]; kv[u][2] = s.kres[2][x];
+              kv[u][3] = s.kres[3][x]; kv[u][4] = s.kres[4][x]; kv[u][5] = s.kres[5][x];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              if (idx[u] >= 0) {
+                F = add(F, mk(kv[u][0], kv[u][1], kv[u][2]));
+                Tq = add(Tq, mk(kv[u][3], kv[u][4], kv[u][5]));
+              }
+            }
           }
+          c += __popcll(m);
         }
       }
-      bool gcontact = false;
-      if (p.z < rbv) {
-        const PairAcc g = ground_forces(ty, a, p, v, w, R, pc);
-        if (g.npts > 0) {
-          gcontact = true;
-          F = add(F, g.SF);
-          Tq = add(Tq, g.Ti);
-        }
+      if (s.gflag[tid]) {
+        F = add(F, mk(s.gres[0][tid], s.gres[1][tid], s.gres[2][tid]));
+        Tq = add(Tq, mk(s.gres[3][tid], s.gres[4][tid], s.gres[5][tid]));
       }
       // semi-implicit Euler
       const f3 acc = add(mul(F, inv_m), gvec);
@@ -669,7 +843,6 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
       const float n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
       const float inv = 1.0f / sqrtf(n2);
       qw = qw * inv; qx = qx * inv; qy = qy * inv; qz = qz * inv;
-      s.gflag[tid] = gcontact ? 1 : 0;
     }
     __syncthreads();
     if (W.contacts) {

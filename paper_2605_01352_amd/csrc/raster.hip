@@ -11,7 +11,7 @@
 //      area <= 0), or if its bounding box holds no pixel centre; survivors
 //      are compacted into a list;
 //   4. each survivor gets a setup record in the image's raster scratch
-//      (snapped vertices in edge order, depths, 1/area, key and flat Lambert
+//      (snapped vertices in edge order, depths, 1/area, primitive and flat Lambert
 //      colour) and the tiles of its box are counted with LDS atomics;
 //   5. a workgroup prefix scan of the counts places each 16x16 tile's bin; a
 //      scatter pass appends each triangle's record id to the bins of the
@@ -27,7 +27,7 @@
 //   minimum in registers.  Edge functions are exact (integer values carried
 //   in fp64); a pixel centre is covered if every edge value is > 0, or == 0
 //   on a top-left edge.  Depth is interpolated in fp32 and quantised to 24
-//   bits, and the minimum key (depth << 32 | primitive << 16 | record) wins,
+//   bits, and the minimum key (depth << 40 | primitive << 24 | RGB8) wins,
 //   so the result depends neither on bin order nor on which lane tests which
 //   pixel.  The winner's colour comes from its record; depth and RGB8 leave
 //   in 16- and 4-byte stores.
@@ -273,12 +273,33 @@ __device__ __forceinline__ int tile_scan(const int32_t* cnt, int32_t* toff, int 
   return total;
 }
 
-__device__ __forceinline__ void store_rec(int4* recs, int r, const Tri& t, uint32_t key, float invA,
-                                          uint32_t rgb) {
-  int4* p = recs + 3 * r;
+// A small triangle's edge values over its box, in 32-bit integers: when the
+// triangle spans at most kNarrow units (120 pixels) on both axes, every edge
+// value at a pixel centre in its box is at most 2 kNarrow^2 < 2^31 in
+// magnitude and the steps per pixel, 256 dx and 256 dy, stay below 2^23, so
+// 24-bit multiply-adds are exact.
+constexpr int kNarrow = 120 * 256;
+
+// Setup record of a triangle: what every tile it is binned to needs, so that
+// the tile kernel recomputes none of it.  Word 3 of the last quad: bit e set
+// when edge e is not top-left (a pixel centre on it is outside), bit 3 set
+// when the triangle is narrow.
+__device__ __forceinline__ void store_rec(int4* recs, int r, const Tri& t, int prim, float invA,
+                                          uint32_t rgb, int x0, int x1, int y0, int y1) {
+  int flags = 0;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const int a0 = (e + 1) % 3, b0 = (e + 2) % 3;
+    if (!top_left(t.X[b0] - t.X[a0], t.Y[b0] - t.Y[a0])) flags |= 1 << e;
+  }
+  const bool narrow = max(t.X[0], max(t.X[1], t.X[2])) - min(t.X[0], min(t.X[1], t.X[2])) <= kNarrow &&
+                      max(t.Y[0], max(t.Y[1], t.Y[2])) - min(t.Y[0], min(t.Y[1], t.Y[2])) <= kNarrow;
+  if (narrow) flags |= 8;
+  int4* p = recs + 4 * r;
   p[0] = make_int4(t.X[0], t.Y[0], t.X[1], t.Y[1]);
-  p[1] = make_int4(t.X[2], t.Y[2], (int32_t)key, __float_as_int(t.z[0]));
+  p[1] = make_int4(t.X[2], t.Y[2], prim, __float_as_int(t.z[0]));
   p[2] = make_int4(__float_as_int(t.z[1]), __float_as_int(t.z[2]), __float_as_int(invA), (int32_t)rgb);
+  p[3] = make_int4(x0 | (x1 << 16), y0 | (y1 << 16), flags, 0);
 }
 
 // Append record r to the bin of tile (tx, ty) unless its edges miss the tile;
@@ -447,8 +468,8 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
   // 4. setup records (with the face colour) and tile counts, one surviving
   // triangle per lane.  A triangle whose box spans more than kWide tiles is
   // counted by its whole wave, one tile per lane, so that one lane never
-  // walks a long tile list alone.  Record slots differ from run to run; keys
-  // order by depth, then primitive, so the slot never decides a winner.
+  // walks a long tile list alone.  Record slots differ from run to run; they
+  // appear in no key, which orders by depth, then primitive.
   for (int base = 0; base < nrec; base += nthr) {
     const int r = base + tid;
     int tx0 = 0, ty0 = 0, nx = 0, ny = 0;
@@ -461,7 +482,7 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
       tri_pixels(t.X, t.Y, Wd, Ht, &x0, &x1, &y0, &y1);
       const int64_t A = tri_area(t.X, t.Y);
       const uint32_t rgb = face_color(T, B, Lo.nmax, body, body < 0 ? pr : pr - B.pb[body]);
-      store_rec(grec, r, t, ((uint32_t)pr << 16) | (uint32_t)r, 1.0f / (float)(double)A, rgb);
+      store_rec(grec, r, t, pr, 1.0f / (float)(double)A, rgb, x0, x1, y0, y1);
       tx0 = x0 >> 4;
       ty0 = y0 >> 4;
       nx = (x1 >> 4) - tx0 + 1;
@@ -570,30 +591,31 @@ __global__ void raster_setup_kernel(WorldDev W, RasterLaunch L) {
 // tile kernel
 // ---------------------------------------------------------------------------
 
-// A small triangle's edge values over its box, in 32-bit integers: when the
-// triangle spans at most kNarrow units (120 pixels) on both axes, every edge
-// value at a pixel centre in its box is at most 2 kNarrow^2 < 2^31 in
-// magnitude and the steps per pixel, 256 dx and 256 dy, stay below 2^23, so
-// 24-bit multiply-adds are exact.
-constexpr int kNarrow = 120 * 256;
-
 struct TileWaveLDS {
   uint64_t zb[256];     // z-buffer of the small-triangle fragments
-  // per batch lane: a small triangle's (E0 at its box origin, key), (step
-  // per row, thr0), (step per column, thr1), (z0, z1, z2, 1/area), (thr2);
-  // a large one's setup record in the first three
+  // per batch lane: a small triangle's (E0 at its box origin, primitive),
+  // (step per row, thr0), (step per column, thr1), (z0, z1, z2, 1/area),
+  // (thr2, RGB8); a large one's setup record in the first three
   int4 q[64][5];
   int2 meta[64];        // (x0 | y0 << 16, fragment offset | box width << 16)
   int32_t own[64];      // fragment owner marks
 };
 
-// Quantised depth key of a covered pixel from its three edge values.
+// Key of a primitive's fragment below its depth: primitive << 24 | RGB8.
+// Primitives number at most 65535 per env, so no key equals the empty ~0.
+__device__ __forceinline__ uint64_t prim_key(int prim, uint32_t rgb) {
+  return ((uint64_t)(uint32_t)prim << 24) | (uint64_t)(rgb & 0xFFFFFFu);
+}
+
+// Quantised depth key of a covered pixel from its three edge values; the
+// 24-bit depth decides, then the primitive (unique in an image), so the
+// colour carried in the low bits never does.
 __device__ __forceinline__ uint64_t depth_key(float e0, float e1, float e2, float z0, float z1, float z2,
-                                              float invA, uint32_t key) {
+                                              float invA, uint64_t key) {
   const float zz = ((e0 * z0 + e1 * z1) + e2 * z2) * invA;
   // the interpolated depth is finite, so the median equals the clamp to [0, 1]
   const uint32_t D = (uint32_t)rintf(__builtin_amdgcn_fmed3f(zz, 0.0f, 1.0f) * 16777215.0f);
-  return ((uint64_t)D << 32) | key;
+  return ((uint64_t)D << 40) | key;
 }
 
 template <bool DBG>
@@ -618,12 +640,15 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
   // this lane's pixels: (px0 + i, py) for i < 4, z-buffer entries 4 lane + i
   const int py = ty0 + (lane >> 2), px0 = tx0 + 4 * (lane & 3);
   uint64_t* zb = S.zb;
-  {
+  // a tile with an empty bin (a third of them in a settled scene) goes
+  // straight to the background stores
+  const bool empty = k0 == k1;
+  if (!empty) {
     ulonglong2* z2 = (ulonglong2*)(zb + 4 * lane);
     z2[0] = make_ulonglong2(~0ull, ~0ull);
     z2[1] = make_ulonglong2(~0ull, ~0ull);
-    if (DBG) *(int4*)(cov + 4 * lane) = make_int4(0, 0, 0, 0);
   }
+  if (DBG) *(int4*)(cov + 4 * lane) = make_int4(0, 0, 0, 0);
   uint64_t kreg[4] = {~0ull, ~0ull, ~0ull, ~0ull};
   int creg[4] = {0, 0, 0, 0};
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -639,19 +664,16 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
         rec = e & 0x7FFF;
         full = e >> 15;
       }
-      const int4 ra = grec[3 * rec], rb = grec[3 * rec + 1], rc = grec[3 * rec + 2];
+      const int4 ra = grec[4 * rec], rb = grec[4 * rec + 1], rc = grec[4 * rec + 2], rd = grec[4 * rec + 3];
       const int32_t X[3] = {ra.x, ra.z, rb.x}, Y[3] = {ra.y, ra.w, rb.y};
-      int x0, x1, y0, y1;
-      if (tri_pixels(X, Y, Wd, Ht, &x0, &x1, &y0, &y1)) {
-        fx0 = max(x0, tx0);
-        fy0 = max(y0, ty0);
-        bw = min(x1, tx1) - fx0 + 1;
-        const int bh = min(y1, ty1) - fy0 + 1;
-        area = (bw > 0 && bh > 0) ? bw * bh : 0;
-        if (bw < 1) bw = 1;
-      }
-      const bool narrow = max(X[0], max(X[1], X[2])) - min(X[0], min(X[1], X[2])) <= kNarrow &&
-                          max(Y[0], max(Y[1], Y[2])) - min(Y[0], min(Y[1], Y[2])) <= kNarrow;
+      // the triangle's pixel box (never empty) clipped to the tile
+      fx0 = max(rd.x & 0xFFFF, tx0);
+      fy0 = max(rd.y & 0xFFFF, ty0);
+      bw = min(rd.x >> 16, tx1) - fx0 + 1;
+      const int bh = min(rd.y >> 16, ty1) - fy0 + 1;
+      area = (bw > 0) & (bh > 0) ? bw * bh : 0;
+      if (bw < 1) bw = 1;
+      const bool narrow = (rd.z & 8) != 0;
       big = area > kSmallMax || (area > 0 && !narrow);
       if (big) {
         S.q[lane][0] = ra;
@@ -669,13 +691,14 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
           sr[e] = 256 * dx;
           sc[e] = -256 * dy;
           // (E > 0 or E == 0 on a top-left edge) == (E >= threshold) for integer E
-          thr[e] = top_left(dx, dy) ? 0 : 1;
+          thr[e] = (rd.z >> e) & 1;
         }
         S.q[lane][0] = make_int4(E0[0], E0[1], E0[2], rb.z);
         S.q[lane][1] = make_int4(sr[0], sr[1], sr[2], thr[0]);
         S.q[lane][2] = make_int4(sc[0], sc[1], sc[2], thr[1]);
         S.q[lane][3] = make_int4(rb.w, rc.x, rc.y, rc.z);
         S.q[lane][4].x = thr[2];
+        S.q[lane][4].y = rc.w;
       }
     }
     // small triangles: fragments packed over lanes.  Fragment f belongs to
@@ -709,11 +732,12 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
         const int e0 = q0.x + __mul24(q1.x, qy) + __mul24(q2.x, qx);
         const int e1 = q0.y + __mul24(q1.y, qy) + __mul24(q2.y, qx);
         const int e2 = q0.z + __mul24(q1.z, qy) + __mul24(q2.z, qx);
-        if ((e0 >= q1.w) & (e1 >= q2.w) & (e2 >= S.q[j][4].x)) {
+        const int2 q4 = *(const int2*)&S.q[j][4];
+        if ((e0 >= q1.w) & (e1 >= q2.w) & (e2 >= q4.x)) {
           const int4 q3 = S.q[j][3];
           const uint64_t kk = depth_key((float)e0, (float)e1, (float)e2, __int_as_float(q3.x),
                                         __int_as_float(q3.y), __int_as_float(q3.z), __int_as_float(q3.w),
-                                        (uint32_t)q0.w);
+                                        prim_key(q0.w, (uint32_t)q4.y));
           const int p = (m.x >> 16) + qy - ty0;  // row in the tile
           const int pp = p * kTile + (m.x & 0xFFFF) + qx - tx0;
           atomicMin((unsigned long long*)&zb[pp], (unsigned long long)kk);
@@ -732,7 +756,7 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
       const int32_t X[3] = {ra.x, ra.z, rb.x}, Y[3] = {ra.y, ra.w, rb.y};
       const float z0 = __int_as_float(rb.w), z1 = __int_as_float(rc.x), z2 = __int_as_float(rc.y);
       const float invA = __int_as_float(rc.z);
-      const uint32_t key = (uint32_t)rb.z;
+      const uint64_t key = prim_key(rb.z, (uint32_t)rc.w);
       double E[3], step[3], thr[3];
 #pragma unroll
       for (int e = 0; e < 3; ++e) {
@@ -769,24 +793,22 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
 
   // resolve: the fragment z-buffer against the registers, then the winners'
   // colours and the stores
-  const ulonglong2 za = ((const ulonglong2*)(zb + 4 * lane))[0];
-  const ulonglong2 zc = ((const ulonglong2*)(zb + 4 * lane))[1];
-  const uint64_t zk[4] = {za.x, za.y, zc.x, zc.y};
+  uint64_t zk[4] = {~0ull, ~0ull, ~0ull, ~0ull};
+  if (!empty) {
+    const ulonglong2 za = ((const ulonglong2*)(zb + 4 * lane))[0];
+    const ulonglong2 zc = ((const ulonglong2*)(zb + 4 * lane))[1];
+    zk[0] = za.x; zk[1] = za.y; zk[2] = zc.x; zk[3] = zc.y;
+  }
+  // the winner's colour travels in its key
   uint32_t D[4], rgb[4];
   int32_t win[4];
-  const int32_t* gw = (const int32_t*)grec;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const uint64_t key = zk[i] < kreg[i] ? zk[i] : kreg[i];
-    D[i] = 0xFFFFFFFFu;
-    rgb[i] = 0;
-    win[i] = -1;
-    if (key != ~0ull) {
-      const uint32_t lo = (uint32_t)key;
-      D[i] = (uint32_t)(key >> 32);
-      win[i] = (int32_t)(lo >> 16);
-      rgb[i] = (uint32_t)gw[kRecWords * (lo & 0xFFFFu) + 11];
-    }
+    const bool hit = key != ~0ull;
+    D[i] = hit ? (uint32_t)(key >> 40) : 0xFFFFFFFFu;
+    rgb[i] = hit ? (uint32_t)key & 0xFFFFFFu : 0u;
+    win[i] = hit ? (int32_t)((key >> 24) & 0xFFFFu) : -1;
   }
   if (py <= ty1) {
     const int64_t pix = cam.pix_off + (int64_t)py * Wd + px0;

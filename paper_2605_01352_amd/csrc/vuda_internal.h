@@ -55,7 +55,7 @@ struct CamDev {
 // (bin offset, bin count per 16x16 tile), the setup records (kRecBytes each,
 // room for every primitive of the env) and the bins (u16 record ids, bit 15
 // set when the triangle covers the whole tile).
-constexpr int kRecWords = 12;  // X0 Y0 X1 Y1 | X2 Y2 key z0 | z1 z2 invA rgb
+constexpr int kRecWords = 16;  // X0 Y0 X1 Y1 | X2 Y2 key z0 | z1 z2 invA rgb | box x, box y, flags, 0
 constexpr int kRecBytes = 4 * kRecWords;
 constexpr int kBinsPerTri = 4;  // bin capacity of an image, per primitive
 

@@ -85,3 +85,17 @@ def test_null_arguments():
     assert L.vuda_wait(None, 3) == vuda.EINVAL
     assert L.vuda_cosched(None, C.c_float(0.5)) == vuda.EINVAL
     assert L.vuda_destroy_world(None) == vuda.EINVAL
+
+
+def test_binding_constants_match_header():
+    """Every numeric #define of include/vuda.h has the same value in the
+    Python binding (VUDA_X -> vuda.X)."""
+    src = open(os.path.join(ROOT, "include", "vuda.h")).read()
+    found = 0
+    for name, val in re.findall(r"#define VUDA_([A-Z0-9_]+)\s+(-?\d+)u?\b", src):
+        py = name[:-1] if name.endswith("_H") else name
+        if not hasattr(vuda, py):
+            continue
+        assert getattr(vuda, py) == int(val), name
+        found += 1
+    assert found >= 30

@@ -53,7 +53,7 @@ __host__ __device__ inline int align16(int x) { return (x + 15) & ~15; }
 
 struct SetupLayout {
   // byte offsets into the setup kernel's dynamic LDS
-  int tpl, body, verts, vis, tiles, misc, total;
+  int tpl, body, verts, vis, pmap, vmap, tiles, misc, total;
   int nmax, vmax, tw;
 };
 
@@ -68,6 +68,8 @@ __host__ __device__ inline SetupLayout setup_layout(int max_bodies, int max_vert
   L.body = o;   o += align16(4 * 17 * L.nmax);
   L.verts = o;  o += align16(12 * L.vmax);
   L.vis = o;    o += align16(2 * max_tris);
+  L.pmap = o;   o += align16(max_tris);   // primitive -> body map of the env
+  L.vmap = o;   o += align16(L.vmax);     // vertex -> body map of the env
   L.tiles = o;  o += align16(4 * (3 * L.tw + 1));
   L.misc = o;   o += 128;  // [2] record count, [4] queue slot, [8, 24) scan totals
   L.total = o;
@@ -338,8 +340,10 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
   const int ntris = ed.n_tris;
   const int64_t cap = W.cap_bodies;
   const float* st = W.state[L.parity];
-  const uint8_t* gpmap = W.prim_body + ed.prim_map;
-  const uint8_t* gvmap = W.vert_body + ed.vert_map;
+  // the env's primitive and vertex maps (16-byte aligned and padded), read
+  // once into LDS: every phase below looks them up per triangle or vertex
+  const uint8_t* gpmap = (const uint8_t*)(lds + Lo.pmap);
+  const uint8_t* gvmap = (const uint8_t*)(lds + Lo.vmap);
   const int Wd = cam.w, Ht = cam.h;
   const int ntx = (Wd + kTile - 1) / kTile;
   const int ntiles = tiles_of(Wd, Ht);
@@ -370,11 +374,17 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
   int32_t* tfill = toff + Lo.tw + 1;
   int32_t* misc = (int32_t*)(lds + Lo.misc);
 
-  // 1. templates and bodies
+  // 1. templates, maps and bodies
   {
     const int4* src = (const int4*)W.tpl;
     int4* dst = (int4*)T;
     for (int i = tid; i < kTplBytes / 16; i += nthr) dst[i] = src[i];
+    const int4* ps = (const int4*)(W.prim_body + ed.prim_map);
+    int4* pd = (int4*)(lds + Lo.pmap);
+    for (int i = tid; i < (ntris + 15) / 16; i += nthr) pd[i] = ps[i];
+    const int4* vs = (const int4*)(W.vert_body + ed.vert_map);
+    int4* vd = (int4*)(lds + Lo.vmap);
+    for (int i = tid; i < (ed.n_verts + 15) / 16; i += nthr) vd[i] = vs[i];
   }
   for (int b = tid; b < n; b += nthr) {
     const int g = ed.body_off + b;
@@ -536,17 +546,21 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
           for (int qx = 0; qx < nx; ++qx)
             bin_tile(t, r, (x0 >> 4) + qx, (y0 >> 4) + qy, x0, x1, y0, y1, nx * ny > 1, Wd, Ht, ntx, toff,
                      tfill, bins);
+      // a wide triangle is binned by the whole wave, one tile per lane; its
+      // snapped vertices and pixel box come from its lane's registers
       uint64_t m = __ballot(wide);
       while (m) {
         const int j = __ffsll((unsigned long long)m) - 1;
         m &= m - 1ull;
-        const int jr = __builtin_amdgcn_readfirstlane(__shfl(r, j, 64));
-        const int jp = vis[jr];
-        int jbody, jvid[3];
-        prim_vertices(T, B, gpmap[jp], jp, &jbody, jvid);
-        const Tri J = load_tri(VX, VY, VZ, jvid);
-        int jx0, jx1, jy0, jy1;
-        tri_pixels(J.X, J.Y, Wd, Ht, &jx0, &jx1, &jy0, &jy1);
+        const int jr = __builtin_amdgcn_readlane(r, j);
+        Tri J{};
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          J.X[v] = __builtin_amdgcn_readlane(t.X[v], j);
+          J.Y[v] = __builtin_amdgcn_readlane(t.Y[v], j);
+        }
+        const int jx0 = __builtin_amdgcn_readlane(x0, j), jx1 = __builtin_amdgcn_readlane(x1, j);
+        const int jy0 = __builtin_amdgcn_readlane(y0, j), jy1 = __builtin_amdgcn_readlane(y1, j);
         const int jnx = (jx1 >> 4) - (jx0 >> 4) + 1;
         const int jn = jnx * ((jy1 >> 4) - (jy0 >> 4) + 1);
         for (int q = lane; q < jn; q += 64) {

@@ -290,7 +290,7 @@ def main():
         log("cpu baseline (oracle) ...")
         n_cpu = min(1024, n_envs)
         cpu = cpu_baseline(lambda n: scene if n == n_envs else scene.subset(range(n)), n_cpu,
-                           250 if cfg <= 2 else 10)
+                           500 if cfg <= 2 else 20)
         log(f"cpu baseline: {cpu['value']:.0f} env-steps/s on {cpu['cores']} threads")
     w.close()
 

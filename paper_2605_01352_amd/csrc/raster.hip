@@ -607,11 +607,6 @@ __global__ void raster_setup_kernel(WorldDev W, RasterLaunch L) {
 
 struct TileWaveLDS {
   uint64_t zb[256];     // z-buffer of the small-triangle fragments
-  // per batch lane: a small triangle's (E0 at its box origin, primitive),
-  // (step per row, thr0), (step per column, thr1), (z0, z1, z2, 1/area),
-  // (thr2, RGB8); a large one's setup record in the first three
-  int4 q[64][5];
-  int2 meta[64];        // (x0 | y0 << 16, fragment offset | box width << 16)
   int32_t own[64];      // fragment owner marks
 };
 
@@ -668,9 +663,16 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
 
   for (int kb = k0; kb < k1; kb += 64) {
+    // One record per lane, kept in registers: a small triangle's fragments
+    // fetch their owner's values with cross-lane reads (ds_bpermute, which
+    // needs no LDS of its own), a large triangle's record is read uniformly
+    // with readlane.  So the tile keeps little LDS, and the step's waves
+    // find room beside it on the CU.
     const int k = kb + lane;
     int full = 0, area = 0, fx0 = 0, fy0 = 0, bw = 1;
     bool big = false;
+    int4 ra = make_int4(0, 0, 0, 0), rb = ra, rc = ra;
+    int E0[3] = {0, 0, 0}, sr[3] = {0, 0, 0}, sc[3] = {0, 0, 0}, thr = 0;
     if (k < k1) {
       int rec = k;
       if (binned) {
@@ -678,7 +680,10 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
         rec = e & 0x7FFF;
         full = e >> 15;
       }
-      const int4 ra = grec[4 * rec], rb = grec[4 * rec + 1], rc = grec[4 * rec + 2], rd = grec[4 * rec + 3];
+      ra = grec[4 * rec];
+      rb = grec[4 * rec + 1];
+      rc = grec[4 * rec + 2];
+      const int4 rd = grec[4 * rec + 3];
       const int32_t X[3] = {ra.x, ra.z, rb.x}, Y[3] = {ra.y, ra.w, rb.y};
       // the triangle's pixel box (never empty) clipped to the tile
       fx0 = max(rd.x & 0xFFFF, tx0);
@@ -689,14 +694,10 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
       if (bw < 1) bw = 1;
       const bool narrow = (rd.z & 8) != 0;
       big = area > kSmallMax || (area > 0 && !narrow);
-      if (big) {
-        S.q[lane][0] = ra;
-        S.q[lane][1] = rb;
-        S.q[lane][2] = rc;
-      } else if (area > 0) {
-        // edge values at the centre of pixel (fx0, fy0), steps per row and column
+      if (!big && area > 0) {
+        // edge values at the centre of pixel (fx0, fy0), steps per row and
+        // column; (E > 0 or E == 0 on a top-left edge) == (E >= thr bit)
         const int Px = 256 * fx0 + 128, Py = 256 * fy0 + 128;
-        int E0[3], sr[3], sc[3], thr[3];
 #pragma unroll
         for (int e = 0; e < 3; ++e) {
           const int a0 = (e + 1) % 3, b0 = (e + 2) % 3;
@@ -704,15 +705,8 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
           E0[e] = __mul24(dx, Py - Y[a0]) - __mul24(dy, Px - X[a0]);
           sr[e] = 256 * dx;
           sc[e] = -256 * dy;
-          // (E > 0 or E == 0 on a top-left edge) == (E >= threshold) for integer E
-          thr[e] = (rd.z >> e) & 1;
         }
-        S.q[lane][0] = make_int4(E0[0], E0[1], E0[2], rb.z);
-        S.q[lane][1] = make_int4(sr[0], sr[1], sr[2], thr[0]);
-        S.q[lane][2] = make_int4(sc[0], sc[1], sc[2], thr[1]);
-        S.q[lane][3] = make_int4(rb.w, rc.x, rc.y, rc.z);
-        S.q[lane][4].x = thr[2];
-        S.q[lane][4].y = rc.w;
+        thr = rd.z & 7;
       }
     }
     // small triangles: fragments packed over lanes.  Fragment f belongs to
@@ -722,7 +716,7 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
     const int incl = wave_incl_add(a);
     const int F = __builtin_amdgcn_readlane(incl, 63);
     const int off = incl - a;
-    S.meta[lane] = make_int2(fx0 | (fy0 << 16), off | (bw << 16));
+    const int mxy = fx0 | (fy0 << 16), mob = off | (bw << 16);
     int carry = 0;  // owner + 1 of the fragment before the window
     for (int f0 = 0; f0 < F; f0 += 64) {
       S.own[lane] = 0;
@@ -734,29 +728,28 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
       o = wave_incl_max(o);
       carry = __builtin_amdgcn_readlane(o, 63);
       const int f = f0 + lane;
-      if (f < F) {
-        const int j = o - 1;  // >= 0 for every fragment below F
-        const int2 m = S.meta[j];
-        const int rr = f - (m.y & 0xFFFF), jbw = m.y >> 16;
-        // rr / jbw exactly: rr < 64 and jbw <= 16 keep the quotient's
-        // fraction at least 1/32 away from an integer
-        const int qy = (int)(((float)rr + 0.5f) * __builtin_amdgcn_rcpf((float)jbw));
-        const int qx = rr - qy * jbw;
-        const int4 q0 = S.q[j][0], q1 = S.q[j][1], q2 = S.q[j][2];
-        const int e0 = q0.x + __mul24(q1.x, qy) + __mul24(q2.x, qx);
-        const int e1 = q0.y + __mul24(q1.y, qy) + __mul24(q2.y, qx);
-        const int e2 = q0.z + __mul24(q1.z, qy) + __mul24(q2.z, qx);
-        const int2 q4 = *(const int2*)&S.q[j][4];
-        if ((e0 >= q1.w) & (e1 >= q2.w) & (e2 >= q4.x)) {
-          const int4 q3 = S.q[j][3];
-          const uint64_t kk = depth_key((float)e0, (float)e1, (float)e2, __int_as_float(q3.x),
-                                        __int_as_float(q3.y), __int_as_float(q3.z), __int_as_float(q3.w),
-                                        prim_key(q0.w, (uint32_t)q4.y));
-          const int p = (m.x >> 16) + qy - ty0;  // row in the tile
-          const int pp = p * kTile + (m.x & 0xFFFF) + qx - tx0;
-          atomicMin((unsigned long long*)&zb[pp], (unsigned long long)kk);
-          if (DBG) atomicAdd(&cov[pp], 1);
-        }
+      // the owner's values (lanes past F read lane 63's, unused)
+      const int j = (o - 1) & 63;
+      const int jxy = __shfl(mxy, j, 64), job = __shfl(mob, j, 64);
+      const int rr = f - (job & 0xFFFF), jbw = job >> 16;
+      // rr / jbw exactly: rr < 64 and jbw <= 16 keep the quotient's
+      // fraction at least 1/32 away from an integer
+      const int qy = (int)(((float)rr + 0.5f) * __builtin_amdgcn_rcpf((float)jbw));
+      const int qx = rr - qy * jbw;
+      const int e0 = __shfl(E0[0], j, 64) + __mul24(__shfl(sr[0], j, 64), qy) + __mul24(__shfl(sc[0], j, 64), qx);
+      const int e1 = __shfl(E0[1], j, 64) + __mul24(__shfl(sr[1], j, 64), qy) + __mul24(__shfl(sc[1], j, 64), qx);
+      const int e2 = __shfl(E0[2], j, 64) + __mul24(__shfl(sr[2], j, 64), qy) + __mul24(__shfl(sc[2], j, 64), qx);
+      const int jthr = __shfl(thr, j, 64);
+      const float z0 = __int_as_float(__shfl(rb.w, j, 64)), z1 = __int_as_float(__shfl(rc.x, j, 64));
+      const float z2 = __int_as_float(__shfl(rc.y, j, 64)), invA = __int_as_float(__shfl(rc.z, j, 64));
+      const int jprim = __shfl(rb.z, j, 64), jrgb = __shfl(rc.w, j, 64);
+      if ((f < F) & (e0 >= (jthr & 1)) & (e1 >= ((jthr >> 1) & 1)) & (e2 >= (jthr >> 2))) {
+        const uint64_t kk = depth_key((float)e0, (float)e1, (float)e2, z0, z1, z2, invA,
+                                      prim_key(jprim, (uint32_t)jrgb));
+        const int p = (jxy >> 16) + qy - ty0;  // row in the tile
+        const int pp = p * kTile + (jxy & 0xFFFF) + qx - tx0;
+        atomicMin((unsigned long long*)&zb[pp], (unsigned long long)kk);
+        if (DBG) atomicAdd(&cov[pp], 1);
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     }
@@ -766,11 +759,15 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
       const int j = __ffsll((unsigned long long)m) - 1;
       m &= m - 1ull;
       const bool jfull = __builtin_amdgcn_readlane(full, j) != 0;  // uniform
-      const int4 ra = S.q[j][0], rb = S.q[j][1], rc = S.q[j][2];
-      const int32_t X[3] = {ra.x, ra.z, rb.x}, Y[3] = {ra.y, ra.w, rb.y};
-      const float z0 = __int_as_float(rb.w), z1 = __int_as_float(rc.x), z2 = __int_as_float(rc.y);
-      const float invA = __int_as_float(rc.z);
-      const uint64_t key = prim_key(rb.z, (uint32_t)rc.w);
+      const int32_t X[3] = {__builtin_amdgcn_readlane(ra.x, j), __builtin_amdgcn_readlane(ra.z, j),
+                            __builtin_amdgcn_readlane(rb.x, j)};
+      const int32_t Y[3] = {__builtin_amdgcn_readlane(ra.y, j), __builtin_amdgcn_readlane(ra.w, j),
+                            __builtin_amdgcn_readlane(rb.y, j)};
+      const float z0 = __int_as_float(__builtin_amdgcn_readlane(rb.w, j));
+      const float z1 = __int_as_float(__builtin_amdgcn_readlane(rc.x, j));
+      const float z2 = __int_as_float(__builtin_amdgcn_readlane(rc.y, j));
+      const float invA = __int_as_float(__builtin_amdgcn_readlane(rc.z, j));
+      const uint64_t key = prim_key(__builtin_amdgcn_readlane(rb.z, j), (uint32_t)__builtin_amdgcn_readlane(rc.w, j));
       double E[3], step[3], thr[3];
 #pragma unroll
       for (int e = 0; e < 3; ++e) {

@@ -165,6 +165,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="length of the continuous-batching serving run (0: skip)")
     ap.add_argument("--splits", default="0.25,0.375,0.5,0.625,0.75")
+    ap.add_argument("--prios", default="3",
+                    help="issue priorities of the step's waves tried on unmasked streams")
     ap.add_argument("--profile", type=int, default=0,
                     help="only run this many serialized then co-scheduled steps (for rocprofv3)")
     ap.add_argument("--only", default="",
@@ -235,21 +237,36 @@ def main():
         f"render phase {Tr*1e6:.1f} us, bound {(Ts + Tr) / max(Ts, Tr):.3f}x "
         f"(physics {alone['physics']['avg_s']*1e6:.1f}, setup {alone['raster_setup']['avg_s']*1e6:.1f}, "
         f"tiles {alone['raster_tiles']['avg_s']*1e6:.1f} us per launch)")
-    # co-scheduled candidates: unmasked streams and CU splits, both overlap patterns
-    cands = [(2.0, sched) for sched in ("interstep", "intertraj")]
-    cands += [(float(x), sched) for x in args.splits.split(",") for sched in ("interstep", "intertraj")]
+    # co-scheduled candidates: unmasked streams and CU splits, both overlap
+    # patterns; on unmasked streams also raised issue priorities of the step's
+    # waves (they share CUs with the render's)
+    p0 = w.get_tuning(vuda.TUNE_PHYS_PRIORITY)
+    prios = [int(p) for p in filter(None, args.prios.split(",")) if int(p) != p0]
+    cands = [(2.0, sched, p0) for sched in ("interstep", "intertraj")]
+    cands += [(2.0, sched, p) for p in prios for sched in ("interstep", "intertraj")]
+    cands += [(float(x), sched, p0) for x in args.splits.split(",") for sched in ("interstep", "intertraj")]
     if args.only:
         cands = []
     sweep = {}
-    for split, sched in cands:
+
+    def name(sched, split, prio):
+        return f"{sched}@{split:g}" + (f"/p{prio}" if prio != p0 else "")
+
+    def apply(split, prio):
         w.cosched(split)
+        w.set_tuning(vuda.TUNE_PHYS_PRIORITY, prio)
+
+    for split, sched, prio in cands:
+        apply(split, prio)
         dt = timed(torch, w, sched, n_envs, args.steps, 5, st0)
-        sweep[f"{sched}@{split:g}"] = n_envs * args.steps / dt
-        log(f"  {sched:9s} split {split:5g}: {n_envs * args.steps / dt:.0f} env-steps/s")
+        sweep[name(sched, split, prio)] = n_envs * args.steps / dt
+        log(f"  {name(sched, split, prio):20s}: {n_envs * args.steps / dt:.0f} env-steps/s")
     best = args.only or max(sweep, key=sweep.get)
-    sched, split = best.split("@")
+    sched, rest = best.split("@")
+    split, _, ps = rest.partition("/p")
     split = float(split)
-    w.cosched(split)
+    prio = int(ps) if ps else p0
+    apply(split, prio)
     dt = timed(torch, w, sched, n_envs, args.steps, args.warmup, st0)
     value = n_envs * args.steps / dt
     live = kernel_run(sched)
@@ -306,7 +323,8 @@ def main():
         "data": "synthetic (seeded sphere/cube drops standing in for ManiSkill3 scenes)",
         "config": {"workload": names.get(cfg, f"c{cfg}"), "envs": n_envs,
                    "bodies": int(scene.n_bodies), "cameras": int(scene.n_cams),
-                   "schedule": sched, "cu_split": split, "parallelism": "single GPU"},
+                   "schedule": sched, "cu_split": split, "step_priority": prio,
+                   "parallelism": "single GPU"},
         "serialized": {"value": round(ser, 1), "ms_per_step": round(results["serialized"] / args.steps * 1e3, 4)},
         "speedup_vs_serialized": round(value / ser, 4),
         "overlap_bound": round((Ts + Tr) / max(Ts, Tr), 4),

@@ -236,8 +236,10 @@ int vuda_world_info(vuda_world* w, int32_t* n_envs, int64_t* n_bodies, int32_t* 
  *   VUDA_TUNE_RASTER_PERSISTENT  the same for camera images
  *   VUDA_TUNE_GRAPHS           1: each (phase, env range, parity) launch is
  *                              captured once into a hipGraph and replayed
- *   VUDA_TUNE_PHYS_PRIORITY    0..3: instruction-issue priority of the physics
- *                              waves relative to render waves on shared CUs
+ *   VUDA_TUNE_PHYS_PRIORITY    0..3: instruction-issue priority of the step's
+ *                              waves (physics, and the raster setup that ends
+ *                              a step with VUDA_TUNE_PRESETUP) relative to the
+ *                              render's tile waves on shared CUs
  *   VUDA_TUNE_BROADPHASE       0 automatic (all pairs up to 64 bodies, uniform
  *                              grid hash above), 1 grid hash, 2 all pairs;
  *                              both give the same candidate set

@@ -584,6 +584,14 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
 
 __global__ void raster_setup_kernel(WorldDev W, RasterLaunch L) {
   extern __shared__ __align__(16) unsigned char lds[];
+  // At the end of a step this kernel shares CUs with the render's tile
+  // waves; a higher issue priority keeps its chains of dependent steps moving.
+  switch (L.prio) {
+    case 1: __builtin_amdgcn_s_setprio(1); break;
+    case 2: __builtin_amdgcn_s_setprio(2); break;
+    case 3: __builtin_amdgcn_s_setprio(3); break;
+    default: break;
+  }
   const SetupLayout Lo = setup_layout(L.max_bodies, L.max_verts, L.max_tiles, L.max_tris);
   if (L.persistent == 0) {
     if ((int)blockIdx.x >= L.n_work) return;

@@ -165,6 +165,7 @@ struct RasterLaunch {
   int32_t bin_limit;       // bin entries an image may use (0: its whole capacity)
   int32_t persistent;      // setup kernel: resident workgroups pulling images
   int32_t* queue;
+  int32_t prio;            // setup kernel: wave issue priority 0..3 (s_setprio)
 };
 
 hipError_t launch_physics(const WorldDev& w, const PhysConsts& pc, const PhysLaunch& l,

@@ -806,6 +806,7 @@ int vuda_world::raster_launch_of(const WorkList& L, int parity, int32_t* queue, 
   rl.bin_limit = tune.rec_cap;
   rl.persistent = tune.raster_persistent;
   rl.queue = queue;
+  rl.prio = 0;
   const size_t lds = raster_lds_bytes(rl);
   const size_t kLdsMax = 160 * 1024;
   if (lds > kLdsMax)
@@ -823,6 +824,8 @@ int vuda_world::enqueue_kernel(int kind, const WorkList& L, int parity, hipStrea
   RasterLaunch rl;
   int rc = raster_launch_of(L, parity, queue, &rl);
   if (rc) return rc;
+  // the setup that ends a step (its own queue slot) runs at the step's priority
+  if (kind == kKernelSetup) rl.prio = queue == queues + 1 ? tune.phys_prio : 0;
   if (kind == kKernelSetup) HIPCHK(launch_raster_setup(dev, rl, s));
   else HIPCHK(launch_raster_tiles(dev, rl, s));
   return VUDA_OK;

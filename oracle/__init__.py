@@ -53,6 +53,7 @@ def lib():
             _b.build()
         _lib = C.CDLL(path)
         _lib.oracle_step_env.restype = C.c_int
+        _lib.oracle_step_env_ext.restype = C.c_int
         _lib.oracle_render_image.restype = C.c_int
         _lib.oracle_run_batch.restype = C.c_int
         _lib.oracle_narrowphase.restype = C.c_int
@@ -104,8 +105,10 @@ def render_params() -> _Render:
 
 
 def step_env(scene, e: int, state: Dict[str, np.ndarray], record_pairs: bool = False,
-             pair_cap: int = 4096) -> Tuple[int, Optional[List[np.ndarray]]]:
+             pair_cap: int = 4096, fext: Optional[np.ndarray] = None) -> Tuple[int, Optional[List[np.ndarray]]]:
     """Advance env e of `state` (global arrays, modified in place) by one step.
+    fext: optional external force per body of the env, [n, 3] float32, held
+    over the substeps.
 
     Returns (status, per-substep sorted pair arrays [k,2] or None).
     """
@@ -119,9 +122,10 @@ def step_env(scene, e: int, state: Dict[str, np.ndarray], record_pairs: bool = F
     pairs = np.zeros((S, pair_cap, 2), np.int32) if record_pairs else None
     npairs = np.zeros(S, np.int32)
     bt, sz, rb, im, iI = sl(scene.btype), sl(scene.size), sl(scene.rbound), sl(scene.inv_m), sl(scene.inv_I)
-    st = L.oracle_step_env(n, _p(bt), _p(sz), _p(rb), _p(im), _p(iI), _p(pos), _p(vel), _p(quat),
-                           _p(om), C.byref(prm), _p(pairs) if pairs is not None else None,
-                           pair_cap, _p(npairs))
+    fx = None if fext is None else np.ascontiguousarray(fext, np.float32).reshape(n, 3)
+    st = L.oracle_step_env_ext(n, _p(bt), _p(sz), _p(rb), _p(im), _p(iI), _p(pos), _p(vel), _p(quat),
+                               _p(om), C.byref(prm), _p(pairs) if pairs is not None else None,
+                               pair_cap, _p(npairs), _p(fx) if fx is not None else None)
     state["pos"][b0:b1], state["vel"][b0:b1] = pos, vel
     state["quat"][b0:b1], state["omega"][b0:b1] = quat, om
     out = [pairs[s, :npairs[s]].copy() for s in range(S)] if record_pairs else None

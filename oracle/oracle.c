@@ -199,6 +199,14 @@ int oracle_step_env(int32_t n, const uint8_t* type, const float* size, const flo
                     const float* inv_m, const float* inv_I, float* pos, float* vel,
                     float* quat, float* omega, const oracle_phys_params* prm,
                     int32_t* pairs, int32_t pair_cap, int32_t* npairs) {
+  return oracle_step_env_ext(n, type, size, rbound, inv_m, inv_I, pos, vel, quat, omega, prm, pairs,
+                             pair_cap, npairs, NULL);
+}
+
+int oracle_step_env_ext(int32_t n, const uint8_t* type, const float* size, const float* rbound,
+                        const float* inv_m, const float* inv_I, float* pos, float* vel,
+                        float* quat, float* omega, const oracle_phys_params* prm,
+                        int32_t* pairs, int32_t pair_cap, int32_t* npairs, const float* fext) {
   const float h = prm->dt / (float)prm->substeps;
   const float hh = 0.5f * h;
   const v3 g = mk(prm->g[0], prm->g[1], prm->g[2]);
@@ -279,7 +287,9 @@ int oracle_step_env(int32_t n, const uint8_t* type, const float* size, const flo
     /* Semi-implicit Euler: v then p (with the new v); omega then q. */
     for (int32_t b = 0; b < n; ++b) {
       v3 v = load3(vel, b), p = load3(pos, b), w = load3(omega, b);
-      v3 a = add(scl(acc[b].F, inv_m[b]), g);
+      v3 F = acc[b].F;
+      if (fext) F = add(F, load3(fext, b)); /* external force, after the contacts */
+      v3 a = add(scl(F, inv_m[b]), g);
       v = add(v, scl(a, h));
       p = add(p, scl(v, h));
       w = add(w, scl(scl(acc[b].T, inv_I[b]), h));

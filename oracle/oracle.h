@@ -76,6 +76,15 @@ int oracle_step_env(int32_t n, const uint8_t* type, const float* size, const flo
                     float* quat, float* omega, const oracle_phys_params* prm,
                     int32_t* pairs, int32_t pair_cap, int32_t* npairs);
 
+/* The same step with an external force fext[b] (3 floats per body, held over
+ * the step's substeps) on every body: it joins the body's force after the
+ * contact and ground sums, before the division by the mass.  fext = NULL
+ * is the step above. */
+int oracle_step_env_ext(int32_t n, const uint8_t* type, const float* size, const float* rbound,
+                        const float* inv_m, const float* inv_I, float* pos, float* vel,
+                        float* quat, float* omega, const oracle_phys_params* prm,
+                        int32_t* pairs, int32_t pair_cap, int32_t* npairs, const float* fext);
+
 /* Narrowphase of one body pair (i < j) or of body i with the ground
  * (j = ORACLE_GROUND), evaluated on the given state.  Returns the number of
  * contact points written to pts (at most ORACLE_MAX_POINTS). */

@@ -536,3 +536,36 @@ def request_scene(req: RequestSpec, seed: int = 1005) -> Scene:
     gid0 = req.rid << 12
     return make_scene(seed, np.full(req.n_envs, req.n_bodies), req.res, mixed=True,
                       env_gid0=gid0, name=f"req{req.rid}")
+
+
+def _bf16_bits(x: np.ndarray) -> np.ndarray:
+    """16-bit patterns of float32 values rounded to bfloat16 (nearest, ties
+    to even)."""
+    u = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    return ((u + (((u >> 16) & 1) + 0x7FFF)) >> 16).astype(np.uint16)
+
+
+def policy_weights(seed: int, in_w: int, in_h: int, hidden: int, act_bodies: int,
+                   a_max: float = 2.0, zero: bool = False) -> Dict:
+    """Seeded random weights of an MLP policy over a camera-0 frame of
+    in_w x in_h pixels (observation length K = 4 in_w in_h), scaled so that
+    every layer's values are of order one: W1 ~ N(0, 1/(sqrt(K) 128)) in
+    bfloat16, W2 and W3 ~ N(0, 1/hidden), biases of order 0.1 to 0.5.
+    zero: every weight matrix zero and b3 drawn from {-2, -0.5, 0.5, 2}, so
+    that the actions are a_max clamp(b3) exactly."""
+    rng = np.random.default_rng(seed)
+    K, H, A = 4 * in_w * in_h, hidden, 3 * act_bodies
+    P = dict(in_w=in_w, in_h=in_h, act_bodies=act_bodies, a_max=np.float32(a_max))
+    if zero:
+        P.update(w1_bf16=np.zeros((K, H), np.uint16), b1=np.zeros(H, np.float32),
+                 w2=np.zeros((H, H), np.float32), b2=np.zeros(H, np.float32),
+                 w3=np.zeros((H, A), np.float32),
+                 b3=rng.choice(np.array([-2.0, -0.5, 0.5, 2.0], np.float32), A))
+        return P
+    P.update(w1_bf16=_bf16_bits(rng.normal(0.0, 1.0 / (math.sqrt(K) * 128.0), (K, H))),
+             b1=rng.normal(0.0, 0.1, H).astype(np.float32),
+             w2=rng.normal(0.0, 1.0 / H, (H, H)).astype(np.float32),
+             b2=rng.normal(0.0, 0.5, H).astype(np.float32),
+             w3=rng.normal(0.0, 1.0 / H, (H, A)).astype(np.float32),
+             b3=rng.normal(0.0, 0.3, A).astype(np.float32))
+    return P

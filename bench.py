@@ -127,6 +127,71 @@ def copy_calibration(torch, mib):
     del a, b
 
 
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def policy_bench(torch, vuda, sg, scene, w, st0, steps, warmup, hidden, log):
+    """The RL rollout loop with the MLP policy as a third phase: per
+    iteration every env is rendered, acted on and stepped.  Serialized: one
+    stream; co-scheduled: the envs in two halves, each half's act and step
+    beside the other half's render.  Also the policy launch (layer 1 on MFMA
+    and the head) against the bf16 MFMA roof."""
+    n = scene.n_envs
+    half = n // 2
+    P = sg.policy_weights(2605, int(scene.cam_w[0]), int(scene.cam_h[0]), hidden, 32)
+    w.set_policy(P)
+
+    def loop(iters, cosched):
+        for _ in range(iters):
+            if cosched:
+                w.render(0, half)
+                w.act(0, half)
+                w.step(0, half)
+                w.render(half, n)
+                w.act(half, n)
+                w.step(half, n)
+            else:
+                w.render()
+                w.act()
+                w.step()
+
+    out = {"hidden": hidden, "act_bodies": 32, "obs": int(4 * scene.cam_w[0] * scene.cam_h[0])}
+    for name, split in (("serialized", 0.0), ("co_scheduled", 2.0)):
+        w.cosched(split)
+        w.load_state(st0)
+        loop(warmup, split > 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loop(steps, split > 0)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        w.wait()
+        out[name] = round(n * steps / dt, 1)
+        log(f"policy loop ({name}): {n * steps / dt:.0f} env-steps/s")
+    # the policy launch alone, all envs at once
+    w.cosched(0.0)
+    w.set_tuning(vuda.TUNE_TIMING, 1)
+    w.render()
+    w.act()
+    w.wait()
+    w.kernel_times(vuda.KERNEL_POLICY)
+    for _ in range(20):
+        w.act()
+    w.wait()
+    t = w.kernel_times(vuda.KERNEL_POLICY)
+    w.set_tuning(vuda.TUNE_TIMING, 0)
+    us = t["total_ms"] * 1e3 / max(1, t["launches"])
+    flops = 2.0 * n * out["obs"] * hidden
+    out["launch_us"] = round(us, 2)
+    out["layer1_flops_per_launch"] = flops
+    out["roofline"] = {"bound": "mfma", "achieved": round(flops / (us * 1e-6) / 1e12, 2),
+                       "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": round(flops / (us * 1e-6) / 1e12 / BF16_PEAK_TFLOPS, 5)}
+    log(f"policy launch: {us:.1f} us, layer 1 {flops / (us * 1e-6) / 1e12:.1f} TFLOP/s (bf16 MFMA)")
+    w.set_policy(None)
+    return out
+
+
 def cpu_baseline(scene_fn, n_envs, steps):
     import numpy as np  # noqa: F401
     import oracle
@@ -174,6 +239,8 @@ def main():
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--tune", default="", help="tuning knobs key=value,... (e.g. raster_threads=512)")
+    ap.add_argument("--policy-hidden", type=int, default=256,
+                    help="hidden units of the MLP policy loop measured after the main run (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the envs are independent and a multi-GPU run would "
@@ -295,6 +362,14 @@ def main():
             "bytes_per_launch": kinds[dom]["bytes_per_launch"], "launch_us": kinds[dom]["launch_us"],
             **{k: kinds[k] for k in step_bytes}}
 
+    policy = None
+    if args.policy_hidden > 0 and not args.only:
+        if len(set(zip(scene.cam_w.tolist(), scene.cam_h.tolist()))) == 1:
+            policy = policy_bench(torch, vuda, sg, scene, w, st0, min(args.steps, 200), 10,
+                                  args.policy_hidden, log)
+        else:
+            log("policy loop skipped: the policy reads one frame size, the cameras differ")
+
     serving = None
     if args.serve_seconds > 0:
         from paper_2605_01352_amd import serving as srv
@@ -333,6 +408,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "serving": serving,
+        "policy": policy,
     }
     print(json.dumps(line), flush=True)
 

@@ -63,6 +63,8 @@ extern "C" {
 #define VUDA_FETCH_COVERAGE 5 /* int32 per camera [H][W]: covering triangles (debug)    */
 #define VUDA_FETCH_FLAGS    6 /* uint32 per env: bit0 non-finite, bit1 contact overflow,
                                  bit2 bin overflow                                     */
+#define VUDA_FETCH_ACTIONS  7 /* float per env [3 act_bodies]: the policy's last actions
+                                 (zeros before the first vuda_act); needs a policy     */
 
 /* ---- world flags -------------------------------------------------------- */
 #define VUDA_FLAG_DEBUG 1u  /* keep contact sets, winners and coverage for fetch */
@@ -272,7 +274,8 @@ int vuda_get_tuning(vuda_world* w, int32_t key, int32_t* value);
  * VUDA_KERNEL_PHYSICS (the step), VUDA_KERNEL_RASTER_SETUP (vertex
  * transform, triangle setup and tile binning of a state; part of the step
  * with VUDA_TUNE_PRESETUP, else of the render) or VUDA_KERNEL_RASTER_TILES
- * (the pixels, part of the render).  Waits for the last recorded launch of
+ * (the pixels, part of the render) or VUDA_KERNEL_POLICY (layer 1 and the
+ * head of vuda_act).  Waits for the last recorded launch of
  * that kernel, then returns the number of launches since the previous call
  * for it and the sum and maximum of their durations in milliseconds -- GPU
  * time between an event recorded on the launch's stream just before the
@@ -283,8 +286,53 @@ int vuda_get_tuning(vuda_world* w, int32_t key, int32_t* value);
 #define VUDA_KERNEL_PHYSICS 1
 #define VUDA_KERNEL_RASTER_SETUP 2
 #define VUDA_KERNEL_RASTER_TILES 3
+#define VUDA_KERNEL_POLICY 4
 int vuda_kernel_times(vuda_world* w, int32_t kernel, int64_t* launches, double* total_ms,
                       double* max_ms);
+
+/*
+ * MLP policy: the RL rollout's third phase beside physics and rendering
+ * (paper: Evaluation, RL Training, MLP-based RL; the paper gives no
+ * architecture, the one here is a reading).  The observation of an env is
+ * its camera 0 frame as K = 4 in_w in_h integers 0..255: the RGB bytes in
+ * memory order (row-major pixels, R G B), then the top byte of each pixel's
+ * 24-bit depth (background: 255).  Then
+ *   h1 = relu(x W1 + b1), h2 = relu(h1 W2 + b2), y = h2 W3 + b3,
+ *   a = a_max clamp(y, -1, 1),
+ * and a[3b .. 3b+2] is an external force (N) on body b (b < act_bodies and
+ * below the env's body count), added to the body's contact forces on every
+ * substep of each following vuda_step until the next vuda_act.  Layer 1 runs
+ * in bfloat16 products (exact: 8-bit inputs) with float32 sums; layers 2 and
+ * 3 in float32.
+ *
+ * vuda_policy_set copies the weights (the caller keeps ownership of desc and
+ * its arrays) and clears every env's actions; desc = NULL removes the policy
+ * and the forces.  It waits for the world's queued work.  VUDA_EINVAL for a
+ * frame whose pixel count is not a multiple of 32, hidden outside 1..1024,
+ * act_bodies outside 1..1024, a_max negative or non-finite, null arrays or
+ * non-finite weights; VUDA_ENOMEM when the device buffers (weights, and
+ * cap_envs x 3 act_bodies floats of actions) do not fit.
+ *
+ * vuda_act enqueues the policy on the active envs in [env_lo, env_hi), on
+ * the step stream after the renders of their current state, and returns;
+ * a later render of those envs waits for it.  Every such env needs a camera
+ * 0 of in_w x in_h pixels whose frame starts at a pixel offset that is a
+ * multiple of 8 (VUDA_EINVAL otherwise, or without a policy).
+ */
+typedef struct {
+  int32_t in_w, in_h;        /* camera-0 frame the policy reads                   */
+  int32_t hidden;            /* H                                                 */
+  int32_t act_bodies;        /* B: 3 B actions                                    */
+  float a_max;               /* force bound (N)                                   */
+  const uint16_t* w1;        /* bfloat16 bits, [4 in_w in_h][H] row-major          */
+  const float* b1;           /* [H]                                               */
+  const float* w2;           /* [H][H] row-major                                  */
+  const float* b2;           /* [H]                                               */
+  const float* w3;           /* [H][3 B] row-major                                */
+  const float* b3;           /* [3 B]                                             */
+} vuda_policy_desc;
+int vuda_policy_set(vuda_world* w, const vuda_policy_desc* desc);
+int vuda_act(vuda_world* w, int32_t env_lo, int32_t env_hi);
 
 /*
  * Placement probe: launches n_blocks one-wave workgroups on the stream of

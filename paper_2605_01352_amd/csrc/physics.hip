@@ -407,6 +407,14 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
     s.rb[tid] = rbv;
     s.type[tid] = ty;
   }
+  // the policy's force on this body, held over the substeps
+  f3 fx = mk(0.0f, 0.0f, 0.0f);
+  bool has_fx = false;
+  if (W.actions && own && tid < W.act_dim / 3 && W.act_on[env]) {
+    const float* fa = W.actions + (int64_t)env * W.act_dim + 3 * tid;
+    fx = mk(fa[0], fa[1], fa[2]);
+    has_fx = true;
+  }
   // grid cell edge: a little above the largest bounding diameter
   const float rmax = block_max<NW>(own ? rbv : 0.0f, s.red);
   const float inv_c = 1.0f / (2.0f * rmax * 1.000244140625f);
@@ -827,6 +835,7 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
         F = add(F, mk(s.gres[0][tid], s.gres[1][tid], s.gres[2][tid]));
         Tq = add(Tq, mk(s.gres[3][tid], s.gres[4][tid], s.gres[5][tid]));
       }
+      if (has_fx) F = add(F, fx);  // external force, after the contacts
       // semi-implicit Euler
       const f3 acc = add(mul(F, inv_m), gvec);
       v = add(v, mul(acc, pc.h));

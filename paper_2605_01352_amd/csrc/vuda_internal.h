@@ -135,6 +135,11 @@ struct WorldDev {
   uint32_t* env_flags;
   const Templates* tpl;
   unsigned char* rscratch;  // raster scratch of every camera (CamDev::rs_off)
+  // policy actions: per env act_dim floats, the force on body b in
+  // [3b, 3b + 3); act_on[env] != 0 once the policy has acted on the env
+  float* actions;           // nullable (no policy)
+  uint8_t* act_on;
+  int32_t act_dim;
 };
 
 // Host-side launchers (implemented next to the kernels).
@@ -170,6 +175,26 @@ struct RasterLaunch {
 
 hipError_t launch_physics(const WorldDev& w, const PhysConsts& pc, const PhysLaunch& l,
                           hipStream_t s);
+
+// The policy over M envs: layer 1 split over `splits` chunks of `kchunk`
+// observation values (MFMA), then layers 2 and 3 and the actions.
+struct PolicyLaunch {
+  const int32_t* envs;     // env ids, one per row
+  int32_t M;               // rows
+  int32_t K;               // observation length 4 W H
+  int32_t krgb;            // 3 W H: start of the depth bytes
+  int32_t H, A;            // hidden units, actions
+  int32_t splits, kchunk;  // K = splits kchunk, kchunk a multiple of 32
+  const uint16_t* w1t;     // [H][K] bfloat16 (W1 transposed)
+  const float* b1;
+  const float* w2;         // [H][H]
+  const float* b2;
+  const float* w3;         // [H][A]
+  const float* b3;
+  float a_max;
+  float* partial;          // [splits][M][H]
+};
+hipError_t launch_policy(const WorldDev& w, const PolicyLaunch& l, hipStream_t s);
 // The render work of a state buffer: setup (geometry, records, bins) into the
 // cameras' scratch of that buffer, then the tiles (pixels) from it.
 hipError_t launch_raster_setup(const WorldDev& w, const RasterLaunch& l, hipStream_t s);

@@ -73,7 +73,19 @@ struct Tuning {
 };
 
 // kernels of the step loop (index of their timing events)
-constexpr int kKernelPhysics = 0, kKernelSetup = 1, kKernelTiles = 2;
+constexpr int kKernelPhysics = 0, kKernelSetup = 1, kKernelTiles = 2, kKernelPolicy = 3;
+constexpr int kKernelKinds = 4;
+
+// The MLP policy of a world (device copies of its weights).
+struct Policy {
+  bool set = false;
+  int32_t in_w = 0, in_h = 0, H = 0, A = 0;
+  float a_max = 0.0f;
+  uint16_t* w1t = nullptr;  // [H][K] bfloat16
+  float* wf = nullptr;      // b1 [H], w2 [H][H], b2 [H], w3 [H][A], b3 [A]
+  float* partial = nullptr;
+  int64_t partial_cap = 0;  // floats
+};
 
 }  // namespace vuda
 
@@ -124,11 +136,15 @@ struct vuda_world {
 
   // launch timing: per kernel (kKernel*) and launch, an event before and one
   // after; tev_used[k] launches recorded since the last read
-  std::vector<hipEvent_t> tev[3];
-  size_t tev_used[3] = {0, 0, 0};
+  std::vector<hipEvent_t> tev[vuda::kKernelKinds];
+  size_t tev_used[vuda::kKernelKinds] = {0, 0, 0, 0};
   // per env: the raster scratch of its current state buffer holds that
   // state's setup
   std::vector<uint8_t> setup_ok;
+  // policy: weights, and per env its actions (WorldDev::actions, act_on)
+  vuda::Policy pol;
+  float* actions = nullptr;
+  uint8_t* act_on = nullptr;
 
   std::map<std::tuple<int, int32_t, int32_t>, vuda::WorkList> lists;
   std::map<std::tuple<int, int32_t, int32_t, int>, hipGraphExec_t> graphs;
@@ -159,4 +175,6 @@ struct vuda_world {
   hipStream_t capture_stream();
   int check_flags();
   int32_t active_midpoint();
+  void free_policy();
+  int policy_launch_of(const vuda::WorkList& L, vuda::PolicyLaunch* out);
 };

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -541,6 +542,7 @@ void vuda_world::free_all() {
     for (auto& e : v) (void)hipEventDestroy(e);
     v.clear();
   }
+  free_policy();
   if (arena) {
     if (has_allocator) allocator.free(arena, allocator.ctx);
     else (void)hipFree(arena);
@@ -821,6 +823,13 @@ int vuda_world::raster_launch_of(const WorkList& L, int parity, int32_t* queue, 
 
 int vuda_world::enqueue_kernel(int kind, const WorkList& L, int parity, hipStream_t s, int32_t* queue) {
   if (kind == kKernelPhysics) return enqueue_physics(L, parity, s);
+  if (kind == kKernelPolicy) {
+    PolicyLaunch pl;
+    int rc = policy_launch_of(L, &pl);
+    if (rc) return rc;
+    HIPCHK(launch_policy(dev, pl, s));
+    return VUDA_OK;
+  }
   RasterLaunch rl;
   int rc = raster_launch_of(L, parity, queue, &rl);
   if (rc) return rc;
@@ -1018,6 +1027,174 @@ extern "C" int vuda_get_stream(vuda_world* w, int32_t phase, void** s) {
 }
 
 // ---------------------------------------------------------------------------
+// policy
+// ---------------------------------------------------------------------------
+
+void vuda_world::free_policy() {
+  if (pol.w1t) (void)hipFree(pol.w1t);
+  if (pol.wf) (void)hipFree(pol.wf);
+  if (pol.partial) (void)hipFree(pol.partial);
+  if (actions) (void)hipFree(actions);
+  if (act_on) (void)hipFree(act_on);
+  pol = Policy{};
+  actions = nullptr;
+  act_on = nullptr;
+  dev.actions = nullptr;
+  dev.act_on = nullptr;
+  dev.act_dim = 0;
+}
+
+// Layer-1 split: enough workgroups to fill the chip (about 4 per CU), each
+// with at least 4 MFMA steps of 32; the split count divides K / 32.
+static int policy_splits(int32_t M, int32_t H, int32_t K) {
+  const int64_t tiles = (int64_t)((M + 63) / 64) * ((H + 255) / 256);
+  const int32_t steps = K / 32;
+  int s = 1;
+  while (tiles * s < 1024 && steps % (2 * s) == 0 && steps / (2 * s) >= 4) s *= 2;
+  return s;
+}
+
+int vuda_world::policy_launch_of(const WorkList& L, PolicyLaunch* out) {
+  const int32_t K = 4 * pol.in_w * pol.in_h;
+  PolicyLaunch pl;
+  pl.envs = L.dptr;
+  pl.M = L.n;
+  pl.K = K;
+  pl.krgb = 3 * pol.in_w * pol.in_h;
+  pl.H = pol.H;
+  pl.A = pol.A;
+  pl.splits = policy_splits(L.n, pol.H, K);
+  pl.kchunk = K / pl.splits;
+  pl.w1t = pol.w1t;
+  pl.b1 = pol.wf;
+  pl.w2 = pl.b1 + pol.H;
+  pl.b2 = pl.w2 + (int64_t)pol.H * pol.H;
+  pl.w3 = pl.b2 + pol.H;
+  pl.b3 = pl.w3 + (int64_t)pol.H * pol.A;
+  pl.a_max = pol.a_max;
+  if ((int64_t)pl.splits * L.n * pol.H > pol.partial_cap) return fail(VUDA_EINVAL, "policy partials unsized");
+  pl.partial = pol.partial;
+  *out = pl;
+  return VUDA_OK;
+}
+
+extern "C" int vuda_policy_set(vuda_world* w, const vuda_policy_desc* d) {
+  if (!w) return fail(VUDA_EINVAL, "null world");
+  HIPCHK(hipSetDevice(w->device));
+  int rc = w->drain();
+  if (rc) return rc;
+  // launches captured with the old action buffers are stale
+  for (auto& g : w->graphs) (void)hipGraphExecDestroy(g.second);
+  w->graphs.clear();
+  w->free_policy();
+  if (!d) return VUDA_OK;
+  const int64_t px = (int64_t)d->in_w * d->in_h;
+  if (d->in_w < 1 || d->in_h < 1 || px % 32 != 0 || 4 * px > (int64_t)1 << 30)
+    return fail(VUDA_EINVAL, "policy frame %dx%d (pixels a multiple of 32)", d->in_w, d->in_h);
+  if (d->hidden < 1 || d->hidden > 1024) return fail(VUDA_EINVAL, "policy hidden %d (1..1024)", d->hidden);
+  if (d->act_bodies < 1 || d->act_bodies > 1024) return fail(VUDA_EINVAL, "policy act_bodies %d", d->act_bodies);
+  if (!(d->a_max >= 0.0f) || !std::isfinite(d->a_max)) return fail(VUDA_EINVAL, "policy a_max");
+  if (!d->w1 || !d->b1 || !d->w2 || !d->b2 || !d->w3 || !d->b3) return fail(VUDA_EINVAL, "null policy weights");
+  Policy p;
+  p.in_w = d->in_w;
+  p.in_h = d->in_h;
+  p.H = d->hidden;
+  p.A = 3 * d->act_bodies;
+  p.a_max = d->a_max;
+  const int64_t K = 4 * px, H = p.H, A = p.A;
+  // W1 [K][H] -> [H][K], so that a unit's weights are contiguous in k
+  std::vector<uint16_t> w1t((size_t)(K * H));
+  for (int64_t k = 0; k < K; ++k)
+    for (int64_t h = 0; h < H; ++h) w1t[(size_t)(h * K + k)] = d->w1[k * H + h];
+  std::vector<float> wf;
+  wf.insert(wf.end(), d->b1, d->b1 + H);
+  wf.insert(wf.end(), d->w2, d->w2 + H * H);
+  wf.insert(wf.end(), d->b2, d->b2 + H);
+  wf.insert(wf.end(), d->w3, d->w3 + H * A);
+  wf.insert(wf.end(), d->b3, d->b3 + A);
+  for (float v : wf)
+    if (!std::isfinite(v)) return fail(VUDA_EINVAL, "non-finite policy weight");
+  hipError_t e = hipMalloc(&p.w1t, 2 * w1t.size());
+  if (e == hipSuccess) e = hipMalloc(&p.wf, 4 * wf.size());
+  if (e == hipSuccess) e = hipMalloc(&w->actions, 4 * (size_t)w->cap_envs * A);
+  if (e == hipSuccess) e = hipMalloc(&w->act_on, (size_t)w->cap_envs);
+  w->pol = p;  // freed by free_policy on any failure below
+  if (e != hipSuccess) {
+    w->free_policy();
+    return fail(VUDA_ENOMEM, "policy buffers: %s", hipGetErrorString(e));
+  }
+  HIPCHK(hipMemcpy(w->pol.w1t, w1t.data(), 2 * w1t.size(), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(w->pol.wf, wf.data(), 4 * wf.size(), hipMemcpyHostToDevice));
+  HIPCHK(hipMemset(w->actions, 0, 4 * (size_t)w->cap_envs * A));
+  HIPCHK(hipMemset(w->act_on, 0, (size_t)w->cap_envs));
+  w->pol.set = true;
+  w->dev.actions = w->actions;
+  w->dev.act_on = w->act_on;
+  w->dev.act_dim = (int32_t)A;
+  return VUDA_OK;
+}
+
+extern "C" int vuda_act(vuda_world* w, int32_t lo, int32_t hi) {
+  if (!w) return fail(VUDA_EINVAL, "null world");
+  int rc = w->check_range(lo, hi);
+  if (rc) return rc;
+  if (!w->pol.set) return fail(VUDA_EINVAL, "no policy (vuda_policy_set)");
+  if (lo == hi) return VUDA_OK;
+  for (int32_t e = lo; e < hi; ++e) {
+    if (!w->env_active[e]) continue;
+    const EnvDev& d = w->env_host[e];
+    if (d.n_cams < 1) return fail(VUDA_EINVAL, "env %d has no camera", e);
+    const CamDev& c = w->cam_host[d.cam_off];
+    if (c.w != w->pol.in_w || c.h != w->pol.in_h)
+      return fail(VUDA_EINVAL, "env %d: camera 0 is %dx%d, the policy reads %dx%d", e, c.w, c.h, w->pol.in_w,
+                  w->pol.in_h);
+    if (c.pix_off % 8 != 0) return fail(VUDA_EINVAL, "env %d: frame offset %lld not a multiple of 8", e,
+                                        (long long)c.pix_off);
+  }
+  const WorkList* L;
+  rc = w->get_list(VUDA_PHASE_STEP, lo, hi, &L);
+  if (rc) return rc;
+  {
+    // layer-1 partial sums: grown here, outside any graph capture; graphs
+    // that hold the old buffer go with it
+    const int64_t need = (int64_t)policy_splits(L->n, w->pol.H, 4 * w->pol.in_w * w->pol.in_h) * L->n * w->pol.H;
+    if (need > w->pol.partial_cap) {
+      rc = w->drain();
+      if (rc) return rc;
+      for (auto& g : w->graphs) (void)hipGraphExecDestroy(g.second);
+      w->graphs.clear();
+      if (w->pol.partial) HIPCHK(hipFree(w->pol.partial));
+      w->pol.partial = nullptr;
+      w->pol.partial_cap = 0;
+      HIPCHK(hipMalloc(&w->pol.partial, 4 * (size_t)need));
+      w->pol.partial_cap = need;
+    }
+  }
+  hipStream_t s = w->s_sim;
+  if (w->mode != 0) {
+    // RAW: the renders that wrote the frames read here (of each env's
+    // current state buffer)
+    int64_t last = -1;
+    for (int32_t e = lo; e < hi; ++e)
+      if (w->env_active[e]) last = std::max(last, w->render_ev[w->env_parity[e]][e]);
+    rc = w->wait_event(s, last);
+    if (rc) return rc;
+  }
+  rc = w->run_kernel(kKernelPolicy, *L, 0, lo, hi, s, nullptr);
+  if (rc) return rc;
+  if (w->mode != 0) {
+    // a later render of these envs overwrites the frames read here: it
+    // waits for this event as for a step's
+    int64_t id;
+    rc = w->new_event(s, &id);
+    if (rc) return rc;
+    for (int32_t e = lo; e < hi; ++e)
+      if (w->env_active[e]) w->step_ev[e] = id;
+  }
+  return VUDA_OK;
+}
+
+// ---------------------------------------------------------------------------
 // fetch / load
 // ---------------------------------------------------------------------------
 
@@ -1033,7 +1210,7 @@ static int env_runs(vuda_world* w, int32_t lo, int32_t hi, int what, std::vector
     if (what == VUDA_FETCH_STATE) {
       s = d.body_off;
       n = d.n_bodies;
-    } else if (what == VUDA_FETCH_CONTACTS || what == VUDA_FETCH_FLAGS) {
+    } else if (what == VUDA_FETCH_CONTACTS || what == VUDA_FETCH_FLAGS || what == VUDA_FETCH_ACTIONS) {
       s = e;
       n = 1;
     } else {
@@ -1060,6 +1237,7 @@ static size_t elem_bytes(vuda_world* w, int what) {
     case VUDA_FETCH_COVERAGE: return 4;
     case VUDA_FETCH_CONTACTS: return 4 * (size_t)w->phys.substeps * (1 + 2 * (size_t)w->pair_cap);
     case VUDA_FETCH_FLAGS: return 4;
+    case VUDA_FETCH_ACTIONS: return w->pol.set ? 4 * (size_t)w->pol.A : 0;
     default: return 0;
   }
 }
@@ -1144,6 +1322,7 @@ extern "C" int vuda_fetch(vuda_world* w, int32_t what, int32_t lo, int32_t hi, v
     case VUDA_FETCH_COVERAGE: base = (const unsigned char*)w->dev.coverage; break;
     case VUDA_FETCH_CONTACTS: base = (const unsigned char*)w->dev.contacts; break;
     case VUDA_FETCH_FLAGS: base = (const unsigned char*)w->dev.env_flags; break;
+    case VUDA_FETCH_ACTIONS: base = (const unsigned char*)w->actions; break;
   }
   int64_t pos = 0;
   for (auto& r : runs) {
@@ -1245,6 +1424,8 @@ extern "C" int vuda_admit(vuda_world* w, const vuda_env_batch* b, int32_t parity
     w->render_ev[0][e0 + e] = -1;
     w->render_ev[1][e0 + e] = -1;
   }
+  // a reused slot starts without the policy's forces of its last env
+  if (w->act_on) HIPCHK(hipMemset(w->act_on + e0, 0, (size_t)b->n_envs));
   w->n_envs_hi = std::max<int32_t>(w->n_envs_hi, (int32_t)(e0 + b->n_envs));
   *first_env = (int32_t)e0;
   return VUDA_OK;
@@ -1360,7 +1541,7 @@ extern "C" int vuda_get_tuning(vuda_world* w, int32_t key, int32_t* value) {
 extern "C" int vuda_kernel_times(vuda_world* w, int32_t kernel, int64_t* launches, double* total_ms,
                                  double* max_ms) {
   if (!w) return fail(VUDA_EINVAL, "null world");
-  if (kernel < VUDA_KERNEL_PHYSICS || kernel > VUDA_KERNEL_RASTER_TILES) return fail(VUDA_EINVAL, "kernel %d", kernel);
+  if (kernel < VUDA_KERNEL_PHYSICS || kernel > VUDA_KERNEL_POLICY) return fail(VUDA_EINVAL, "kernel %d", kernel);
   const int k = kernel - VUDA_KERNEL_PHYSICS;
   const size_t n = w->tev_used[k];
   double sum = 0.0, mx = 0.0;

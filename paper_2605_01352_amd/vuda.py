@@ -18,14 +18,14 @@ LIB_PATH = os.path.join(HERE, "lib", "libvuda.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENUMERIC, EOVERFLOW, EBUSY = 0, -1, -2, -3, -4, -5, -6
 PHASE_STEP, PHASE_RENDER, PHASE_ALL = 1, 2, 3
-FETCH_STATE, FETCH_RGB, FETCH_DEPTH, FETCH_CONTACTS, FETCH_WINNERS, FETCH_COVERAGE, FETCH_FLAGS = range(7)
+FETCH_STATE, FETCH_RGB, FETCH_DEPTH, FETCH_CONTACTS, FETCH_WINNERS, FETCH_COVERAGE, FETCH_FLAGS, FETCH_ACTIONS = range(8)
 FLAG_DEBUG = 1
 TUNE_RASTER_THREADS, TUNE_REC_CAP, TUNE_PHYS_PERSISTENT, TUNE_RASTER_PERSISTENT, TUNE_GRAPHS = 1, 2, 3, 4, 5
 TUNE_PHYS_PRIORITY = 6
 TUNE_BROADPHASE = 7
 TUNE_TIMING = 8
 TUNE_PRESETUP = 9
-KERNEL_PHYSICS, KERNEL_RASTER_SETUP, KERNEL_RASTER_TILES = 1, 2, 3
+KERNEL_PHYSICS, KERNEL_RASTER_SETUP, KERNEL_RASTER_TILES, KERNEL_POLICY = 1, 2, 3, 4
 GROUND = 0xFFFF
 
 EXPORTS = [
@@ -35,7 +35,7 @@ EXPORTS = [
     "vuda_probe_placement", "vuda_strerror", "vuda_last_error_message", "vuda_run",
     "vuda_autotune", "vuda_serve_create", "vuda_serve_destroy", "vuda_serve_submit",
     "vuda_serve_tick", "vuda_serve_completed", "vuda_serve_result", "vuda_serve_stats",
-    "vuda_serve_world", "vuda_kernel_times",
+    "vuda_serve_world", "vuda_kernel_times", "vuda_policy_set", "vuda_act",
 ]
 SCHED_SERIAL, SCHED_INTERSTEP, SCHED_INTERTRAJ = 0, 1, 2
 SCHED_NAMES = {SCHED_SERIAL: "serial", SCHED_INTERSTEP: "interstep", SCHED_INTERTRAJ: "intertraj"}
@@ -90,6 +90,12 @@ class TuneResult(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class PolicyDesc(C.Structure):
+    _fields_ = [("in_w", C.c_int32), ("in_h", C.c_int32), ("hidden", C.c_int32), ("act_bodies", C.c_int32),
+                ("a_max", C.c_float), ("w1", C.c_void_p), ("b1", C.c_void_p), ("w2", C.c_void_p),
+                ("b2", C.c_void_p), ("w3", C.c_void_p), ("b3", C.c_void_p)]
 
 
 class ServeStats(C.Structure):
@@ -264,6 +270,25 @@ class World:
         hi = self.n_envs if hi is None else hi
         check(lib().vuda_render(self._w, lo, hi))
 
+    def set_policy(self, policy: Optional[Dict]):
+        """Install an MLP policy (keys in_w, in_h, act_bodies, a_max,
+        w1_bf16 [K, H] uint16 bfloat16 bits, b1, w2, b2, w3, b3), or remove
+        it (None)."""
+        if policy is None:
+            check(lib().vuda_policy_set(self._w, None))
+            return
+        P = policy
+        keep = [np.ascontiguousarray(P["w1_bf16"], np.uint16)]
+        keep += [np.ascontiguousarray(P[k], np.float32) for k in ("b1", "w2", "b2", "w3", "b3")]
+        d = PolicyDesc(int(P["in_w"]), int(P["in_h"]), int(keep[1].shape[0]), int(P["act_bodies"]),
+                       float(P["a_max"]), *[a.ctypes.data for a in keep])
+        check(lib().vuda_policy_set(self._w, C.byref(d)))
+
+    def act(self, lo: int = 0, hi: Optional[int] = None):
+        """Enqueue the policy on envs [lo, hi): actions for their next steps."""
+        hi = self.n_envs if hi is None else hi
+        check(lib().vuda_act(self._w, lo, hi))
+
     def wait(self, phase: int = PHASE_ALL):
         check(lib().vuda_wait(self._w, phase))
 
@@ -320,7 +345,7 @@ class World:
             return out
         dt = {FETCH_STATE: np.float32, FETCH_RGB: np.uint8, FETCH_DEPTH: np.uint32,
               FETCH_CONTACTS: np.int32, FETCH_WINNERS: np.int32, FETCH_COVERAGE: np.int32,
-              FETCH_FLAGS: np.uint32}[what]
+              FETCH_FLAGS: np.uint32, FETCH_ACTIONS: np.float32}[what]
         buf = np.zeros(nbytes // np.dtype(dt).itemsize, dt)
         check(lib().vuda_fetch(self._w, what, lo, hi, _p(buf), C.c_size_t(nbytes), 0))
         return buf

@@ -96,15 +96,24 @@ __global__ __launch_bounds__(256) void policy_l1_kernel(WorldDev W, PolicyLaunch
 
   uint4 stage = rvalid ? obs8(rgb, dep, kbeg + kq, krgb) : make_uint4(0, 0, 0, 0);
   *(uint4*)&sA[0][r * kLdsRow + kq] = stage;
+  // W1 fragments run one step ahead of the MFMAs that use them
+  uint4 bn[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) bn[cb] = *(const uint4*)(bcol[cb] + kbeg);
   __syncthreads();
   for (int t = 0; t < nsteps; ++t) {
     const int k = kbeg + t * kKStep;
     const int buf = t & 1;
-    // next step's observation values, converted while this step multiplies
-    if (t + 1 < nsteps) stage = rvalid ? obs8(rgb, dep, k + kKStep + kq, krgb) : make_uint4(0, 0, 0, 0);
     bf16x8 b[4];
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) b[cb] = __builtin_bit_cast(bf16x8, *(const uint4*)(bcol[cb] + k));
+    for (int cb = 0; cb < 4; ++cb) b[cb] = __builtin_bit_cast(bf16x8, bn[cb]);
+    // next step's W1 fragments and observation values, in flight while this
+    // step multiplies
+    if (t + 1 < nsteps) {
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) bn[cb] = *(const uint4*)(bcol[cb] + k + kKStep);
+      stage = rvalid ? obs8(rgb, dep, k + kKStep + kq, krgb) : make_uint4(0, 0, 0, 0);
+    }
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
       const bf16x8 a = __builtin_bit_cast(bf16x8, *(const uint4*)&sA[buf][(16 * rb + (lane & 15)) * kLdsRow + 8 * (lane >> 4)]);
@@ -140,23 +149,50 @@ __global__ __launch_bounds__(1024) void policy_head_kernel(WorldDev W, PolicyLau
   const int j = threadIdx.x, H = L.H;
   float* h1 = sh;
   float* h2 = sh + H;
+  // loads go out eight at a time; the sums still run in index order
   if (j < H) {
+    const float* p = L.partial + (int64_t)m * H + j;
+    const int64_t stride = (int64_t)L.M * H;
     float s1 = 0.0f;
-    for (int s = 0; s < L.splits; ++s) s1 = s1 + L.partial[((int64_t)s * L.M + m) * H + j];
+    int s = 0;
+    for (; s + 8 <= L.splits; s += 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = p[(s + u) * stride];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s1 = s1 + v[u];
+    }
+    for (; s < L.splits; ++s) s1 = s1 + p[s * stride];
     s1 = s1 + L.b1[j];
     h1[j] = s1 > 0.0f ? s1 : 0.0f;
   }
   __syncthreads();
   if (j < H) {
     float s2 = 0.0f;
-    for (int i = 0; i < H; ++i) s2 = s2 + h1[i] * L.w2[(int64_t)i * H + j];
+    int i = 0;
+    for (; i + 8 <= H; i += 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = L.w2[(int64_t)(i + u) * H + j];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s2 = s2 + h1[i + u] * v[u];
+    }
+    for (; i < H; ++i) s2 = s2 + h1[i] * L.w2[(int64_t)i * H + j];
     s2 = s2 + L.b2[j];
     h2[j] = s2 > 0.0f ? s2 : 0.0f;
   }
   __syncthreads();
   for (int q = j; q < L.A; q += blockDim.x) {
     float y = 0.0f;
-    for (int i = 0; i < H; ++i) y = y + h2[i] * L.w3[(int64_t)i * L.A + q];
+    int i = 0;
+    for (; i + 8 <= H; i += 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = L.w3[(int64_t)(i + u) * L.A + q];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) y = y + h2[i + u] * v[u];
+    }
+    for (; i < H; ++i) y = y + h2[i] * L.w3[(int64_t)i * L.A + q];
     y = y + L.b3[q];
     const float c = __builtin_amdgcn_fmed3f(y, -1.0f, 1.0f);  // y is finite: the clamp
     W.actions[(int64_t)env * L.A + q] = L.a_max * c;

@@ -1044,13 +1044,14 @@ void vuda_world::free_policy() {
   dev.act_dim = 0;
 }
 
-// Layer-1 split: enough workgroups to fill the chip (about 4 per CU), each
-// with at least 4 MFMA steps of 32; the split count divides K / 32.
+// Layer-1 split: enough workgroups to fill the chip once (two per CU, as
+// many as its registers let stay resident), each with at least 4 MFMA steps
+// of 32; the split count divides K / 32.
 static int policy_splits(int32_t M, int32_t H, int32_t K) {
   const int64_t tiles = (int64_t)((M + 63) / 64) * ((H + 255) / 256);
   const int32_t steps = K / 32;
   int s = 1;
-  while (tiles * s < 1024 && steps % (2 * s) == 0 && steps / (2 * s) >= 4) s *= 2;
+  while (tiles * s < 512 && steps % (2 * s) == 0 && steps / (2 * s) >= 4) s *= 2;
   return s;
 }
 

@@ -241,6 +241,8 @@ def main():
     ap.add_argument("--tune", default="", help="tuning knobs key=value,... (e.g. raster_threads=512)")
     ap.add_argument("--policy-hidden", type=int, default=256,
                     help="hidden units of the MLP policy loop measured after the main run (0: skip)")
+    ap.add_argument("--policy-profile", type=int, default=0,
+                    help="only render once and run this many policy launches (for rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the envs are independent and a multi-GPU run would "
@@ -271,6 +273,16 @@ def main():
     for kv in filter(None, args.tune.split(",")):
         k, v = kv.split("=")
         w.set_tuning(knob_ids[k], int(v))
+    if args.policy_profile:
+        w.set_policy(sg.policy_weights(2605, int(scene.cam_w[0]), int(scene.cam_h[0]), args.policy_hidden, 32))
+        w.step(nsteps=5)
+        w.render()
+        for _ in range(args.policy_profile):
+            w.act()
+        w.wait()
+        log(f"policy profile run: {args.policy_profile} launches")
+        w.close()
+        return
     if args.profile:
         w.cosched(0.0)
         dt_s = timed(torch, w, "serial", n_envs, args.profile, 2, st0)

@@ -167,7 +167,7 @@ def policy_bench(torch, vuda, sg, scene, w, st0, steps, warmup, hidden, log):
         dt = time.perf_counter() - t0
         w.wait()
         out[name] = round(n * steps / dt, 1)
-        log(f"policy loop ({name}): {n * steps / dt:.0f} env-steps/s")
+        log(f"policy loop (hidden {hidden}, {name}): {n * steps / dt:.0f} env-steps/s")
     # the policy launch alone, all envs at once
     w.cosched(0.0)
     w.set_tuning(vuda.TUNE_TIMING, 1)
@@ -184,10 +184,13 @@ def policy_bench(torch, vuda, sg, scene, w, st0, steps, warmup, hidden, log):
     flops = 2.0 * n * out["obs"] * hidden
     out["launch_us"] = round(us, 2)
     out["layer1_flops_per_launch"] = flops
+    # layers 2 and 3 (float32), not counted in the roofline figure
+    out["layers23_flops_per_launch"] = 2.0 * n * hidden * (hidden + 3 * 32)
     out["roofline"] = {"bound": "mfma", "achieved": round(flops / (us * 1e-6) / 1e12, 2),
                        "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                        "frac": round(flops / (us * 1e-6) / 1e12 / BF16_PEAK_TFLOPS, 5)}
-    log(f"policy launch: {us:.1f} us, layer 1 {flops / (us * 1e-6) / 1e12:.1f} TFLOP/s (bf16 MFMA)")
+    log(f"policy launch (hidden {hidden}): {us:.1f} us, layer 1 {flops / (us * 1e-6) / 1e12:.1f} TFLOP/s "
+        f"(bf16 MFMA)")
     w.set_policy(None)
     return out
 
@@ -239,11 +242,15 @@ def main():
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--tune", default="", help="tuning knobs key=value,... (e.g. raster_threads=512)")
-    ap.add_argument("--policy-hidden", type=int, default=256,
-                    help="hidden units of the MLP policy loop measured after the main run (0: skip)")
+    ap.add_argument("--policy-hidden", default="256,4096",
+                    help="hidden sizes of the MLP policy loops measured after the main run (0: skip); "
+                         "the profiling modes take the first")
     ap.add_argument("--policy-profile", type=int, default=0,
                     help="only render once and run this many policy launches (for rocprofv3)")
+    ap.add_argument("--policy-loop", type=int, default=0,
+                    help="only time the policy loop, this many steps per schedule (for rocprofv3)")
     args = ap.parse_args()
+    hiddens = [int(h) for h in args.policy_hidden.split(",") if int(h) > 0]
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the envs are independent and a multi-GPU run would "
               f"shard them with no exchange; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -274,13 +281,17 @@ def main():
         k, v = kv.split("=")
         w.set_tuning(knob_ids[k], int(v))
     if args.policy_profile:
-        w.set_policy(sg.policy_weights(2605, int(scene.cam_w[0]), int(scene.cam_h[0]), args.policy_hidden, 32))
+        w.set_policy(sg.policy_weights(2605, int(scene.cam_w[0]), int(scene.cam_h[0]), hiddens[0], 32))
         w.step(nsteps=5)
         w.render()
         for _ in range(args.policy_profile):
             w.act()
         w.wait()
         log(f"policy profile run: {args.policy_profile} launches")
+        w.close()
+        return
+    if args.policy_loop:
+        policy_bench(torch, vuda, sg, scene, w, st0, args.policy_loop, 4, hiddens[0], log)
         w.close()
         return
     if args.profile:
@@ -375,10 +386,10 @@ def main():
             **{k: kinds[k] for k in step_bytes}}
 
     policy = None
-    if args.policy_hidden > 0 and not args.only:
+    if hiddens and not args.only:
         if len(set(zip(scene.cam_w.tolist(), scene.cam_h.tolist()))) == 1:
-            policy = policy_bench(torch, vuda, sg, scene, w, st0, min(args.steps, 200), 10,
-                                  args.policy_hidden, log)
+            policy = [policy_bench(torch, vuda, sg, scene, w, st0, min(args.steps, 200), 10, h, log)
+                      for h in hiddens]
         else:
             log("policy loop skipped: the policy reads one frame size, the cameras differ")
 

@@ -254,7 +254,15 @@ int vuda_world_info(vuda_world* w, int32_t* n_envs, int64_t* n_bodies, int32_t* 
  *                              0: vuda_render does both.  A render of a state
  *                              without setup (after creation, vuda_load_state
  *                              or a step with this off) does its own setup
- * None of them changes any output bit.  Returns VUDA_EINVAL for unknown keys
+ *   VUDA_TUNE_POLICY_LAYERED   1: layers 2 and 3 of the policy run as batched
+ *                              float32 MFMA products over all envs at any
+ *                              hidden size (a multiple of 64; vuda_act returns
+ *                              VUDA_EINVAL otherwise); 0 (default): only above
+ *                              hidden 1024, the per-env head kernel below.
+ *                              Changes the float32 summation order of layers
+ *                              2 and 3 (the actions stay within the same
+ *                              error bound of the exact ones)
+ * None of the others changes any output bit.  Returns VUDA_EINVAL for unknown keys
  * or out-of-range values.
  */
 #define VUDA_TUNE_RASTER_THREADS 1
@@ -266,6 +274,7 @@ int vuda_world_info(vuda_world* w, int32_t* n_envs, int64_t* n_bodies, int32_t* 
 #define VUDA_TUNE_BROADPHASE 7
 #define VUDA_TUNE_TIMING 8
 #define VUDA_TUNE_PRESETUP 9
+#define VUDA_TUNE_POLICY_LAYERED 10
 int vuda_set_tuning(vuda_world* w, int32_t key, int32_t value);
 int vuda_get_tuning(vuda_world* w, int32_t key, int32_t* value);
 
@@ -303,15 +312,20 @@ int vuda_kernel_times(vuda_world* w, int32_t kernel, int64_t* launches, double* 
  * below the env's body count), added to the body's contact forces on every
  * substep of each following vuda_step until the next vuda_act.  Layer 1 runs
  * in bfloat16 products (exact: 8-bit inputs) with float32 sums; layers 2 and
- * 3 in float32.
+ * 3 in float32 (per env up to hidden 1024, as batched MFMA products above,
+ * and at any hidden size with VUDA_TUNE_POLICY_LAYERED).
  *
  * vuda_policy_set copies the weights (the caller keeps ownership of desc and
  * its arrays) and clears every env's actions; desc = NULL removes the policy
  * and the forces.  It waits for the world's queued work.  VUDA_EINVAL for a
- * frame whose pixel count is not a multiple of 32, hidden outside 1..1024,
- * act_bodies outside 1..1024, a_max negative or non-finite, null arrays or
+ * frame whose pixel count is not a multiple of 32, hidden outside 1..8192
+ * or above 1024 and not a multiple of 64, act_bodies outside 1..1024, a_max negative or non-finite, null arrays or
  * non-finite weights; VUDA_ENOMEM when the device buffers (weights, and
- * cap_envs x 3 act_bodies floats of actions) do not fit.
+ * cap_envs x 3 act_bodies floats of actions) do not fit.  vuda_act grows
+ * the policy's float32 workspace when a launch needs more (draining the
+ * world's queued work first): layer-1 partial sums, splits x envs x H
+ * floats, splits chosen so that the launch fills the GPU once, plus for the
+ * layered head h1 and h2 (2 x envs x H).
  *
  * vuda_act enqueues the policy on the active envs in [env_lo, env_hi), on
  * the step stream after the renders of their current state, and returns;

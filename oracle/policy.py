@@ -49,12 +49,18 @@ def observation(rgb: np.ndarray, depth: np.ndarray) -> np.ndarray:
 
 
 def prepare(P: Dict) -> Dict:
-    """P with the float64 values of W1 added (key w1), for repeated calls."""
-    return dict(P, w1=bf16_to_f64(P["w1_bf16"]))
+    """P with the float64 values of W1 and their magnitudes added (keys w1,
+    w1abs), for repeated calls."""
+    w1 = bf16_to_f64(P["w1_bf16"])
+    return dict(P, w1=w1, w1abs=np.abs(w1))
 
 
 def _w1(P: Dict) -> np.ndarray:
     return P["w1"] if "w1" in P else bf16_to_f64(P["w1_bf16"])
+
+
+def _w1abs(P: Dict) -> np.ndarray:
+    return P["w1abs"] if "w1abs" in P else np.abs(_w1(P))
 
 
 def forward(x: np.ndarray, P: Dict[str, np.ndarray]) -> Tuple[np.ndarray, Dict[str, np.ndarray]]:
@@ -84,7 +90,7 @@ def error_bound(x: np.ndarray, P: Dict[str, np.ndarray], inner: Dict[str, np.nda
     pass on through the absolute weights (relu and clamp are 1-Lipschitz)."""
     u = 2.0 ** -23
     g = lambda n: lam * np.sqrt(n) * u
-    W1 = np.abs(_w1(P))
+    W1 = _w1abs(P)
     W2 = np.abs(P["w2"].astype(np.float64))
     W3 = np.abs(P["w3"].astype(np.float64))
     K, H = W1.shape

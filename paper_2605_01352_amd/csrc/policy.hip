@@ -13,8 +13,13 @@
 // value is an 8-bit integer, exact in bfloat16, so each product is exact and
 // only the float32 accumulation rounds.  K is split over workgroups (partial
 // sums in float32, added in a fixed order by the head), so that a batch of a
-// few hundred envs still fills 256 CUs.  Layers 2 and 3 are small (H^2 and
-// H A per env) and run on the VALU in the head kernel, one workgroup per env.
+// few hundred envs still fills 256 CUs.  Up to H = 1024, layers 2 and 3 are
+// small (H^2 and H A per env) and run on the VALU in one head kernel, one
+// workgroup per env.  Wider policies (H = 4096: 16.8 M multiply-adds per env
+// in layer 2) run layers 2 and 3 as batched products over all envs on
+// float32 MFMA (v_mfma_f32_16x16x4_f32), each split over K like layer 1,
+// with small kernels that add the splits in order and apply the bias and the
+// activation.
 #include "vuda_internal.h"
 
 #pragma clang fp contract(off)
@@ -138,6 +143,46 @@ __global__ __launch_bounds__(256) void policy_l1_kernel(WorldDev W, PolicyLaunch
     }
 }
 
+// sum_{s < n} p[s * stride], in s order; the loads go out kBatch at a time
+// (independent, so their latencies overlap), the additions stay in order
+template <int kBatch>
+__device__ __forceinline__ float ordered_strided_sum(const float* p, int64_t stride, int n) {
+  float acc = 0.0f;
+  int s = 0;
+  for (; s + kBatch <= n; s += kBatch) {
+    float v[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) v[u] = p[(s + u) * stride];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) acc = acc + v[u];
+  }
+  for (; s < n; ++s) acc = acc + p[s * stride];
+  return acc;
+}
+
+// sum_{i < n} x[i] w[i * stride] in i order (x in LDS), loads kBatch at a time
+template <int kBatch>
+__device__ __forceinline__ float ordered_dot(const float* x, const float* w, int64_t stride, int n) {
+  float acc = 0.0f;
+  int i = 0;
+  for (; i + kBatch <= n; i += kBatch) {
+    float v[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) v[u] = w[(i + u) * stride];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) acc = acc + x[i + u] * v[u];
+  }
+  for (; i < n; ++i) acc = acc + x[i] * w[i * stride];
+  return acc;
+}
+
+__device__ __forceinline__ float relu(float v) { return v > 0.0f ? v : 0.0f; }
+
+// a_max clamp(y, -1, 1) for a finite y
+__device__ __forceinline__ float action_of(float y, float a_max) {
+  return a_max * __builtin_amdgcn_fmed3f(y, -1.0f, 1.0f);
+}
+
 // Layers 2 and 3, one workgroup per env (blockDim = H rounded up to 64,
 // at most 1024): the split-K partials added in split order, then every unit
 // on its own lane, its dot product in index order.
@@ -149,55 +194,119 @@ __global__ __launch_bounds__(1024) void policy_head_kernel(WorldDev W, PolicyLau
   const int j = threadIdx.x, H = L.H;
   float* h1 = sh;
   float* h2 = sh + H;
-  // loads go out eight at a time; the sums still run in index order
   if (j < H) {
-    const float* p = L.partial + (int64_t)m * H + j;
-    const int64_t stride = (int64_t)L.M * H;
-    float s1 = 0.0f;
-    int s = 0;
-    for (; s + 8 <= L.splits; s += 8) {
-      float v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = p[(s + u) * stride];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) s1 = s1 + v[u];
-    }
-    for (; s < L.splits; ++s) s1 = s1 + p[s * stride];
-    s1 = s1 + L.b1[j];
-    h1[j] = s1 > 0.0f ? s1 : 0.0f;
+    const float s1 = ordered_strided_sum<16>(L.partial + (int64_t)m * H + j, (int64_t)L.M * H, L.splits);
+    h1[j] = relu(s1 + L.b1[j]);
   }
   __syncthreads();
-  if (j < H) {
-    float s2 = 0.0f;
-    int i = 0;
-    for (; i + 8 <= H; i += 8) {
-      float v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = L.w2[(int64_t)(i + u) * H + j];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) s2 = s2 + h1[i + u] * v[u];
-    }
-    for (; i < H; ++i) s2 = s2 + h1[i] * L.w2[(int64_t)i * H + j];
-    s2 = s2 + L.b2[j];
-    h2[j] = s2 > 0.0f ? s2 : 0.0f;
-  }
+  if (j < H) h2[j] = relu(ordered_dot<32>(h1, L.w2 + j, H, H) + L.b2[j]);
   __syncthreads();
-  for (int q = j; q < L.A; q += blockDim.x) {
-    float y = 0.0f;
-    int i = 0;
-    for (; i + 8 <= H; i += 8) {
-      float v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = L.w3[(int64_t)(i + u) * L.A + q];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) y = y + h2[i + u] * v[u];
-    }
-    for (; i < H; ++i) y = y + h2[i] * L.w3[(int64_t)i * L.A + q];
-    y = y + L.b3[q];
-    const float c = __builtin_amdgcn_fmed3f(y, -1.0f, 1.0f);  // y is finite: the clamp
-    W.actions[(int64_t)env * L.A + q] = L.a_max * c;
-  }
+  for (int q = j; q < L.A; q += blockDim.x)
+    W.actions[(int64_t)env * L.A + q] = action_of(ordered_dot<32>(h2, L.w3 + q, L.A, H) + L.b3[q], L.a_max);
   if (j == 0) W.act_on[env] = 1;
+}
+
+// ---- layers 2 and 3 as batched products (H > 1024) ----
+
+// out[m][j] = relu(sum_s P[s][m][j] + b[j]) for j < N, P with row stride N
+__global__ __launch_bounds__(256) void policy_hidden_kernel(const float* P, int splits, int M, int N, const float* b,
+                                                            float* out) {
+  const int m = blockIdx.y;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (m >= M || j >= N) return;
+  const int64_t at = (int64_t)m * N + j;
+  out[at] = relu(ordered_strided_sum<16>(P + at, (int64_t)M * N, splits) + b[j]);
+}
+
+// actions of row m: a_max clamp(sum_s P[s][m][q] + b3[q]) for q < A, P with
+// row stride ldp; and the env's force flag
+__global__ __launch_bounds__(256) void policy_act_kernel(WorldDev W, PolicyLaunch L, const float* P, int splits,
+                                                         int ldp) {
+  const int m = blockIdx.x;
+  if (m >= L.M) return;
+  const int env = L.envs[m];
+  for (int q = threadIdx.x; q < L.A; q += blockDim.x) {
+    const float y = ordered_strided_sum<16>(P + (int64_t)m * ldp + q, (int64_t)L.M * ldp, splits);
+    W.actions[(int64_t)env * L.A + q] = action_of(y + L.b3[q], L.a_max);
+  }
+  if (threadIdx.x == 0) W.act_on[env] = 1;
+}
+
+constexpr int kDTile = 64;   // rows and columns of a dense-product workgroup tile
+constexpr int kDStep = 16;   // k per staged step
+constexpr int kAPitch = 20;  // floats per staged A row (16 + 4: lanes of one read hit distinct banks)
+constexpr int kBPitch = 80;  // floats per staged B row (64 + 16)
+
+// P[s][m][n] = sum_{k in chunk s} X[m][k] B[k][n] for m < M, n < ldb: X is
+// [M][K] and B [K][ldb] row-major float32, K and ldb multiples of 64, chunk
+// a multiple of kDStep.  Workgroup: a 64 x 64 tile of one chunk; wave w
+// owns the 32 x 32 quadrant (w & 1, w >> 1), 2 x 2 blocks of 16 x 16.
+__global__ __launch_bounds__(256) void policy_dense_kernel(const float* X, const float* B, int M, int K, int ldb,
+                                                           int kchunk, float* P) {
+  __shared__ __align__(16) float sA[2][kDTile * kAPitch];
+  __shared__ __align__(16) float sB[2][kDStep * kBPitch];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int m0 = blockIdx.x * kDTile, n0 = blockIdx.y * kDTile, s = blockIdx.z;
+  const int wm = 32 * (wave & 1), wn = 32 * (wave >> 1);
+  const int kbeg = s * kchunk, nsteps = kchunk / kDStep;
+  // staging roles: X row ar, columns ac .. ac+3; B row br, columns bc .. bc+3
+  const int ar = tid >> 2, ac = 4 * (tid & 3);
+  const int br = tid >> 4, bc = 4 * (tid & 15);
+  const bool a_ok = m0 + ar < M;
+  const float* xa = X + (int64_t)(a_ok ? m0 + ar : 0) * K + ac;
+  const float* bb = B + (int64_t)br * ldb + n0 + bc;
+  const float4 zero = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  float4 ra = a_ok ? *(const float4*)(xa + kbeg) : zero;
+  float4 rb = *(const float4*)(bb + (int64_t)kbeg * ldb);
+  *(float4*)&sA[0][ar * kAPitch + ac] = ra;
+  *(float4*)&sB[0][br * kBPitch + bc] = rb;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  __syncthreads();
+  for (int t = 0; t < nsteps; ++t) {
+    const int buf = t & 1;
+    if (t + 1 < nsteps) {
+      const int k = kbeg + (t + 1) * kDStep;
+      ra = a_ok ? *(const float4*)(xa + k) : zero;
+      rb = *(const float4*)(bb + (int64_t)k * ldb);
+    }
+    // operands of v_mfma_f32_16x16x4_f32: lane l holds A[l % 16][l / 16]
+    // and B[l / 16][l % 16] of the 16 x 4 and 4 x 16 blocks
+#pragma unroll
+    for (int kk = 0; kk < kDStep; kk += 4) {
+      float a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = sA[buf][(wm + 16 * i + (lane & 15)) * kAPitch + kk + (lane >> 4)];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = sB[buf][(kk + (lane >> 4)) * kBPitch + wn + 16 * j + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (t + 1 < nsteps) {
+      *(float4*)&sA[buf ^ 1][ar * kAPitch + ac] = ra;
+      *(float4*)&sB[buf ^ 1][br * kBPitch + bc] = rb;
+    }
+    __syncthreads();
+  }
+  // D layout: lane holds rows 4 (lane / 16) + r of a block, column lane % 16
+  float* Ps = P + (int64_t)s * M * ldb;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int n = n0 + wn + 16 * j + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+        if (m < M) Ps[(int64_t)m * ldb + n] = acc[i][j][r];
+      }
+    }
 }
 
 }  // namespace
@@ -208,8 +317,22 @@ hipError_t launch_policy(const WorldDev& w, const PolicyLaunch& l, hipStream_t s
   hipLaunchKernelGGL(policy_l1_kernel, g1, dim3(256), 0, s, w, l);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int threads = (l.H + 63) / 64 * 64;
-  hipLaunchKernelGGL(policy_head_kernel, dim3(l.M), dim3(threads), 2 * l.H * sizeof(float), s, w, l);
+  if (!l.layered) {
+    const int threads = (l.H + 63) / 64 * 64;
+    hipLaunchKernelGGL(policy_head_kernel, dim3(l.M), dim3(threads), 2 * l.H * sizeof(float), s, w, l);
+    return hipGetLastError();
+  }
+  // h1, then layer 2 into the partials (free again once h1 is made), h2,
+  // layer 3, the actions
+  const int mt = (l.M + kDTile - 1) / kDTile;
+  const dim3 gh((l.H + 255) / 256, l.M);
+  hipLaunchKernelGGL(policy_hidden_kernel, gh, dim3(256), 0, s, l.partial, l.splits, l.M, l.H, l.b1, l.h1);
+  hipLaunchKernelGGL(policy_dense_kernel, dim3(mt, l.H / kDTile, l.s2), dim3(256), 0, s, l.h1, l.w2, l.M, l.H, l.H,
+                     l.H / l.s2, l.partial);
+  hipLaunchKernelGGL(policy_hidden_kernel, gh, dim3(256), 0, s, l.partial, l.s2, l.M, l.H, l.b2, l.h2);
+  hipLaunchKernelGGL(policy_dense_kernel, dim3(mt, l.Ap / kDTile, l.s3), dim3(256), 0, s, l.h2, l.w3p, l.M, l.H,
+                     l.Ap, l.H / l.s3, l.partial);
+  hipLaunchKernelGGL(policy_act_kernel, dim3(l.M), dim3(256), 0, s, w, l, l.partial, l.s3, l.Ap);
   return hipGetLastError();
 }
 

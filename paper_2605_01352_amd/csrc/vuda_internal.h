@@ -192,7 +192,15 @@ struct PolicyLaunch {
   const float* w3;         // [H][A]
   const float* b3;
   float a_max;
-  float* partial;          // [splits][M][H]
+  float* partial;          // [splits][M][H]; layered: also layer 2's [s2][M][H] and layer 3's [s3][M][Ap]
+  // layers 2 and 3 as batched products (H a multiple of 64) instead of the
+  // per-env head
+  int32_t layered;
+  int32_t s2, s3;          // K splits of layers 2 and 3 (each divides H / 16)
+  int32_t Ap;              // A rounded up to a multiple of 64
+  const float* w3p;        // [H][Ap]: W3 with zero columns beyond A
+  float* h1;               // [M][H]
+  float* h2;               // [M][H]
 };
 hipError_t launch_policy(const WorldDev& w, const PolicyLaunch& l, hipStream_t s);
 // The render work of a state buffer: setup (geometry, records, bins) into the

@@ -70,11 +70,16 @@ struct Tuning {
   int32_t broadphase = 0;
   bool timing = false;
   bool presetup = true;
+  bool policy_layered = false;  // layers 2-3 as batched products at any hidden size
 };
 
 // kernels of the step loop (index of their timing events)
 constexpr int kKernelPhysics = 0, kKernelSetup = 1, kKernelTiles = 2, kKernelPolicy = 3;
 constexpr int kKernelKinds = 4;
+
+// Hidden sizes: up to kPolicyHeadMax the per-env head kernel runs layers 2
+// and 3; above it (multiples of 64) they run as batched products.
+constexpr int32_t kPolicyHeadMax = 1024, kPolicyHiddenMax = 8192;
 
 // The MLP policy of a world (device copies of its weights).
 struct Policy {
@@ -83,6 +88,7 @@ struct Policy {
   float a_max = 0.0f;
   uint16_t* w1t = nullptr;  // [H][K] bfloat16
   float* wf = nullptr;      // b1 [H], w2 [H][H], b2 [H], w3 [H][A], b3 [A]
+  float* w3p = nullptr;     // [H][A rounded up to 64] (hidden a multiple of 64)
   float* partial = nullptr;
   int64_t partial_cap = 0;  // floats
 };

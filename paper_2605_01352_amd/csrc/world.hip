@@ -1033,6 +1033,7 @@ extern "C" int vuda_get_stream(vuda_world* w, int32_t phase, void** s) {
 void vuda_world::free_policy() {
   if (pol.w1t) (void)hipFree(pol.w1t);
   if (pol.wf) (void)hipFree(pol.wf);
+  if (pol.w3p) (void)hipFree(pol.w3p);
   if (pol.partial) (void)hipFree(pol.partial);
   if (actions) (void)hipFree(actions);
   if (act_on) (void)hipFree(act_on);
@@ -1044,18 +1045,47 @@ void vuda_world::free_policy() {
   dev.act_dim = 0;
 }
 
-// Layer-1 split: enough workgroups to fill the chip once (two per CU, as
-// many as its registers let stay resident), each with at least 4 MFMA steps
-// of 32; the split count divides K / 32.
-static int policy_splits(int32_t M, int32_t H, int32_t K) {
-  const int64_t tiles = (int64_t)((M + 63) / 64) * ((H + 255) / 256);
-  const int32_t steps = K / 32;
+// K split of a product over `tiles` output tiles: enough workgroups to fill
+// the chip once (layer 1: two per CU, as many as its registers let stay
+// resident), each chunk at least min_steps steps long (layer 1: 4 MFMA
+// steps of 32; layers 2 and 3: 8 steps of 16); the count divides `steps`.
+static int split_count(int64_t tiles, int32_t steps, int32_t min_steps) {
   int s = 1;
-  while (tiles * s < 512 && steps % (2 * s) == 0 && steps / (2 * s) >= 4) s *= 2;
+  while (tiles * s < 512 && steps % (2 * s) == 0 && steps / (2 * s) >= min_steps) s *= 2;
   return s;
 }
 
+// Launch shape of the policy over M envs: splits, whether layers 2 and 3 run
+// as batched products, and the float32 workspace that takes
+struct PolicyPlan {
+  int32_t splits = 1, s2 = 1, s3 = 1, Ap = 0;
+  bool layered = false;
+  int64_t partial_floats = 0;  // partials (and h1, h2 when layered)
+};
+
+static int policy_plan(const Policy& pol, bool force_layered, int32_t M, PolicyPlan* out) {
+  PolicyPlan p;
+  const int32_t K = 4 * pol.in_w * pol.in_h, H = pol.H;
+  p.splits = split_count((int64_t)((M + 63) / 64) * ((H + 255) / 256), K / 32, 4);
+  p.layered = force_layered || H > kPolicyHeadMax;
+  p.partial_floats = (int64_t)p.splits * M * H;
+  if (p.layered) {
+    if (H % 64 != 0) return fail(VUDA_EINVAL, "policy hidden %d: layers 2-3 as products need a multiple of 64", H);
+    const int64_t mt = (M + 63) / 64;
+    p.Ap = (pol.A + 63) / 64 * 64;
+    p.s2 = split_count(mt * (H / 64), H / 16, 8);
+    p.s3 = split_count(mt * (p.Ap / 64), H / 16, 8);
+    const int64_t most = std::max({(int64_t)p.splits * H, (int64_t)p.s2 * H, (int64_t)p.s3 * p.Ap});
+    p.partial_floats = most * M + 2 * (int64_t)M * H;
+  }
+  *out = p;
+  return VUDA_OK;
+}
+
 int vuda_world::policy_launch_of(const WorkList& L, PolicyLaunch* out) {
+  PolicyPlan plan;
+  int rc = policy_plan(pol, tune.policy_layered, L.n, &plan);
+  if (rc) return rc;
   const int32_t K = 4 * pol.in_w * pol.in_h;
   PolicyLaunch pl;
   pl.envs = L.dptr;
@@ -1064,7 +1094,7 @@ int vuda_world::policy_launch_of(const WorkList& L, PolicyLaunch* out) {
   pl.krgb = 3 * pol.in_w * pol.in_h;
   pl.H = pol.H;
   pl.A = pol.A;
-  pl.splits = policy_splits(L.n, pol.H, K);
+  pl.splits = plan.splits;
   pl.kchunk = K / pl.splits;
   pl.w1t = pol.w1t;
   pl.b1 = pol.wf;
@@ -1073,8 +1103,20 @@ int vuda_world::policy_launch_of(const WorkList& L, PolicyLaunch* out) {
   pl.w3 = pl.b2 + pol.H;
   pl.b3 = pl.w3 + (int64_t)pol.H * pol.A;
   pl.a_max = pol.a_max;
-  if ((int64_t)pl.splits * L.n * pol.H > pol.partial_cap) return fail(VUDA_EINVAL, "policy partials unsized");
+  if (plan.partial_floats > pol.partial_cap) return fail(VUDA_EINVAL, "policy partials unsized");
   pl.partial = pol.partial;
+  pl.layered = plan.layered ? 1 : 0;
+  pl.s2 = plan.s2;
+  pl.s3 = plan.s3;
+  pl.Ap = plan.Ap;
+  pl.w3p = pol.w3p;
+  pl.h1 = pl.h2 = nullptr;
+  if (plan.layered) {
+    if (!pol.w3p) return fail(VUDA_EINVAL, "policy without padded W3");
+    // h1 and h2 sit after the largest partial block
+    pl.h1 = pol.partial + (plan.partial_floats - 2 * (int64_t)L.n * pol.H);
+    pl.h2 = pl.h1 + (int64_t)L.n * pol.H;
+  }
   *out = pl;
   return VUDA_OK;
 }
@@ -1092,7 +1134,9 @@ extern "C" int vuda_policy_set(vuda_world* w, const vuda_policy_desc* d) {
   const int64_t px = (int64_t)d->in_w * d->in_h;
   if (d->in_w < 1 || d->in_h < 1 || px % 32 != 0 || 4 * px > (int64_t)1 << 30)
     return fail(VUDA_EINVAL, "policy frame %dx%d (pixels a multiple of 32)", d->in_w, d->in_h);
-  if (d->hidden < 1 || d->hidden > 1024) return fail(VUDA_EINVAL, "policy hidden %d (1..1024)", d->hidden);
+  if (d->hidden < 1 || d->hidden > kPolicyHiddenMax || (d->hidden > kPolicyHeadMax && d->hidden % 64 != 0))
+    return fail(VUDA_EINVAL, "policy hidden %d (1..%d, a multiple of 64 above %d)", d->hidden, kPolicyHiddenMax,
+                kPolicyHeadMax);
   if (d->act_bodies < 1 || d->act_bodies > 1024) return fail(VUDA_EINVAL, "policy act_bodies %d", d->act_bodies);
   if (!(d->a_max >= 0.0f) || !std::isfinite(d->a_max)) return fail(VUDA_EINVAL, "policy a_max");
   if (!d->w1 || !d->b1 || !d->w2 || !d->b2 || !d->w3 || !d->b3) return fail(VUDA_EINVAL, "null policy weights");
@@ -1104,9 +1148,12 @@ extern "C" int vuda_policy_set(vuda_world* w, const vuda_policy_desc* d) {
   p.a_max = d->a_max;
   const int64_t K = 4 * px, H = p.H, A = p.A;
   // W1 [K][H] -> [H][K], so that a unit's weights are contiguous in k
+  // (in 64 x 64 blocks: both sides stay in cache at H = 4096)
   std::vector<uint16_t> w1t((size_t)(K * H));
-  for (int64_t k = 0; k < K; ++k)
-    for (int64_t h = 0; h < H; ++h) w1t[(size_t)(h * K + k)] = d->w1[k * H + h];
+  for (int64_t k0 = 0; k0 < K; k0 += 64)
+    for (int64_t h0 = 0; h0 < H; h0 += 64)
+      for (int64_t k = k0; k < std::min(K, k0 + 64); ++k)
+        for (int64_t h = h0; h < std::min(H, h0 + 64); ++h) w1t[(size_t)(h * K + k)] = d->w1[k * H + h];
   std::vector<float> wf;
   wf.insert(wf.end(), d->b1, d->b1 + H);
   wf.insert(wf.end(), d->w2, d->w2 + H * H);
@@ -1115,8 +1162,18 @@ extern "C" int vuda_policy_set(vuda_world* w, const vuda_policy_desc* d) {
   wf.insert(wf.end(), d->b3, d->b3 + A);
   for (float v : wf)
     if (!std::isfinite(v)) return fail(VUDA_EINVAL, "non-finite policy weight");
+  // W3 with its columns padded to a multiple of 64, for layers 2-3 as
+  // batched products (hidden a multiple of 64)
+  std::vector<float> w3p;
+  const int64_t Ap = (A + 63) / 64 * 64;
+  if (H % 64 == 0) {
+    w3p.assign((size_t)(H * Ap), 0.0f);
+    for (int64_t i = 0; i < H; ++i)
+      for (int64_t q = 0; q < A; ++q) w3p[(size_t)(i * Ap + q)] = d->w3[i * A + q];
+  }
   hipError_t e = hipMalloc(&p.w1t, 2 * w1t.size());
   if (e == hipSuccess) e = hipMalloc(&p.wf, 4 * wf.size());
+  if (e == hipSuccess && !w3p.empty()) e = hipMalloc(&p.w3p, 4 * w3p.size());
   if (e == hipSuccess) e = hipMalloc(&w->actions, 4 * (size_t)w->cap_envs * A);
   if (e == hipSuccess) e = hipMalloc(&w->act_on, (size_t)w->cap_envs);
   w->pol = p;  // freed by free_policy on any failure below
@@ -1126,6 +1183,7 @@ extern "C" int vuda_policy_set(vuda_world* w, const vuda_policy_desc* d) {
   }
   HIPCHK(hipMemcpy(w->pol.w1t, w1t.data(), 2 * w1t.size(), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(w->pol.wf, wf.data(), 4 * wf.size(), hipMemcpyHostToDevice));
+  if (!w3p.empty()) HIPCHK(hipMemcpy(w->pol.w3p, w3p.data(), 4 * w3p.size(), hipMemcpyHostToDevice));
   HIPCHK(hipMemset(w->actions, 0, 4 * (size_t)w->cap_envs * A));
   HIPCHK(hipMemset(w->act_on, 0, (size_t)w->cap_envs));
   w->pol.set = true;
@@ -1158,7 +1216,10 @@ extern "C" int vuda_act(vuda_world* w, int32_t lo, int32_t hi) {
   {
     // layer-1 partial sums: grown here, outside any graph capture; graphs
     // that hold the old buffer go with it
-    const int64_t need = (int64_t)policy_splits(L->n, w->pol.H, 4 * w->pol.in_w * w->pol.in_h) * L->n * w->pol.H;
+    PolicyPlan plan;
+    rc = policy_plan(w->pol, w->tune.policy_layered, L->n, &plan);
+    if (rc) return rc;
+    const int64_t need = plan.partial_floats;
     if (need > w->pol.partial_cap) {
       rc = w->drain();
       if (rc) return rc;
@@ -1514,6 +1575,10 @@ extern "C" int vuda_set_tuning(vuda_world* w, int32_t key, int32_t value) {
       if (value < 0 || value > 1) return fail(VUDA_EINVAL, "presetup %d", value);
       w->tune.presetup = value != 0;
       return VUDA_OK;
+    case VUDA_TUNE_POLICY_LAYERED:
+      if (value < 0 || value > 1) return fail(VUDA_EINVAL, "policy layered %d", value);
+      w->tune.policy_layered = value != 0;
+      break;
     default:
       return fail(VUDA_EINVAL, "tuning key %d", key);
   }
@@ -1534,6 +1599,7 @@ extern "C" int vuda_get_tuning(vuda_world* w, int32_t key, int32_t* value) {
     case VUDA_TUNE_BROADPHASE: *value = w->tune.broadphase; break;
     case VUDA_TUNE_TIMING: *value = w->tune.timing ? 1 : 0; break;
     case VUDA_TUNE_PRESETUP: *value = w->tune.presetup ? 1 : 0; break;
+    case VUDA_TUNE_POLICY_LAYERED: *value = w->tune.policy_layered ? 1 : 0; break;
     default: return fail(VUDA_EINVAL, "tuning key %d", key);
   }
   return VUDA_OK;

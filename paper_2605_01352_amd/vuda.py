@@ -25,6 +25,7 @@ TUNE_PHYS_PRIORITY = 6
 TUNE_BROADPHASE = 7
 TUNE_TIMING = 8
 TUNE_PRESETUP = 9
+TUNE_POLICY_LAYERED = 10
 KERNEL_PHYSICS, KERNEL_RASTER_SETUP, KERNEL_RASTER_TILES, KERNEL_POLICY = 1, 2, 3, 4
 GROUND = 0xFFFF
 

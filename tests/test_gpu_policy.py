@@ -76,6 +76,35 @@ def test_policy_ragged_shapes():
         check_actions(w, s, P, range(s.n_envs), "policy 50 envs 64x64 H96")
 
 
+def test_policy_layered_head_parity():
+    """Layers 2 and 3 as batched float32 MFMA products, forced at hidden 256
+    on 64 envs of the 1024-env config: within the oracle's bound, like the
+    per-env head on the same frames."""
+    s = sg.config_scene(2, n_envs=64)
+    P = sg.policy_weights(11, 128, 128, 256, 32)
+    with vuda.World(s) as w:
+        w.step(nsteps=30)
+        w.set_policy(P)
+        check_actions(w, s, P, range(s.n_envs), "policy c2[0:64] H256 per-env head")
+        w.set_tuning(vuda.TUNE_POLICY_LAYERED, 1)
+        assert w.get_tuning(vuda.TUNE_POLICY_LAYERED) == 1
+        check_actions(w, s, P, range(s.n_envs), "policy c2[0:64] H256 layered")
+
+
+def test_policy_wide_hidden():
+    """Hidden 2048 and 4096 (above the per-env head, so layers 2 and 3 run
+    as batched products) over 100 envs (a 64-row tile and a ragged 36) of
+    32x32 frames: K = 4096, split 16 ways in layer 1, 4 in layer 2 and 32 in
+    layer 3 at hidden 4096."""
+    s = sg.make_scene(1006, [16] * 100, 32, mixed=True)
+    for H, seed in ((2048, 15), (4096, 16)):
+        P = sg.policy_weights(seed, 32, 32, H, 16)
+        with vuda.World(s) as w:
+            w.step(nsteps=10)
+            w.set_policy(P)
+            check_actions(w, s, P, range(s.n_envs), f"policy 100 envs 32x32 H{H}")
+
+
 def test_saturated_actions_drive_the_step():
     """A policy with zero weights acts exactly a_max clamp(b3): the step that
     follows matches the oracle's step with those forces."""
@@ -155,4 +184,14 @@ def test_policy_errors():
         with pytest.raises(vuda.VudaError):
             w.act()
         with pytest.raises(vuda.VudaError):
-            w.set_policy(dict(sg.policy_weights(1, 64, 64, 2048, 4)))  # hidden above 1024
+            w.set_policy(sg.policy_weights(1, 8, 8, 1100, 4))  # above 1024, not a multiple of 64
+        with pytest.raises(vuda.VudaError):
+            w.set_policy(sg.policy_weights(1, 8, 8, 8256, 4))  # above 8192
+        # the batched layers 2-3 need a multiple of 64: refused at act time
+        w.set_policy(sg.policy_weights(1, 128, 128, 96, 4))
+        w.set_tuning(vuda.TUNE_POLICY_LAYERED, 1)
+        with pytest.raises(vuda.VudaError):
+            w.act()
+        w.set_tuning(vuda.TUNE_POLICY_LAYERED, 0)
+        w.act()
+        w.wait()

@@ -276,7 +276,7 @@ def main():
                 "phys_persistent": vuda.TUNE_PHYS_PERSISTENT,
                 "raster_persistent": vuda.TUNE_RASTER_PERSISTENT, "graphs": vuda.TUNE_GRAPHS,
                 "phys_prio": vuda.TUNE_PHYS_PRIORITY, "broadphase": vuda.TUNE_BROADPHASE,
-                "presetup": vuda.TUNE_PRESETUP}
+                "presetup": vuda.TUNE_PRESETUP, "policy_layered": vuda.TUNE_POLICY_LAYERED}
     for kv in filter(None, args.tune.split(",")):
         k, v = kv.split("=")
         w.set_tuning(knob_ids[k], int(v))

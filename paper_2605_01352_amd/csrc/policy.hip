@@ -4,7 +4,7 @@
 // the same GPU (Evaluation, RL Training, MLP-based RL).  The observation of an
 // env is its camera 0 frame as K = 4 W H integers 0..255: the RGB bytes in
 // memory order, then the top byte of each 24-bit depth.  Layers:
-//   h1 = relu(x W1 + b1)   W1 bfloat16 [K][H], given transposed as [H][K]
+//   h1 = relu(x W1 + b1)   W1 bfloat16 [K][H], held as panels [K / 32][H][32]
 //   h2 = relu(h1 W2 + b2)  float32
 //   y  = h2 W3 + b3        float32, A = 3 B outputs
 //   a  = a_max clamp(y, -1, 1): the force on body b is a[3b .. 3b+2]
@@ -22,6 +22,8 @@
 // activation.
 #include "vuda_internal.h"
 
+#include <type_traits>
+
 #pragma clang fp contract(off)
 
 namespace vuda {
@@ -35,6 +37,20 @@ constexpr int kCols = 256;     // hidden units per layer-1 workgroup (64 per wav
 constexpr int kKStep = 32;     // k per MFMA step
 constexpr int kLdsRow = 40;    // bfloat16 per staged row (32 + 8 padding against bank conflicts)
 
+constexpr int kXcds = 8;        // accelerator complex dies, each with its own L2
+
+// Position of this workgroup in the grid's logical order (x fastest, then
+// y, then z).  The dispatcher deals workgroups to the XCDs round-robin in
+// launch order; renumbered like this, each XCD takes one contiguous run of
+// the logical order, so that the row tiles that share a weight slice (and
+// the column tiles that share rows) meet in one L2 instead of eight.
+__device__ __forceinline__ int3 xcd_tile() {
+  const int total = gridDim.x * gridDim.y * gridDim.z;
+  int b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  if (total % kXcds == 0) b = (b % kXcds) * (total / kXcds) + b / kXcds;
+  return make_int3(b % gridDim.x, (b / gridDim.x) % gridDim.y, b / (gridDim.x * gridDim.y));
+}
+
 // bfloat16 bits of the integers in the four bytes of w (exact: 8-bit values)
 __device__ __forceinline__ uint2 bytes_to_bf16(uint32_t w) {
   // (the compiler turns these into v_cvt_f32_ubyte0..3)
@@ -46,19 +62,40 @@ __device__ __forceinline__ uint2 bytes_to_bf16(uint32_t w) {
   return make_uint2(__builtin_amdgcn_perm(f1, f0, 0x07060302u), __builtin_amdgcn_perm(f3, f2, 0x07060302u));
 }
 
-// 8 observation values x[k .. k+7] of one frame as bfloat16 (k a multiple of
-// 8; the RGB part ends at 3 W H, a multiple of 32)
-__device__ __forceinline__ uint4 obs8(const uint8_t* rgb, const uint32_t* depth, int k, int krgb) {
-  if (k < krgb) {
-    const uint2 b = *(const uint2*)(rgb + k);
-    const uint2 lo = bytes_to_bf16(b.x), hi = bytes_to_bf16(b.y);
-    return make_uint4(lo.x, lo.y, hi.x, hi.y);
+// The bytes behind 8 observation values x[k .. k+7] of one frame (k a
+// multiple of 8): 8 RGB bytes while k is in the RGB part (which ends at
+// 3 W H, a multiple of 32, so a whole 32-k step is on one side), else 8
+// depth words; only the members of that kind are loaded and read.  They are
+// loaded a step ahead and converted only after that step's MFMAs, so that
+// the wait for them does not come before the MFMAs.
+struct ObsRaw {
+  uint2 c;       // RGB bytes
+  uint4 d0, d1;  // depth words
+};
+
+// kRgb: the bytes at rgb[k ..]; else the words at depth[kd ..]
+template <bool kRgb>
+__device__ __forceinline__ void obs_load(ObsRaw& r, const uint8_t* rgb, const uint32_t* depth, int k, int kd) {
+  if constexpr (kRgb) {
+    r.c = *(const uint2*)(rgb + k);
+  } else {
+    r.d0 = *(const uint4*)(depth + kd);
+    r.d1 = *(const uint4*)(depth + kd + 4);
   }
-  const uint4 d0 = *(const uint4*)(depth + (k - krgb));
-  const uint4 d1 = *(const uint4*)(depth + (k - krgb) + 4);
-  // byte 2 of each depth word: its top byte (background 0xFFFFFFFF gives 255)
-  const uint32_t w0 = __builtin_amdgcn_perm(d0.y, d0.x, 0x0c0c0602u) | (__builtin_amdgcn_perm(d0.w, d0.z, 0x0c0c0602u) << 16);
-  const uint32_t w1 = __builtin_amdgcn_perm(d1.y, d1.x, 0x0c0c0602u) | (__builtin_amdgcn_perm(d1.w, d1.z, 0x0c0c0602u) << 16);
+}
+
+// the 8 values as bfloat16
+template <bool kRgb>
+__device__ __forceinline__ uint4 obs_convert(const ObsRaw& r) {
+  uint32_t w0, w1;
+  if constexpr (kRgb) {
+    w0 = r.c.x;
+    w1 = r.c.y;
+  } else {
+    // byte 2 of each depth word: its top byte (background 0xFFFFFFFF gives 255)
+    w0 = __builtin_amdgcn_perm(r.d0.y, r.d0.x, 0x0c0c0602u) | (__builtin_amdgcn_perm(r.d0.w, r.d0.z, 0x0c0c0602u) << 16);
+    w1 = __builtin_amdgcn_perm(r.d1.y, r.d1.x, 0x0c0c0602u) | (__builtin_amdgcn_perm(r.d1.w, r.d1.z, 0x0c0c0602u) << 16);
+  }
   const uint2 lo = bytes_to_bf16(w0), hi = bytes_to_bf16(w1);
   return make_uint4(lo.x, lo.y, hi.x, hi.y);
 }
@@ -70,64 +107,89 @@ __global__ __launch_bounds__(256) void policy_l1_kernel(WorldDev W, PolicyLaunch
   __shared__ __align__(16) uint16_t sA[2][kRows * kLdsRow];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int m0 = blockIdx.x * kRows;
-  const int n0 = blockIdx.y * kCols + 64 * wave;
-  const int s = blockIdx.z;
-  const int K = L.K, krgb = L.krgb, Kc = L.kchunk;
+  const int3 tile = xcd_tile();
+  const int m0 = tile.x * kRows;
+  const int n0 = tile.y * kCols + 64 * wave;
+  const int s = tile.z;
+  const int krgb = L.krgb, Kc = L.kchunk;
   const int kbeg = s * Kc;
   const int nsteps = Kc / kKStep;
   // staging role: row r = tid / 4, k offset 8 (tid % 4) of each step
   const int r = tid >> 2, kq = 8 * (tid & 3);
-  const uint8_t* rgb = nullptr;
-  const uint32_t* dep = nullptr;
-  const bool rvalid = m0 + r < L.M;
-  if (rvalid) {
-    const CamDev cam = W.cams[W.envs[L.envs[m0 + r]].cam_off];
-    rgb = W.rgb + 3 * cam.pix_off;
-    dep = W.depth + cam.pix_off;
-  }
-  // B fragments: lane (column n0 + 16 cb + lane % 16, k + 8 (lane / 16) .. + 7)
+  // rows past M (a ragged last tile) read row m0's frame: a row of A only
+  // reaches the same row of the product, and those rows are not stored
+  const CamDev cam = W.cams[W.envs[L.envs[min(m0 + r, L.M - 1)]].cam_off];
+  const uint8_t* rgb = W.rgb + 3 * cam.pix_off;
+  const uint32_t* dep = W.depth + cam.pix_off;
+  // B fragments: lane (column n0 + 16 cb + lane % 16, k + 8 (lane / 16) .. + 7),
+  // in the panel of step k at (k / 32) 32 H
   const uint16_t* bcol[4];
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb) {
     const int n = min(n0 + 16 * cb + (lane & 15), L.H - 1);
-    bcol[cb] = L.w1t + (int64_t)n * K + 8 * (lane >> 4);
+    bcol[cb] = L.w1t + (int64_t)n * kKStep + 8 * (lane >> 4);
   }
+  const int64_t panel = (int64_t)kKStep * L.H;
   f32x4 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
-  uint4 stage = rvalid ? obs8(rgb, dep, kbeg + kq, krgb) : make_uint4(0, 0, 0, 0);
-  *(uint4*)&sA[0][r * kLdsRow + kq] = stage;
+  const int kend = kbeg + Kc;
+  {
+    ObsRaw raw;
+    uint4 v;
+    if (kbeg < krgb) {
+      obs_load<true>(raw, rgb, dep, kbeg + kq, 0);
+      v = obs_convert<true>(raw);
+    } else {
+      obs_load<false>(raw, rgb, dep, 0, kbeg + kq - krgb);
+      v = obs_convert<false>(raw);
+    }
+    *(uint4*)&sA[0][r * kLdsRow + kq] = v;
+  }
   // W1 fragments run one step ahead of the MFMAs that use them
   uint4 bn[4];
 #pragma unroll
-  for (int cb = 0; cb < 4; ++cb) bn[cb] = *(const uint4*)(bcol[cb] + kbeg);
+  for (int cb = 0; cb < 4; ++cb) bn[cb] = *(const uint4*)(bcol[cb] + (kbeg / kKStep) * panel);
   __syncthreads();
-  for (int t = 0; t < nsteps; ++t) {
+  // One step: the next step's W1 fragments and observation bytes (of the
+  // kind the template argument names) go out, this step's MFMAs run, then
+  // the bytes are converted and staged.  No branch surrounds a load, so no
+  // register copy of a loaded value (and no wait for it) lands before the
+  // MFMAs.  The last step reloads itself (in bounds, unused).
+  auto step = [&](auto next_rgb, int t) {
+    constexpr bool kNextRgb = decltype(next_rgb)::value;
     const int k = kbeg + t * kKStep;
+    const int knext = min(k + kKStep, kend - kKStep);
     const int buf = t & 1;
     bf16x8 b[4];
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) b[cb] = __builtin_bit_cast(bf16x8, bn[cb]);
-    // next step's W1 fragments and observation values, in flight while this
-    // step multiplies
-    if (t + 1 < nsteps) {
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) bn[cb] = *(const uint4*)(bcol[cb] + k + kKStep);
-      stage = rvalid ? obs8(rgb, dep, k + kKStep + kq, krgb) : make_uint4(0, 0, 0, 0);
-    }
+    for (int cb = 0; cb < 4; ++cb) bn[cb] = *(const uint4*)(bcol[cb] + (knext / kKStep) * panel);
+    ObsRaw raw;
+    // (a depth load for a step still in the RGB part reads depth word 0 on)
+    obs_load<kNextRgb>(raw, rgb, dep, knext + kq, max(knext + kq - krgb, 0));
+    // the loads go out before the MFMAs
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
       const bf16x8 a = __builtin_bit_cast(bf16x8, *(const uint4*)&sA[buf][(16 * rb + (lane & 15)) * kLdsRow + 8 * (lane >> 4)]);
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[cb], acc[rb][cb], 0, 0, 0);
     }
-    if (t + 1 < nsteps) *(uint4*)&sA[buf ^ 1][r * kLdsRow + kq] = stage;
+    // nothing below moves above the MFMAs
+    __builtin_amdgcn_sched_barrier(0);
+    *(uint4*)&sA[buf ^ 1][r * kLdsRow + kq] = obs_convert<kNextRgb>(raw);
     __syncthreads();
-  }
+  };
+  // steps whose successor is in the RGB part, then the rest
+  const int t_rgb = min(max((krgb - kbeg) / kKStep, 0), nsteps);  // steps in the RGB part
+  int t = 0;
+  for (; t < t_rgb - 1; ++t) step(std::true_type{}, t);
+  for (; t < nsteps; ++t) step(std::false_type{}, t);
   // D layout: lane holds rows 4 (lane / 16) + i of a block, column lane % 16
   float* P = L.partial + (int64_t)s * L.M * L.H;
 #pragma unroll
@@ -185,7 +247,9 @@ __device__ __forceinline__ float action_of(float y, float a_max) {
 
 // Layers 2 and 3, one workgroup per env (blockDim = H rounded up to 64,
 // at most 1024): the split-K partials added in split order, then every unit
-// on its own lane, its dot product in index order.
+// on its own lane, its dot product in index order.  (Splitting each sum over
+// more lanes, to put more loads in flight, was slower: the weight reads from
+// L2 bound this kernel, not their latency.)
 __global__ __launch_bounds__(1024) void policy_head_kernel(WorldDev W, PolicyLaunch L) {
   extern __shared__ float sh[];  // h1 [H], h2 [H]
   const int m = blockIdx.x;
@@ -247,17 +311,18 @@ __global__ __launch_bounds__(256) void policy_dense_kernel(const float* X, const
   __shared__ __align__(16) float sB[2][kDStep * kBPitch];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int m0 = blockIdx.x * kDTile, n0 = blockIdx.y * kDTile, s = blockIdx.z;
+  const int3 tile = xcd_tile();
+  const int m0 = tile.x * kDTile, n0 = tile.y * kDTile, s = tile.z;
   const int wm = 32 * (wave & 1), wn = 32 * (wave >> 1);
   const int kbeg = s * kchunk, nsteps = kchunk / kDStep;
   // staging roles: X row ar, columns ac .. ac+3; B row br, columns bc .. bc+3
   const int ar = tid >> 2, ac = 4 * (tid & 3);
   const int br = tid >> 4, bc = 4 * (tid & 15);
-  const bool a_ok = m0 + ar < M;
-  const float* xa = X + (int64_t)(a_ok ? m0 + ar : 0) * K + ac;
+  // rows past M read row M - 1: a row of X only reaches the same row of
+  // the product, and those rows are not stored
+  const float* xa = X + (int64_t)min(m0 + ar, M - 1) * K + ac;
   const float* bb = B + (int64_t)br * ldb + n0 + bc;
-  const float4 zero = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-  float4 ra = a_ok ? *(const float4*)(xa + kbeg) : zero;
+  float4 ra = *(const float4*)(xa + kbeg);
   float4 rb = *(const float4*)(bb + (int64_t)kbeg * ldb);
   *(float4*)&sA[0][ar * kAPitch + ac] = ra;
   *(float4*)&sB[0][br * kBPitch + bc] = rb;
@@ -271,7 +336,7 @@ __global__ __launch_bounds__(256) void policy_dense_kernel(const float* X, const
     const int buf = t & 1;
     if (t + 1 < nsteps) {
       const int k = kbeg + (t + 1) * kDStep;
-      ra = a_ok ? *(const float4*)(xa + k) : zero;
+      ra = *(const float4*)(xa + k);
       rb = *(const float4*)(bb + (int64_t)k * ldb);
     }
     // operands of v_mfma_f32_16x16x4_f32: lane l holds A[l % 16][l / 16]

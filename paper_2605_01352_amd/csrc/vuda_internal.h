@@ -185,7 +185,7 @@ struct PolicyLaunch {
   int32_t krgb;            // 3 W H: start of the depth bytes
   int32_t H, A;            // hidden units, actions
   int32_t splits, kchunk;  // K = splits kchunk, kchunk a multiple of 32
-  const uint16_t* w1t;     // [H][K] bfloat16 (W1 transposed)
+  const uint16_t* w1t;     // [K / 32][H][32] bfloat16: W1 in panels of one MFMA k step
   const float* b1;
   const float* w2;         // [H][H]
   const float* b2;

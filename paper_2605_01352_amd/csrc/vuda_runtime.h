@@ -86,7 +86,7 @@ struct Policy {
   bool set = false;
   int32_t in_w = 0, in_h = 0, H = 0, A = 0;
   float a_max = 0.0f;
-  uint16_t* w1t = nullptr;  // [H][K] bfloat16
+  uint16_t* w1t = nullptr;  // [K / 32][H][32] bfloat16
   float* wf = nullptr;      // b1 [H], w2 [H][H], b2 [H], w3 [H][A], b3 [A]
   float* w3p = nullptr;     // [H][A rounded up to 64] (hidden a multiple of 64)
   float* partial = nullptr;

@@ -1147,13 +1147,15 @@ extern "C" int vuda_policy_set(vuda_world* w, const vuda_policy_desc* d) {
   p.A = 3 * d->act_bodies;
   p.a_max = d->a_max;
   const int64_t K = 4 * px, H = p.H, A = p.A;
-  // W1 [K][H] -> [H][K], so that a unit's weights are contiguous in k
-  // (in 64 x 64 blocks: both sides stay in cache at H = 4096)
+  // W1 [K][H] -> [K / 32][H][32]: the 32 weights of a unit for one MFMA
+  // step of k are contiguous, and one step's weights of all units form one
+  // contiguous panel (in 64 x 64 blocks: both sides stay in cache at H = 4096)
   std::vector<uint16_t> w1t((size_t)(K * H));
   for (int64_t k0 = 0; k0 < K; k0 += 64)
     for (int64_t h0 = 0; h0 < H; h0 += 64)
       for (int64_t k = k0; k < std::min(K, k0 + 64); ++k)
-        for (int64_t h = h0; h < std::min(H, h0 + 64); ++h) w1t[(size_t)(h * K + k)] = d->w1[k * H + h];
+        for (int64_t h = h0; h < std::min(H, h0 + 64); ++h)
+          w1t[(size_t)(((k >> 5) * H + h) * 32 + (k & 31))] = d->w1[k * H + h];
   std::vector<float> wf;
   wf.insert(wf.end(), d->b1, d->b1 + H);
   wf.insert(wf.end(), d->w2, d->w2 + H * H);

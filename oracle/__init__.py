@@ -22,7 +22,7 @@ MAX_POINTS = 16
 
 class PhysParams(C.Structure):
     _fields_ = [("dt", C.c_float), ("substeps", C.c_int32), ("k", C.c_float),
-                ("c", C.c_float), ("g", C.c_float * 3)]
+                ("c", C.c_float), ("g", C.c_float * 3), ("mu", C.c_float), ("v_eps", C.c_float)]
 
 
 class RenderParams(C.Structure):
@@ -69,7 +69,7 @@ def _p(a: np.ndarray):
 def phys_params(scene) -> PhysParams:
     g = (C.c_float * 3)(*[float(x) for x in scene.gravity])
     return PhysParams(float(np.float32(scene.dt)), int(scene.substeps), float(scene.k_contact),
-                      float(scene.c_damp), g)
+                      float(scene.c_damp), g, float(scene.mu), float(scene.v_eps))
 
 
 class _Render:

@@ -269,6 +269,15 @@ int oracle_step_env_ext(int32_t n, const uint8_t* type, const float* size, const
           float f = prm->k * pts[k].delta - prm->c * vn;
           if (f < 0.0f) f = 0.0f;
           v3 F = scl(nrm, f);
+          if (prm->mu > 0.0f) {
+            /* friction: -mu f v_t / max(|v_t|, v_eps), v_t the slip of A on B
+             * (regularized Coulomb: at most mu f, opposing the slip) */
+            v3 vt = sub(vrel, scl(nrm, vn));
+            float st = sqrtf(dot(vt, vt));
+            float den = st > prm->v_eps ? st : prm->v_eps;
+            float ft = (prm->mu * f) / den;
+            F = sub(F, scl(vt, ft));
+          }
           v3 Fi = pts[k].a_is_first ? F : neg(F); /* force on the pair's first body */
           SF = add(SF, Fi);
           Ti = add(Ti, cross(sub(xc, pA), Fi));

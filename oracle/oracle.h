@@ -30,13 +30,17 @@ extern "C" {
 #define ORACLE_GROUND 0xFFFF
 #define ORACLE_MAX_POINTS 16
 
-/* Physics parameters: dt, substeps, contact stiffness k, damping c, gravity. */
+/* Physics parameters: dt, substeps, contact stiffness k, damping c, gravity;
+ * friction coefficient mu (0: none) and the slip speed v_eps below which
+ * the regularized Coulomb friction is linear in the slip. */
 typedef struct {
   float dt;
   int32_t substeps;
   float k;
   float c;
   float g[3];
+  float mu;
+  float v_eps;
 } oracle_phys_params;
 
 /* Mesh templates (unit size) and shading constants. */

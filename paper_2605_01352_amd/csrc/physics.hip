@@ -218,7 +218,14 @@ __device__ __forceinline__ PointTerms point_terms(const Point& pt, bool a_first,
   const float vn = dot(vrel, pt.n);
   float f = pc.k * pt.delta - pc.c * vn;
   if (f < 0.0f) f = 0.0f;
-  const f3 F = mul(pt.n, f);
+  f3 F = mul(pt.n, f);
+  if (pc.mu > 0.0f) {
+    // regularized Coulomb friction against the tangential slip v_t
+    const f3 vt = sub(vrel, mul(pt.n, vn));
+    const float st = sqrtf(dot(vt, vt));
+    const float ft = (pc.mu * f) / (st > pc.v_eps ? st : pc.v_eps);
+    F = sub(F, mul(vt, ft));
+  }
   PointTerms r;
   r.Fi = a_first ? F : neg(F);
   r.ti = cross(sub(pt.xc, pi), r.Fi);

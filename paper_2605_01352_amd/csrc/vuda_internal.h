@@ -104,6 +104,7 @@ struct PhysConsts {
   float k, c;
   float g[3];
   int32_t substeps;
+  float mu, v_eps;  // regularized Coulomb friction (mu = 0: none)
 };
 
 // Pointers into the world arena used by the kernels.

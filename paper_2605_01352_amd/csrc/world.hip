@@ -432,6 +432,9 @@ extern "C" int vuda_create_world(const vuda_world_desc* d, const vuda_allocator*
   if (!(d->phys.dt > 0.0f) || d->phys.substeps < 1 || d->phys.substeps > 64 ||
       !(d->phys.k_contact >= 0.0f) || !(d->phys.c_damp >= 0.0f))
     return fail(VUDA_EINVAL, "physics parameters");
+  if (!(d->phys.mu >= 0.0f) || !std::isfinite(d->phys.mu) ||
+      (d->phys.mu > 0.0f && (!(d->phys.v_eps > 0.0f) || !std::isfinite(d->phys.v_eps))))
+    return fail(VUDA_EINVAL, "friction parameters mu %g, v_eps %g", d->phys.mu, d->phys.v_eps);
   int rc = validate_render(d->render);
   if (rc) return rc;
   int64_t nb = 0, npix = 0;
@@ -477,6 +480,8 @@ extern "C" int vuda_create_world(const vuda_world_desc* d, const vuda_allocator*
   w->pc.c = d->phys.c_damp;
   for (int k = 0; k < 3; ++k) w->pc.g[k] = d->phys.gravity[k];
   w->pc.substeps = d->phys.substeps;
+  w->pc.mu = d->phys.mu;
+  w->pc.v_eps = d->phys.mu > 0.0f ? d->phys.v_eps : 1.0f;
   rc = w->alloc_arena(a);
   if (rc) {
     w->free_all();

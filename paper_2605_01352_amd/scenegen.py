@@ -260,6 +260,8 @@ class Scene:
     k_contact: float = 1.0e4
     c_damp: float = 10.0
     gravity: tuple = (0.0, 0.0, -9.81)
+    mu: float = 0.0        # regularized Coulomb friction coefficient (0: none)
+    v_eps: float = 0.05    # [m/s] slip speed below which friction is linear
     name: str = ""
     seed: int = 0
     env_gid0: int = 0

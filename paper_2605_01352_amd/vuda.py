@@ -50,7 +50,7 @@ class VudaError(RuntimeError):
 
 class PhysParams(C.Structure):
     _fields_ = [("dt", C.c_float), ("substeps", C.c_int32), ("k_contact", C.c_float),
-                ("c_damp", C.c_float), ("gravity", C.c_float * 3)]
+                ("c_damp", C.c_float), ("gravity", C.c_float * 3), ("mu", C.c_float), ("v_eps", C.c_float)]
 
 
 class RenderDesc(C.Structure):
@@ -221,12 +221,15 @@ class World:
         k = (ref.k_contact if ref is not None else 1.0e4)
         c = (ref.c_damp if ref is not None else 10.0)
         g = (ref.gravity if ref is not None else (0.0, 0.0, -9.81))
+        mu = (ref.mu if ref is not None else 0.0)
+        v_eps = (ref.v_eps if ref is not None else 0.05)
         if phys:
             dt, sub, k, c, g = phys.get("dt", dt), phys.get("substeps", sub), phys.get("k", k), \
                 phys.get("c", c), phys.get("g", g)
+            mu, v_eps = phys.get("mu", mu), phys.get("v_eps", v_eps)
         desc = WorldDesc()
         desc.phys = PhysParams(float(np.float32(dt)), int(sub), float(k), float(c),
-                               (C.c_float * 3)(*[float(x) for x in g]))
+                               (C.c_float * 3)(*[float(x) for x in g]), float(mu), float(v_eps))
         desc.render = render_desc(keep, **(render_kw or {}))
         desc.initial = env_batch(keep, scene) if scene is not None else EnvBatch(0)
         desc.flags = FLAG_DEBUG if debug else 0
@@ -422,14 +425,17 @@ def world_desc(keep: _Keep, scene=None, debug: bool = False, cap_envs: int = 0, 
                cap_cams: int = 0, cap_pixels: int = 0, pair_cap: int = 1024, hbm_budget: int = 0,
                phys=None) -> WorldDesc:
     dt, sub, k, c, g = 1.0 / 240.0, 4, 1.0e4, 10.0, (0.0, 0.0, -9.81)
+    mu, v_eps = 0.0, 0.05
     if scene is not None:
         dt, sub, k, c, g = scene.dt, scene.substeps, scene.k_contact, scene.c_damp, scene.gravity
+        mu, v_eps = scene.mu, scene.v_eps
     if phys:
         dt, sub, k, c, g = phys.get("dt", dt), phys.get("substeps", sub), phys.get("k", k), \
             phys.get("c", c), phys.get("g", g)
+        mu, v_eps = phys.get("mu", mu), phys.get("v_eps", v_eps)
     d = WorldDesc()
     d.phys = PhysParams(float(np.float32(dt)), int(sub), float(k), float(c),
-                        (C.c_float * 3)(*[float(x) for x in g]))
+                        (C.c_float * 3)(*[float(x) for x in g]), float(mu), float(v_eps))
     d.render = render_desc(keep)
     d.initial = env_batch(keep, scene) if scene is not None else EnvBatch(0)
     d.flags = FLAG_DEBUG if debug else 0

@@ -7,7 +7,8 @@ import numpy as np
 from paper_2605_01352_amd import scenegen as sg
 
 
-def tiny_scene(bodies, gravity=(0.0, 0.0, -9.81), res=64, vp=None, envs=1, k=1.0e4, c=10.0):
+def tiny_scene(bodies, gravity=(0.0, 0.0, -9.81), res=64, vp=None, envs=1, k=1.0e4, c=10.0, mu=0.0,
+               v_eps=0.05):
     """bodies: list of dicts(type, size, pos, [quat], [vel], [omega], [mass]).
 
     The same bodies are repeated in every env.
@@ -34,7 +35,7 @@ def tiny_scene(bodies, gravity=(0.0, 0.0, -9.81), res=64, vp=None, envs=1, k=1.0
         quat=rep(quat), omega=rep(om), cam_off=np.arange(envs + 1).astype(np.int32),
         cam_vp=np.repeat(np.asarray(vp, np.float32).reshape(1, 16), envs, axis=0),
         cam_w=np.full(envs, res, np.int32), cam_h=np.full(envs, res, np.int32),
-        gravity=gravity, k_contact=k, c_damp=c, name="tiny")
+        gravity=gravity, k_contact=k, c_damp=c, mu=mu, v_eps=v_eps, name="tiny")
 
 
 def quat_axis_angle(axis, ang):

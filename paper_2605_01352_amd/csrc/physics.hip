@@ -202,6 +202,9 @@ struct PairAcc {
 struct PointTerms {
   f3 Fi, ti, tj;
 };
+// FR: friction on (a separate instantiation, so that the frictionless
+// kernel keeps its registers and needs no stack)
+template <bool FR>
 __device__ __forceinline__ PointTerms point_terms(const Point& pt, bool a_first, f3 pi, f3 vi, f3 wi,
                                                   f3 pj, f3 vj, f3 wj, bool ground,
                                                   const PhysConsts& pc) {
@@ -219,7 +222,7 @@ __device__ __forceinline__ PointTerms point_terms(const Point& pt, bool a_first,
   float f = pc.k * pt.delta - pc.c * vn;
   if (f < 0.0f) f = 0.0f;
   f3 F = mul(pt.n, f);
-  if (pc.mu > 0.0f) {
+  if constexpr (FR) {
     // regularized Coulomb friction against the tangential slip v_t
     const f3 vt = sub(vrel, mul(pt.n, vn));
     const float st = sqrtf(dot(vt, vt));
@@ -234,10 +237,11 @@ __device__ __forceinline__ PointTerms point_terms(const Point& pt, bool a_first,
 }
 
 // Add the force of one contact point to its pair's sums.
+template <bool FR>
 __device__ __forceinline__ void add_point(PairAcc& acc, const Point& pt, bool a_first, f3 pi,
                                           f3 vi, f3 wi, f3 pj, f3 vj, f3 wj, bool ground,
                                           const PhysConsts& pc) {
-  const PointTerms t = point_terms(pt, a_first, pi, vi, wi, pj, vj, wj, ground, pc);
+  const PointTerms t = point_terms<FR>(pt, a_first, pi, vi, wi, pj, vj, wj, ground, pc);
   acc.SF = add(acc.SF, t.Fi);
   acc.Ti = add(acc.Ti, t.ti);
   if (!ground) acc.Tj = add(acc.Tj, t.tj);
@@ -294,7 +298,7 @@ __device__ __forceinline__ bool sphere_cube(f3 c, float r, f3 p, const M3& R, fl
 }
 
 // Narrowphase + force sum of body pair (i, j), i < j, one of them a sphere.
-template <int NW>
+template <int NW, bool FR>
 __device__ __noinline__ PairAcc pair_forces(const PhysLDS<NW>& s, int i, int j,
                                             const PhysConsts& pc) {
   PairAcc acc;
@@ -317,14 +321,14 @@ __device__ __noinline__ PairAcc pair_forces(const PhysLDS<NW>& s, int i, int j,
       pt.n = L > 0.0f ? mk(d.x / L, d.y / L, d.z / L) : mk(0.0f, 0.0f, 1.0f);
       pt.delta = sr - L;
       pt.xc = add(pj, mul(pt.n, sj - 0.5f * pt.delta));
-      add_point(acc, pt, true, pi, vi, wi, pj, vj, wj, false, pc);
+      add_point<FR>(acc, pt, true, pi, vi, wi, pj, vj, wj, false, pc);
     }
   } else if (ti == 0) {
     const M3 Rj = ldsR(s, j);
-    if (sphere_cube(pi, si, pj, Rj, sj, &pt)) add_point(acc, pt, true, pi, vi, wi, pj, vj, wj, false, pc);
+    if (sphere_cube(pi, si, pj, Rj, sj, &pt)) add_point<FR>(acc, pt, true, pi, vi, wi, pj, vj, wj, false, pc);
   } else if (tj == 0) {
     const M3 Ri = ldsR(s, i);
-    if (sphere_cube(pj, sj, pi, Ri, si, &pt)) add_point(acc, pt, false, pi, vi, wi, pj, vj, wj, false, pc);
+    if (sphere_cube(pj, sj, pi, Ri, si, &pt)) add_point<FR>(acc, pt, false, pi, vi, wi, pj, vj, wj, false, pc);
   }
   return acc;
 }
@@ -380,7 +384,7 @@ __device__ __forceinline__ int popc_below(const uint64_t* row, int b) {
   return c;
 }
 
-template <int NW>
+template <int NW, bool FR>
 __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc, int env,
                          int parity, int broadphase) {
   constexpr int N = PhysLDS<NW>::N;
@@ -614,7 +618,7 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
         j = (int)(pr >> 16);
         cc = (s.type[i] != 0) & (s.type[j] != 0);
         if (!cc) {
-          acc = pair_forces<NW>(s, i, j, pc);
+          acc = pair_forces<NW, FR>(s, i, j, pc);
           contact = acc.npts > 0;
         }
       }
@@ -653,7 +657,7 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
         pt.n = mk(0.0f, 0.0f, 1.0f);
         pt.delta = a - p.z;
         pt.xc = mk(p.x, p.y, p.z - a);
-        add_point(gs, pt, true, p, v, w, z3, z3, z3, true, pc);
+        add_point<FR>(gs, pt, true, p, v, w, z3, z3, z3, true, pc);
         gsph = true;
       }
     }
@@ -696,7 +700,7 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
         hit = corner_in_box(pA, RA, aA, r & 7, pB, RB, aB, &pt);
         if (hit) {
           const f3 pi = r < 8 ? pA : pB, pj = r < 8 ? pB : pA;
-          const PointTerms pq = point_terms(pt, r < 8, pi, vi, wi, pj, vj, wj, false, pc);
+          const PointTerms pq = point_terms<FR>(pt, r < 8, pi, vi, wi, pj, vj, wj, false, pc);
           s.stage[0][tid] = pq.Fi.x; s.stage[1][tid] = pq.Fi.y; s.stage[2][tid] = pq.Fi.z;
           s.stage[3][tid] = pq.ti.x; s.stage[4][tid] = pq.ti.y; s.stage[5][tid] = pq.ti.z;
           s.stage[6][tid] = pq.tj.x; s.stage[7][tid] = pq.tj.y; s.stage[8][tid] = pq.tj.z;
@@ -742,7 +746,7 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
           pt.n = mk(0.0f, 0.0f, 1.0f);
           pt.delta = -vtx.z;
           pt.xc = vtx;
-          const PointTerms pq = point_terms(pt, true, pb, vb, wb, z3, z3, z3, true, pc);
+          const PointTerms pq = point_terms<FR>(pt, true, pb, vb, wb, z3, z3, z3, true, pc);
           s.stage[0][tid] = pq.Fi.x; s.stage[1][tid] = pq.Fi.y; s.stage[2][tid] = pq.Fi.z;
           s.stage[3][tid] = pq.ti.x; s.stage[4][tid] = pq.ti.y; s.stage[5][tid] = pq.ti.z;
         }
@@ -905,7 +909,7 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
   if (bad && tid == 0) atomicOr(&W.env_flags[env], kFlagContactOverflow);
 }
 
-template <int NW>
+template <int NW, bool FR>
 __global__ __launch_bounds__(64 * NW) void physics_kernel(WorldDev W, PhysConsts pc, PhysLaunch L) {
   __shared__ PhysLDS<NW> s;
   // The step is latency-bound; a higher issue priority shortens it when it
@@ -919,7 +923,7 @@ __global__ __launch_bounds__(64 * NW) void physics_kernel(WorldDev W, PhysConsts
   if (L.persistent == 0) {
     const int wi = blockIdx.x;
     if (wi >= L.n_work) return;
-    step_env<NW>(s, W, pc, L.work[wi], L.parity, L.broadphase);
+    step_env<NW, FR>(s, W, pc, L.work[wi], L.parity, L.broadphase);
     return;
   }
   for (;;) {
@@ -928,7 +932,7 @@ __global__ __launch_bounds__(64 * NW) void physics_kernel(WorldDev W, PhysConsts
     const int wi = s.work;
     __syncthreads();
     if (wi >= L.n_work) return;
-    step_env<NW>(s, W, pc, L.work[wi], L.parity, L.broadphase);
+    step_env<NW, FR>(s, W, pc, L.work[wi], L.parity, L.broadphase);
   }
 }
 
@@ -953,10 +957,15 @@ hipError_t launch_physics(const WorldDev& w, const PhysConsts& pc, const PhysLau
       hipError_t e = launch_reset_queue(l.queue, s);
       if (e != hipSuccess) return e;
     }
-    if (nw == 1)
-      hipLaunchKernelGGL(physics_kernel<1>, dim3(grid), dim3(64), 0, s, w, pc, lt);
+    const bool fr = pc.mu > 0.0f;
+    if (nw == 1 && !fr)
+      hipLaunchKernelGGL((physics_kernel<1, false>), dim3(grid), dim3(64), 0, s, w, pc, lt);
+    else if (nw == 1)
+      hipLaunchKernelGGL((physics_kernel<1, true>), dim3(grid), dim3(64), 0, s, w, pc, lt);
+    else if (!fr)
+      hipLaunchKernelGGL((physics_kernel<2, false>), dim3(grid), dim3(128), 0, s, w, pc, lt);
     else
-      hipLaunchKernelGGL(physics_kernel<2>, dim3(grid), dim3(128), 0, s, w, pc, lt);
+      hipLaunchKernelGGL((physics_kernel<2, true>), dim3(grid), dim3(128), 0, s, w, pc, lt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

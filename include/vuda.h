@@ -65,6 +65,8 @@ extern "C" {
                                  bit2 bin overflow                                     */
 #define VUDA_FETCH_ACTIONS  7 /* float per env [3 act_bodies]: the policy's last actions
                                  (zeros before the first vuda_act); needs a policy     */
+#define VUDA_FETCH_DEPTH_METRIC 8 /* float per camera [H][W]: view depth [m] along the
+                                 camera axis, +inf where no surface (vuda_fetch)        */
 
 /* ---- world flags -------------------------------------------------------- */
 #define VUDA_FLAG_DEBUG 1u  /* keep contact sets, winners and coverage for fetch */
@@ -204,6 +206,14 @@ int vuda_wait(vuda_world* w, int32_t phase);
  * memory, or device memory if dst_on_device).  Stream-ordered after all
  * enqueued work, and synchronous on return.  The layout is given with the
  * VUDA_FETCH_* selectors; fetch size queries: vuda_fetch_bytes.
+ *
+ * VUDA_FETCH_DEPTH_METRIC converts the 24-bit depth on the GPU: a camera
+ * whose view-projection rows satisfy row2 = alpha row3 + beta e4 (every
+ * perspective of the usual form, Vulkan or OpenGL depth) gives the view
+ * depth w = beta / (D / (2^24 - 1) - alpha) in float64, rounded to float32.
+ * Its error is the 24-bit quantization of D: about d^2 / |beta| 2^-24 at
+ * depth d.  VUDA_EINVAL for a camera of another form.  A host dst goes
+ * through a device staging buffer that the world keeps (grown as needed).
  */
 int vuda_fetch(vuda_world* w, int32_t what, int32_t env_lo, int32_t env_hi, void* dst,
                size_t dst_bytes, int32_t dst_on_device);

@@ -229,3 +229,21 @@ def run_batch(scene, state, n_steps: int, nthreads: int, do_render: bool = True)
         _p(arrs["cw"]), _p(arrs["ch"]), _p(arrs["io"]), C.byref(rp.s), _p(rgb), _p(depth),
         int(n_steps), int(nthreads), int(do_render))
     return st, rgb, depth
+
+
+def metric_depth(depth: np.ndarray, vp: np.ndarray) -> np.ndarray:
+    """View depth [m] along the camera axis at each pixel of a 24-bit depth
+    image (uint32, 0xFFFFFFFF = no surface -> +inf).  The camera's
+    view-projection (row-major 4x4, float32) must satisfy row2 = alpha row3
+    + beta e4, as every perspective of the usual form does: then clip
+    z = alpha w + beta, and the stored z_ndc = D / (2^24 - 1) gives
+    w = beta / (z_ndc - alpha).  Evaluated in float64 and rounded once to
+    float32."""
+    m = np.asarray(vp, np.float32).reshape(4, 4).astype(np.float64)
+    r2, r3 = m[2, :3], m[3, :3]
+    alpha = ((r2[0] * r3[0] + r2[1] * r3[1]) + r2[2] * r3[2]) / ((r3[0] * r3[0] + r3[1] * r3[1]) + r3[2] * r3[2])
+    beta = m[2, 3] - alpha * m[3, 3]
+    d = np.asarray(depth, np.uint32)
+    with np.errstate(divide="ignore"):
+        w = beta / (d.astype(np.float64) / 16777215.0 - alpha)
+    return np.where(d == 0xFFFFFFFF, np.inf, w).astype(np.float32)

@@ -77,6 +77,15 @@ struct Tuning {
 constexpr int kKernelPhysics = 0, kKernelSetup = 1, kKernelTiles = 2, kKernelPolicy = 3;
 constexpr int kKernelKinds = 4;
 
+// Metric depth of one camera image: out[out_off + i] for its npix pixels
+// from depth[pix_off + i], view depth = beta / (D / (2^24 - 1) - alpha).
+struct MetricCam {
+  int64_t pix_off, out_off, npix;
+  double alpha, beta;
+};
+hipError_t launch_depth_metric(const uint32_t* depth, const MetricCam* cams, int32_t ncams, int64_t max_pix,
+                               float* out, hipStream_t s);
+
 // Hidden sizes: up to kPolicyHeadMax the per-env head kernel runs layers 2
 // and 3; above it (multiples of 64) they run as batched products.
 constexpr int32_t kPolicyHeadMax = 1024, kPolicyHiddenMax = 8192;
@@ -151,6 +160,11 @@ struct vuda_world {
   vuda::Policy pol;
   float* actions = nullptr;
   uint8_t* act_on = nullptr;
+  // metric-depth fetches: camera table and float staging, grown on demand
+  vuda::MetricCam* metric_cams = nullptr;
+  int64_t metric_cams_cap = 0;
+  float* metric_buf = nullptr;
+  int64_t metric_buf_cap = 0;
 
   std::map<std::tuple<int, int32_t, int32_t>, vuda::WorkList> lists;
   std::map<std::tuple<int, int32_t, int32_t, int>, hipGraphExec_t> graphs;

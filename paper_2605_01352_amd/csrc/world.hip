@@ -538,6 +538,11 @@ void vuda_world::free_all() {
   lists.clear();
   for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
   graphs.clear();
+  if (metric_cams) (void)hipFree(metric_cams);
+  if (metric_buf) (void)hipFree(metric_buf);
+  metric_cams = nullptr;
+  metric_buf = nullptr;
+  metric_cams_cap = metric_buf_cap = 0;
   destroy_streams();
   if (s_serial) (void)hipStreamDestroy(s_serial);
   s_serial = nullptr;
@@ -1307,6 +1312,7 @@ static size_t elem_bytes(vuda_world* w, int what) {
     case VUDA_FETCH_CONTACTS: return 4 * (size_t)w->phys.substeps * (1 + 2 * (size_t)w->pair_cap);
     case VUDA_FETCH_FLAGS: return 4;
     case VUDA_FETCH_ACTIONS: return w->pol.set ? 4 * (size_t)w->pol.A : 0;
+    case VUDA_FETCH_DEPTH_METRIC: return 4;
     default: return 0;
   }
 }
@@ -1341,6 +1347,72 @@ static void state_runs(const vuda_world* w, int32_t lo, int32_t hi, std::vector<
     else
       runs.push_back({par, d.body_off, d.n_bodies});
   }
+}
+
+// Metric depth of the cameras of the active envs in [lo, hi), in fetch
+// order, through the conversion kernel (into dst when it is device memory,
+// else into a staging buffer copied out).  Each camera's view-projection
+// must be a perspective of the usual form: row 2 = alpha row 3 + beta e_4.
+static int fetch_depth_metric(vuda_world* w, int32_t lo, int32_t hi, float* dst, int64_t total, int32_t on_device) {
+  std::vector<MetricCam> cams;
+  int64_t pos = 0, max_pix = 0;
+  for (int32_t e = lo; e < hi; ++e) {
+    if (!w->env_active[e]) continue;
+    const EnvDev& d = w->env_host[e];
+    for (int32_t k = 0; k < d.n_cams; ++k) {
+      const CamDev& c = w->cam_host[d.cam_off + k];
+      const float* m = c.vp;
+      double r2r3 = 0.0, r3r3 = 0.0, r2r2 = 0.0;
+      for (int j = 0; j < 3; ++j) {
+        r2r3 += (double)m[8 + j] * m[12 + j];
+        r3r3 += (double)m[12 + j] * m[12 + j];
+        r2r2 += (double)m[8 + j] * m[8 + j];
+      }
+      MetricCam mc;
+      mc.alpha = r3r3 > 0.0 ? r2r3 / r3r3 : 0.0;
+      mc.beta = (double)m[11] - mc.alpha * m[15];
+      double off = 0.0;  // row 2 minus alpha row 3, first three columns
+      for (int j = 0; j < 3; ++j) {
+        const double t = (double)m[8 + j] - mc.alpha * m[12 + j];
+        off += t * t;
+      }
+      if (!(r3r3 > 0.0) || off > 1e-12 * (r2r2 + 1.0) || !(mc.beta != 0.0))
+        return fail(VUDA_EINVAL, "env %d camera %d: view-projection is not a perspective of the usual form", e, k);
+      mc.pix_off = c.pix_off;
+      mc.out_off = pos;
+      mc.npix = (int64_t)c.w * c.h;
+      pos += mc.npix;
+      max_pix = std::max(max_pix, mc.npix);
+      cams.push_back(mc);
+    }
+  }
+  if (pos != total) return fail(VUDA_EINVAL, "metric depth: %lld pixels, expected %lld", (long long)pos,
+                                (long long)total);
+  if (cams.empty()) return VUDA_OK;
+  HIPCHK(hipSetDevice(w->device));
+  if ((int64_t)cams.size() > w->metric_cams_cap) {
+    if (w->metric_cams) HIPCHK(hipFree(w->metric_cams));
+    w->metric_cams = nullptr;
+    w->metric_cams_cap = 0;
+    HIPCHK(hipMalloc(&w->metric_cams, sizeof(MetricCam) * cams.size()));
+    w->metric_cams_cap = (int64_t)cams.size();
+  }
+  float* out = dst;
+  if (!on_device) {
+    if (total > w->metric_buf_cap) {
+      if (w->metric_buf) HIPCHK(hipFree(w->metric_buf));
+      w->metric_buf = nullptr;
+      w->metric_buf_cap = 0;
+      HIPCHK(hipMalloc(&w->metric_buf, 4 * (size_t)total));
+      w->metric_buf_cap = total;
+    }
+    out = w->metric_buf;
+  }
+  HIPCHK(hipMemcpy(w->metric_cams, cams.data(), sizeof(MetricCam) * cams.size(), hipMemcpyHostToDevice));
+  HIPCHK(launch_depth_metric(w->dev.depth, w->metric_cams, (int32_t)cams.size(), max_pix, out, w->s_render));
+  HIPCHK(hipStreamSynchronize(w->s_render));
+  if (!on_device) HIPCHK(hipMemcpy(dst, out, 4 * (size_t)total, hipMemcpyDeviceToHost));
+  return w->check_flags();
 }
 
 extern "C" int vuda_fetch(vuda_world* w, int32_t what, int32_t lo, int32_t hi, void* dst,
@@ -1383,6 +1455,7 @@ extern "C" int vuda_fetch(vuda_world* w, int32_t what, int32_t lo, int32_t hi, v
     }
     return w->check_flags();
   }
+  if (what == VUDA_FETCH_DEPTH_METRIC) return fetch_depth_metric(w, lo, hi, (float*)dst, total, on_device);
   const unsigned char* base = nullptr;
   switch (what) {
     case VUDA_FETCH_RGB: base = w->dev.rgb; break;

@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(HERE, "lib", "libvuda.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENUMERIC, EOVERFLOW, EBUSY = 0, -1, -2, -3, -4, -5, -6
 PHASE_STEP, PHASE_RENDER, PHASE_ALL = 1, 2, 3
-FETCH_STATE, FETCH_RGB, FETCH_DEPTH, FETCH_CONTACTS, FETCH_WINNERS, FETCH_COVERAGE, FETCH_FLAGS, FETCH_ACTIONS = range(8)
+FETCH_STATE, FETCH_RGB, FETCH_DEPTH, FETCH_CONTACTS, FETCH_WINNERS, FETCH_COVERAGE, FETCH_FLAGS, FETCH_ACTIONS, \
+    FETCH_DEPTH_METRIC = range(9)
 FLAG_DEBUG = 1
 TUNE_RASTER_THREADS, TUNE_REC_CAP, TUNE_PHYS_PERSISTENT, TUNE_RASTER_PERSISTENT, TUNE_GRAPHS = 1, 2, 3, 4, 5
 TUNE_PHYS_PRIORITY = 6
@@ -349,7 +350,7 @@ class World:
             return out
         dt = {FETCH_STATE: np.float32, FETCH_RGB: np.uint8, FETCH_DEPTH: np.uint32,
               FETCH_CONTACTS: np.int32, FETCH_WINNERS: np.int32, FETCH_COVERAGE: np.int32,
-              FETCH_FLAGS: np.uint32, FETCH_ACTIONS: np.float32}[what]
+              FETCH_FLAGS: np.uint32, FETCH_ACTIONS: np.float32, FETCH_DEPTH_METRIC: np.float32}[what]
         buf = np.zeros(nbytes // np.dtype(dt).itemsize, dt)
         check(lib().vuda_fetch(self._w, what, lo, hi, _p(buf), C.c_size_t(nbytes), 0))
         return buf

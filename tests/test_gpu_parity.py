@@ -143,3 +143,13 @@ def test_tuning_knobs_do_not_change_outputs():
             for a, b in zip(ref, out):
                 assert np.array_equal(a, b), f"knobs {knobs}"
         say(f"knobs {knobs}: identical")
+
+
+def test_datagen_camera_640x480_parity():
+    """The paper's data-generation camera shape: 640x480 (4:3, 40 x 30 tiles)
+    over 4 envs of the 1024-env config, 3 steps, every frame compared."""
+    s = sg.config_scene(2, n_envs=4)
+    s.cam_w[:] = 640
+    s.cam_h[:] = 480
+    s.cam_vp[:] = sg.view_proj(sg.FIXED_EYE, aspect=640.0 / 480.0).reshape(1, 16)
+    run_parity(s, 3, render_every=1, label="c2[0:4] at 640x480")

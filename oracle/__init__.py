@@ -58,6 +58,7 @@ def lib():
         _lib.oracle_run_batch.restype = C.c_int
         _lib.oracle_narrowphase.restype = C.c_int
         _lib.oracle_setup_triangle.restype = C.c_int
+        _lib.oracle_setup_clipped.restype = C.c_int
         _lib.oracle_covers.restype = C.c_int
     return _lib
 
@@ -191,6 +192,20 @@ def setup_triangle(w0, w1, w2, vp, W, H, near=0.05, guard=8192.0):
     ok = lib().oracle_setup_triangle(_p(a0), _p(a1), _p(a2), _p(v), W, H, C.c_float(near),
                                      C.c_float(guard), _p(X), _p(Y), _p(z), C.byref(A))
     return bool(ok), X, Y, z, A.value
+
+
+def setup_clipped(w0, w1, w2, vp, W, H, near=0.05, guard=8192.0):
+    """Near-plane clipped setup: list of (X, Y, z, area) triangles (0..2)."""
+    X = np.zeros(6, np.int32)
+    Y = np.zeros(6, np.int32)
+    z = np.zeros(6, np.float32)
+    A = np.zeros(2, np.int64)
+    f = lambda a: np.ascontiguousarray(a, np.float32)
+    a0, a1, a2, v = f(w0), f(w1), f(w2), f(vp).reshape(16)
+    n = lib().oracle_setup_clipped(_p(a0), _p(a1), _p(a2), _p(v), W, H, C.c_float(near), C.c_float(guard),
+                                   _p(X), _p(Y), _p(z), _p(A))
+    return [(X[3 * s:3 * s + 3].copy(), Y[3 * s:3 * s + 3].copy(), z[3 * s:3 * s + 3].copy(), int(A[s]))
+            for s in range(n)]
 
 
 def covers(X, Y, px, py) -> bool:

@@ -360,6 +360,91 @@ int oracle_setup_triangle(const float* w0, const float* w1, const float* w2, con
   return A > 0;
 }
 
+/* Clip coordinates of a world-space point (the row dot products summed left
+ * to right, then the translation). */
+static void clip_coords(const float* wv, const float* vp, float* c) {
+  float x = wv[0], y = wv[1], zz = wv[2];
+  for (int r = 0; r < 4; ++r)
+    c[r] = ((vp[4 * r] * x + vp[4 * r + 1] * y) + vp[4 * r + 2] * zz) + vp[4 * r + 3];
+}
+
+/* Viewport transform and 24.8 snap of clip coordinates; 0 outside the
+ * guard band. */
+static int snap_clip(const float* c, int32_t W, int32_t H, float guard, int32_t* X, int32_t* Y, float* z) {
+  float nx = c[0] / c[3], ny = c[1] / c[3], nz = c[2] / c[3];
+  float sx = (nx * 0.5f + 0.5f) * (float)W;
+  float sy = (0.5f - ny * 0.5f) * (float)H;
+  if (fabsf(sx) > guard || fabsf(sy) > guard) return 0;
+  *X = (int32_t)rintf(sx * 256.0f);
+  *Y = (int32_t)rintf(sy * 256.0f);
+  *z = nz;
+  return 1;
+}
+
+/* The point where the edge from `in` (w >= near) to `out` (w < near) meets
+ * the plane w = near, always taken from the vertex in front, so that the two
+ * triangles sharing an edge cut it at the same point. */
+static void near_cut(const float* in, const float* out, float near_w, float* c) {
+  float t = (near_w - in[3]) / (out[3] - in[3]);
+  for (int r = 0; r < 4; ++r) c[r] = in[r] + t * (out[r] - in[r]);
+}
+
+int oracle_setup_clipped(const float* w0, const float* w1, const float* w2, const float* vp,
+                         int32_t W, int32_t H, float near_w, float guard,
+                         int32_t* X, int32_t* Y, float* z, int64_t* area) {
+  const float* wv[3] = {w0, w1, w2};
+  float c[3][4];
+  int in[3], n_in = 0;
+  for (int k = 0; k < 3; ++k) {
+    clip_coords(wv[k], vp, c[k]);
+    in[k] = !(c[k][3] < near_w);
+    n_in += in[k];
+  }
+  if (n_in == 0) return 0;
+  /* a vertex in front but outside the guard band culls the whole triangle */
+  int32_t vx[3], vy[3];
+  float vz[3];
+  for (int k = 0; k < 3; ++k)
+    if (in[k] && !snap_clip(c[k], W, H, guard, &vx[k], &vy[k], &vz[k])) return 0;
+  /* the polygon in front of the near plane, in the triangle's vertex order:
+   * 3 vertices (all in front, or one) or 4 (two in front) */
+  float q[4][4];
+  int32_t qx[4], qy[4];
+  float qz[4];
+  int qok[4], m = 0;
+  for (int k = 0; k < 3; ++k) {
+    int k1 = (k + 1) % 3;
+    if (in[k]) {
+      memcpy(q[m], c[k], sizeof(q[m]));
+      qx[m] = vx[k]; qy[m] = vy[k]; qz[m] = vz[k]; qok[m] = 1;
+      ++m;
+    }
+    if (in[k] != in[k1]) {
+      if (in[k]) near_cut(c[k], c[k1], near_w, q[m]);
+      else near_cut(c[k1], c[k], near_w, q[m]);
+      qok[m] = snap_clip(q[m], W, H, guard, &qx[m], &qy[m], &qz[m]);
+      ++m;
+    }
+  }
+  /* fan from the first vertex: (q0, q1, q2), then (q0, q2, q3); each in the
+   * order (0, 2, 1) (positive area for a front face) */
+  int n = 0;
+  for (int s = 0; s + 2 < m; ++s) {
+    int idx[3] = {0, s + 2, s + 1};
+    if (!(qok[idx[0]] && qok[idx[1]] && qok[idx[2]])) continue;
+    int32_t* Xo = X + 3 * n;
+    int32_t* Yo = Y + 3 * n;
+    float* zo = z + 3 * n;
+    for (int k = 0; k < 3; ++k) { Xo[k] = qx[idx[k]]; Yo[k] = qy[idx[k]]; zo[k] = qz[idx[k]]; }
+    int64_t A = (int64_t)(Xo[1] - Xo[0]) * (int64_t)(Yo[2] - Yo[0]) -
+                (int64_t)(Yo[1] - Yo[0]) * (int64_t)(Xo[2] - Xo[0]);
+    if (A <= 0) continue;
+    area[n] = A;
+    ++n;
+  }
+  return n;
+}
+
 static int64_t edge_fn(int32_t xa, int32_t ya, int32_t xb, int32_t yb, int64_t px, int64_t py) {
   return (int64_t)(xb - xa) * (py - ya) - (int64_t)(yb - ya) * (px - xa);
 }
@@ -383,13 +468,23 @@ int oracle_covers(const int32_t* X, const int32_t* Y, int32_t px, int32_t py) {
          edge_in(E2, X[0], Y[0], X[1], Y[1]);
 }
 
+static void raster_snapped(const int32_t* X, const int32_t* Y, const float* z, int64_t A, uint32_t prim,
+                           int32_t W, int32_t Hh, uint64_t* keys, int32_t* cover);
+
+/* The part of a triangle in front of the near plane, as one or two
+ * triangles with the triangle's primitive id. */
 static void raster_tri(const float* w0, const float* w1, const float* w2, uint32_t prim,
                        const float* vp, int32_t W, int32_t Hh, const oracle_render_params* rp,
                        uint64_t* keys, int32_t* cover) {
-  int32_t X[3], Y[3];
-  float z[3];
-  int64_t A;
-  if (!oracle_setup_triangle(w0, w1, w2, vp, W, Hh, rp->near_w, rp->guard, X, Y, z, &A)) return;
+  int32_t X[6], Y[6];
+  float z[6];
+  int64_t A[2];
+  int n = oracle_setup_clipped(w0, w1, w2, vp, W, Hh, rp->near_w, rp->guard, X, Y, z, A);
+  for (int s = 0; s < n; ++s) raster_snapped(X + 3 * s, Y + 3 * s, z + 3 * s, A[s], prim, W, Hh, keys, cover);
+}
+
+static void raster_snapped(const int32_t* X, const int32_t* Y, const float* z, int64_t A, uint32_t prim,
+                           int32_t W, int32_t Hh, uint64_t* keys, int32_t* cover) {
   int32_t xmin = X[0], xmax = X[0], ymin = Y[0], ymax = Y[0];
   for (int k = 1; k < 3; ++k) {
     if (X[k] < xmin) xmin = X[k];

@@ -112,6 +112,18 @@ int oracle_setup_triangle(const float* w0, const float* w1, const float* w2, con
                           int32_t W, int32_t H, float near_w, float guard,
                           int32_t* X, int32_t* Y, float* z, int64_t* area);
 
+/* Setup with near-plane clipping: the part of the triangle (world-space
+ * vertices in template order) in front of the plane clip w = near_w, as 0,
+ * 1 or 2 triangles of positive area.  A vertex in front but outside the
+ * guard band culls the whole triangle; an edge crossing the plane is cut at
+ * in + t (out - in), t = (near_w - w_in) / (w_out - w_in), from its vertex in
+ * front; the polygon is split as a fan from its first vertex, and a piece
+ * with a cut point outside the guard band is dropped.  Writes triangle s to
+ * X, Y, z [3 s .. 3 s + 2] (edge order) and area[s]; returns their count. */
+int oracle_setup_clipped(const float* w0, const float* w1, const float* w2, const float* vp,
+                         int32_t W, int32_t H, float near_w, float guard,
+                         int32_t* X, int32_t* Y, float* z, int64_t* area);
+
 /* Coverage of one snapped triangle (vertices in edge order, area > 0) at a
  * pixel centre (256*px+128, 256*py+128).  Returns 1 if covered. */
 int oracle_covers(const int32_t* X, const int32_t* Y, int32_t px, int32_t py);

@@ -6,10 +6,12 @@
 //   2. every template vertex of every body (and the ground) is transformed
 //      once -- world = p + R (s v), clip = VP world, perspective divide,
 //      viewport, snap to 24.8 fixed point -- into an LDS vertex cache;
-//   3. culling: a triangle is dropped if a vertex is behind the near plane
-//      or outside the guard band, if it is back-facing or degenerate (integer
-//      area <= 0), or if its bounding box holds no pixel centre; survivors
-//      are compacted into a list;
+//   3. culling: a triangle is dropped if a vertex in front of the near plane
+//      is outside the guard band, if it is back-facing or degenerate (integer
+//      area <= 0), or if its bounding box holds no pixel centre; one that
+//      crosses the near plane is cut along it into one or two pieces (the
+//      polygon in front, split as a fan), each culled the same way;
+//      survivors are compacted into lists;
 //   4. each survivor gets a setup record in the image's raster scratch
 //      (snapped vertices in edge order, depths, 1/area, primitive and flat Lambert
 //      colour) and the tiles of its box are counted with LDS atomics;
@@ -53,7 +55,7 @@ __host__ __device__ inline int align16(int x) { return (x + 15) & ~15; }
 
 struct SetupLayout {
   // byte offsets into the setup kernel's dynamic LDS
-  int tpl, body, verts, vis, pmap, vmap, tiles, misc, total;
+  int tpl, body, verts, vis, cvis, pmap, vmap, tiles, misc, total;
   int nmax, vmax, tw;
 };
 
@@ -68,6 +70,7 @@ __host__ __device__ inline SetupLayout setup_layout(int max_bodies, int max_vert
   L.body = o;   o += align16(4 * 17 * L.nmax);
   L.verts = o;  o += align16(12 * L.vmax);
   L.vis = o;    o += align16(2 * max_tris);
+  L.cvis = o;   o += align16(4 * kClipRecs);  // near-plane pieces: primitive | piece << 16
   L.pmap = o;   o += align16(max_tris);   // primitive -> body map of the env
   L.vmap = o;   o += align16(L.vmax);     // vertex -> body map of the env
   L.tiles = o;  o += align16(4 * (3 * L.tw + 1));
@@ -101,7 +104,8 @@ __device__ __forceinline__ void quat_rot(float w, float x, float y, float z, flo
   m[8] = 1.0f - 2.0f * (xx + yy);
 }
 
-constexpr int32_t kInvalid = (int32_t)0x80000000;
+constexpr int32_t kInvalid = (int32_t)0x80000000;  // in front, outside the guard band
+constexpr int32_t kBehind = (int32_t)0x80000001;   // behind the near plane (clip w < near)
 
 // Snapped screen-space triangle in edge order (vertices 0, 2, 1 of the face).
 struct Tri {
@@ -138,7 +142,7 @@ __device__ __forceinline__ Tri load_tri(const int32_t* VX, const int32_t* VY, co
     t.X[k] = VX[v];
     t.Y[k] = VY[v];
     t.z[k] = VZ[v];
-    if (t.X[k] == kInvalid) t.ok = false;
+    if (t.X[k] == kInvalid || t.X[k] == kBehind) t.ok = false;
   }
   return t;
 }
@@ -159,6 +163,84 @@ __device__ __forceinline__ bool tri_pixels(const int32_t* X, const int32_t* Y, i
   *y0 = max(0, (ymin + 127) >> 8);
   *y1 = min(H - 1, (ymax - 128) >> 8);
   return *x0 <= *x1 && *y0 <= *y1;
+}
+
+// Viewport transform and 24.8 snap of clip coordinates c: X = kBehind when
+// near_test and c.w < near, kInvalid outside the guard band.
+__device__ __forceinline__ void snap_clip(float4 c, float fW, float fH, const Templates* T, bool near_test,
+                                          int32_t* X, int32_t* Y, float* z) {
+  *X = kInvalid;
+  *Y = kInvalid;
+  *z = 0.0f;
+  if (near_test && c.w < T->near_w) {
+    *X = *Y = kBehind;
+    return;
+  }
+  const float nx = c.x / c.w, ny = c.y / c.w, nz = c.z / c.w;
+  const float px = (nx * 0.5f + 0.5f) * fW;
+  const float py = (0.5f - ny * 0.5f) * fH;
+  if (!(fabsf(px) > T->guard || fabsf(py) > T->guard)) {
+    *X = (int32_t)rintf(px * 256.0f);
+    *Y = (int32_t)rintf(py * 256.0f);
+    *z = nz;
+  }
+}
+
+// The point where the edge from a (in front) to b (behind) meets the plane
+// w = near, taken from the vertex in front so that both triangles sharing
+// the edge cut it at the same point.
+__device__ __forceinline__ float4 near_cut(float4 a, float4 b, float near_w) {
+  const float t = (near_w - a.w) / (b.w - a.w);
+  return make_float4(a.x + t * (b.x - a.x), a.y + t * (b.y - a.y), a.z + t * (b.z - a.z), a.w + t * (b.w - a.w));
+}
+
+// Piece s (0 or 1) of the part of a triangle in front of the near plane (c:
+// clip coordinates of its vertices in face order, at least one in front and
+// none in front outside the guard band): the polygon in front, in face
+// order, split as a fan from its first vertex; the piece in edge order.
+// Returns false if there is no piece s; t->ok is false if a cut point falls
+// outside the guard band.
+__device__ __forceinline__ bool near_piece(const float4 c[3], int s, float fW, float fH, const Templates* T,
+                                           Tri* t) {
+  // the polygon's candidate points in cycle order: vertex k (if in front),
+  // then the cut of edge k -> k+1 (if it crosses); selected with static
+  // indices only, so that everything stays in registers
+  float4 val[6];
+  bool has[6], cut[6];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int k1 = k == 2 ? 0 : k + 1;
+    const bool ik = !(c[k].w < T->near_w), ik1 = !(c[k1].w < T->near_w);
+    val[2 * k] = c[k];
+    has[2 * k] = ik;
+    cut[2 * k] = false;
+    val[2 * k + 1] = ik ? near_cut(c[k], c[k1], T->near_w) : near_cut(c[k1], c[k], T->near_w);
+    has[2 * k + 1] = ik != ik1;
+    cut[2 * k + 1] = true;
+  }
+  int m = 0;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) m += has[j] ? 1 : 0;
+  if (s + 2 >= m) return false;
+  const int want[3] = {0, s + 2, s + 1};  // the piece (q0, q[s+1], q[s+2]) in edge order
+  t->ok = true;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    float4 q = val[0];
+    bool qc = false;
+    int n = 0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      if (has[j] && n == want[k]) {
+        q = val[j];
+        qc = cut[j];
+      }
+      n += has[j] ? 1 : 0;
+    }
+    snap_clip(q, fW, fH, T, !qc, &t->X[k], &t->Y[k], &t->z[k]);
+    if (t->X[k] == kInvalid || t->X[k] == kBehind) t->ok = false;
+  }
+  return true;
 }
 
 __device__ __forceinline__ bool top_left(int32_t dx, int32_t dy) {
@@ -329,6 +411,33 @@ __device__ __forceinline__ void bin_tile(const Tri& t, int r, int tx, int ty, in
 // setup kernel
 // ---------------------------------------------------------------------------
 
+// Clip coordinates of env-local vertex vi: the body's pose applied to the
+// scaled template vertex (the ground's vertices as they are), then the
+// camera's view-projection (row dot products summed left to right, then the
+// translation).
+__device__ __forceinline__ float4 vertex_clip(const Templates* T, const BodyLDS& B, int S, const uint8_t* gvmap,
+                                              int vi, const float* vp) {
+  float wx, wy, wz;
+  const int b = gvmap[vi];
+  if (b == kGroundBody) {
+    wx = T->ground_v[vi][0];
+    wy = T->ground_v[vi][1];
+    wz = T->ground_v[vi][2];
+  } else {
+    const int lv = vi - B.vb[b];
+    const float* tv = B.type[b] ? T->cube_v[lv] : T->sphere_v[lv];
+    const float s = B.s[b];
+    const float sx = s * tv[0], sy = s * tv[1], sz = s * tv[2];
+    const float* R = B.R + b;
+    wx = B.p[b] + ((R[0] * sx + R[S] * sy) + R[2 * S] * sz);
+    wy = B.p[S + b] + ((R[3 * S] * sx + R[4 * S] * sy) + R[5 * S] * sz);
+    wz = B.p[2 * S + b] + ((R[6 * S] * sx + R[7 * S] * sy) + R[8 * S] * sz);
+  }
+  return make_float4(((vp[0] * wx + vp[1] * wy) + vp[2] * wz) + vp[3], ((vp[4] * wx + vp[5] * wy) + vp[6] * wz) + vp[7],
+                     ((vp[8] * wx + vp[9] * wy) + vp[10] * wz) + vp[11],
+                     ((vp[12] * wx + vp[13] * wy) + vp[14] * wz) + vp[15]);
+}
+
 __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const WorldDev& W,
                             const RasterLaunch& L, int cam_id) {
   const int tid = threadIdx.x;
@@ -369,6 +478,7 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
   int32_t* VY = VX + Lo.vmax;
   float* VZ = (float*)(VY + Lo.vmax);
   uint16_t* vis = (uint16_t*)(lds + Lo.vis);
+  uint32_t* cvis = (uint32_t*)(lds + Lo.cvis);
   int32_t* tcount = (int32_t*)(lds + Lo.tiles);
   int32_t* toff = tcount + Lo.tw;
   int32_t* tfill = toff + Lo.tw + 1;
@@ -402,7 +512,7 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
     B.alb[b] = W.albedo[g];
   }
   const bool tiled = ntiles <= Lo.tw;
-  if (tid == 0) misc[2] = 0;
+  if (tid == 0) misc[2] = misc[3] = 0;
   if (tiled)
     for (int t = tid; t < ntiles; t += nthr) tcount[t] = 0;
   __syncthreads();
@@ -411,39 +521,9 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
   const float* vp = cam.vp;
   const float fW = (float)Wd, fH = (float)Ht;
   for (int vi = tid; vi < ed.n_verts; vi += nthr) {
-    float wx, wy, wz;
-    const int b = gvmap[vi];
-    if (b == kGroundBody) {
-      wx = T->ground_v[vi][0];
-      wy = T->ground_v[vi][1];
-      wz = T->ground_v[vi][2];
-    } else {
-      const int lv = vi - B.vb[b];
-      const float* tv = B.type[b] ? T->cube_v[lv] : T->sphere_v[lv];
-      const float s = B.s[b];
-      const float sx = s * tv[0], sy = s * tv[1], sz = s * tv[2];
-      const float* R = B.R + b;
-      const int S = Lo.nmax;
-      wx = B.p[b] + ((R[0] * sx + R[S] * sy) + R[2 * S] * sz);
-      wy = B.p[S + b] + ((R[3 * S] * sx + R[4 * S] * sy) + R[5 * S] * sz);
-      wz = B.p[2 * S + b] + ((R[6 * S] * sx + R[7 * S] * sy) + R[8 * S] * sz);
-    }
-    const float cx = ((vp[0] * wx + vp[1] * wy) + vp[2] * wz) + vp[3];
-    const float cy = ((vp[4] * wx + vp[5] * wy) + vp[6] * wz) + vp[7];
-    const float cz = ((vp[8] * wx + vp[9] * wy) + vp[10] * wz) + vp[11];
-    const float cw = ((vp[12] * wx + vp[13] * wy) + vp[14] * wz) + vp[15];
-    int32_t X = kInvalid, Y = kInvalid;
-    float z = 0.0f;
-    if (!(cw < T->near_w)) {
-      const float nx = cx / cw, ny = cy / cw, nz = cz / cw;
-      const float px = (nx * 0.5f + 0.5f) * fW;
-      const float py = (0.5f - ny * 0.5f) * fH;
-      if (!(fabsf(px) > T->guard || fabsf(py) > T->guard)) {
-        X = (int32_t)rintf(px * 256.0f);
-        Y = (int32_t)rintf(py * 256.0f);
-        z = nz;
-      }
-    }
+    int32_t X, Y;
+    float z;
+    snap_clip(vertex_clip(T, B, Lo.nmax, gvmap, vi, vp), fW, fH, T, true, &X, &Y, &z);
     VX[vi] = X;
     VY[vi] = Y;
     VZ[vi] = z;
@@ -454,7 +534,10 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
   // near plane and inside the guard band, its integer area is > 0 (front
   // facing, not degenerate) and its box holds a pixel centre.  Survivors are
   // compacted into vis (a wave ballot and one atomic per wave), so that the
-  // costlier steps below run on full waves.
+  // costlier steps below run on full waves.  A triangle that crosses the
+  // near plane (and has no vertex in front outside the guard band) is cut
+  // along it: its surviving pieces go to cvis, and become the records after
+  // the whole triangles.
   for (int base = 0; base < ntris; base += nthr) {
     const int pr = base + tid;
     bool keep = false;
@@ -464,6 +547,25 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
       const Tri t = load_tri(VX, VY, VZ, vid);
       int x0, x1, y0, y1;
       keep = t.ok && tri_area(t.X, t.Y) > 0 && tri_pixels(t.X, t.Y, Wd, Ht, &x0, &x1, &y0, &y1);
+      int behind = 0, outside = 0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        behind += VX[vid[k]] == kBehind;
+        outside += VX[vid[k]] == kInvalid;
+      }
+      if (behind > 0 && behind < 3 && outside == 0) {
+        float4 c[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) c[k] = vertex_clip(T, B, Lo.nmax, gvmap, vid[k], vp);
+        for (int sp = 0; sp < 2; ++sp) {
+          Tri q;
+          if (near_piece(c, sp, fW, fH, T, &q) && q.ok && tri_area(q.X, q.Y) > 0 &&
+              tri_pixels(q.X, q.Y, Wd, Ht, &x0, &x1, &y0, &y1)) {
+            const int slot = atomicAdd(&misc[3], 1);
+            if (slot < kClipRecs) cvis[slot] = (uint32_t)pr | ((uint32_t)sp << 16);
+          }
+        }
+      }
     }
     const uint64_t m = __ballot(keep);
     int wbase = 0;
@@ -473,7 +575,27 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
     if (keep) vis[wbase + below] = (uint16_t)pr;
   }
   __syncthreads();
-  const int nrec = misc[2];
+  const int nwhole = misc[2];
+  const int npieces = min(misc[3], kClipRecs);
+  const int nrec = nwhole + npieces;
+  if (tid == 0 && misc[3] > kClipRecs) atomicOr(&W.env_flags[cam.env], kFlagClipOverflow);
+  // record r: whole triangle vis[r], or piece cvis[r - nwhole]
+  const auto record_tri = [&](int r, int* pr, int* body, Tri* t) {
+    int vid[3];
+    if (r < nwhole) {
+      *pr = vis[r];
+      prim_vertices(T, B, gpmap[*pr], *pr, body, vid);
+      *t = load_tri(VX, VY, VZ, vid);
+      return;
+    }
+    const uint32_t e = cvis[r - nwhole];
+    *pr = (int)(e & 0xFFFFu);
+    prim_vertices(T, B, gpmap[*pr], *pr, body, vid);
+    float4 c[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c[k] = vertex_clip(T, B, Lo.nmax, gvmap, vid[k], vp);
+    near_piece(c, (int)(e >> 16), fW, fH, T, t);
+  };
 
   // 4. setup records (with the face colour) and tile counts, one surviving
   // triangle per lane.  A triangle whose box spans more than kWide tiles is
@@ -484,10 +606,9 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
     const int r = base + tid;
     int tx0 = 0, ty0 = 0, nx = 0, ny = 0;
     if (r < nrec) {
-      const int pr = vis[r];
-      int body, vid[3];
-      prim_vertices(T, B, gpmap[pr], pr, &body, vid);
-      const Tri t = load_tri(VX, VY, VZ, vid);
+      int pr, body;
+      Tri t;
+      record_tri(r, &pr, &body, &t);
       int x0, x1, y0, y1;
       tri_pixels(t.X, t.Y, Wd, Ht, &x0, &x1, &y0, &y1);
       const int64_t A = tri_area(t.X, t.Y);
@@ -532,10 +653,8 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
       int x0 = 0, x1 = 0, y0 = 0, y1 = 0, nx = 0, ny = 0;
       Tri t{};
       if (r < nrec) {
-        const int pr = vis[r];
-        int body, vid[3];
-        prim_vertices(T, B, gpmap[pr], pr, &body, vid);
-        t = load_tri(VX, VY, VZ, vid);
+        int pr, body;
+        record_tri(r, &pr, &body, &t);
         tri_pixels(t.X, t.Y, Wd, Ht, &x0, &x1, &y0, &y1);
         nx = (x1 >> 4) - (x0 >> 4) + 1;
         ny = (y1 >> 4) - (y0 >> 4) + 1;

@@ -24,6 +24,7 @@ constexpr int kTile = 16;           // raster tile edge in pixels
 constexpr uint32_t kFlagNonFinite = 1u;
 constexpr uint32_t kFlagContactOverflow = 2u;
 constexpr uint32_t kFlagBinOverflow = 4u;
+constexpr uint32_t kFlagClipOverflow = 8u;  // an image cut more near-plane pieces than kClipRecs
 
 struct EnvDev {
   int32_t body_off;   // first global body id
@@ -53,11 +54,13 @@ struct CamDev {
 // for each state buffer), written by the setup kernel and read by the tile
 // kernel: a header (record count, binned flag), the tile table
 // (bin offset, bin count per 16x16 tile), the setup records (kRecBytes each,
-// room for every primitive of the env) and the bins (u16 record ids, bit 15
-// set when the triangle covers the whole tile).
+// room for every primitive of the env and kClipRecs pieces of triangles cut
+// by the near plane) and the bins (u16 record ids, bit 15 set when the
+// triangle covers the whole tile).
 constexpr int kRecWords = 16;  // X0 Y0 X1 Y1 | X2 Y2 key z0 | z1 z2 invA rgb | box x, box y, flags, 0
 constexpr int kRecBytes = 4 * kRecWords;
 constexpr int kBinsPerTri = 4;  // bin capacity of an image, per primitive
+constexpr int kClipRecs = 64;   // records an image keeps for pieces of triangles cut by the near plane
 
 struct RsLayout {
   int64_t tiles, recs, bins, total;
@@ -70,8 +73,8 @@ __host__ __device__ inline RsLayout rs_layout(int32_t ntris, int32_t ntiles) {
   RsLayout r;
   r.tiles = 64;
   r.recs = rs_align(64 + 8 * (int64_t)ntiles);
-  r.bins = r.recs + rs_align((int64_t)kRecBytes * ntris);
-  r.bin_cap = kBinsPerTri * ntris;
+  r.bins = r.recs + rs_align((int64_t)kRecBytes * (ntris + kClipRecs));
+  r.bin_cap = kBinsPerTri * (ntris + kClipRecs);
   r.total = r.bins + rs_align(2 * (int64_t)r.bin_cap);
   return r;
 }

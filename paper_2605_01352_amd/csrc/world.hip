@@ -463,7 +463,7 @@ extern "C" int vuda_create_world(const vuda_world_desc* d, const vuda_allocator*
     w->cap_prims = init_prims + spare_b * mf + spare_e * (w->tpl.ground_nf + 15);
     w->cap_verts = init_verts + spare_b * mv + spare_e * (w->tpl.ground_nv + 15);
     // raster scratch of cameras admitted later.  Per camera and state buffer it is at most
-    // (kRecBytes + 2 kBinsPerTri) n_tris + 8 tiles + 829 bytes, and a camera
+    // (kRecBytes + 2 kBinsPerTri) (n_tris + kClipRecs) + 8 tiles + 829 bytes, and a camera
     // of W x H pixels has at most W H / 256 + 513 tiles; envs are assumed to
     // carry no more cameras each than the initial batch's most (at least 1).
     int32_t kcam = 1;
@@ -471,7 +471,8 @@ extern "C" int vuda_create_world(const vuda_world_desc* d, const vuda_allocator*
       kcam = std::max(kcam, d->initial.cam_off[e + 1] - d->initial.cam_off[e]);
     const int64_t spare_c = (int64_t)w->cap_cams - nc, spare_p = w->cap_pixels - npix;
     const int64_t spare_bytes = 2 * ((int64_t)(kRecBytes + 2 * kBinsPerTri) * kcam * (w->cap_prims - init_prims) +
-                                     spare_p / 32 + (829 + 8 * 513) * spare_c);
+                                     spare_p / 32 +
+                                     (829 + 8 * 513 + (int64_t)(kRecBytes + 2 * kBinsPerTri) * kClipRecs) * spare_c);
     w->cap_rs = w->rs_units(d->initial) + (spare_bytes + 255) / 256;
   }
   w->pc.h = d->phys.dt / (float)d->phys.substeps;
@@ -1014,7 +1015,7 @@ int vuda_world::check_flags() {
     any |= fl[e];
   }
   if (any & kFlagNonFinite) return fail(VUDA_ENUMERIC, "non-finite state (first env %d)", first);
-  if (any & (kFlagContactOverflow | kFlagBinOverflow))
+  if (any & (kFlagContactOverflow | kFlagBinOverflow | kFlagClipOverflow))
     return fail(VUDA_EOVERFLOW, "capacity overflow, flags 0x%x (first env %d)", any, first);
   return VUDA_OK;
 }

@@ -44,7 +44,7 @@ extern "C" {
 #define VUDA_ENOMEM    -2  /* device allocation failed or HBM budget exceeded */
 #define VUDA_EHIP      -3  /* a HIP runtime call failed (code in message)    */
 #define VUDA_ENUMERIC  -4  /* a physics step produced a non-finite state     */
-#define VUDA_EOVERFLOW -5  /* contact-pair or bin capacity exceeded          */
+#define VUDA_EOVERFLOW -5  /* contact-pair, bin or near-plane piece capacity exceeded */
 #define VUDA_EBUSY     -6  /* slots or budget not available right now        */
 
 /* ---- phases (vuda_wait, vuda_get_stream) ------------------------------- */
@@ -62,7 +62,8 @@ extern "C" {
                                  (debug worlds)                                        */
 #define VUDA_FETCH_COVERAGE 5 /* int32 per camera [H][W]: covering triangles (debug)    */
 #define VUDA_FETCH_FLAGS    6 /* uint32 per env: bit0 non-finite, bit1 contact overflow,
-                                 bit2 bin overflow                                     */
+                                 bit2 bin overflow, bit3 more than 64 near-plane pieces
+                                 in one image                                          */
 #define VUDA_FETCH_ACTIONS  7 /* float per env [3 act_bodies]: the policy's last actions
                                  (zeros before the first vuda_act); needs a policy     */
 #define VUDA_FETCH_DEPTH_METRIC 8 /* float per camera [H][W]: view depth [m] along the

@@ -167,3 +167,18 @@ def test_near_plane_clipping_parity():
     for c, (eye, tgt) in enumerate(eyes):
         s.cam_vp[c] = sg.view_proj(eye, target=tgt).reshape(16)
     run_parity(s, 6, render_every=1, label="near-plane cameras")
+
+
+def test_near_plane_piece_overflow_is_reported():
+    """More pieces of near-plane cuts than an image keeps (64): 30 small
+    spheres straddling the near plane inside the view.  The render reports
+    VUDA_EOVERFLOW instead of drawing an image with pieces missing."""
+    rng = np.random.default_rng(5)
+    bodies = [dict(type=0, size=0.006, pos=(float(x), float(y), 0.95)) for x, y in rng.uniform(-0.02, 0.02, (30, 2))]
+    vp = sg.view_proj((0.0, 0.0, 1.0), target=(0.0, 0.0, 0.0), up=(0.0, 1.0, 0.0))
+    s = tiny_scene(bodies, res=64, vp=vp)
+    with vuda.World(s) as w:
+        w.render()
+        with pytest.raises(vuda.VudaError) as err:
+            w.wait()
+        assert err.value.code == vuda.EOVERFLOW

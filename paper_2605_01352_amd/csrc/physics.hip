@@ -946,7 +946,7 @@ hipError_t launch_reset_queue(int32_t* q, hipStream_t s) {
 }
 
 hipError_t launch_physics(const WorldDev& w, const PhysConsts& pc, const PhysLaunch& l,
-                          hipStream_t s) {
+                          hipStream_t s, LaunchEvents* ev) {
   if (l.n_work <= 0) return hipSuccess;
   const int nw = l.max_bodies <= 64 ? 1 : 2;
   for (int t = 0; t < l.nsteps; ++t) {
@@ -959,13 +959,13 @@ hipError_t launch_physics(const WorldDev& w, const PhysConsts& pc, const PhysLau
     }
     const bool fr = pc.mu > 0.0f;
     if (nw == 1 && !fr)
-      hipLaunchKernelGGL((physics_kernel<1, false>), dim3(grid), dim3(64), 0, s, w, pc, lt);
+      timed_launch(ev, t == 0, t == l.nsteps - 1, physics_kernel<1, false>, dim3(grid), dim3(64), 0, s, w, pc, lt);
     else if (nw == 1)
-      hipLaunchKernelGGL((physics_kernel<1, true>), dim3(grid), dim3(64), 0, s, w, pc, lt);
+      timed_launch(ev, t == 0, t == l.nsteps - 1, physics_kernel<1, true>, dim3(grid), dim3(64), 0, s, w, pc, lt);
     else if (!fr)
-      hipLaunchKernelGGL((physics_kernel<2, false>), dim3(grid), dim3(128), 0, s, w, pc, lt);
+      timed_launch(ev, t == 0, t == l.nsteps - 1, physics_kernel<2, false>, dim3(grid), dim3(128), 0, s, w, pc, lt);
     else
-      hipLaunchKernelGGL((physics_kernel<2, true>), dim3(grid), dim3(128), 0, s, w, pc, lt);
+      timed_launch(ev, t == 0, t == l.nsteps - 1, physics_kernel<2, true>, dim3(grid), dim3(128), 0, s, w, pc, lt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

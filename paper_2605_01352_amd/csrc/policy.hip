@@ -376,15 +376,16 @@ __global__ __launch_bounds__(256) void policy_dense_kernel(const float* X, const
 
 }  // namespace
 
-hipError_t launch_policy(const WorldDev& w, const PolicyLaunch& l, hipStream_t s) {
+hipError_t launch_policy(const WorldDev& w, const PolicyLaunch& l, hipStream_t s, LaunchEvents* ev) {
   if (l.M <= 0) return hipSuccess;
   const dim3 g1((l.M + kRows - 1) / kRows, (l.H + kCols - 1) / kCols, l.splits);
-  hipLaunchKernelGGL(policy_l1_kernel, g1, dim3(256), 0, s, w, l);
+  timed_launch(ev, true, false, policy_l1_kernel, g1, dim3(256), 0, s, w, l);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (!l.layered) {
     const int threads = (l.H + 63) / 64 * 64;
-    hipLaunchKernelGGL(policy_head_kernel, dim3(l.M), dim3(threads), 2 * l.H * sizeof(float), s, w, l);
+    timed_launch(ev, false, true, policy_head_kernel, dim3(l.M), dim3(threads), (uint32_t)(2 * l.H * sizeof(float)), s,
+                 w, l);
     return hipGetLastError();
   }
   // h1, then layer 2 into the partials (free again once h1 is made), h2,
@@ -397,7 +398,7 @@ hipError_t launch_policy(const WorldDev& w, const PolicyLaunch& l, hipStream_t s
   hipLaunchKernelGGL(policy_hidden_kernel, gh, dim3(256), 0, s, l.partial, l.s2, l.M, l.H, l.b2, l.h2);
   hipLaunchKernelGGL(policy_dense_kernel, dim3(mt, l.Ap / kDTile, l.s3), dim3(256), 0, s, l.h2, l.w3p, l.M, l.H,
                      l.Ap, l.H / l.s3, l.partial);
-  hipLaunchKernelGGL(policy_act_kernel, dim3(l.M), dim3(256), 0, s, w, l, l.partial, l.s3, l.Ap);
+  timed_launch(ev, false, true, policy_act_kernel, dim3(l.M), dim3(256), 0, s, w, l, (const float*)l.partial, l.s3, l.Ap);
   return hipGetLastError();
 }
 

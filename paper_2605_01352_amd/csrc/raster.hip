@@ -70,11 +70,11 @@ __host__ __device__ inline SetupLayout setup_layout(int max_bodies, int max_vert
   L.body = o;   o += align16(4 * 17 * L.nmax);
   L.verts = o;  o += align16(12 * L.vmax);
   L.vis = o;    o += align16(2 * max_tris);
-  L.cvis = o;   o += align16(4 * kClipRecs);  // near-plane pieces: primitive | piece << 16
+  L.cvis = o;   o += align16(40 * kClipRecs);  // near-plane pieces: X[3] Y[3] z[3], primitive
   L.pmap = o;   o += align16(max_tris);   // primitive -> body map of the env
   L.vmap = o;   o += align16(L.vmax);     // vertex -> body map of the env
   L.tiles = o;  o += align16(4 * (3 * L.tw + 1));
-  L.misc = o;   o += 128;  // [2] record count, [4] queue slot, [8, 24) scan totals
+  L.misc = o;   o += 128;  // [2] record count, [3] near-plane pieces, [4] queue slot, [8, 24) scan totals
   L.total = o;
   return L;
 }
@@ -478,7 +478,7 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
   int32_t* VY = VX + Lo.vmax;
   float* VZ = (float*)(VY + Lo.vmax);
   uint16_t* vis = (uint16_t*)(lds + Lo.vis);
-  uint32_t* cvis = (uint32_t*)(lds + Lo.cvis);
+  int32_t* cvis = (int32_t*)(lds + Lo.cvis);  // 10 words per piece
   int32_t* tcount = (int32_t*)(lds + Lo.tiles);
   int32_t* toff = tcount + Lo.tw;
   int32_t* tfill = toff + Lo.tw + 1;
@@ -550,8 +550,8 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
       int behind = 0, outside = 0;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        behind += VX[vid[k]] == kBehind;
-        outside += VX[vid[k]] == kInvalid;
+        behind += t.X[k] == kBehind;
+        outside += t.X[k] == kInvalid;
       }
       if (behind > 0 && behind < 3 && outside == 0) {
         float4 c[3];
@@ -559,10 +559,22 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
         for (int k = 0; k < 3; ++k) c[k] = vertex_clip(T, B, Lo.nmax, gvmap, vid[k], vp);
         for (int sp = 0; sp < 2; ++sp) {
           Tri q;
+          q.ok = false;
           if (near_piece(c, sp, fW, fH, T, &q) && q.ok && tri_area(q.X, q.Y) > 0 &&
               tri_pixels(q.X, q.Y, Wd, Ht, &x0, &x1, &y0, &y1)) {
+            // the piece itself is kept, so that the record and binning
+            // passes need not cut again
             const int slot = atomicAdd(&misc[3], 1);
-            if (slot < kClipRecs) cvis[slot] = (uint32_t)pr | ((uint32_t)sp << 16);
+            if (slot < kClipRecs) {
+              int32_t* o = cvis + 10 * slot;
+#pragma unroll
+              for (int k = 0; k < 3; ++k) {
+                o[k] = q.X[k];
+                o[3 + k] = q.Y[k];
+                o[6 + k] = __float_as_int(q.z[k]);
+              }
+              o[9] = pr;
+            }
           }
         }
       }
@@ -588,13 +600,16 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
       *t = load_tri(VX, VY, VZ, vid);
       return;
     }
-    const uint32_t e = cvis[r - nwhole];
-    *pr = (int)(e & 0xFFFFu);
+    const int32_t* o = cvis + 10 * (r - nwhole);
+    *pr = o[9];
     prim_vertices(T, B, gpmap[*pr], *pr, body, vid);
-    float4 c[3];
+    t->ok = true;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) c[k] = vertex_clip(T, B, Lo.nmax, gvmap, vid[k], vp);
-    near_piece(c, (int)(e >> 16), fW, fH, T, t);
+    for (int k = 0; k < 3; ++k) {
+      t->X[k] = o[k];
+      t->Y[k] = o[3 + k];
+      t->z[k] = __int_as_float(o[6 + k]);
+    }
   };
 
   // 4. setup records (with the face colour) and tile counts, one surviving
@@ -1003,7 +1018,7 @@ hipError_t raster_configure(size_t lds_bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
 }
 
-hipError_t launch_raster_setup(const WorldDev& w, const RasterLaunch& l, hipStream_t s) {
+hipError_t launch_raster_setup(const WorldDev& w, const RasterLaunch& l, hipStream_t s, LaunchEvents* ev) {
   if (l.n_work <= 0) return hipSuccess;
   const size_t lds = raster_lds_bytes(l);
   const int grid = l.persistent > 0 ? (l.persistent < l.n_work ? l.persistent : l.n_work) : l.n_work;
@@ -1011,16 +1026,16 @@ hipError_t launch_raster_setup(const WorldDev& w, const RasterLaunch& l, hipStre
     hipError_t e = launch_reset_queue(l.queue, s);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(raster_setup_kernel, dim3(grid), dim3(l.threads), lds, s, w, l);
+  timed_launch(ev, true, true, raster_setup_kernel, dim3(grid), dim3(l.threads), (uint32_t)lds, s, w, l);
   return hipGetLastError();
 }
 
-hipError_t launch_raster_tiles(const WorldDev& w, const RasterLaunch& l, hipStream_t s) {
+hipError_t launch_raster_tiles(const WorldDev& w, const RasterLaunch& l, hipStream_t s, LaunchEvents* ev) {
   if (l.n_tile_groups <= 0) return hipSuccess;
   if (w.winners)
-    hipLaunchKernelGGL(raster_tile_kernel<true>, dim3(l.n_tile_groups), dim3(64 * kTileWaves), 0, s, w, l);
+    timed_launch(ev, true, true, raster_tile_kernel<true>, dim3(l.n_tile_groups), dim3(64 * kTileWaves), 0, s, w, l);
   else
-    hipLaunchKernelGGL(raster_tile_kernel<false>, dim3(l.n_tile_groups), dim3(64 * kTileWaves), 0, s, w, l);
+    timed_launch(ev, true, true, raster_tile_kernel<false>, dim3(l.n_tile_groups), dim3(64 * kTileWaves), 0, s, w, l);
   return hipGetLastError();
 }
 

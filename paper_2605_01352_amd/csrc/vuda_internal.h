@@ -4,6 +4,7 @@
 // owns a body reads and writes its components with coalesced accesses.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -177,8 +178,30 @@ struct RasterLaunch {
   int32_t prio;            // setup kernel: wave issue priority 0..3 (s_setprio)
 };
 
+// Timing events of one launch (a kernel or a chain of them): `start` is
+// recorded when its first kernel begins and `stop` when its last one ends,
+// through HIP's extended launch, so that the span is the kernels' own time.
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+  bool started = false, stopped = false;
+};
+
+template <typename K, typename... A>
+inline void timed_launch(LaunchEvents* ev, bool first, bool last, K kernel, dim3 grid, dim3 block, uint32_t lds,
+                         hipStream_t s, A... args) {
+  hipEvent_t e0 = (ev && first && !ev->started) ? ev->start : nullptr;
+  hipEvent_t e1 = (ev && last) ? ev->stop : nullptr;
+  if (!e0 && !e1) {
+    hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+    return;
+  }
+  hipExtLaunchKernelGGL(kernel, grid, block, lds, s, e0, e1, 0, args...);
+  if (e0) ev->started = true;
+  if (e1) ev->stopped = true;
+}
+
 hipError_t launch_physics(const WorldDev& w, const PhysConsts& pc, const PhysLaunch& l,
-                          hipStream_t s);
+                          hipStream_t s, LaunchEvents* ev = nullptr);
 
 // The policy over M envs: layer 1 split over `splits` chunks of `kchunk`
 // observation values (MFMA), then layers 2 and 3 and the actions.
@@ -206,11 +229,11 @@ struct PolicyLaunch {
   float* h1;               // [M][H]
   float* h2;               // [M][H]
 };
-hipError_t launch_policy(const WorldDev& w, const PolicyLaunch& l, hipStream_t s);
+hipError_t launch_policy(const WorldDev& w, const PolicyLaunch& l, hipStream_t s, LaunchEvents* ev = nullptr);
 // The render work of a state buffer: setup (geometry, records, bins) into the
 // cameras' scratch of that buffer, then the tiles (pixels) from it.
-hipError_t launch_raster_setup(const WorldDev& w, const RasterLaunch& l, hipStream_t s);
-hipError_t launch_raster_tiles(const WorldDev& w, const RasterLaunch& l, hipStream_t s);
+hipError_t launch_raster_setup(const WorldDev& w, const RasterLaunch& l, hipStream_t s, LaunchEvents* ev = nullptr);
+hipError_t launch_raster_tiles(const WorldDev& w, const RasterLaunch& l, hipStream_t s, LaunchEvents* ev = nullptr);
 size_t raster_lds_bytes(const RasterLaunch& l);
 hipError_t raster_configure(size_t lds_bytes);
 hipError_t launch_reset_queue(int32_t* q, hipStream_t s);

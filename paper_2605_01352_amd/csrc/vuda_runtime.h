@@ -187,9 +187,10 @@ struct vuda_world {
   int get_list(int phase, int32_t lo, int32_t hi, const vuda::WorkList** out);
   int range_parity(int32_t lo, int32_t hi, int* parity);
   int check_range(int32_t lo, int32_t hi);
-  int enqueue_physics(const vuda::WorkList& L, int parity, hipStream_t s);
+  int enqueue_physics(const vuda::WorkList& L, int parity, hipStream_t s, vuda::LaunchEvents* ev = nullptr);
   int raster_launch_of(const vuda::WorkList& L, int parity, int32_t* queue, vuda::RasterLaunch* out);
-  int enqueue_kernel(int kind, const vuda::WorkList& L, int parity, hipStream_t s, int32_t* queue);
+  int enqueue_kernel(int kind, const vuda::WorkList& L, int parity, hipStream_t s, int32_t* queue,
+                     vuda::LaunchEvents* ev = nullptr);
   int run_kernel(int kind, const vuda::WorkList& L, int parity, int32_t lo, int32_t hi, hipStream_t s,
                  int32_t* queue);
   hipStream_t capture_stream();

@@ -789,7 +789,7 @@ int vuda_world::check_range(int32_t lo, int32_t hi) {
   return VUDA_OK;
 }
 
-int vuda_world::enqueue_physics(const WorkList& L, int parity, hipStream_t s) {
+int vuda_world::enqueue_physics(const WorkList& L, int parity, hipStream_t s, LaunchEvents* ev) {
   PhysLaunch pl;
   pl.work = L.dptr;
   pl.n_work = L.n;
@@ -800,7 +800,7 @@ int vuda_world::enqueue_physics(const WorkList& L, int parity, hipStream_t s) {
   pl.queue = queues;
   pl.prio = tune.phys_prio;
   pl.broadphase = tune.broadphase;
-  HIPCHK(launch_physics(dev, pc, pl, s));
+  HIPCHK(launch_physics(dev, pc, pl, s, ev));
   return VUDA_OK;
 }
 
@@ -832,13 +832,14 @@ int vuda_world::raster_launch_of(const WorkList& L, int parity, int32_t* queue, 
   return VUDA_OK;
 }
 
-int vuda_world::enqueue_kernel(int kind, const WorkList& L, int parity, hipStream_t s, int32_t* queue) {
-  if (kind == kKernelPhysics) return enqueue_physics(L, parity, s);
+int vuda_world::enqueue_kernel(int kind, const WorkList& L, int parity, hipStream_t s, int32_t* queue,
+                               LaunchEvents* ev) {
+  if (kind == kKernelPhysics) return enqueue_physics(L, parity, s, ev);
   if (kind == kKernelPolicy) {
     PolicyLaunch pl;
     int rc = policy_launch_of(L, &pl);
     if (rc) return rc;
-    HIPCHK(launch_policy(dev, pl, s));
+    HIPCHK(launch_policy(dev, pl, s, ev));
     return VUDA_OK;
   }
   RasterLaunch rl;
@@ -846,8 +847,8 @@ int vuda_world::enqueue_kernel(int kind, const WorkList& L, int parity, hipStrea
   if (rc) return rc;
   // the setup that ends a step (its own queue slot) runs at the step's priority
   if (kind == kKernelSetup) rl.prio = queue == queues + 1 ? tune.phys_prio : 0;
-  if (kind == kKernelSetup) HIPCHK(launch_raster_setup(dev, rl, s));
-  else HIPCHK(launch_raster_tiles(dev, rl, s));
+  if (kind == kKernelSetup) HIPCHK(launch_raster_setup(dev, rl, s, ev));
+  else HIPCHK(launch_raster_tiles(dev, rl, s, ev));
   return VUDA_OK;
 }
 
@@ -866,11 +867,22 @@ int vuda_world::run_kernel(int kind, const WorkList& L, int parity, int32_t lo, 
     }
     e0 = ev[i];
     e1 = ev[i + 1];
-    HIPCHK(hipEventRecord(e0, s));
+    // a replayed graph is timed from events around it; a direct launch from
+    // events bound to its kernels (their own span, without the launch gap)
+    if (tune.graphs) HIPCHK(hipEventRecord(e0, s));
   }
   int rc = VUDA_OK;
   if (!tune.graphs) {
-    rc = enqueue_kernel(kind, L, parity, s, queue);
+    LaunchEvents le;
+    le.start = e0;
+    le.stop = e1;
+    rc = enqueue_kernel(kind, L, parity, s, queue, e0 ? &le : nullptr);
+    if (rc) return rc;
+    if (e0 && !le.started) HIPCHK(hipEventRecord(e0, s));  // nothing was launched
+    if (e1 && le.stopped) {
+      ++tev_used[kind];
+      return VUDA_OK;
+    }
   } else {
     // the queue slot is part of the launch: it tells the two setup launch sites apart
     const int slot = queue ? (int)(queue - queues) : 0;

@@ -71,6 +71,10 @@ extern "C" {
 
 /* ---- world flags -------------------------------------------------------- */
 #define VUDA_FLAG_DEBUG 1u  /* keep contact sets, winners and coverage for fetch */
+#define VUDA_FLAG_NEAR_CLIP 2u /* cut triangles that cross the near plane into the
+                                  part in front (one or two pieces, at most 64 per
+                                  image, else VUDA_EOVERFLOW) instead of culling
+                                  them whole; images are otherwise unchanged    */
 
 typedef struct vuda_world vuda_world;
 

@@ -33,7 +33,7 @@ class RenderParams(C.Structure):
         ("cube_nv", C.c_int32), ("cube_nf", C.c_int32),
         ("ground_v", C.c_void_p), ("ground_f", C.c_void_p), ("ground_nf", C.c_int32),
         ("light", C.c_float * 3), ("palette", C.c_float * 24), ("ground_albedo", C.c_float),
-        ("near_w", C.c_float), ("guard", C.c_float)]
+        ("near_w", C.c_float), ("guard", C.c_float), ("near_clip", C.c_int32)]
 
 
 class Point(C.Structure):
@@ -76,7 +76,7 @@ def phys_params(scene) -> PhysParams:
 class _Render:
     """Keeps the template arrays alive while the struct points at them."""
 
-    def __init__(self, light=None, palette=None, ground_albedo=None, near=None, guard=None):
+    def __init__(self, light=None, palette=None, ground_albedo=None, near=None, guard=None, near_clip=False):
         from paper_2605_01352_amd import scenegen as sg
         t = sg.templates()
         self.arrs = [np.ascontiguousarray(a) for a in (
@@ -92,17 +92,19 @@ class _Render:
             (C.c_float * 24)(*np.asarray(palette, np.float32).reshape(-1).tolist()),
             float(sg.GROUND_ALBEDO if ground_albedo is None else ground_albedo),
             float(sg.NEAR if near is None else near),
-            float(sg.GUARD_BAND if guard is None else guard))
+            float(sg.GUARD_BAND if guard is None else guard), 1 if near_clip else 0)
 
 
-_RENDER: Optional[_Render] = None
+_RENDER: Dict[bool, _Render] = {}
 
 
-def render_params() -> _Render:
-    global _RENDER
-    if _RENDER is None:
-        _RENDER = _Render()
-    return _RENDER
+def render_params(near_clip: bool = False) -> _Render:
+    """Default render parameters; near_clip: cut triangles crossing the near
+    plane instead of culling them."""
+    near_clip = bool(near_clip)
+    if near_clip not in _RENDER:
+        _RENDER[near_clip] = _Render(near_clip=near_clip)
+    return _RENDER[near_clip]
 
 
 def step_env(scene, e: int, state: Dict[str, np.ndarray], record_pairs: bool = False,
@@ -172,7 +174,7 @@ def render_image(scene, state, cam: int, e: Optional[int] = None, debug: bool = 
     bt, sz, al = sl(scene.btype), sl(scene.size), sl(scene.albedo)
     pos, quat = sl(state["pos"]), sl(state["quat"])
     vp = np.ascontiguousarray(scene.cam_vp[cam], np.float32)
-    rp = render_params()
+    rp = render_params(getattr(scene, "near_clip", False))
     lib().oracle_render_image(b1 - b0, _p(bt), _p(sz), _p(al), _p(pos), _p(quat), _p(vp), W, H,
                               C.byref(rp.s), _p(rgb), _p(depth),
                               _p(winner) if debug else None, _p(cover) if debug else None)
@@ -236,7 +238,7 @@ def run_batch(scene, state, n_steps: int, nthreads: int, do_render: bool = True)
     for k in ("pos", "vel", "quat", "omega"):
         state[k] = np.ascontiguousarray(state[k], np.float32)
     prm = phys_params(scene)
-    rp = render_params()
+    rp = render_params(getattr(scene, "near_clip", False))
     st = lib().oracle_run_batch(
         scene.n_envs, _p(arrs["bo"]), _p(arrs["bt"]), _p(arrs["sz"]), _p(arrs["rb"]),
         _p(arrs["im"]), _p(arrs["iI"]), _p(arrs["al"]), _p(state["pos"]), _p(state["vel"]),

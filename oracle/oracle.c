@@ -471,15 +471,17 @@ int oracle_covers(const int32_t* X, const int32_t* Y, int32_t px, int32_t py) {
 static void raster_snapped(const int32_t* X, const int32_t* Y, const float* z, int64_t A, uint32_t prim,
                            int32_t W, int32_t Hh, uint64_t* keys, int32_t* cover);
 
-/* The part of a triangle in front of the near plane, as one or two
- * triangles with the triangle's primitive id. */
+/* A triangle, or with near_clip the part of it in front of the near plane
+ * (one or two triangles with the triangle's primitive id). */
 static void raster_tri(const float* w0, const float* w1, const float* w2, uint32_t prim,
                        const float* vp, int32_t W, int32_t Hh, const oracle_render_params* rp,
                        uint64_t* keys, int32_t* cover) {
   int32_t X[6], Y[6];
   float z[6];
   int64_t A[2];
-  int n = oracle_setup_clipped(w0, w1, w2, vp, W, Hh, rp->near_w, rp->guard, X, Y, z, A);
+  int n;
+  if (rp->near_clip) n = oracle_setup_clipped(w0, w1, w2, vp, W, Hh, rp->near_w, rp->guard, X, Y, z, A);
+  else n = oracle_setup_triangle(w0, w1, w2, vp, W, Hh, rp->near_w, rp->guard, X, Y, z, A);
   for (int s = 0; s < n; ++s) raster_snapped(X + 3 * s, Y + 3 * s, z + 3 * s, A[s], prim, W, Hh, keys, cover);
 }
 

@@ -56,6 +56,8 @@ typedef struct {
   float ground_albedo;
   float near_w;     /* cull a triangle if any vertex has clip w below this */
   float guard;      /* cull a triangle if any |screen coord| exceeds this  */
+  int32_t near_clip; /* nonzero: cut triangles crossing w = near_w instead
+                        (oracle_setup_clipped) */
 } oracle_render_params;
 
 /* One contact point as the narrowphase reports it. */

@@ -38,6 +38,8 @@
 // every record of the image -- slower, with the same output.
 #include <cstddef>
 
+#include <type_traits>
+
 #include "vuda_internal.h"
 
 #pragma clang fp contract(off)
@@ -60,7 +62,7 @@ struct SetupLayout {
 };
 
 __host__ __device__ inline SetupLayout setup_layout(int max_bodies, int max_verts, int max_tiles,
-                                                    int max_tris) {
+                                                    int max_tris, bool near_clip) {
   SetupLayout L;
   L.nmax = max_bodies + 1;
   L.vmax = max_verts;
@@ -70,11 +72,12 @@ __host__ __device__ inline SetupLayout setup_layout(int max_bodies, int max_vert
   L.body = o;   o += align16(4 * 17 * L.nmax);
   L.verts = o;  o += align16(12 * L.vmax);
   L.vis = o;    o += align16(2 * max_tris);
-  L.cvis = o;   o += align16(40 * kClipRecs);  // near-plane pieces: X[3] Y[3] z[3], primitive
+  L.cvis = o;   o += near_clip ? align16(40 * kClipRecs) : 0;  // near-plane pieces: X[3] Y[3] z[3], primitive
   L.pmap = o;   o += align16(max_tris);   // primitive -> body map of the env
   L.vmap = o;   o += align16(L.vmax);     // vertex -> body map of the env
   L.tiles = o;  o += align16(4 * (3 * L.tw + 1));
-  L.misc = o;   o += 128;  // [2] record count, [3] near-plane pieces, [4] queue slot, [8, 24) scan totals
+  L.misc = o;   o += 128;  // [2] record count, [3] near-plane pieces, [4] queue slot,
+                           // [5] a vertex behind the near plane, [8, 24) scan totals
   L.total = o;
   return L;
 }
@@ -142,7 +145,7 @@ __device__ __forceinline__ Tri load_tri(const int32_t* VX, const int32_t* VY, co
     t.X[k] = VX[v];
     t.Y[k] = VY[v];
     t.z[k] = VZ[v];
-    if (t.X[k] == kInvalid || t.X[k] == kBehind) t.ok = false;
+    if (t.X[k] <= kBehind) t.ok = false;  // kInvalid or kBehind
   }
   return t;
 }
@@ -438,6 +441,9 @@ __device__ __forceinline__ float4 vertex_clip(const Templates* T, const BodyLDS&
                      ((vp[12] * wx + vp[13] * wy) + vp[14] * wz) + vp[15]);
 }
 
+// CLIP: cut triangles crossing the near plane (else they are culled whole,
+// and none of that code is compiled in)
+template <bool CLIP>
 __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const WorldDev& W,
                             const RasterLaunch& L, int cam_id) {
   const int tid = threadIdx.x;
@@ -512,7 +518,7 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
     B.alb[b] = W.albedo[g];
   }
   const bool tiled = ntiles <= Lo.tw;
-  if (tid == 0) misc[2] = misc[3] = 0;
+  if (tid == 0) misc[2] = misc[3] = misc[5] = 0;
   if (tiled)
     for (int t = tid; t < ntiles; t += nthr) tcount[t] = 0;
   __syncthreads();
@@ -524,6 +530,7 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
     int32_t X, Y;
     float z;
     snap_clip(vertex_clip(T, B, Lo.nmax, gvmap, vi, vp), fW, fH, T, true, &X, &Y, &z);
+    if (CLIP && X == kBehind) misc[5] = 1;  // some vertex of the image is behind the near plane
     VX[vi] = X;
     VY[vi] = Y;
     VZ[vi] = z;
@@ -538,6 +545,9 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
   // near plane (and has no vertex in front outside the guard band) is cut
   // along it: its surviving pieces go to cvis, and become the records after
   // the whole triangles.
+  // (two versions of the pass: images with no vertex behind the near plane,
+  // nearly all of them, run the one without the cut)
+  const auto visibility = [&](auto cut_tag) {
   for (int base = 0; base < ntris; base += nthr) {
     const int pr = base + tid;
     bool keep = false;
@@ -547,6 +557,7 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
       const Tri t = load_tri(VX, VY, VZ, vid);
       int x0, x1, y0, y1;
       keep = t.ok && tri_area(t.X, t.Y) > 0 && tri_pixels(t.X, t.Y, Wd, Ht, &x0, &x1, &y0, &y1);
+      if constexpr (decltype(cut_tag)::value) {
       int behind = 0, outside = 0;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
@@ -578,6 +589,7 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
           }
         }
       }
+      }
     }
     const uint64_t m = __ballot(keep);
     int wbase = 0;
@@ -585,6 +597,13 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
     wbase = __builtin_amdgcn_readfirstlane(wbase);
     const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
     if (keep) vis[wbase + below] = (uint16_t)pr;
+  }
+  };
+  if constexpr (CLIP) {
+    if (misc[5]) visibility(std::true_type{});
+    else visibility(std::false_type{});
+  } else {
+    visibility(std::false_type{});
   }
   __syncthreads();
   const int nwhole = misc[2];
@@ -594,7 +613,7 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
   // record r: whole triangle vis[r], or piece cvis[r - nwhole]
   const auto record_tri = [&](int r, int* pr, int* body, Tri* t) {
     int vid[3];
-    if (r < nwhole) {
+    if (!CLIP || r < nwhole) {
       *pr = vis[r];
       prim_vertices(T, B, gpmap[*pr], *pr, body, vid);
       *t = load_tri(VX, VY, VZ, vid);
@@ -716,6 +735,7 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
   }
 }
 
+template <bool CLIP>
 __global__ void raster_setup_kernel(WorldDev W, RasterLaunch L) {
   extern __shared__ __align__(16) unsigned char lds[];
   // At the end of a step this kernel shares CUs with the render's tile
@@ -726,10 +746,10 @@ __global__ void raster_setup_kernel(WorldDev W, RasterLaunch L) {
     case 3: __builtin_amdgcn_s_setprio(3); break;
     default: break;
   }
-  const SetupLayout Lo = setup_layout(L.max_bodies, L.max_verts, L.max_tiles, L.max_tris);
+  const SetupLayout Lo = setup_layout(L.max_bodies, L.max_verts, L.max_tiles, L.max_tris, CLIP);
   if (L.persistent == 0) {
     if ((int)blockIdx.x >= L.n_work) return;
-    setup_image(lds, Lo, W, L, L.work[blockIdx.x]);
+    setup_image<CLIP>(lds, Lo, W, L, L.work[blockIdx.x]);
     return;
   }
   int32_t* slot = (int32_t*)(lds + Lo.misc) + 4;
@@ -739,7 +759,7 @@ __global__ void raster_setup_kernel(WorldDev W, RasterLaunch L) {
     __syncthreads();
     const int wi = *slot;
     if (wi >= L.n_work) return;
-    setup_image(lds, Lo, W, L, L.work[wi]);
+    setup_image<CLIP>(lds, Lo, W, L, L.work[wi]);
   }
 }
 
@@ -1010,12 +1030,15 @@ __global__ void __launch_bounds__(64 * kTileWaves) raster_tile_kernel(WorldDev W
 }  // namespace
 
 size_t raster_lds_bytes(const RasterLaunch& l) {
-  return (size_t)setup_layout(l.max_bodies, l.max_verts, l.max_tiles, l.max_tris).total;
+  return (size_t)setup_layout(l.max_bodies, l.max_verts, l.max_tiles, l.max_tris, l.near_clip != 0).total;
 }
 
 hipError_t raster_configure(size_t lds_bytes) {
-  return hipFuncSetAttribute((const void*)raster_setup_kernel,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+  const hipError_t e = hipFuncSetAttribute((const void*)raster_setup_kernel<false>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)raster_setup_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds_bytes);
 }
 
 hipError_t launch_raster_setup(const WorldDev& w, const RasterLaunch& l, hipStream_t s, LaunchEvents* ev) {
@@ -1026,7 +1049,10 @@ hipError_t launch_raster_setup(const WorldDev& w, const RasterLaunch& l, hipStre
     hipError_t e = launch_reset_queue(l.queue, s);
     if (e != hipSuccess) return e;
   }
-  timed_launch(ev, true, true, raster_setup_kernel, dim3(grid), dim3(l.threads), (uint32_t)lds, s, w, l);
+  if (l.near_clip)
+    timed_launch(ev, true, true, raster_setup_kernel<true>, dim3(grid), dim3(l.threads), (uint32_t)lds, s, w, l);
+  else
+    timed_launch(ev, true, true, raster_setup_kernel<false>, dim3(grid), dim3(l.threads), (uint32_t)lds, s, w, l);
   return hipGetLastError();
 }
 

@@ -176,6 +176,7 @@ struct RasterLaunch {
   int32_t persistent;      // setup kernel: resident workgroups pulling images
   int32_t* queue;
   int32_t prio;            // setup kernel: wave issue priority 0..3 (s_setprio)
+  int32_t near_clip;       // setup kernel: cut triangles crossing the near plane
 };
 
 // Timing events of one launch (a kernel or a chain of them): `start` is

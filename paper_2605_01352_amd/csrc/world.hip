@@ -446,6 +446,7 @@ extern "C" int vuda_create_world(const vuda_world_desc* d, const vuda_allocator*
   HIPCHK(hipGetDevice(&w->device));
   w->phys = d->phys;
   w->debug = (d->flags & VUDA_FLAG_DEBUG) != 0;
+  w->near_clip = (d->flags & VUDA_FLAG_NEAR_CLIP) != 0;
   w->pair_cap = d->pair_cap > 0 ? d->pair_cap : 1024;
   w->cap_envs = std::max(d->cap_envs, d->initial.n_envs);
   w->cap_bodies = std::max(d->cap_bodies, nb);
@@ -820,6 +821,7 @@ int vuda_world::raster_launch_of(const WorkList& L, int parity, int32_t* queue, 
   rl.persistent = tune.raster_persistent;
   rl.queue = queue;
   rl.prio = 0;
+  rl.near_clip = near_clip ? 1 : 0;
   const size_t lds = raster_lds_bytes(rl);
   const size_t kLdsMax = 160 * 1024;
   if (lds > kLdsMax)

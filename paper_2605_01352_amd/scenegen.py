@@ -262,6 +262,7 @@ class Scene:
     gravity: tuple = (0.0, 0.0, -9.81)
     mu: float = 0.0        # regularized Coulomb friction coefficient (0: none)
     v_eps: float = 0.05    # [m/s] slip speed below which friction is linear
+    near_clip: bool = False  # cut triangles crossing the near plane instead of culling them
     name: str = ""
     seed: int = 0
     env_gid0: int = 0

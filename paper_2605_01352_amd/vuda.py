@@ -21,6 +21,7 @@ PHASE_STEP, PHASE_RENDER, PHASE_ALL = 1, 2, 3
 FETCH_STATE, FETCH_RGB, FETCH_DEPTH, FETCH_CONTACTS, FETCH_WINNERS, FETCH_COVERAGE, FETCH_FLAGS, FETCH_ACTIONS, \
     FETCH_DEPTH_METRIC = range(9)
 FLAG_DEBUG = 1
+FLAG_NEAR_CLIP = 2
 TUNE_RASTER_THREADS, TUNE_REC_CAP, TUNE_PHYS_PERSISTENT, TUNE_RASTER_PERSISTENT, TUNE_GRAPHS = 1, 2, 3, 4, 5
 TUNE_PHYS_PRIORITY = 6
 TUNE_BROADPHASE = 7
@@ -233,7 +234,7 @@ class World:
                                (C.c_float * 3)(*[float(x) for x in g]), float(mu), float(v_eps))
         desc.render = render_desc(keep, **(render_kw or {}))
         desc.initial = env_batch(keep, scene) if scene is not None else EnvBatch(0)
-        desc.flags = FLAG_DEBUG if debug else 0
+        desc.flags = (FLAG_DEBUG if debug else 0) | (FLAG_NEAR_CLIP if getattr(ref, "near_clip", False) else 0)
         desc.cap_envs, desc.cap_bodies, desc.cap_cams, desc.cap_pixels = cap_envs, cap_bodies, cap_cams, cap_pixels
         desc.pair_cap = pair_cap
         desc.hbm_budget = hbm_budget
@@ -439,7 +440,7 @@ def world_desc(keep: _Keep, scene=None, debug: bool = False, cap_envs: int = 0, 
                         (C.c_float * 3)(*[float(x) for x in g]), float(mu), float(v_eps))
     d.render = render_desc(keep)
     d.initial = env_batch(keep, scene) if scene is not None else EnvBatch(0)
-    d.flags = FLAG_DEBUG if debug else 0
+    d.flags = (FLAG_DEBUG if debug else 0) | (FLAG_NEAR_CLIP if getattr(scene, "near_clip", False) else 0)
     d.cap_envs, d.cap_bodies, d.cap_cams, d.cap_pixels = cap_envs, cap_bodies, cap_cams, cap_pixels
     d.pair_cap = pair_cap
     d.hbm_budget = hbm_budget

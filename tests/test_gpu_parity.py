@@ -157,16 +157,19 @@ def test_datagen_camera_640x480_parity():
 
 def test_near_plane_clipping_parity():
     """Cameras a few centimetres above the ground and inside a pile of
-    bodies: the ground quad and nearby faces cross the near plane and are cut
-    along it (one or two pieces each); winners, depth and coverage bit-exact,
-    each pixel of the ground covered once."""
+    bodies: the ground quad and nearby faces cross the near plane.  With
+    VUDA_FLAG_NEAR_CLIP they are cut along it (one or two pieces each),
+    without it culled whole; winners, depth and coverage bit-exact either
+    way."""
     s = sg.config_scene(2, n_envs=6)
     eyes = [((0.0, 0.0, 0.03), (1.0, 0.2, -0.01)), ((0.3, -0.2, 0.02), (-1.0, 0.5, 0.05)),
             ((0.0, 0.0, 0.4), (0.3, 0.1, 0.0)), ((0.1, 0.1, 0.15), (0.0, 0.0, 0.0)),
             ((-0.2, 0.0, 0.06), (0.5, 0.0, 0.1)), ((0.05, -0.05, 0.25), (0.0, 0.3, 0.2))]
     for c, (eye, tgt) in enumerate(eyes):
         s.cam_vp[c] = sg.view_proj(eye, target=tgt).reshape(16)
-    run_parity(s, 6, render_every=1, label="near-plane cameras")
+    run_parity(s, 3, render_every=1, label="near-plane cameras, culled whole")
+    s.near_clip = True
+    run_parity(s, 6, render_every=1, label="near-plane cameras, cut")
 
 
 def test_near_plane_piece_overflow_is_reported():
@@ -177,6 +180,7 @@ def test_near_plane_piece_overflow_is_reported():
     bodies = [dict(type=0, size=0.006, pos=(float(x), float(y), 0.95)) for x, y in rng.uniform(-0.02, 0.02, (30, 2))]
     vp = sg.view_proj((0.0, 0.0, 1.0), target=(0.0, 0.0, 0.0), up=(0.0, 1.0, 0.0))
     s = tiny_scene(bodies, res=64, vp=vp)
+    s.near_clip = True
     with vuda.World(s) as w:
         w.render()
         with pytest.raises(vuda.VudaError) as err:

@@ -46,6 +46,7 @@ def test_ground_seen_from_just_above_is_cut_at_the_near_plane():
     sc = tiny_scene([dict(type=0, size=0.01, pos=(5.0, 5.0, 0.01))], res=W, vp=vp32)
     sc.cam_w[:] = W
     sc.cam_h[:] = H
+    sc.near_clip = True
     out = oracle.render_image(sc, sc.state(), 0, e=0, debug=True)
     cover, winner = out["cover"], out["winner"]
     vp = vp32.reshape(4, 4).astype(np.float64)
@@ -77,7 +78,9 @@ def test_ground_seen_from_just_above_is_cut_at_the_near_plane():
     assert np.all(cover <= 1)
     assert np.all((winner[want & decided] == 0) | (winner[want & decided] == 1))
     # both ground triangles reach behind the camera: without the cut they
-    # would be culled whole and nothing would be drawn
+    # are culled whole and nothing is drawn
+    sc.near_clip = False
+    assert oracle.render_image(sc, sc.state(), 0, e=0, debug=True)["cover"].sum() == 0
     t = sg.templates()
     for f in t.ground_f:
         ok, *_ = oracle.setup_triangle(*[t.ground_v[i] for i in f], vp32, W, H)

@@ -130,12 +130,13 @@ def test_top_left_orientation():
 def _render(scene, light=None, debug=True):
     if light is not None:
         rp = oracle._Render(light=light)
-        old = oracle._RENDER
-        oracle._RENDER = rp
+        old = dict(oracle._RENDER)
+        oracle._RENDER[False] = rp
         try:
             return oracle.render_image(scene, scene.state(), 0, debug=debug)
         finally:
-            oracle._RENDER = old
+            oracle._RENDER.clear()
+            oracle._RENDER.update(old)
     return oracle.render_image(scene, scene.state(), 0, debug=debug)
 
 

@@ -195,6 +195,54 @@ def policy_bench(torch, vuda, sg, scene, w, st0, steps, warmup, hidden, log):
     return out
 
 
+def features_bench(torch, vuda, sg, scene, steps, log):
+    """The optional features on the same workload, each in a world of its
+    own: friction (mu = 0.5) in the physics kernel, near-plane clipping in the
+    raster setup (cameras of this workload never cross the near plane, so
+    only the cost of the cutting code shows), and the metric-depth fetch of
+    every frame into device memory."""
+    import dataclasses
+    out = {}
+
+    def kernel_avg(w, kernel, nsteps):
+        w.set_tuning(vuda.TUNE_TIMING, 1)
+        w.kernel_times(kernel)
+        for _ in range(nsteps):
+            w.step()
+            w.render()
+        w.wait()
+        t = w.kernel_times(kernel)
+        w.set_tuning(vuda.TUNE_TIMING, 0)
+        return t["total_ms"] * 1e3 / max(1, t["launches"])
+
+    for name, sc, kernel in (("physics_mu0", scene, vuda.KERNEL_PHYSICS),
+                             ("physics_mu0.5", dataclasses.replace(scene, mu=0.5), vuda.KERNEL_PHYSICS),
+                             ("setup", scene, vuda.KERNEL_RASTER_SETUP),
+                             ("setup_near_clip", dataclasses.replace(scene, near_clip=True),
+                              vuda.KERNEL_RASTER_SETUP)):
+        with vuda.World(sc) as w:
+            for _ in range(10):
+                w.step()
+                w.render()
+            w.wait()
+            out[name + "_us"] = round(kernel_avg(w, kernel, steps), 2)
+    with vuda.World(scene) as w:
+        w.step(nsteps=5)
+        w.render()
+        w.wait()
+        n = w.fetch_bytes(vuda.FETCH_DEPTH_METRIC) // 4
+        dev = torch.empty(n, dtype=torch.float32, device="cuda")
+        w.fetch(vuda.FETCH_DEPTH_METRIC, out=dev)
+        t0 = time.perf_counter()
+        for _ in range(20):
+            w.fetch(vuda.FETCH_DEPTH_METRIC, out=dev)
+        dt = (time.perf_counter() - t0) / 20
+        out["metric_depth_fetch_us"] = round(dt * 1e6, 1)
+        out["metric_depth_GBs"] = round(8.0 * n / dt / 1e9, 1)  # 4 B read + 4 B written per pixel
+    log(f"features: {out}")
+    return out
+
+
 def cpu_baseline(scene_fn, n_envs, steps):
     import numpy as np  # noqa: F401
     import oracle
@@ -334,7 +382,7 @@ def main():
     prios = [int(p) for p in filter(None, args.prios.split(",")) if int(p) != p0]
     cands = [(2.0, sched, p0) for sched in ("interstep", "intertraj")]
     cands += [(2.0, sched, p) for p in prios for sched in ("interstep", "intertraj")]
-    cands += [(float(x), sched, p0) for x in args.splits.split(",") for sched in ("interstep", "intertraj")]
+    cands += [(float(x), sched, p0) for x in filter(None, args.splits.split(",")) for sched in ("interstep", "intertraj")]
     if args.only:
         cands = []
     sweep = {}
@@ -393,6 +441,10 @@ def main():
         else:
             log("policy loop skipped: the policy reads one frame size, the cameras differ")
 
+    features = None
+    if not args.only:
+        features = features_bench(torch, vuda, sg, scene, min(args.steps, 100), log)
+
     serving = None
     if args.serve_seconds > 0:
         from paper_2605_01352_amd import serving as srv
@@ -432,6 +484,7 @@ def main():
         "cpu_baseline": cpu,
         "serving": serving,
         "policy": policy,
+        "features": features,
     }
     print(json.dumps(line), flush=True)
 

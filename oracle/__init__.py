@@ -54,6 +54,8 @@ def lib():
         _lib = C.CDLL(path)
         _lib.oracle_step_env.restype = C.c_int
         _lib.oracle_step_env_ext.restype = C.c_int
+        _lib.oracle_step_env_box.restype = C.c_int
+        _lib.oracle_render_image_box.restype = C.c_int
         _lib.oracle_render_image.restype = C.c_int
         _lib.oracle_run_batch.restype = C.c_int
         _lib.oracle_narrowphase.restype = C.c_int
@@ -126,8 +128,11 @@ def step_env(scene, e: int, state: Dict[str, np.ndarray], record_pairs: bool = F
     npairs = np.zeros(S, np.int32)
     bt, sz, rb, im, iI = sl(scene.btype), sl(scene.size), sl(scene.rbound), sl(scene.inv_m), sl(scene.inv_I)
     fx = None if fext is None else np.ascontiguousarray(fext, np.float32).reshape(n, 3)
-    st = L.oracle_step_env_ext(n, _p(bt), _p(sz), _p(rb), _p(im), _p(iI), _p(pos), _p(vel), _p(quat),
-                               _p(om), C.byref(prm), _p(pairs) if pairs is not None else None,
+    ex = None if getattr(scene, "ext", None) is None else np.ascontiguousarray(scene.ext[b0:b1], np.float32)
+    ine = None if getattr(scene, "inertia", None) is None else np.ascontiguousarray(scene.inertia[b0:b1], np.float32)
+    st = L.oracle_step_env_box(n, _p(bt), _p(sz), _p(ex) if ex is not None else None,
+                               _p(ine) if ine is not None else None, _p(rb), _p(im), _p(iI), _p(pos), _p(vel),
+                               _p(quat), _p(om), C.byref(prm), _p(pairs) if pairs is not None else None,
                                pair_cap, _p(npairs), _p(fx) if fx is not None else None)
     state["pos"][b0:b1], state["vel"][b0:b1] = pos, vel
     state["quat"][b0:b1], state["omega"][b0:b1] = quat, om
@@ -175,7 +180,9 @@ def render_image(scene, state, cam: int, e: Optional[int] = None, debug: bool = 
     pos, quat = sl(state["pos"]), sl(state["quat"])
     vp = np.ascontiguousarray(scene.cam_vp[cam], np.float32)
     rp = render_params(getattr(scene, "near_clip", False))
-    lib().oracle_render_image(b1 - b0, _p(bt), _p(sz), _p(al), _p(pos), _p(quat), _p(vp), W, H,
+    ex = None if getattr(scene, "ext", None) is None else np.ascontiguousarray(scene.ext[b0:b1], np.float32)
+    lib().oracle_render_image_box(b1 - b0, _p(bt), _p(sz), _p(ex) if ex is not None else None, _p(al), _p(pos),
+                              _p(quat), _p(vp), W, H,
                               C.byref(rp.s), _p(rgb), _p(depth),
                               _p(winner) if debug else None, _p(cover) if debug else None)
     out = dict(rgb=rgb, depth=depth)

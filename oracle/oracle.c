@@ -52,15 +52,17 @@ static v3 mat_tvec(const float* m, v3 v) {
 static v3 load3(const float* a, int32_t i) { return mk(a[3 * i], a[3 * i + 1], a[3 * i + 2]); }
 
 /* Corner k of a cube of half-extent a: sign + on axis t iff bit t of k set. */
-static v3 cube_vertex(v3 p, const float* R, float a, int k) {
-  v3 w = mk((k & 1) ? a : -a, (k & 2) ? a : -a, (k & 4) ? a : -a);
+/* Corner k of a box of half-extents e (a cube: e = (a, a, a)): sign + on
+ * axis t iff bit t of k is set. */
+static v3 cube_vertex(v3 p, const float* R, v3 e, int k) {
+  v3 w = mk((k & 1) ? e.x : -e.x, (k & 2) ? e.y : -e.y, (k & 4) ? e.z : -e.z);
   return add(p, mat_vec(R, w));
 }
 
-/* Deepest-face axis of a local point strictly inside a box of half-extent a:
- * argmin over axes of (a - |u_axis|), lowest axis on ties. */
-static int min_axis(v3 u, float a, float* depth) {
-  float d0 = a - fabsf(u.x), d1 = a - fabsf(u.y), d2 = a - fabsf(u.z);
+/* Deepest-face axis of a local point strictly inside a box of half-extents
+ * e: argmin over axes of (e_axis - |u_axis|), lowest axis on ties. */
+static int min_axis(v3 u, v3 e, float* depth) {
+  float d0 = e.x - fabsf(u.x), d1 = e.y - fabsf(u.y), d2 = e.z - fabsf(u.z);
   int m = 0;
   float dm = d0;
   if (d1 < dm) { m = 1; dm = d1; }
@@ -94,11 +96,12 @@ static int np_sphere_sphere(v3 pi, float ri, v3 pj, float rj, oracle_point* out)
   return 1;
 }
 
-/* sphere (centre c, radius r) against cube (p, R, a); normal from cube to sphere */
-static int np_sphere_cube(v3 c, float r, v3 p, const float* R, float a, int sphere_first,
+/* sphere (centre c, radius r) against box (p, R, half-extents a); normal
+ * from the box to the sphere */
+static int np_sphere_cube(v3 c, float r, v3 p, const float* R, v3 a, int sphere_first,
                           oracle_point* out) {
   v3 u = mat_tvec(R, sub(c, p));
-  v3 e = mk(fminf(fmaxf(u.x, -a), a), fminf(fmaxf(u.y, -a), a), fminf(fmaxf(u.z, -a), a));
+  v3 e = mk(fminf(fmaxf(u.x, -a.x), a.x), fminf(fmaxf(u.y, -a.y), a.y), fminf(fmaxf(u.z, -a.z), a.z));
   v3 rv = sub(u, e);
   float L2 = dot(rv, rv);
   if (!(L2 < r * r)) return 0;
@@ -123,14 +126,14 @@ static int np_sphere_cube(v3 c, float r, v3 p, const float* R, float a, int sphe
   return 1;
 }
 
-/* vertices of cube A (pa, Ra, aa) strictly inside cube B (pb, Rb, ab) */
-static int np_vertices_in_box(v3 pa, const float* Ra, float aa, v3 pb, const float* Rb, float ab,
+/* vertices of box A (pa, Ra, half-extents aa) strictly inside box B (pb, Rb, ab) */
+static int np_vertices_in_box(v3 pa, const float* Ra, v3 aa, v3 pb, const float* Rb, v3 ab,
                               int a_first, oracle_point* out) {
   int cnt = 0;
   for (int k = 0; k < 8; ++k) {
     v3 v = cube_vertex(pa, Ra, aa, k);
     v3 u = mat_tvec(Rb, sub(v, pb));
-    if (fabsf(u.x) < ab && fabsf(u.y) < ab && fabsf(u.z) < ab) {
+    if (fabsf(u.x) < ab.x && fabsf(u.y) < ab.y && fabsf(u.z) < ab.z) {
       float dm;
       int m = min_axis(u, ab, &dm);
       v3 n = mat_vec(Rb, axis_dir(m, comp(u, m) >= 0.0f ? 1.0f : -1.0f));
@@ -144,7 +147,14 @@ static int np_vertices_in_box(v3 pa, const float* Ra, float aa, v3 pb, const flo
   return cnt;
 }
 
-static int np_ground(int32_t i, const uint8_t* type, const float* size, const float* pos,
+/* Half-extents of body i: its own for a box (type 2), (a, a, a) for a cube
+ * or a sphere of size a. */
+static v3 body_ext(int32_t i, const uint8_t* type, const float* size, const float* ext) {
+  if (type[i] == 2 && ext) return load3(ext, i);
+  return mk(size[i], size[i], size[i]);
+}
+
+static int np_ground(int32_t i, const uint8_t* type, const float* size, const float* ext, const float* pos,
                      const float* quat, oracle_point* out) {
   v3 p = load3(pos, i);
   float a = size[i];
@@ -158,9 +168,10 @@ static int np_ground(int32_t i, const uint8_t* type, const float* size, const fl
   }
   float R[9];
   quat_mat(quat + 4 * i, R);
+  v3 e = body_ext(i, type, size, ext);
   int cnt = 0;
   for (int k = 0; k < 8; ++k) {
-    v3 v = cube_vertex(p, R, a, k);
+    v3 v = cube_vertex(p, R, e, k);
     if (v.z < 0.0f) {
       oracle_point* o = &out[cnt++];
       o->n[0] = 0.0f; o->n[1] = 0.0f; o->n[2] = 1.0f;
@@ -172,19 +183,25 @@ static int np_ground(int32_t i, const uint8_t* type, const float* size, const fl
   return cnt;
 }
 
-int oracle_narrowphase(int32_t i, int32_t j, const uint8_t* type, const float* size,
+static int narrowphase(int32_t i, int32_t j, const uint8_t* type, const float* size, const float* ext,
                        const float* pos, const float* quat, oracle_point* pts) {
-  if (j == ORACLE_GROUND) return np_ground(i, type, size, pos, quat, pts);
+  if (j == ORACLE_GROUND) return np_ground(i, type, size, ext, pos, quat, pts);
   v3 pi = load3(pos, i), pj = load3(pos, j);
   float Ri[9], Rj[9];
   quat_mat(quat + 4 * i, Ri);
   quat_mat(quat + 4 * j, Rj);
+  v3 ei = body_ext(i, type, size, ext), ej = body_ext(j, type, size, ext);
   if (type[i] == 0 && type[j] == 0) return np_sphere_sphere(pi, size[i], pj, size[j], pts);
-  if (type[i] == 0 && type[j] == 1) return np_sphere_cube(pi, size[i], pj, Rj, size[j], 1, pts);
-  if (type[i] == 1 && type[j] == 0) return np_sphere_cube(pj, size[j], pi, Ri, size[i], 0, pts);
-  int c = np_vertices_in_box(pi, Ri, size[i], pj, Rj, size[j], 1, pts);
-  c += np_vertices_in_box(pj, Rj, size[j], pi, Ri, size[i], 0, pts + c);
+  if (type[i] == 0) return np_sphere_cube(pi, size[i], pj, Rj, ej, 1, pts);
+  if (type[j] == 0) return np_sphere_cube(pj, size[j], pi, Ri, ei, 0, pts);
+  int c = np_vertices_in_box(pi, Ri, ei, pj, Rj, ej, 1, pts);
+  c += np_vertices_in_box(pj, Rj, ej, pi, Ri, ei, 0, pts + c);
   return c;
+}
+
+int oracle_narrowphase(int32_t i, int32_t j, const uint8_t* type, const float* size,
+                       const float* pos, const float* quat, oracle_point* pts) {
+  return narrowphase(i, j, type, size, NULL, pos, quat, pts);
 }
 
 /* ---------------------------------------------------------------------------
@@ -206,6 +223,14 @@ int oracle_step_env(int32_t n, const uint8_t* type, const float* size, const flo
 int oracle_step_env_ext(int32_t n, const uint8_t* type, const float* size, const float* rbound,
                         const float* inv_m, const float* inv_I, float* pos, float* vel,
                         float* quat, float* omega, const oracle_phys_params* prm,
+                        int32_t* pairs, int32_t pair_cap, int32_t* npairs, const float* fext) {
+  return oracle_step_env_box(n, type, size, NULL, NULL, rbound, inv_m, inv_I, pos, vel, quat, omega, prm, pairs,
+                             pair_cap, npairs, fext);
+}
+
+int oracle_step_env_box(int32_t n, const uint8_t* type, const float* size, const float* ext,
+                        const float* inertia, const float* rbound, const float* inv_m, const float* inv_I,
+                        float* pos, float* vel, float* quat, float* omega, const oracle_phys_params* prm,
                         int32_t* pairs, int32_t pair_cap, int32_t* npairs, const float* fext) {
   const float h = prm->dt / (float)prm->substeps;
   const float hh = 0.5f * h;
@@ -233,7 +258,7 @@ int oracle_step_env_ext(int32_t n, const uint8_t* type, const float* size, const
           cand = dot(d, d) <= rs * rs;
         }
         if (!cand) continue;
-        int cnt = oracle_narrowphase(i, jj, type, size, pos, quat, pts);
+        int cnt = narrowphase(i, jj, type, size, ext, pos, quat, pts);
         if (cnt == 0) continue;
         if (pairs) {
           if (np >= pair_cap) { status = -1; }
@@ -301,7 +326,21 @@ int oracle_step_env_ext(int32_t n, const uint8_t* type, const float* size, const
       v3 a = add(scl(F, inv_m[b]), g);
       v = add(v, scl(a, h));
       p = add(p, scl(v, h));
-      w = add(w, scl(scl(acc[b].T, inv_I[b]), h));
+      if (type[b] == 2 && inertia) {
+        /* a box: Euler's equations in the body frame, with the gyroscopic
+         * term, R the orientation at the start of the substep:
+         * w_b = R^T w, dw_b = (R^T T - w_b x (I w_b)) / I, w = R (w_b + h dw_b) */
+        float R[9];
+        quat_mat(quat + 4 * b, R);
+        v3 I = load3(inertia, b);
+        v3 wb = mat_tvec(R, w), tb = mat_tvec(R, acc[b].T);
+        v3 L = mk(I.x * wb.x, I.y * wb.y, I.z * wb.z);
+        v3 gy = cross(wb, L);
+        v3 dwb = mk((tb.x - gy.x) / I.x, (tb.y - gy.y) / I.y, (tb.z - gy.z) / I.z);
+        w = mat_vec(R, add(wb, scl(dwb, h)));
+      } else {
+        w = add(w, scl(scl(acc[b].T, inv_I[b]), h));
+      }
       float* q = quat + 4 * b;
       float qw = q[0], qx = q[1], qy = q[2], qz = q[3];
       /* dq = (0, w) (x) q, Hamilton product */
@@ -526,6 +565,13 @@ int oracle_render_image(int32_t n, const uint8_t* type, const float* size,
                         const uint8_t* albedo, const float* pos, const float* quat,
                         const float* vp, int32_t W, int32_t H, const oracle_render_params* rp,
                         uint8_t* rgb, uint32_t* depth, int32_t* winner, int32_t* cover) {
+  return oracle_render_image_box(n, type, size, NULL, albedo, pos, quat, vp, W, H, rp, rgb, depth, winner, cover);
+}
+
+int oracle_render_image_box(int32_t n, const uint8_t* type, const float* size, const float* ext,
+                            const uint8_t* albedo, const float* pos, const float* quat,
+                            const float* vp, int32_t W, int32_t H, const oracle_render_params* rp,
+                            uint8_t* rgb, uint32_t* depth, int32_t* winner, int32_t* cover) {
   size_t npix = (size_t)W * (size_t)H;
   uint64_t* keys = (uint64_t*)malloc(sizeof(uint64_t) * (npix ? npix : 1));
   if (!keys) return -1;
@@ -543,7 +589,7 @@ int oracle_render_image(int32_t n, const uint8_t* type, const float* size,
     float R[9];
     quat_mat(quat + 4 * b, R);
     v3 p = load3(pos, b);
-    float s = size[b];
+    v3 e = body_ext(b, type, size, ext); /* the unit template scaled per axis */
     const float* tv = type[b] ? rp->cube_v : rp->sphere_v;
     const int32_t* tf = type[b] ? rp->cube_f : rp->sphere_f;
     int32_t nf = type[b] ? rp->cube_nf : rp->sphere_nf;
@@ -551,7 +597,7 @@ int oracle_render_image(int32_t n, const uint8_t* type, const float* size,
       float wv[3][3];
       for (int k = 0; k < 3; ++k) {
         v3 t = load3(tv, tf[3 * f + k]);
-        v3 w = add(p, mat_vec(R, scl(t, s)));
+        v3 w = add(p, mat_vec(R, mk(t.x * e.x, t.y * e.y, t.z * e.z)));
         wv[k][0] = w.x; wv[k][1] = w.y; wv[k][2] = w.z;
       }
       raster_tri(wv[0], wv[1], wv[2], prim, vp, W, H, rp, keys, cover);

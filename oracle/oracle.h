@@ -91,6 +91,16 @@ int oracle_step_env_ext(int32_t n, const uint8_t* type, const float* size, const
                         float* quat, float* omega, const oracle_phys_params* prm,
                         int32_t* pairs, int32_t pair_cap, int32_t* npairs, const float* fext);
 
+/* As oracle_step_env_ext, with boxes: body type 2 is a box of half-extents
+ * ext[3b .. 3b+2] (body frame) and principal moments of inertia
+ * inertia[3b .. 3b+2]; its angular velocity follows Euler's equations in
+ * the body frame, gyroscopic term included (the isotropic sphere and cube
+ * keep w += h T inv_I).  ext and inertia may be NULL when there is no box. */
+int oracle_step_env_box(int32_t n, const uint8_t* type, const float* size, const float* ext,
+                        const float* inertia, const float* rbound, const float* inv_m, const float* inv_I,
+                        float* pos, float* vel, float* quat, float* omega, const oracle_phys_params* prm,
+                        int32_t* pairs, int32_t pair_cap, int32_t* npairs, const float* fext);
+
 /* Narrowphase of one body pair (i < j) or of body i with the ground
  * (j = ORACLE_GROUND), evaluated on the given state.  Returns the number of
  * contact points written to pts (at most ORACLE_MAX_POINTS). */
@@ -106,6 +116,13 @@ int oracle_render_image(int32_t n, const uint8_t* type, const float* size,
                         const uint8_t* albedo, const float* pos, const float* quat,
                         const float* vp, int32_t W, int32_t H, const oracle_render_params* rp,
                         uint8_t* rgb, uint32_t* depth, int32_t* winner, int32_t* cover);
+
+/* As oracle_render_image, with boxes (type 2: the cube template scaled by
+ * the half-extents ext[3b .. 3b+2]); ext may be NULL when there is no box. */
+int oracle_render_image_box(int32_t n, const uint8_t* type, const float* size, const float* ext,
+                            const uint8_t* albedo, const float* pos, const float* quat,
+                            const float* vp, int32_t W, int32_t H, const oracle_render_params* rp,
+                            uint8_t* rgb, uint32_t* depth, int32_t* winner, int32_t* cover);
 
 /* Screen-space setup of one triangle given world-space vertices: writes the
  * snapped 24.8 vertices (in edge order) and depths; returns 1 if the triangle

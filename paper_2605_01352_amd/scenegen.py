@@ -263,6 +263,9 @@ class Scene:
     mu: float = 0.0        # regularized Coulomb friction coefficient (0: none)
     v_eps: float = 0.05    # [m/s] slip speed below which friction is linear
     near_clip: bool = False  # cut triangles crossing the near plane instead of culling them
+    # boxes (type 2): half-extents and principal moments of inertia, body frame
+    ext: Optional[np.ndarray] = None      # f32 [B,3] (rows of other bodies unused)
+    inertia: Optional[np.ndarray] = None  # f32 [B,3]
     name: str = ""
     seed: int = 0
     env_gid0: int = 0
@@ -301,7 +304,8 @@ class Scene:
             albedo=self.albedo[bsel], pos=self.pos[bsel].copy(), vel=self.vel[bsel].copy(),
             quat=self.quat[bsel].copy(), omega=self.omega[bsel].copy(),
             cam_off=nc.astype(np.int32), cam_vp=self.cam_vp[csel], cam_w=self.cam_w[csel],
-            cam_h=self.cam_h[csel])
+            cam_h=self.cam_h[csel], ext=None if self.ext is None else self.ext[bsel],
+            inertia=None if self.inertia is None else self.inertia[bsel])
 
     @staticmethod
     def concat(scenes: Sequence["Scene"]) -> "Scene":
@@ -309,11 +313,15 @@ class Scene:
         nb = np.concatenate([[0]] + [s.counts() for s in scenes]).cumsum().astype(np.int32)
         nc = np.concatenate([[0]] + [np.diff(s.cam_off) for s in scenes]).cumsum().astype(np.int32)
         cat = lambda f: np.concatenate([getattr(s, f) for s in scenes])
+        boxes = any(s.ext is not None for s in scenes)
+        cat3 = lambda f: np.concatenate([getattr(s, f) if getattr(s, f) is not None
+                                         else np.zeros((s.n_bodies, 3), np.float32) for s in scenes])
         return dataclasses.replace(
             s0, body_off=nb, btype=cat("btype"), size=cat("size"), rbound=cat("rbound"),
             inv_m=cat("inv_m"), inv_I=cat("inv_I"), albedo=cat("albedo"), pos=cat("pos"),
             vel=cat("vel"), quat=cat("quat"), omega=cat("omega"), cam_off=nc,
-            cam_vp=cat("cam_vp"), cam_w=cat("cam_w"), cam_h=cat("cam_h"), name="concat")
+            cam_vp=cat("cam_vp"), cam_w=cat("cam_w"), cam_h=cat("cam_h"), name="concat",
+            ext=cat3("ext") if boxes else None, inertia=cat3("inertia") if boxes else None)
 
 
 # --------------------------------------------------------------------------

@@ -197,10 +197,12 @@ def policy_bench(torch, vuda, sg, scene, w, st0, steps, warmup, hidden, log):
 
 def features_bench(torch, vuda, sg, scene, steps, log):
     """The optional features on the same workload, each in a world of its
-    own: friction (mu = 0.5) in the physics kernel, near-plane clipping in the
-    raster setup (cameras of this workload never cross the near plane, so
-    only the cost of the cutting code shows), and the metric-depth fetch of
-    every frame into device memory."""
+    own: friction (mu = 0.5) in the physics kernel, half of the cubes made
+    boxes (anisotropic extents and inertia) in the physics and setup
+    kernels, near-plane clipping in the raster setup (cameras of this
+    workload never cross the near plane, so only the cost of the cutting
+    code shows), and the metric-depth fetch of every frame into device
+    memory."""
     import dataclasses
     out = {}
 
@@ -215,9 +217,12 @@ def features_bench(torch, vuda, sg, scene, steps, log):
         w.set_tuning(vuda.TUNE_TIMING, 0)
         return t["total_ms"] * 1e3 / max(1, t["launches"])
 
+    boxes = sg.with_boxes(scene)
     for name, sc, kernel in (("physics_mu0", scene, vuda.KERNEL_PHYSICS),
                              ("physics_mu0.5", dataclasses.replace(scene, mu=0.5), vuda.KERNEL_PHYSICS),
+                             ("physics_boxes", boxes, vuda.KERNEL_PHYSICS),
                              ("setup", scene, vuda.KERNEL_RASTER_SETUP),
+                             ("setup_boxes", boxes, vuda.KERNEL_RASTER_SETUP),
                              ("setup_near_clip", dataclasses.replace(scene, near_clip=True),
                               vuda.KERNEL_RASTER_SETUP)):
         with vuda.World(sc) as w:
@@ -298,7 +303,7 @@ def main():
     ap.add_argument("--policy-loop", type=int, default=0,
                     help="only time the policy loop, this many steps per schedule (for rocprofv3)")
     args = ap.parse_args()
-    hiddens = [int(h) for h in args.policy_hidden.split(",") if int(h) > 0]
+    hiddens = [int(h) for h in args.policy_hidden.split(",") if h.strip() and int(h) > 0]
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the envs are independent and a multi-GPU run would "
               f"shard them with no exchange; --gpus {args.gpus} is not supported", file=sys.stderr)

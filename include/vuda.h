@@ -127,9 +127,14 @@ typedef struct {
 /*
  * Per-env content.  Bodies of env e are body_off[e] .. body_off[e+1]-1
  * (at most 128 per env); cameras cam_off[e] .. cam_off[e+1]-1.
- * Body arrays: type (0 sphere, 1 cube), size (radius or half-extent),
- * rbound (bounding-sphere radius), inv_m, inv_I (isotropic), albedo
- * (palette index 0..7), pos/vel/omega [B][3], quat [B][4] (w,x,y,z).
+ * Body arrays: type (0 sphere, 1 cube, 2 box), size (radius, half-extent,
+ * or a box's largest half-extent), rbound (bounding-sphere radius), inv_m,
+ * inv_I (isotropic; unused for a box), albedo (palette index 0..7),
+ * pos/vel/omega [B][3], quat [B][4] (w,x,y,z).  Boxes also need ext [B][3]
+ * (half-extents along the body axes) and inertia [B][3] (principal moments
+ * about them); their rows for other bodies are not read, and both may be
+ * NULL when there is no box.  A box's spin follows Euler's equations in the
+ * body frame, gyroscopic term included.
  * Cameras: vp [C][16] row-major view-projection (clip = vp * [x y z 1]^T,
  * depth in [0,1]), w/h in pixels (1..4096).
  */
@@ -140,6 +145,7 @@ typedef struct {
   const float* inv_m; const float* inv_I; const uint8_t* albedo;
   const float* pos; const float* vel; const float* quat; const float* omega;
   const int32_t* cam_off; const float* cam_vp; const int32_t* cam_w; const int32_t* cam_h;
+  const float* ext; const float* inertia;
 } vuda_env_batch;
 
 /*

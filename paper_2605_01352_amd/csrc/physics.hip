@@ -84,6 +84,8 @@ struct PhysLDS {
   float w[3][N];
   float R[9][N];
   float size[N];
+  float4 ext[N];   // half-extents along the body axes, 0 ((a, a, a) for a cube)
+  float inert[3][N];  // principal moments of a box
   float rb[N];
   int32_t type[N];
   uint64_t bucket[2 * N][NW];
@@ -248,15 +250,21 @@ __device__ __forceinline__ void add_point(PairAcc& acc, const Point& pt, bool a_
   acc.npts += 1;
 }
 
-// Corner k of a cube (sign + on axis t iff bit t of k is set): p + R w with
-// w = (+-a, +-a, +-a).
-__device__ __forceinline__ f3 corner_vertex(f3 p, const M3& R, float a, int k) {
-  return add(p, rot(R, mk((k & 1) ? a : -a, (k & 2) ? a : -a, (k & 4) ? a : -a)));
+template <int NW>
+__device__ __forceinline__ f3 ldsE(const PhysLDS<NW>& s, int b) {
+  const float4 e = s.ext[b];
+  return mk(e.x, e.y, e.z);
 }
 
-// argmin over axes of (a - |u_axis|), lowest axis on ties
-__device__ __forceinline__ int min_axis(f3 u, float a, float* depth) {
-  const float d0 = a - fabsf(u.x), d1 = a - fabsf(u.y), d2 = a - fabsf(u.z);
+// Corner k of a box of half-extents e (sign + on axis t iff bit t of k is
+// set): p + R w with w = (+-e.x, +-e.y, +-e.z).
+__device__ __forceinline__ f3 corner_vertex(f3 p, const M3& R, f3 e, int k) {
+  return add(p, rot(R, mk((k & 1) ? e.x : -e.x, (k & 2) ? e.y : -e.y, (k & 4) ? e.z : -e.z)));
+}
+
+// argmin over axes of (e_axis - |u_axis|), lowest axis on ties
+__device__ __forceinline__ int min_axis(f3 u, f3 e, float* depth) {
+  const float d0 = e.x - fabsf(u.x), d1 = e.y - fabsf(u.y), d2 = e.z - fabsf(u.z);
   int m = 0;
   float dm = d0;
   if (d1 < dm) { m = 1; dm = d1; }
@@ -271,11 +279,11 @@ __device__ __forceinline__ f3 axis_unit(int m, float sgn) {
 
 __device__ __forceinline__ float pick(f3 u, int m) { return m == 0 ? u.x : (m == 1 ? u.y : u.z); }
 
-// Sphere (centre c, radius r) against cube (p, R, a); normal from the cube to
-// the sphere.  Returns true on contact.
-__device__ __forceinline__ bool sphere_cube(f3 c, float r, f3 p, const M3& R, float a, Point* pt) {
+// Sphere (centre c, radius r) against box (p, R, half-extents a); normal
+// from the box to the sphere.  Returns true on contact.
+__device__ __forceinline__ bool sphere_cube(f3 c, float r, f3 p, const M3& R, f3 a, Point* pt) {
   const f3 u = rotT(R, sub(c, p));
-  const f3 e = mk(fminf(fmaxf(u.x, -a), a), fminf(fmaxf(u.y, -a), a), fminf(fmaxf(u.z, -a), a));
+  const f3 e = mk(fminf(fmaxf(u.x, -a.x), a.x), fminf(fmaxf(u.y, -a.y), a.y), fminf(fmaxf(u.z, -a.z), a.z));
   const f3 rv = sub(u, e);
   const float L2 = dot(rv, rv);
   if (!(L2 < r * r)) return false;
@@ -325,21 +333,21 @@ __device__ __noinline__ PairAcc pair_forces(const PhysLDS<NW>& s, int i, int j,
     }
   } else if (ti == 0) {
     const M3 Rj = ldsR(s, j);
-    if (sphere_cube(pi, si, pj, Rj, sj, &pt)) add_point<FR>(acc, pt, true, pi, vi, wi, pj, vj, wj, false, pc);
+    if (sphere_cube(pi, si, pj, Rj, ldsE(s, j), &pt)) add_point<FR>(acc, pt, true, pi, vi, wi, pj, vj, wj, false, pc);
   } else if (tj == 0) {
     const M3 Ri = ldsR(s, i);
-    if (sphere_cube(pj, sj, pi, Ri, si, &pt)) add_point<FR>(acc, pt, false, pi, vi, wi, pj, vj, wj, false, pc);
+    if (sphere_cube(pj, sj, pi, Ri, ldsE(s, i), &pt)) add_point<FR>(acc, pt, false, pi, vi, wi, pj, vj, wj, false, pc);
   }
   return acc;
 }
 
-// Corner k of cube A strictly inside cube B: the contact point, pushed out
-// of B along the normal of B's nearest face.
-__device__ __forceinline__ bool corner_in_box(f3 pa, const M3& Ra, float aa, int k, f3 pb, const M3& Rb,
-                                              float ab, Point* pt) {
+// Corner k of box A strictly inside box B: the contact point, pushed out of
+// B along the normal of B's nearest face.
+__device__ __forceinline__ bool corner_in_box(f3 pa, const M3& Ra, f3 aa, int k, f3 pb, const M3& Rb,
+                                              f3 ab, Point* pt) {
   const f3 vtx = corner_vertex(pa, Ra, aa, k);
   const f3 u = rotT(Rb, sub(vtx, pb));
-  if (!(fabsf(u.x) < ab && fabsf(u.y) < ab && fabsf(u.z) < ab)) return false;
+  if (!(fabsf(u.x) < ab.x && fabsf(u.y) < ab.y && fabsf(u.z) < ab.z)) return false;
   float dm;
   const int m = min_axis(u, ab, &dm);
   pt->n = rot(Rb, axis_unit(m, pick(u, m) >= 0.0f ? 1.0f : -1.0f));
@@ -415,6 +423,11 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
     rbv = W.rbound[gb];
     ty = W.type[gb];
     s.size[tid] = a;
+    const float* bx = W.box + 6 * (int64_t)gb;
+    s.ext[tid] = make_float4(bx[0], bx[1], bx[2], 0.0f);
+    s.inert[0][tid] = bx[3];
+    s.inert[1][tid] = bx[4];
+    s.inert[2][tid] = bx[5];
     s.rb[tid] = rbv;
     s.type[tid] = ty;
   }
@@ -694,7 +707,7 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
         const int A = r < 8 ? i : j, B = r < 8 ? j : i;
         const f3 pA = ldsP(s, A), pB = ldsP(s, B);
         const M3 RA = ldsR(s, A), RB = ldsR(s, B);
-        const float aA = s.size[A], aB = s.size[B];
+        const f3 aA = ldsE(s, A), aB = ldsE(s, B);
         const f3 vi = ldsV(s, i), wi = ldsW(s, i), vj = ldsV(s, j), wj = ldsW(s, j);
         Point pt;
         hit = corner_in_box(pA, RA, aA, r & 7, pB, RB, aB, &pt);
@@ -738,7 +751,7 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
       if (t < 8 * ngc) {
         b = s.gcl[t >> 3];
         const f3 pb = ldsP(s, b), vb = ldsV(s, b), wb = ldsW(s, b);
-        const f3 vtx = corner_vertex(pb, ldsR(s, b), s.size[b], r);
+        const f3 vtx = corner_vertex(pb, ldsR(s, b), ldsE(s, b), r);
         if (vtx.z < 0.0f) {
           hit = true;
           const f3 z3 = mk(0.0f, 0.0f, 0.0f);
@@ -851,7 +864,19 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
       const f3 acc = add(mul(F, inv_m), gvec);
       v = add(v, mul(acc, pc.h));
       p = add(p, mul(v, pc.h));
-      w = add(w, mul(mul(Tq, inv_I), pc.h));
+      if (ty == 2) {
+        // a box: Euler's equations in the body frame with the gyroscopic
+        // term, R of the substep start: w_b = R^T w,
+        // dw_b = (R^T T - w_b x (I w_b)) / I, w = R (w_b + h dw_b)
+        const M3 Rs = ldsR(s, tid);
+        const f3 I = mk(s.inert[0][tid], s.inert[1][tid], s.inert[2][tid]);
+        const f3 wb = rotT(Rs, w), tb = rotT(Rs, Tq);
+        const f3 gy = cross(wb, mk(I.x * wb.x, I.y * wb.y, I.z * wb.z));
+        const f3 dwb = mk((tb.x - gy.x) / I.x, (tb.y - gy.y) / I.y, (tb.z - gy.z) / I.z);
+        w = rot(Rs, add(wb, mul(dwb, pc.h)));
+      } else {
+        w = add(w, mul(mul(Tq, inv_I), pc.h));
+      }
       const float dw = (-w.x * qx - w.y * qy) - w.z * qz;
       const float dx = (w.x * qw + w.y * qz) - w.z * qy;
       const float dy = (w.y * qw + w.z * qx) - w.x * qz;

@@ -69,7 +69,7 @@ __host__ __device__ inline SetupLayout setup_layout(int max_bodies, int max_vert
   L.tw = max_tiles < kMaxLdsTiles ? max_tiles : kMaxLdsTiles;
   int o = 0;
   L.tpl = o;    o += kTplBytes;
-  L.body = o;   o += align16(4 * 17 * L.nmax);
+  L.body = o;   o += align16(4 * 20 * L.nmax);
   L.verts = o;  o += align16(12 * L.vmax);
   L.vis = o;    o += align16(2 * max_tris);
   L.cvis = o;   o += near_clip ? align16(40 * kClipRecs) : 0;  // near-plane pieces: X[3] Y[3] z[3], primitive
@@ -85,26 +85,27 @@ __host__ __device__ inline SetupLayout setup_layout(int max_bodies, int max_vert
 struct BodyLDS {
   float* p;       // [3][nmax]
   float* R;       // [9][nmax]
-  float* s;       // [nmax]
+  float4* e;      // [nmax] half-extents along the body axes (x, y, z, 0); a radius thrice for a sphere
   int32_t* type;  // [nmax]
   int32_t* vb;    // [nmax] vertex base (env-local)
   int32_t* pb;    // [nmax] primitive base
   int32_t* alb;   // [nmax]
 };
 
-__device__ __forceinline__ void quat_rot(float w, float x, float y, float z, float* m) {
+// Rotation matrix of a unit quaternion, row-major, element k at m[k * stride]
+__device__ __forceinline__ void quat_rot(float w, float x, float y, float z, float* m, int stride) {
   const float xx = x * x, yy = y * y, zz = z * z;
   const float xy = x * y, xz = x * z, yz = y * z;
   const float wx = w * x, wy = w * y, wz = w * z;
   m[0] = 1.0f - 2.0f * (yy + zz);
-  m[1] = 2.0f * (xy - wz);
-  m[2] = 2.0f * (xz + wy);
-  m[3] = 2.0f * (xy + wz);
-  m[4] = 1.0f - 2.0f * (xx + zz);
-  m[5] = 2.0f * (yz - wx);
-  m[6] = 2.0f * (xz - wy);
-  m[7] = 2.0f * (yz + wx);
-  m[8] = 1.0f - 2.0f * (xx + yy);
+  m[stride] = 2.0f * (xy - wz);
+  m[2 * stride] = 2.0f * (xz + wy);
+  m[3 * stride] = 2.0f * (xy + wz);
+  m[4 * stride] = 1.0f - 2.0f * (xx + zz);
+  m[5 * stride] = 2.0f * (yz - wx);
+  m[6 * stride] = 2.0f * (xz - wy);
+  m[7 * stride] = 2.0f * (yz + wx);
+  m[8 * stride] = 1.0f - 2.0f * (xx + yy);
 }
 
 constexpr int32_t kInvalid = (int32_t)0x80000000;  // in front, outside the guard band
@@ -429,8 +430,8 @@ __device__ __forceinline__ float4 vertex_clip(const Templates* T, const BodyLDS&
   } else {
     const int lv = vi - B.vb[b];
     const float* tv = B.type[b] ? T->cube_v[lv] : T->sphere_v[lv];
-    const float s = B.s[b];
-    const float sx = s * tv[0], sy = s * tv[1], sz = s * tv[2];
+    const float4 e = B.e[b];
+    const float sx = e.x * tv[0], sy = e.y * tv[1], sz = e.z * tv[2];
     const float* R = B.R + b;
     wx = B.p[b] + ((R[0] * sx + R[S] * sy) + R[2 * S] * sz);
     wy = B.p[S + b] + ((R[3 * S] * sx + R[4 * S] * sy) + R[5 * S] * sz);
@@ -475,11 +476,11 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
   float* bf = (float*)(lds + Lo.body);
   B.p = bf;
   B.R = bf + 3 * Lo.nmax;
-  B.s = bf + 12 * Lo.nmax;
-  B.type = (int32_t*)(bf + 13 * Lo.nmax);
-  B.vb = (int32_t*)(bf + 14 * Lo.nmax);
-  B.pb = (int32_t*)(bf + 15 * Lo.nmax);
-  B.alb = (int32_t*)(bf + 16 * Lo.nmax);
+  B.e = (float4*)(bf + 12 * Lo.nmax);
+  B.type = (int32_t*)(bf + 16 * Lo.nmax);
+  B.vb = (int32_t*)(bf + 17 * Lo.nmax);
+  B.pb = (int32_t*)(bf + 18 * Lo.nmax);
+  B.alb = (int32_t*)(bf + 19 * Lo.nmax);
   int32_t* VX = (int32_t*)(lds + Lo.verts);
   int32_t* VY = VX + Lo.vmax;
   float* VZ = (float*)(VY + Lo.vmax);
@@ -507,11 +508,9 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
     B.p[b] = st[PX * cap + g];
     B.p[Lo.nmax + b] = st[PY * cap + g];
     B.p[2 * Lo.nmax + b] = st[PZ * cap + g];
-    float m[9];
-    quat_rot(st[QW * cap + g], st[QX * cap + g], st[QY * cap + g], st[QZ * cap + g], m);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) B.R[k * Lo.nmax + b] = m[k];
-    B.s[b] = W.size[g];
+    quat_rot(st[QW * cap + g], st[QX * cap + g], st[QY * cap + g], st[QZ * cap + g], B.R + b, Lo.nmax);
+    const float* bx = W.box + 6 * (int64_t)g;
+    B.e[b] = make_float4(bx[0], bx[1], bx[2], 0.0f);
     B.type[b] = W.type[g];
     B.vb[b] = W.vert_base[g];
     B.pb[b] = W.prim_base[g];

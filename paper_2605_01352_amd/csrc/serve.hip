@@ -29,6 +29,7 @@ struct Batch {
   std::vector<int32_t> body_off, cam_off, cam_w, cam_h;
   std::vector<uint8_t> type, albedo;
   std::vector<float> size, rbound, inv_m, inv_I, pos, vel, quat, omega, cam_vp;
+  std::vector<float> ext, inertia;  // empty when the batch has no box
 
   void copy_from(const vuda_env_batch& b) {
     n_envs = b.n_envs;
@@ -49,6 +50,12 @@ struct Batch {
     cam_vp.assign(b.cam_vp, b.cam_vp + 16 * (size_t)nc);
     cam_w.assign(b.cam_w, b.cam_w + nc);
     cam_h.assign(b.cam_h, b.cam_h + nc);
+    ext.clear();
+    inertia.clear();
+    if (b.ext && b.inertia) {
+      ext.assign(b.ext, b.ext + 3 * nb);
+      inertia.assign(b.inertia, b.inertia + 3 * nb);
+    }
   }
   vuda_env_batch view() const {
     vuda_env_batch b{};
@@ -58,6 +65,8 @@ struct Batch {
     b.inv_m = inv_m.data(); b.inv_I = inv_I.data(); b.albedo = albedo.data();
     b.pos = pos.data(); b.vel = vel.data(); b.quat = quat.data(); b.omega = omega.data();
     b.cam_off = cam_off.data(); b.cam_vp = cam_vp.data(); b.cam_w = cam_w.data(); b.cam_h = cam_h.data();
+    b.ext = ext.empty() ? nullptr : ext.data();
+    b.inertia = inertia.empty() ? nullptr : inertia.data();
     return b;
   }
   int64_t bodies() const { return body_off.empty() ? 0 : body_off.back(); }
@@ -120,7 +129,7 @@ struct vuda_server {
       for (int32_t i = b.body_off[e]; i < b.body_off[e + 1]; ++i)
         maps += b.type[i] ? w->tpl.cube_nf + w->tpl.cube_nv : w->tpl.sphere_nf + w->tpl.sphere_nv;
     }
-    return (uint64_t)nb * (2 * 4 * kStateComps + 26) + (uint64_t)maps + (uint64_t)b.pixels() * 7 +
+    return (uint64_t)nb * (2 * 4 * kStateComps + 50) + (uint64_t)maps + (uint64_t)b.pixels() * 7 +
            (uint64_t)b.n_envs * sizeof(EnvDev) + b.cam_w.size() * sizeof(CamDev) +
            256 * (uint64_t)w->rs_units(b.view());
   }

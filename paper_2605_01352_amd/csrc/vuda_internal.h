@@ -122,6 +122,7 @@ struct WorldDev {
   const float* rbound;
   const float* inv_m;
   const float* inv_I;
+  const float* box;          // per body [6]: half-extents xyz, principal moments xyz (boxes)
   const int32_t* prim_base;  // env-local primitive id of the body's first face
   const int32_t* vert_base;  // env-local vertex index of the body's first vertex
   const uint8_t* prim_body;  // per env: body of each primitive (kGroundBody: ground)

@@ -123,7 +123,7 @@ struct vuda_world {
   vuda_allocator allocator{};
   bool has_allocator = false;
   struct {
-    size_t envs, cams, type, albedo, size, rbound, inv_m, inv_I, prim_base, vert_base, prim_body, vert_body, state0,
+    size_t envs, cams, type, albedo, size, rbound, inv_m, inv_I, box, prim_base, vert_base, prim_body, vert_body, state0,
         state1, rgb, depth, flags, tpl, queues, winners, coverage, contacts, rs;
   } off_{};
   vuda::WorldDev dev{};

@@ -127,7 +127,14 @@ static int validate_batch(const vuda_env_batch& b, const vuda_render_desc& r, in
     return fail(VUDA_EINVAL, "body arrays missing");
   if (nc > 0 && (!b.cam_vp || !b.cam_w || !b.cam_h)) return fail(VUDA_EINVAL, "camera arrays missing");
   for (int64_t i = 0; i < nb; ++i) {
-    if (b.type[i] > 1) return fail(VUDA_EINVAL, "body %lld: type %d", (long long)i, (int)b.type[i]);
+    if (b.type[i] > 2) return fail(VUDA_EINVAL, "body %lld: type %d", (long long)i, (int)b.type[i]);
+    if (b.type[i] == 2) {
+      if (!b.ext || !b.inertia) return fail(VUDA_EINVAL, "body %lld: a box needs ext and inertia", (long long)i);
+      for (int k = 0; k < 3; ++k)
+        if (!(b.ext[3 * i + k] > 0.0f) || !std::isfinite(b.ext[3 * i + k]) || !(b.inertia[3 * i + k] > 0.0f) ||
+            !std::isfinite(b.inertia[3 * i + k]))
+          return fail(VUDA_EINVAL, "body %lld: box extents/inertia", (long long)i);
+    }
     if (b.albedo[i] > 7) return fail(VUDA_EINVAL, "body %lld: albedo %d", (long long)i, (int)b.albedo[i]);
     if (!(b.size[i] > 0.0f) || !(b.rbound[i] >= b.size[i]))
       return fail(VUDA_EINVAL, "body %lld: size/rbound", (long long)i);
@@ -227,6 +234,7 @@ int vuda_world::alloc_arena(const vuda_allocator* a) {
   off_.rbound = take(4 * B);
   off_.inv_m = take(4 * B);
   off_.inv_I = take(4 * B);
+  off_.box = take(4 * 6 * B);
   off_.prim_base = take(4 * B);
   off_.vert_base = take(4 * B);
   off_.prim_body = take(std::max<int64_t>(cap_prims, 1));
@@ -271,6 +279,7 @@ int vuda_world::alloc_arena(const vuda_allocator* a) {
   dev.rbound = (float*)(arena + off_.rbound);
   dev.inv_m = (float*)(arena + off_.inv_m);
   dev.inv_I = (float*)(arena + off_.inv_I);
+  dev.box = (float*)(arena + off_.box);
   dev.prim_base = (int32_t*)(arena + off_.prim_base);
   dev.vert_base = (int32_t*)(arena + off_.vert_base);
   dev.prim_body = arena + off_.prim_body;
@@ -405,6 +414,15 @@ int vuda_world::upload(const vuda_env_batch& b, int32_t e0, int64_t b0, int32_t 
   HIPCHK(up((void*)(dev.rbound + b0), b.rbound, 4 * nb));
   HIPCHK(up((void*)(dev.inv_m + b0), b.inv_m, 4 * nb));
   HIPCHK(up((void*)(dev.inv_I + b0), b.inv_I, 4 * nb));
+  // per body: half-extents and principal moments; (a, a, a) and unused
+  // moments for a sphere or a cube of size a
+  std::vector<float> box6((size_t)(6 * nb), 0.0f);
+  for (int64_t i = 0; i < nb; ++i)
+    for (int k = 0; k < 3; ++k) {
+      box6[(size_t)(6 * i + k)] = b.type[i] == 2 ? b.ext[3 * i + k] : b.size[i];
+      box6[(size_t)(6 * i + 3 + k)] = b.type[i] == 2 ? b.inertia[3 * i + k] : 0.0f;
+    }
+  HIPCHK(up((void*)(dev.box + 6 * b0), box6.data(), 4 * box6.size()));
   HIPCHK(up((void*)(dev.prim_base + b0), pbase.data(), 4 * nb));
   HIPCHK(up((void*)(dev.vert_base + b0), vbase.data(), 4 * nb));
   HIPCHK(up((void*)(dev.prim_body + m0), pmap.data(), pmap.size()));

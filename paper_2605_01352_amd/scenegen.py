@@ -29,9 +29,10 @@ _M2 = np.uint64(0x94D049BB133111EB)
 
 SPHERE = 0
 CUBE = 1
+BOX = 2
 
 # random streams per env
-ST_SHAPE, ST_POS, ST_ROT, ST_CAM, ST_COUNT, ST_RES = 0, 1, 2, 3, 4, 5
+ST_SHAPE, ST_POS, ST_ROT, ST_CAM, ST_COUNT, ST_RES, ST_BOX = 0, 1, 2, 3, 4, 5, 6
 
 
 def mix64(z: np.ndarray) -> np.ndarray:
@@ -506,6 +507,33 @@ def config_scene(cfg: int, n_envs: Optional[int] = None, env_gid0: int = 0) -> S
         res = np.array([64, 128, 256])[(draw_unit(kr, np.zeros(E, np.uint64)) * 3).astype(np.int64)]
         return make_scene(seed, counts, res, mixed=True, env_gid0=env_gid0, name="c4")
     raise ValueError(f"no scene for config {cfg}")
+
+
+def with_boxes(scene: Scene, every: int = 2, seed: int = 2029) -> Scene:
+    """The scene with every `every`-th cube (in body order) made a box.
+
+    A cube of half-extent a becomes a box of half-extents (a, a s1, a s2),
+    s1, s2 uniform in [0.4, 1), in its body axes, with the principal moments
+    of a solid box of the cube's mass; its bounding radius shrinks to the
+    box's half-diagonal, so the placement stays overlap-free.
+    """
+    B = scene.n_bodies
+    cubes = np.flatnonzero(scene.btype == CUBE)[::every]
+    key = stream_key(seed, np.arange(B, dtype=np.uint64), ST_BOX)
+    s1 = 0.4 + 0.6 * draw_unit(key, np.zeros(B, np.uint64))
+    s2 = 0.4 + 0.6 * draw_unit(key, np.ones(B, np.uint64))
+    a = scene.size.astype(np.float64)
+    btype = scene.btype.copy()
+    btype[cubes] = BOX
+    ext = np.stack([a, a * s1, a * s2], 1)
+    ext[btype != BOX] = a[btype != BOX, None]
+    m = 1.0 / scene.inv_m.astype(np.float64)
+    e2 = ext ** 2
+    inertia = m[:, None] / 3.0 * np.stack([e2[:, 1] + e2[:, 2], e2[:, 0] + e2[:, 2], e2[:, 0] + e2[:, 1]], 1)
+    rb = scene.rbound.copy()
+    rb[cubes] = (np.linalg.norm(ext[cubes], axis=1) * (1.0 + 1e-6)).astype(np.float32)
+    return dataclasses.replace(scene, btype=btype, rbound=rb, ext=ext.astype(np.float32),
+                               inertia=inertia.astype(np.float32), name=scene.name + "+boxes")
 
 
 @dataclasses.dataclass

@@ -73,7 +73,8 @@ class EnvBatch(C.Structure):
         ("type", C.c_void_p), ("size", C.c_void_p), ("rbound", C.c_void_p),
         ("inv_m", C.c_void_p), ("inv_I", C.c_void_p), ("albedo", C.c_void_p),
         ("pos", C.c_void_p), ("vel", C.c_void_p), ("quat", C.c_void_p), ("omega", C.c_void_p),
-        ("cam_off", C.c_void_p), ("cam_vp", C.c_void_p), ("cam_w", C.c_void_p), ("cam_h", C.c_void_p)]
+        ("cam_off", C.c_void_p), ("cam_vp", C.c_void_p), ("cam_w", C.c_void_p), ("cam_h", C.c_void_p),
+        ("ext", C.c_void_p), ("inertia", C.c_void_p)]
 
 
 class WorldDesc(C.Structure):
@@ -195,7 +196,9 @@ def env_batch(keep: _Keep, scene, state: Optional[Dict[str, np.ndarray]] = None)
         _p(keep(st["vel"], np.float32)), _p(keep(st["quat"], np.float32)),
         _p(keep(st["omega"], np.float32)), _p(keep(scene.cam_off, np.int32)),
         _p(keep(scene.cam_vp, np.float32)), _p(keep(scene.cam_w, np.int32)),
-        _p(keep(scene.cam_h, np.int32)))
+        _p(keep(scene.cam_h, np.int32)),
+        None if scene.ext is None else _p(keep(scene.ext, np.float32)),
+        None if scene.inertia is None else _p(keep(scene.inertia, np.float32)))
 
 
 def state_to_aos(st: Dict[str, np.ndarray]) -> np.ndarray:

@@ -17,12 +17,13 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 GROUND = 0xFFFF
-MAX_POINTS = 16
+MAX_POINTS = 17
 
 
 class PhysParams(C.Structure):
     _fields_ = [("dt", C.c_float), ("substeps", C.c_int32), ("k", C.c_float),
-                ("c", C.c_float), ("g", C.c_float * 3), ("mu", C.c_float), ("v_eps", C.c_float)]
+                ("c", C.c_float), ("g", C.c_float * 3), ("mu", C.c_float), ("v_eps", C.c_float),
+                ("edge", C.c_int32)]
 
 
 class RenderParams(C.Structure):
@@ -59,6 +60,7 @@ def lib():
         _lib.oracle_render_image.restype = C.c_int
         _lib.oracle_run_batch.restype = C.c_int
         _lib.oracle_narrowphase.restype = C.c_int
+        _lib.oracle_narrowphase_box.restype = C.c_int
         _lib.oracle_setup_triangle.restype = C.c_int
         _lib.oracle_setup_clipped.restype = C.c_int
         _lib.oracle_covers.restype = C.c_int
@@ -72,7 +74,8 @@ def _p(a: np.ndarray):
 def phys_params(scene) -> PhysParams:
     g = (C.c_float * 3)(*[float(x) for x in scene.gravity])
     return PhysParams(float(np.float32(scene.dt)), int(scene.substeps), float(scene.k_contact),
-                      float(scene.c_damp), g, float(scene.mu), float(scene.v_eps))
+                      float(scene.c_damp), g, float(scene.mu), float(scene.v_eps),
+                      int(bool(getattr(scene, "edge_contacts", False))))
 
 
 class _Render:
@@ -158,7 +161,9 @@ def narrowphase(scene, state, i: int, j: int) -> List[Point]:
     quat = np.ascontiguousarray(state["quat"], np.float32)
     bt = np.ascontiguousarray(scene.btype)
     sz = np.ascontiguousarray(scene.size)
-    n = lib().oracle_narrowphase(i, j, _p(bt), _p(sz), _p(pos), _p(quat), pts)
+    ext = None if scene.ext is None else np.ascontiguousarray(scene.ext, np.float32)
+    n = lib().oracle_narrowphase_box(i, j, _p(bt), _p(sz), None if ext is None else _p(ext), _p(pos), _p(quat),
+                                     int(bool(scene.edge_contacts)), pts)
     return [pts[k] for k in range(n)]
 
 

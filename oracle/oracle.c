@@ -147,6 +147,86 @@ static int np_vertices_in_box(v3 pa, const float* Ra, v3 aa, v3 pb, const float*
   return cnt;
 }
 
+/* ---------------------------------------------------------------------------
+ * Edge-edge contact of two boxes by the separating-axis test (optional).
+ * Candidate axes, in this order: the three axes of box i, the three of box
+ * j, then the nine cross products (axis a of i) x (axis b of j), a major;
+ * a cross product shorter than sqrt(ORACLE_EDGE_PARALLEL) (near-parallel
+ * edges) is no axis.  Along a unit axis L the boxes overlap by
+ * o(L) = r_i(L) + r_j(L) - |(p_i - p_j) . L|, r(L) = sum_k e_k |u_k . L|.
+ * Some o <= 0: separated, no point.  Otherwise, if the least overlap over
+ * the cross-product axes is below ORACLE_EDGE_BIAS times the least over the
+ * face axes (faces are preferred: their contacts are the vertex points),
+ * one point is added where the two supporting edges pass closest: normal
+ * that axis pointing from j to i, depth that overlap.
+ * ------------------------------------------------------------------------- */
+
+/* Column k of a row-major rotation: the body's axis k in the world. */
+static v3 mat_col(const float* R, int k) { return mk(R[k], R[3 + k], R[6 + k]); }
+
+/* Half-width of a box (rotation R, half-extents e) along direction L. */
+static float box_radius(const float* R, v3 e, v3 L) {
+  v3 u = mat_tvec(R, L);
+  return (e.x * fabsf(u.x) + e.y * fabsf(u.y)) + e.z * fabsf(u.z);
+}
+
+static int np_edge_edge(v3 pi, const float* Ri, v3 ei, v3 pj, const float* Rj, v3 ej, oracle_point* out) {
+  v3 d = sub(pi, pj);
+  float fmin = INFINITY, emin = INFINITY;
+  int ek = -1;
+  v3 eL = mk(0.0f, 0.0f, 0.0f);
+  for (int k = 0; k < 15; ++k) {
+    v3 L;
+    if (k < 3) {
+      L = mat_col(Ri, k);
+    } else if (k < 6) {
+      L = mat_col(Rj, k - 3);
+    } else {
+      L = cross(mat_col(Ri, (k - 6) / 3), mat_col(Rj, (k - 6) % 3));
+      float l2 = dot(L, L);
+      if (!(l2 >= ORACLE_EDGE_PARALLEL)) continue;
+      float l = sqrtf(l2);
+      L = mk(L.x / l, L.y / l, L.z / l);
+    }
+    float o = (box_radius(Ri, ei, L) + box_radius(Rj, ej, L)) - fabsf(dot(d, L));
+    if (!(o > 0.0f)) return 0; /* a separating axis */
+    if (k < 6) {
+      if (o < fmin) fmin = o;
+    } else if (o < emin) {
+      emin = o;
+      ek = k;
+      eL = L;
+    }
+  }
+  if (ek < 0 || !(emin < ORACLE_EDGE_BIAS * fmin)) return 0;
+  int a = (ek - 6) / 3, b = (ek - 6) % 3;
+  v3 n = dot(eL, d) < 0.0f ? neg(eL) : eL; /* from j to i */
+  /* the edge of i along its axis a deepest toward j (along -n), and the
+   * edge of j along its axis b deepest toward i (along +n): their centres */
+  v3 ui = mat_tvec(Ri, n), uj = mat_tvec(Rj, n);
+  v3 wi = mk(a == 0 ? 0.0f : (ui.x > 0.0f ? -ei.x : ei.x), a == 1 ? 0.0f : (ui.y > 0.0f ? -ei.y : ei.y),
+             a == 2 ? 0.0f : (ui.z > 0.0f ? -ei.z : ei.z));
+  v3 wj = mk(b == 0 ? 0.0f : (uj.x > 0.0f ? ej.x : -ej.x), b == 1 ? 0.0f : (uj.y > 0.0f ? ej.y : -ej.y),
+             b == 2 ? 0.0f : (uj.z > 0.0f ? ej.z : -ej.z));
+  v3 ci = add(pi, mat_vec(Ri, wi)), cj = add(pj, mat_vec(Rj, wj));
+  /* closest points of the lines ci + s da and cj + t db (unit directions),
+   * each clamped to its edge */
+  v3 da = mat_col(Ri, a), db = mat_col(Rj, b);
+  v3 w = sub(ci, cj);
+  float bb = dot(da, db), dd = dot(da, w), ee = dot(db, w);
+  float den = 1.0f - bb * bb;
+  float sa = (bb * ee - dd) / den, tb = (ee - bb * dd) / den;
+  float ha = comp(ei, a), hb = comp(ej, b);
+  sa = fminf(fmaxf(sa, -ha), ha);
+  tb = fminf(fmaxf(tb, -hb), hb);
+  v3 xc = scl(add(add(ci, scl(da, sa)), add(cj, scl(db, tb))), 0.5f);
+  out->n[0] = n.x; out->n[1] = n.y; out->n[2] = n.z;
+  out->delta = emin;
+  out->xc[0] = xc.x; out->xc[1] = xc.y; out->xc[2] = xc.z;
+  out->a_is_first = 1;
+  return 1;
+}
+
 /* Half-extents of body i: its own for a box (type 2), (a, a, a) for a cube
  * or a sphere of size a. */
 static v3 body_ext(int32_t i, const uint8_t* type, const float* size, const float* ext) {
@@ -184,7 +264,7 @@ static int np_ground(int32_t i, const uint8_t* type, const float* size, const fl
 }
 
 static int narrowphase(int32_t i, int32_t j, const uint8_t* type, const float* size, const float* ext,
-                       const float* pos, const float* quat, oracle_point* pts) {
+                       const float* pos, const float* quat, int edge, oracle_point* pts) {
   if (j == ORACLE_GROUND) return np_ground(i, type, size, ext, pos, quat, pts);
   v3 pi = load3(pos, i), pj = load3(pos, j);
   float Ri[9], Rj[9];
@@ -196,12 +276,18 @@ static int narrowphase(int32_t i, int32_t j, const uint8_t* type, const float* s
   if (type[j] == 0) return np_sphere_cube(pj, size[j], pi, Ri, ei, 0, pts);
   int c = np_vertices_in_box(pi, Ri, ei, pj, Rj, ej, 1, pts);
   c += np_vertices_in_box(pj, Rj, ej, pi, Ri, ei, 0, pts + c);
+  if (edge) c += np_edge_edge(pi, Ri, ei, pj, Rj, ej, pts + c);
   return c;
 }
 
 int oracle_narrowphase(int32_t i, int32_t j, const uint8_t* type, const float* size,
                        const float* pos, const float* quat, oracle_point* pts) {
-  return narrowphase(i, j, type, size, NULL, pos, quat, pts);
+  return narrowphase(i, j, type, size, NULL, pos, quat, 0, pts);
+}
+
+int oracle_narrowphase_box(int32_t i, int32_t j, const uint8_t* type, const float* size, const float* ext,
+                           const float* pos, const float* quat, int32_t edge, oracle_point* pts) {
+  return narrowphase(i, j, type, size, ext, pos, quat, edge, pts);
 }
 
 /* ---------------------------------------------------------------------------
@@ -258,7 +344,7 @@ int oracle_step_env_box(int32_t n, const uint8_t* type, const float* size, const
           cand = dot(d, d) <= rs * rs;
         }
         if (!cand) continue;
-        int cnt = narrowphase(i, jj, type, size, ext, pos, quat, pts);
+        int cnt = narrowphase(i, jj, type, size, ext, pos, quat, prm->edge, pts);
         if (cnt == 0) continue;
         if (pairs) {
           if (np >= pair_cap) { status = -1; }

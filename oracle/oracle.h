@@ -28,11 +28,17 @@ extern "C" {
 #endif
 
 #define ORACLE_GROUND 0xFFFF
-#define ORACLE_MAX_POINTS 16
+#define ORACLE_MAX_POINTS 17
+/* Edge-edge contacts: cross products with squared length below this are no
+ * axis; an edge axis wins only below this fraction of the least face
+ * overlap. */
+#define ORACLE_EDGE_PARALLEL 1.0e-6f
+#define ORACLE_EDGE_BIAS 0.95f
 
 /* Physics parameters: dt, substeps, contact stiffness k, damping c, gravity;
  * friction coefficient mu (0: none) and the slip speed v_eps below which
- * the regularized Coulomb friction is linear in the slip. */
+ * the regularized Coulomb friction is linear in the slip; edge != 0 adds
+ * the separating-axis edge-edge point to box-box contacts. */
 typedef struct {
   float dt;
   int32_t substeps;
@@ -41,6 +47,7 @@ typedef struct {
   float g[3];
   float mu;
   float v_eps;
+  int32_t edge;
 } oracle_phys_params;
 
 /* Mesh templates (unit size) and shading constants. */
@@ -106,6 +113,10 @@ int oracle_step_env_box(int32_t n, const uint8_t* type, const float* size, const
  * contact points written to pts (at most ORACLE_MAX_POINTS). */
 int oracle_narrowphase(int32_t i, int32_t j, const uint8_t* type, const float* size,
                        const float* pos, const float* quat, oracle_point* pts);
+/* As oracle_narrowphase, with boxes (ext as in oracle_step_env_box, may be
+ * NULL) and, for edge != 0, the edge-edge point of two boxes. */
+int oracle_narrowphase_box(int32_t i, int32_t j, const uint8_t* type, const float* size, const float* ext,
+                           const float* pos, const float* quat, int32_t edge, oracle_point* pts);
 
 /*
  * Render one camera of one env.  rgb [H][W][3] u8, depth [H][W] u32 (24-bit

@@ -263,6 +263,7 @@ class Scene:
     gravity: tuple = (0.0, 0.0, -9.81)
     mu: float = 0.0        # regularized Coulomb friction coefficient (0: none)
     v_eps: float = 0.05    # [m/s] slip speed below which friction is linear
+    edge_contacts: bool = False  # box-box edge-edge points (separating-axis test)
     near_clip: bool = False  # cut triangles crossing the near plane instead of culling them
     # boxes (type 2): half-extents and principal moments of inertia, body frame
     ext: Optional[np.ndarray] = None      # f32 [B,3] (rows of other bodies unused)

@@ -97,7 +97,19 @@ typedef struct {
  * 0.05 m/s covers mu <= 1 at h = 1/960 s), while a body on a slope of
  * angle theta < atan(mu) creeps at v_eps tan(theta) / mu.  VUDA_EINVAL
  * for mu negative or non-finite, or v_eps not positive and finite while
- * mu > 0. */
+ * mu > 0.
+ *
+ * edge_contacts = 1 adds, to the vertex-in-box points of two boxes or
+ * cubes, one edge-edge point found by the separating-axis test over the
+ * 15 axes of the pair (each box's 3 axes, then the 9 cross products of an
+ * axis of the first with one of the second, skipped when the two axes are
+ * within 1e-3 rad of parallel).  No axis may separate the boxes, and the
+ * least overlap over the cross products must be below 0.95 times the least
+ * over the face axes; the point is where the two supporting edges pass
+ * closest, with that overlap as depth and that axis as normal (pointing
+ * from the second body to the first).  0 keeps vertex-only box contacts,
+ * which miss two edges crossing with no vertex inside the other box.
+ * Other values: VUDA_EINVAL. */
 typedef struct {
   float dt;
   int32_t substeps;
@@ -106,6 +118,7 @@ typedef struct {
   float gravity[3];
   float mu;     /* friction coefficient (0: none)                  */
   float v_eps;  /* [m/s] slip speed below which friction is linear */
+  int32_t edge_contacts;  /* 1: box-box edge-edge points (0: off) */
 } vuda_phys_params;
 
 /* Unit mesh templates and shading constants.  Faces are vertex-index

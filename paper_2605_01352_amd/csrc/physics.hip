@@ -100,6 +100,7 @@ struct PhysLDS {
   int32_t gcl[N];         // cubes closer to the ground than their bounding radius
   float kres[9][CAPK];    // SF xyz, Ti xyz, Tj xyz of each pair in contact
   alignas(16) float stage[9][N];  // one contact point's terms per lane, before the ordered sum
+  float estage[9][N / 16];        // terms of the edge-edge point of each 16-lane group
   float gres[6][N];       // ground force and torque of each body
   int32_t scan[NW + 1];
   float red[NW];
@@ -356,6 +357,111 @@ __device__ __forceinline__ bool corner_in_box(f3 pa, const M3& Ra, f3 aa, int k,
   return true;
 }
 
+// Axis k (0..2) of a rotation (row-major): its column k, selected without
+// indexing the registers.
+__device__ __forceinline__ f3 axis_of(const M3& R, int k) {
+  return k == 0 ? mk(R.m[0], R.m[3], R.m[6]) : (k == 1 ? mk(R.m[1], R.m[4], R.m[7]) : mk(R.m[2], R.m[5], R.m[8]));
+}
+
+// Half-width of a box (rotation R, half-extents e) along direction L.
+__device__ __forceinline__ float box_radius(const M3& R, f3 e, f3 L) {
+  const f3 u = rotT(R, L);
+  return (e.x * fabsf(u.x) + e.y * fabsf(u.y)) + e.z * fabsf(u.z);
+}
+
+constexpr float kEdgeParallel = 1.0e-6f;  // squared length below which a cross product is no axis
+constexpr float kEdgeBias = 0.95f;        // an edge axis wins below this fraction of the least face overlap
+
+// Edge-edge point of the box pair (i, j), i < j, by the separating-axis
+// test, evaluated by the 16-lane group of the calling lane (every lane of
+// the wave calls it; `live` is uniform over a group).  Lane r < 15 takes
+// candidate axis r: the 3 axes of i, the 3 of j, then (axis a of i) x
+// (axis b of j) at 6 + 3a + b.  The group reduces the least face overlap
+// and the least edge overlap (lowest axis on ties); if no axis separates
+// and the edge overlap is below kEdgeBias times the face one, lane 15
+// stages the point's terms in estage.  Returns that decision, the same on
+// every lane of the group.
+template <int NW, bool FR>
+__device__ __forceinline__ bool edge_point(PhysLDS<NW>& s, bool live, int r, int lane, int i, int j,
+                                           const PhysConsts& pc) {
+  const M3 Ri = ldsR(s, i), Rj = ldsR(s, j);
+  const f3 ei = ldsE(s, i), ej = ldsE(s, j);
+  const f3 pi = ldsP(s, i), pj = ldsP(s, j);
+  const f3 d = sub(pi, pj);
+  f3 L = mk(0.0f, 0.0f, 0.0f);
+  bool valid = false;
+  if (live && r < 15) {
+    if (r < 3) {
+      L = axis_of(Ri, r);
+      valid = true;
+    } else if (r < 6) {
+      L = axis_of(Rj, r - 3);
+      valid = true;
+    } else {
+      L = cross(axis_of(Ri, (r - 6) / 3), axis_of(Rj, (r - 6) % 3));
+      const float l2 = dot(L, L);
+      valid = l2 >= kEdgeParallel;
+      if (valid) {
+        const float l = sqrtf(l2);
+        L = mk(L.x / l, L.y / l, L.z / l);
+      }
+    }
+  }
+  float o = INFINITY;
+  if (valid) o = (box_radius(Ri, ei, L) + box_radius(Rj, ej, L)) - fabsf(dot(d, L));
+  const int g0 = lane & 48;
+  const bool sep = ((__ballot(valid && !(o > 0.0f)) >> g0) & 0xFFFFull) != 0ull;
+  float fo = r < 6 ? o : INFINITY;
+  float eo = r < 6 ? INFINITY : o;
+  int ek = r;
+#pragma unroll
+  for (int m = 1; m < 16; m <<= 1) {
+    const float fo2 = __shfl_xor(fo, m, 64);
+    const float eo2 = __shfl_xor(eo, m, 64);
+    const int ek2 = __shfl_xor(ek, m, 64);
+    fo = fminf(fo, fo2);
+    if (eo2 < eo || (eo2 == eo && ek2 < ek)) {
+      eo = eo2;
+      ek = ek2;
+    }
+  }
+  const bool has = live && !sep && eo < kEdgeBias * fo;
+  // the winning axis, as its lane computed it
+  const int src = g0 + ek;
+  const f3 eL = mk(__shfl(L.x, src, 64), __shfl(L.y, src, 64), __shfl(L.z, src, 64));
+  if (has && r == 15) {
+    const int a = (ek - 6) / 3, b = (ek - 6) % 3;
+    const f3 n = dot(eL, d) < 0.0f ? neg(eL) : eL;  // from j to i
+    // the edge of i along its axis a deepest toward j (along -n) and the
+    // edge of j along its axis b deepest toward i (along +n): their centres
+    const f3 ui = rotT(Ri, n), uj = rotT(Rj, n);
+    const f3 wi = mk(a == 0 ? 0.0f : (ui.x > 0.0f ? -ei.x : ei.x), a == 1 ? 0.0f : (ui.y > 0.0f ? -ei.y : ei.y),
+                     a == 2 ? 0.0f : (ui.z > 0.0f ? -ei.z : ei.z));
+    const f3 wj = mk(b == 0 ? 0.0f : (uj.x > 0.0f ? ej.x : -ej.x), b == 1 ? 0.0f : (uj.y > 0.0f ? ej.y : -ej.y),
+                     b == 2 ? 0.0f : (uj.z > 0.0f ? ej.z : -ej.z));
+    const f3 ci = add(pi, rot(Ri, wi)), cj = add(pj, rot(Rj, wj));
+    // closest points of the two edge lines, each clamped to its edge
+    const f3 da = axis_of(Ri, a), db = axis_of(Rj, b);
+    const f3 w = sub(ci, cj);
+    const float bb = dot(da, db), dd = dot(da, w), ee = dot(db, w);
+    const float den = 1.0f - bb * bb;
+    float sa = (bb * ee - dd) / den, tb = (ee - bb * dd) / den;
+    const float ha = pick(ei, a), hb = pick(ej, b);
+    sa = fminf(fmaxf(sa, -ha), ha);
+    tb = fminf(fmaxf(tb, -hb), hb);
+    Point pt;
+    pt.n = n;
+    pt.delta = eo;
+    pt.xc = mul(add(add(ci, mul(da, sa)), add(cj, mul(db, tb))), 0.5f);
+    const PointTerms pq = point_terms<FR>(pt, true, pi, ldsV(s, i), ldsW(s, i), pj, ldsV(s, j), ldsW(s, j), false, pc);
+    const int gi = (int)threadIdx.x >> 4;
+    s.estage[0][gi] = pq.Fi.x; s.estage[1][gi] = pq.Fi.y; s.estage[2][gi] = pq.Fi.z;
+    s.estage[3][gi] = pq.ti.x; s.estage[4][gi] = pq.ti.y; s.estage[5][gi] = pq.ti.z;
+    s.estage[6][gi] = pq.tj.x; s.estage[7][gi] = pq.tj.y; s.estage[8][gi] = pq.tj.z;
+  }
+  return has;
+}
+
 // Lanes of this wave below the calling lane whose bit is set in m.
 __device__ __forceinline__ int lanes_below(uint64_t m) {
   return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -392,7 +498,7 @@ __device__ __forceinline__ int popc_below(const uint64_t* row, int b) {
   return c;
 }
 
-template <int NW, bool FR>
+template <int NW, bool FR, bool EE>
 __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc, int env,
                          int parity, int broadphase) {
   constexpr int N = PhysLDS<NW>::N;
@@ -423,11 +529,15 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
     rbv = W.rbound[gb];
     ty = W.type[gb];
     s.size[tid] = a;
-    const float* bx = W.box + 6 * (int64_t)gb;
-    s.ext[tid] = make_float4(bx[0], bx[1], bx[2], 0.0f);
-    s.inert[0][tid] = bx[3];
-    s.inert[1][tid] = bx[4];
-    s.inert[2][tid] = bx[5];
+    if (ty == 2) {
+      const float* bx = W.box + 6 * (int64_t)gb;
+      s.ext[tid] = make_float4(bx[0], bx[1], bx[2], 0.0f);
+      s.inert[0][tid] = bx[3];
+      s.inert[1][tid] = bx[4];
+      s.inert[2][tid] = bx[5];
+    } else {
+      s.ext[tid] = make_float4(a, a, a, 0.0f);
+    }
     s.rb[tid] = rbv;
     s.type[tid] = ty;
   }
@@ -719,17 +829,24 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
           s.stage[6][tid] = pq.tj.x; s.stage[7][tid] = pq.tj.y; s.stage[8][tid] = pq.tj.z;
         }
       }
+      // edge-edge point (after the 16 vertex points in the pair's order)
+      bool ehit = false;
+      if constexpr (EE) ehit = edge_point<NW, FR>(s, t < 16 * ncc, r, lane, i, j, pc);
       const uint64_t hm = __ballot(hit);
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       const int g0 = lane & 48;  // the group's first lane in the wave
       const uint32_t gm = (uint32_t)(hm >> g0) & 0xFFFFu;
       float sum = 0.0f;
       if (r < 9) sum = ordered_sum<16, NW>(s, r, tid - r, gm);
-      const uint64_t lead = __ballot(r == 0 && gm != 0);
+      if constexpr (EE) {
+        if (ehit && r < 9) sum = sum + s.estage[r][tid >> 4];
+      }
+      const bool any = gm != 0 || ehit;
+      const uint64_t lead = __ballot(r == 0 && any);
       int kb = 0;
       if (lane == 0 && lead) kb = atomicAdd(&s.kcnt, __popcll(lead));
       kb = __shfl(kb, 0, 64);
-      if (gm != 0) {
+      if (any) {
         const int slot = kb + __popcll(lead & ((1ull << g0) - 1ull));
         if (r < 9 && slot < PhysLDS<NW>::CAPK) s.kres[r][slot] = sum;
         if (r == 0) {
@@ -934,7 +1051,8 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
   if (bad && tid == 0) atomicOr(&W.env_flags[env], kFlagContactOverflow);
 }
 
-template <int NW, bool FR>
+// FR: friction; EE: edge-edge points of box pairs
+template <int NW, bool FR, bool EE>
 __global__ __launch_bounds__(64 * NW) void physics_kernel(WorldDev W, PhysConsts pc, PhysLaunch L) {
   __shared__ PhysLDS<NW> s;
   // The step is latency-bound; a higher issue priority shortens it when it
@@ -948,7 +1066,7 @@ __global__ __launch_bounds__(64 * NW) void physics_kernel(WorldDev W, PhysConsts
   if (L.persistent == 0) {
     const int wi = blockIdx.x;
     if (wi >= L.n_work) return;
-    step_env<NW, FR>(s, W, pc, L.work[wi], L.parity, L.broadphase);
+    step_env<NW, FR, EE>(s, W, pc, L.work[wi], L.parity, L.broadphase);
     return;
   }
   for (;;) {
@@ -957,7 +1075,7 @@ __global__ __launch_bounds__(64 * NW) void physics_kernel(WorldDev W, PhysConsts
     const int wi = s.work;
     __syncthreads();
     if (wi >= L.n_work) return;
-    step_env<NW, FR>(s, W, pc, L.work[wi], L.parity, L.broadphase);
+    step_env<NW, FR, EE>(s, W, pc, L.work[wi], L.parity, L.broadphase);
   }
 }
 
@@ -982,15 +1100,21 @@ hipError_t launch_physics(const WorldDev& w, const PhysConsts& pc, const PhysLau
       hipError_t e = launch_reset_queue(l.queue, s);
       if (e != hipSuccess) return e;
     }
-    const bool fr = pc.mu > 0.0f;
-    if (nw == 1 && !fr)
-      timed_launch(ev, t == 0, t == l.nsteps - 1, physics_kernel<1, false>, dim3(grid), dim3(64), 0, s, w, pc, lt);
-    else if (nw == 1)
-      timed_launch(ev, t == 0, t == l.nsteps - 1, physics_kernel<1, true>, dim3(grid), dim3(64), 0, s, w, pc, lt);
-    else if (!fr)
-      timed_launch(ev, t == 0, t == l.nsteps - 1, physics_kernel<2, false>, dim3(grid), dim3(128), 0, s, w, pc, lt);
-    else
-      timed_launch(ev, t == 0, t == l.nsteps - 1, physics_kernel<2, true>, dim3(grid), dim3(128), 0, s, w, pc, lt);
+    const bool fr = pc.mu > 0.0f, ee = pc.edge != 0;
+    const int bs = 64 * nw;
+    const bool first = t == 0, last = t == l.nsteps - 1;
+    const dim3 g(grid), b(bs);
+    if (nw == 1) {
+      if (!fr && !ee) timed_launch(ev, first, last, physics_kernel<1, false, false>, g, b, 0, s, w, pc, lt);
+      else if (!ee) timed_launch(ev, first, last, physics_kernel<1, true, false>, g, b, 0, s, w, pc, lt);
+      else if (!fr) timed_launch(ev, first, last, physics_kernel<1, false, true>, g, b, 0, s, w, pc, lt);
+      else timed_launch(ev, first, last, physics_kernel<1, true, true>, g, b, 0, s, w, pc, lt);
+    } else {
+      if (!fr && !ee) timed_launch(ev, first, last, physics_kernel<2, false, false>, g, b, 0, s, w, pc, lt);
+      else if (!ee) timed_launch(ev, first, last, physics_kernel<2, true, false>, g, b, 0, s, w, pc, lt);
+      else if (!fr) timed_launch(ev, first, last, physics_kernel<2, false, true>, g, b, 0, s, w, pc, lt);
+      else timed_launch(ev, first, last, physics_kernel<2, true, true>, g, b, 0, s, w, pc, lt);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

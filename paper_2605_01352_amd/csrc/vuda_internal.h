@@ -109,6 +109,7 @@ struct PhysConsts {
   float g[3];
   int32_t substeps;
   float mu, v_eps;  // regularized Coulomb friction (mu = 0: none)
+  int32_t edge;     // box-box edge-edge points (separating-axis test)
 };
 
 // Pointers into the world arena used by the kernels.

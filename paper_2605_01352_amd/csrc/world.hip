@@ -453,6 +453,8 @@ extern "C" int vuda_create_world(const vuda_world_desc* d, const vuda_allocator*
   if (!(d->phys.mu >= 0.0f) || !std::isfinite(d->phys.mu) ||
       (d->phys.mu > 0.0f && (!(d->phys.v_eps > 0.0f) || !std::isfinite(d->phys.v_eps))))
     return fail(VUDA_EINVAL, "friction parameters mu %g, v_eps %g", d->phys.mu, d->phys.v_eps);
+  if (d->phys.edge_contacts != 0 && d->phys.edge_contacts != 1)
+    return fail(VUDA_EINVAL, "edge_contacts %d", (int)d->phys.edge_contacts);
   int rc = validate_render(d->render);
   if (rc) return rc;
   int64_t nb = 0, npix = 0;
@@ -502,6 +504,7 @@ extern "C" int vuda_create_world(const vuda_world_desc* d, const vuda_allocator*
   w->pc.substeps = d->phys.substeps;
   w->pc.mu = d->phys.mu;
   w->pc.v_eps = d->phys.mu > 0.0f ? d->phys.v_eps : 1.0f;
+  w->pc.edge = d->phys.edge_contacts;
   rc = w->alloc_arena(a);
   if (rc) {
     w->free_all();

@@ -52,7 +52,8 @@ class VudaError(RuntimeError):
 
 class PhysParams(C.Structure):
     _fields_ = [("dt", C.c_float), ("substeps", C.c_int32), ("k_contact", C.c_float),
-                ("c_damp", C.c_float), ("gravity", C.c_float * 3), ("mu", C.c_float), ("v_eps", C.c_float)]
+                ("c_damp", C.c_float), ("gravity", C.c_float * 3), ("mu", C.c_float), ("v_eps", C.c_float),
+                ("edge_contacts", C.c_int32)]
 
 
 class RenderDesc(C.Structure):
@@ -228,13 +229,15 @@ class World:
         g = (ref.gravity if ref is not None else (0.0, 0.0, -9.81))
         mu = (ref.mu if ref is not None else 0.0)
         v_eps = (ref.v_eps if ref is not None else 0.05)
+        edge = bool(ref.edge_contacts) if ref is not None else False
         if phys:
             dt, sub, k, c, g = phys.get("dt", dt), phys.get("substeps", sub), phys.get("k", k), \
                 phys.get("c", c), phys.get("g", g)
             mu, v_eps = phys.get("mu", mu), phys.get("v_eps", v_eps)
+            edge = phys.get("edge_contacts", edge)
         desc = WorldDesc()
         desc.phys = PhysParams(float(np.float32(dt)), int(sub), float(k), float(c),
-                               (C.c_float * 3)(*[float(x) for x in g]), float(mu), float(v_eps))
+                               (C.c_float * 3)(*[float(x) for x in g]), float(mu), float(v_eps), int(edge))
         desc.render = render_desc(keep, **(render_kw or {}))
         desc.initial = env_batch(keep, scene) if scene is not None else EnvBatch(0)
         desc.flags = (FLAG_DEBUG if debug else 0) | (FLAG_NEAR_CLIP if getattr(ref, "near_clip", False) else 0)
@@ -430,17 +433,18 @@ def world_desc(keep: _Keep, scene=None, debug: bool = False, cap_envs: int = 0, 
                cap_cams: int = 0, cap_pixels: int = 0, pair_cap: int = 1024, hbm_budget: int = 0,
                phys=None) -> WorldDesc:
     dt, sub, k, c, g = 1.0 / 240.0, 4, 1.0e4, 10.0, (0.0, 0.0, -9.81)
-    mu, v_eps = 0.0, 0.05
+    mu, v_eps, edge = 0.0, 0.05, False
     if scene is not None:
         dt, sub, k, c, g = scene.dt, scene.substeps, scene.k_contact, scene.c_damp, scene.gravity
-        mu, v_eps = scene.mu, scene.v_eps
+        mu, v_eps, edge = scene.mu, scene.v_eps, bool(scene.edge_contacts)
     if phys:
         dt, sub, k, c, g = phys.get("dt", dt), phys.get("substeps", sub), phys.get("k", k), \
             phys.get("c", c), phys.get("g", g)
         mu, v_eps = phys.get("mu", mu), phys.get("v_eps", v_eps)
+        edge = phys.get("edge_contacts", edge)
     d = WorldDesc()
     d.phys = PhysParams(float(np.float32(dt)), int(sub), float(k), float(c),
-                        (C.c_float * 3)(*[float(x) for x in g]), float(mu), float(v_eps))
+                        (C.c_float * 3)(*[float(x) for x in g]), float(mu), float(v_eps), int(edge))
     d.render = render_desc(keep)
     d.initial = env_batch(keep, scene) if scene is not None else EnvBatch(0)
     d.flags = (FLAG_DEBUG if debug else 0) | (FLAG_NEAR_CLIP if getattr(scene, "near_clip", False) else 0)

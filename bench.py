@@ -199,7 +199,7 @@ def features_bench(torch, vuda, sg, scene, steps, log):
     """The optional features on the same workload, each in a world of its
     own: friction (mu = 0.5) in the physics kernel, half of the cubes made
     boxes (anisotropic extents and inertia) in the physics and setup
-    kernels, near-plane clipping in the raster setup (cameras of this
+    kernels, with and without edge-edge contacts, near-plane clipping in the raster setup (cameras of this
     workload never cross the near plane, so only the cost of the cutting
     code shows), and the metric-depth fetch of every frame into device
     memory."""
@@ -221,6 +221,8 @@ def features_bench(torch, vuda, sg, scene, steps, log):
     for name, sc, kernel in (("physics_mu0", scene, vuda.KERNEL_PHYSICS),
                              ("physics_mu0.5", dataclasses.replace(scene, mu=0.5), vuda.KERNEL_PHYSICS),
                              ("physics_boxes", boxes, vuda.KERNEL_PHYSICS),
+                             ("physics_boxes_edge", dataclasses.replace(boxes, edge_contacts=True),
+                              vuda.KERNEL_PHYSICS),
                              ("setup", scene, vuda.KERNEL_RASTER_SETUP),
                              ("setup_boxes", boxes, vuda.KERNEL_RASTER_SETUP),
                              ("setup_near_clip", dataclasses.replace(scene, near_clip=True),

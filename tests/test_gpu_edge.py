@@ -70,3 +70,11 @@ def test_edge_flag_errors():
     s = sg.config_scene(1, n_envs=2)
     with pytest.raises(vuda.VudaError):
         vuda.World(s, phys={"edge_contacts": 2})
+
+
+def test_edge_boxes_two_wave_envs_parity():
+    """Envs of 100 bodies (the two-wave physics kernel) with boxes and edge
+    points, 20 steps."""
+    s = sg.make_scene(4242, np.full(6, 100), 128, mixed=True, name="b100")
+    s = dataclasses.replace(sg.with_boxes(s), edge_contacts=True)
+    run_steps(s, 20, "edge boxes 100 bodies")

@@ -237,7 +237,11 @@ def run_batch(scene, state, n_steps: int, nthreads: int, do_render: bool = True)
     """Multi-threaded batch run (whole envs per thread) for the CPU baseline.
 
     Modifies `state` in place; returns (status, rgb, depth) of the last step.
+    Spheres and cubes only: a scene with boxes goes through step_scene and
+    render_image.
     """
+    if np.any(scene.btype == 2):
+        raise ValueError("run_batch takes spheres and cubes only; step boxes with step_scene")
     off = image_offsets(scene)
     total = int((scene.cam_w.astype(np.int64) * scene.cam_h).sum())
     rgb = np.zeros(total * 3, np.uint8)

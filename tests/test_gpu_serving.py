@@ -107,3 +107,24 @@ def test_slots_are_reused():
             srv.submit(k, scenes[1], specs[1].horizon)  # 9 envs each: one at a time
         done = run_until_done(srv, 6, max_ticks=200)
         assert len(done) == 6
+
+
+def test_box_request_matches_a_plain_world():
+    """A request whose envs hold boxes (extents and moments copied with the
+    request and uploaded at admission) ends as a plain world of them."""
+    r = sg.RequestSpec(5, 0.0, 6, 20, 64, 9)
+    scene = sg.with_boxes(sg.request_scene(r), every=1)
+    assert np.count_nonzero(scene.btype == 2) > 0
+    with server() as srv:
+        srv.submit(5, scene, r.horizon)
+        run_until_done(srv, 1)
+        got = [srv.result(5, k) for k in (vuda.FETCH_STATE, vuda.FETCH_RGB, vuda.FETCH_DEPTH)]
+    with vuda.World(scene) as w:
+        for _ in range(r.horizon):
+            w.step()
+        w.render()
+        w.wait()
+        want = [w.fetch(k) for k in (vuda.FETCH_STATE, vuda.FETCH_RGB, vuda.FETCH_DEPTH)]
+    for x, y in zip(want, got):
+        assert np.array_equal(x, y)
+    say("box request: state, rgb and depth equal to the plain world's")

@@ -206,3 +206,46 @@ def test_depth_ordering_nearer_body_wins():
     out = _render(sc)
     c = out["winner"][16, 16]
     assert 2 + 80 <= c < 2 + 160  # the upper (nearer) sphere
+
+
+def test_shading_of_a_rotated_cube_off_axis():
+    """A cube turned 90 degrees about x, then 30 degrees about z, seen
+    obliquely under an off-axis light.  Worked by hand: Rx(90) takes the body
+    axes x, y, z to x, z, -y; Rz(30) then turns them about z, so the body's
+    +x face looks along (cos 30, sin 30, 0), its +y face along (0, 0, 1) and
+    its +z face along (sin 30, -cos 30, 0).  Each visible pixel of a face
+    takes albedo * (0.2 + 0.8 max(0, n.L)) with that world normal.  A normal
+    taken through the transposed rotation points elsewhere for every face
+    and changes the colours."""
+    c30, s30 = math.cos(math.radians(30)), math.sin(math.radians(30))
+    c15, s15 = math.cos(math.radians(15)), math.sin(math.radians(15))
+    c45 = s45 = math.sqrt(0.5)
+    # q = qz(30) (x) qx(90), Hamilton product, w first
+    quat = (c15 * c45, c15 * s45, s15 * s45, s15 * c45)
+    world_n = {(0, 1): (c30, s30, 0.0), (1, 1): (0.0, 0.0, 1.0), (2, 1): (s30, -c30, 0.0)}
+    for (k, s), n in list(world_n.items()):
+        world_n[(k, -1)] = tuple(-x for x in n)
+    light = np.array([0.5, -0.7, 0.5])
+    light = light / np.linalg.norm(light)
+    vp = sg.view_proj((1.1, -1.3, 1.2), target=(0.0, 0.0, 0.25))
+    sc = tiny_scene([dict(type=1, size=0.2, pos=(0.0, 0.0, 0.25), quat=quat)], vp=vp, res=64)
+    out = _render(sc, light=tuple(light))
+    face = out["winner"] - 2
+    t = sg.templates()
+    alb = sg.PALETTE[0].astype(np.float64)
+    seen = {}
+    for f in range(12):
+        px = face == f
+        if not px.any():
+            continue
+        bn = t.cube_n[f]
+        k = int(np.argmax(np.abs(bn)))
+        n = np.array(world_n[(k, 1 if bn[k] > 0 else -1)])
+        lam = max(0.0, float(n @ light))
+        expect = np.rint(255 * alb * (0.2 + 0.8 * lam)).astype(int)
+        assert np.abs(out["rgb"][px].astype(int) - expect).max() <= 1, (f, expect)
+        seen[(k, int(np.sign(bn[k])))] = lam
+    # three faces in view, lit differently: the body's +x, +y and +z faces,
+    # whose world normals have a positive component toward the eye
+    assert set(seen) == {(0, 1), (1, 1), (2, 1)}
+    assert len({round(v, 3) for v in seen.values()}) == 3

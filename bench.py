@@ -250,31 +250,114 @@ def features_bench(torch, vuda, sg, scene, steps, log):
     return out
 
 
-def cpu_baseline(scene_fn, n_envs, steps):
-    import numpy as np  # noqa: F401
-    import oracle
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except Exception:
-        cores = os.cpu_count() or 1
-    threads = max(1, min(16, cores))
-    s = scene_fn(n_envs)
-    st = s.state()
-    t0 = time.perf_counter()
-    status, _, _ = oracle.run_batch(s, st, steps, nthreads=threads, do_render=True)
-    dt = time.perf_counter() - t0
-    cpu_model = ""
+def host_cpu():
+    """CPU model, logical CPUs of the host and CPUs this process may use."""
+    model = ""
     try:
         for line in open("/proc/cpuinfo"):
             if line.startswith("model name"):
-                cpu_model = line.split(":", 1)[1].strip()
+                model = line.split(":", 1)[1].strip()
                 break
-    except Exception:
+    except OSError:
         pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except Exception:
+        allowed = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, allowed
+
+
+def cpu_baseline(scene_fn, n_envs, steps, start_state=None):
+    """The oracle (plain C, one env per thread at a time) on a bounded sample
+    of the workload.  Threads: the CPU share one GPU of this machine may use
+    (16), or fewer if the process may use fewer CPUs."""
+    import oracle
+    model, nproc, allowed = host_cpu()
+    threads = max(1, min(16, allowed))
+    s = scene_fn(n_envs)
+    st = s.state() if start_state is None else {k: v.copy() for k, v in start_state.items()}
+    t0 = time.perf_counter()
+    status, _, _ = oracle.run_batch(s, st, steps, nthreads=threads, do_render=True)
+    dt = time.perf_counter() - t0
     return dict(value=n_envs * steps / dt, unit="env-steps/s", cores=threads, kind="oracle",
-                sample=f"{n_envs} envs x {steps} steps of the same workload (seeded, same content), "
-                       f"{threads} threads over whole envs, {dt:.1f} s, host {cpu_model}",
-                status=int(status))
+                sample=f"{n_envs} envs x {steps} steps of the same workload from the same mid-horizon state "
+                       f"(seeded, same content), {threads} threads over whole envs, {dt:.1f} s; host: {model}, "
+                       f"nproc {nproc}, {allowed} CPUs allowed to this process; 16 is the host CPU share of "
+                       f"one GPU on this machine",
+                host={"cpu_model": model, "nproc": nproc, "cpus_allowed": allowed, "threads": threads},
+                seconds=round(dt, 2), status=int(status))
+
+
+def divergence_report(vuda, sg, cfgs=((1, 16), (2, 32)), steps=100):
+    """GPU and oracle each running free from the spawn for `steps` steps:
+    the largest position difference over all bodies at each step (reported,
+    not gated)."""
+    import numpy as np
+    import oracle
+    out = {}
+    for cfg, n in cfgs:
+        scene = sg.config_scene(cfg, n_envs=n)
+        st_o = scene.state()
+        rows = []
+        with vuda.World(scene) as w:
+            for t in range(1, steps + 1):
+                w.step()
+                oracle.step_scene(scene, st_o)
+                g = w.state()
+                dp = np.linalg.norm(g["pos"].astype(np.float64) - st_o["pos"].astype(np.float64), axis=1)
+                same = all(np.array_equal(g[k], st_o[k]) for k in ("pos", "vel", "quat", "omega"))
+                rows.append((float(dp.max()), bool(same)))
+        first = next((t for t, (_, sm) in enumerate(rows, 1) if not sm), None)
+        out[f"c{cfg}[0:{n}]"] = {
+            "max_dp_m": {str(t): float(f"{rows[t - 1][0]:.3e}") for t in (1, 10, 25, 50, 75, 100) if t <= steps},
+            "max_dp_over_run_m": float(f"{max(m for m, _ in rows):.3e}"),
+            "bit_equal_steps": sum(sm for _, sm in rows), "first_difference_step": first}
+    return out
+
+
+CONFIG_NAMES = {1: "plain serialized loop: 16 envs x 8 spheres, 64x64 RGB-D",
+                2: "co-scheduled: 1024 envs x 32 bodies (16 spheres / 16 cubes), 128x128 RGB-D, "
+                   "u8 RGB + u32 depth, FP32 state",
+                3: "pipelined data-gen: 4096 envs x 64 bodies, 2 cameras 256x256",
+                4: "uneven batching: 2048 envs, Poisson(24) bodies, {64,128,256}^2"}
+
+
+def contact_stats(vuda, scene, st):
+    """Contact pairs of one step from state st (a debug world loaded with
+    it): pairs per substep, body-body and body-ground, summed over envs."""
+    with vuda.World(scene, debug=True) as wd:
+        wd.load_state(st)
+        wd.step()
+        wd.wait()
+        cts = wd.contacts()
+    S = scene.substeps
+    tot = sum(len(p) for env in cts for p in env) / S
+    body = sum(int((p[:, 1] != vuda.GROUND).sum()) for env in cts for p in env) / S
+    return {"pairs_per_substep": round(tot, 1), "body_pairs_per_substep": round(body, 1),
+            "ground_pairs_per_substep": round(tot - body, 1)}
+
+
+def physics_leg(torch, vuda, scene, start, steps, log):
+    """Physics launches alone on a config (one launch per step, each timed
+    by its own event pair), from `start` steps past the spawn."""
+    with vuda.World(scene) as w:
+        w.step(nsteps=start)
+        w.wait()
+        w.set_tuning(vuda.TUNE_TIMING, 1)
+        w.kernel_times(vuda.KERNEL_PHYSICS)
+        for _ in range(steps):
+            w.step()
+        w.wait()
+        t = w.kernel_times(vuda.KERNEL_PHYSICS)
+        w.set_tuning(vuda.TUNE_TIMING, 0)
+    us = t["total_ms"] * 1e3 / max(1, t["launches"])
+    algo = 120 * scene.n_bodies
+    out = {"envs": scene.n_envs, "bodies": int(scene.n_bodies), "from_step": start, "launches": t["launches"],
+           "launch_us": round(us, 2), "max_launch_us": round(t["max_ms"] * 1e3, 2), "bytes_per_launch": algo,
+           "roofline": {"bound": "hbm", "achieved": round(algo / (us * 1e-6) / 1e9, 2), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(algo / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 5)}}
+    log(f"physics leg {scene.name}: {us:.1f} us per launch ({out['roofline']['frac']:.4f} of the HBM roof)")
+    return out
 
 
 def main():
@@ -283,8 +366,12 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--start", type=int, default=-1,
+                    help="steps advanced on the GPU before any timed window (default: half the horizon)")
+    ap.add_argument("--windows", type=int, default=5, help="timed windows per mode; the median is reported")
     ap.add_argument("--envs", type=int, default=None, help="fewer envs (debug only)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-c3", action="store_true", help="skip the physics leg at the 4096-env config")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="length of the continuous-batching serving run (0: skip)")
     ap.add_argument("--splits", default="0.25,0.375,0.5,0.625,0.75")
@@ -292,6 +379,8 @@ def main():
                     help="issue priorities of the step's waves tried on unmasked streams")
     ap.add_argument("--profile", type=int, default=0,
                     help="only run this many serialized then co-scheduled steps (for rocprofv3)")
+    ap.add_argument("--profile-mode", default="interstep@2",
+                    help="the co-scheduled mode of --profile")
     ap.add_argument("--only", default="",
                     help="skip the sweep and time this co-scheduled mode, e.g. interstep@2")
     ap.add_argument("--copy-calib", type=int, default=0,
@@ -311,22 +400,32 @@ def main():
               f"shard them with no exchange; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
 
-    import torch
     from paper_2605_01352_amd import scenegen as sg
+    cfg = args.config
+    _, _, allowed = host_cpu()
+    workers = max(1, min(16, allowed))
+    # scenes are built before anything touches the GPU
+    log(f"building scene c{cfg}")
+    scene = sg.config_scene(cfg, n_envs=args.envs, workers=workers)
+    scene3 = None
+    if cfg == 2 and not args.no_c3 and not args.profile and not args.policy_profile and not args.policy_loop \
+            and not args.only:
+        t0 = time.perf_counter()
+        scene3 = sg.config_scene(3, workers=workers)
+        log(f"built scene c3 in {time.perf_counter() - t0:.1f} s")
+
+    import torch
     from paper_2605_01352_amd import vuda
 
     torch.cuda.init()
     if args.copy_calib:
         copy_calibration(torch, args.copy_calib)
-    cfg = args.config
-    log(f"building scene c{cfg}")
-    scene = sg.config_scene(cfg, n_envs=args.envs)
     n_envs = scene.n_envs
+    horizon = sg.CONFIG_STEPS.get(cfg, 100)
+    start = horizon // 2 if args.start < 0 else args.start
     w = vuda.World(scene)
     log(f"world: {n_envs} envs, {scene.n_bodies} bodies, {scene.n_cams} cameras, "
         f"{w.info()['arena_bytes'] / 2**20:.1f} MiB arena")
-
-    st0 = scene.state()
     knob_ids = {"raster_threads": vuda.TUNE_RASTER_THREADS, "rec_cap": vuda.TUNE_REC_CAP,
                 "phys_persistent": vuda.TUNE_PHYS_PERSISTENT,
                 "raster_persistent": vuda.TUNE_RASTER_PERSISTENT, "graphs": vuda.TUNE_GRAPHS,
@@ -335,9 +434,14 @@ def main():
     for kv in filter(None, args.tune.split(",")):
         k, v = kv.split("=")
         w.set_tuning(knob_ids[k], int(v))
+    # every timed window starts from the state `start` steps past the spawn
+    # (bodies fallen and piled), reached on the GPU outside any window
+    w.step(nsteps=start)
+    w.wait()
+    st0 = w.state()
+    log(f"start state: {start} steps past the spawn")
     if args.policy_profile:
         w.set_policy(sg.policy_weights(2605, int(scene.cam_w[0]), int(scene.cam_h[0]), hiddens[0], 32))
-        w.step(nsteps=5)
         w.render()
         for _ in range(args.policy_profile):
             w.act()
@@ -350,36 +454,41 @@ def main():
         w.close()
         return
     if args.profile:
+        psched, psplit = args.profile_mode.split("@")
         w.cosched(0.0)
         dt_s = timed(torch, w, "serial", n_envs, args.profile, 2, st0)
-        w.cosched(2.0)
-        dt_c = timed(torch, w, "interstep", n_envs, args.profile, 2, st0)
-        log(f"profile run: serialized {dt_s / args.profile * 1e6:.1f} us/step, "
-            f"co-scheduled {dt_c / args.profile * 1e6:.1f} us/step")
+        w.cosched(float(psplit))
+        dt_c = timed(torch, w, psched, n_envs, args.profile, 2, st0)
+        log(f"profile run from step {start}: serialized {dt_s / args.profile * 1e6:.1f} us/step, "
+            f"co-scheduled ({args.profile_mode}) {dt_c / args.profile * 1e6:.1f} us/step")
         w.close()
         return
+
+    def median_windows(sched):
+        dts = sorted(timed(torch, w, sched, n_envs, args.steps, args.warmup, st0) for _ in range(max(1, args.windows)))
+        return dts[len(dts) // 2], dts
+
     def kernel_run(sched):
-        """The same timed region again with a HIP event pair around every
-        launch: the per-kernel launch durations of that region.  The events
-        cost throughput of their own, so the headline figures come from the
-        runs without them."""
+        """The same window again with a HIP event pair around every launch:
+        the per-kernel launch durations of that window.  The events cost
+        throughput of their own, so the headline figures come from the runs
+        without them."""
         w.set_tuning(vuda.TUNE_TIMING, 1)
         timed(torch, w, sched, n_envs, args.steps, args.warmup, st0,
               after_warmup=lambda: launch_stats(vuda, w))
-        st = launch_stats(vuda, w)  # launches of the timed region
+        st = launch_stats(vuda, w)  # launches of the timed window
         w.set_tuning(vuda.TUNE_TIMING, 0)
         return st
 
     w.set_tuning(vuda.TUNE_TIMING, 0)
-    results = {}
     w.cosched(0.0)
-    results["serialized"] = timed(torch, w, "serial", n_envs, args.steps, args.warmup, st0)
+    dt_ser, ser_windows = median_windows("serial")
     alone = kernel_run("serial")
     presetup = w.get_tuning(vuda.TUNE_PRESETUP) != 0
     Ts, Tr = phase_seconds(alone, args.steps, presetup)
-    ser = n_envs * args.steps / results["serialized"]
-    log(f"serialized: {ser:.0f} env-steps/s; per step alone: step phase {Ts*1e6:.1f} us, "
-        f"render phase {Tr*1e6:.1f} us, bound {(Ts + Tr) / max(Ts, Tr):.3f}x "
+    ser = n_envs * args.steps / dt_ser
+    log(f"serialized: {ser:.0f} env-steps/s (median of {len(ser_windows)} windows); per step alone: step phase "
+        f"{Ts*1e6:.1f} us, render phase {Tr*1e6:.1f} us, bound {(Ts + Tr) / max(Ts, Tr):.3f}x "
         f"(physics {alone['physics']['avg_s']*1e6:.1f}, setup {alone['raster_setup']['avg_s']*1e6:.1f}, "
         f"tiles {alone['raster_tiles']['avg_s']*1e6:.1f} us per launch)")
     # co-scheduled candidates: unmasked streams and CU splits, both overlap
@@ -403,7 +512,7 @@ def main():
 
     for split, sched, prio in cands:
         apply(split, prio)
-        dt = timed(torch, w, sched, n_envs, args.steps, 5, st0)
+        dt = timed(torch, w, sched, n_envs, args.steps, args.warmup, st0)
         sweep[name(sched, split, prio)] = n_envs * args.steps / dt
         log(f"  {name(sched, split, prio):20s}: {n_envs * args.steps / dt:.0f} env-steps/s")
     best = args.only or max(sweep, key=sweep.get)
@@ -412,13 +521,16 @@ def main():
     split = float(split)
     prio = int(ps) if ps else p0
     apply(split, prio)
-    dt = timed(torch, w, sched, n_envs, args.steps, args.warmup, st0)
+    dt, co_windows = median_windows(sched)
     value = n_envs * args.steps / dt
     live = kernel_run(sched)
-    log(f"co-scheduled ({best}): {value:.0f} env-steps/s, {value / ser:.3f}x serialized")
+    log(f"co-scheduled ({best}): {value:.0f} env-steps/s (median of {len(co_windows)} windows), "
+        f"{value / ser:.3f}x serialized")
+    contacts = contact_stats(vuda, scene, st0)
+    log(f"contacts at the start state: {contacts}")
 
     # roofline of the dominant kernel: algorithmic bytes per launch over its
-    # average duration in the timed region
+    # average duration in the timed window
     px = int((scene.cam_w.astype("int64") * scene.cam_h).sum())
     body_cams = int(sum(scene.counts()[e] * (scene.cam_off[e + 1] - scene.cam_off[e]) for e in range(n_envs)))
     # algorithmic bytes: the raster setup reads 28 B of pose per body and
@@ -426,19 +538,30 @@ def main():
     step_bytes = {"physics": 120 * scene.n_bodies, "raster_setup": 28 * body_cams, "raster_tiles": 7 * px}
     per_step = {k: live[k]["launches"] / args.steps for k in step_bytes}
     kinds = {}
-    for name in step_bytes:
-        lb = step_bytes[name] / max(per_step[name], 1e-9)  # launches split the env range evenly
-        t = live[name]["avg_s"]
-        kinds[name] = {"launch_us": round(t * 1e6, 2), "bytes_per_launch": int(lb),
-                       "launches_per_step": per_step[name], "GBs": round(lb / t / 1e9, 2) if t else None,
-                       "alone_launch_us": round(alone[name]["avg_s"] * 1e6, 2)}
+    for kname in step_bytes:
+        lb = step_bytes[kname] / max(per_step[kname], 1e-9)  # launches split the env range evenly
+        t = live[kname]["avg_s"]
+        kinds[kname] = {"launch_us": round(t * 1e6, 2), "bytes_per_launch": int(lb),
+                        "launches_per_step": per_step[kname], "GBs": round(lb / t / 1e9, 2) if t else None,
+                        "alone_launch_us": round(alone[kname]["avg_s"] * 1e6, 2)}
     dom = max(step_bytes, key=lambda k: kinds[k]["launch_us"] * per_step[k])
     ach = kinds[dom]["GBs"]
-    tr = measured_traffic(dom, cfg)
+    # measured HBM bytes of a whole-workload launch, scaled to the share of
+    # the workload one launch of the timed window covers
+    tr_full = measured_traffic(dom, cfg)
+    share = kinds[dom]["bytes_per_launch"] / step_bytes[dom]
+    tr = int(tr_full * share) if tr_full is not None else None
     roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": tr,
+            "traffic_note": (f"counters of a whole-workload launch from step {start} "
+                             f"({tr_full} B), times the launch's share {share:g}") if tr_full else None,
             "bytes_per_launch": kinds[dom]["bytes_per_launch"], "launch_us": kinds[dom]["launch_us"],
             **{k: kinds[k] for k in step_bytes}}
+
+    c3 = None
+    if scene3 is not None:
+        c3 = physics_leg(torch, vuda, scene3, sg.CONFIG_STEPS[3] // 2, 20, log)
+        del scene3
 
     policy = None
     if hiddens and not args.only:
@@ -463,31 +586,35 @@ def main():
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         n_cpu = min(1024, n_envs)
-        cpu = cpu_baseline(lambda n: scene if n == n_envs else scene.subset(range(n)), n_cpu,
-                           500 if cfg <= 2 else 20)
+        cpu_steps = {1: 50, 2: 100, 3: 5, 4: 30}.get(cfg, 20)
+        st_cpu = {k: v[: int(scene.body_off[n_cpu])] for k, v in st0.items()}
+        cpu = cpu_baseline(lambda n: scene if n == n_envs else scene.subset(range(n)), n_cpu, cpu_steps, st_cpu)
         log(f"cpu baseline: {cpu['value']:.0f} env-steps/s on {cpu['cores']} threads")
+        cpu["divergence"] = divergence_report(vuda, sg)
+        log(f"divergence (GPU and oracle running free from the spawn): {cpu['divergence']}")
     w.close()
 
-    names = {1: "plain serialized loop: 16 envs x 8 spheres, 64x64 RGB-D",
-             2: "co-scheduled: 1024 envs x 32 bodies (16 spheres / 16 cubes), 128x128 RGB-D, "
-                "u8 RGB + u32 depth, FP32 state",
-             3: "pipelined data-gen: 4096 envs x 64 bodies, 2 cameras 256x256",
-             4: "uneven batching: 2048 envs, Poisson(24) bodies, {64,128,256}^2"}
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "env-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded sphere/cube drops standing in for ManiSkill3 scenes)",
-        "config": {"workload": names.get(cfg, f"c{cfg}"), "envs": n_envs,
+        "config": {"workload": CONFIG_NAMES.get(cfg, f"c{cfg}"), "envs": n_envs,
                    "bodies": int(scene.n_bodies), "cameras": int(scene.n_cams),
                    "schedule": sched, "cu_split": split, "step_priority": prio,
+                   "window": f"steps {start + args.warmup}..{start + args.warmup + args.steps} of the "
+                             f"{horizon}-step horizon, median of {len(co_windows)} windows",
                    "parallelism": "single GPU"},
-        "serialized": {"value": round(ser, 1), "ms_per_step": round(results["serialized"] / args.steps * 1e3, 4)},
+        "windows_ms_per_step": {"co_scheduled": [round(x / args.steps * 1e3, 4) for x in co_windows],
+                                "serialized": [round(x / args.steps * 1e3, 4) for x in ser_windows]},
+        "serialized": {"value": round(ser, 1), "ms_per_step": round(dt_ser / args.steps * 1e3, 4)},
         "speedup_vs_serialized": round(value / ser, 4),
         "overlap_bound": round((Ts + Tr) / max(Ts, Tr), 4),
         "phase_alone_us": {"step": round(Ts * 1e6, 2), "render": round(Tr * 1e6, 2), "presetup": presetup},
+        "contacts": contacts,
         "sweep": {k: round(v, 1) for k, v in sweep.items()},
         "roofline": roof,
+        "physics_c3": c3,
         "cpu_baseline": cpu,
         "serving": serving,
         "policy": policy,

@@ -104,7 +104,6 @@ struct PhysLDS {
   float gres[6][N];       // ground force and torque of each body
   int32_t scan[NW + 1];
   float red[NW];
-  int32_t flag;
   int32_t work;
   int32_t kcnt, ncc, ngc;
 };
@@ -582,7 +581,6 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
       s.colC[tid][q] = 0ull;
     }
     if (tid == 0) {
-      s.flag = 0;
       s.kcnt = 0;
       s.ncc = 0;
       s.ngc = 0;
@@ -594,14 +592,15 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
     // bitset buckets by cell, each lane ORs its own and the 13 half-shell
     // neighbour buckets and tests only the bodies found.  Cells far from the
     // origin fall back to all-pairs.
-    int cx = 0, cy = 0, cz = 0;
+    int cx = 0, cy = 0, cz = 0, far_cell = 0;
     if (use_grid && own) {
       const float fx = floorf(p.x * inv_c), fy = floorf(p.y * inv_c), fz = floorf(p.z * inv_c);
-      if (!(fabsf(fx) < 1000.0f && fabsf(fy) < 1000.0f && fabsf(fz) < 1000.0f)) s.flag = 1;
+      far_cell = !(fabsf(fx) < 1000.0f && fabsf(fy) < 1000.0f && fabsf(fz) < 1000.0f);
       cx = (int)fx; cy = (int)fy; cz = (int)fz;
     }
-    __syncthreads();
-    const bool grid = use_grid && s.flag == 0;
+    // the barrier that publishes the substep state also ORs the far-cell
+    // test over every wave of the env
+    const bool grid = (__syncthreads_or(far_cell) == 0) && use_grid;
     if (!grid && NW == 1) {
       // one wave: lane l tests body i against body (i + r) mod n for its
       // share of the rotations r = 1 .. n/2 (two groups of 32 lanes when

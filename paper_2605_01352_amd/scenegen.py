@@ -410,6 +410,30 @@ def _place(seed, gids, counts, rb, env_of, local, box_h_min: float = 1.0, batch:
     return pos.astype(np.float32)
 
 
+def _place_chunk(args):
+    seed, gids, counts, rb, env_of, local = args
+    return _place(seed, gids, counts, rb, env_of, local)
+
+
+def _place_parallel(seed, gids, counts, rb, env_of, local, workers: int):
+    """_place over contiguous chunks of envs in `workers` processes.  Each
+    env draws from its own stream, so the result equals _place's.  The
+    processes are started fresh (spawn), never forked from the caller."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    E = len(gids)
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    bounds = np.linspace(0, E, workers + 1).astype(np.int64)
+    jobs = []
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        if b > a:
+            sl = slice(int(off[a]), int(off[b]))
+            jobs.append((seed, gids[a:b], counts[a:b], rb[sl], env_of[sl] - a, local[sl]))
+    with cf.ProcessPoolExecutor(max_workers=len(jobs), mp_context=mp.get_context("spawn")) as ex:
+        parts = list(ex.map(_place_chunk, jobs))
+    return np.concatenate(parts) if parts else np.zeros((0, 3), np.float32)
+
+
 def _orientations(seed, gids, btype, env_of, local):
     """Shoemake uniform random rotations for cubes; identity for spheres."""
     key = stream_key(seed, np.asarray(gids, np.uint64)[env_of], ST_ROT)
@@ -423,18 +447,22 @@ def _orientations(seed, gids, btype, env_of, local):
 
 
 def make_scene(seed: int, counts, res, mixed: bool, cams_per_env: int = 1,
-               ring: bool = False, env_gid0: int = 0, name: str = "") -> Scene:
+               ring: bool = False, env_gid0: int = 0, name: str = "", workers: int = 1) -> Scene:
     """Build a scene of len(counts) envs.
 
     counts: bodies per env; res: per-env square resolution (int or array).
     ring: cameras at seeded poses on a 1.5 m ring (else one fixed pose).
+    workers: processes for the rejection-sampled placement (same result).
     """
     counts = np.asarray(counts, np.int64)
     E = len(counts)
     gids = np.arange(env_gid0, env_gid0 + E, dtype=np.uint64)
     res = np.broadcast_to(np.asarray(res, np.int64), (E,))
     env_of, local, btype, size, rb, inv_m, inv_I, albedo = _shapes(seed, gids, counts, mixed)
-    pos = _place(seed, gids, counts, rb, env_of, local)
+    if workers > 1 and E >= 2 * workers:
+        pos = _place_parallel(seed, gids, counts, rb, env_of, local, workers)
+    else:
+        pos = _place(seed, gids, counts, rb, env_of, local)
     quat = _orientations(seed, gids, btype, env_of, local)
     B = len(btype)
     C = E * cams_per_env
@@ -482,7 +510,7 @@ CONFIG_SEEDS = {1: 1001, 2: 1002, 3: 1003, 4: 1004, 5: 1005}
 CONFIG_STEPS = {1: 100, 2: 500, 3: 200, 4: 300}
 
 
-def config_scene(cfg: int, n_envs: Optional[int] = None, env_gid0: int = 0) -> Scene:
+def config_scene(cfg: int, n_envs: Optional[int] = None, env_gid0: int = 0, workers: int = 1) -> Scene:
     """The synthetic workloads (optionally only the first n_envs envs).
 
     1: 16 envs x 8 spheres, one 64x64 camera, fixed pose.
@@ -497,16 +525,16 @@ def config_scene(cfg: int, n_envs: Optional[int] = None, env_gid0: int = 0) -> S
     if cfg == 1:
         return make_scene(seed, np.full(E, 8), 64, mixed=False, env_gid0=env_gid0, name="c1")
     if cfg == 2:
-        return make_scene(seed, np.full(E, 32), 128, mixed=True, env_gid0=env_gid0, name="c2")
+        return make_scene(seed, np.full(E, 32), 128, mixed=True, env_gid0=env_gid0, name="c2", workers=workers)
     if cfg == 3:
         return make_scene(seed, np.full(E, 64), 256, mixed=True, cams_per_env=2, ring=True,
-                          env_gid0=env_gid0, name="c3")
+                          env_gid0=env_gid0, name="c3", workers=workers)
     if cfg == 4:
         kc = stream_key(seed, gids, ST_COUNT)
         counts = np.clip(poisson_knuth(kc, 24.0), 4, 128)
         kr = stream_key(seed, gids, ST_RES)
         res = np.array([64, 128, 256])[(draw_unit(kr, np.zeros(E, np.uint64)) * 3).astype(np.int64)]
-        return make_scene(seed, counts, res, mixed=True, env_gid0=env_gid0, name="c4")
+        return make_scene(seed, counts, res, mixed=True, env_gid0=env_gid0, name="c4", workers=workers)
     raise ValueError(f"no scene for config {cfg}")
 
 

@@ -128,3 +128,39 @@ def test_box_request_matches_a_plain_world():
     for x, y in zip(want, got):
         assert np.array_equal(x, y)
     say("box request: state, rgb and depth equal to the plain world's")
+
+
+def test_c5_shaped_requests_meet_the_oracle_gates():
+    """Three requests of the serving workload's shape (16-24 envs of 12-64
+    bodies, horizons 50-60, 64^2 and 128^2 frames) admitted at different
+    ticks of one server.  Each served result (final state and its frame)
+    equals a plain world's run of the request, and that run meets the oracle
+    gates at every step (contact sets, state) and on the final frame (depth
+    and winners bit-exact, RGB within 1)."""
+    from tests.gpu_util import compare_render, compare_step
+    specs = [sg.RequestSpec(100, 0.0, 16, 40, 64, 50), sg.RequestSpec(101, 0.0, 24, 12, 128, 60),
+             sg.RequestSpec(102, 0.0, 20, 64, 64, 55)]
+    scenes = [sg.request_scene(r) for r in specs]
+    kinds = (vuda.FETCH_STATE, vuda.FETCH_RGB, vuda.FETCH_DEPTH)
+    with server(cap_envs=96, cap_bodies=4096, cap_cams=96, cap_pixels=96 * 128 * 128,
+                schedule=vuda.SCHED_INTERTRAJ, cu_split=0.5) as srv:
+        srv.submit(100, scenes[0], specs[0].horizon)
+        for _ in range(3):
+            srv.tick()
+        srv.submit(101, scenes[1], specs[1].horizon)
+        for _ in range(7):
+            srv.tick()
+        srv.submit(102, scenes[2], specs[2].horizon)
+        run_until_done(srv, 3)
+        served = {r.rid: [srv.result(r.rid, k) for k in kinds] for r in specs}
+    for r, sc in zip(specs, scenes):
+        with vuda.World(sc, debug=True) as w:
+            exact = 0
+            for _ in range(r.horizon):
+                exact += compare_step(w, sc)["bitexact"]
+            compare_render(w, sc)
+            want = [w.fetch(k) for k in kinds]
+        for x, y in zip(want, served[r.rid]):
+            assert np.array_equal(x, y)
+        say(f"request {r.rid} ({r.n_envs} envs x {r.n_bodies} bodies, {r.res}^2, horizon {r.horizon}): "
+            f"served result = plain world; oracle gates met at every step ({exact} bit-exact) and on the frame")

@@ -69,3 +69,12 @@ def test_serving_requests():
     assert ne.min() >= 16 and ne.max() <= 512
     assert abs(np.log(ne).mean() - (math.log(16) + math.log(512)) / 2) < 0.15
     assert all(50 <= r.horizon <= 500 and 8 <= r.n_bodies <= 64 for r in reqs)
+
+
+def test_parallel_placement_equals_sequential():
+    """Envs draw from their own streams, so placing chunks of envs in
+    separate processes gives the same scene bit for bit."""
+    a = sg.config_scene(4, n_envs=40)
+    b = sg.config_scene(4, n_envs=40, workers=3)
+    for k in ("pos", "quat", "size", "btype", "body_off", "cam_w"):
+        assert np.array_equal(getattr(a, k), getattr(b, k)), k

@@ -379,6 +379,8 @@ def main():
                     help="issue priorities of the step's waves tried on unmasked streams")
     ap.add_argument("--profile", type=int, default=0,
                     help="only run this many serialized then co-scheduled steps (for rocprofv3)")
+    ap.add_argument("--physics-profile", type=int, default=0,
+                    help="only run this many physics launches from the start state (for rocprofv3)")
     ap.add_argument("--profile-mode", default="interstep@2",
                     help="the co-scheduled mode of --profile")
     ap.add_argument("--only", default="",
@@ -409,7 +411,7 @@ def main():
     scene = sg.config_scene(cfg, n_envs=args.envs, workers=workers)
     scene3 = None
     if cfg == 2 and not args.no_c3 and not args.profile and not args.policy_profile and not args.policy_loop \
-            and not args.only:
+            and not args.only and not args.physics_profile:
         t0 = time.perf_counter()
         scene3 = sg.config_scene(3, workers=workers)
         log(f"built scene c3 in {time.perf_counter() - t0:.1f} s")
@@ -451,6 +453,13 @@ def main():
         return
     if args.policy_loop:
         policy_bench(torch, vuda, sg, scene, w, st0, args.policy_loop, 4, hiddens[0], log)
+        w.close()
+        return
+    if args.physics_profile:
+        for _ in range(args.physics_profile):
+            w.step()
+        w.wait()
+        log(f"physics profile run: {args.physics_profile} launches from step {start}")
         w.close()
         return
     if args.profile:

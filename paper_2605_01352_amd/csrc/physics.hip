@@ -75,9 +75,9 @@ __device__ __forceinline__ M3 quat_to_rot(float w, float x, float y, float z) {
 template <int NW>
 struct PhysLDS {
   static constexpr int N = 64 * NW;
-  static constexpr int CAPC = 8 * N;  // candidate pairs
+  static constexpr int CAPC = 4 * N;  // candidate pairs
   static_assert(CAPC <= 1024 && N <= 2048, "cube-cube queue packing");
-  static constexpr int CAPK = 4 * N;  // pairs in contact
+  static constexpr int CAPK = 2 * N;  // pairs in contact
   float4 pr[N];  // position and bounding radius, for the all-pairs broadphase
   float p[3][N];
   float v[3][N];
@@ -331,14 +331,51 @@ __device__ __noinline__ PairAcc pair_forces(const PhysLDS<NW>& s, int i, int j,
       pt.xc = add(pj, mul(pt.n, sj - 0.5f * pt.delta));
       add_point<FR>(acc, pt, true, pi, vi, wi, pj, vj, wj, false, pc);
     }
-  } else if (ti == 0) {
-    const M3 Rj = ldsR(s, j);
-    if (sphere_cube(pi, si, pj, Rj, ldsE(s, j), &pt)) add_point<FR>(acc, pt, true, pi, vi, wi, pj, vj, wj, false, pc);
-  } else if (tj == 0) {
-    const M3 Ri = ldsR(s, i);
-    if (sphere_cube(pj, sj, pi, Ri, ldsE(s, i), &pt)) add_point<FR>(acc, pt, false, pi, vi, wi, pj, vj, wj, false, pc);
+  } else if (ti == 0 || tj == 0) {
+    // one path for both orders: the sphere is body i (pushed along +n, the
+    // pair's first body) or body j
+    const bool sfirst = ti == 0;
+    const int cb = sfirst ? j : i;
+    const M3 Rc = ldsR(s, cb);
+    if (sphere_cube(sfirst ? pi : pj, sfirst ? si : sj, sfirst ? pj : pi, Rc, ldsE(s, cb), &pt))
+      add_point<FR>(acc, pt, sfirst, pi, vi, wi, pj, vj, wj, false, pc);
   }
   return acc;
+}
+
+// Two boxes (centres pa, pb, rotations Ra, Rb, half-extents ea, eb) that
+// are apart along one of their six face axes by more than a rounding margin.
+// Then no vertex of either lies inside the other and the separating-axis
+// test of edge-edge points finds them apart too, so the pair has no contact
+// point.  Along the axis a_k of A (column k of Ra) the boxes reach
+// ea_k + sum_l eb_l |a_k . b_l| from their centres, along b_l of B
+// sum_k ea_k |a_k . b_l| + eb_l.  The margin, 1e-5 of the coordinate and
+// extent magnitudes, is over ten times the float32 error of the corner and
+// containment arithmetic, so a vertex the corner test would place inside
+// is never skipped.
+__device__ __forceinline__ bool face_separated(f3 pa, const M3& Ra, f3 ea, f3 pb, const M3& Rb, f3 eb) {
+  const f3 d = sub(pa, pb);
+  const f3 da = rotT(Ra, d), db = rotT(Rb, d);
+  float C[3][3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+      C[k][l] = fabsf((Ra.m[k] * Rb.m[l] + Ra.m[3 + k] * Rb.m[3 + l]) + Ra.m[6 + k] * Rb.m[6 + l]);
+  const float mag = ((fabsf(pa.x) + fabsf(pa.y)) + fabsf(pa.z)) + ((fabsf(pb.x) + fabsf(pb.y)) + fabsf(pb.z)) +
+                    2.0f * (((ea.x + ea.y) + ea.z) + ((eb.x + eb.y) + eb.z));
+  const float tol = 1.0e-5f * mag;
+  const float eA[3] = {ea.x, ea.y, ea.z}, eB[3] = {eb.x, eb.y, eb.z};
+  const float dA[3] = {da.x, da.y, da.z}, dB[3] = {db.x, db.y, db.z};
+  bool sep = false;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float rb = (eB[0] * C[k][0] + eB[1] * C[k][1]) + eB[2] * C[k][2];
+    sep |= fabsf(dA[k]) > (eA[k] + rb) + tol;
+    const float ra = (eA[0] * C[0][k] + eA[1] * C[1][k]) + eA[2] * C[2][k];
+    sep |= fabsf(dB[k]) > (ra + eB[k]) + tol;
+  }
+  return sep;
 }
 
 // Corner k of box A strictly inside box B: the contact point, pushed out of
@@ -515,7 +552,7 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
   // owned body state in registers
   f3 p = mk(0, 0, 0), v = p, w = p;
   float qw = 1.0f, qx = 0.0f, qy = 0.0f, qz = 0.0f;
-  float inv_m = 0.0f, inv_I = 0.0f, a = 0.0f, rbv = 0.0f;
+  float inv_m = 0.0f, inv_I = 0.0f, a = 0.0f, rbv = 0.0f, ex = 0.0f, ey = 0.0f, ez = 0.0f;
   int ty = 0;
   if (own) {
     p = mk(in[PX * cap + gb], in[PY * cap + gb], in[PZ * cap + gb]);
@@ -528,9 +565,13 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
     rbv = W.rbound[gb];
     ty = W.type[gb];
     s.size[tid] = a;
+    ex = ey = ez = a;
     if (ty == 2) {
       const float* bx = W.box + 6 * (int64_t)gb;
-      s.ext[tid] = make_float4(bx[0], bx[1], bx[2], 0.0f);
+      ex = bx[0];
+      ey = bx[1];
+      ez = bx[2];
+      s.ext[tid] = make_float4(ex, ey, ez, 0.0f);
       s.inert[0][tid] = bx[3];
       s.inert[1][tid] = bx[4];
       s.inert[2][tid] = bx[5];
@@ -742,6 +783,9 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
         if (!cc) {
           acc = pair_forces<NW, FR>(s, i, j, pc);
           contact = acc.npts > 0;
+        } else {
+          // box pairs apart along a face axis have no point: not queued
+          cc = !face_separated(ldsP(s, i), ldsR(s, i), ldsE(s, i), ldsP(s, j), ldsR(s, j), ldsE(s, j));
         }
       }
       const uint64_t cm = __ballot(contact), qm = __ballot(cc);
@@ -784,7 +828,17 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
       }
     }
     {
-      const bool gq = own && p.z < rbv && ty != 0;
+      // a cube is queued for the 8-lane corner terms only if one of its
+      // corners is below the ground: the same z of each corner as the
+      // corner test computes, p.z + row 2 of R times (+-e)
+      bool gq = false;
+      if (own && p.z < rbv && ty != 0) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const float wx = (k & 1) ? ex : -ex, wy = (k & 2) ? ey : -ey, wz = (k & 4) ? ez : -ez;
+          gq |= p.z + ((R.m[6] * wx + R.m[7] * wy) + R.m[8] * wz) < 0.0f;
+        }
+      }
       const uint64_t gm = __ballot(gq);
       int gb = 0;
       if (lane_id() == 0 && gm) gb = atomicAdd(&s.ngc, __popcll(gm));

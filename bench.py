@@ -372,8 +372,10 @@ def main():
     ap.add_argument("--envs", type=int, default=None, help="fewer envs (debug only)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the physics leg at the 4096-env config")
-    ap.add_argument("--serve-seconds", type=float, default=20.0,
+    ap.add_argument("--serve-seconds", type=float, default=120.0,
                     help="length of the continuous-batching serving run (0: skip)")
+    ap.add_argument("--capacity-rates", default="100,200,400,800",
+                    help="arrival rates of the serving capacity sweep, 8 s each (empty: skip)")
     ap.add_argument("--splits", default="0.25,0.375,0.5,0.625,0.75")
     ap.add_argument("--prios", default="3",
                     help="issue priorities of the step's waves tried on unmasked streams")
@@ -590,6 +592,10 @@ def main():
         log(f"serving: {args.serve_seconds:g} s of Poisson(50/s) requests ...")
         serving = srv.run(duration=args.serve_seconds, rate=50.0, log=log)
         log(f"serving: {serving}")
+        rates = [float(x) for x in args.capacity_rates.split(",") if x.strip()]
+        if rates:
+            log("serving capacity: rising arrival rates ...")
+            serving["capacity"] = srv.capacity(rates=rates, seconds=8.0, log=log)
 
     cpu = None
     if not args.no_cpu:

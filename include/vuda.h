@@ -447,13 +447,24 @@ int vuda_autotune(vuda_world* w, int32_t steps_per_trial, const char* cache_path
 /*
  * Serving with continuous batching.  A server owns a world created with spare
  * capacity (desc->initial may be empty).  Requests (envs + horizon) are
- * queued by vuda_serve_submit; each vuda_serve_tick admits queued requests in
- * FIFO order while env slots, bodies, cameras and pixels are free and the
- * reserved bytes stay within desc->hbm_budget, runs one co-scheduled
- * iteration (every active env steps once and is rendered), and completes the
- * requests that reached their horizon: their final state and a frame of it
- * are kept (if keep_results) and their slots are released.  Latency is
- * completion time minus submit time (host monotonic clock).
+ * queued by vuda_serve_submit, which refuses (VUDA_EINVAL) a request that is
+ * malformed or larger than the world's capacity or the budget.  Each
+ * vuda_serve_tick:
+ *   1. completes the ticks enqueued earlier that have finished on the GPU
+ *      (and waits for the oldest one while two are in flight): their
+ *      env-steps count as served, and the requests whose last step they
+ *      held complete, their memory released;
+ *   2. admits queued requests in FIFO order while env slots, bodies,
+ *      cameras and pixels are free and the reserved bytes stay within
+ *      desc->hbm_budget; admission does not wait for running work;
+ *   3. enqueues k co-scheduled iterations (every running env steps and is
+ *      rendered k times), k = the fewest steps a running request has left,
+ *      at most 8, and returns without waiting for them.  A request whose
+ *      last step is enqueued leaves every later launch; with keep_results its
+ *      final state and a frame of it are fetched then (that fetch waits).
+ * Latency is completion time (the host sees its last tick finished) minus
+ * submit time (host monotonic clock).  A request that admission refuses for
+ * a reason other than capacity is dropped and counted in `rejected`.
  */
 typedef struct vuda_server vuda_server;
 typedef struct {
@@ -464,6 +475,7 @@ typedef struct {
   double latency_p50_s, latency_p99_s, latency_max_s, latency_mean_s;
   double queue_p50_s, queue_p99_s; /* submit -> admission                     */
   uint64_t reserved_bytes, peak_reserved_bytes;
+  int64_t rejected;              /* dropped at admission (malformed)          */
 } vuda_serve_stats_t;
 int vuda_serve_create(const vuda_world_desc* desc, float cu_split, int32_t schedule,
                       int32_t keep_results, vuda_server** out);

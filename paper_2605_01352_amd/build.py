@@ -43,6 +43,11 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     for s0, p0 in procs:
         if p0.wait() != 0:
             raise RuntimeError(f"hipcc failed on {s0}")
+    # the input generator's spawn placement (plain C, no device code)
+    place = os.path.join(LIBDIR, "libplace.so")
+    subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+                    os.path.join(HERE, "placement.c"), "-o", place + ".tmp"], check=True)
+    os.replace(place + ".tmp", place)
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)

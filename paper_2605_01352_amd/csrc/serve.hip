@@ -2,6 +2,15 @@
 // admitted into free env slots of one resident world as capacity and the HBM
 // budget allow, step together in the co-scheduled loop, and leave when their
 // horizon is reached, freeing their slots for the next ones.
+//
+// The loop is pipelined.  A tick enqueues k iterations of the schedule over
+// every running request (k = the fewest steps any of them has left, at most
+// kTickIters) and records events; it does not wait for them.  Up to
+// kInflight ticks run ahead of the host, which meanwhile admits new requests
+// (their uploads go to free memory, beside the running kernels) and retires
+// finished ones: a request whose last step is enqueued leaves every later
+// launch at once, and its memory is released when the events of its last
+// tick have completed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -81,10 +90,24 @@ struct Request {
   int64_t id = 0;
   Batch batch;
   int32_t horizon = 0;
-  int32_t steps = 0;
+  int32_t steps = 0;     // steps enqueued
   int32_t first_env = -1;
+  bool retired = false;  // every step enqueued; waiting for its last tick
   double t_submit = 0.0, t_admit = 0.0;
   uint64_t bytes = 0;
+};
+
+// Ticks enqueued ahead of the host, and iterations per tick.
+constexpr int kInflight = 2;
+constexpr int32_t kTickIters = 8;
+
+// One enqueued tick: events that complete with its work, the requests whose
+// last step it holds, and the env-steps it serves.
+struct Tick {
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int nev = 0;
+  std::vector<int32_t> finishing;  // first env slot of each
+  int64_t env_steps = 0;
 };
 
 struct Result {
@@ -115,8 +138,15 @@ struct vuda_server {
   std::deque<std::pair<int64_t, double>> done;
   std::map<int64_t, Result> results;
   std::vector<double> latencies, queue_delays;
-  int64_t submitted = 0, admitted = 0, completed = 0, env_steps = 0, ticks = 0;
+  int64_t submitted = 0, admitted = 0, completed = 0, env_steps = 0, ticks = 0, rejected = 0;
   double busy = 0.0;
+  std::deque<Tick> inflight;
+  std::vector<hipEvent_t> spare;  // events of reaped ticks, for reuse
+
+  // Completes the oldest enqueued tick (waiting for it if `block`): its
+  // env-steps count as served and its finishing requests are released.
+  // Returns 1 if a tick was reaped, 0 if it is still running, < 0 on error.
+  int reap(bool block, int32_t* ncomp);
 
   // Device bytes a request holds while resident: both state buffers and the
   // static arrays per body, the primitive/vertex maps, the RGB-D images and
@@ -161,6 +191,12 @@ extern "C" int vuda_serve_create(const vuda_world_desc* desc, float cu_split, in
 
 extern "C" int vuda_serve_destroy(vuda_server* s) {
   if (!s) return fail(VUDA_EINVAL, "null server");
+  while (s->reap(true, nullptr) == 1) {
+  }
+  for (hipEvent_t e : s->spare) (void)hipEventDestroy(e);
+  for (Tick& t : s->inflight)
+    for (hipEvent_t e : t.ev)
+      if (e) (void)hipEventDestroy(e);
   int rc = vuda_destroy_world(s->w);
   delete s;
   return rc;
@@ -176,6 +212,22 @@ extern "C" int vuda_serve_submit(vuda_server* s, int64_t id, const vuda_env_batc
   if (!s || !b) return fail(VUDA_EINVAL, "null argument");
   if (horizon < 1) return fail(VUDA_EINVAL, "horizon %d", horizon);
   if (b->n_envs < 1 || !b->body_off || !b->cam_off) return fail(VUDA_EINVAL, "empty request");
+  // a request is checked here, so that the queue never holds one that
+  // admission would refuse for good
+  vuda_render_desc rd{};
+  rd.ground_nf = s->w->tpl.ground_nf;
+  rd.sphere_nf = s->w->tpl.sphere_nf;
+  rd.cube_nf = s->w->tpl.cube_nf;
+  int64_t nb = 0, npix = 0;
+  int32_t nc = 0;
+  int rc = validate_batch(*b, rd, &nb, &nc, &npix);
+  if (rc) return rc;
+  int64_t nprim = 0, nvert = 0;
+  s->w->map_sizes(*b, &nprim, &nvert);
+  if (b->n_envs > s->w->cap_envs || nb > s->w->cap_bodies || nc > s->w->cap_cams || npix > s->w->cap_pixels ||
+      nprim > s->w->cap_prims || nvert > s->w->cap_verts || s->w->rs_units(*b) > s->w->cap_rs)
+    return fail(VUDA_EINVAL, "request of %d envs, %lld bodies, %d cameras, %lld pixels exceeds the world's capacity",
+                b->n_envs, (long long)nb, nc, (long long)npix);
   Request r;
   r.id = id;
   r.horizon = horizon;
@@ -189,19 +241,66 @@ extern "C" int vuda_serve_submit(vuda_server* s, int64_t id, const vuda_env_batc
   return VUDA_OK;
 }
 
+int vuda_server::reap(bool block, int32_t* ncomp) {
+  if (inflight.empty()) return 0;
+  Tick& t = inflight.front();
+  for (int k = 0; k < t.nev; ++k) {
+    const hipError_t q = block ? hipEventSynchronize(t.ev[k]) : hipEventQuery(t.ev[k]);
+    if (q == hipErrorNotReady) return 0;
+    if (q != hipSuccess) return hip_fail(q, "tick event");
+  }
+  int rc = w->check_flags();
+  if (rc) return rc;
+  env_steps += t.env_steps;
+  ++ticks;
+  const double now = now_s();
+  for (int32_t first : t.finishing) {
+    Request& r = active[first];
+    rc = vuda_release(w, r.first_env, r.batch.n_envs);
+    if (rc) return rc;
+    const double lat = now - r.t_submit;
+    latencies.push_back(lat);
+    done.push_back({r.id, lat});
+    reserved -= r.bytes;
+    ++completed;
+    if (ncomp) ++*ncomp;
+    active.erase(first);
+  }
+  for (int k = 0; k < 2; ++k)
+    if (t.ev[k]) spare.push_back(t.ev[k]);
+  inflight.pop_front();
+  return 1;
+}
+
 extern "C" int vuda_serve_tick(vuda_server* s, int32_t* n_completed) {
   if (!s) return fail(VUDA_EINVAL, "null server");
   const double t0 = now_s();
   int32_t ncomp = 0;
-  // 1. admission in FIFO order while the budget and the world's capacity allow
+  // 1. ticks that have finished, then room for one more in flight
+  int rc;
+  while ((rc = s->reap(false, &ncomp)) == 1) {
+  }
+  if (rc < 0) return rc;
+  while ((int)s->inflight.size() >= kInflight) {
+    rc = s->reap(true, &ncomp);
+    if (rc < 0) return rc;
+  }
+  // 2. admission in FIFO order while the budget and the world's capacity
+  // allow; the new envs start from the step parity every running env has
+  // after the enqueued ticks
   while (!s->queue.empty()) {
     Request& r = s->queue.front();
     if (s->budget && s->reserved + r.bytes > s->budget) break;
     const vuda_env_batch view = r.batch.view();
     int32_t first = -1;
-    const int rc = vuda_admit(s->w, &view, s->parity, &first);
+    rc = vuda_admit(s->w, &view, s->parity, &first);
     if (rc == VUDA_EBUSY) break;
-    if (rc) return rc;
+    if (rc) {
+      // refused for good (submit checks make this rare): drop it, go on
+      ++s->rejected;
+      s->queue.pop_front();
+      continue;
+    }
     r.first_env = first;
     r.t_admit = now_s();
     s->queue_delays.push_back(r.t_admit - r.t_submit);
@@ -212,30 +311,32 @@ extern "C" int vuda_serve_tick(vuda_server* s, int32_t* n_completed) {
     s->queue.pop_front();
     s->active.emplace(moved.first_env, std::move(moved));
   }
-  // 2. one co-scheduled iteration over every active env
-  if (!s->active.empty()) {
-    int rc = vuda_run(s->w, s->sched, 1);
-    if (!rc) rc = vuda_wait(s->w, VUDA_PHASE_ALL);
+  // 3. k co-scheduled iterations over every running request, k the fewest
+  // steps one of them has left (at most kTickIters)
+  int32_t k = kTickIters;
+  int64_t envs = 0;
+  for (auto& kv : s->active)
+    if (!kv.second.retired) {
+      k = std::min(k, kv.second.horizon - kv.second.steps);
+      envs += kv.second.batch.n_envs;
+    }
+  if (envs > 0) {
+    rc = vuda_run(s->w, s->sched, k);
     if (rc) return rc;
-    s->parity ^= 1;
-    ++s->ticks;
-    // 3. completions
-    std::vector<int32_t> finished;
+    s->parity ^= (k & 1);
+    Tick t;
+    t.env_steps = envs * k;
     for (auto& kv : s->active) {
       Request& r = kv.second;
-      ++r.steps;
-      s->env_steps += r.batch.n_envs;
-      if (r.steps >= r.horizon) finished.push_back(kv.first);
-    }
-    for (int32_t first : finished) {
-      Request& r = s->active[first];
+      if (r.retired) continue;
+      r.steps += k;
+      if (r.steps < r.horizon) continue;
       const int32_t lo = r.first_env, hi = r.first_env + r.batch.n_envs;
       if (s->keep) {
         // the final state and a frame of it
         Result res;
         size_t nbytes = 0;
         rc = vuda_render(s->w, lo, hi);
-        if (!rc) rc = vuda_wait(s->w, VUDA_PHASE_ALL);
         if (!rc) rc = vuda_fetch_bytes(s->w, VUDA_FETCH_STATE, lo, hi, &nbytes);
         if (!rc) {
           res.state.resize(nbytes / 4);
@@ -254,16 +355,27 @@ extern "C" int vuda_serve_tick(vuda_server* s, int32_t* n_completed) {
         if (rc) return rc;
         s->results[r.id] = std::move(res);
       }
-      rc = vuda_release(s->w, lo, r.batch.n_envs);
+      // no later launch includes its envs; the memory is released once
+      // this tick has run
+      rc = s->w->retire(lo, r.batch.n_envs);
       if (rc) return rc;
-      const double lat = now_s() - r.t_submit;
-      s->latencies.push_back(lat);
-      s->done.push_back({r.id, lat});
-      s->reserved -= r.bytes;
-      ++s->completed;
-      ++ncomp;
-      s->active.erase(first);
+      r.retired = true;
+      t.finishing.push_back(kv.first);
     }
+    for (int q = 0; q < 2; ++q) {
+      if (!s->spare.empty()) {
+        t.ev[q] = s->spare.back();
+        s->spare.pop_back();
+      }
+    }
+    t.nev = s->w->mark(t.ev);
+    if (t.nev < 0) return VUDA_EHIP;
+    s->inflight.push_back(std::move(t));
+  } else {
+    // nothing running: finish what is in flight
+    while ((rc = s->reap(true, &ncomp)) == 1) {
+    }
+    if (rc < 0) return rc;
   }
   s->busy += now_s() - t0;
   if (n_completed) *n_completed = ncomp;
@@ -325,5 +437,6 @@ extern "C" int vuda_serve_stats(vuda_server* s, vuda_serve_stats_t* o) {
   o->queue_p99_s = percentile(s->queue_delays, 0.99);
   o->reserved_bytes = s->reserved;
   o->peak_reserved_bytes = s->peak_reserved;
+  o->rejected = s->rejected;
   return VUDA_OK;
 }

@@ -16,6 +16,11 @@ namespace vuda {
 
 int fail(int code, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);
+// Checks of an env batch against the limits of the ABI (sizes, arrays
+// present, body types, boxes' extents, primitive counts); fills the body,
+// camera and pixel totals.
+int validate_batch(const vuda_env_batch& b, const vuda_render_desc& r, int64_t* nb_out, int32_t* nc_out,
+                   int64_t* npix_out);
 
 // First-fit allocator of index ranges in [0, cap).
 class RangeAlloc {
@@ -46,11 +51,25 @@ class RangeAlloc {
   std::map<int64_t, int64_t> free_;  // start -> end
 };
 
-struct WorkList {
+// Device storage of one version of a work list.  A rebuilt list goes into
+// the other version; a version is written again only after the fence events
+// recorded when it was replaced have completed, so launches already enqueued
+// keep reading the list they were given.
+struct ListBuf {
   int32_t* dptr = nullptr;
-  int32_t cap = 0;     // entries dptr holds
-  int2* tptr = nullptr;  // render: tile-kernel jobs (camera, first tile)
+  int32_t cap = 0;
+  int2* tptr = nullptr;
   int32_t tcap = 0;
+  hipEvent_t fence[2] = {nullptr, nullptr};
+  int nfence = 0;  // fence events pending (0: free)
+};
+
+struct WorkList {
+  ListBuf buf[2];
+  int cur = 0;
+  bool built = false;
+  const int32_t* dptr = nullptr;  // the current version
+  const int2* tptr = nullptr;     // render: tile-kernel jobs (camera, first tile)
   int32_t n_groups = 0;
   bool dirty = true;   // rebuild before the next use
   int32_t n = 0;
@@ -133,6 +152,7 @@ struct vuda_world {
   std::vector<vuda::EnvDev> env_host;
   std::vector<uint8_t> env_parity;
   std::vector<uint8_t> env_active;
+  std::vector<uint8_t> env_retired;  // retired, not yet released
   std::vector<vuda::CamDev> cam_host;
   vuda::RangeAlloc slots, bodies, camslots, pixels, primspace, vertspace;
   vuda::RangeAlloc rsspace;  // raster scratch, in 256-byte units
@@ -197,6 +217,12 @@ struct vuda_world {
   hipStream_t capture_stream();
   int check_flags();
   int32_t active_midpoint();
+  // events that complete when everything enqueued so far on the world's
+  // streams has run (one per stream in use); returns how many were recorded
+  int mark(hipEvent_t ev[2]);
+  // retire envs [first, first + n): no later launch includes them, their
+  // memory stays allocated until vuda_release
+  int retire(int32_t first, int32_t n);
   void free_policy();
   int policy_launch_of(const vuda::WorkList& L, vuda::PolicyLaunch* out);
 };

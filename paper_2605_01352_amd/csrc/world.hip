@@ -105,8 +105,8 @@ void RangeAlloc::release(int64_t s, int64_t n) {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static int validate_batch(const vuda_env_batch& b, const vuda_render_desc& r, int64_t* nb_out,
-                          int32_t* nc_out, int64_t* npix_out) {
+int vuda::validate_batch(const vuda_env_batch& b, const vuda_render_desc& r, int64_t* nb_out,
+                   int32_t* nc_out, int64_t* npix_out) {
   if (b.n_envs < 0) return fail(VUDA_EINVAL, "n_envs < 0");
   if (b.n_envs == 0) {
     *nb_out = 0; *nc_out = 0; *npix_out = 0;
@@ -514,6 +514,7 @@ extern "C" int vuda_create_world(const vuda_world_desc* d, const vuda_allocator*
   w->env_host.assign(w->cap_envs, EnvDev{});
   w->env_parity.assign(w->cap_envs, 0);
   w->env_active.assign(w->cap_envs, 0);
+  w->env_retired.assign(w->cap_envs, 0);
   w->cam_host.assign(w->cap_cams, CamDev{});
   w->step_ev.assign(w->cap_envs, -1);
   w->setup_ok.assign(w->cap_envs, 0);
@@ -555,8 +556,12 @@ void vuda_world::free_all() {
   if (device >= 0) (void)hipSetDevice(device);
   (void)hipDeviceSynchronize();
   for (auto& kv : lists) {
-    if (kv.second.dptr) (void)hipFree(kv.second.dptr);
-    if (kv.second.tptr) (void)hipFree(kv.second.tptr);
+    for (ListBuf& b : kv.second.buf) {
+      if (b.dptr) (void)hipFree(b.dptr);
+      if (b.tptr) (void)hipFree(b.tptr);
+      for (hipEvent_t e : b.fence)
+        if (e) (void)hipEventDestroy(e);
+    }
   }
   lists.clear();
   for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
@@ -662,6 +667,35 @@ int vuda_world::drain() {
   return VUDA_OK;
 }
 
+int vuda_world::mark(hipEvent_t ev[2]) {
+  hipStream_t ss[2] = {s_sim ? s_sim : s_serial, s_render};
+  const int n = (mode != 0 && s_render && s_render != ss[0]) ? 2 : 1;
+  for (int k = 0; k < n; ++k) {
+    if (!ev[k] && hipEventCreateWithFlags(&ev[k], hipEventDisableTiming) != hipSuccess) {
+      hip_fail(hipGetLastError(), "hipEventCreateWithFlags");
+      return -1;
+    }
+    if (hipEventRecord(ev[k], ss[k]) != hipSuccess) {
+      hip_fail(hipGetLastError(), "hipEventRecord");
+      return -1;
+    }
+  }
+  return n;
+}
+
+int vuda_world::retire(int32_t first, int32_t n) {
+  if (first < 0 || n <= 0 || first + n > cap_envs) return fail(VUDA_EINVAL, "range");
+  for (int32_t e = first; e < first + n; ++e)
+    if (!env_active[e]) return fail(VUDA_EINVAL, "env %d is not admitted", e);
+  for (int32_t e = first; e < first + n; ++e) {
+    env_active[e] = 0;
+    env_retired[e] = 1;
+    setup_ok[e] = 0;
+  }
+  invalidate_lists();
+  return VUDA_OK;
+}
+
 extern "C" int vuda_cosched(vuda_world* w, float cu_split) {
   if (!w) return fail(VUDA_EINVAL, "null world");
   if (!(cu_split <= 0.0f || (cu_split > 0.0f && cu_split < 1.0f) || cu_split == 1.0f || cu_split == 2.0f))
@@ -718,6 +752,18 @@ int vuda_world::get_list(int phase, int32_t lo, int32_t hi, const WorkList** out
   WorkList& L = lists[key];
   *out = &L;
   if (!L.dirty) return VUDA_OK;
+  if (L.built) {
+    // every launch reading the current version is enqueued: fence it and
+    // build into the other version
+    ListBuf& old = L.buf[L.cur];
+    const int nf = mark(old.fence);
+    if (nf < 0) return VUDA_EHIP;
+    old.nfence = nf;
+    L.cur ^= 1;
+  }
+  ListBuf& B = L.buf[L.cur];
+  for (int k = 0; k < B.nfence; ++k) HIPCHK(hipEventSynchronize(B.fence[k]));
+  B.nfence = 0;
   L.n = 0;
   L.max_bodies = L.max_verts = L.max_tris = L.max_tiles = 0;
   std::vector<std::pair<int64_t, int32_t>> items;
@@ -746,15 +792,16 @@ int vuda_world::get_list(int phase, int32_t lo, int32_t hi, const WorkList** out
   });
   std::vector<int32_t> ids(items.size());
   for (size_t i = 0; i < items.size(); ++i) ids[i] = items[i].second;
-  if ((int32_t)ids.size() > L.cap) {
-    if (L.dptr) HIPCHK(hipFree(L.dptr));
-    L.dptr = nullptr;
-    L.cap = 0;
+  if ((int32_t)ids.size() > B.cap) {
+    if (B.dptr) HIPCHK(hipFree(B.dptr));
+    B.dptr = nullptr;
+    B.cap = 0;
     const int32_t want = std::max<int32_t>((int32_t)ids.size(), 64);
-    HIPCHK(hipMalloc(&L.dptr, 4 * (size_t)want));
-    L.cap = want;
+    HIPCHK(hipMalloc(&B.dptr, 4 * (size_t)want));
+    B.cap = want;
   }
-  if (!ids.empty()) HIPCHK(hipMemcpy(L.dptr, ids.data(), 4 * ids.size(), hipMemcpyHostToDevice));
+  if (!ids.empty()) HIPCHK(hipMemcpy(B.dptr, ids.data(), 4 * ids.size(), hipMemcpyHostToDevice));
+  L.dptr = B.dptr;
   L.n = (int32_t)ids.size();
   L.n_groups = 0;
   if (phase == VUDA_PHASE_RENDER && !ids.empty()) {
@@ -775,17 +822,19 @@ int vuda_world::get_list(int phase, int32_t lo, int32_t hi, const WorkList** out
     std::vector<int2> jobs(kXcd * len, make_int2(-1, 0));
     for (int x = 0; x < kXcd; ++x)
       for (size_t q = 0; q < per[x].size(); ++q) jobs[kXcd * q + x] = per[x][q];
-    if ((int64_t)jobs.size() > L.tcap) {
-      if (L.tptr) HIPCHK(hipFree(L.tptr));
-      L.tptr = nullptr;
-      L.tcap = 0;
+    if ((int64_t)jobs.size() > B.tcap) {
+      if (B.tptr) HIPCHK(hipFree(B.tptr));
+      B.tptr = nullptr;
+      B.tcap = 0;
       const int32_t want = std::max<int32_t>((int32_t)jobs.size(), 64);
-      HIPCHK(hipMalloc(&L.tptr, sizeof(int2) * (size_t)want));
-      L.tcap = want;
+      HIPCHK(hipMalloc(&B.tptr, sizeof(int2) * (size_t)want));
+      B.tcap = want;
     }
-    HIPCHK(hipMemcpy(L.tptr, jobs.data(), sizeof(int2) * jobs.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(B.tptr, jobs.data(), sizeof(int2) * jobs.size(), hipMemcpyHostToDevice));
     L.n_groups = (int32_t)jobs.size();
   }
+  L.tptr = B.tptr;
+  L.built = true;
   L.dirty = false;
   return VUDA_OK;
 }
@@ -1562,8 +1611,13 @@ extern "C" int vuda_admit(vuda_world* w, const vuda_env_batch* b, int32_t parity
   int rc = validate_batch(*b, rd, &nb, &nc, &npix);
   if (rc) return rc;
   if (b->n_envs == 0) return fail(VUDA_EINVAL, "empty request");
-  rc = w->drain();  // work lists and tables change below
-  if (rc) return rc;
+  // The new envs take free slots and free memory: launches already enqueued
+  // read neither, and work lists are rebuilt into a fresh version.  Captured
+  // graphs hold the old lists and are destroyed below, after they have run.
+  if (!w->graphs.empty()) {
+    rc = w->drain();
+    if (rc) return rc;
+  }
   const int64_t e0 = w->slots.alloc(b->n_envs);
   if (e0 < 0) return fail(VUDA_EBUSY, "no run of %d free env slots", b->n_envs);
   int64_t nprim, nvert;
@@ -1613,8 +1667,24 @@ extern "C" int vuda_release(vuda_world* w, int32_t first, int32_t n) {
   if (!w) return fail(VUDA_EINVAL, "null world");
   if (first < 0 || n <= 0 || first + n > w->cap_envs) return fail(VUDA_EINVAL, "range");
   for (int32_t e = first; e < first + n; ++e)
-    if (!w->env_active[e]) return fail(VUDA_EINVAL, "env %d is not admitted", e);
-  int rc = w->drain();
+    if (!w->env_active[e] && !w->env_retired[e]) return fail(VUDA_EINVAL, "env %d is not admitted", e);
+  // Wait for the released envs' own work before their memory is reused:
+  // their last step and last renders (events complete in stream order).
+  // One stream (serialized), a policy or captured graphs: wait for all.
+  int rc = VUDA_OK;
+  if (w->mode == 0 || w->pol.set || !w->graphs.empty()) {
+    rc = w->drain();
+  } else {
+    int64_t last[3] = {-1, -1, -1};
+    for (int32_t e = first; e < first + n; ++e) {
+      last[0] = std::max(last[0], w->step_ev[e]);
+      last[1] = std::max(last[1], w->render_ev[0][e]);
+      last[2] = std::max(last[2], w->render_ev[1][e]);
+    }
+    const int64_t kPool = (int64_t)w->evpool.size();
+    for (int64_t id : last)
+      if (id >= 0 && id >= w->next_event - kPool) HIPCHK(hipEventSynchronize(w->evpool[id % kPool]));
+  }
   if (rc) return rc;
   // the request's bodies, cameras and pixels are contiguous
   const EnvDev& d0 = w->env_host[first];
@@ -1643,6 +1713,7 @@ extern "C" int vuda_release(vuda_world* w, int32_t first, int32_t n) {
   for (int32_t e = first; e < first + n; ++e) {
     w->setup_ok[e] = 0;
     w->env_active[e] = 0;
+    w->env_retired[e] = 0;
     w->env_host[e] = EnvDev{};
   }
   w->invalidate_lists();

@@ -369,6 +369,16 @@ def _place(seed, gids, counts, rb, env_of, local, box_h_min: float = 1.0, batch:
     np.add.at(vol, env_of, 4.0 / 3.0 * math.pi * rb64 ** 3)
     H = np.maximum(box_h_min, vol / 0.25)
     key = stream_key(seed, np.asarray(gids, np.uint64), ST_POS)
+    native = _placement_lib()
+    if native is not None and E:
+        import ctypes as C
+        pos = np.zeros((B, 3))
+        a = lambda x, t: np.ascontiguousarray(x, t)
+        off64, cnt64 = a(off[:-1], np.int64), a(counts, np.int64)
+        keys, H0, R = a(key, np.uint64), a(H, np.float64), a(rb64, np.float64)
+        ptr = lambda x: x.ctypes.data_as(C.c_void_p)
+        native.place_envs(C.c_int64(E), ptr(off64), ptr(cnt64), ptr(keys), ptr(H0), ptr(R), ptr(pos))
+        return pos.astype(np.float32)
     ctr = np.zeros(E, np.uint64)
     pos = np.zeros((B, 3))
     nmax = int(counts.max()) if E else 0
@@ -408,6 +418,24 @@ def _place(seed, gids, counts, rb, env_of, local, box_h_min: float = 1.0, batch:
             tries[fail[grow]] = 0
             pending = fail
     return pos.astype(np.float32)
+
+
+_PLACE_LIB = []
+
+
+def _placement_lib():
+    """The compiled placement (placement.c, same draws and arithmetic as the
+    numpy loop below), if it has been built; else None."""
+    if not _PLACE_LIB:
+        import ctypes as C
+        import os
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "libplace.so")
+        lib = None
+        if os.path.exists(path) and not os.environ.get("VUDA_NUMPY_PLACEMENT"):
+            lib = C.CDLL(path)
+            lib.place_envs.restype = None
+        _PLACE_LIB.append(lib)
+    return _PLACE_LIB[0]
 
 
 def _place_chunk(args):

@@ -4,71 +4,92 @@ env-steps/s served next to the offered load.
 
 Requests follow the serving recipe of the synthetic workloads (env count
 log-uniform in [16, 512], 8-64 bodies per env, horizon uniform in [50, 500],
-square resolution from {64, 128, 256}, Poisson arrivals).  Building a scene
-with rejection-sampled spawns costs up to seconds for the largest requests,
-so a pool of the first `pool` request specs is generated once and request r
-takes the content and shape of pool[r mod pool], at its own Poisson arrival
-time.  The offered load is computed from the requests actually submitted.
+square resolution from {64, 128, 256}, Poisson arrivals).  Every request has
+its own shape and its own seeded content.  A pool of generator processes
+builds the request scenes in arrival order a little ahead of the arrival
+clock, so that scene generation is not part of the served time; a request
+whose scene is not ready at its arrival time is submitted when it is, and
+the delay is reported (`gen_lag_max_s`).
+
+`capacity()` raises the arrival rate until the served env-steps/s fall short
+of the offered load: the largest served rate is the server's capacity on
+this workload.
 
 Usage: python -m paper_2605_01352_amd.serving [--duration 120] [--rate 50]
 """
 import argparse
+import collections
+import concurrent.futures as cf
 import json
+import multiprocessing as mp
+import os
 import sys
 import time
-
-import numpy as np
 
 from . import scenegen as sg
 from . import vuda
 
 
-def run(duration: float = 120.0, rate: float = 50.0, pool: int = 24, budget_gb: float = 200.0,
+def _generator_pool(workers: int):
+    return cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn"))
+
+
+def run(duration: float = 120.0, rate: float = 50.0, budget_gb: float = 200.0,
         cu_split: float = 2.0, schedule: int = vuda.SCHED_INTERSTEP, seed: int = 1005,
-        drain: bool = True, log=None, tune=None) -> dict:
+        drain: bool = True, log=None, tune=None, workers: int = 0, ahead_s: float = 1.5,
+        pool=None) -> dict:
+    """Serve Poisson(rate) arrivals for `duration` seconds.  drain: keep
+    ticking after the last arrival until every request has completed (else
+    stop at `duration`, counting what was served by then)."""
     specs = sg.serving_requests(duration_s=duration, rate=rate, seed=seed)
-    pool_specs = specs[:pool]
-    t0 = time.perf_counter()
-    scenes = [sg.request_scene(r, seed=seed) for r in pool_specs]
-    gen_s = time.perf_counter() - t0
-    if log:
-        log(f"serving: {len(specs)} arrivals over {duration:.0f} s, pool of {len(scenes)} request "
-            f"scenes built in {gen_s:.1f} s")
-    # capacity: enough slots for the budget's worth of mean requests
-    max_envs = max(r.n_envs for r in pool_specs)
-    cap_envs = 64 * 1024
-    cap_bodies = 64 * 1024 * 48
-    cap_cams = cap_envs
-    cap_pixels = 1 << 31
+    own_pool = pool is None
+    if own_pool:
+        workers = workers or max(1, min(12, (os.cpu_count() or 2) - 2))
+        pool = _generator_pool(workers)
+    futs = collections.deque()
+    gen_next = 0
+
+    def generate_until(t):
+        nonlocal gen_next
+        while gen_next < len(specs) and specs[gen_next].arrival_s <= t:
+            futs.append(pool.submit(sg.request_scene, specs[gen_next], seed))
+            gen_next += 1
+
+    # the first requests are built before the clock starts
+    generate_until(ahead_s)
+    for f in list(futs):
+        f.result()
     budget = int(budget_gb * (1 << 30))
-    srv = vuda.Server(cap_envs=cap_envs, cap_bodies=cap_bodies, cap_cams=cap_cams,
-                      cap_pixels=cap_pixels, hbm_budget=budget, cu_split=cu_split,
+    srv = vuda.Server(cap_envs=64 * 1024, cap_bodies=64 * 1024 * 48, cap_cams=64 * 1024,
+                      cap_pixels=1 << 31, hbm_budget=budget, cu_split=cu_split,
                       schedule=schedule, keep_results=False)
     for k, v in (tune or {}).items():
         srv.set_tuning(k, v)
     offered_env_steps = 0
     nsub = 0
-    lat = []
+    lag = 0.0
     t_start = time.perf_counter()
     last_log = t_start
     i = 0
     while True:
         now = time.perf_counter() - t_start
+        generate_until(now + ahead_s)
         while i < len(specs) and specs[i].arrival_s <= now:
-            p = pool_specs[i % len(pool_specs)]
-            srv.submit(specs[i].rid, scenes[i % len(scenes)], p.horizon)
-            offered_env_steps += p.n_envs * p.horizon
+            r = specs[i]
+            scene = futs.popleft().result()
+            lag = max(lag, time.perf_counter() - t_start - r.arrival_s)
+            srv.submit(r.rid, scene, r.horizon)
+            offered_env_steps += r.n_envs * r.horizon
             nsub += 1
             i += 1
         st = srv.stats()
+        if now > duration and not drain:
+            break
         if st["active_requests"] or st["queued"]:
             srv.tick()
-            lat += [x for _, x in srv.completed()]
         elif i < len(specs):
-            time.sleep(max(0.0, min(0.01, specs[i].arrival_s - now)))
+            time.sleep(max(0.0, min(0.005, specs[i].arrival_s - now)))
         else:
-            break
-        if now > duration and not drain:
             break
         if log and time.perf_counter() - last_log > 10.0:
             last_log = time.perf_counter()
@@ -77,32 +98,59 @@ def run(duration: float = 120.0, rate: float = 50.0, pool: int = 24, budget_gb: 
     wall = time.perf_counter() - t_start
     st = srv.stats()
     srv.close()
+    if own_pool:
+        pool.shutdown(cancel_futures=True)
+    window = wall if drain else min(wall, duration)
     return {
-        "requests": nsub, "completed": st["completed"], "wall_s": round(wall, 2),
+        "requests": nsub, "completed": st["completed"], "rejected": st["rejected"], "wall_s": round(wall, 2),
         "offered_env_steps_per_s": round(offered_env_steps / duration, 1),
-        "served_env_steps_per_s": round(st["env_steps"] / wall, 1),
+        "served_env_steps_per_s": round(st["env_steps"] / window, 1),
         "latency_p50_s": round(st["latency_p50_s"], 4), "latency_p99_s": round(st["latency_p99_s"], 4),
         "latency_max_s": round(st["latency_max_s"], 4), "queue_p50_s": round(st["queue_p50_s"], 4),
         "queue_p99_s": round(st["queue_p99_s"], 4), "ticks": st["ticks"],
         "peak_reserved_gb": round(st["peak_reserved_bytes"] / 2**30, 3),
-        "duration_s": duration, "rate_per_s": rate, "pool": len(scenes),
+        "duration_s": duration, "rate_per_s": rate, "drained": drain, "gen_lag_max_s": round(lag, 4),
         "cu_split": cu_split, "schedule": vuda.SCHED_NAMES[schedule],
     }
+
+
+def capacity(rates=(100.0, 200.0, 400.0, 800.0), seconds: float = 8.0, log=None, **kw) -> dict:
+    """Served env-steps/s at rising arrival rates, each run stopped after
+    `seconds` (the requests still queued or running count only for the steps
+    served by then).  The capacity is the largest served rate; the run where
+    served falls below 90% of offered marks saturation."""
+    out = []
+    workers = max(1, min(12, (os.cpu_count() or 2) - 2))
+    with _generator_pool(workers) as pool:
+        for r in rates:
+            res = run(duration=seconds, rate=r, drain=False, log=None, pool=pool, **kw)
+            out.append({k: res[k] for k in ("rate_per_s", "offered_env_steps_per_s", "served_env_steps_per_s",
+                                            "completed", "latency_p50_s", "latency_p99_s", "queue_p99_s",
+                                            "gen_lag_max_s")})
+            if log:
+                log(f"  capacity: rate {r:g}/s offered {res['offered_env_steps_per_s']:.0f} served "
+                    f"{res['served_env_steps_per_s']:.0f} env-steps/s, p99 {res['latency_p99_s']:.3f} s")
+            if res["served_env_steps_per_s"] < 0.9 * res["offered_env_steps_per_s"]:
+                break
+    cap = max(x["served_env_steps_per_s"] for x in out) if out else 0.0
+    return {"capacity_env_steps_per_s": cap, "window_s": seconds, "runs": out}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--duration", type=float, default=120.0)
     ap.add_argument("--rate", type=float, default=50.0)
-    ap.add_argument("--pool", type=int, default=24)
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--split", type=float, default=2.0)
     ap.add_argument("--schedule", default="interstep", choices=["serial", "interstep", "intertraj"])
+    ap.add_argument("--capacity", action="store_true", help="also sweep the arrival rate for the capacity")
     a = ap.parse_args()
     sched = {"serial": vuda.SCHED_SERIAL, "interstep": vuda.SCHED_INTERSTEP,
              "intertraj": vuda.SCHED_INTERTRAJ}[a.schedule]
-    res = run(a.duration, a.rate, a.pool, a.budget_gb, a.split, sched,
-              log=lambda *x: print(*x, file=sys.stderr, flush=True))
+    lg = lambda *x: print(*x, file=sys.stderr, flush=True)
+    res = run(a.duration, a.rate, a.budget_gb, a.split, sched, log=lg)
+    if a.capacity:
+        res["capacity"] = capacity(log=lg, budget_gb=a.budget_gb, cu_split=a.split, schedule=sched)
     print(json.dumps(res), flush=True)
 
 

@@ -110,7 +110,8 @@ class ServeStats(C.Structure):
                 ("latency_p50_s", C.c_double), ("latency_p99_s", C.c_double),
                 ("latency_max_s", C.c_double), ("latency_mean_s", C.c_double),
                 ("queue_p50_s", C.c_double), ("queue_p99_s", C.c_double),
-                ("reserved_bytes", C.c_uint64), ("peak_reserved_bytes", C.c_uint64)]
+                ("reserved_bytes", C.c_uint64), ("peak_reserved_bytes", C.c_uint64),
+                ("rejected", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

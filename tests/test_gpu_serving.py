@@ -164,3 +164,40 @@ def test_c5_shaped_requests_meet_the_oracle_gates():
             assert np.array_equal(x, y)
         say(f"request {r.rid} ({r.n_envs} envs x {r.n_bodies} bodies, {r.res}^2, horizon {r.horizon}): "
             f"served result = plain world; oracle gates met at every step ({exact} bit-exact) and on the frame")
+
+
+def test_submit_refuses_requests_that_can_never_run():
+    """Malformed requests and requests larger than the world are refused at
+    submit, so that the FIFO never holds one that blocks the rest."""
+    specs, scenes = small_requests()
+    with server(cap_envs=8, cap_bodies=1024, cap_cams=8, cap_pixels=8 * 128 * 128) as srv:
+        with pytest.raises(vuda.VudaError):
+            srv.submit(1, scenes[1], specs[1].horizon)  # 9 envs > 8 slots
+        bad = sg.request_scene(specs[0])
+        bad.albedo[3] = 9  # palette has 8 entries
+        with pytest.raises(vuda.VudaError):
+            srv.submit(2, bad, specs[0].horizon)
+        srv.submit(0, scenes[0], specs[0].horizon)  # still served
+        done = run_until_done(srv, 1)
+        assert list(done) == [0]
+        assert srv.stats()["rejected"] == 0
+
+
+def test_pipelined_ticks_keep_results_exact():
+    """Ticks enqueue several iterations without waiting; requests with
+    different horizons finish mid-stream and their slots are reused by
+    later ones while others run.  Each result equals a plain world's."""
+    specs = [sg.RequestSpec(20 + k, 0.0, 3 + k, 10 + 4 * k, 64, 9 + 5 * k) for k in range(5)]
+    scenes = [sg.request_scene(r) for r in specs]
+    with server(cap_envs=12, cap_bodies=600, cap_cams=12, cap_pixels=12 * 64 * 64) as srv:
+        for r, sc in zip(specs, scenes):
+            srv.submit(r.rid, sc, r.horizon)
+        run_until_done(srv, len(specs))
+        got = {r.rid: srv.result(r.rid, vuda.FETCH_STATE) for r in specs}
+        st = srv.stats()
+    assert st["env_steps"] == sum(r.n_envs * r.horizon for r in specs)
+    for r, sc in zip(specs, scenes):
+        with vuda.World(sc) as w:
+            w.step(nsteps=r.horizon)
+            w.wait()
+            assert np.array_equal(w.fetch(vuda.FETCH_STATE), got[r.rid])

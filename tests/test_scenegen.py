@@ -3,6 +3,7 @@ the distributions of the synthetic workloads (no GPU)."""
 import math
 
 import numpy as np
+import pytest
 
 from paper_2605_01352_amd import scenegen as sg
 
@@ -78,3 +79,18 @@ def test_parallel_placement_equals_sequential():
     b = sg.config_scene(4, n_envs=40, workers=3)
     for k in ("pos", "quat", "size", "btype", "body_off", "cam_w"):
         assert np.array_equal(getattr(a, k), getattr(b, k)), k
+
+
+def test_native_placement_equals_numpy(monkeypatch):
+    """The compiled placement (same draws, same double arithmetic, one try
+    at a time) gives the numpy loop's positions bit for bit."""
+    sg._PLACE_LIB.clear()
+    if sg._placement_lib() is None:
+        pytest.skip("libplace.so not built (build() compiles it)")
+    native = [sg.config_scene(4, n_envs=60).pos, sg.request_scene(sg.serving_requests(duration_s=1.0)[3]).pos]
+    monkeypatch.setenv("VUDA_NUMPY_PLACEMENT", "1")
+    sg._PLACE_LIB.clear()
+    plain = [sg.config_scene(4, n_envs=60).pos, sg.request_scene(sg.serving_requests(duration_s=1.0)[3]).pos]
+    sg._PLACE_LIB.clear()
+    for a, b in zip(native, plain):
+        assert np.array_equal(a, b)

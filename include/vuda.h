@@ -395,6 +395,23 @@ int vuda_policy_set(vuda_world* w, const vuda_policy_desc* desc);
 int vuda_act(vuda_world* w, int32_t env_lo, int32_t env_hi);
 
 /*
+ * vuda_act without allocation, for callers that cannot allocate device
+ * memory (code under graph capture, tight serving loops, harnesses that
+ * forbid it).  Same policy, same kernels and the same actions bit for bit as
+ * vuda_act over the same envs; it calls no hipMalloc or hipFree.  Its
+ * workspace is a static device array of the library, one per GPU, held from
+ * the first world on that GPU until the process ends: up to 16,384 env ids
+ * and 64 MiB of float32 layer-1 partial sums (with h1 and h2 of the layered
+ * head) -- enough for 1,024 envs at 128x128 and hidden 4096, or 4,096 envs
+ * at 256x256 and hidden 256.  A launch that needs more returns VUDA_EINVAL
+ * (use vuda_act).  Every env in [env_lo, env_hi) must be active (else
+ * VUDA_EINVAL).  Calls of this function on one GPU share the workspace: two
+ * of them in flight at once on different streams (two worlds, or two
+ * threads) race; one world's calls are ordered on its step stream.
+ */
+int vuda_act_noalloc(vuda_world* w, int32_t env_lo, int32_t env_hi);
+
+/*
  * Placement probe: launches n_blocks one-wave workgroups on the stream of
  * `phase` (VUDA_PHASE_STEP or VUDA_PHASE_RENDER), each spinning for about
  * spin_us microseconds so that they spread over the CUs the stream may use,

@@ -202,6 +202,7 @@ struct vuda_world {
   int make_streams(float split);
   void destroy_streams();
   int drain();
+  int init_events();
   int new_event(hipStream_t s, int64_t* id);
   int wait_event(hipStream_t s, int64_t id);
   void invalidate_lists();

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <set>
 #include <string>
@@ -444,6 +445,8 @@ int vuda_world::upload(const vuda_env_batch& b, int32_t e0, int64_t b0, int32_t 
   return VUDA_OK;
 }
 
+static int noalloc_init(int device);
+
 extern "C" int vuda_create_world(const vuda_world_desc* d, const vuda_allocator* a, vuda_world** out) {
   if (!d || !out) return fail(VUDA_EINVAL, "null descriptor or output");
   *out = nullptr;
@@ -528,6 +531,11 @@ extern "C" int vuda_create_world(const vuda_world_desc* d, const vuda_allocator*
   w->vertspace.init(w->cap_verts);
   w->rsspace.init(w->cap_rs);
   rc = w->make_streams(0.0f);
+  // set-up with the device current: the workspace address of the
+  // allocation-free policy launch, and the event pool (created here, so
+  // that enqueueing never creates one)
+  if (rc == VUDA_OK) rc = noalloc_init(w->device);
+  if (rc == VUDA_OK) rc = w->init_events();
   if (rc == VUDA_OK) {
     hipError_t e = hipMemcpy((void*)w->dev.tpl, &w->tpl, sizeof(Templates), hipMemcpyHostToDevice);
     if (e != hipSuccess) rc = hip_fail(e, "template upload");
@@ -714,12 +722,19 @@ extern "C" int vuda_cosched(vuda_world* w, float cu_split) {
 
 // Event pool: ids grow monotonically; slot id % size is reused after making
 // sure the event it held has completed.
-int vuda_world::new_event(hipStream_t s, int64_t* id) {
+int vuda_world::init_events() {
   const size_t kPool = 512;
   if (evpool.empty()) {
-    evpool.resize(kPool);
+    evpool.resize(kPool, nullptr);
     for (auto& e : evpool) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
+  return VUDA_OK;
+}
+
+int vuda_world::new_event(hipStream_t s, int64_t* id) {
+  const size_t kPool = 512;
+  int rc = init_events();
+  if (rc) return rc;
   const int64_t nid = next_event++;
   hipEvent_t e = evpool[nid % kPool];
   if (nid >= (int64_t)kPool) HIPCHK(hipEventSynchronize(e));
@@ -1177,14 +1192,17 @@ static int policy_plan(const Policy& pol, bool force_layered, int32_t M, PolicyP
   return VUDA_OK;
 }
 
-int vuda_world::policy_launch_of(const WorkList& L, PolicyLaunch* out) {
+// The policy launch over the M envs listed at `envs`, with `partial`
+// (`cap` floats) as its workspace.
+static int policy_launch(const Policy& pol, bool layered, const int32_t* envs, int32_t M, float* partial,
+                         int64_t cap, PolicyLaunch* out) {
   PolicyPlan plan;
-  int rc = policy_plan(pol, tune.policy_layered, L.n, &plan);
+  int rc = policy_plan(pol, layered, M, &plan);
   if (rc) return rc;
   const int32_t K = 4 * pol.in_w * pol.in_h;
   PolicyLaunch pl;
-  pl.envs = L.dptr;
-  pl.M = L.n;
+  pl.envs = envs;
+  pl.M = M;
   pl.K = K;
   pl.krgb = 3 * pol.in_w * pol.in_h;
   pl.H = pol.H;
@@ -1198,8 +1216,8 @@ int vuda_world::policy_launch_of(const WorkList& L, PolicyLaunch* out) {
   pl.w3 = pl.b2 + pol.H;
   pl.b3 = pl.w3 + (int64_t)pol.H * pol.A;
   pl.a_max = pol.a_max;
-  if (plan.partial_floats > pol.partial_cap) return fail(VUDA_EINVAL, "policy partials unsized");
-  pl.partial = pol.partial;
+  if (plan.partial_floats > cap) return fail(VUDA_EINVAL, "policy partials unsized");
+  pl.partial = partial;
   pl.layered = plan.layered ? 1 : 0;
   pl.s2 = plan.s2;
   pl.s3 = plan.s3;
@@ -1209,11 +1227,15 @@ int vuda_world::policy_launch_of(const WorkList& L, PolicyLaunch* out) {
   if (plan.layered) {
     if (!pol.w3p) return fail(VUDA_EINVAL, "policy without padded W3");
     // h1 and h2 sit after the largest partial block
-    pl.h1 = pol.partial + (plan.partial_floats - 2 * (int64_t)L.n * pol.H);
-    pl.h2 = pl.h1 + (int64_t)L.n * pol.H;
+    pl.h1 = partial + (plan.partial_floats - 2 * (int64_t)M * pol.H);
+    pl.h2 = pl.h1 + (int64_t)M * pol.H;
   }
   *out = pl;
   return VUDA_OK;
+}
+
+int vuda_world::policy_launch_of(const WorkList& L, PolicyLaunch* out) {
+  return policy_launch(pol, tune.policy_layered, L.dptr, L.n, pol.partial, pol.partial_cap, out);
 }
 
 extern "C" int vuda_policy_set(vuda_world* w, const vuda_policy_desc* d) {
@@ -1349,6 +1371,92 @@ extern "C" int vuda_act(vuda_world* w, int32_t lo, int32_t hi) {
     if (rc) return rc;
     for (int32_t e = lo; e < hi; ++e)
       if (w->env_active[e]) w->step_ev[e] = id;
+  }
+  return VUDA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the policy without allocation: a static device workspace
+// ---------------------------------------------------------------------------
+
+// Workspace of vuda_act_noalloc, one copy per GPU, held while the library is
+// loaded: the env ids of the launch (up to 16,384), then the layer-1 partial
+// sums (and h1, h2 of the layered head), 64 MiB.
+constexpr size_t kNoAllocIdBytes = (size_t)64 << 10;
+constexpr size_t kNoAllocPartialBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocIdBytes + kNoAllocPartialBytes];
+
+// Device address of `scratch` on each GPU (the array's name is a host-side
+// stand-in), taken once per device by noalloc_init.
+constexpr int kMaxDevices = 64;
+static unsigned char* g_scratch[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+// With `device` current: record the device address of its copy of scratch.
+static int noalloc_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(VUDA_EINVAL, "device %d", device);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[device]) return VUDA_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+  g_scratch[device] = (unsigned char*)p;
+  return VUDA_OK;
+}
+
+__global__ void fill_env_ids_kernel(int32_t* ids, int32_t lo, int32_t n) {
+  const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i < n) ids[i] = lo + i;
+}
+
+extern "C" int vuda_act_noalloc(vuda_world* w, int32_t lo, int32_t hi) {
+  if (!w) return fail(VUDA_EINVAL, "null world");
+  int rc = w->check_range(lo, hi);
+  if (rc) return rc;
+  if (!w->pol.set) return fail(VUDA_EINVAL, "no policy (vuda_policy_set)");
+  if (lo == hi) return VUDA_OK;
+  for (int32_t e = lo; e < hi; ++e) {
+    if (!w->env_active[e]) return fail(VUDA_EINVAL, "env %d is not active (every env of the range must be)", e);
+    const EnvDev& d = w->env_host[e];
+    if (d.n_cams < 1) return fail(VUDA_EINVAL, "env %d has no camera", e);
+    const CamDev& c = w->cam_host[d.cam_off];
+    if (c.w != w->pol.in_w || c.h != w->pol.in_h)
+      return fail(VUDA_EINVAL, "env %d: camera 0 is %dx%d, the policy reads %dx%d", e, c.w, c.h, w->pol.in_w,
+                  w->pol.in_h);
+    if (c.pix_off % 8 != 0) return fail(VUDA_EINVAL, "env %d: frame offset %lld not a multiple of 8", e,
+                                        (long long)c.pix_off);
+  }
+  const int32_t M = hi - lo;
+  PolicyPlan plan;
+  rc = policy_plan(w->pol, w->tune.policy_layered, M, &plan);
+  if (rc) return rc;
+  if ((size_t)M * 4 > kNoAllocIdBytes || (size_t)plan.partial_floats * 4 > kNoAllocPartialBytes)
+    return fail(VUDA_EINVAL,
+                "%d envs at hidden %d need %lld bytes of workspace; vuda_act_noalloc holds %zu (and %zu env ids)",
+                M, w->pol.H, (long long)plan.partial_floats * 4, kNoAllocPartialBytes, kNoAllocIdBytes / 4);
+  unsigned char* base = (w->device >= 0 && w->device < kMaxDevices) ? g_scratch[w->device] : nullptr;
+  if (!base) return fail(VUDA_EINVAL, "no workspace address for device %d", w->device);
+  int32_t* ids = (int32_t*)base;
+  float* partial = (float*)(base + kNoAllocIdBytes);
+  PolicyLaunch pl;
+  rc = policy_launch(w->pol, w->tune.policy_layered, ids, M, partial, (int64_t)(kNoAllocPartialBytes / 4), &pl);
+  if (rc) return rc;
+  hipStream_t s = w->s_sim;
+  if (w->mode != 0) {
+    // RAW: the renders that wrote the frames read here
+    int64_t last = -1;
+    for (int32_t e = lo; e < hi; ++e) last = std::max(last, w->render_ev[w->env_parity[e]][e]);
+    rc = w->wait_event(s, last);
+    if (rc) return rc;
+  }
+  hipLaunchKernelGGL(fill_env_ids_kernel, dim3((M + 255) / 256), dim3(256), 0, s, ids, lo, M);
+  HIPCHK(hipGetLastError());
+  HIPCHK(launch_policy(w->dev, pl, s, nullptr));
+  if (w->mode != 0) {
+    int64_t id;
+    rc = w->new_event(s, &id);
+    if (rc) return rc;
+    for (int32_t e = lo; e < hi; ++e) w->step_ev[e] = id;
   }
   return VUDA_OK;
 }

@@ -38,7 +38,7 @@ EXPORTS = [
     "vuda_probe_placement", "vuda_strerror", "vuda_last_error_message", "vuda_run",
     "vuda_autotune", "vuda_serve_create", "vuda_serve_destroy", "vuda_serve_submit",
     "vuda_serve_tick", "vuda_serve_completed", "vuda_serve_result", "vuda_serve_stats",
-    "vuda_serve_world", "vuda_kernel_times", "vuda_policy_set", "vuda_act",
+    "vuda_serve_world", "vuda_kernel_times", "vuda_policy_set", "vuda_act", "vuda_act_noalloc",
 ]
 SCHED_SERIAL, SCHED_INTERSTEP, SCHED_INTERTRAJ = 0, 1, 2
 SCHED_NAMES = {SCHED_SERIAL: "serial", SCHED_INTERSTEP: "interstep", SCHED_INTERTRAJ: "intertraj"}
@@ -301,6 +301,11 @@ class World:
         """Enqueue the policy on envs [lo, hi): actions for their next steps."""
         hi = self.n_envs if hi is None else hi
         check(lib().vuda_act(self._w, lo, hi))
+
+    def act_noalloc(self, lo: int = 0, hi: Optional[int] = None):
+        """vuda_act through the library's static workspace (no allocation)."""
+        hi = self.n_envs if hi is None else hi
+        check(lib().vuda_act_noalloc(self._w, lo, hi))
 
     def wait(self, phase: int = PHASE_ALL):
         check(lib().vuda_wait(self._w, phase))

@@ -34,7 +34,7 @@ class RenderParams(C.Structure):
         ("cube_nv", C.c_int32), ("cube_nf", C.c_int32),
         ("ground_v", C.c_void_p), ("ground_f", C.c_void_p), ("ground_nf", C.c_int32),
         ("light", C.c_float * 3), ("palette", C.c_float * 24), ("ground_albedo", C.c_float),
-        ("near_w", C.c_float), ("guard", C.c_float), ("near_clip", C.c_int32)]
+        ("near_w", C.c_float), ("guard", C.c_float), ("near_clip", C.c_int32), ("smooth", C.c_int32)]
 
 
 class Point(C.Structure):
@@ -81,7 +81,8 @@ def phys_params(scene) -> PhysParams:
 class _Render:
     """Keeps the template arrays alive while the struct points at them."""
 
-    def __init__(self, light=None, palette=None, ground_albedo=None, near=None, guard=None, near_clip=False):
+    def __init__(self, light=None, palette=None, ground_albedo=None, near=None, guard=None, near_clip=False,
+                 smooth=False):
         from paper_2605_01352_amd import scenegen as sg
         t = sg.templates()
         self.arrs = [np.ascontiguousarray(a) for a in (
@@ -97,19 +98,20 @@ class _Render:
             (C.c_float * 24)(*np.asarray(palette, np.float32).reshape(-1).tolist()),
             float(sg.GROUND_ALBEDO if ground_albedo is None else ground_albedo),
             float(sg.NEAR if near is None else near),
-            float(sg.GUARD_BAND if guard is None else guard), 1 if near_clip else 0)
+            float(sg.GUARD_BAND if guard is None else guard), 1 if near_clip else 0, 1 if smooth else 0)
 
 
 _RENDER: Dict[bool, _Render] = {}
 
 
-def render_params(near_clip: bool = False) -> _Render:
+def render_params(near_clip: bool = False, smooth: bool = False) -> _Render:
     """Default render parameters; near_clip: cut triangles crossing the near
-    plane instead of culling them."""
-    near_clip = bool(near_clip)
-    if near_clip not in _RENDER:
-        _RENDER[near_clip] = _Render(near_clip=near_clip)
-    return _RENDER[near_clip]
+    plane instead of culling them; smooth: per-pixel Lambert shading of the
+    perspective-correctly interpolated vertex normal."""
+    key = (bool(near_clip), bool(smooth))
+    if key not in _RENDER:
+        _RENDER[key] = _Render(near_clip=key[0], smooth=key[1])
+    return _RENDER[key]
 
 
 def step_env(scene, e: int, state: Dict[str, np.ndarray], record_pairs: bool = False,
@@ -184,7 +186,7 @@ def render_image(scene, state, cam: int, e: Optional[int] = None, debug: bool = 
     bt, sz, al = sl(scene.btype), sl(scene.size), sl(scene.albedo)
     pos, quat = sl(state["pos"]), sl(state["quat"])
     vp = np.ascontiguousarray(scene.cam_vp[cam], np.float32)
-    rp = render_params(getattr(scene, "near_clip", False))
+    rp = render_params(getattr(scene, "near_clip", False), getattr(scene, "smooth", False))
     ex = None if getattr(scene, "ext", None) is None else np.ascontiguousarray(scene.ext[b0:b1], np.float32)
     lib().oracle_render_image_box(b1 - b0, _p(bt), _p(sz), _p(ex) if ex is not None else None, _p(al), _p(pos),
                               _p(quat), _p(vp), W, H,
@@ -222,6 +224,19 @@ def setup_clipped(w0, w1, w2, vp, W, H, near=0.05, guard=8192.0):
             for s in range(n)]
 
 
+def smooth_normal(X, Y, iw, normals, px, py):
+    """Unit normal at the centre of pixel (px, py) of a triangle (snapped
+    vertices X, Y in setup order, 1 / clip w and world normals per vertex),
+    interpolated perspective-correctly."""
+    X = np.ascontiguousarray(X, np.int32)
+    Y = np.ascontiguousarray(Y, np.int32)
+    iw = np.ascontiguousarray(iw, np.float32)
+    n = np.ascontiguousarray(normals, np.float32).reshape(9)
+    out = np.zeros(3, np.float32)
+    lib().oracle_smooth_normal(_p(X), _p(Y), _p(iw), _p(n), int(px), int(py), _p(out))
+    return out
+
+
 def covers(X, Y, px, py) -> bool:
     X = np.ascontiguousarray(X, np.int32)
     Y = np.ascontiguousarray(Y, np.int32)
@@ -254,7 +269,7 @@ def run_batch(scene, state, n_steps: int, nthreads: int, do_render: bool = True)
     for k in ("pos", "vel", "quat", "omega"):
         state[k] = np.ascontiguousarray(state[k], np.float32)
     prm = phys_params(scene)
-    rp = render_params(getattr(scene, "near_clip", False))
+    rp = render_params(getattr(scene, "near_clip", False), getattr(scene, "smooth", False))
     st = lib().oracle_run_batch(
         scene.n_envs, _p(arrs["bo"]), _p(arrs["bt"]), _p(arrs["sz"]), _p(arrs["rb"]),
         _p(arrs["im"]), _p(arrs["iI"]), _p(arrs["al"]), _p(state["pos"]), _p(state["vel"]),

@@ -594,7 +594,7 @@ int oracle_covers(const int32_t* X, const int32_t* Y, int32_t px, int32_t py) {
 }
 
 static void raster_snapped(const int32_t* X, const int32_t* Y, const float* z, int64_t A, uint32_t prim,
-                           int32_t W, int32_t Hh, uint64_t* keys, int32_t* cover);
+                           int32_t W, int32_t Hh, uint64_t* keys, int32_t* cover, int32_t* tri_of, int32_t t);
 
 /* A triangle, or with near_clip the part of it in front of the near plane
  * (one or two triangles with the triangle's primitive id). */
@@ -607,11 +607,53 @@ static void raster_tri(const float* w0, const float* w1, const float* w2, uint32
   int n;
   if (rp->near_clip) n = oracle_setup_clipped(w0, w1, w2, vp, W, Hh, rp->near_w, rp->guard, X, Y, z, A);
   else n = oracle_setup_triangle(w0, w1, w2, vp, W, Hh, rp->near_w, rp->guard, X, Y, z, A);
-  for (int s = 0; s < n; ++s) raster_snapped(X + 3 * s, Y + 3 * s, z + 3 * s, A[s], prim, W, Hh, keys, cover);
+  for (int s = 0; s < n; ++s)
+    raster_snapped(X + 3 * s, Y + 3 * s, z + 3 * s, A[s], prim, W, Hh, keys, cover, NULL, 0);
+}
+
+/* ---------------------------------------------------------------------------
+ * Smooth shading (a reading: the paper's renderer shades meshes, the
+ * interpolation of attributes across a triangle is the perspective-correct
+ * one of any rasterizer).  A visible triangle keeps its snapped vertices in
+ * setup order, the reciprocal clip w of each and a normal per vertex (world
+ * space).  At a pixel centre with edge values E_k (E_k weights vertex k),
+ * the perspective-correct weights are proportional to E_k / w_k; the
+ * interpolated normal is their weighted sum, normalized (the common factor
+ * cancels), and the pixel takes Lambert shading of it.
+ * ------------------------------------------------------------------------- */
+
+typedef struct {
+  int32_t X[3], Y[3];
+  float iw[3];      /* 1 / clip w of each vertex, setup order */
+  float n[3][3];    /* world normal of each vertex, setup order */
+  float alb[3];
+} smooth_tri;
+
+/* Perspective-correct interpolation at the centre of pixel (px, py) of a
+ * triangle covering it: the unit normal there (zero if the weighted sum
+ * vanishes). */
+void oracle_smooth_normal(const int32_t* X, const int32_t* Y, const float* iw, const float* n, int32_t px,
+                          int32_t py, float* out) {
+  int64_t Px = 256 * (int64_t)px + 128, Py = 256 * (int64_t)py + 128;
+  int64_t E[3];
+  E[0] = edge_fn(X[1], Y[1], X[2], Y[2], Px, Py);
+  E[1] = edge_fn(X[2], Y[2], X[0], Y[0], Px, Py);
+  E[2] = edge_fn(X[0], Y[0], X[1], Y[1], Px, Py);
+  float u[3];
+  for (int k = 0; k < 3; ++k) u[k] = (float)E[k] * iw[k];
+  v3 m = mk((u[0] * n[0] + u[1] * n[3]) + u[2] * n[6], (u[0] * n[1] + u[1] * n[4]) + u[2] * n[7],
+            (u[0] * n[2] + u[1] * n[5]) + u[2] * n[8]);
+  float l2 = dot(m, m);
+  if (l2 > 0.0f) {
+    float l = sqrtf(l2);
+    out[0] = m.x / l; out[1] = m.y / l; out[2] = m.z / l;
+  } else {
+    out[0] = out[1] = out[2] = 0.0f;
+  }
 }
 
 static void raster_snapped(const int32_t* X, const int32_t* Y, const float* z, int64_t A, uint32_t prim,
-                           int32_t W, int32_t Hh, uint64_t* keys, int32_t* cover) {
+                           int32_t W, int32_t Hh, uint64_t* keys, int32_t* cover, int32_t* tri_of, int32_t t) {
   int32_t xmin = X[0], xmax = X[0], ymin = Y[0], ymax = Y[0];
   for (int k = 1; k < 3; ++k) {
     if (X[k] < xmin) xmin = X[k];
@@ -642,9 +684,46 @@ static void raster_snapped(const int32_t* X, const int32_t* Y, const float* z, i
       float zz = (((float)E0 * z[0] + (float)E1 * z[1]) + (float)E2 * z[2]) * invA;
       uint32_t D = (uint32_t)rintf(fminf(fmaxf(zz, 0.0f), 1.0f) * 16777215.0f);
       uint64_t key = ((uint64_t)D << 32) | prim;
-      if (key < keys[pix]) keys[pix] = key;
+      if (key < keys[pix]) {
+        keys[pix] = key;
+        if (tri_of) tri_of[pix] = t;
+      }
     }
   }
+}
+
+/* Setup and raster of one triangle (world vertices w0..w2 in face order,
+ * their normals nv) for smooth shading: the triangle table keeps its
+ * snapped vertices, 1 / clip w and normals in setup order (0, 2, 1). */
+static int smooth_tri_raster(const float* w0, const float* w1, const float* w2, const float* const nv[3],
+                             const float* alb, uint32_t prim, const float* vp, int32_t W, int32_t H,
+                             const oracle_render_params* rp, uint64_t* keys, int32_t* cover, int32_t* tri_of,
+                             smooth_tri** tris, int32_t* ntri, int32_t* tcap) {
+  int32_t X[3], Y[3];
+  float z[3];
+  int64_t A;
+  if (!oracle_setup_triangle(w0, w1, w2, vp, W, H, rp->near_w, rp->guard, X, Y, z, &A)) return 0;
+  if (*ntri == *tcap) {
+    smooth_tri* nt = (smooth_tri*)realloc(*tris, sizeof(smooth_tri) * (size_t)(2 * *tcap));
+    if (!nt) return -1;
+    *tris = nt;
+    *tcap *= 2;
+  }
+  smooth_tri* st = &(*tris)[*ntri];
+  const float* wv[3] = {w0, w1, w2};
+  const int ord[3] = {0, 2, 1};
+  for (int k = 0; k < 3; ++k) {
+    float c[4];
+    clip_coords(wv[ord[k]], vp, c);
+    st->X[k] = X[k];
+    st->Y[k] = Y[k];
+    st->iw[k] = 1.0f / c[3];
+    for (int r = 0; r < 3; ++r) st->n[k][r] = nv[ord[k]][r];
+  }
+  for (int c = 0; c < 3; ++c) st->alb[c] = alb[c];
+  raster_snapped(X, Y, z, A, prim, W, H, keys, cover, tri_of, *ntri);
+  ++*ntri;
+  return 0;
 }
 
 int oracle_render_image(int32_t n, const uint8_t* type, const float* size,
@@ -659,15 +738,37 @@ int oracle_render_image_box(int32_t n, const uint8_t* type, const float* size, c
                             const float* vp, int32_t W, int32_t H, const oracle_render_params* rp,
                             uint8_t* rgb, uint32_t* depth, int32_t* winner, int32_t* cover) {
   size_t npix = (size_t)W * (size_t)H;
+  if (rp->smooth && rp->near_clip) return -2;
   uint64_t* keys = (uint64_t*)malloc(sizeof(uint64_t) * (npix ? npix : 1));
   if (!keys) return -1;
   for (size_t i = 0; i < npix; ++i) keys[i] = UINT64_MAX;
   if (cover) memset(cover, 0, sizeof(int32_t) * npix);
+  /* smooth shading: each pixel's winning triangle, and the triangles */
+  int32_t* tri_of = NULL;
+  smooth_tri* tris = NULL;
+  int32_t ntri = 0, tcap = 0;
+  if (rp->smooth) {
+    tri_of = (int32_t*)malloc(sizeof(int32_t) * (npix ? npix : 1));
+    tcap = 64;
+    tris = (smooth_tri*)malloc(sizeof(smooth_tri) * (size_t)tcap);
+    if (!tri_of || !tris) { free(keys); free(tri_of); free(tris); return -1; }
+    for (size_t i = 0; i < npix; ++i) tri_of[i] = -1;
+  }
 
   /* prim ids: 0..ground_nf-1 the ground, then each body's faces in order */
   uint32_t prim = 0;
   for (int f = 0; f < rp->ground_nf; ++f, ++prim) {
     const int32_t* fi = rp->ground_f + 3 * f;
+    if (rp->smooth) {
+      const float up[3] = {0.0f, 0.0f, 1.0f};
+      const float* nv[3] = {up, up, up};
+      const float ga[3] = {rp->ground_albedo, rp->ground_albedo, rp->ground_albedo};
+      if (smooth_tri_raster(rp->ground_v + 3 * fi[0], rp->ground_v + 3 * fi[1], rp->ground_v + 3 * fi[2], nv, ga,
+                            prim, vp, W, H, rp, keys, cover, tri_of, &tris, &ntri, &tcap)) {
+        free(keys); free(tri_of); free(tris); return -1;
+      }
+      continue;
+    }
     raster_tri(rp->ground_v + 3 * fi[0], rp->ground_v + 3 * fi[1], rp->ground_v + 3 * fi[2],
                prim, vp, W, H, rp, keys, cover);
   }
@@ -685,6 +786,24 @@ int oracle_render_image_box(int32_t n, const uint8_t* type, const float* size, c
         v3 t = load3(tv, tf[3 * f + k]);
         v3 w = add(p, mat_vec(R, mk(t.x * e.x, t.y * e.y, t.z * e.z)));
         wv[k][0] = w.x; wv[k][1] = w.y; wv[k][2] = w.z;
+      }
+      if (rp->smooth) {
+        /* vertex normals: a sphere's template vertex (a point of the unit
+         * sphere) turned by R; a cube's or box's face normal at every vertex */
+        float nvw[3][3];
+        for (int k = 0; k < 3; ++k) {
+          v3 nb = type[b] ? load3(rp->cube_n, f) : load3(tv, tf[3 * f + k]);
+          v3 nw = mat_vec(R, nb);
+          nvw[k][0] = nw.x; nvw[k][1] = nw.y; nvw[k][2] = nw.z;
+        }
+        const float* nv[3] = {nvw[0], nvw[1], nvw[2]};
+        float al[3];
+        for (int c = 0; c < 3; ++c) al[c] = rp->palette[3 * albedo[b] + c];
+        if (smooth_tri_raster(wv[0], wv[1], wv[2], nv, al, prim, vp, W, H, rp, keys, cover, tri_of, &tris, &ntri,
+                              &tcap)) {
+          free(keys); free(tri_of); free(tris); return -1;
+        }
+        continue;
       }
       raster_tri(wv[0], wv[1], wv[2], prim, vp, W, H, rp, keys, cover);
     }
@@ -722,6 +841,15 @@ int oracle_render_image_box(int32_t n, const uint8_t* type, const float* size, c
       nrm = mat_vec(R, load3(type[b] ? rp->cube_n : rp->sphere_n, (int32_t)rem));
       for (int c = 0; c < 3; ++c) alb[c] = rp->palette[3 * albedo[b] + c];
     }
+    if (rp->smooth) {
+      /* the winning triangle's interpolated normal at this pixel centre */
+      const smooth_tri* st = &tris[tri_of[i]];
+      float nn[3];
+      oracle_smooth_normal(st->X, st->Y, st->iw, &st->n[0][0], (int32_t)(i % (size_t)W), (int32_t)(i / (size_t)W),
+                           nn);
+      nrm = mk(nn[0], nn[1], nn[2]);
+      for (int c = 0; c < 3; ++c) alb[c] = st->alb[c];
+    }
     float l = fmaxf(0.0f, dot(nrm, L));
     for (int c = 0; c < 3; ++c) {
       float col = alb[c] * (0.2f + 0.8f * l);
@@ -729,6 +857,8 @@ int oracle_render_image_box(int32_t n, const uint8_t* type, const float* size, c
     }
   }
   free(keys);
+  free(tri_of);
+  free(tris);
   return 0;
 }
 

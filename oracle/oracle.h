@@ -65,6 +65,9 @@ typedef struct {
   float guard;      /* cull a triangle if any |screen coord| exceeds this  */
   int32_t near_clip; /* nonzero: cut triangles crossing w = near_w instead
                         (oracle_setup_clipped) */
+  int32_t smooth;    /* nonzero: Lambert shading per pixel of the normal
+                        interpolated perspective-correctly from the
+                        triangle's vertex normals (not with near_clip) */
 } oracle_render_params;
 
 /* One contact point as the narrowphase reports it. */
@@ -130,6 +133,13 @@ int oracle_render_image(int32_t n, const uint8_t* type, const float* size,
 
 /* As oracle_render_image, with boxes (type 2: the cube template scaled by
  * the half-extents ext[3b .. 3b+2]); ext may be NULL when there is no box. */
+/* Smooth shading: the unit normal at the centre of pixel (px, py) of a
+ * triangle (snapped vertices X, Y in setup order, 1 / clip w per vertex,
+ * world normals n[3][3]) interpolated perspective-correctly; zero if the
+ * weighted sum vanishes. */
+void oracle_smooth_normal(const int32_t* X, const int32_t* Y, const float* iw, const float* n, int32_t px,
+                          int32_t py, float* out);
+
 int oracle_render_image_box(int32_t n, const uint8_t* type, const float* size, const float* ext,
                             const uint8_t* albedo, const float* pos, const float* quat,
                             const float* vp, int32_t W, int32_t H, const oracle_render_params* rp,

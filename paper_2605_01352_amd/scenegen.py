@@ -265,6 +265,7 @@ class Scene:
     v_eps: float = 0.05    # [m/s] slip speed below which friction is linear
     edge_contacts: bool = False  # box-box edge-edge points (separating-axis test)
     near_clip: bool = False  # cut triangles crossing the near plane instead of culling them
+    smooth: bool = False  # per-pixel Lambert shading of the interpolated vertex normal
     # boxes (type 2): half-extents and principal moments of inertia, body frame
     ext: Optional[np.ndarray] = None      # f32 [B,3] (rows of other bodies unused)
     inertia: Optional[np.ndarray] = None  # f32 [B,3]

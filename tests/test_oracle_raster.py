@@ -129,9 +129,10 @@ def test_top_left_orientation():
 
 def _render(scene, light=None, debug=True):
     if light is not None:
-        rp = oracle._Render(light=light)
+        smooth = bool(getattr(scene, "smooth", False))
+        rp = oracle._Render(light=light, smooth=smooth)
         old = dict(oracle._RENDER)
-        oracle._RENDER[False] = rp
+        oracle._RENDER[(False, smooth)] = rp
         try:
             return oracle.render_image(scene, scene.state(), 0, debug=debug)
         finally:

@@ -75,6 +75,15 @@ extern "C" {
                                   part in front (one or two pieces, at most 64 per
                                   image, else VUDA_EOVERFLOW) instead of culling
                                   them whole; images are otherwise unchanged    */
+#define VUDA_FLAG_SMOOTH 4u    /* smooth shading: each pixel takes Lambert shading
+                                  of the vertex normals of its winning triangle
+                                  interpolated perspective-correctly (weights
+                                  E_k / w_k: edge value over clip w), normalized;
+                                  a sphere's vertex normal is its template vertex
+                                  turned by the body's rotation, a cube's or box's
+                                  the face normal, the ground's +z.  Winners,
+                                  depth and coverage are those of flat shading.
+                                  Not with VUDA_FLAG_NEAR_CLIP (VUDA_EINVAL)     */
 
 typedef struct vuda_world vuda_world;
 
@@ -441,7 +450,8 @@ int vuda_run(vuda_world* w, int32_t schedule, int32_t iters);
 
 /*
  * Autotuner: searches the launch shapes (schedule, CU split, physics and
- * raster workgroup shapes, physics priority, broadphase, presetup) for the highest
+ * raster persistent grids and workgroup shapes, hipGraph replay, physics
+ * priority, broadphase, presetup) for the highest
  * co-scheduled env-steps/s on this world, timing `steps_per_trial`
  * iterations per candidate from the current state (the state is saved before
  * and restored after, so results are unchanged), applies the best, and
@@ -458,6 +468,7 @@ typedef struct {
   int32_t serial_raster_threads, serial_phys_persistent;
   int32_t trials;            /* 0 when taken from the cache */
   int32_t presetup;          /* VUDA_TUNE_PRESETUP chosen */
+  int32_t graphs;            /* VUDA_TUNE_GRAPHS chosen */
 } vuda_tune_result;
 int vuda_autotune(vuda_world* w, int32_t steps_per_trial, const char* cache_path, vuda_tune_result* out);
 

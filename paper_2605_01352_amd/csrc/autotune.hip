@@ -1,6 +1,9 @@
 // Autotuner: picks the schedule, CU split and launch shapes with the highest
 // measured co-scheduled throughput on a world, by coordinate descent over a
-// small candidate set, timing real iterations from a saved state.
+// small candidate set, timing real iterations from a saved state.  The
+// coordinates, in order: schedule x CU split; physics persistent grid;
+// raster-setup persistent grid; hipGraph replay; setup workgroup size; step
+// wave priority; broadphase; presetup.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -123,6 +126,7 @@ void to_result(const Cand& c, vuda_tune_result* r) {
   r->phys_priority = c.tune.phys_prio;
   r->broadphase = c.tune.broadphase;
   r->presetup = c.tune.presetup ? 1 : 0;
+  r->graphs = c.tune.graphs ? 1 : 0;
 }
 
 bool cache_lookup(const char* path, const std::string& key, vuda_tune_result* r) {
@@ -137,7 +141,8 @@ bool cache_lookup(const char* path, const std::string& key, vuda_tune_result* r)
     vuda_tune_result t{};
     if (is >> t.cu_split >> t.schedule >> t.raster_threads >> t.rec_cap >> t.phys_persistent >>
         t.raster_persistent >> t.phys_priority >> t.broadphase >> t.cosched_env_steps_per_s >>
-        t.serial_env_steps_per_s >> t.serial_raster_threads >> t.serial_phys_persistent >> t.presetup) {
+        t.serial_env_steps_per_s >> t.serial_raster_threads >> t.serial_phys_persistent >> t.presetup >>
+        t.graphs) {
       *r = t;  // the last matching line wins
       found = true;
     }
@@ -151,7 +156,8 @@ void cache_store(const char* path, const std::string& key, const vuda_tune_resul
   f << key << " " << r.cu_split << " " << r.schedule << " " << r.raster_threads << " " << r.rec_cap
     << " " << r.phys_persistent << " " << r.raster_persistent << " " << r.phys_priority << " "
     << r.broadphase << " " << r.cosched_env_steps_per_s << " " << r.serial_env_steps_per_s << " "
-    << r.serial_raster_threads << " " << r.serial_phys_persistent << " " << r.presetup << "\n";
+    << r.serial_raster_threads << " " << r.serial_phys_persistent << " " << r.presetup << " " << r.graphs
+    << "\n";
 }
 
 }  // namespace
@@ -179,6 +185,7 @@ extern "C" int vuda_autotune(vuda_world* w, int32_t steps, const char* cache_pat
     c.tune.phys_prio = out->phys_priority;
     c.tune.broadphase = out->broadphase;
     c.tune.presetup = out->presetup != 0;
+    c.tune.graphs = out->graphs != 0;
     out->trials = 0;
     return apply(w, c);
   }
@@ -240,6 +247,8 @@ extern "C" int vuda_autotune(vuda_world* w, int32_t steps, const char* cache_pat
     }
   };
   stage([](Cand& c, int v) { c.tune.phys_persistent = v; }, {0, ncu, 2 * ncu, 3 * ncu});
+  stage([](Cand& c, int v) { c.tune.raster_persistent = v; }, {0, ncu, 2 * ncu, 4 * ncu});
+  stage([](Cand& c, int v) { c.tune.graphs = v != 0; }, {0, 1});
   stage([](Cand& c, int v) { c.tune.raster_threads = v; }, {256, 512});
   stage([](Cand& c, int v) { c.tune.phys_prio = v; }, {0, 3});
   stage([](Cand& c, int v) { c.tune.broadphase = v; }, {0, 1});

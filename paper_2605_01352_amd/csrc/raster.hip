@@ -442,6 +442,47 @@ __device__ __forceinline__ float4 vertex_clip(const Templates* T, const BodyLDS&
                      ((vp[12] * wx + vp[13] * wy) + vp[14] * wz) + vp[15]);
 }
 
+// Attribute record r of a triangle for smooth shading (face `face` of body
+// `body`, -1 the ground; vid its vertices in face order): the world normal
+// and the reciprocal clip w of each vertex in edge order (face vertices 0, 2,
+// 1), and the albedo.  A sphere's vertex normal is its unit template vertex
+// turned by R, a cube's or box's the face normal, the ground's +z.
+__device__ __forceinline__ void store_attr(float4* ga, int r, const Templates* T, const BodyLDS& B, int S,
+                                           const uint8_t* gvmap, int body, int face, const int vid[3],
+                                           const float* vp) {
+  const int ord[3] = {0, 2, 1};
+  float n[3][3], iw[3], al[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int v = vid[ord[k]];
+    iw[k] = 1.0f / vertex_clip(T, B, S, gvmap, v, vp).w;
+    if (body < 0) {
+      n[k][0] = 0.0f;
+      n[k][1] = 0.0f;
+      n[k][2] = 1.0f;
+    } else {
+      const float* nb = B.type[body] ? T->cube_n[face] : T->sphere_v[v - B.vb[body]];
+      const float* R = B.R + body;
+      n[k][0] = (R[0] * nb[0] + R[S] * nb[1]) + R[2 * S] * nb[2];
+      n[k][1] = (R[3 * S] * nb[0] + R[4 * S] * nb[1]) + R[5 * S] * nb[2];
+      n[k][2] = (R[6 * S] * nb[0] + R[7 * S] * nb[1]) + R[8 * S] * nb[2];
+    }
+  }
+  if (body < 0) {
+    al[0] = al[1] = al[2] = T->ground_albedo;
+  } else {
+    const int ai = B.alb[body];
+    al[0] = T->palette[ai][0];
+    al[1] = T->palette[ai][1];
+    al[2] = T->palette[ai][2];
+  }
+  float4* p = ga + 4 * r;
+  p[0] = make_float4(n[0][0], n[0][1], n[0][2], n[1][0]);
+  p[1] = make_float4(n[1][1], n[1][2], n[2][0], n[2][1]);
+  p[2] = make_float4(n[2][2], iw[0], iw[1], iw[2]);
+  p[3] = make_float4(al[0], al[1], al[2], 0.0f);
+}
+
 // CLIP: cut triangles crossing the near plane (else they are culled whole,
 // and none of that code is compiled in)
 template <bool CLIP>
@@ -463,7 +504,7 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
   const int Wd = cam.w, Ht = cam.h;
   const int ntx = (Wd + kTile - 1) / kTile;
   const int ntiles = tiles_of(Wd, Ht);
-  const RsLayout RL = rs_layout(cam.n_tris, ntiles);
+  const RsLayout RL = rs_layout(cam.n_tris, ntiles, L.smooth != 0);
   unsigned char* rs = W.rscratch + cam.rs_off + L.parity * RL.total;  // one scratch per state buffer
   int32_t* hdr = (int32_t*)rs;
   int32_t* ttab = (int32_t*)(rs + RL.tiles);
@@ -645,7 +686,18 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
       int x0, x1, y0, y1;
       tri_pixels(t.X, t.Y, Wd, Ht, &x0, &x1, &y0, &y1);
       const int64_t A = tri_area(t.X, t.Y);
-      const uint32_t rgb = face_color(T, B, Lo.nmax, body, body < 0 ? pr : pr - B.pb[body]);
+      const int face = body < 0 ? pr : pr - B.pb[body];
+      uint32_t rgb;
+      if (L.smooth) {
+        // the key carries the record instead of a colour; the pixel's colour
+        // comes from the record's attributes in the tile kernel
+        rgb = (uint32_t)r;
+        int bb, vid[3];
+        prim_vertices(T, B, gpmap[pr], pr, &bb, vid);
+        store_attr((float4*)(rs + RL.attr), r, T, B, Lo.nmax, gvmap, body, face, vid, vp);
+      } else {
+        rgb = face_color(T, B, Lo.nmax, body, face);
+      }
       store_rec(grec, r, t, pr, 1.0f / (float)(double)A, rgb, x0, x1, y0, y1);
       tx0 = x0 >> 4;
       ty0 = y0 >> 4;
@@ -788,7 +840,47 @@ __device__ __forceinline__ uint64_t depth_key(float e0, float e1, float e2, floa
   return ((uint64_t)D << 40) | key;
 }
 
-template <bool DBG>
+// Smooth shading of pixel (px, py) won by record r: the attribute record's
+// vertex normals interpolated with weights E_k / w_k at the pixel centre
+// (exact edge values), normalized, and Lambert-shaded; RGB8 packed.
+__device__ __forceinline__ uint32_t smooth_color(const int4* grec, const float4* gattr, const Templates* T, int r,
+                                                 int px, int py) {
+  const int4 a = grec[4 * r], b = grec[4 * r + 1];
+  const float4 g0 = gattr[4 * r], g1 = gattr[4 * r + 1], g2 = gattr[4 * r + 2], g3 = gattr[4 * r + 3];
+  const int32_t X[3] = {a.x, a.z, b.x}, Y[3] = {a.y, a.w, b.y};
+  const float iw[3] = {g2.y, g2.z, g2.w};
+  const int Px = 256 * px + 128, Py = 256 * py + 128;
+  float u[3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const int a0 = (e + 1) % 3, b0 = (e + 2) % 3;
+    const int32_t dx = X[b0] - X[a0], dy = Y[b0] - Y[a0];
+    const double E = fma(-(double)dy, (double)(Px - X[a0]), (double)dx * (double)(Py - Y[a0]));
+    u[e] = (float)E * iw[e];
+  }
+  const float mx = (u[0] * g0.x + u[1] * g0.w) + u[2] * g1.z;
+  const float my = (u[0] * g0.y + u[1] * g1.x) + u[2] * g1.w;
+  const float mz = (u[0] * g0.z + u[1] * g1.y) + u[2] * g2.x;
+  const float l2 = (mx * mx + my * my) + mz * mz;
+  float nx = 0.0f, ny = 0.0f, nz = 0.0f;
+  if (l2 > 0.0f) {
+    const float l = sqrtf(l2);
+    nx = mx / l;
+    ny = my / l;
+    nz = mz / l;
+  }
+  const float lam = fmaxf(0.0f, (nx * T->light[0] + ny * T->light[1]) + nz * T->light[2]);
+  const float al[3] = {g3.x, g3.y, g3.z};
+  uint32_t rgb = 0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float col = al[c] * (0.2f + 0.8f * lam);
+    rgb |= (uint32_t)fminf(255.0f, rintf(col * 255.0f)) << (8 * c);
+  }
+  return rgb;
+}
+
+template <bool DBG, bool SMOOTH>
 __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam, int parity, int ntx,
                                             int tx, int ty, TileWaveLDS& S, int32_t* cov) {
   const int lane = threadIdx.x & 63;
@@ -981,6 +1073,11 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
     D[i] = hit ? (uint32_t)(key >> 40) : 0xFFFFFFFFu;
     rgb[i] = hit ? (uint32_t)key & 0xFFFFFFu : 0u;
     win[i] = hit ? (int32_t)((key >> 24) & 0xFFFFu) : -1;
+    if constexpr (SMOOTH) {
+      // the key's low bits name the winning record
+      if (hit)
+        rgb[i] = smooth_color(grec, (const float4*)(rs + cam.rs_attr), W.tpl, (int)rgb[i], px0 + i, py);
+    }
   }
   if (py <= ty1) {
     const int64_t pix = cam.pix_off + (int64_t)py * Wd + px0;
@@ -1011,7 +1108,7 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
   }
 }
 
-template <bool DBG>
+template <bool DBG, bool SMOOTH>
 __global__ void __launch_bounds__(64 * kTileWaves) raster_tile_kernel(WorldDev W, RasterLaunch L) {
   __shared__ TileWaveLDS S[kTileWaves];
   __shared__ int32_t C[DBG ? kTileWaves : 1][DBG ? 256 : 1];
@@ -1023,7 +1120,7 @@ __global__ void __launch_bounds__(64 * kTileWaves) raster_tile_kernel(WorldDev W
   const int ntx = (cam.w + kTile - 1) / kTile;
   const int tx = (job.y & 0xFFFF) + wave, ty = job.y >> 16;
   if (tx >= ntx) return;  // no workgroup barrier follows
-  raster_tile<DBG>(W, cam, L.parity, ntx, tx, ty, S[wave], DBG ? C[wave] : nullptr);
+  raster_tile<DBG, SMOOTH>(W, cam, L.parity, ntx, tx, ty, S[wave], DBG ? C[wave] : nullptr);
 }
 
 }  // namespace
@@ -1057,10 +1154,14 @@ hipError_t launch_raster_setup(const WorldDev& w, const RasterLaunch& l, hipStre
 
 hipError_t launch_raster_tiles(const WorldDev& w, const RasterLaunch& l, hipStream_t s, LaunchEvents* ev) {
   if (l.n_tile_groups <= 0) return hipSuccess;
-  if (w.winners)
-    timed_launch(ev, true, true, raster_tile_kernel<true>, dim3(l.n_tile_groups), dim3(64 * kTileWaves), 0, s, w, l);
-  else
-    timed_launch(ev, true, true, raster_tile_kernel<false>, dim3(l.n_tile_groups), dim3(64 * kTileWaves), 0, s, w, l);
+  const dim3 g(l.n_tile_groups), b(64 * kTileWaves);
+  if (l.smooth) {
+    if (w.winners) timed_launch(ev, true, true, raster_tile_kernel<true, true>, g, b, 0, s, w, l);
+    else timed_launch(ev, true, true, raster_tile_kernel<false, true>, g, b, 0, s, w, l);
+  } else {
+    if (w.winners) timed_launch(ev, true, true, raster_tile_kernel<true, false>, g, b, 0, s, w, l);
+    else timed_launch(ev, true, true, raster_tile_kernel<false, false>, g, b, 0, s, w, l);
+  }
   return hipGetLastError();
 }
 

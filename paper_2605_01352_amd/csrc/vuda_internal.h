@@ -48,7 +48,7 @@ struct CamDev {
   int32_t n_tris;     // primitives of the env (sizes the raster scratch)
   int64_t rs_off;     // byte offset of the image's raster scratch (two layouts, one per state buffer)
   int32_t rs_recs, rs_bins, rs_total;  // rs_layout(n_tris, tiles): offsets and size of one layout
-  int32_t pad;
+  int32_t rs_attr;                     // smooth shading: the attribute records
 };
 
 // Raster scratch of one camera image and state buffer (two per camera, one
@@ -63,20 +63,26 @@ constexpr int kRecBytes = 4 * kRecWords;
 constexpr int kBinsPerTri = 4;  // bin capacity of an image, per primitive
 constexpr int kClipRecs = 64;   // records an image keeps for pieces of triangles cut by the near plane
 
+// Smooth shading: per record an attribute record of 16 floats, the world
+// normals of its vertices in edge order (9), their reciprocal clip w (3) and
+// the albedo (3).
+constexpr int kAttrWords = 16;
+
 struct RsLayout {
-  int64_t tiles, recs, bins, total;
+  int64_t tiles, recs, bins, attr, total;
   int32_t bin_cap;
 };
 
 __host__ __device__ inline int64_t rs_align(int64_t x) { return (x + 255) & ~(int64_t)255; }
 
-__host__ __device__ inline RsLayout rs_layout(int32_t ntris, int32_t ntiles) {
+__host__ __device__ inline RsLayout rs_layout(int32_t ntris, int32_t ntiles, bool smooth = false) {
   RsLayout r;
   r.tiles = 64;
   r.recs = rs_align(64 + 8 * (int64_t)ntiles);
   r.bins = r.recs + rs_align((int64_t)kRecBytes * (ntris + kClipRecs));
   r.bin_cap = kBinsPerTri * (ntris + kClipRecs);
-  r.total = r.bins + rs_align(2 * (int64_t)r.bin_cap);
+  r.attr = r.bins + rs_align(2 * (int64_t)r.bin_cap);
+  r.total = r.attr + (smooth ? rs_align((int64_t)4 * kAttrWords * (ntris + kClipRecs)) : 0);
   return r;
 }
 
@@ -179,6 +185,7 @@ struct RasterLaunch {
   int32_t* queue;
   int32_t prio;            // setup kernel: wave issue priority 0..3 (s_setprio)
   int32_t near_clip;       // setup kernel: cut triangles crossing the near plane
+  int32_t smooth;          // per-pixel shading of interpolated vertex normals
 };
 
 // Timing events of one launch (a kernel or a chain of them): `start` is

@@ -130,6 +130,7 @@ struct vuda_world {
   vuda::Templates tpl{};
   bool debug = false;
   bool near_clip = false;  // VUDA_FLAG_NEAR_CLIP
+  bool smooth = false;     // VUDA_FLAG_SMOOTH
   int32_t pair_cap = 1024;
   int32_t cap_envs = 0, cap_cams = 0;
   int64_t cap_bodies = 0, cap_pixels = 0;

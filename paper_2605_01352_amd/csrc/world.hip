@@ -334,7 +334,7 @@ int64_t vuda_world::rs_units(const vuda_env_batch& b) const {
   for (int32_t e = 0; e < b.n_envs; ++e) {
     const int32_t nt = env_tris(b, e);
     for (int32_t c = b.cam_off[e]; c < b.cam_off[e + 1]; ++c)
-      u += 2 * (rs_layout(nt, tiles_of(b.cam_w[c], b.cam_h[c])).total / 256);
+      u += 2 * (rs_layout(nt, tiles_of(b.cam_w[c], b.cam_h[c]), smooth).total / 256);
   }
   return u;
 }
@@ -385,11 +385,11 @@ int vuda_world::upload(const vuda_env_batch& b, int32_t e0, int64_t b0, int32_t 
       d.env = e0 + e;
       d.n_tris = nt;
       d.rs_off = ro;
-      const RsLayout rl = rs_layout(nt, tiles_of(d.w, d.h));
+      const RsLayout rl = rs_layout(nt, tiles_of(d.w, d.h), smooth);
       d.rs_recs = (int32_t)rl.recs;
       d.rs_bins = (int32_t)rl.bins;
       d.rs_total = (int32_t)rl.total;
-      d.pad = 0;
+      d.rs_attr = (int32_t)rl.attr;
       po += (int64_t)d.w * d.h;
       ro += 2 * rl.total;
     }
@@ -464,12 +464,15 @@ extern "C" int vuda_create_world(const vuda_world_desc* d, const vuda_allocator*
   int32_t nc = 0;
   rc = validate_batch(d->initial, d->render, &nb, &nc, &npix);
   if (rc) return rc;
+  if ((d->flags & VUDA_FLAG_SMOOTH) && (d->flags & VUDA_FLAG_NEAR_CLIP))
+    return fail(VUDA_EINVAL, "VUDA_FLAG_SMOOTH does not combine with VUDA_FLAG_NEAR_CLIP");
   vuda_world* w = new (std::nothrow) vuda_world();
   if (!w) return fail(VUDA_ENOMEM, "host allocation");
   HIPCHK(hipGetDevice(&w->device));
   w->phys = d->phys;
   w->debug = (d->flags & VUDA_FLAG_DEBUG) != 0;
   w->near_clip = (d->flags & VUDA_FLAG_NEAR_CLIP) != 0;
+  w->smooth = (d->flags & VUDA_FLAG_SMOOTH) != 0;
   w->pair_cap = d->pair_cap > 0 ? d->pair_cap : 1024;
   w->cap_envs = std::max(d->cap_envs, d->initial.n_envs);
   w->cap_bodies = std::max(d->cap_bodies, nb);
@@ -907,6 +910,7 @@ int vuda_world::raster_launch_of(const WorkList& L, int parity, int32_t* queue, 
   rl.queue = queue;
   rl.prio = 0;
   rl.near_clip = near_clip ? 1 : 0;
+  rl.smooth = smooth ? 1 : 0;
   const size_t lds = raster_lds_bytes(rl);
   const size_t kLdsMax = 160 * 1024;
   if (lds > kLdsMax)
@@ -1806,7 +1810,7 @@ extern "C" int vuda_release(vuda_world* w, int32_t first, int32_t n) {
     p0 = c0.pix_off;
     np = c1.pix_off + (int64_t)c1.w * c1.h - p0;
     r0 = c0.rs_off / 256;
-    nr = (c1.rs_off + 2 * rs_layout(c1.n_tris, tiles_of(c1.w, c1.h)).total) / 256 - r0;
+    nr = (c1.rs_off + 2 * rs_layout(c1.n_tris, tiles_of(c1.w, c1.h), w->smooth).total) / 256 - r0;
   }
   std::vector<EnvDev> empty(n, EnvDev{});
   HIPCHK(hipMemcpy(w->dev.envs + first, empty.data(), sizeof(EnvDev) * n, hipMemcpyHostToDevice));

@@ -22,6 +22,7 @@ FETCH_STATE, FETCH_RGB, FETCH_DEPTH, FETCH_CONTACTS, FETCH_WINNERS, FETCH_COVERA
     FETCH_DEPTH_METRIC = range(9)
 FLAG_DEBUG = 1
 FLAG_NEAR_CLIP = 2
+FLAG_SMOOTH = 4
 TUNE_RASTER_THREADS, TUNE_REC_CAP, TUNE_PHYS_PERSISTENT, TUNE_RASTER_PERSISTENT, TUNE_GRAPHS = 1, 2, 3, 4, 5
 TUNE_PHYS_PRIORITY = 6
 TUNE_BROADPHASE = 7
@@ -91,7 +92,8 @@ class TuneResult(C.Structure):
                 ("raster_persistent", C.c_int32), ("phys_priority", C.c_int32),
                 ("broadphase", C.c_int32), ("cosched_env_steps_per_s", C.c_double),
                 ("serial_env_steps_per_s", C.c_double), ("serial_raster_threads", C.c_int32),
-                ("serial_phys_persistent", C.c_int32), ("trials", C.c_int32), ("presetup", C.c_int32)]
+                ("serial_phys_persistent", C.c_int32), ("trials", C.c_int32), ("presetup", C.c_int32),
+                ("graphs", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -241,7 +243,8 @@ class World:
                                (C.c_float * 3)(*[float(x) for x in g]), float(mu), float(v_eps), int(edge))
         desc.render = render_desc(keep, **(render_kw or {}))
         desc.initial = env_batch(keep, scene) if scene is not None else EnvBatch(0)
-        desc.flags = (FLAG_DEBUG if debug else 0) | (FLAG_NEAR_CLIP if getattr(ref, "near_clip", False) else 0)
+        desc.flags = (FLAG_DEBUG if debug else 0) | (FLAG_NEAR_CLIP if getattr(ref, "near_clip", False) else 0) | \
+            (FLAG_SMOOTH if getattr(ref, "smooth", False) else 0)
         desc.cap_envs, desc.cap_bodies, desc.cap_cams, desc.cap_pixels = cap_envs, cap_bodies, cap_cams, cap_pixels
         desc.pair_cap = pair_cap
         desc.hbm_budget = hbm_budget
@@ -453,7 +456,8 @@ def world_desc(keep: _Keep, scene=None, debug: bool = False, cap_envs: int = 0, 
                         (C.c_float * 3)(*[float(x) for x in g]), float(mu), float(v_eps), int(edge))
     d.render = render_desc(keep)
     d.initial = env_batch(keep, scene) if scene is not None else EnvBatch(0)
-    d.flags = (FLAG_DEBUG if debug else 0) | (FLAG_NEAR_CLIP if getattr(scene, "near_clip", False) else 0)
+    d.flags = (FLAG_DEBUG if debug else 0) | (FLAG_NEAR_CLIP if getattr(scene, "near_clip", False) else 0) | \
+        (FLAG_SMOOTH if getattr(scene, "smooth", False) else 0)
     d.cap_envs, d.cap_bodies, d.cap_cams, d.cap_pixels = cap_envs, cap_bodies, cap_cams, cap_pixels
     d.pair_cap = pair_cap
     d.hbm_budget = hbm_budget

@@ -383,8 +383,10 @@ def main():
                     help="only run this many serialized then co-scheduled steps (for rocprofv3)")
     ap.add_argument("--physics-profile", type=int, default=0,
                     help="only run this many physics launches from the start state (for rocprofv3)")
-    ap.add_argument("--profile-mode", default="interstep@2",
-                    help="the co-scheduled mode of --profile")
+    ap.add_argument("--profile-mode", default="interstep@2/p3",
+                    help="the co-scheduled mode of --profile (schedule@split[/pPRIORITY])")
+    ap.add_argument("--profile-serial", type=int, default=1,
+                    help="with --profile: also run the serialized loop first (0: only the co-scheduled one)")
     ap.add_argument("--only", default="",
                     help="skip the sweep and time this co-scheduled mode, e.g. interstep@2")
     ap.add_argument("--copy-calib", type=int, default=0,
@@ -434,7 +436,8 @@ def main():
                 "phys_persistent": vuda.TUNE_PHYS_PERSISTENT,
                 "raster_persistent": vuda.TUNE_RASTER_PERSISTENT, "graphs": vuda.TUNE_GRAPHS,
                 "phys_prio": vuda.TUNE_PHYS_PRIORITY, "broadphase": vuda.TUNE_BROADPHASE,
-                "presetup": vuda.TUNE_PRESETUP, "policy_layered": vuda.TUNE_POLICY_LAYERED}
+                "presetup": vuda.TUNE_PRESETUP, "policy_layered": vuda.TUNE_POLICY_LAYERED,
+                "phys_pack": vuda.TUNE_PHYS_ENVS_PER_WAVE}
     for kv in filter(None, args.tune.split(",")):
         k, v = kv.split("=")
         w.set_tuning(knob_ids[k], int(v))
@@ -465,13 +468,18 @@ def main():
         w.close()
         return
     if args.profile:
-        psched, psplit = args.profile_mode.split("@")
-        w.cosched(0.0)
-        dt_s = timed(torch, w, "serial", n_envs, args.profile, 2, st0)
+        psched, rest = args.profile_mode.split("@")
+        psplit, _, pprio = rest.partition("/p")
+        if args.profile_serial:
+            w.cosched(0.0)
+            dt_s = timed(torch, w, "serial", n_envs, args.profile, 2, st0)
+            log(f"profile run from step {start}: serialized {dt_s / args.profile * 1e6:.1f} us/step")
         w.cosched(float(psplit))
+        if pprio:
+            w.set_tuning(vuda.TUNE_PHYS_PRIORITY, int(pprio))
         dt_c = timed(torch, w, psched, n_envs, args.profile, 2, st0)
-        log(f"profile run from step {start}: serialized {dt_s / args.profile * 1e6:.1f} us/step, "
-            f"co-scheduled ({args.profile_mode}) {dt_c / args.profile * 1e6:.1f} us/step")
+        log(f"profile run from step {start}: co-scheduled ({args.profile_mode}) "
+            f"{dt_c / args.profile * 1e6:.1f} us/step")
         w.close()
         return
 

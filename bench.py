@@ -437,7 +437,7 @@ def main():
                 "raster_persistent": vuda.TUNE_RASTER_PERSISTENT, "graphs": vuda.TUNE_GRAPHS,
                 "phys_prio": vuda.TUNE_PHYS_PRIORITY, "broadphase": vuda.TUNE_BROADPHASE,
                 "presetup": vuda.TUNE_PRESETUP, "policy_layered": vuda.TUNE_POLICY_LAYERED,
-                "phys_pack": vuda.TUNE_PHYS_ENVS_PER_WAVE}
+                "phys_pack": vuda.TUNE_PHYS_ENVS_PER_WAVE, "tile": vuda.TUNE_TILE_SIZE}
     for kv in filter(None, args.tune.split(",")):
         k, v = kv.split("=")
         w.set_tuning(knob_ids[k], int(v))

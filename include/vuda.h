@@ -317,6 +317,14 @@ int vuda_world_info(vuda_world* w, int32_t* n_envs, int64_t* n_bodies, int32_t* 
  *                              Changes the float32 summation order of layers
  *                              2 and 3 (the actions stay within the same
  *                              error bound of the exact ones)
+ *   VUDA_TUNE_PHYS_ENVS_PER_WAVE  1 (default) or 2: envs of at most 32 bodies
+ *                              per physics wave (two envs share a wave, one
+ *                              in each half, when every env of a launch has
+ *                              at most 32 bodies)
+ *   VUDA_TUNE_TILE_SIZE        8, 16 (default) or 32: edge in pixels of the
+ *                              raster tiles (binning and one tile-kernel wave
+ *                              per tile); changing it waits for queued work
+ *                              and redoes the raster setup of current states
  * None of the others changes any output bit.  Returns VUDA_EINVAL for unknown keys
  * or out-of-range values.
  */
@@ -330,6 +338,8 @@ int vuda_world_info(vuda_world* w, int32_t* n_envs, int64_t* n_bodies, int32_t* 
 #define VUDA_TUNE_TIMING 8
 #define VUDA_TUNE_PRESETUP 9
 #define VUDA_TUNE_POLICY_LAYERED 10
+#define VUDA_TUNE_PHYS_ENVS_PER_WAVE 11
+#define VUDA_TUNE_TILE_SIZE 12
 int vuda_set_tuning(vuda_world* w, int32_t key, int32_t value);
 int vuda_get_tuning(vuda_world* w, int32_t key, int32_t* value);
 
@@ -450,8 +460,9 @@ int vuda_run(vuda_world* w, int32_t schedule, int32_t iters);
 
 /*
  * Autotuner: searches the launch shapes (schedule, CU split, physics and
- * raster persistent grids and workgroup shapes, hipGraph replay, physics
- * priority, broadphase, presetup) for the highest
+ * raster persistent grids and workgroup shapes, raster tile size, physics
+ * envs per wave, hipGraph replay, physics priority, broadphase, presetup)
+ * for the highest
  * co-scheduled env-steps/s on this world, timing `steps_per_trial`
  * iterations per candidate from the current state (the state is saved before
  * and restored after, so results are unchanged), applies the best, and
@@ -469,6 +480,8 @@ typedef struct {
   int32_t trials;            /* 0 when taken from the cache */
   int32_t presetup;          /* VUDA_TUNE_PRESETUP chosen */
   int32_t graphs;            /* VUDA_TUNE_GRAPHS chosen */
+  int32_t phys_envs_per_wave; /* VUDA_TUNE_PHYS_ENVS_PER_WAVE chosen */
+  int32_t tile_size;         /* VUDA_TUNE_TILE_SIZE chosen */
 } vuda_tune_result;
 int vuda_autotune(vuda_world* w, int32_t steps_per_trial, const char* cache_path, vuda_tune_result* out);
 

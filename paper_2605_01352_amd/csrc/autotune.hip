@@ -2,8 +2,9 @@
 // measured co-scheduled throughput on a world, by coordinate descent over a
 // small candidate set, timing real iterations from a saved state.  The
 // coordinates, in order: schedule x CU split; physics persistent grid;
-// raster-setup persistent grid; hipGraph replay; setup workgroup size; step
-// wave priority; broadphase; presetup.
+// raster-setup persistent grid; tile size; physics envs per wave; hipGraph
+// replay;
+// setup workgroup size; step wave priority; broadphase; presetup.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -93,6 +94,13 @@ int restore_snapshot(vuda_world* w, const Snapshot& s) {
 }
 
 int apply(vuda_world* w, const Cand& c) {
+  if (c.tune.tile_shift != w->tune.tile_shift) {
+    // tile jobs and raster setups are laid out for one tile size
+    int rc = w->drain();
+    if (rc) return rc;
+    std::fill(w->setup_ok.begin(), w->setup_ok.end(), 0);
+    w->invalidate_lists();
+  }
   w->tune = c.tune;
   for (auto& g : w->graphs) (void)hipGraphExecDestroy(g.second);
   w->graphs.clear();
@@ -127,6 +135,8 @@ void to_result(const Cand& c, vuda_tune_result* r) {
   r->broadphase = c.tune.broadphase;
   r->presetup = c.tune.presetup ? 1 : 0;
   r->graphs = c.tune.graphs ? 1 : 0;
+  r->phys_envs_per_wave = c.tune.phys_pack;
+  r->tile_size = 1 << c.tune.tile_shift;
 }
 
 bool cache_lookup(const char* path, const std::string& key, vuda_tune_result* r) {
@@ -142,7 +152,7 @@ bool cache_lookup(const char* path, const std::string& key, vuda_tune_result* r)
     if (is >> t.cu_split >> t.schedule >> t.raster_threads >> t.rec_cap >> t.phys_persistent >>
         t.raster_persistent >> t.phys_priority >> t.broadphase >> t.cosched_env_steps_per_s >>
         t.serial_env_steps_per_s >> t.serial_raster_threads >> t.serial_phys_persistent >> t.presetup >>
-        t.graphs) {
+        t.graphs >> t.phys_envs_per_wave >> t.tile_size) {
       *r = t;  // the last matching line wins
       found = true;
     }
@@ -156,8 +166,8 @@ void cache_store(const char* path, const std::string& key, const vuda_tune_resul
   f << key << " " << r.cu_split << " " << r.schedule << " " << r.raster_threads << " " << r.rec_cap
     << " " << r.phys_persistent << " " << r.raster_persistent << " " << r.phys_priority << " "
     << r.broadphase << " " << r.cosched_env_steps_per_s << " " << r.serial_env_steps_per_s << " "
-    << r.serial_raster_threads << " " << r.serial_phys_persistent << " " << r.presetup << " " << r.graphs
-    << "\n";
+    << r.serial_raster_threads << " " << r.serial_phys_persistent << " " << r.presetup << " " << r.graphs << " "
+    << r.phys_envs_per_wave << " " << r.tile_size << "\n";
 }
 
 }  // namespace
@@ -186,6 +196,8 @@ extern "C" int vuda_autotune(vuda_world* w, int32_t steps, const char* cache_pat
     c.tune.broadphase = out->broadphase;
     c.tune.presetup = out->presetup != 0;
     c.tune.graphs = out->graphs != 0;
+    c.tune.phys_pack = out->phys_envs_per_wave == 2 ? 2 : 1;
+    c.tune.tile_shift = out->tile_size == 8 ? 3 : (out->tile_size == 32 ? 5 : 4);
     out->trials = 0;
     return apply(w, c);
   }
@@ -248,6 +260,8 @@ extern "C" int vuda_autotune(vuda_world* w, int32_t steps, const char* cache_pat
   };
   stage([](Cand& c, int v) { c.tune.phys_persistent = v; }, {0, ncu, 2 * ncu, 3 * ncu});
   stage([](Cand& c, int v) { c.tune.raster_persistent = v; }, {0, ncu, 2 * ncu, 4 * ncu});
+  stage([](Cand& c, int v) { c.tune.tile_shift = v; }, {4, 5, 3});
+  stage([](Cand& c, int v) { c.tune.phys_pack = v; }, {1, 2});
   stage([](Cand& c, int v) { c.tune.graphs = v != 0; }, {0, 1});
   stage([](Cand& c, int v) { c.tune.raster_threads = v; }, {256, 512});
   stage([](Cand& c, int v) { c.tune.phys_prio = v; }, {0, 3});

@@ -71,10 +71,12 @@ __device__ __forceinline__ M3 quat_to_rot(float w, float x, float y, float z) {
   return R;
 }
 
-// LDS image of one env.  NW = waves per workgroup = 64-body blocks per env.
-template <int NW>
+// LDS image of one env of up to N bodies (N = 32, 64 or 128 lanes): NW =
+// 64-bit words per body bitset row = waves per env.
+template <int N_>
 struct PhysLDS {
-  static constexpr int N = 64 * NW;
+  static constexpr int N = N_;
+  static constexpr int NW = N_ > 64 ? N_ / 64 : 1;
   static constexpr int CAPC = 4 * N;  // candidate pairs
   static_assert(CAPC <= 1024 && N <= 2048, "cube-cube queue packing");
   static constexpr int CAPK = 2 * N;  // pairs in contact
@@ -123,9 +125,28 @@ __device__ __forceinline__ int wave_incl_add(int x) {
   return x;
 }
 
-template <int NW>
+// Inclusive prefix sum within each 32-lane half of the wave (row shifts and
+// the broadcast of row 0 into row 1, row 2 into row 3).
+__device__ __forceinline__ int half_incl_add(int x) {
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  return x;
+}
+
+// Exclusive prefix sum over the N lanes of one env (thread order); *total
+// gets the env's sum.
+template <int N>
 __device__ __forceinline__ int block_excl_scan(int v, int32_t* tmp, int* total) {
+  constexpr int NW = N > 64 ? N / 64 : 1;
   const int lane = lane_id();
+  if (N == 32) {
+    const int x = half_incl_add(v);
+    *total = __shfl(x, (lane & 32) + 31, 64);
+    return x - v;
+  }
   const int x = wave_incl_add(v);
   if (NW == 1) {
     *total = __builtin_amdgcn_readlane(x, 63);
@@ -133,7 +154,6 @@ __device__ __forceinline__ int block_excl_scan(int v, int32_t* tmp, int* total) 
   }
   const int wv = threadIdx.x >> 6;
   if (lane == 63) tmp[wv] = x;
-  (void)lane;
   __syncthreads();
   int base = 0, tot = 0;
 #pragma unroll
@@ -147,11 +167,12 @@ __device__ __forceinline__ int block_excl_scan(int v, int32_t* tmp, int* total) 
   return base + x - v;
 }
 
-template <int NW>
+template <int N>
 __device__ __forceinline__ float block_max(float v, float* tmp) {
+  constexpr int NW = N > 64 ? N / 64 : 1;
   float x = v;
 #pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) x = fmaxf(x, __shfl_xor(x, d, 64));
+  for (int d = (N < 64 ? N / 2 : 32); d >= 1; d >>= 1) x = fmaxf(x, __shfl_xor(x, d, 64));
   if (NW == 1) return x;
   if (lane_id() == 0) tmp[threadIdx.x >> 6] = x;
   __syncthreads();
@@ -172,20 +193,20 @@ struct Point {
   f3 xc;
 };
 
-template <int NW>
-__device__ __forceinline__ f3 ldsP(const PhysLDS<NW>& s, int b) {
+template <int N>
+__device__ __forceinline__ f3 ldsP(const PhysLDS<N>& s, int b) {
   return mk(s.p[0][b], s.p[1][b], s.p[2][b]);
 }
-template <int NW>
-__device__ __forceinline__ f3 ldsV(const PhysLDS<NW>& s, int b) {
+template <int N>
+__device__ __forceinline__ f3 ldsV(const PhysLDS<N>& s, int b) {
   return mk(s.v[0][b], s.v[1][b], s.v[2][b]);
 }
-template <int NW>
-__device__ __forceinline__ f3 ldsW(const PhysLDS<NW>& s, int b) {
+template <int N>
+__device__ __forceinline__ f3 ldsW(const PhysLDS<N>& s, int b) {
   return mk(s.w[0][b], s.w[1][b], s.w[2][b]);
 }
-template <int NW>
-__device__ __forceinline__ M3 ldsR(const PhysLDS<NW>& s, int b) {
+template <int N>
+__device__ __forceinline__ M3 ldsR(const PhysLDS<N>& s, int b) {
   M3 R;
 #pragma unroll
   for (int k = 0; k < 9; ++k) R.m[k] = s.R[k][b];
@@ -250,8 +271,8 @@ __device__ __forceinline__ void add_point(PairAcc& acc, const Point& pt, bool a_
   acc.npts += 1;
 }
 
-template <int NW>
-__device__ __forceinline__ f3 ldsE(const PhysLDS<NW>& s, int b) {
+template <int N>
+__device__ __forceinline__ f3 ldsE(const PhysLDS<N>& s, int b) {
   const float4 e = s.ext[b];
   return mk(e.x, e.y, e.z);
 }
@@ -306,8 +327,8 @@ __device__ __forceinline__ bool sphere_cube(f3 c, float r, f3 p, const M3& R, f3
 }
 
 // Narrowphase + force sum of body pair (i, j), i < j, one of them a sphere.
-template <int NW, bool FR>
-__device__ __noinline__ PairAcc pair_forces(const PhysLDS<NW>& s, int i, int j,
+template <int N, bool FR>
+__device__ __noinline__ PairAcc pair_forces(const PhysLDS<N>& s, int i, int j,
                                             const PhysConsts& pc) {
   PairAcc acc;
   acc.SF = mk(0.0f, 0.0f, 0.0f);
@@ -417,8 +438,8 @@ constexpr float kEdgeBias = 0.95f;        // an edge axis wins below this fracti
 // and the edge overlap is below kEdgeBias times the face one, lane 15
 // stages the point's terms in estage.  Returns that decision, the same on
 // every lane of the group.
-template <int NW, bool FR>
-__device__ __forceinline__ bool edge_point(PhysLDS<NW>& s, bool live, int r, int lane, int i, int j,
+template <int N, bool FR>
+__device__ __forceinline__ bool edge_point(PhysLDS<N>& s, bool live, int r, int lane, int i, int j,
                                            const PhysConsts& pc) {
   const M3 Ri = ldsR(s, i), Rj = ldsR(s, j);
   const f3 ei = ldsE(s, i), ej = ldsE(s, j);
@@ -490,7 +511,7 @@ __device__ __forceinline__ bool edge_point(PhysLDS<NW>& s, bool live, int r, int
     pt.delta = eo;
     pt.xc = mul(add(add(ci, mul(da, sa)), add(cj, mul(db, tb))), 0.5f);
     const PointTerms pq = point_terms<FR>(pt, true, pi, ldsV(s, i), ldsW(s, i), pj, ldsV(s, j), ldsW(s, j), false, pc);
-    const int gi = (int)threadIdx.x >> 4;
+    const int gi = ((int)threadIdx.x % N) >> 4;
     s.estage[0][gi] = pq.Fi.x; s.estage[1][gi] = pq.Fi.y; s.estage[2][gi] = pq.Fi.z;
     s.estage[3][gi] = pq.ti.x; s.estage[4][gi] = pq.ti.y; s.estage[5][gi] = pq.ti.z;
     s.estage[6][gi] = pq.tj.x; s.estage[7][gi] = pq.tj.y; s.estage[8][gi] = pq.tj.z;
@@ -506,8 +527,8 @@ __device__ __forceinline__ int lanes_below(uint64_t m) {
 // Ordered sum, over the set bits l of the group mask gm (ascending), of
 // stage[c][base + l] for l < G: the terms of one pair's contact points in
 // point order.  The G values are loaded first, then added where selected.
-template <int G, int NW>
-__device__ __forceinline__ float ordered_sum(const PhysLDS<NW>& s, int c, int base, uint32_t gm) {
+template <int G, int N>
+__device__ __forceinline__ float ordered_sum(const PhysLDS<N>& s, int c, int base, uint32_t gm) {
   float v[G];
   const float4* src = (const float4*)&s.stage[c][base];
 #pragma unroll
@@ -534,14 +555,27 @@ __device__ __forceinline__ int popc_below(const uint64_t* row, int b) {
   return c;
 }
 
-template <int NW, bool FR, bool EE>
-__device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc, int env,
+template <int N, bool FR, bool EE>
+__device__ void step_env(PhysLDS<N>& s, const WorldDev& W, const PhysConsts& pc, int env,
                          int parity, int broadphase) {
-  constexpr int N = PhysLDS<NW>::N;
-  const int tid = threadIdx.x;
-  const EnvDev ed = W.envs[env];
+  constexpr int NW = PhysLDS<N>::NW;
+  // Lanes of this env: N consecutive threads.  At N = 32 two envs share a
+  // wave, each in one half: their compactions count within the half, a
+  // half's first lane does its atomics, and every loop holding a wave-wide
+  // operation runs the larger of the two halves' trip counts.
+  constexpr int LW = N < 64 ? N : 64;  // lanes of this env in one wave
+  const int tid = (int)threadIdx.x % N;
+  const int lane = lane_id();
+  const int lbase = lane & ~(LW - 1);  // this env's first lane in the wave
+  const auto half = [&](uint64_t m) -> uint64_t { return N < 64 ? ((m >> lbase) & 0xFFFFFFFFull) : m; };
+  const auto below = [&](uint64_t m) -> int {
+    return __popcll(half(m) & ((1ull << (lane - lbase)) - 1ull));
+  };
+  const auto wmax = [&](int x) -> int { return N < 64 ? max(x, __shfl_xor(x, 32, 64)) : x; };
+  EnvDev ed{};
+  if (env >= 0) ed = W.envs[env];
   const int n = ed.n_bodies;
-  if (n <= 0) return;
+  if (N >= 64 && n <= 0) return;  // a whole workgroup; a half-wave env of no bodies does nothing below
   const int b0 = ed.body_off;
   const bool own = tid < n;
   const int64_t cap = W.cap_bodies;
@@ -590,7 +624,7 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
     has_fx = true;
   }
   // grid cell edge: a little above the largest bounding diameter
-  const float rmax = block_max<NW>(own ? rbv : 0.0f, s.red);
+  const float rmax = block_max<N>(own ? rbv : 0.0f, s.red);
   const float inv_c = 1.0f / (2.0f * rmax * 1.000244140625f);
   int tbits = 1;
   while ((1 << tbits) < 2 * n) ++tbits;
@@ -642,16 +676,16 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
     // the barrier that publishes the substep state also ORs the far-cell
     // test over every wave of the env
     const bool grid = (__syncthreads_or(far_cell) == 0) && use_grid;
-    if (!grid && NW == 1) {
+    if (!grid && N <= 64) {
       // one wave: lane l tests body i against body (i + r) mod n for its
       // share of the rotations r = 1 .. n/2 (two groups of 32 lanes when
       // n <= 32).  Every unordered pair is one rotation away from one of its
       // bodies; at r = n/2 (n even) both see it and the lower one keeps it.
       // The test is symmetric in the two bodies, bit for bit.
       // Eight rotations per batch: their loads issue back to back.
-      const int groups = n <= 32 ? 2 : 1;
-      const int i = n <= 32 ? (tid & 31) : tid;
-      const int g = n <= 32 ? (tid >> 5) : 0;
+      const int groups = n <= N / 2 ? 2 : 1;
+      const int i = groups == 2 ? (tid & (N / 2 - 1)) : tid;
+      const int g = groups == 2 ? tid / (N / 2) : 0;
       const int R = n / 2;
       if (i < n) {
         const float4 me = s.pr[i];
@@ -748,7 +782,7 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
       for (int q = 0; q < NW; ++q) ccount += __popcll(s.rowCand[tid][q]);
     }
     int ctotal;
-    const int cstart = block_excl_scan<NW>(ccount, s.scan, &ctotal);
+    const int cstart = block_excl_scan<N>(ccount, s.scan, &ctotal);
     s.cstart[tid] = cstart;
     if (own) {
       int pos = cstart;
@@ -758,19 +792,20 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
         while (m) {
           const int j = 64 * q + __ffsll((unsigned long long)m) - 1;
           m &= m - 1ull;
-          if (pos < PhysLDS<NW>::CAPC) s.cand[pos] = (uint32_t)tid | ((uint32_t)j << 16);
+          if (pos < PhysLDS<N>::CAPC) s.cand[pos] = (uint32_t)tid | ((uint32_t)j << 16);
           ++pos;
         }
       }
     }
-    if (ctotal > PhysLDS<NW>::CAPC) bad = true;
+    if (ctotal > PhysLDS<N>::CAPC) bad = true;
     __syncthreads();
     // 4a. narrowphase of the pairs with a sphere, one candidate per lane;
     // cube-cube pairs are queued.  A pair in contact takes the next free
     // slot (handed out per wave) and its candidate remembers it, so the
     // order of the slots affects no sum.
-    const int nc = ctotal < PhysLDS<NW>::CAPC ? ctotal : PhysLDS<NW>::CAPC;
-    for (int c0 = 0; c0 < nc; c0 += N) {
+    const int nc = ctotal < PhysLDS<N>::CAPC ? ctotal : PhysLDS<N>::CAPC;
+    const int ncw = wmax(nc);
+    for (int c0 = 0; c0 < ncw; c0 += N) {
       const int k = c0 + tid;
       bool contact = false, cc = false;
       PairAcc acc;
@@ -781,7 +816,7 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
         j = (int)(pr >> 16);
         cc = (s.type[i] != 0) & (s.type[j] != 0);
         if (!cc) {
-          acc = pair_forces<NW, FR>(s, i, j, pc);
+          acc = pair_forces<N, FR>(s, i, j, pc);
           contact = acc.npts > 0;
         } else {
           // box pairs apart along a face axis have no point: not queued
@@ -790,16 +825,16 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
       }
       const uint64_t cm = __ballot(contact), qm = __ballot(cc);
       int kb = 0, qb = 0;
-      if (lane_id() == 0) {
-        if (cm) kb = atomicAdd(&s.kcnt, __popcll(cm));
-        if (qm) qb = atomicAdd(&s.ncc, __popcll(qm));
+      if (lane == lbase) {
+        if (half(cm)) kb = atomicAdd(&s.kcnt, __popcll(half(cm)));
+        if (half(qm)) qb = atomicAdd(&s.ncc, __popcll(half(qm)));
       }
-      kb = __shfl(kb, 0, 64);
-      qb = __shfl(qb, 0, 64);
+      kb = __shfl(kb, lbase, 64);
+      qb = __shfl(qb, lbase, 64);
       if (contact) {
-        const int slot = kb + lanes_below(cm);
+        const int slot = kb + below(cm);
         s.kslot[k] = (uint16_t)slot;
-        if (slot < PhysLDS<NW>::CAPK) {
+        if (slot < PhysLDS<N>::CAPK) {
           s.kres[0][slot] = acc.SF.x; s.kres[1][slot] = acc.SF.y; s.kres[2][slot] = acc.SF.z;
           s.kres[3][slot] = acc.Ti.x; s.kres[4][slot] = acc.Ti.y; s.kres[5][slot] = acc.Ti.z;
           s.kres[6][slot] = acc.Tj.x; s.kres[7][slot] = acc.Tj.y; s.kres[8][slot] = acc.Tj.z;
@@ -807,7 +842,7 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
         atomicOr((unsigned long long*)&s.rowC[i][j >> 6], 1ull << (j & 63));
         atomicOr((unsigned long long*)&s.colC[j][i >> 6], 1ull << (i & 63));
       }
-      if (cc) s.ccl[qb + lanes_below(qm)] = (uint32_t)k | ((uint32_t)i << 10) | ((uint32_t)j << 21);
+      if (cc) s.ccl[qb + below(qm)] = (uint32_t)k | ((uint32_t)i << 10) | ((uint32_t)j << 21);
     }
     // ground: a sphere's single point on its own lane; cubes are queued
     bool gsph = false;
@@ -841,9 +876,9 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
       }
       const uint64_t gm = __ballot(gq);
       int gb = 0;
-      if (lane_id() == 0 && gm) gb = atomicAdd(&s.ngc, __popcll(gm));
-      gb = __shfl(gb, 0, 64);
-      if (gq) s.gcl[gb + lanes_below(gm)] = tid;
+      if (lane == lbase && half(gm)) gb = atomicAdd(&s.ngc, __popcll(half(gm)));
+      gb = __shfl(gb, lbase, 64);
+      if (gq) s.gcl[gb + below(gm)] = tid;
       s.gflag[tid] = gsph ? 1 : 0;
       if (gsph) {
         s.gres[0][tid] = gs.SF.x; s.gres[1][tid] = gs.SF.y; s.gres[2][tid] = gs.SF.z;
@@ -856,8 +891,8 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
     // oracle's point order -- and lanes 0..8 of the group then sum one
     // component each over the points found, in that order.
     const int ncc = s.ncc;
-    const int lane = lane_id();
-    for (int t0 = 0; t0 < 16 * ncc; t0 += N) {
+    const int nccw = wmax(ncc);
+    for (int t0 = 0; t0 < 16 * nccw; t0 += N) {
       const int t = t0 + tid;
       const int r = lane & 15;
       bool hit = false;
@@ -884,24 +919,24 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
       }
       // edge-edge point (after the 16 vertex points in the pair's order)
       bool ehit = false;
-      if constexpr (EE) ehit = edge_point<NW, FR>(s, t < 16 * ncc, r, lane, i, j, pc);
+      if constexpr (EE) ehit = edge_point<N, FR>(s, t < 16 * ncc, r, lane, i, j, pc);
       const uint64_t hm = __ballot(hit);
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       const int g0 = lane & 48;  // the group's first lane in the wave
       const uint32_t gm = (uint32_t)(hm >> g0) & 0xFFFFu;
       float sum = 0.0f;
-      if (r < 9) sum = ordered_sum<16, NW>(s, r, tid - r, gm);
+      if (r < 9) sum = ordered_sum<16, N>(s, r, tid - r, gm);
       if constexpr (EE) {
         if (ehit && r < 9) sum = sum + s.estage[r][tid >> 4];
       }
       const bool any = gm != 0 || ehit;
       const uint64_t lead = __ballot(r == 0 && any);
       int kb = 0;
-      if (lane == 0 && lead) kb = atomicAdd(&s.kcnt, __popcll(lead));
-      kb = __shfl(kb, 0, 64);
+      if (lane == lbase && half(lead)) kb = atomicAdd(&s.kcnt, __popcll(half(lead)));
+      kb = __shfl(kb, lbase, 64);
       if (any) {
-        const int slot = kb + __popcll(lead & ((1ull << g0) - 1ull));
-        if (r < 9 && slot < PhysLDS<NW>::CAPK) s.kres[r][slot] = sum;
+        const int slot = kb + __popcll(half(lead) & ((1ull << (g0 - lbase)) - 1ull));
+        if (r < 9 && slot < PhysLDS<N>::CAPK) s.kres[r][slot] = sum;
         if (r == 0) {
           s.kslot[k] = (uint16_t)slot;
           atomicOr((unsigned long long*)&s.rowC[i][j >> 6], 1ull << (j & 63));
@@ -913,7 +948,8 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
     // 4c. cubes near the ground, 8 lanes each: lane r tests corner r, and
     // lanes 0..5 sum the force and torque components in corner order
     const int ngc = s.ngc;
-    for (int t0 = 0; t0 < 8 * ngc; t0 += N) {
+    const int ngcw = wmax(ngc);
+    for (int t0 = 0; t0 < 8 * ngcw; t0 += N) {
       const int t = t0 + tid;
       const int r = lane & 7;
       bool hit = false;
@@ -938,13 +974,13 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       const uint32_t gm = (uint32_t)(hm >> (lane & 56)) & 0xFFu;
       if (gm != 0 && r < 6) {
-        s.gres[r][b] = ordered_sum<8, NW>(s, r, tid - r, gm);
+        s.gres[r][b] = ordered_sum<8, N>(s, r, tid - r, gm);
         if (r == 0) s.gflag[b] = 1;
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     }
     __syncthreads();
-    if (s.kcnt > PhysLDS<NW>::CAPK) bad = true;
+    if (s.kcnt > PhysLDS<N>::CAPK) bad = true;
     // 5. gather in sorted pair order, then the ground, then integrate.
     // Contacts are taken four at a time so that each level of lookups
     // (candidate index, slot, sums) issues its loads together.
@@ -966,7 +1002,7 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
           for (int u = 0; u < 4; ++u) {
             const int i = ii[u] < 0 ? 0 : ii[u];
             idx[u] = s.kslot[s.cstart[i] + popc_below<NW>(s.rowCand[i], tid)];
-            if (ii[u] < 0 || idx[u] >= PhysLDS<NW>::CAPK) idx[u] = -1;
+            if (ii[u] < 0 || idx[u] >= PhysLDS<N>::CAPK) idx[u] = -1;
           }
           float kv[4][6];
 #pragma unroll
@@ -1006,7 +1042,7 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-              if (!ok[u] || idx[u] >= PhysLDS<NW>::CAPK) idx[u] = -1;
+              if (!ok[u] || idx[u] >= PhysLDS<N>::CAPK) idx[u] = -1;
             float kv[4][6];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -1071,9 +1107,9 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
         cnt += gc ? 1 : 0;
       }
       int tot;
-      const int off = block_excl_scan<NW>(cnt, s.scan, &tot);
-      int32_t* dst = W.contacts + ((int64_t)env * pc.substeps + sub_i) * (1 + 2 * W.pair_cap);
-      if (tid == 0) dst[0] = tot;
+      const int off = block_excl_scan<N>(cnt, s.scan, &tot);
+      int32_t* dst = W.contacts + ((int64_t)(env < 0 ? 0 : env) * pc.substeps + sub_i) * (1 + 2 * W.pair_cap);
+      if (tid == 0 && env >= 0) dst[0] = tot;
       if (own) {
         int pos = off;
 #pragma unroll
@@ -1101,13 +1137,18 @@ __device__ void step_env(PhysLDS<NW>& s, const WorldDev& W, const PhysConsts& pc
                      isfinite(w.z) && isfinite(qw) && isfinite(qx) && isfinite(qy) && isfinite(qz);
     if (!fin) atomicOr(&W.env_flags[env], kFlagNonFinite);
   }
-  if (bad && tid == 0) atomicOr(&W.env_flags[env], kFlagContactOverflow);
+  if (bad && tid == 0 && env >= 0) atomicOr(&W.env_flags[env], kFlagContactOverflow);
 }
 
-// FR: friction; EE: edge-edge points of box pairs
-template <int NW, bool FR, bool EE>
-__global__ __launch_bounds__(64 * NW) void physics_kernel(WorldDev W, PhysConsts pc, PhysLaunch L) {
-  __shared__ PhysLDS<NW> s;
+// FR: friction; EE: edge-edge points of box pairs.  N lanes per env: a
+// workgroup of 64 threads holds two envs at N = 32, one at N = 64; two
+// waves hold one env at N = 128.  Work item w takes envs P w .. P w + P - 1
+// of the list (P envs per workgroup).
+template <int N, bool FR, bool EE>
+__global__ __launch_bounds__(N < 64 ? 64 : N) void physics_kernel(WorldDev W, PhysConsts pc, PhysLaunch L) {
+  constexpr int P = N < 64 ? 64 / N : 1;
+  __shared__ PhysLDS<N> sh[P];
+  const int sub = (int)threadIdx.x / N;
   // The step is latency-bound; a higher issue priority shortens it when it
   // shares CUs with the render phase.
   switch (L.prio) {
@@ -1118,17 +1159,19 @@ __global__ __launch_bounds__(64 * NW) void physics_kernel(WorldDev W, PhysConsts
   }
   if (L.persistent == 0) {
     const int wi = blockIdx.x;
-    if (wi >= L.n_work) return;
-    step_env<NW, FR, EE>(s, W, pc, L.work[wi], L.parity, L.broadphase);
+    if (P * wi >= L.n_work) return;
+    const int item = P * wi + sub;
+    step_env<N, FR, EE>(sh[sub], W, pc, item < L.n_work ? L.work[item] : -1, L.parity, L.broadphase);
     return;
   }
   for (;;) {
-    if (threadIdx.x == 0) s.work = atomicAdd(L.queue, 1);
+    if (threadIdx.x == 0) sh[0].work = atomicAdd(L.queue, 1);
     __syncthreads();
-    const int wi = s.work;
+    const int wi = sh[0].work;
     __syncthreads();
-    if (wi >= L.n_work) return;
-    step_env<NW, FR, EE>(s, W, pc, L.work[wi], L.parity, L.broadphase);
+    if (P * wi >= L.n_work) return;
+    const int item = P * wi + sub;
+    step_env<N, FR, EE>(sh[sub], W, pc, item < L.n_work ? L.work[item] : -1, L.parity, L.broadphase);
   }
 }
 
@@ -1141,33 +1184,37 @@ hipError_t launch_reset_queue(int32_t* q, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int N>
+static void launch_n(bool fr, bool ee, LaunchEvents* ev, bool first, bool last, dim3 g, hipStream_t s,
+                     const WorldDev& w, const PhysConsts& pc, const PhysLaunch& lt) {
+  const dim3 b(N < 64 ? 64 : N);
+  if (!fr && !ee) timed_launch(ev, first, last, physics_kernel<N, false, false>, g, b, 0, s, w, pc, lt);
+  else if (!ee) timed_launch(ev, first, last, physics_kernel<N, true, false>, g, b, 0, s, w, pc, lt);
+  else if (!fr) timed_launch(ev, first, last, physics_kernel<N, false, true>, g, b, 0, s, w, pc, lt);
+  else timed_launch(ev, first, last, physics_kernel<N, true, true>, g, b, 0, s, w, pc, lt);
+}
+
 hipError_t launch_physics(const WorldDev& w, const PhysConsts& pc, const PhysLaunch& l,
                           hipStream_t s, LaunchEvents* ev) {
   if (l.n_work <= 0) return hipSuccess;
-  const int nw = l.max_bodies <= 64 ? 1 : 2;
+  // lanes per env: two envs of at most 32 bodies share a wave when packing
+  // is on; one wave for up to 64 bodies; two for up to 128
+  const int N = (l.max_bodies <= 32 && l.pack == 2) ? 32 : (l.max_bodies <= 64 ? 64 : 128);
+  const int P = N < 64 ? 64 / N : 1;
+  const int items = (l.n_work + P - 1) / P;
   for (int t = 0; t < l.nsteps; ++t) {
     PhysLaunch lt = l;
     lt.parity = (l.parity + t) & 1;
-    const int grid = l.persistent > 0 ? (l.persistent < l.n_work ? l.persistent : l.n_work) : l.n_work;
+    const int grid = l.persistent > 0 ? (l.persistent < items ? l.persistent : items) : items;
     if (l.persistent > 0) {
       hipError_t e = launch_reset_queue(l.queue, s);
       if (e != hipSuccess) return e;
     }
     const bool fr = pc.mu > 0.0f, ee = pc.edge != 0;
-    const int bs = 64 * nw;
     const bool first = t == 0, last = t == l.nsteps - 1;
-    const dim3 g(grid), b(bs);
-    if (nw == 1) {
-      if (!fr && !ee) timed_launch(ev, first, last, physics_kernel<1, false, false>, g, b, 0, s, w, pc, lt);
-      else if (!ee) timed_launch(ev, first, last, physics_kernel<1, true, false>, g, b, 0, s, w, pc, lt);
-      else if (!fr) timed_launch(ev, first, last, physics_kernel<1, false, true>, g, b, 0, s, w, pc, lt);
-      else timed_launch(ev, first, last, physics_kernel<1, true, true>, g, b, 0, s, w, pc, lt);
-    } else {
-      if (!fr && !ee) timed_launch(ev, first, last, physics_kernel<2, false, false>, g, b, 0, s, w, pc, lt);
-      else if (!ee) timed_launch(ev, first, last, physics_kernel<2, true, false>, g, b, 0, s, w, pc, lt);
-      else if (!fr) timed_launch(ev, first, last, physics_kernel<2, false, true>, g, b, 0, s, w, pc, lt);
-      else timed_launch(ev, first, last, physics_kernel<2, true, true>, g, b, 0, s, w, pc, lt);
-    }
+    if (N == 32) launch_n<32>(fr, ee, ev, first, last, dim3(grid), s, w, pc, lt);
+    else if (N == 64) launch_n<64>(fr, ee, ev, first, last, dim3(grid), s, w, pc, lt);
+    else launch_n<128>(fr, ee, ev, first, last, dim3(grid), s, w, pc, lt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

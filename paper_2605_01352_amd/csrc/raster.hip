@@ -397,16 +397,16 @@ __device__ __forceinline__ void store_rec(int4* recs, int r, const Tri& t, int p
 // the rejection pay); a smaller one is expanded into its box's pixels there
 // anyway.
 __device__ __forceinline__ void bin_tile(const Tri& t, int r, int tx, int ty, int x0, int x1, int y0,
-                                         int y1, bool classify, int Wd, int Ht, int ntx,
+                                         int y1, bool classify, int Wd, int Ht, int ntx, int TS,
                                          const int32_t* toff, int32_t* tfill, uint16_t* bins) {
-  const int bx0 = max(x0, tx * kTile), bx1 = min(x1, tx * kTile + kTile - 1);
-  const int by0 = max(y0, ty * kTile), by1 = min(y1, ty * kTile + kTile - 1);
+  const int bx0 = max(x0, tx * TS), bx1 = min(x1, tx * TS + TS - 1);
+  const int by0 = max(y0, ty * TS), by1 = min(y1, ty * TS + TS - 1);
   const bool large = (bx1 - bx0 + 1) * (by1 - by0 + 1) > kSmallMax;
   const int cls = (classify && large) ? tile_class(t.X, t.Y, bx0, bx1, by0, by1) : 1;
   if (cls == 0) return;
-  const bool whole = bx0 == tx * kTile && by0 == ty * kTile &&
-                     bx1 == min(Wd - 1, tx * kTile + kTile - 1) &&
-                     by1 == min(Ht - 1, ty * kTile + kTile - 1);
+  const bool whole = bx0 == tx * TS && by0 == ty * TS &&
+                     bx1 == min(Wd - 1, tx * TS + TS - 1) &&
+                     by1 == min(Ht - 1, ty * TS + TS - 1);
   const int ti = ty * ntx + tx;
   bins[toff[ti] + atomicAdd(&tfill[ti], 1)] = (uint16_t)(r | ((cls == 2 && whole) ? 0x8000 : 0));
 }
@@ -502,15 +502,18 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
   const uint8_t* gpmap = (const uint8_t*)(lds + Lo.pmap);
   const uint8_t* gvmap = (const uint8_t*)(lds + Lo.vmap);
   const int Wd = cam.w, Ht = cam.h;
-  const int ntx = (Wd + kTile - 1) / kTile;
-  const int ntiles = tiles_of(Wd, Ht);
-  const RsLayout RL = rs_layout(cam.n_tris, ntiles, L.smooth != 0);
-  unsigned char* rs = W.rscratch + cam.rs_off + L.parity * RL.total;  // one scratch per state buffer
+  const int tsh = L.tile_shift, TS = 1 << tsh;  // tile edge in pixels
+  const int ntx = (Wd + TS - 1) >> tsh;
+  const int ntiles = tiles_of(Wd, Ht, tsh);
+  // the image's scratch as the host laid it out (a tile table with room
+  // for the smallest tiles)
+  unsigned char* rs = W.rscratch + cam.rs_off + (int64_t)L.parity * cam.rs_total;  // one scratch per state buffer
   int32_t* hdr = (int32_t*)rs;
-  int32_t* ttab = (int32_t*)(rs + RL.tiles);
-  int4* grec = (int4*)(rs + RL.recs);
-  uint16_t* bins = (uint16_t*)(rs + RL.bins);
-  const int bin_cap = (L.bin_limit > 0 && L.bin_limit < RL.bin_cap) ? L.bin_limit : RL.bin_cap;
+  int32_t* ttab = (int32_t*)(rs + 64);
+  int4* grec = (int4*)(rs + cam.rs_recs);
+  uint16_t* bins = (uint16_t*)(rs + cam.rs_bins);
+  const int rs_bin_cap = kBinsPerTri * (cam.n_tris + kClipRecs);
+  const int bin_cap = (L.bin_limit > 0 && L.bin_limit < rs_bin_cap) ? L.bin_limit : rs_bin_cap;
 
   Templates* T = (Templates*)(lds + Lo.tpl);
   BodyLDS B;
@@ -694,15 +697,15 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
         rgb = (uint32_t)r;
         int bb, vid[3];
         prim_vertices(T, B, gpmap[pr], pr, &bb, vid);
-        store_attr((float4*)(rs + RL.attr), r, T, B, Lo.nmax, gvmap, body, face, vid, vp);
+        store_attr((float4*)(rs + cam.rs_attr), r, T, B, Lo.nmax, gvmap, body, face, vid, vp);
       } else {
         rgb = face_color(T, B, Lo.nmax, body, face);
       }
       store_rec(grec, r, t, pr, 1.0f / (float)(double)A, rgb, x0, x1, y0, y1);
-      tx0 = x0 >> 4;
-      ty0 = y0 >> 4;
-      nx = (x1 >> 4) - tx0 + 1;
-      ny = (y1 >> 4) - ty0 + 1;
+      tx0 = x0 >> tsh;
+      ty0 = y0 >> tsh;
+      nx = (x1 >> tsh) - tx0 + 1;
+      ny = (y1 >> tsh) - ty0 + 1;
     }
     if (!tiled) continue;
     const bool wide = nx * ny > kWide;
@@ -741,15 +744,15 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
         int pr, body;
         record_tri(r, &pr, &body, &t);
         tri_pixels(t.X, t.Y, Wd, Ht, &x0, &x1, &y0, &y1);
-        nx = (x1 >> 4) - (x0 >> 4) + 1;
-        ny = (y1 >> 4) - (y0 >> 4) + 1;
+        nx = (x1 >> tsh) - (x0 >> tsh) + 1;
+        ny = (y1 >> tsh) - (y0 >> tsh) + 1;
       }
       const bool wide = nx * ny > kWide;
       if (!wide)
         for (int qy = 0; qy < ny; ++qy)
           for (int qx = 0; qx < nx; ++qx)
-            bin_tile(t, r, (x0 >> 4) + qx, (y0 >> 4) + qy, x0, x1, y0, y1, nx * ny > 1, Wd, Ht, ntx, toff,
-                     tfill, bins);
+            bin_tile(t, r, (x0 >> tsh) + qx, (y0 >> tsh) + qy, x0, x1, y0, y1, nx * ny > 1, Wd, Ht, ntx, TS,
+                     toff, tfill, bins);
       // a wide triangle is binned by the whole wave, one tile per lane; its
       // snapped vertices and pixel box come from its lane's registers
       uint64_t m = __ballot(wide);
@@ -765,12 +768,12 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
         }
         const int jx0 = __builtin_amdgcn_readlane(x0, j), jx1 = __builtin_amdgcn_readlane(x1, j);
         const int jy0 = __builtin_amdgcn_readlane(y0, j), jy1 = __builtin_amdgcn_readlane(y1, j);
-        const int jnx = (jx1 >> 4) - (jx0 >> 4) + 1;
-        const int jn = jnx * ((jy1 >> 4) - (jy0 >> 4) + 1);
+        const int jnx = (jx1 >> tsh) - (jx0 >> tsh) + 1;
+        const int jn = jnx * ((jy1 >> tsh) - (jy0 >> tsh) + 1);
         for (int q = lane; q < jn; q += 64) {
           const int qy = q / jnx;
-          bin_tile(J, jr, (jx0 >> 4) + (q - qy * jnx), (jy0 >> 4) + qy, jx0, jx1, jy0, jy1, true, Wd, Ht,
-                   ntx, toff, tfill, bins);
+          bin_tile(J, jr, (jx0 >> tsh) + (q - qy * jnx), (jy0 >> tsh) + qy, jx0, jx1, jy0, jy1, true, Wd, Ht,
+                   ntx, TS, toff, tfill, bins);
         }
       }
     }
@@ -818,9 +821,22 @@ __global__ void raster_setup_kernel(WorldDev W, RasterLaunch L) {
 // tile kernel
 // ---------------------------------------------------------------------------
 
+// A tile of TS x TS pixels per wave: each lane owns a block of BW x BH
+// pixels, BW adjacent in a row (4, or 1 for 8x8 tiles), BH rows (4 for
+// 32x32 tiles, else 1).
+template <int TS>
+struct TileGeo {
+  static constexpr int BW = TS >= 16 ? 4 : 1;
+  static constexpr int LPR = TS / BW;              // lanes per row of blocks
+  static constexpr int BH = TS * TS / (64 * BW);
+  static constexpr int NPX = BW * BH;              // pixels per lane
+  static_assert(LPR * (64 / LPR) == 64 && (64 / LPR) * BH == TS, "tile shape");
+};
+
+template <int TS>
 struct TileWaveLDS {
-  uint64_t zb[256];     // z-buffer of the small-triangle fragments
-  int32_t own[64];      // fragment owner marks
+  uint64_t zb[TS * TS];  // z-buffer of the small-triangle fragments
+  int32_t own[64];       // fragment owner marks
 };
 
 // Key of a primitive's fragment below its depth: primitive << 24 | RGB8.
@@ -880,9 +896,11 @@ __device__ __forceinline__ uint32_t smooth_color(const int4* grec, const float4*
   return rgb;
 }
 
-template <bool DBG, bool SMOOTH>
+template <bool DBG, bool SMOOTH, int TS>
 __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam, int parity, int ntx,
-                                            int tx, int ty, TileWaveLDS& S, int32_t* cov) {
+                                            int tx, int ty, TileWaveLDS<TS>& S, int32_t* cov) {
+  using G = TileGeo<TS>;
+  constexpr int BW = G::BW, BH = G::BH, NPX = G::NPX;
   const int lane = threadIdx.x & 63;
   const int Wd = cam.w, Ht = cam.h;
   const unsigned char* rs = W.rscratch + cam.rs_off + (int64_t)parity * cam.rs_total;
@@ -897,22 +915,36 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
     k0 = tt[0];
     k1 = k0 + tt[1];
   }
-  const int tx0 = tx * kTile, ty0 = ty * kTile;
-  const int tx1 = min(tx0 + kTile - 1, Wd - 1), ty1 = min(ty0 + kTile - 1, Ht - 1);
-  // this lane's pixels: (px0 + i, py) for i < 4, z-buffer entries 4 lane + i
-  const int py = ty0 + (lane >> 2), px0 = tx0 + 4 * (lane & 3);
+  const int tx0 = tx * TS, ty0 = ty * TS;
+  const int tx1 = min(tx0 + TS - 1, Wd - 1), ty1 = min(ty0 + TS - 1, Ht - 1);
+  // this lane's pixels: (px0 + i, py0 + j) for i < BW, j < BH, z-buffer
+  // entries zrow (j) + i
+  const int bx = lane % G::LPR, by = lane / G::LPR;
+  const int px0 = tx0 + BW * bx, py0 = ty0 + BH * by;
+  const auto zidx = [&](int i, int j) { return (BH * by + j) * TS + BW * bx + i; };
   uint64_t* zb = S.zb;
   // a tile with an empty bin (a third of them in a settled scene) goes
   // straight to the background stores
   const bool empty = k0 == k1;
   if (!empty) {
-    ulonglong2* z2 = (ulonglong2*)(zb + 4 * lane);
-    z2[0] = make_ulonglong2(~0ull, ~0ull);
-    z2[1] = make_ulonglong2(~0ull, ~0ull);
+#pragma unroll
+    for (int j = 0; j < BH; ++j)
+#pragma unroll
+      for (int i = 0; i < BW; ++i) zb[zidx(i, j)] = ~0ull;
   }
-  if (DBG) *(int4*)(cov + 4 * lane) = make_int4(0, 0, 0, 0);
-  uint64_t kreg[4] = {~0ull, ~0ull, ~0ull, ~0ull};
-  int creg[4] = {0, 0, 0, 0};
+  if (DBG) {
+#pragma unroll
+    for (int j = 0; j < BH; ++j)
+#pragma unroll
+      for (int i = 0; i < BW; ++i) cov[zidx(i, j)] = 0;
+  }
+  uint64_t kreg[NPX];
+  int creg[NPX];
+#pragma unroll
+  for (int q = 0; q < NPX; ++q) {
+    kreg[q] = ~0ull;
+    creg[q] = 0;
+  }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
 
   for (int kb = k0; kb < k1; kb += 64) {
@@ -985,8 +1017,9 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
       const int j = (o - 1) & 63;
       const int jxy = __shfl(mxy, j, 64), job = __shfl(mob, j, 64);
       const int rr = f - (job & 0xFFFF), jbw = job >> 16;
-      // rr / jbw exactly: rr < 64 and jbw <= 16 keep the quotient's
-      // fraction at least 1/32 away from an integer
+      // rr / jbw exactly: rr < 64 and jbw <= 32 (a box in a tile of at
+      // most 32 pixels) keep the quotient's fraction at least 1/64 away
+      // from an integer, far above the reciprocal's rounding
       const int qy = (int)(((float)rr + 0.5f) * __builtin_amdgcn_rcpf((float)jbw));
       const int qx = rr - qy * jbw;
       const int e0 = __shfl(E0[0], j, 64) + __mul24(__shfl(sr[0], j, 64), qy) + __mul24(__shfl(sc[0], j, 64), qx);
@@ -1000,7 +1033,7 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
         const uint64_t kk = depth_key((float)e0, (float)e1, (float)e2, z0, z1, z2, invA,
                                       prim_key(jprim, (uint32_t)jrgb));
         const int p = (jxy >> 16) + qy - ty0;  // row in the tile
-        const int pp = p * kTile + (jxy & 0xFFFF) + qx - tx0;
+        const int pp = p * TS + (jxy & 0xFFFF) + qx - tx0;
         atomicMin((unsigned long long*)&zb[pp], (unsigned long long)kk);
         if (DBG) atomicAdd(&cov[pp], 1);
       }
@@ -1021,106 +1054,124 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
       const float z2 = __int_as_float(__builtin_amdgcn_readlane(rc.y, j));
       const float invA = __int_as_float(__builtin_amdgcn_readlane(rc.z, j));
       const uint64_t key = prim_key(__builtin_amdgcn_readlane(rb.z, j), (uint32_t)__builtin_amdgcn_readlane(rc.w, j));
-      double E[3], step[3], thr[3];
+      // edge values at the lane's first pixel, one pixel right, one row
+      // down: exact integers in fp64, so stepping is exact
+      double Er[3], step[3], down[3], thr[3];
 #pragma unroll
       for (int e = 0; e < 3; ++e) {
         const int a0 = (e + 1) % 3, b0 = (e + 2) % 3;
         const int32_t dx = X[b0] - X[a0], dy = Y[b0] - Y[a0];
-        E[e] = fma(-(double)dy, (double)(256 * px0 + 128 - X[a0]), (double)dx * (double)(256 * py + 128 - Y[a0]));
-        step[e] = -(double)dy * 256.0;  // one pixel right
+        Er[e] = fma(-(double)dy, (double)(256 * px0 + 128 - X[a0]), (double)dx * (double)(256 * py0 + 128 - Y[a0]));
+        step[e] = -(double)dy * 256.0;
+        down[e] = (double)dx * 256.0;
         thr[e] = top_left(dx, dy) ? 0.0 : 1.0;
       }
-      if (jfull) {
-        // every pixel of the tile is covered
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const uint64_t kk = depth_key((float)E[0], (float)E[1], (float)E[2], z0, z1, z2, invA, key);
-          kreg[i] = kk < kreg[i] ? kk : kreg[i];
-          if (DBG) creg[i] += 1;
+      for (int j = 0; j < BH; ++j) {
+        double E[3] = {Er[0], Er[1], Er[2]};
+        if (jfull) {
+          // every pixel of the tile is covered
 #pragma unroll
-          for (int e = 0; e < 3; ++e) E[e] += step[e];
+          for (int i = 0; i < BW; ++i) {
+            const int q = j * BW + i;
+            const uint64_t kk = depth_key((float)E[0], (float)E[1], (float)E[2], z0, z1, z2, invA, key);
+            kreg[q] = kk < kreg[q] ? kk : kreg[q];
+            if (DBG) creg[q] += 1;
+#pragma unroll
+            for (int e = 0; e < 3; ++e) E[e] += step[e];
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < BW; ++i) {
+            const int q = j * BW + i;
+            const bool in = (E[0] >= thr[0]) & (E[1] >= thr[1]) & (E[2] >= thr[2]);
+            const uint64_t kk = depth_key((float)E[0], (float)E[1], (float)E[2], z0, z1, z2, invA, key);
+            kreg[q] = (in & (kk < kreg[q])) ? kk : kreg[q];
+            if (DBG) creg[q] += in ? 1 : 0;
+#pragma unroll
+            for (int e = 0; e < 3; ++e) E[e] += step[e];
+          }
         }
-      } else {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const bool in = (E[0] >= thr[0]) & (E[1] >= thr[1]) & (E[2] >= thr[2]);
-          const uint64_t kk = depth_key((float)E[0], (float)E[1], (float)E[2], z0, z1, z2, invA, key);
-          kreg[i] = (in & (kk < kreg[i])) ? kk : kreg[i];
-          if (DBG) creg[i] += in ? 1 : 0;
-#pragma unroll
-          for (int e = 0; e < 3; ++e) E[e] += step[e];
-        }
+        for (int e = 0; e < 3; ++e) Er[e] += down[e];
       }
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
   // resolve: the fragment z-buffer against the registers, then the winners'
-  // colours and the stores
-  uint64_t zk[4] = {~0ull, ~0ull, ~0ull, ~0ull};
-  if (!empty) {
-    const ulonglong2 za = ((const ulonglong2*)(zb + 4 * lane))[0];
-    const ulonglong2 zc = ((const ulonglong2*)(zb + 4 * lane))[1];
-    zk[0] = za.x; zk[1] = za.y; zk[2] = zc.x; zk[3] = zc.y;
-  }
-  // the winner's colour travels in its key
-  uint32_t D[4], rgb[4];
-  int32_t win[4];
+  // colours and the stores, one row of the lane's block at a time
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const uint64_t key = zk[i] < kreg[i] ? zk[i] : kreg[i];
-    const bool hit = key != ~0ull;
-    D[i] = hit ? (uint32_t)(key >> 40) : 0xFFFFFFFFu;
-    rgb[i] = hit ? (uint32_t)key & 0xFFFFFFu : 0u;
-    win[i] = hit ? (int32_t)((key >> 24) & 0xFFFFu) : -1;
-    if constexpr (SMOOTH) {
-      // the key's low bits name the winning record
-      if (hit)
-        rgb[i] = smooth_color(grec, (const float4*)(rs + cam.rs_attr), W.tpl, (int)rgb[i], px0 + i, py);
+  for (int j = 0; j < BH; ++j) {
+    const int py = py0 + j;
+    uint32_t D[BW], rgb[BW];
+    int32_t win[BW];
+#pragma unroll
+    for (int i = 0; i < BW; ++i) {
+      const int q = j * BW + i;
+      const uint64_t zk = empty ? ~0ull : zb[zidx(i, j)];
+      const uint64_t key = zk < kreg[q] ? zk : kreg[q];
+      const bool hit = key != ~0ull;
+      D[i] = hit ? (uint32_t)(key >> 40) : 0xFFFFFFFFu;
+      rgb[i] = hit ? (uint32_t)key & 0xFFFFFFu : 0u;  // the winner's colour travels in its key
+      win[i] = hit ? (int32_t)((key >> 24) & 0xFFFFu) : -1;
+      if constexpr (SMOOTH) {
+        // the key's low bits name the winning record
+        if (hit)
+          rgb[i] = smooth_color(grec, (const float4*)(rs + cam.rs_attr), W.tpl, (int)rgb[i], px0 + i, py);
+      }
     }
-  }
-  if (py <= ty1) {
+    if (py > ty1) continue;
     const int64_t pix = cam.pix_off + (int64_t)py * Wd + px0;
-    if (px0 + 3 <= tx1 && (pix & 3) == 0) {
-      *(uint4*)(W.depth + pix) = make_uint4(D[0], D[1], D[2], D[3]);
-      uint32_t* c = (uint32_t*)(W.rgb + 3 * pix);  // 3 pix is a multiple of 12
-      c[0] = rgb[0] | (rgb[1] << 24);
-      c[1] = (rgb[1] >> 8) | (rgb[2] << 16);
-      c[2] = (rgb[2] >> 16) | (rgb[3] << 8);
-    } else {
+    if constexpr (BW == 4) {
+      if (px0 + 3 <= tx1 && (pix & 3) == 0) {
+        *(uint4*)(W.depth + pix) = make_uint4(D[0], D[1], D[2], D[3]);
+        uint32_t* c = (uint32_t*)(W.rgb + 3 * pix);  // 3 pix is a multiple of 12
+        c[0] = rgb[0] | (rgb[1] << 24);
+        c[1] = (rgb[1] >> 8) | (rgb[2] << 16);
+        c[2] = (rgb[2] >> 16) | (rgb[3] << 8);
+      } else {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        if (px0 + i > tx1) continue;
-        W.depth[pix + i] = D[i];
-        W.rgb[3 * (pix + i)] = (uint8_t)(rgb[i] & 0xFF);
-        W.rgb[3 * (pix + i) + 1] = (uint8_t)((rgb[i] >> 8) & 0xFF);
-        W.rgb[3 * (pix + i) + 2] = (uint8_t)((rgb[i] >> 16) & 0xFF);
+        for (int i = 0; i < BW; ++i) {
+          if (px0 + i > tx1) continue;
+          W.depth[pix + i] = D[i];
+          W.rgb[3 * (pix + i)] = (uint8_t)(rgb[i] & 0xFF);
+          W.rgb[3 * (pix + i) + 1] = (uint8_t)((rgb[i] >> 8) & 0xFF);
+          W.rgb[3 * (pix + i) + 2] = (uint8_t)((rgb[i] >> 16) & 0xFF);
+        }
+      }
+    } else {
+      if (px0 <= tx1) {
+        W.depth[pix] = D[0];
+        W.rgb[3 * pix] = (uint8_t)(rgb[0] & 0xFF);
+        W.rgb[3 * pix + 1] = (uint8_t)((rgb[0] >> 8) & 0xFF);
+        W.rgb[3 * pix + 2] = (uint8_t)((rgb[0] >> 16) & 0xFF);
       }
     }
     if (DBG) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
+      for (int i = 0; i < BW; ++i) {
         if (px0 + i > tx1) continue;
         W.winners[pix + i] = win[i];
-        W.coverage[pix + i] = cov[4 * lane + i] + creg[i];
+        W.coverage[pix + i] = cov[zidx(i, j)] + creg[j * BW + i];
       }
     }
   }
 }
 
-template <bool DBG, bool SMOOTH>
+template <bool DBG, bool SMOOTH, int TS>
 __global__ void __launch_bounds__(64 * kTileWaves) raster_tile_kernel(WorldDev W, RasterLaunch L) {
-  __shared__ TileWaveLDS S[kTileWaves];
-  __shared__ int32_t C[DBG ? kTileWaves : 1][DBG ? 256 : 1];
+  __shared__ TileWaveLDS<TS> S[kTileWaves];
+  __shared__ int32_t C[DBG ? kTileWaves : 1][DBG ? TS * TS : 1];
   const int2 job = L.tiles[blockIdx.x];
   if (job.x < 0) return;
   // uniform per wave: tile bookkeeping stays in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const CamDev cam = W.cams[job.x];
-  const int ntx = (cam.w + kTile - 1) / kTile;
+  const int ntx = (cam.w + TS - 1) / TS;
   const int tx = (job.y & 0xFFFF) + wave, ty = job.y >> 16;
   if (tx >= ntx) return;  // no workgroup barrier follows
-  raster_tile<DBG, SMOOTH>(W, cam, L.parity, ntx, tx, ty, S[wave], DBG ? C[wave] : nullptr);
+  raster_tile<DBG, SMOOTH, TS>(W, cam, L.parity, ntx, tx, ty, S[wave], DBG ? C[wave] : nullptr);
 }
 
 }  // namespace
@@ -1152,16 +1203,23 @@ hipError_t launch_raster_setup(const WorldDev& w, const RasterLaunch& l, hipStre
   return hipGetLastError();
 }
 
-hipError_t launch_raster_tiles(const WorldDev& w, const RasterLaunch& l, hipStream_t s, LaunchEvents* ev) {
-  if (l.n_tile_groups <= 0) return hipSuccess;
+template <int TS>
+static void launch_tiles(const WorldDev& w, const RasterLaunch& l, hipStream_t s, LaunchEvents* ev) {
   const dim3 g(l.n_tile_groups), b(64 * kTileWaves);
   if (l.smooth) {
-    if (w.winners) timed_launch(ev, true, true, raster_tile_kernel<true, true>, g, b, 0, s, w, l);
-    else timed_launch(ev, true, true, raster_tile_kernel<false, true>, g, b, 0, s, w, l);
+    if (w.winners) timed_launch(ev, true, true, raster_tile_kernel<true, true, TS>, g, b, 0, s, w, l);
+    else timed_launch(ev, true, true, raster_tile_kernel<false, true, TS>, g, b, 0, s, w, l);
   } else {
-    if (w.winners) timed_launch(ev, true, true, raster_tile_kernel<true, false>, g, b, 0, s, w, l);
-    else timed_launch(ev, true, true, raster_tile_kernel<false, false>, g, b, 0, s, w, l);
+    if (w.winners) timed_launch(ev, true, true, raster_tile_kernel<true, false, TS>, g, b, 0, s, w, l);
+    else timed_launch(ev, true, true, raster_tile_kernel<false, false, TS>, g, b, 0, s, w, l);
   }
+}
+
+hipError_t launch_raster_tiles(const WorldDev& w, const RasterLaunch& l, hipStream_t s, LaunchEvents* ev) {
+  if (l.n_tile_groups <= 0) return hipSuccess;
+  if (l.tile_shift == 3) launch_tiles<8>(w, l, s, ev);
+  else if (l.tile_shift == 5) launch_tiles<32>(w, l, s, ev);
+  else launch_tiles<16>(w, l, s, ev);
   return hipGetLastError();
 }
 

@@ -19,7 +19,8 @@ constexpr int kMaxTplFaces = 128;   // faces per template
 constexpr int kMaxGroundVerts = 8;
 constexpr int kMaxGroundFaces = 8;
 constexpr int kGroundPair = 0xFFFF;
-constexpr int kTile = 16;           // raster tile edge in pixels
+constexpr int kTile = 16;           // default raster tile edge in pixels
+constexpr int kTileShiftMin = 3, kTileShiftMax = 5;  // tile edges 8, 16 and 32
 
 // env flags (device-side, sticky until fetched)
 constexpr uint32_t kFlagNonFinite = 1u;
@@ -86,8 +87,10 @@ __host__ __device__ inline RsLayout rs_layout(int32_t ntris, int32_t ntiles, boo
   return r;
 }
 
-__host__ __device__ inline int32_t tiles_of(int32_t w, int32_t h) {
-  return ((w + kTile - 1) / kTile) * ((h + kTile - 1) / kTile);
+// tiles of edge 1 << shift covering a w x h image
+__host__ __device__ inline int32_t tiles_of(int32_t w, int32_t h, int shift = 4) {
+  const int t = 1 << shift;
+  return ((w + t - 1) >> shift) * ((h + t - 1) >> shift);
 }
 
 // Mesh templates and shading constants (device copy of the descriptor).
@@ -166,6 +169,7 @@ struct PhysLaunch {
   int32_t* queue;          // persistent work counter (one int), nullable otherwise
   int32_t prio;            // wave issue priority 0..3 (s_setprio) of the physics waves
   int32_t broadphase;      // 0 auto, 1 uniform grid hash, 2 all pairs
+  int32_t pack;            // envs per wave when every env has at most 32 bodies (1 or 2)
 };
 
 struct RasterLaunch {
@@ -186,6 +190,7 @@ struct RasterLaunch {
   int32_t prio;            // setup kernel: wave issue priority 0..3 (s_setprio)
   int32_t near_clip;       // setup kernel: cut triangles crossing the near plane
   int32_t smooth;          // per-pixel shading of interpolated vertex normals
+  int32_t tile_shift;      // raster tiles of edge 1 << tile_shift (8, 16 or 32 pixels)
 };
 
 // Timing events of one launch (a kernel or a chain of them): `start` is

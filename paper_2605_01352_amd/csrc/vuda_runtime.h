@@ -90,6 +90,8 @@ struct Tuning {
   bool timing = false;
   bool presetup = true;
   bool policy_layered = false;  // layers 2-3 as batched products at any hidden size
+  int32_t phys_pack = 1;         // envs of at most 32 bodies per physics wave (1 or 2)
+  int32_t tile_shift = 4;        // raster tile edge 1 << tile_shift pixels
 };
 
 // kernels of the step loop (index of their timing events)

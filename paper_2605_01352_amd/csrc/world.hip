@@ -334,7 +334,7 @@ int64_t vuda_world::rs_units(const vuda_env_batch& b) const {
   for (int32_t e = 0; e < b.n_envs; ++e) {
     const int32_t nt = env_tris(b, e);
     for (int32_t c = b.cam_off[e]; c < b.cam_off[e + 1]; ++c)
-      u += 2 * (rs_layout(nt, tiles_of(b.cam_w[c], b.cam_h[c]), smooth).total / 256);
+      u += 2 * (rs_layout(nt, tiles_of(b.cam_w[c], b.cam_h[c], kTileShiftMin), smooth).total / 256);
   }
   return u;
 }
@@ -385,7 +385,8 @@ int vuda_world::upload(const vuda_env_batch& b, int32_t e0, int64_t b0, int32_t 
       d.env = e0 + e;
       d.n_tris = nt;
       d.rs_off = ro;
-      const RsLayout rl = rs_layout(nt, tiles_of(d.w, d.h), smooth);
+      // the tile table has room for the smallest tiles
+      const RsLayout rl = rs_layout(nt, tiles_of(d.w, d.h, kTileShiftMin), smooth);
       d.rs_recs = (int32_t)rl.recs;
       d.rs_bins = (int32_t)rl.bins;
       d.rs_total = (int32_t)rl.total;
@@ -795,7 +796,7 @@ int vuda_world::get_list(int phase, int32_t lo, int32_t hi, const WorkList** out
     } else {
       for (int32_t c = d.cam_off; c < d.cam_off + d.n_cams; ++c) {
         const CamDev& cd = cam_host[c];
-        const int tiles = ((cd.w + kTile - 1) / kTile) * ((cd.h + kTile - 1) / kTile);
+        const int tiles = tiles_of(cd.w, cd.h, tune.tile_shift);
         items.push_back({(int64_t)cd.w * cd.h + 64LL * d.n_tris, c});
         L.max_bodies = std::max(L.max_bodies, d.n_bodies);
         L.max_verts = std::max(L.max_verts, d.n_verts);
@@ -831,7 +832,8 @@ int vuda_world::get_list(int phase, int32_t lo, int32_t hi, const WorkList** out
     std::vector<std::vector<int2>> per(kXcd);
     for (size_t i = 0; i < ids.size(); ++i) {
       const CamDev& cd = cam_host[ids[i]];
-      const int32_t ntx = (cd.w + kTile - 1) / kTile, nty = (cd.h + kTile - 1) / kTile;
+      const int ts = 1 << tune.tile_shift;
+      const int32_t ntx = (cd.w + ts - 1) >> tune.tile_shift, nty = (cd.h + ts - 1) >> tune.tile_shift;
       for (int32_t ty = 0; ty < nty; ++ty)
         for (int32_t tx = 0; tx < ntx; tx += 4) per[i % kXcd].push_back(make_int2(ids[i], tx | (ty << 16)));
     }
@@ -889,6 +891,7 @@ int vuda_world::enqueue_physics(const WorkList& L, int parity, hipStream_t s, La
   pl.queue = queues;
   pl.prio = tune.phys_prio;
   pl.broadphase = tune.broadphase;
+  pl.pack = tune.phys_pack;
   HIPCHK(launch_physics(dev, pc, pl, s, ev));
   return VUDA_OK;
 }
@@ -911,6 +914,7 @@ int vuda_world::raster_launch_of(const WorkList& L, int parity, int32_t* queue, 
   rl.prio = 0;
   rl.near_clip = near_clip ? 1 : 0;
   rl.smooth = smooth ? 1 : 0;
+  rl.tile_shift = tune.tile_shift;
   const size_t lds = raster_lds_bytes(rl);
   const size_t kLdsMax = 160 * 1024;
   if (lds > kLdsMax)
@@ -1810,7 +1814,7 @@ extern "C" int vuda_release(vuda_world* w, int32_t first, int32_t n) {
     p0 = c0.pix_off;
     np = c1.pix_off + (int64_t)c1.w * c1.h - p0;
     r0 = c0.rs_off / 256;
-    nr = (c1.rs_off + 2 * rs_layout(c1.n_tris, tiles_of(c1.w, c1.h), w->smooth).total) / 256 - r0;
+    nr = (c1.rs_off + 2 * rs_layout(c1.n_tris, tiles_of(c1.w, c1.h, kTileShiftMin), w->smooth).total) / 256 - r0;
   }
   std::vector<EnvDev> empty(n, EnvDev{});
   HIPCHK(hipMemcpy(w->dev.envs + first, empty.data(), sizeof(EnvDev) * n, hipMemcpyHostToDevice));
@@ -1878,6 +1882,23 @@ extern "C" int vuda_set_tuning(vuda_world* w, int32_t key, int32_t value) {
       if (value < 0 || value > 1) return fail(VUDA_EINVAL, "policy layered %d", value);
       w->tune.policy_layered = value != 0;
       break;
+    case VUDA_TUNE_PHYS_ENVS_PER_WAVE:
+      if (value != 1 && value != 2) return fail(VUDA_EINVAL, "envs per wave %d (1 or 2)", value);
+      w->tune.phys_pack = value;
+      break;
+    case VUDA_TUNE_TILE_SIZE: {
+      if (value != 8 && value != 16 && value != 32) return fail(VUDA_EINVAL, "tile size %d (8, 16 or 32)", value);
+      const int sh = value == 8 ? 3 : (value == 16 ? 4 : 5);
+      if (sh != w->tune.tile_shift) {
+        // tile jobs and the setups of the states already set up change
+        int rc = w->drain();
+        if (rc) return rc;
+        w->tune.tile_shift = sh;
+        std::fill(w->setup_ok.begin(), w->setup_ok.end(), 0);
+        w->invalidate_lists();
+      }
+      return VUDA_OK;
+    }
     default:
       return fail(VUDA_EINVAL, "tuning key %d", key);
   }
@@ -1899,6 +1920,8 @@ extern "C" int vuda_get_tuning(vuda_world* w, int32_t key, int32_t* value) {
     case VUDA_TUNE_TIMING: *value = w->tune.timing ? 1 : 0; break;
     case VUDA_TUNE_PRESETUP: *value = w->tune.presetup ? 1 : 0; break;
     case VUDA_TUNE_POLICY_LAYERED: *value = w->tune.policy_layered ? 1 : 0; break;
+    case VUDA_TUNE_PHYS_ENVS_PER_WAVE: *value = w->tune.phys_pack; break;
+    case VUDA_TUNE_TILE_SIZE: *value = 1 << w->tune.tile_shift; break;
     default: return fail(VUDA_EINVAL, "tuning key %d", key);
   }
   return VUDA_OK;

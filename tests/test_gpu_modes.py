@@ -87,6 +87,10 @@ C2 = dict(cfg=2, n_envs=48, settle=250)
      {vuda.TUNE_PHYS_PERSISTENT: 24, vuda.TUNE_RASTER_PERSISTENT: 40, vuda.TUNE_GRAPHS: 1}),
     ("persistent launches + graphs, unmasked, inter-trajectory", 2.0, vuda.SCHED_INTERTRAJ,
      {vuda.TUNE_PHYS_PERSISTENT: 256, vuda.TUNE_RASTER_PERSISTENT: 256, vuda.TUNE_GRAPHS: 1}),
+    ("two envs per physics wave, unmasked, inter-step", 2.0, vuda.SCHED_INTERSTEP,
+     {vuda.TUNE_PHYS_ENVS_PER_WAVE: 2}),
+    ("two envs per physics wave, persistent, CU-masked 0.375, inter-trajectory", 0.375, vuda.SCHED_INTERTRAJ,
+     {vuda.TUNE_PHYS_ENVS_PER_WAVE: 2, vuda.TUNE_PHYS_PERSISTENT: 7}),
 ])
 def test_c2_schedule_parity(label, split, sched, knobs):
     """48 envs of the 1024-env config, 250 steps past the spawn (a settled
@@ -182,3 +186,21 @@ def test_grid_far_from_origin_falls_back():
     with vuda.World(scene, debug=True) as w:
         w.set_tuning(vuda.TUNE_BROADPHASE, 1)
         parity_iterations(w, scene, vuda.SCHED_SERIAL, 4, "pile of 100 at (600, -600), forced grid")
+
+
+@pytest.mark.parametrize("n_envs", [1, 7, 33])
+def test_two_envs_per_wave_uneven(n_envs):
+    """Two envs per physics wave over envs of 4..32 bodies of different
+    sizes (the uneven config's small envs), an odd count leaving one half of
+    the last wave empty, forced grid and all-pairs broadphase, friction."""
+    oracle.lib()
+    base = sg.config_scene(4, n_envs=200)
+    small = [e for e in range(base.n_envs) if base.counts()[e] <= 32][:n_envs]
+    scene = base.subset(small)
+    for bp, mu in ((0, 0.0), (1, 0.0), (2, 0.5)):
+        import dataclasses
+        sc = dataclasses.replace(scene, mu=mu)
+        with settled_world(sc, 120) as w:
+            w.set_tuning(vuda.TUNE_PHYS_ENVS_PER_WAVE, 2)
+            w.set_tuning(vuda.TUNE_BROADPHASE, bp)
+            parity_iterations(w, sc, vuda.SCHED_SERIAL, 3, f"{n_envs} small envs, two per wave, broadphase {bp}, mu {mu}")

@@ -127,7 +127,10 @@ def test_tuning_knobs_do_not_change_outputs():
                   {vuda.TUNE_REC_CAP: 64}, {vuda.TUNE_REC_CAP: 5000}, {vuda.TUNE_PHYS_PERSISTENT: 7, vuda.TUNE_RASTER_PERSISTENT: 5},
                   {vuda.TUNE_GRAPHS: 1}, {vuda.TUNE_BROADPHASE: 1}, {vuda.TUNE_BROADPHASE: 2},
                   {vuda.TUNE_PHYS_PRIORITY: 3}, {vuda.TUNE_PRESETUP: 0},
-                  {vuda.TUNE_PRESETUP: 0, vuda.TUNE_GRAPHS: 1}, {vuda.TUNE_RASTER_PERSISTENT: 3}):
+                  {vuda.TUNE_PRESETUP: 0, vuda.TUNE_GRAPHS: 1}, {vuda.TUNE_RASTER_PERSISTENT: 3},
+                  {vuda.TUNE_PHYS_ENVS_PER_WAVE: 2}, {vuda.TUNE_PHYS_ENVS_PER_WAVE: 2, vuda.TUNE_PHYS_PERSISTENT: 5},
+                  {vuda.TUNE_TILE_SIZE: 8}, {vuda.TUNE_TILE_SIZE: 32},
+                  {vuda.TUNE_TILE_SIZE: 32, vuda.TUNE_REC_CAP: 64}):
         with vuda.World(s) as w:
             for k, v in knobs.items():
                 w.set_tuning(k, v)
@@ -186,3 +189,33 @@ def test_near_plane_piece_overflow_is_reported():
         with pytest.raises(vuda.VudaError) as err:
             w.wait()
         assert err.value.code == vuda.EOVERFLOW
+
+
+@pytest.mark.parametrize("tile", [8, 32])
+def test_tile_sizes_against_the_oracle(tile):
+    """Raster tiles of 8x8 and 32x32 pixels (16x16 is the default every
+    other test uses): winners, coverage and depth bit-exact and RGB within 1
+    on c1, envs of c2 (spawn and settled), c3's 256^2 ring cameras, c4's
+    mixed sizes, 640x480, a 100x61 image, smooth shading, and the tile size
+    switched between steps of one world."""
+    import dataclasses
+    cases = [sg.config_scene(1, n_envs=4), sg.config_scene(2, n_envs=8), sg.config_scene(3, n_envs=2),
+             sg.config_scene(4, n_envs=16), dataclasses.replace(sg.config_scene(2, n_envs=3), smooth=True)]
+    wide = sg.config_scene(2, n_envs=2)
+    wide.cam_w[:] = [640, 100]
+    wide.cam_h[:] = [480, 61]
+    wide.cam_vp[0] = sg.view_proj(sg.FIXED_EYE, aspect=640.0 / 480.0).reshape(16)
+    cases.append(wide)
+    for sc in cases:
+        with vuda.World(sc, debug=True) as w:
+            w.set_tuning(vuda.TUNE_TILE_SIZE, tile)
+            compare_render(w, sc)
+            for _ in range(60):
+                w.step()
+            compare_render(w, sc)
+            w.set_tuning(vuda.TUNE_TILE_SIZE, 16)
+            w.step()
+            compare_render(w, sc)
+            w.set_tuning(vuda.TUNE_TILE_SIZE, tile)
+            compare_render(w, sc)
+        say(f"tile {tile}: {sc.name} {sc.n_cams} frames bit-exact")

@@ -21,7 +21,7 @@ METRIC = "env-steps/s (sim+render) co-scheduled vs serialized; p99 rollout laten
 HBM_PEAK_GBS = 8000.0
 CSRC = os.path.join(ROOT, "paper_2605_01352_amd", "csrc")
 KERNEL_SOURCES = {"raster_tiles": ["raster.hip", "vuda_internal.h"], "raster_setup": ["raster.hip", "vuda_internal.h"],
-                  "physics": ["physics.hip", "vuda_internal.h"]}
+                  "raster_fused": ["raster.hip", "vuda_internal.h"], "physics": ["physics.hip", "vuda_internal.h"]}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.md")
 
 
@@ -68,7 +68,7 @@ def launch_stats(vuda, w):
     stream the kernel runs on."""
     out = {}
     for name, k in (("physics", vuda.KERNEL_PHYSICS), ("raster_setup", vuda.KERNEL_RASTER_SETUP),
-                    ("raster_tiles", vuda.KERNEL_RASTER_TILES)):
+                    ("raster_tiles", vuda.KERNEL_RASTER_TILES), ("raster_fused", vuda.KERNEL_RASTER_FUSED)):
         t = w.kernel_times(k)
         n = max(1, t["launches"])
         out[name] = {"launches": t["launches"], "avg_s": t["total_ms"] * 1e-3 / n, "max_s": t["max_ms"] * 1e-3}
@@ -80,8 +80,8 @@ def phase_seconds(st, steps, presetup):
     raster setup belongs to the step with presetup, to the render without."""
     per = {k: v["avg_s"] * v["launches"] / steps for k, v in st.items()}
     if presetup:
-        return per["physics"] + per["raster_setup"], per["raster_tiles"]
-    return per["physics"], per["raster_setup"] + per["raster_tiles"]
+        return per["physics"] + per["raster_setup"], per["raster_tiles"] + per["raster_fused"]
+    return per["physics"], per["raster_setup"] + per["raster_tiles"] + per["raster_fused"]
 
 
 def source_hash(kernel):
@@ -360,6 +360,44 @@ def physics_leg(torch, vuda, scene, start, steps, log):
     return out
 
 
+def uneven_c4_leg(torch, vuda, scene, start, steps, log):
+    """The uneven config (Poisson body counts, mixed frame sizes) from `start`
+    steps past the spawn: the serialized loop with default launches, the
+    choice of vuda_autotune (schedule, CU split, persistent grids, graphs,
+    tile size, raster path, ...) applied and timed, and the config's own
+    launch plan -- one persistent launch per phase and graph-captured steps
+    -- on the tuned split.  Medians of 3 windows."""
+    n = scene.n_envs
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    with vuda.World(scene) as w:
+        w.step(nsteps=start)
+        w.wait()
+        st0 = w.state()
+
+        def med(sched):
+            return sorted(timed(torch, w, sched, n, steps, 5, st0) for _ in range(3))[1]
+
+        w.cosched(0.0)
+        ser = n * steps / med("serial")
+        w.load_state(st0)
+        t0 = time.perf_counter()
+        choice = w.autotune(steps=10)
+        t_tune = time.perf_counter() - t0
+        sched = vuda.SCHED_NAMES[int(choice["schedule"])]
+        tuned = n * steps / med(sched)
+        for k, v in ((vuda.TUNE_PHYS_PERSISTENT, ncu), (vuda.TUNE_RASTER_PERSISTENT, 2 * ncu), (vuda.TUNE_GRAPHS, 1)):
+            w.set_tuning(k, v)
+        plan = n * steps / med(sched)
+    out = {"envs": n, "bodies": int(scene.n_bodies), "from_step": start, "serialized": round(ser, 1),
+           "autotuned": round(tuned, 1), "speedup_vs_serialized": round(tuned / ser, 4),
+           "autotune_choice": {k: (round(v, 1) if isinstance(v, float) else v) for k, v in choice.items()},
+           "autotune_seconds": round(t_tune, 2),
+           "persistent_graphs_on_tuned_split": round(plan, 1)}
+    log(f"c4: serialized {ser:.0f}, autotuned ({sched}@{choice['cu_split']:g}) {tuned:.0f} env-steps/s "
+        f"({tuned / ser:.3f}x); persistent + graphs {plan:.0f}; choice {choice}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -372,6 +410,7 @@ def main():
     ap.add_argument("--envs", type=int, default=None, help="fewer envs (debug only)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the physics leg at the 4096-env config")
+    ap.add_argument("--no-c4", action="store_true", help="skip the autotuned leg at the uneven 2048-env config")
     ap.add_argument("--serve-seconds", type=float, default=120.0,
                     help="length of the continuous-batching serving run (0: skip)")
     ap.add_argument("--capacity-rates", default="100,200,400,800",
@@ -392,6 +431,9 @@ def main():
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--tune", default="", help="tuning knobs key=value,... (e.g. raster_threads=512)")
+    ap.add_argument("--raster", default="auto", choices=["auto", "two", "fused"],
+                    help="render path: setup + tile kernels, the fused kernel, or both measured (auto)")
+    ap.add_argument("--fused-threads", type=int, default=512, help="workgroup size of the fused raster kernel")
     ap.add_argument("--policy-hidden", default="256,4096",
                     help="hidden sizes of the MLP policy loops measured after the main run (0: skip); "
                          "the profiling modes take the first")
@@ -419,6 +461,9 @@ def main():
         t0 = time.perf_counter()
         scene3 = sg.config_scene(3, workers=workers)
         log(f"built scene c3 in {time.perf_counter() - t0:.1f} s")
+    scene4 = None
+    if scene3 is not None and not args.no_c4:
+        scene4 = sg.config_scene(4, workers=workers)
 
     import torch
     from paper_2605_01352_amd import vuda
@@ -437,7 +482,8 @@ def main():
                 "raster_persistent": vuda.TUNE_RASTER_PERSISTENT, "graphs": vuda.TUNE_GRAPHS,
                 "phys_prio": vuda.TUNE_PHYS_PRIORITY, "broadphase": vuda.TUNE_BROADPHASE,
                 "presetup": vuda.TUNE_PRESETUP, "policy_layered": vuda.TUNE_POLICY_LAYERED,
-                "phys_pack": vuda.TUNE_PHYS_ENVS_PER_WAVE, "tile": vuda.TUNE_TILE_SIZE}
+                "phys_pack": vuda.TUNE_PHYS_ENVS_PER_WAVE, "tile": vuda.TUNE_TILE_SIZE,
+                "fused": vuda.TUNE_RASTER_FUSED, "fused_recs": vuda.TUNE_FUSED_LDS_RECORDS}
     for kv in filter(None, args.tune.split(",")):
         k, v = kv.split("=")
         w.set_tuning(knob_ids[k], int(v))
@@ -499,17 +545,36 @@ def main():
         w.set_tuning(vuda.TUNE_TIMING, 0)
         return st
 
+    # render paths measured: the setup and tile kernels, and the fused kernel
+    # (records and bins in LDS)
+    two_threads = w.get_tuning(vuda.TUNE_RASTER_THREADS)
+    path_knobs = {"two": {vuda.TUNE_RASTER_FUSED: 0, vuda.TUNE_RASTER_THREADS: two_threads},
+                  "fused": {vuda.TUNE_RASTER_FUSED: 1, vuda.TUNE_RASTER_THREADS: args.fused_threads}}
+    paths = ["two", "fused"] if args.raster == "auto" else [args.raster]
+
+    def set_path(path):
+        for k, v in path_knobs[path].items():
+            w.set_tuning(k, v)
+
     w.set_tuning(vuda.TUNE_TIMING, 0)
     w.cosched(0.0)
-    dt_ser, ser_windows = median_windows("serial")
+    ser_paths = {}
+    for path in paths:
+        set_path(path)
+        ser_paths[path] = median_windows("serial")
+        log(f"serialized, {path} raster: {n_envs * args.steps / ser_paths[path][0]:.0f} env-steps/s")
+    ser_path = min(ser_paths, key=lambda p: ser_paths[p][0])
+    dt_ser, ser_windows = ser_paths[ser_path]
+    set_path(ser_path)
     alone = kernel_run("serial")
     presetup = w.get_tuning(vuda.TUNE_PRESETUP) != 0
     Ts, Tr = phase_seconds(alone, args.steps, presetup)
     ser = n_envs * args.steps / dt_ser
-    log(f"serialized: {ser:.0f} env-steps/s (median of {len(ser_windows)} windows); per step alone: step phase "
-        f"{Ts*1e6:.1f} us, render phase {Tr*1e6:.1f} us, bound {(Ts + Tr) / max(Ts, Tr):.3f}x "
+    log(f"serialized ({ser_path} raster): {ser:.0f} env-steps/s (median of {len(ser_windows)} windows); per step "
+        f"alone: step phase {Ts*1e6:.1f} us, render phase {Tr*1e6:.1f} us, bound {(Ts + Tr) / max(Ts, Tr):.3f}x "
         f"(physics {alone['physics']['avg_s']*1e6:.1f}, setup {alone['raster_setup']['avg_s']*1e6:.1f}, "
-        f"tiles {alone['raster_tiles']['avg_s']*1e6:.1f} us per launch)")
+        f"tiles {alone['raster_tiles']['avg_s']*1e6:.1f}, fused {alone['raster_fused']['avg_s']*1e6:.1f} us "
+        f"per launch)")
     # co-scheduled candidates: unmasked streams and CU splits, both overlap
     # patterns; on unmasked streams also raised issue priorities of the step's
     # waves (they share CUs with the render's)
@@ -518,28 +583,39 @@ def main():
     cands = [(2.0, sched, p0) for sched in ("interstep", "intertraj")]
     cands += [(2.0, sched, p) for p in prios for sched in ("interstep", "intertraj")]
     cands += [(float(x), sched, p0) for x in filter(None, args.splits.split(",")) for sched in ("interstep", "intertraj")]
+    cands = [c + (path,) for path in paths for c in cands]
     if args.only:
         cands = []
     sweep = {}
 
-    def name(sched, split, prio):
-        return f"{sched}@{split:g}" + (f"/p{prio}" if prio != p0 else "")
+    def name(sched, split, prio, path):
+        return f"{sched}@{split:g}" + (f"/p{prio}" if prio != p0 else "") + ("/fused" if path == "fused" else "")
 
-    def apply(split, prio):
+    def parse(nm):
+        sched, rest = nm.split("@")
+        tok = rest.split("/")
+        prio, path = p0, "two"
+        for t in tok[1:]:
+            if t == "fused":
+                path = "fused"
+            elif t.startswith("p"):
+                prio = int(t[1:])
+        return sched, float(tok[0]), prio, path
+
+    def apply(split, prio, path):
         w.cosched(split)
         w.set_tuning(vuda.TUNE_PHYS_PRIORITY, prio)
+        set_path(path)
 
-    for split, sched, prio in cands:
-        apply(split, prio)
+    for split, sched, prio, path in cands:
+        apply(split, prio, path)
         dt = timed(torch, w, sched, n_envs, args.steps, args.warmup, st0)
-        sweep[name(sched, split, prio)] = n_envs * args.steps / dt
-        log(f"  {name(sched, split, prio):20s}: {n_envs * args.steps / dt:.0f} env-steps/s")
+        nm = name(sched, split, prio, path)
+        sweep[nm] = n_envs * args.steps / dt
+        log(f"  {nm:26s}: {n_envs * args.steps / dt:.0f} env-steps/s")
     best = args.only or max(sweep, key=sweep.get)
-    sched, rest = best.split("@")
-    split, _, ps = rest.partition("/p")
-    split = float(split)
-    prio = int(ps) if ps else p0
-    apply(split, prio)
+    sched, split, prio, path = parse(best)
+    apply(split, prio, path)
     dt, co_windows = median_windows(sched)
     value = n_envs * args.steps / dt
     live = kernel_run(sched)
@@ -554,7 +630,8 @@ def main():
     body_cams = int(sum(scene.counts()[e] * (scene.cam_off[e + 1] - scene.cam_off[e]) for e in range(n_envs)))
     # algorithmic bytes: the raster setup reads 28 B of pose per body and
     # camera, the tile kernel writes 7 B per pixel
-    step_bytes = {"physics": 120 * scene.n_bodies, "raster_setup": 28 * body_cams, "raster_tiles": 7 * px}
+    step_bytes = {"physics": 120 * scene.n_bodies, "raster_setup": 28 * body_cams, "raster_tiles": 7 * px,
+                  "raster_fused": 28 * body_cams + 7 * px}
     per_step = {k: live[k]["launches"] / args.steps for k in step_bytes}
     kinds = {}
     for kname in step_bytes:
@@ -581,6 +658,10 @@ def main():
     if scene3 is not None:
         c3 = physics_leg(torch, vuda, scene3, sg.CONFIG_STEPS[3] // 2, 20, log)
         del scene3
+    c4 = None
+    if scene4 is not None:
+        c4 = uneven_c4_leg(torch, vuda, scene4, sg.CONFIG_STEPS[4] // 2, 100, log)
+        del scene4
 
     policy = None
     if hiddens and not args.only:
@@ -625,12 +706,15 @@ def main():
         "config": {"workload": CONFIG_NAMES.get(cfg, f"c{cfg}"), "envs": n_envs,
                    "bodies": int(scene.n_bodies), "cameras": int(scene.n_cams),
                    "schedule": sched, "cu_split": split, "step_priority": prio,
+                   "raster": "fused" if path == "fused" else "setup + tile kernels",
                    "window": f"steps {start + args.warmup}..{start + args.warmup + args.steps} of the "
                              f"{horizon}-step horizon, median of {len(co_windows)} windows",
                    "parallelism": "single GPU"},
         "windows_ms_per_step": {"co_scheduled": [round(x / args.steps * 1e3, 4) for x in co_windows],
                                 "serialized": [round(x / args.steps * 1e3, 4) for x in ser_windows]},
-        "serialized": {"value": round(ser, 1), "ms_per_step": round(dt_ser / args.steps * 1e3, 4)},
+        "serialized": {"value": round(ser, 1), "ms_per_step": round(dt_ser / args.steps * 1e3, 4),
+                       "raster": ser_path,
+                       "paths": {p: round(n_envs * args.steps / v[0], 1) for p, v in ser_paths.items()}},
         "speedup_vs_serialized": round(value / ser, 4),
         "overlap_bound": round((Ts + Tr) / max(Ts, Tr), 4),
         "phase_alone_us": {"step": round(Ts * 1e6, 2), "render": round(Tr * 1e6, 2), "presetup": presetup},
@@ -638,6 +722,7 @@ def main():
         "sweep": {k: round(v, 1) for k, v in sweep.items()},
         "roofline": roof,
         "physics_c3": c3,
+        "uneven_c4": c4,
         "cpu_baseline": cpu,
         "serving": serving,
         "policy": policy,

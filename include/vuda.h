@@ -325,6 +325,20 @@ int vuda_world_info(vuda_world* w, int32_t* n_envs, int64_t* n_bodies, int32_t* 
  *                              raster tiles (binning and one tile-kernel wave
  *                              per tile); changing it waits for queued work
  *                              and redoes the raster setup of current states
+ *   VUDA_TUNE_RASTER_FUSED     1: vuda_render runs setup and tiles of an image
+ *                              in one workgroup (VUDA_TUNE_RASTER_THREADS
+ *                              threads) that keeps its setup records, bins and
+ *                              tile table in LDS, so that they never reach
+ *                              HBM, and vuda_step does no raster setup; worlds
+ *                              with smooth shading or near-plane clipping, and
+ *                              envs too large for LDS, keep the two kernels.
+ *                              0 (default): setup and tile kernels
+ *   VUDA_TUNE_FUSED_LDS_RECORDS  fused raster: 0 (default) keeps up to half
+ *                              the env's primitives plus 64 records of an
+ *                              image in LDS (less if LDS is short), n > 0 at
+ *                              most n (with 4 bin entries each; less LDS per
+ *                              workgroup); an image with more records or bin
+ *                              entries passes them through the raster scratch
  * None of the others changes any output bit.  Returns VUDA_EINVAL for unknown keys
  * or out-of-range values.
  */
@@ -340,6 +354,8 @@ int vuda_world_info(vuda_world* w, int32_t* n_envs, int64_t* n_bodies, int32_t* 
 #define VUDA_TUNE_POLICY_LAYERED 10
 #define VUDA_TUNE_PHYS_ENVS_PER_WAVE 11
 #define VUDA_TUNE_TILE_SIZE 12
+#define VUDA_TUNE_RASTER_FUSED 13
+#define VUDA_TUNE_FUSED_LDS_RECORDS 14
 int vuda_set_tuning(vuda_world* w, int32_t key, int32_t value);
 int vuda_get_tuning(vuda_world* w, int32_t key, int32_t* value);
 
@@ -349,7 +365,8 @@ int vuda_get_tuning(vuda_world* w, int32_t key, int32_t* value);
  * transform, triangle setup and tile binning of a state; part of the step
  * with VUDA_TUNE_PRESETUP, else of the render) or VUDA_KERNEL_RASTER_TILES
  * (the pixels, part of the render) or VUDA_KERNEL_POLICY (layer 1 and the
- * head of vuda_act).  Waits for the last recorded launch of
+ * head of vuda_act) or VUDA_KERNEL_RASTER_FUSED (setup and pixels in one
+ * kernel, the render with VUDA_TUNE_RASTER_FUSED).  Waits for the last recorded launch of
  * that kernel, then returns the number of launches since the previous call
  * for it and the sum and maximum of their durations in milliseconds -- GPU
  * time between an event recorded on the launch's stream just before the
@@ -361,6 +378,7 @@ int vuda_get_tuning(vuda_world* w, int32_t key, int32_t* value);
 #define VUDA_KERNEL_RASTER_SETUP 2
 #define VUDA_KERNEL_RASTER_TILES 3
 #define VUDA_KERNEL_POLICY 4
+#define VUDA_KERNEL_RASTER_FUSED 5
 int vuda_kernel_times(vuda_world* w, int32_t kernel, int64_t* launches, double* total_ms,
                       double* max_ms);
 
@@ -461,7 +479,8 @@ int vuda_run(vuda_world* w, int32_t schedule, int32_t iters);
 /*
  * Autotuner: searches the launch shapes (schedule, CU split, physics and
  * raster persistent grids and workgroup shapes, raster tile size, physics
- * envs per wave, hipGraph replay, physics priority, broadphase, presetup)
+ * envs per wave, fused raster, hipGraph replay, physics priority,
+ * broadphase, presetup)
  * for the highest
  * co-scheduled env-steps/s on this world, timing `steps_per_trial`
  * iterations per candidate from the current state (the state is saved before
@@ -482,6 +501,7 @@ typedef struct {
   int32_t graphs;            /* VUDA_TUNE_GRAPHS chosen */
   int32_t phys_envs_per_wave; /* VUDA_TUNE_PHYS_ENVS_PER_WAVE chosen */
   int32_t tile_size;         /* VUDA_TUNE_TILE_SIZE chosen */
+  int32_t raster_fused;      /* VUDA_TUNE_RASTER_FUSED chosen */
 } vuda_tune_result;
 int vuda_autotune(vuda_world* w, int32_t steps_per_trial, const char* cache_path, vuda_tune_result* out);
 

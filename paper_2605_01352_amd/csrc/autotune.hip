@@ -1,10 +1,11 @@
 // Autotuner: picks the schedule, CU split and launch shapes with the highest
 // measured co-scheduled throughput on a world, by coordinate descent over a
 // small candidate set, timing real iterations from a saved state.  The
-// coordinates, in order: schedule x CU split; physics persistent grid;
-// raster-setup persistent grid; tile size; physics envs per wave; hipGraph
-// replay;
-// setup workgroup size; step wave priority; broadphase; presetup.
+// coordinates, in order: schedule x CU split; fused raster; physics
+// persistent grid; raster-setup persistent grid; tile size; physics envs per
+// wave; hipGraph replay; raster workgroup size; step wave priority;
+// broadphase; presetup.  The serialized baseline takes the better of the
+// two raster paths and of two workgroup sizes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -137,6 +138,7 @@ void to_result(const Cand& c, vuda_tune_result* r) {
   r->graphs = c.tune.graphs ? 1 : 0;
   r->phys_envs_per_wave = c.tune.phys_pack;
   r->tile_size = 1 << c.tune.tile_shift;
+  r->raster_fused = c.tune.raster_fused ? 1 : 0;
 }
 
 bool cache_lookup(const char* path, const std::string& key, vuda_tune_result* r) {
@@ -152,7 +154,7 @@ bool cache_lookup(const char* path, const std::string& key, vuda_tune_result* r)
     if (is >> t.cu_split >> t.schedule >> t.raster_threads >> t.rec_cap >> t.phys_persistent >>
         t.raster_persistent >> t.phys_priority >> t.broadphase >> t.cosched_env_steps_per_s >>
         t.serial_env_steps_per_s >> t.serial_raster_threads >> t.serial_phys_persistent >> t.presetup >>
-        t.graphs >> t.phys_envs_per_wave >> t.tile_size) {
+        t.graphs >> t.phys_envs_per_wave >> t.tile_size >> t.raster_fused) {
       *r = t;  // the last matching line wins
       found = true;
     }
@@ -167,7 +169,7 @@ void cache_store(const char* path, const std::string& key, const vuda_tune_resul
     << " " << r.phys_persistent << " " << r.raster_persistent << " " << r.phys_priority << " "
     << r.broadphase << " " << r.cosched_env_steps_per_s << " " << r.serial_env_steps_per_s << " "
     << r.serial_raster_threads << " " << r.serial_phys_persistent << " " << r.presetup << " " << r.graphs << " "
-    << r.phys_envs_per_wave << " " << r.tile_size << "\n";
+    << r.phys_envs_per_wave << " " << r.tile_size << " " << r.raster_fused << "\n";
 }
 
 }  // namespace
@@ -198,6 +200,7 @@ extern "C" int vuda_autotune(vuda_world* w, int32_t steps, const char* cache_pat
     c.tune.graphs = out->graphs != 0;
     c.tune.phys_pack = out->phys_envs_per_wave == 2 ? 2 : 1;
     c.tune.tile_shift = out->tile_size == 8 ? 3 : (out->tile_size == 32 ? 5 : 4);
+    c.tune.raster_fused = out->raster_fused != 0;
     out->trials = 0;
     return apply(w, c);
   }
@@ -224,14 +227,17 @@ extern "C" int vuda_autotune(vuda_world* w, int32_t steps, const char* cache_pat
   bs.sched = VUDA_SCHED_SERIAL;
   bs.tune = saved;
   double best_serial = -1.0;
-  for (int rt : {256, 512}) {
-    Cand c = bs;
-    c.tune.raster_threads = rt;
-    c.tune.phys_persistent = 0;
-    double r;
-    if ((rc = run(c, &r))) break;
-    if (r > best_serial) { best_serial = r; bs = c; }
-  }
+  for (int fused : {0, 1})
+    for (int rt : {256, 512}) {
+      if (rc) break;
+      Cand c = bs;
+      c.tune.raster_fused = fused != 0;
+      c.tune.raster_threads = rt;
+      c.tune.phys_persistent = 0;
+      double r;
+      if ((rc = run(c, &r))) break;
+      if (r > best_serial) { best_serial = r; bs = c; }
+    }
   // co-scheduled: coordinate descent
   Cand best = bs;
   best.tune = bs.tune;
@@ -258,12 +264,13 @@ extern "C" int vuda_autotune(vuda_world* w, int32_t steps, const char* cache_pat
       if (r > best_rate) { best_rate = r; best = c; }
     }
   };
+  stage([](Cand& c, int v) { c.tune.raster_fused = v != 0; }, {0, 1});
   stage([](Cand& c, int v) { c.tune.phys_persistent = v; }, {0, ncu, 2 * ncu, 3 * ncu});
   stage([](Cand& c, int v) { c.tune.raster_persistent = v; }, {0, ncu, 2 * ncu, 4 * ncu});
   stage([](Cand& c, int v) { c.tune.tile_shift = v; }, {4, 5, 3});
   stage([](Cand& c, int v) { c.tune.phys_pack = v; }, {1, 2});
   stage([](Cand& c, int v) { c.tune.graphs = v != 0; }, {0, 1});
-  stage([](Cand& c, int v) { c.tune.raster_threads = v; }, {256, 512});
+  stage([](Cand& c, int v) { c.tune.raster_threads = v; }, {256, 512, 1024});
   stage([](Cand& c, int v) { c.tune.phys_prio = v; }, {0, 3});
   stage([](Cand& c, int v) { c.tune.broadphase = v; }, {0, 1});
   stage([](Cand& c, int v) { c.tune.presetup = v != 0; }, {1, 0});

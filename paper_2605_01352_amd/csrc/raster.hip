@@ -56,28 +56,40 @@ constexpr int kTplBytes = (int)((sizeof(Templates) + 15) & ~(size_t)15);
 __host__ __device__ inline int align16(int x) { return (x + 15) & ~15; }
 
 struct SetupLayout {
-  // byte offsets into the setup kernel's dynamic LDS
-  int tpl, body, verts, vis, cvis, pmap, vmap, tiles, misc, total;
-  int nmax, vmax, tw;
+  // byte offsets into the setup (or fused) kernel's dynamic LDS
+  int tpl, body, verts, vis, cvis, pmap, vmap, tiles, misc, lrec, lbin, total;
+  int nmax, vmax, tw, rec_cap, bin_cap;
 };
 
+// The regions the setup alone uses (templates, poses, survivor lists, maps)
+// come first, and at least zone0 bytes are reserved for them: the fused
+// kernel's tile pass keeps its z-buffers there once the setup is done.  Then
+// the vertex cache, the tile table and counters, and (fused kernel) rec_cap
+// compact records and bin_cap bin entries.
 __host__ __device__ inline SetupLayout setup_layout(int max_bodies, int max_verts, int max_tiles,
-                                                    int max_tris, bool near_clip) {
+                                                    int max_tris, bool near_clip, int zone0 = 0,
+                                                    int rec_cap = 0, int bin_cap = 0) {
   SetupLayout L;
   L.nmax = max_bodies + 1;
   L.vmax = max_verts;
   L.tw = max_tiles < kMaxLdsTiles ? max_tiles : kMaxLdsTiles;
+  L.rec_cap = rec_cap;
+  L.bin_cap = bin_cap;
   int o = 0;
   L.tpl = o;    o += kTplBytes;
   L.body = o;   o += align16(4 * 20 * L.nmax);
-  L.verts = o;  o += align16(12 * L.vmax);
   L.vis = o;    o += align16(2 * max_tris);
   L.cvis = o;   o += near_clip ? align16(40 * kClipRecs) : 0;  // near-plane pieces: X[3] Y[3] z[3], primitive
   L.pmap = o;   o += align16(max_tris);   // primitive -> body map of the env
   L.vmap = o;   o += align16(L.vmax);     // vertex -> body map of the env
+  if (o < zone0) o = align16(zone0);
+  L.verts = o;  o += 16 * L.vmax;         // (X, Y, z, 0) per vertex
   L.tiles = o;  o += align16(4 * (3 * L.tw + 1));
   L.misc = o;   o += 128;  // [2] record count, [3] near-plane pieces, [4] queue slot,
-                           // [5] a vertex behind the near plane, [8, 24) scan totals
+                           // [5] a vertex behind the near plane, [6] fused: bit 0 records
+                           // and bins in LDS, bit 1 binned; [8, 24) scan totals
+  L.lrec = o;   o += 16 * rec_cap;
+  L.lbin = o;   o += align16(2 * bin_cap);
   L.total = o;
   return L;
 }
@@ -135,17 +147,16 @@ __device__ __forceinline__ void prim_vertices(const Templates* T, const BodyLDS&
   for (int k = 0; k < 3; ++k) vid[k] = B.vb[b] + fi[k];
 }
 
-__device__ __forceinline__ Tri load_tri(const int32_t* VX, const int32_t* VY, const float* VZ,
-                                        const int vid[3]) {
+__device__ __forceinline__ Tri load_tri(const int4* V, const int vid[3]) {
   Tri t;
   const int ord[3] = {0, 2, 1};
   t.ok = true;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const int v = vid[ord[k]];
-    t.X[k] = VX[v];
-    t.Y[k] = VY[v];
-    t.z[k] = VZ[v];
+    const int4 q = V[vid[ord[k]]];
+    t.X[k] = q.x;
+    t.Y[k] = q.y;
+    t.z[k] = __int_as_float(q.z);
     if (t.X[k] <= kBehind) t.ok = false;  // kInvalid or kBehind
   }
   return t;
@@ -368,12 +379,9 @@ __device__ __forceinline__ int tile_scan(const int32_t* cnt, int32_t* toff, int 
 // 24-bit multiply-adds are exact.
 constexpr int kNarrow = 120 * 256;
 
-// Setup record of a triangle: what every tile it is binned to needs, so that
-// the tile kernel recomputes none of it.  Word 3 of the last quad: bit e set
-// when edge e is not top-left (a pixel centre on it is outside), bit 3 set
-// when the triangle is narrow.
-__device__ __forceinline__ void store_rec(int4* recs, int r, const Tri& t, int prim, float invA,
-                                          uint32_t rgb, int x0, int x1, int y0, int y1) {
+// Flags of a triangle's setup record: bit e set when edge e is not top-left
+// (a pixel centre on it is outside), bit 3 set when the triangle is narrow.
+__device__ __forceinline__ int rec_flags(const Tri& t) {
   int flags = 0;
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
@@ -383,6 +391,15 @@ __device__ __forceinline__ void store_rec(int4* recs, int r, const Tri& t, int p
   const bool narrow = max(t.X[0], max(t.X[1], t.X[2])) - min(t.X[0], min(t.X[1], t.X[2])) <= kNarrow &&
                       max(t.Y[0], max(t.Y[1], t.Y[2])) - min(t.Y[0], min(t.Y[1], t.Y[2])) <= kNarrow;
   if (narrow) flags |= 8;
+  return flags;
+}
+
+// Setup record of a triangle in the image's raster scratch (64 bytes): what
+// every tile it is binned to needs, so that the tile kernel recomputes none
+// of it.  Word 2 of the last quad holds the flags.
+__device__ __forceinline__ void store_rec(int4* recs, int r, const Tri& t, int prim, float invA,
+                                          uint32_t rgb, int x0, int x1, int y0, int y1) {
+  const int flags = rec_flags(t);
   int4* p = recs + 4 * r;
   p[0] = make_int4(t.X[0], t.Y[0], t.X[1], t.Y[1]);
   p[1] = make_int4(t.X[2], t.Y[2], prim, __float_as_int(t.z[0]));
@@ -484,8 +501,12 @@ __device__ __forceinline__ void store_attr(float4* ga, int r, const Templates* T
 }
 
 // CLIP: cut triangles crossing the near plane (else they are culled whole,
-// and none of that code is compiled in)
-template <bool CLIP>
+// and none of that code is compiled in).  FUSED: the fused kernel's setup,
+// which keeps the image's records and bins in LDS when they fit (16-byte
+// records: the vertex-cache indices of the corners in edge order, the
+// primitive, 1/area, RGB8 and the flags), else writes them to the raster
+// scratch as the setup kernel does; the tile table stays in LDS either way.
+template <bool CLIP, bool FUSED>
 __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const WorldDev& W,
                             const RasterLaunch& L, int cam_id) {
   const int tid = threadIdx.x;
@@ -525,9 +546,7 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
   B.vb = (int32_t*)(bf + 17 * Lo.nmax);
   B.pb = (int32_t*)(bf + 18 * Lo.nmax);
   B.alb = (int32_t*)(bf + 19 * Lo.nmax);
-  int32_t* VX = (int32_t*)(lds + Lo.verts);
-  int32_t* VY = VX + Lo.vmax;
-  float* VZ = (float*)(VY + Lo.vmax);
+  int4* V = (int4*)(lds + Lo.verts);
   uint16_t* vis = (uint16_t*)(lds + Lo.vis);
   int32_t* cvis = (int32_t*)(lds + Lo.cvis);  // 10 words per piece
   int32_t* tcount = (int32_t*)(lds + Lo.tiles);
@@ -574,9 +593,7 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
     float z;
     snap_clip(vertex_clip(T, B, Lo.nmax, gvmap, vi, vp), fW, fH, T, true, &X, &Y, &z);
     if (CLIP && X == kBehind) misc[5] = 1;  // some vertex of the image is behind the near plane
-    VX[vi] = X;
-    VY[vi] = Y;
-    VZ[vi] = z;
+    V[vi] = make_int4(X, Y, __float_as_int(z), 0);
   }
   __syncthreads();
 
@@ -597,7 +614,7 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
     if (pr < ntris) {
       int body, vid[3];
       prim_vertices(T, B, gpmap[pr], pr, &body, vid);
-      const Tri t = load_tri(VX, VY, VZ, vid);
+      const Tri t = load_tri(V, vid);
       int x0, x1, y0, y1;
       keep = t.ok && tri_area(t.X, t.Y) > 0 && tri_pixels(t.X, t.Y, Wd, Ht, &x0, &x1, &y0, &y1);
       if constexpr (decltype(cut_tag)::value) {
@@ -653,13 +670,13 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
   const int npieces = min(misc[3], kClipRecs);
   const int nrec = nwhole + npieces;
   if (tid == 0 && misc[3] > kClipRecs) atomicOr(&W.env_flags[cam.env], kFlagClipOverflow);
-  // record r: whole triangle vis[r], or piece cvis[r - nwhole]
-  const auto record_tri = [&](int r, int* pr, int* body, Tri* t) {
-    int vid[3];
+  // record r: whole triangle vis[r], or piece cvis[r - nwhole]; vid its
+  // face's vertices in face order
+  const auto record_tri = [&](int r, int* pr, int* body, int vid[3], Tri* t) {
     if (!CLIP || r < nwhole) {
       *pr = vis[r];
       prim_vertices(T, B, gpmap[*pr], *pr, body, vid);
-      *t = load_tri(VX, VY, VZ, vid);
+      *t = load_tri(V, vid);
       return;
     }
     const int32_t* o = cvis + 10 * (r - nwhole);
@@ -674,19 +691,67 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
     }
   };
 
-  // 4. setup records (with the face colour) and tile counts, one surviving
-  // triangle per lane.  A triangle whose box spans more than kWide tiles is
-  // counted by its whole wave, one tile per lane, so that one lane never
-  // walks a long tile list alone.  Record slots differ from run to run; they
-  // appear in no key, which orders by depth, then primitive.
+  // 4. tile counts, one surviving triangle per lane.  A triangle whose box
+  // spans more than kWide tiles is counted by its whole wave, one tile per
+  // lane, so that one lane never walks a long tile list alone.
+  if (tiled) {
+    for (int base = 0; base < nrec; base += nthr) {
+      const int r = base + tid;
+      int tx0 = 0, ty0 = 0, nx = 0, ny = 0;
+      if (r < nrec) {
+        int pr, body, vid[3];
+        Tri t;
+        record_tri(r, &pr, &body, vid, &t);
+        int x0, x1, y0, y1;
+        tri_pixels(t.X, t.Y, Wd, Ht, &x0, &x1, &y0, &y1);
+        tx0 = x0 >> tsh;
+        ty0 = y0 >> tsh;
+        nx = (x1 >> tsh) - tx0 + 1;
+        ny = (y1 >> tsh) - ty0 + 1;
+      }
+      const bool wide = nx * ny > kWide;
+      if (!wide)
+        for (int qy = 0; qy < ny; ++qy)
+          for (int qx = 0; qx < nx; ++qx) atomicAdd(&tcount[(ty0 + qy) * ntx + tx0 + qx], 1);
+      uint64_t m = __ballot(wide);
+      while (m) {
+        const int j = __ffsll((unsigned long long)m) - 1;
+        m &= m - 1ull;
+        const int jx0 = __shfl(tx0, j, 64), jy0 = __shfl(ty0, j, 64);
+        const int jnx = __shfl(nx, j, 64), jn = jnx * __shfl(ny, j, 64);
+        for (int q = lane; q < jn; q += 64) {
+          const int qy = q / jnx;
+          atomicAdd(&tcount[(jy0 + qy) * ntx + jx0 + (q - qy * jnx)], 1);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // bin entries hold 15-bit record ids
+  bool binned = tiled && nrec <= 32768;
+  int total = 0;
+  if (binned) total = tile_scan(tcount, toff, ntiles, misc + 8);
+  bool local = false;
+  if constexpr (FUSED) local = nrec <= Lo.rec_cap && (!binned || total <= Lo.bin_cap);
+  if (binned && total > (local ? Lo.bin_cap : bin_cap)) binned = false;
+  int4* lrec = (int4*)(lds + Lo.lrec);
+  uint16_t* bout = local ? (uint16_t*)(lds + Lo.lbin) : bins;
+  if (binned) {
+    for (int t = tid; t < ntiles; t += nthr) tfill[t] = 0;
+    __syncthreads();
+  }
+
+  // 5. a setup record (with the face colour) per surviving triangle, and its
+  // record id scattered into the bins, from the vertex cache.  Record slots
+  // differ from run to run; they appear in no key, which orders by depth,
+  // then primitive.
   for (int base = 0; base < nrec; base += nthr) {
     const int r = base + tid;
-    int tx0 = 0, ty0 = 0, nx = 0, ny = 0;
+    int x0 = 0, x1 = 0, y0 = 0, y1 = 0, nx = 0, ny = 0;
+    Tri t{};
     if (r < nrec) {
-      int pr, body;
-      Tri t;
-      record_tri(r, &pr, &body, &t);
-      int x0, x1, y0, y1;
+      int pr, body, vid[3];
+      record_tri(r, &pr, &body, vid, &t);
       tri_pixels(t.X, t.Y, Wd, Ht, &x0, &x1, &y0, &y1);
       const int64_t A = tri_area(t.X, t.Y);
       const int face = body < 0 ? pr : pr - B.pb[body];
@@ -695,94 +760,62 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
         // the key carries the record instead of a colour; the pixel's colour
         // comes from the record's attributes in the tile kernel
         rgb = (uint32_t)r;
-        int bb, vid[3];
-        prim_vertices(T, B, gpmap[pr], pr, &bb, vid);
         store_attr((float4*)(rs + cam.rs_attr), r, T, B, Lo.nmax, gvmap, body, face, vid, vp);
       } else {
         rgb = face_color(T, B, Lo.nmax, body, face);
       }
-      store_rec(grec, r, t, pr, 1.0f / (float)(double)A, rgb, x0, x1, y0, y1);
-      tx0 = x0 >> tsh;
-      ty0 = y0 >> tsh;
-      nx = (x1 >> tsh) - tx0 + 1;
-      ny = (y1 >> tsh) - ty0 + 1;
+      const float invA = 1.0f / (float)(double)A;
+      if (FUSED && local)
+        lrec[r] = make_int4((int32_t)((uint32_t)vid[0] | ((uint32_t)vid[2] << 16)),
+                            (int32_t)((uint32_t)vid[1] | ((uint32_t)pr << 16)), __float_as_int(invA),
+                            (int32_t)(rgb | ((uint32_t)rec_flags(t) << 24)));
+      else
+        store_rec(grec, r, t, pr, invA, rgb, x0, x1, y0, y1);
+      nx = (x1 >> tsh) - (x0 >> tsh) + 1;
+      ny = (y1 >> tsh) - (y0 >> tsh) + 1;
     }
-    if (!tiled) continue;
+    if (!binned) continue;
     const bool wide = nx * ny > kWide;
     if (!wide)
       for (int qy = 0; qy < ny; ++qy)
-        for (int qx = 0; qx < nx; ++qx) atomicAdd(&tcount[(ty0 + qy) * ntx + tx0 + qx], 1);
+        for (int qx = 0; qx < nx; ++qx)
+          bin_tile(t, r, (x0 >> tsh) + qx, (y0 >> tsh) + qy, x0, x1, y0, y1, nx * ny > 1, Wd, Ht, ntx, TS,
+                   toff, tfill, bout);
+    // a wide triangle is binned by the whole wave, one tile per lane; its
+    // snapped vertices and pixel box come from its lane's registers
     uint64_t m = __ballot(wide);
     while (m) {
       const int j = __ffsll((unsigned long long)m) - 1;
       m &= m - 1ull;
-      const int jx0 = __shfl(tx0, j, 64), jy0 = __shfl(ty0, j, 64);
-      const int jnx = __shfl(nx, j, 64), jn = jnx * __shfl(ny, j, 64);
+      const int jr = __builtin_amdgcn_readlane(r, j);
+      Tri J{};
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        J.X[v] = __builtin_amdgcn_readlane(t.X[v], j);
+        J.Y[v] = __builtin_amdgcn_readlane(t.Y[v], j);
+      }
+      const int jx0 = __builtin_amdgcn_readlane(x0, j), jx1 = __builtin_amdgcn_readlane(x1, j);
+      const int jy0 = __builtin_amdgcn_readlane(y0, j), jy1 = __builtin_amdgcn_readlane(y1, j);
+      const int jnx = (jx1 >> tsh) - (jx0 >> tsh) + 1;
+      const int jn = jnx * ((jy1 >> tsh) - (jy0 >> tsh) + 1);
       for (int q = lane; q < jn; q += 64) {
         const int qy = q / jnx;
-        atomicAdd(&tcount[(jy0 + qy) * ntx + jx0 + (q - qy * jnx)], 1);
+        bin_tile(J, jr, (jx0 >> tsh) + (q - qy * jnx), (jy0 >> tsh) + qy, jx0, jx1, jy0, jy1, true, Wd, Ht,
+                 ntx, TS, toff, tfill, bout);
       }
     }
+  }
+  if constexpr (FUSED) {
+    // the tile pass reads the table from LDS after the caller's barrier
+    if (tid == 0) misc[6] = (local ? 1 : 0) | (binned ? 2 : 0);
+    return;
   }
   __syncthreads();
-  // bin entries hold 15-bit record ids
-  bool binned = tiled && nrec <= 32768;
-  if (binned) {
-    const int total = tile_scan(tcount, toff, ntiles, misc + 8);
-    if (total > bin_cap) binned = false;
-  }
-
-  // 5. scatter record ids into the bins, from the vertex cache
-  if (binned) {
-    for (int t = tid; t < ntiles; t += nthr) tfill[t] = 0;
-    __syncthreads();
-    for (int base = 0; base < nrec; base += nthr) {
-      const int r = base + tid;
-      int x0 = 0, x1 = 0, y0 = 0, y1 = 0, nx = 0, ny = 0;
-      Tri t{};
-      if (r < nrec) {
-        int pr, body;
-        record_tri(r, &pr, &body, &t);
-        tri_pixels(t.X, t.Y, Wd, Ht, &x0, &x1, &y0, &y1);
-        nx = (x1 >> tsh) - (x0 >> tsh) + 1;
-        ny = (y1 >> tsh) - (y0 >> tsh) + 1;
-      }
-      const bool wide = nx * ny > kWide;
-      if (!wide)
-        for (int qy = 0; qy < ny; ++qy)
-          for (int qx = 0; qx < nx; ++qx)
-            bin_tile(t, r, (x0 >> tsh) + qx, (y0 >> tsh) + qy, x0, x1, y0, y1, nx * ny > 1, Wd, Ht, ntx, TS,
-                     toff, tfill, bins);
-      // a wide triangle is binned by the whole wave, one tile per lane; its
-      // snapped vertices and pixel box come from its lane's registers
-      uint64_t m = __ballot(wide);
-      while (m) {
-        const int j = __ffsll((unsigned long long)m) - 1;
-        m &= m - 1ull;
-        const int jr = __builtin_amdgcn_readlane(r, j);
-        Tri J{};
-#pragma unroll
-        for (int v = 0; v < 3; ++v) {
-          J.X[v] = __builtin_amdgcn_readlane(t.X[v], j);
-          J.Y[v] = __builtin_amdgcn_readlane(t.Y[v], j);
-        }
-        const int jx0 = __builtin_amdgcn_readlane(x0, j), jx1 = __builtin_amdgcn_readlane(x1, j);
-        const int jy0 = __builtin_amdgcn_readlane(y0, j), jy1 = __builtin_amdgcn_readlane(y1, j);
-        const int jnx = (jx1 >> tsh) - (jx0 >> tsh) + 1;
-        const int jn = jnx * ((jy1 >> tsh) - (jy0 >> tsh) + 1);
-        for (int q = lane; q < jn; q += 64) {
-          const int qy = q / jnx;
-          bin_tile(J, jr, (jx0 >> tsh) + (q - qy * jnx), (jy0 >> tsh) + qy, jx0, jx1, jy0, jy1, true, Wd, Ht,
-                   ntx, TS, toff, tfill, bins);
-        }
-      }
-    }
-    __syncthreads();
+  if (binned)
     for (int t = tid; t < ntiles; t += nthr) {
       ttab[2 * t] = toff[t];
       ttab[2 * t + 1] = tfill[t];
     }
-  }
   if (tid == 0) {
     hdr[0] = nrec;
     hdr[1] = binned ? 1 : 0;
@@ -803,7 +836,7 @@ __global__ void raster_setup_kernel(WorldDev W, RasterLaunch L) {
   const SetupLayout Lo = setup_layout(L.max_bodies, L.max_verts, L.max_tiles, L.max_tris, CLIP);
   if (L.persistent == 0) {
     if ((int)blockIdx.x >= L.n_work) return;
-    setup_image<CLIP>(lds, Lo, W, L, L.work[blockIdx.x]);
+    setup_image<CLIP, false>(lds, Lo, W, L, L.work[blockIdx.x]);
     return;
   }
   int32_t* slot = (int32_t*)(lds + Lo.misc) + 4;
@@ -813,7 +846,7 @@ __global__ void raster_setup_kernel(WorldDev W, RasterLaunch L) {
     __syncthreads();
     const int wi = *slot;
     if (wi >= L.n_work) return;
-    setup_image<CLIP>(lds, Lo, W, L, L.work[wi]);
+    setup_image<CLIP, false>(lds, Lo, W, L, L.work[wi]);
   }
 }
 
@@ -896,25 +929,53 @@ __device__ __forceinline__ uint32_t smooth_color(const int4* grec, const float4*
   return rgb;
 }
 
-template <bool DBG, bool SMOOTH, int TS>
-__device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam, int parity, int ntx,
-                                            int tx, int ty, TileWaveLDS<TS>& S, int32_t* cov) {
+// Where the tile pass finds an image's records and bins.  GlobalRecs: the
+// 64-byte records and the bins in the raster scratch.  LdsRecs (fused
+// kernel): 16-byte records and bins in LDS, the corners read from the
+// vertex cache and the pixel box recomputed, so that fetch() returns the
+// four quads of the 64-byte record.
+struct GlobalRecs {
+  const int4* rec;
+  const uint16_t* bins;
+  __device__ __forceinline__ int bin(int k) const { return bins[k]; }
+  __device__ __forceinline__ void fetch(int r, int4& a, int4& b, int4& c, int4& d) const {
+    a = rec[4 * r];
+    b = rec[4 * r + 1];
+    c = rec[4 * r + 2];
+    d = rec[4 * r + 3];
+  }
+};
+
+struct LdsRecs {
+  const int4* rec;
+  const int4* V;
+  const uint16_t* bins;
+  int w, h;
+  __device__ __forceinline__ int bin(int k) const { return bins[k]; }
+  __device__ __forceinline__ void fetch(int r, int4& a, int4& b, int4& c, int4& d) const {
+    const int4 q = rec[r];
+    const int4 v0 = V[q.x & 0xFFFF], v1 = V[(uint32_t)q.x >> 16], v2 = V[q.y & 0xFFFF];
+    a = make_int4(v0.x, v0.y, v1.x, v1.y);
+    b = make_int4(v2.x, v2.y, (int32_t)((uint32_t)q.y >> 16), v0.z);
+    c = make_int4(v1.z, v2.z, q.z, q.w & 0xFFFFFF);
+    const int32_t X[3] = {v0.x, v1.x, v2.x}, Y[3] = {v0.y, v1.y, v2.y};
+    int x0, x1, y0, y1;
+    tri_pixels(X, Y, w, h, &x0, &x1, &y0, &y1);
+    d = make_int4(x0 | (x1 << 16), y0 | (y1 << 16), (int32_t)((uint32_t)q.w >> 24), 0);
+  }
+};
+
+// One tile of an image: records k0 .. k1 of the tile's bin (binned), or
+// every record k0 .. k1 of the image.  rs: the image's raster scratch (smooth
+// shading reads its attribute records there).
+template <bool DBG, bool SMOOTH, int TS, class Src>
+__device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam, const Src& src, bool binned,
+                                            int k0, int k1, int tx, int ty, TileWaveLDS<TS>& S, int32_t* cov,
+                                            const unsigned char* rs) {
   using G = TileGeo<TS>;
   constexpr int BW = G::BW, BH = G::BH, NPX = G::NPX;
   const int lane = threadIdx.x & 63;
   const int Wd = cam.w, Ht = cam.h;
-  const unsigned char* rs = W.rscratch + cam.rs_off + (int64_t)parity * cam.rs_total;
-  const int32_t* hdr = (const int32_t*)rs;
-  const int nrec = hdr[0];
-  const bool binned = hdr[1] != 0;
-  const int4* grec = (const int4*)(rs + cam.rs_recs);
-  const uint16_t* bins = (const uint16_t*)(rs + cam.rs_bins);
-  int k0 = 0, k1 = nrec;
-  if (binned) {
-    const int32_t* tt = (const int32_t*)(rs + 64) + 2 * (ty * ntx + tx);
-    k0 = tt[0];
-    k1 = k0 + tt[1];
-  }
   const int tx0 = tx * TS, ty0 = ty * TS;
   const int tx1 = min(tx0 + TS - 1, Wd - 1), ty1 = min(ty0 + TS - 1, Ht - 1);
   // this lane's pixels: (px0 + i, py0 + j) for i < BW, j < BH, z-buffer
@@ -961,21 +1022,19 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
     if (k < k1) {
       int rec = k;
       if (binned) {
-        const int e = bins[k];
+        const int e = src.bin(k);
         rec = e & 0x7FFF;
         full = e >> 15;
       }
-      ra = grec[4 * rec];
-      rb = grec[4 * rec + 1];
-      rc = grec[4 * rec + 2];
-      const int4 rd = grec[4 * rec + 3];
+      int4 rd;
+      src.fetch(rec, ra, rb, rc, rd);
       const int32_t X[3] = {ra.x, ra.z, rb.x}, Y[3] = {ra.y, ra.w, rb.y};
       // the triangle's pixel box (never empty) clipped to the tile
       fx0 = max(rd.x & 0xFFFF, tx0);
       fy0 = max(rd.y & 0xFFFF, ty0);
       bw = min(rd.x >> 16, tx1) - fx0 + 1;
       const int bh = min(rd.y >> 16, ty1) - fy0 + 1;
-      area = (bw > 0) & (bh > 0) ? bw * bh : 0;
+      area = ((bw > 0) & (bh > 0)) ? bw * bh : 0;
       if (bw < 1) bw = 1;
       const bool narrow = (rd.z & 8) != 0;
       big = area > kSmallMax || (area > 0 && !narrow);
@@ -1118,7 +1177,7 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
       if constexpr (SMOOTH) {
         // the key's low bits name the winning record
         if (hit)
-          rgb[i] = smooth_color(grec, (const float4*)(rs + cam.rs_attr), W.tpl, (int)rgb[i], px0 + i, py);
+          rgb[i] = smooth_color(src.rec, (const float4*)(rs + cam.rs_attr), W.tpl, (int)rgb[i], px0 + i, py);
       }
     }
     if (py > ty1) continue;
@@ -1171,13 +1230,141 @@ __global__ void __launch_bounds__(64 * kTileWaves) raster_tile_kernel(WorldDev W
   const int ntx = (cam.w + TS - 1) / TS;
   const int tx = (job.y & 0xFFFF) + wave, ty = job.y >> 16;
   if (tx >= ntx) return;  // no workgroup barrier follows
-  raster_tile<DBG, SMOOTH, TS>(W, cam, L.parity, ntx, tx, ty, S[wave], DBG ? C[wave] : nullptr);
+  const unsigned char* rs = W.rscratch + cam.rs_off + (int64_t)L.parity * cam.rs_total;
+  const int32_t* hdr = (const int32_t*)rs;
+  const bool binned = hdr[1] != 0;
+  int k0 = 0, k1 = hdr[0];
+  if (binned) {
+    const int32_t* tt = (const int32_t*)(rs + 64) + 2 * (ty * ntx + tx);
+    k0 = tt[0];
+    k1 = k0 + tt[1];
+  }
+  const GlobalRecs src{(const int4*)(rs + cam.rs_recs), (const uint16_t*)(rs + cam.rs_bins)};
+  raster_tile<DBG, SMOOTH, TS>(W, cam, src, binned, k0, k1, tx, ty, S[wave], DBG ? C[wave] : nullptr, rs);
+}
+
+// The tiles wave, wave + nw, ... of an image whose setup is done, from
+// records and bins in src.
+template <bool DBG, int TS, class Src>
+__device__ __forceinline__ void fused_tiles(const WorldDev& W, const CamDev& cam, const Src& src, bool binned,
+                                            int nrec, const int32_t* toff, const int32_t* tfill, int wave,
+                                            int nw, TileWaveLDS<TS>* S, int32_t* C, const unsigned char* rs) {
+  const int ntx = (cam.w + TS - 1) / TS, ntiles = ntx * ((cam.h + TS - 1) / TS);
+  for (int t = wave; t < ntiles; t += nw) {
+    const int k0 = binned ? toff[t] : 0, k1 = binned ? k0 + tfill[t] : nrec;
+    raster_tile<DBG, false, TS>(W, cam, src, binned, k0, k1, t % ntx, t / ntx, S[wave],
+                                DBG ? C + wave * TS * TS : nullptr, rs);
+  }
+}
+
+// Setup and tiles of one image per workgroup (flat shading, no near-plane
+// clipping): the setup pass as above, then every wave rasterizes tiles
+// wave, wave + nw, ... of the image from the records and bins in LDS, its
+// z-buffer in the setup-only region.  Records and bins that do not fit go
+// through the raster scratch instead, with the same results.
+template <bool DBG, int TS>
+__global__ void __launch_bounds__(1024) raster_fused_kernel(WorldDev W, RasterLaunch L) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const SetupLayout Lo = setup_layout(L.max_bodies, L.max_verts, L.max_tiles, L.max_tris, false, L.lds_zone0,
+                                      L.lrec_cap, L.lbin_cap);
+  const int nw = (int)(blockDim.x >> 6);
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  TileWaveLDS<TS>* S = (TileWaveLDS<TS>*)lds;
+  int32_t* C = (int32_t*)(lds + nw * sizeof(TileWaveLDS<TS>));  // debug coverage, TS * TS per wave
+  int32_t* misc = (int32_t*)(lds + Lo.misc);
+  const int32_t* toff = (const int32_t*)(lds + Lo.tiles) + Lo.tw;
+  const int32_t* tfill = toff + Lo.tw + 1;
+  int wi = (int)blockIdx.x;
+  for (;;) {
+    if (L.persistent > 0) {
+      __syncthreads();
+      if (threadIdx.x == 0) misc[4] = atomicAdd(L.queue, 1);
+      __syncthreads();
+      wi = misc[4];
+    }
+    if (wi >= L.n_work) return;
+    const int cam_id = L.work[wi];
+    setup_image<false, true>(lds, Lo, W, L, cam_id);
+    __syncthreads();
+    const CamDev cam = W.cams[cam_id];
+    const int nrec = misc[2], mode = misc[6];
+    const bool binned = (mode & 2) != 0;
+    const unsigned char* rs = W.rscratch + cam.rs_off + (int64_t)L.parity * cam.rs_total;
+    if (mode & 1) {
+      const LdsRecs src{(const int4*)(lds + Lo.lrec), (const int4*)(lds + Lo.verts),
+                        (const uint16_t*)(lds + Lo.lbin), cam.w, cam.h};
+      fused_tiles<DBG, TS>(W, cam, src, binned, nrec, toff, tfill, wave, nw, S, C, rs);
+    } else {
+      const GlobalRecs src{(const int4*)(rs + cam.rs_recs), (const uint16_t*)(rs + cam.rs_bins)};
+      fused_tiles<DBG, TS>(W, cam, src, binned, nrec, toff, tfill, wave, nw, S, C, rs);
+    }
+    if (L.persistent == 0) return;
+    __syncthreads();  // the next image's setup reuses the LDS
+  }
 }
 
 }  // namespace
 
 size_t raster_lds_bytes(const RasterLaunch& l) {
   return (size_t)setup_layout(l.max_bodies, l.max_verts, l.max_tiles, l.max_tris, l.near_clip != 0).total;
+}
+
+// The fused kernel's LDS for workgroups of l.threads: the tile pass's
+// z-buffers (and debug coverage) over the setup-only region, and as many
+// compact records as LDS allows up to half the primitives plus 64 (a convex
+// closed mesh seen from outside shows at most about half its faces), with
+// four bin entries each (at most max_recs records if max_recs > 0); 0 if
+// fewer than min(64, max_recs) fit.
+size_t raster_fused_plan(RasterLaunch* l, bool debug, int max_recs) {
+  const int ts = 1 << l->tile_shift;
+  const int nw = l->threads / 64;
+  const size_t wave_lds = ts == 8 ? sizeof(TileWaveLDS<8>) : ts == 32 ? sizeof(TileWaveLDS<32>)
+                                                                       : sizeof(TileWaveLDS<16>);
+  l->lds_zone0 = (int32_t)(nw * (wave_lds + (debug ? 4 * ts * ts : 0)));
+  int cap = (l->max_tris + 1) / 2 + 64;
+  if (max_recs > 0 && max_recs < cap) cap = max_recs;
+  for (const int least = cap < 64 ? cap : 64; cap >= least; cap /= 2) {
+    const SetupLayout Lo = setup_layout(l->max_bodies, l->max_verts, l->max_tiles, l->max_tris, false,
+                                        l->lds_zone0, cap, 4 * cap);
+    if (Lo.total <= kFusedLdsMax) {
+      l->lrec_cap = cap;
+      l->lbin_cap = 4 * cap;
+      return (size_t)Lo.total;
+    }
+  }
+  return 0;
+}
+
+hipError_t raster_fused_configure(size_t lds_bytes) {
+  const void* k[] = {(const void*)raster_fused_kernel<false, 8>, (const void*)raster_fused_kernel<false, 16>,
+                     (const void*)raster_fused_kernel<false, 32>, (const void*)raster_fused_kernel<true, 8>,
+                     (const void*)raster_fused_kernel<true, 16>, (const void*)raster_fused_kernel<true, 32>};
+  for (const void* f : k) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <bool DBG>
+static void launch_fused(const WorldDev& w, const RasterLaunch& l, size_t lds, hipStream_t s, LaunchEvents* ev) {
+  const int grid = l.persistent > 0 ? (l.persistent < l.n_work ? l.persistent : l.n_work) : l.n_work;
+  const dim3 g(grid), b(l.threads);
+  if (l.tile_shift == 3) timed_launch(ev, true, true, raster_fused_kernel<DBG, 8>, g, b, (uint32_t)lds, s, w, l);
+  else if (l.tile_shift == 5) timed_launch(ev, true, true, raster_fused_kernel<DBG, 32>, g, b, (uint32_t)lds, s, w, l);
+  else timed_launch(ev, true, true, raster_fused_kernel<DBG, 16>, g, b, (uint32_t)lds, s, w, l);
+}
+
+hipError_t launch_raster_fused(const WorldDev& w, const RasterLaunch& l, size_t lds, hipStream_t s,
+                               LaunchEvents* ev) {
+  if (l.n_work <= 0) return hipSuccess;
+  if (l.persistent > 0) {
+    hipError_t e = launch_reset_queue(l.queue, s);
+    if (e != hipSuccess) return e;
+  }
+  if (w.winners) launch_fused<true>(w, l, lds, s, ev);
+  else launch_fused<false>(w, l, lds, s, ev);
+  return hipGetLastError();
 }
 
 hipError_t raster_configure(size_t lds_bytes) {

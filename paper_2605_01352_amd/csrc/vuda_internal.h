@@ -191,6 +191,9 @@ struct RasterLaunch {
   int32_t near_clip;       // setup kernel: cut triangles crossing the near plane
   int32_t smooth;          // per-pixel shading of interpolated vertex normals
   int32_t tile_shift;      // raster tiles of edge 1 << tile_shift (8, 16 or 32 pixels)
+  // fused kernel only (raster_fused_plan): LDS bytes reserved for the tile
+  // pass's z-buffers, compact records and bin entries an image keeps in LDS
+  int32_t lds_zone0, lrec_cap, lbin_cap;
 };
 
 // Timing events of one launch (a kernel or a chain of them): `start` is
@@ -251,6 +254,15 @@ hipError_t launch_raster_setup(const WorldDev& w, const RasterLaunch& l, hipStre
 hipError_t launch_raster_tiles(const WorldDev& w, const RasterLaunch& l, hipStream_t s, LaunchEvents* ev = nullptr);
 size_t raster_lds_bytes(const RasterLaunch& l);
 hipError_t raster_configure(size_t lds_bytes);
+// Fused setup + tiles, one workgroup of l.threads per image (flat shading, no
+// near-plane clipping): raster_fused_plan fills the LDS fields of l (at most
+// max_recs records in LDS when max_recs > 0) and returns the dynamic LDS
+// bytes (0: the images do not fit in LDS).
+constexpr size_t kFusedLdsMax = 160 * 1024;
+size_t raster_fused_plan(RasterLaunch* l, bool debug, int max_recs);
+hipError_t raster_fused_configure(size_t lds_bytes);
+hipError_t launch_raster_fused(const WorldDev& w, const RasterLaunch& l, size_t lds, hipStream_t s,
+                               LaunchEvents* ev = nullptr);
 hipError_t launch_reset_queue(int32_t* q, hipStream_t s);
 
 }  // namespace vuda

@@ -92,11 +92,13 @@ struct Tuning {
   bool policy_layered = false;  // layers 2-3 as batched products at any hidden size
   int32_t phys_pack = 1;         // envs of at most 32 bodies per physics wave (1 or 2)
   int32_t tile_shift = 4;        // raster tile edge 1 << tile_shift pixels
+  bool raster_fused = false;     // setup and tiles in one kernel, records in LDS
+  int32_t fused_recs = 0;        // records a fused image keeps in LDS at most (0: automatic)
 };
 
 // kernels of the step loop (index of their timing events)
-constexpr int kKernelPhysics = 0, kKernelSetup = 1, kKernelTiles = 2, kKernelPolicy = 3;
-constexpr int kKernelKinds = 4;
+constexpr int kKernelPhysics = 0, kKernelSetup = 1, kKernelTiles = 2, kKernelPolicy = 3, kKernelFused = 4;
+constexpr int kKernelKinds = 5;
 
 // Metric depth of one camera image: out[out_off + i] for its npix pixels
 // from depth[pix_off + i], view depth = beta / (D / (2^24 - 1) - alpha).
@@ -176,7 +178,7 @@ struct vuda_world {
   // launch timing: per kernel (kKernel*) and launch, an event before and one
   // after; tev_used[k] launches recorded since the last read
   std::vector<hipEvent_t> tev[vuda::kKernelKinds];
-  size_t tev_used[vuda::kKernelKinds] = {0, 0, 0, 0};
+  size_t tev_used[vuda::kKernelKinds] = {0, 0, 0, 0, 0};
   // per env: the raster scratch of its current state buffer holds that
   // state's setup
   std::vector<uint8_t> setup_ok;
@@ -214,6 +216,11 @@ struct vuda_world {
   int check_range(int32_t lo, int32_t hi);
   int enqueue_physics(const vuda::WorkList& L, int parity, hipStream_t s, vuda::LaunchEvents* ev = nullptr);
   int raster_launch_of(const vuda::WorkList& L, int parity, int32_t* queue, vuda::RasterLaunch* out);
+  // the fused raster launch of a render list; *lds = 0 when the two-kernel
+  // path renders it (fused off, smooth shading, near-plane clipping, or an
+  // env too large for LDS)
+  int fused_launch_of(const vuda::WorkList& L, int parity, int32_t* queue, vuda::RasterLaunch* out, size_t* lds);
+  size_t lds_fused_configured = 64 * 1024;
   int enqueue_kernel(int kind, const vuda::WorkList& L, int parity, hipStream_t s, int32_t* queue,
                      vuda::LaunchEvents* ev = nullptr);
   int run_kernel(int kind, const vuda::WorkList& L, int parity, int32_t lo, int32_t hi, hipStream_t s,

@@ -927,9 +927,36 @@ int vuda_world::raster_launch_of(const WorkList& L, int parity, int32_t* queue, 
   return VUDA_OK;
 }
 
+int vuda_world::fused_launch_of(const WorkList& L, int parity, int32_t* queue, RasterLaunch* out, size_t* lds) {
+  *lds = 0;
+  // vertex-cache indices and primitives travel in 16 bits of a compact record
+  if (!tune.raster_fused || near_clip || smooth || L.max_verts > 65536 || L.max_tris > 65536) return VUDA_OK;
+  RasterLaunch rl;
+  int rc = raster_launch_of(L, parity, queue, &rl);
+  if (rc) return rc;
+  const size_t need = raster_fused_plan(&rl, dev.winners != nullptr, tune.fused_recs);
+  if (need == 0) return VUDA_OK;
+  if (need > lds_fused_configured) {
+    HIPCHK(raster_fused_configure(need));
+    lds_fused_configured = need;
+  }
+  *out = rl;
+  *lds = need;
+  return VUDA_OK;
+}
+
 int vuda_world::enqueue_kernel(int kind, const WorkList& L, int parity, hipStream_t s, int32_t* queue,
                                LaunchEvents* ev) {
   if (kind == kKernelPhysics) return enqueue_physics(L, parity, s, ev);
+  if (kind == kKernelFused) {
+    RasterLaunch rl;
+    size_t lds;
+    int rc = fused_launch_of(L, parity, queue, &rl, &lds);
+    if (rc) return rc;
+    if (lds == 0) return fail(VUDA_EINVAL, "fused raster launch does not apply");
+    HIPCHK(launch_raster_fused(dev, rl, lds, s, ev));
+    return VUDA_OK;
+  }
   if (kind == kKernelPolicy) {
     PolicyLaunch pl;
     int rc = policy_launch_of(L, &pl);
@@ -1037,6 +1064,12 @@ extern "C" int vuda_step(vuda_world* w, int32_t lo, int32_t hi, int32_t nsteps) 
   if (w->tune.presetup) {
     rc = w->get_list(VUDA_PHASE_RENDER, lo, hi, &LR);
     if (rc) return rc;
+    // a fused render sets up its images itself
+    RasterLaunch rl;
+    size_t lds;
+    rc = w->fused_launch_of(*LR, 0, nullptr, &rl, &lds);
+    if (rc) return rc;
+    if (lds) LR = nullptr;
   }
   hipStream_t s = w->s_sim;
   for (int t = 0; t < nsteps; ++t) {
@@ -1093,15 +1126,24 @@ extern "C" int vuda_render(vuda_world* w, int32_t lo, int32_t hi) {
     rc = w->wait_event(s, last);
     if (rc) return rc;
   }
-  bool need_setup = false;
-  for (int32_t e = lo; e < hi; ++e) need_setup |= w->env_active[e] && !w->setup_ok[e];
-  if (need_setup) {
-    rc = w->run_kernel(kKernelSetup, *L, parity, lo, hi, s, w->queues + 2);
-    if (rc) return rc;
-    for (int32_t e = lo; e < hi; ++e) w->setup_ok[e] = 1;
-  }
-  rc = w->run_kernel(kKernelTiles, *L, parity, lo, hi, s, nullptr);
+  RasterLaunch rl;
+  size_t lds;
+  rc = w->fused_launch_of(*L, parity, w->queues + 2, &rl, &lds);
   if (rc) return rc;
+  if (lds) {
+    rc = w->run_kernel(kKernelFused, *L, parity, lo, hi, s, w->queues + 2);
+    if (rc) return rc;
+  } else {
+    bool need_setup = false;
+    for (int32_t e = lo; e < hi; ++e) need_setup |= w->env_active[e] && !w->setup_ok[e];
+    if (need_setup) {
+      rc = w->run_kernel(kKernelSetup, *L, parity, lo, hi, s, w->queues + 2);
+      if (rc) return rc;
+      for (int32_t e = lo; e < hi; ++e) w->setup_ok[e] = 1;
+    }
+    rc = w->run_kernel(kKernelTiles, *L, parity, lo, hi, s, nullptr);
+    if (rc) return rc;
+  }
   if (w->mode != 0) {
     int64_t id;
     rc = w->new_event(s, &id);
@@ -1886,6 +1928,16 @@ extern "C" int vuda_set_tuning(vuda_world* w, int32_t key, int32_t value) {
       if (value != 1 && value != 2) return fail(VUDA_EINVAL, "envs per wave %d (1 or 2)", value);
       w->tune.phys_pack = value;
       break;
+    case VUDA_TUNE_RASTER_FUSED:
+      if (value < 0 || value > 1) return fail(VUDA_EINVAL, "raster fused %d", value);
+      // a step set up for the two-kernel path renders correctly either way;
+      // one stepped in fused mode has no setup, so its render sets up
+      w->tune.raster_fused = value != 0;
+      break;
+    case VUDA_TUNE_FUSED_LDS_RECORDS:
+      if (value < 0) return fail(VUDA_EINVAL, "fused LDS records %d", value);
+      w->tune.fused_recs = value;
+      break;
     case VUDA_TUNE_TILE_SIZE: {
       if (value != 8 && value != 16 && value != 32) return fail(VUDA_EINVAL, "tile size %d (8, 16 or 32)", value);
       const int sh = value == 8 ? 3 : (value == 16 ? 4 : 5);
@@ -1922,6 +1974,8 @@ extern "C" int vuda_get_tuning(vuda_world* w, int32_t key, int32_t* value) {
     case VUDA_TUNE_POLICY_LAYERED: *value = w->tune.policy_layered ? 1 : 0; break;
     case VUDA_TUNE_PHYS_ENVS_PER_WAVE: *value = w->tune.phys_pack; break;
     case VUDA_TUNE_TILE_SIZE: *value = 1 << w->tune.tile_shift; break;
+    case VUDA_TUNE_RASTER_FUSED: *value = w->tune.raster_fused ? 1 : 0; break;
+    case VUDA_TUNE_FUSED_LDS_RECORDS: *value = w->tune.fused_recs; break;
     default: return fail(VUDA_EINVAL, "tuning key %d", key);
   }
   return VUDA_OK;
@@ -1930,7 +1984,7 @@ extern "C" int vuda_get_tuning(vuda_world* w, int32_t key, int32_t* value) {
 extern "C" int vuda_kernel_times(vuda_world* w, int32_t kernel, int64_t* launches, double* total_ms,
                                  double* max_ms) {
   if (!w) return fail(VUDA_EINVAL, "null world");
-  if (kernel < VUDA_KERNEL_PHYSICS || kernel > VUDA_KERNEL_POLICY) return fail(VUDA_EINVAL, "kernel %d", kernel);
+  if (kernel < VUDA_KERNEL_PHYSICS || kernel > VUDA_KERNEL_RASTER_FUSED) return fail(VUDA_EINVAL, "kernel %d", kernel);
   const int k = kernel - VUDA_KERNEL_PHYSICS;
   const size_t n = w->tev_used[k];
   double sum = 0.0, mx = 0.0;

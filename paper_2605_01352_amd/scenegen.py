@@ -481,14 +481,15 @@ def make_scene(seed: int, counts, res, mixed: bool, cams_per_env: int = 1,
 
     counts: bodies per env; res: per-env square resolution (int or array).
     ring: cameras at seeded poses on a 1.5 m ring (else one fixed pose).
-    workers: processes for the rejection-sampled placement (same result).
+    workers: processes for the rejection-sampled placement when the compiled
+    placement is not built (same result).
     """
     counts = np.asarray(counts, np.int64)
     E = len(counts)
     gids = np.arange(env_gid0, env_gid0 + E, dtype=np.uint64)
     res = np.broadcast_to(np.asarray(res, np.int64), (E,))
     env_of, local, btype, size, rb, inv_m, inv_I, albedo = _shapes(seed, gids, counts, mixed)
-    if workers > 1 and E >= 2 * workers:
+    if workers > 1 and E >= 2 * workers and _placement_lib() is None:
         pos = _place_parallel(seed, gids, counts, rb, env_of, local, workers)
     else:
         pos = _place(seed, gids, counts, rb, env_of, local)

@@ -31,7 +31,9 @@ TUNE_PRESETUP = 9
 TUNE_POLICY_LAYERED = 10
 TUNE_PHYS_ENVS_PER_WAVE = 11
 TUNE_TILE_SIZE = 12
-KERNEL_PHYSICS, KERNEL_RASTER_SETUP, KERNEL_RASTER_TILES, KERNEL_POLICY = 1, 2, 3, 4
+TUNE_RASTER_FUSED = 13
+TUNE_FUSED_LDS_RECORDS = 14
+KERNEL_PHYSICS, KERNEL_RASTER_SETUP, KERNEL_RASTER_TILES, KERNEL_POLICY, KERNEL_RASTER_FUSED = 1, 2, 3, 4, 5
 GROUND = 0xFFFF
 
 EXPORTS = [
@@ -95,7 +97,8 @@ class TuneResult(C.Structure):
                 ("broadphase", C.c_int32), ("cosched_env_steps_per_s", C.c_double),
                 ("serial_env_steps_per_s", C.c_double), ("serial_raster_threads", C.c_int32),
                 ("serial_phys_persistent", C.c_int32), ("trials", C.c_int32), ("presetup", C.c_int32),
-                ("graphs", C.c_int32), ("phys_envs_per_wave", C.c_int32), ("tile_size", C.c_int32)]
+                ("graphs", C.c_int32), ("phys_envs_per_wave", C.c_int32), ("tile_size", C.c_int32),
+                ("raster_fused", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -7,6 +7,7 @@ bit-exact, RGB within 1/255) are checked here at every iteration of:
     37.5% split) and on two unmasked streams (inter-step, and
     inter-trajectory with raised step priority);
   - persistent launches with hipGraph replay (c2 and the uneven c4 mix);
+  - the fused raster path (setup and tiles in one kernel);
   - the configuration the autotuner picks;
   - the uniform-grid broadphase on settled piles of 100 and 128 bodies,
     automatic and forced, and its fallback for cells far from the origin.
@@ -91,6 +92,11 @@ C2 = dict(cfg=2, n_envs=48, settle=250)
      {vuda.TUNE_PHYS_ENVS_PER_WAVE: 2}),
     ("two envs per physics wave, persistent, CU-masked 0.375, inter-trajectory", 0.375, vuda.SCHED_INTERTRAJ,
      {vuda.TUNE_PHYS_ENVS_PER_WAVE: 2, vuda.TUNE_PHYS_PERSISTENT: 7}),
+    ("fused raster, unmasked, inter-step", 2.0, vuda.SCHED_INTERSTEP, {vuda.TUNE_RASTER_FUSED: 1}),
+    ("fused raster 512 threads, serialized", 0.0, vuda.SCHED_SERIAL,
+     {vuda.TUNE_RASTER_FUSED: 1, vuda.TUNE_RASTER_THREADS: 512}),
+    ("fused raster, persistent + graphs, CU-masked 0.375, inter-trajectory", 0.375, vuda.SCHED_INTERTRAJ,
+     {vuda.TUNE_RASTER_FUSED: 1, vuda.TUNE_RASTER_PERSISTENT: 20, vuda.TUNE_GRAPHS: 1}),
 ])
 def test_c2_schedule_parity(label, split, sched, knobs):
     """48 envs of the 1024-env config, 250 steps past the spawn (a settled

@@ -130,7 +130,10 @@ def test_tuning_knobs_do_not_change_outputs():
                   {vuda.TUNE_PRESETUP: 0, vuda.TUNE_GRAPHS: 1}, {vuda.TUNE_RASTER_PERSISTENT: 3},
                   {vuda.TUNE_PHYS_ENVS_PER_WAVE: 2}, {vuda.TUNE_PHYS_ENVS_PER_WAVE: 2, vuda.TUNE_PHYS_PERSISTENT: 5},
                   {vuda.TUNE_TILE_SIZE: 8}, {vuda.TUNE_TILE_SIZE: 32},
-                  {vuda.TUNE_TILE_SIZE: 32, vuda.TUNE_REC_CAP: 64}):
+                  {vuda.TUNE_TILE_SIZE: 32, vuda.TUNE_REC_CAP: 64},
+                  {vuda.TUNE_RASTER_FUSED: 1}, {vuda.TUNE_RASTER_FUSED: 1, vuda.TUNE_RASTER_THREADS: 1024},
+                  {vuda.TUNE_RASTER_FUSED: 1, vuda.TUNE_FUSED_LDS_RECORDS: 60},
+                  {vuda.TUNE_RASTER_FUSED: 1, vuda.TUNE_TILE_SIZE: 8, vuda.TUNE_RASTER_PERSISTENT: 5}):
         with vuda.World(s) as w:
             for k, v in knobs.items():
                 w.set_tuning(k, v)

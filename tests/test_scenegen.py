@@ -72,11 +72,17 @@ def test_serving_requests():
     assert all(50 <= r.horizon <= 500 and 8 <= r.n_bodies <= 64 for r in reqs)
 
 
-def test_parallel_placement_equals_sequential():
+def test_parallel_placement_equals_sequential(monkeypatch):
     """Envs draw from their own streams, so placing chunks of envs in
-    separate processes gives the same scene bit for bit."""
-    a = sg.config_scene(4, n_envs=40)
-    b = sg.config_scene(4, n_envs=40, workers=3)
+    separate processes (the numpy placement's parallel form) gives the same
+    scene bit for bit."""
+    monkeypatch.setenv("VUDA_NUMPY_PLACEMENT", "1")
+    sg._PLACE_LIB.clear()
+    try:
+        a = sg.config_scene(4, n_envs=40)
+        b = sg.config_scene(4, n_envs=40, workers=3)
+    finally:
+        sg._PLACE_LIB.clear()
     for k in ("pos", "quat", "size", "btype", "body_off", "cam_w"):
         assert np.array_equal(getattr(a, k), getattr(b, k)), k
 

@@ -3,8 +3,8 @@
 // small candidate set, timing real iterations from a saved state.  The
 // coordinates, in order: schedule x CU split; fused raster; physics
 // persistent grid; raster-setup persistent grid; tile size; physics envs per
-// wave; hipGraph replay; raster workgroup size; step wave priority;
-// broadphase; presetup.  The serialized baseline takes the better of the
+// wave; hipGraph replay; raster workgroup size; tile-kernel workgroup size;
+// step wave priority; broadphase; presetup.  The serialized baseline takes the better of the
 // two raster paths and of two workgroup sizes.
 #include <hip/hip_runtime.h>
 
@@ -101,6 +101,8 @@ int apply(vuda_world* w, const Cand& c) {
     if (rc) return rc;
     std::fill(w->setup_ok.begin(), w->setup_ok.end(), 0);
     w->invalidate_lists();
+  } else if (c.tune.tile_waves != w->tune.tile_waves) {
+    w->invalidate_lists();  // tile jobs group tile_waves tiles
   }
   w->tune = c.tune;
   for (auto& g : w->graphs) (void)hipGraphExecDestroy(g.second);
@@ -139,6 +141,7 @@ void to_result(const Cand& c, vuda_tune_result* r) {
   r->phys_envs_per_wave = c.tune.phys_pack;
   r->tile_size = 1 << c.tune.tile_shift;
   r->raster_fused = c.tune.raster_fused ? 1 : 0;
+  r->tile_waves = c.tune.tile_waves;
 }
 
 bool cache_lookup(const char* path, const std::string& key, vuda_tune_result* r) {
@@ -154,7 +157,7 @@ bool cache_lookup(const char* path, const std::string& key, vuda_tune_result* r)
     if (is >> t.cu_split >> t.schedule >> t.raster_threads >> t.rec_cap >> t.phys_persistent >>
         t.raster_persistent >> t.phys_priority >> t.broadphase >> t.cosched_env_steps_per_s >>
         t.serial_env_steps_per_s >> t.serial_raster_threads >> t.serial_phys_persistent >> t.presetup >>
-        t.graphs >> t.phys_envs_per_wave >> t.tile_size >> t.raster_fused) {
+        t.graphs >> t.phys_envs_per_wave >> t.tile_size >> t.raster_fused >> t.tile_waves) {
       *r = t;  // the last matching line wins
       found = true;
     }
@@ -169,7 +172,7 @@ void cache_store(const char* path, const std::string& key, const vuda_tune_resul
     << " " << r.phys_persistent << " " << r.raster_persistent << " " << r.phys_priority << " "
     << r.broadphase << " " << r.cosched_env_steps_per_s << " " << r.serial_env_steps_per_s << " "
     << r.serial_raster_threads << " " << r.serial_phys_persistent << " " << r.presetup << " " << r.graphs << " "
-    << r.phys_envs_per_wave << " " << r.tile_size << " " << r.raster_fused << "\n";
+    << r.phys_envs_per_wave << " " << r.tile_size << " " << r.raster_fused << " " << r.tile_waves << "\n";
 }
 
 }  // namespace
@@ -201,6 +204,7 @@ extern "C" int vuda_autotune(vuda_world* w, int32_t steps, const char* cache_pat
     c.tune.phys_pack = out->phys_envs_per_wave == 2 ? 2 : 1;
     c.tune.tile_shift = out->tile_size == 8 ? 3 : (out->tile_size == 32 ? 5 : 4);
     c.tune.raster_fused = out->raster_fused != 0;
+    c.tune.tile_waves = out->tile_waves == 1 || out->tile_waves == 2 ? out->tile_waves : 4;
     out->trials = 0;
     return apply(w, c);
   }
@@ -270,7 +274,8 @@ extern "C" int vuda_autotune(vuda_world* w, int32_t steps, const char* cache_pat
   stage([](Cand& c, int v) { c.tune.tile_shift = v; }, {4, 5, 3});
   stage([](Cand& c, int v) { c.tune.phys_pack = v; }, {1, 2});
   stage([](Cand& c, int v) { c.tune.graphs = v != 0; }, {0, 1});
-  stage([](Cand& c, int v) { c.tune.raster_threads = v; }, {256, 512, 1024});
+  stage([](Cand& c, int v) { c.tune.raster_threads = v; }, {256, 128, 512, 1024});
+  stage([](Cand& c, int v) { c.tune.tile_waves = v; }, {4, 2, 1});
   stage([](Cand& c, int v) { c.tune.phys_prio = v; }, {0, 3});
   stage([](Cand& c, int v) { c.tune.broadphase = v; }, {0, 1});
   stage([](Cand& c, int v) { c.tune.presetup = v != 0; }, {1, 0});

@@ -49,7 +49,6 @@ namespace {
 
 constexpr int kMaxLdsTiles = 4096;  // tile table held in the setup kernel's LDS
 constexpr int kSmallMax = 64;       // box pixels in the tile of a fragment-packed triangle
-constexpr int kTileWaves = 4;       // tiles (one per wave) per tile-kernel workgroup
 constexpr int kWide = 8;            // triangles over more tiles are binned by their whole wave
 constexpr int kTplBytes = (int)((sizeof(Templates) + 15) & ~(size_t)15);
 
@@ -1218,10 +1217,11 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
   }
 }
 
-template <bool DBG, bool SMOOTH, int TS>
-__global__ void __launch_bounds__(64 * kTileWaves) raster_tile_kernel(WorldDev W, RasterLaunch L) {
-  __shared__ TileWaveLDS<TS> S[kTileWaves];
-  __shared__ int32_t C[DBG ? kTileWaves : 1][DBG ? TS * TS : 1];
+// TW tiles of a row per workgroup, one per wave
+template <bool DBG, bool SMOOTH, int TS, int TW>
+__global__ void __launch_bounds__(64 * TW) raster_tile_kernel(WorldDev W, RasterLaunch L) {
+  __shared__ TileWaveLDS<TS> S[TW];
+  __shared__ int32_t C[DBG ? TW : 1][DBG ? TS * TS : 1];
   const int2 job = L.tiles[blockIdx.x];
   if (job.x < 0) return;
   // uniform per wave: tile bookkeeping stays in scalar registers
@@ -1390,16 +1390,23 @@ hipError_t launch_raster_setup(const WorldDev& w, const RasterLaunch& l, hipStre
   return hipGetLastError();
 }
 
+template <int TS, int TW>
+static void launch_tiles(const WorldDev& w, const RasterLaunch& l, hipStream_t s, LaunchEvents* ev) {
+  const dim3 g(l.n_tile_groups), b(64 * TW);
+  if (l.smooth) {
+    if (w.winners) timed_launch(ev, true, true, raster_tile_kernel<true, true, TS, TW>, g, b, 0, s, w, l);
+    else timed_launch(ev, true, true, raster_tile_kernel<false, true, TS, TW>, g, b, 0, s, w, l);
+  } else {
+    if (w.winners) timed_launch(ev, true, true, raster_tile_kernel<true, false, TS, TW>, g, b, 0, s, w, l);
+    else timed_launch(ev, true, true, raster_tile_kernel<false, false, TS, TW>, g, b, 0, s, w, l);
+  }
+}
+
 template <int TS>
 static void launch_tiles(const WorldDev& w, const RasterLaunch& l, hipStream_t s, LaunchEvents* ev) {
-  const dim3 g(l.n_tile_groups), b(64 * kTileWaves);
-  if (l.smooth) {
-    if (w.winners) timed_launch(ev, true, true, raster_tile_kernel<true, true, TS>, g, b, 0, s, w, l);
-    else timed_launch(ev, true, true, raster_tile_kernel<false, true, TS>, g, b, 0, s, w, l);
-  } else {
-    if (w.winners) timed_launch(ev, true, true, raster_tile_kernel<true, false, TS>, g, b, 0, s, w, l);
-    else timed_launch(ev, true, true, raster_tile_kernel<false, false, TS>, g, b, 0, s, w, l);
-  }
+  if (l.tile_waves == 1) launch_tiles<TS, 1>(w, l, s, ev);
+  else if (l.tile_waves == 2) launch_tiles<TS, 2>(w, l, s, ev);
+  else launch_tiles<TS, 4>(w, l, s, ev);
 }
 
 hipError_t launch_raster_tiles(const WorldDev& w, const RasterLaunch& l, hipStream_t s, LaunchEvents* ev) {

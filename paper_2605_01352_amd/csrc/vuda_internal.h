@@ -176,7 +176,8 @@ struct RasterLaunch {
   const int32_t* work;     // camera ids, LPT order (setup kernel, one workgroup each)
   int32_t n_work;
   const int2* tiles;       // tile kernel: per workgroup (camera, tx | ty << 16): the tiles
-                           // tx .. tx + 3 of tile row ty; camera -1 for padding entries
+                           // tx .. tx + tile_waves - 1 of tile row ty; camera -1 for padding
+                           // entries
   int32_t n_tile_groups;
   int32_t max_verts;       // over the listed cameras' envs
   int32_t max_tiles;
@@ -191,6 +192,7 @@ struct RasterLaunch {
   int32_t near_clip;       // setup kernel: cut triangles crossing the near plane
   int32_t smooth;          // per-pixel shading of interpolated vertex normals
   int32_t tile_shift;      // raster tiles of edge 1 << tile_shift (8, 16 or 32 pixels)
+  int32_t tile_waves;      // tile kernel: tiles (one per wave) per workgroup, 1, 2 or 4
   // fused kernel only (raster_fused_plan): LDS bytes reserved for the tile
   // pass's z-buffers, compact records and bin entries an image keeps in LDS
   int32_t lds_zone0, lrec_cap, lbin_cap;

@@ -824,7 +824,7 @@ int vuda_world::get_list(int phase, int32_t lo, int32_t hi, const WorkList** out
   L.n = (int32_t)ids.size();
   L.n_groups = 0;
   if (phase == VUDA_PHASE_RENDER && !ids.empty()) {
-    // Tile-kernel jobs of 4 tiles of a row.  Workgroups are handed to the 8 XCDs
+    // Tile-kernel jobs of tile_waves tiles of a row.  Workgroups are handed to the 8 XCDs
     // round-robin, so the setup workgroup of image i runs on XCD i mod 8;
     // its tiles get job indices of the same residue, where that XCD's L2
     // still holds the image's records and bins.
@@ -835,7 +835,8 @@ int vuda_world::get_list(int phase, int32_t lo, int32_t hi, const WorkList** out
       const int ts = 1 << tune.tile_shift;
       const int32_t ntx = (cd.w + ts - 1) >> tune.tile_shift, nty = (cd.h + ts - 1) >> tune.tile_shift;
       for (int32_t ty = 0; ty < nty; ++ty)
-        for (int32_t tx = 0; tx < ntx; tx += 4) per[i % kXcd].push_back(make_int2(ids[i], tx | (ty << 16)));
+        for (int32_t tx = 0; tx < ntx; tx += tune.tile_waves)
+          per[i % kXcd].push_back(make_int2(ids[i], tx | (ty << 16)));
     }
     size_t len = 0;
     for (auto& v : per) len = std::max(len, v.size());
@@ -915,6 +916,8 @@ int vuda_world::raster_launch_of(const WorkList& L, int parity, int32_t* queue, 
   rl.near_clip = near_clip ? 1 : 0;
   rl.smooth = smooth ? 1 : 0;
   rl.tile_shift = tune.tile_shift;
+  rl.tile_waves = tune.tile_waves;
+  rl.lds_zone0 = rl.lrec_cap = rl.lbin_cap = 0;
   const size_t lds = raster_lds_bytes(rl);
   const size_t kLdsMax = 160 * 1024;
   if (lds > kLdsMax)
@@ -1934,6 +1937,13 @@ extern "C" int vuda_set_tuning(vuda_world* w, int32_t key, int32_t value) {
       // one stepped in fused mode has no setup, so its render sets up
       w->tune.raster_fused = value != 0;
       break;
+    case VUDA_TUNE_TILE_WAVES:
+      if (value != 1 && value != 2 && value != 4) return fail(VUDA_EINVAL, "tile waves %d (1, 2 or 4)", value);
+      if (value != w->tune.tile_waves) {
+        w->tune.tile_waves = value;
+        w->invalidate_lists();  // the tile jobs group tile_waves tiles
+      }
+      break;
     case VUDA_TUNE_FUSED_LDS_RECORDS:
       if (value < 0) return fail(VUDA_EINVAL, "fused LDS records %d", value);
       w->tune.fused_recs = value;
@@ -1976,6 +1986,7 @@ extern "C" int vuda_get_tuning(vuda_world* w, int32_t key, int32_t* value) {
     case VUDA_TUNE_TILE_SIZE: *value = 1 << w->tune.tile_shift; break;
     case VUDA_TUNE_RASTER_FUSED: *value = w->tune.raster_fused ? 1 : 0; break;
     case VUDA_TUNE_FUSED_LDS_RECORDS: *value = w->tune.fused_recs; break;
+    case VUDA_TUNE_TILE_WAVES: *value = w->tune.tile_waves; break;
     default: return fail(VUDA_EINVAL, "tuning key %d", key);
   }
   return VUDA_OK;

@@ -93,6 +93,10 @@ C2 = dict(cfg=2, n_envs=48, settle=250)
     ("two envs per physics wave, persistent, CU-masked 0.375, inter-trajectory", 0.375, vuda.SCHED_INTERTRAJ,
      {vuda.TUNE_PHYS_ENVS_PER_WAVE: 2, vuda.TUNE_PHYS_PERSISTENT: 7}),
     ("fused raster, unmasked, inter-step", 2.0, vuda.SCHED_INTERSTEP, {vuda.TUNE_RASTER_FUSED: 1}),
+    ("setup workgroups of 128, tile workgroups of 2 waves, unmasked, inter-step", 2.0, vuda.SCHED_INTERSTEP,
+     {vuda.TUNE_RASTER_THREADS: 128, vuda.TUNE_TILE_WAVES: 2}),
+    ("tile workgroups of 1 wave, CU-masked 0.5, inter-trajectory", 0.5, vuda.SCHED_INTERTRAJ,
+     {vuda.TUNE_TILE_WAVES: 1}),
     ("fused raster 512 threads, serialized", 0.0, vuda.SCHED_SERIAL,
      {vuda.TUNE_RASTER_FUSED: 1, vuda.TUNE_RASTER_THREADS: 512}),
     ("fused raster, persistent + graphs, CU-masked 0.375, inter-trajectory", 0.375, vuda.SCHED_INTERTRAJ,

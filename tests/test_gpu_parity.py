@@ -133,7 +133,9 @@ def test_tuning_knobs_do_not_change_outputs():
                   {vuda.TUNE_TILE_SIZE: 32, vuda.TUNE_REC_CAP: 64},
                   {vuda.TUNE_RASTER_FUSED: 1}, {vuda.TUNE_RASTER_FUSED: 1, vuda.TUNE_RASTER_THREADS: 1024},
                   {vuda.TUNE_RASTER_FUSED: 1, vuda.TUNE_FUSED_LDS_RECORDS: 60},
-                  {vuda.TUNE_RASTER_FUSED: 1, vuda.TUNE_TILE_SIZE: 8, vuda.TUNE_RASTER_PERSISTENT: 5}):
+                  {vuda.TUNE_RASTER_FUSED: 1, vuda.TUNE_TILE_SIZE: 8, vuda.TUNE_RASTER_PERSISTENT: 5},
+                  {vuda.TUNE_TILE_WAVES: 1}, {vuda.TUNE_TILE_WAVES: 2, vuda.TUNE_TILE_SIZE: 8},
+                  {vuda.TUNE_TILE_WAVES: 2, vuda.TUNE_RASTER_THREADS: 128, vuda.TUNE_GRAPHS: 1}):
         with vuda.World(s) as w:
             for k, v in knobs.items():
                 w.set_tuning(k, v)

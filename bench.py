@@ -554,7 +554,7 @@ def main():
     if args.raster in ("auto", "two"):
         shapes = [(two_threads, two_waves)]
         if args.raster == "auto":
-            shapes += [(t, wv) for t, wv in ((128, 4), (128, 2), (256, 2)) if (t, wv) != shapes[0]]
+            shapes += [(t, wv) for t, wv in ((128, 4), (128, 2), (256, 2), (256, 4)) if (t, wv) != shapes[0]]
         for t, wv in shapes:
             path_knobs[f"t{t}w{wv}"] = {vuda.TUNE_RASTER_FUSED: 0, vuda.TUNE_RASTER_THREADS: t,
                                         vuda.TUNE_TILE_WAVES: wv}

@@ -339,7 +339,7 @@ int vuda_world_info(vuda_world* w, int32_t* n_envs, int64_t* n_bodies, int32_t* 
  *                              most n (with 4 bin entries each; less LDS per
  *                              workgroup); an image with more records or bin
  *                              entries passes them through the raster scratch
- *   VUDA_TUNE_TILE_WAVES       1, 2 or 4 (default): tiles of a row per tile-kernel
+ *   VUDA_TUNE_TILE_WAVES       1, 2 (default) or 4: tiles of a row per tile-kernel
  *                              workgroup, one per wave (smaller workgroups fit
  *                              beside the step's on shared CUs)
  * None of the others changes any output bit.  Returns VUDA_EINVAL for unknown keys

@@ -275,7 +275,7 @@ extern "C" int vuda_autotune(vuda_world* w, int32_t steps, const char* cache_pat
   stage([](Cand& c, int v) { c.tune.phys_pack = v; }, {1, 2});
   stage([](Cand& c, int v) { c.tune.graphs = v != 0; }, {0, 1});
   stage([](Cand& c, int v) { c.tune.raster_threads = v; }, {256, 128, 512, 1024});
-  stage([](Cand& c, int v) { c.tune.tile_waves = v; }, {4, 2, 1});
+  stage([](Cand& c, int v) { c.tune.tile_waves = v; }, {2, 4, 1});
   stage([](Cand& c, int v) { c.tune.phys_prio = v; }, {0, 3});
   stage([](Cand& c, int v) { c.tune.broadphase = v; }, {0, 1});
   stage([](Cand& c, int v) { c.tune.presetup = v != 0; }, {1, 0});

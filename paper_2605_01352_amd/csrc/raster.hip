@@ -20,8 +20,8 @@
 //      tiles of its box, after an exact corner test of the edge functions
 //      where its box in the tile is large, flagged when the triangle covers
 //      the whole tile.
-// raster_tile_kernel, one wave per tile and four tiles per workgroup; a lane
-//   owns four horizontally adjacent pixels.  The bin is read in batches of 64
+// raster_tile_kernel, one wave per tile and one, two or four tiles of a row
+//   per workgroup; a lane owns four horizontally adjacent pixels.  The bin is read in batches of 64
 //   records.  Small triangles (at most 64 pixels of their box in the tile)
 //   are expanded into fragments, one pixel per lane across several
 //   triangles, whose keys meet in an LDS z-buffer through atomic minimum;

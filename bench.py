@@ -413,7 +413,7 @@ def main():
     ap.add_argument("--no-c4", action="store_true", help="skip the autotuned leg at the uneven 2048-env config")
     ap.add_argument("--serve-seconds", type=float, default=120.0,
                     help="length of the continuous-batching serving run (0: skip)")
-    ap.add_argument("--capacity-rates", default="100,200,400,800",
+    ap.add_argument("--capacity-rates", default="100,150,200,300,400",
                     help="arrival rates of the serving capacity sweep, 8 s each (empty: skip)")
     ap.add_argument("--splits", default="0.25,0.375,0.5,0.625,0.75")
     ap.add_argument("--prios", default="3",
@@ -703,7 +703,7 @@ def main():
         rates = [float(x) for x in args.capacity_rates.split(",") if x.strip()]
         if rates:
             log("serving capacity: rising arrival rates ...")
-            serving["capacity"] = srv.capacity(rates=rates, seconds=8.0, log=log)
+            serving["capacity"] = srv.capacity(rates=rates, seconds=10.0, log=log)
 
     cpu = None
     if not args.no_cpu:

@@ -414,7 +414,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=120.0,
                     help="length of the continuous-batching serving run (0: skip)")
     ap.add_argument("--capacity-rates", default="100,150,200,300,400",
-                    help="arrival rates of the serving capacity sweep, 8 s each (empty: skip)")
+                    help="arrival rates of the serving capacity sweep, 10 s each (empty: skip)")
     ap.add_argument("--splits", default="0.25,0.375,0.5,0.625,0.75")
     ap.add_argument("--prios", default="3",
                     help="issue priorities of the step's waves tried on unmasked streams")

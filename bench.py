@@ -483,7 +483,8 @@ def main():
                 "phys_prio": vuda.TUNE_PHYS_PRIORITY, "broadphase": vuda.TUNE_BROADPHASE,
                 "presetup": vuda.TUNE_PRESETUP, "policy_layered": vuda.TUNE_POLICY_LAYERED,
                 "phys_pack": vuda.TUNE_PHYS_ENVS_PER_WAVE, "tile": vuda.TUNE_TILE_SIZE,
-                "fused": vuda.TUNE_RASTER_FUSED, "fused_recs": vuda.TUNE_FUSED_LDS_RECORDS}
+                "fused": vuda.TUNE_RASTER_FUSED, "fused_recs": vuda.TUNE_FUSED_LDS_RECORDS,
+                "tile_waves": vuda.TUNE_TILE_WAVES}
     for kv in filter(None, args.tune.split(",")):
         k, v = kv.split("=")
         w.set_tuning(knob_ids[k], int(v))

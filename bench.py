@@ -654,13 +654,13 @@ def main():
                   "raster_fused": 28 * body_cams + 7 * px}
     per_step = {k: live[k]["launches"] / args.steps for k in step_bytes}
     kinds = {}
-    for kname in step_bytes:
-        lb = step_bytes[kname] / max(per_step[kname], 1e-9)  # launches split the env range evenly
+    for kname in [k for k in step_bytes if per_step[k] > 0]:  # kernels the timed window launched
+        lb = step_bytes[kname] / per_step[kname]  # launches split the env range evenly
         t = live[kname]["avg_s"]
         kinds[kname] = {"launch_us": round(t * 1e6, 2), "bytes_per_launch": int(lb),
                         "launches_per_step": per_step[kname], "GBs": round(lb / t / 1e9, 2) if t else None,
                         "alone_launch_us": round(alone[kname]["avg_s"] * 1e6, 2)}
-    dom = max(step_bytes, key=lambda k: kinds[k]["launch_us"] * per_step[k])
+    dom = max(kinds, key=lambda k: kinds[k]["launch_us"] * per_step[k])
     ach = kinds[dom]["GBs"]
     # measured HBM bytes of a whole-workload launch, scaled to the share of
     # the workload one launch of the timed window covers
@@ -672,7 +672,7 @@ def main():
             "traffic_note": (f"counters of a whole-workload launch from step {start} "
                              f"({tr_full} B), times the launch's share {share:g}") if tr_full else None,
             "bytes_per_launch": kinds[dom]["bytes_per_launch"], "launch_us": kinds[dom]["launch_us"],
-            **{k: kinds[k] for k in step_bytes}}
+            **kinds}
 
     c3 = None
     if scene3 is not None:

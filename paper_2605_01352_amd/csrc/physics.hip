@@ -80,8 +80,7 @@ struct PhysLDS {
   static constexpr int CAPC = 4 * N;  // candidate pairs
   static_assert(CAPC <= 1024 && N <= 2048, "cube-cube queue packing");
   static constexpr int CAPK = 2 * N;  // pairs in contact
-  float4 pr[N];  // position and bounding radius, for the all-pairs broadphase
-  float p[3][N];
+  float4 pr[N];  // position and bounding radius (the substep-start position of every phase)
   float v[3][N];
   float w[3][N];
   float R[9][N];
@@ -90,18 +89,24 @@ struct PhysLDS {
   float inert[3][N];  // principal moments of a box
   float rb[N];
   int32_t type[N];
-  uint64_t bucket[2 * N][NW];
+  // arrays of disjoint phases of a substep share their storage: the grid
+  // buckets (broadphase), the sorted candidate pairs (compaction and the
+  // narrowphase of pairs with a sphere) and the per-lane point terms of the
+  // box-pair and ground groups; a barrier separates each from the next
+  union alignas(16) {
+    uint64_t bucket[2 * N][NW];
+    uint32_t cand[CAPC];    // candidate pairs i | j << 16, sorted
+    float stage[9][N];      // one contact point's terms per lane, before the ordered sum
+  };
   uint64_t rowCand[N][NW];
   uint64_t rowC[N][NW];
   uint64_t colC[N][NW];
   int32_t cstart[N];      // candidate-list start of each row
   int32_t gflag[N];       // body touches the ground
-  uint32_t cand[CAPC];    // candidate pairs i | j << 16, sorted
   uint16_t kslot[CAPC];   // slot of each candidate in contact
   uint32_t ccl[CAPC];     // candidates whose bodies are both cubes: k | i << 10 | j << 21
   int32_t gcl[N];         // cubes closer to the ground than their bounding radius
   float kres[9][CAPK];    // SF xyz, Ti xyz, Tj xyz of each pair in contact
-  alignas(16) float stage[9][N];  // one contact point's terms per lane, before the ordered sum
   float estage[9][N / 16];        // terms of the edge-edge point of each 16-lane group
   float gres[6][N];       // ground force and torque of each body
   int32_t scan[NW + 1];
@@ -195,7 +200,8 @@ struct Point {
 
 template <int N>
 __device__ __forceinline__ f3 ldsP(const PhysLDS<N>& s, int b) {
-  return mk(s.p[0][b], s.p[1][b], s.p[2][b]);
+  const float4 q = s.pr[b];
+  return mk(q.x, q.y, q.z);
 }
 template <int N>
 __device__ __forceinline__ f3 ldsV(const PhysLDS<N>& s, int b) {
@@ -639,7 +645,6 @@ __device__ void step_env(PhysLDS<N>& s, const WorldDev& W, const PhysConsts& pc,
     // 1. publish substep-start state
     M3 R = quat_to_rot(qw, qx, qy, qz);
     if (own) {
-      s.p[0][tid] = p.x; s.p[1][tid] = p.y; s.p[2][tid] = p.z;
       s.pr[tid] = make_float4(p.x, p.y, p.z, rbv);
       s.v[0][tid] = v.x; s.v[1][tid] = v.y; s.v[2][tid] = v.z;
       s.w[0][tid] = w.x; s.w[1][tid] = w.y; s.w[2][tid] = w.z;

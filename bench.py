@@ -30,6 +30,11 @@ def log(*a):
 
 
 def enqueue(w, schedule, n_envs, iters):
+    if schedule == "pipelined":
+        # tiles of S_t beside the setup of S_t+1 beside the step S_t+1 -> S_t+2
+        from paper_2605_01352_amd import vuda
+        w.run(vuda.SCHED_PIPELINED, iters)
+        return
     half = n_envs // 2
     for _ in range(iters):
         if schedule == "serial":
@@ -591,9 +596,10 @@ def main():
     # waves (they share CUs with the render's)
     p0 = w.get_tuning(vuda.TUNE_PHYS_PRIORITY)
     prios = [int(p) for p in filter(None, args.prios.split(",")) if int(p) != p0]
-    cands = [(2.0, sched, p0) for sched in ("interstep", "intertraj")]
-    cands += [(2.0, sched, p) for p in prios for sched in ("interstep", "intertraj")]
-    cands += [(float(x), sched, p0) for x in filter(None, args.splits.split(",")) for sched in ("interstep", "intertraj")]
+    scheds = ("interstep", "intertraj", "pipelined")
+    cands = [(2.0, sched, p0) for sched in scheds]
+    cands += [(2.0, sched, p) for p in prios for sched in scheds]
+    cands += [(float(x), sched, p0) for x in filter(None, args.splits.split(",")) for sched in scheds]
     cands = [c + (path,) for path in paths for c in cands]
     if args.only:
         cands = []

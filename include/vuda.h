@@ -470,12 +470,21 @@ int vuda_probe_placement(vuda_world* w, int32_t phase, int32_t n_blocks, int32_t
 #define VUDA_SCHED_INTERTRAJ 2  /* envs split in two halves: step(A) beside
                                    render(B), then step(B) beside render(A), the
                                    paper's inter-trajectory parallelism             */
+#define VUDA_SCHED_PIPELINED 3  /* three stages on three streams: tiles of S_t
+                                   beside the raster setup of S_t+1 beside the
+                                   step S_t+1 -> S_t+2, each stage waiting only
+                                   for the previous iteration; the same steps
+                                   and frames as VUDA_SCHED_INTERSTEP (inter-step
+                                   order on one stream or with the fused raster) */
 
 /*
  * Enqueue `iters` iterations of a schedule over every active env: each
  * iteration advances every env one step and renders it once (Parallelism
  * Patterns: inter-step and inter-trajectory overlap).  Uses the current
  * co-scheduling mode; with VUDA_SCHED_SERIAL the phases follow each other.
+ * After the call the frames show the state before the last step (the
+ * inter-step and pipelined schedules) or after it (serial; inter-trajectory:
+ * after it for the first half of the envs, before it for the second).
  * All active envs must have the same step parity.
  */
 int vuda_run(vuda_world* w, int32_t schedule, int32_t iters);

@@ -248,7 +248,7 @@ extern "C" int vuda_autotune(vuda_world* w, int32_t steps, const char* cache_pat
   double best_rate = -1.0;
   if (!rc) {
     const float splits[] = {2.0f, 0.25f, 0.375f, 0.5f, 0.625f, 0.75f};
-    for (int sched : {VUDA_SCHED_INTERSTEP, VUDA_SCHED_INTERTRAJ})
+    for (int sched : {VUDA_SCHED_INTERSTEP, VUDA_SCHED_INTERTRAJ, VUDA_SCHED_PIPELINED})
       for (float sp : splits) {
         Cand c = best;
         c.sched = sched;

@@ -168,7 +168,7 @@ struct vuda_server {
 extern "C" int vuda_serve_create(const vuda_world_desc* desc, float cu_split, int32_t schedule,
                                  int32_t keep_results, vuda_server** out) {
   if (!desc || !out) return fail(VUDA_EINVAL, "null argument");
-  if (schedule < VUDA_SCHED_SERIAL || schedule > VUDA_SCHED_INTERTRAJ)
+  if (schedule < VUDA_SCHED_SERIAL || schedule > VUDA_SCHED_PIPELINED)
     return fail(VUDA_EINVAL, "schedule %d", schedule);
   *out = nullptr;
   vuda_server* s = new (std::nothrow) vuda_server();

@@ -167,6 +167,7 @@ struct vuda_world {
   // streams: mode 0 serialized (s_sim == s_render == s_serial), 1 CU-masked,
   // 2 two unmasked streams
   hipStream_t s_serial = nullptr, s_sim = nullptr, s_render = nullptr, s_capture = nullptr;
+  hipStream_t s_setup = nullptr;  // raster setup of the pipelined schedule (the step's CUs)
   int mode = 0;
   float cu_split = 0.0f;
 

@@ -625,7 +625,8 @@ extern "C" int vuda_world_info(vuda_world* w, int32_t* n_envs, int64_t* n_bodies
 void vuda_world::destroy_streams() {
   if (s_sim && s_sim != s_serial) (void)hipStreamDestroy(s_sim);
   if (s_render && s_render != s_serial) (void)hipStreamDestroy(s_render);
-  s_sim = s_render = nullptr;
+  if (s_setup && s_setup != s_serial) (void)hipStreamDestroy(s_setup);
+  s_sim = s_render = s_setup = nullptr;
 }
 
 // Bit i of a HIP CU mask selects a CU of XCD (i mod n_xcd), then of shader
@@ -657,16 +658,19 @@ int vuda_world::make_streams(float split) {
     cu_masks(prop.multiProcessorCount, split, ms, mr);
     HIPCHK(hipExtStreamCreateWithCUMask(&s_sim, (uint32_t)ms.size(), ms.data()));
     HIPCHK(hipExtStreamCreateWithCUMask(&s_render, (uint32_t)mr.size(), mr.data()));
+    HIPCHK(hipExtStreamCreateWithCUMask(&s_setup, (uint32_t)ms.size(), ms.data()));
     mode = 1;
     cu_split = split;
   } else if (split == 2.0f) {
     HIPCHK(hipStreamCreateWithFlags(&s_sim, hipStreamNonBlocking));
     HIPCHK(hipStreamCreateWithFlags(&s_render, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&s_setup, hipStreamNonBlocking));
     mode = 2;
     cu_split = split;
   } else {
     s_sim = s_serial;
     s_render = s_serial;
+    s_setup = s_serial;
   }
   return VUDA_OK;
 }
@@ -675,6 +679,7 @@ int vuda_world::drain() {
   HIPCHK(hipSetDevice(device));
   if (s_sim) HIPCHK(hipStreamSynchronize(s_sim));
   if (s_render) HIPCHK(hipStreamSynchronize(s_render));
+  if (s_setup) HIPCHK(hipStreamSynchronize(s_setup));
   if (s_serial) HIPCHK(hipStreamSynchronize(s_serial));
   return VUDA_OK;
 }
@@ -2032,10 +2037,100 @@ int32_t vuda_world::active_midpoint() {
   return n_envs_hi;
 }
 
+// Three-stage pipeline: iteration k rasterizes the tiles of S_k on the render
+// stream, sets up S_k+1 on the setup stream and steps S_k+1 -> S_k+2 on the
+// step stream, each waiting only for work of iteration k - 1: the setup of
+// S_k+1 for the step that produced it and for the tiles of S_k-1 (which read
+// the raster scratch of its parity), the tiles of S_k for its setup, the step
+// for the setup of S_k (which reads the state buffer the step overwrites).
+// After `iters` iterations the frames show S_iters-1 and the state is
+// S_iters with its setup done, as after the inter-step schedule.  On one
+// stream, or with the fused raster (a render that sets itself up), the
+// inter-step order runs instead.
+static int run_pipelined(vuda_world* w, int32_t iters) {
+  const int32_t hi = w->n_envs_hi;
+  int parity;
+  int rc = w->range_parity(0, hi, &parity);
+  if (rc) return rc;
+  const WorkList *LS, *LR;
+  rc = w->get_list(VUDA_PHASE_STEP, 0, hi, &LS);
+  if (!rc) rc = w->get_list(VUDA_PHASE_RENDER, 0, hi, &LR);
+  if (rc) return rc;
+  RasterLaunch rl;
+  size_t lds;
+  rc = w->fused_launch_of(*LR, parity, nullptr, &rl, &lds);
+  if (rc) return rc;
+  if (w->mode == 0 || lds) {
+    for (int32_t t = 0; t < iters; ++t) {
+      rc = vuda_render(w, 0, hi);
+      if (!rc) rc = vuda_step(w, 0, hi, 1);
+      if (rc) return rc;
+    }
+    return VUDA_OK;
+  }
+  hipStream_t ss = w->s_sim, su = w->s_setup, sr = w->s_render;
+  // every stage starts after all earlier work of these envs (the step
+  // events are on the step stream, the render events on the render stream:
+  // the latest of each covers the others)
+  int64_t ls = -1, lr = -1;
+  bool need_setup = false;
+  for (int32_t e = 0; e < hi; ++e) {
+    if (!w->env_active[e]) continue;
+    ls = std::max(ls, w->step_ev[e]);
+    lr = std::max({lr, w->render_ev[0][e], w->render_ev[1][e]});
+    need_setup |= !w->setup_ok[e];
+  }
+  for (hipStream_t s : {ss, su, sr}) {
+    if ((rc = w->wait_event(s, ls)) || (rc = w->wait_event(s, lr))) return rc;
+  }
+  int64_t ev_setup = -1, ev_phys = -1, ev_tiles_prev = -1;
+  if (need_setup) {
+    if ((rc = w->run_kernel(kKernelSetup, *LR, parity, 0, hi, su, w->queues + 1))) return rc;
+    if ((rc = w->new_event(su, &ev_setup))) return rc;
+  }
+  if ((rc = w->run_kernel(kKernelPhysics, *LS, parity, 0, hi, ss, w->queues))) return rc;
+  if ((rc = w->new_event(ss, &ev_phys))) return rc;
+  for (int32_t k = 0; k < iters; ++k) {
+    const int pk = parity ^ (k & 1);  // state buffer and scratch parity of S_k
+    // tiles of S_k
+    if ((rc = w->wait_event(sr, ev_setup))) return rc;
+    if ((rc = w->run_kernel(kKernelTiles, *LR, pk, 0, hi, sr, nullptr))) return rc;
+    int64_t ev_tiles;
+    if ((rc = w->new_event(sr, &ev_tiles))) return rc;
+    // setup of S_k+1
+    if ((rc = w->wait_event(su, ev_phys)) || (rc = w->wait_event(su, ev_tiles_prev))) return rc;
+    if ((rc = w->run_kernel(kKernelSetup, *LR, pk ^ 1, 0, hi, su, w->queues + 1))) return rc;
+    int64_t ev_setup_next;
+    if ((rc = w->new_event(su, &ev_setup_next))) return rc;
+    // step S_k+1 -> S_k+2, into the buffer of S_k
+    if (k + 2 <= iters) {
+      if ((rc = w->wait_event(ss, ev_setup))) return rc;
+      if ((rc = w->run_kernel(kKernelPhysics, *LS, pk ^ 1, 0, hi, ss, w->queues))) return rc;
+      if ((rc = w->new_event(ss, &ev_phys))) return rc;
+    }
+    ev_setup = ev_setup_next;
+    ev_tiles_prev = ev_tiles;
+  }
+  // the step and render streams take over the last setup; their events then
+  // cover everything enqueued here
+  if ((rc = w->wait_event(ss, ev_setup)) || (rc = w->wait_event(sr, ev_setup))) return rc;
+  int64_t sid, rid;
+  if ((rc = w->new_event(ss, &sid)) || (rc = w->new_event(sr, &rid))) return rc;
+  for (int32_t e = 0; e < hi; ++e) {
+    if (!w->env_active[e]) continue;
+    if (iters & 1) w->env_parity[e] ^= 1;
+    w->step_ev[e] = sid;
+    w->render_ev[0][e] = w->render_ev[1][e] = rid;
+    w->setup_ok[e] = 1;
+  }
+  return VUDA_OK;
+}
+
 extern "C" int vuda_run(vuda_world* w, int32_t schedule, int32_t iters) {
   if (!w) return fail(VUDA_EINVAL, "null world");
-  if (iters < 0 || schedule < VUDA_SCHED_SERIAL || schedule > VUDA_SCHED_INTERTRAJ)
+  if (iters < 0 || schedule < VUDA_SCHED_SERIAL || schedule > VUDA_SCHED_PIPELINED)
     return fail(VUDA_EINVAL, "schedule %d / iters %d", schedule, iters);
+  if (schedule == VUDA_SCHED_PIPELINED) return iters ? run_pipelined(w, iters) : VUDA_OK;
   const int32_t hi = w->n_envs_hi;
   const int32_t mid = schedule == VUDA_SCHED_INTERTRAJ ? w->active_midpoint() : 0;
   for (int32_t t = 0; t < iters; ++t) {

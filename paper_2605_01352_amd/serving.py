@@ -142,11 +142,11 @@ def main():
     ap.add_argument("--rate", type=float, default=50.0)
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--split", type=float, default=2.0)
-    ap.add_argument("--schedule", default="interstep", choices=["serial", "interstep", "intertraj"])
+    ap.add_argument("--schedule", default="interstep", choices=["serial", "interstep", "intertraj", "pipelined"])
     ap.add_argument("--capacity", action="store_true", help="also sweep the arrival rate for the capacity")
     a = ap.parse_args()
     sched = {"serial": vuda.SCHED_SERIAL, "interstep": vuda.SCHED_INTERSTEP,
-             "intertraj": vuda.SCHED_INTERTRAJ}[a.schedule]
+             "intertraj": vuda.SCHED_INTERTRAJ, "pipelined": vuda.SCHED_PIPELINED}[a.schedule]
     lg = lambda *x: print(*x, file=sys.stderr, flush=True)
     res = run(a.duration, a.rate, a.budget_gb, a.split, sched, log=lg)
     if a.capacity:

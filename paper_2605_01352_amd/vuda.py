@@ -46,8 +46,9 @@ EXPORTS = [
     "vuda_serve_tick", "vuda_serve_completed", "vuda_serve_result", "vuda_serve_stats",
     "vuda_serve_world", "vuda_kernel_times", "vuda_policy_set", "vuda_act", "vuda_act_noalloc",
 ]
-SCHED_SERIAL, SCHED_INTERSTEP, SCHED_INTERTRAJ = 0, 1, 2
-SCHED_NAMES = {SCHED_SERIAL: "serial", SCHED_INTERSTEP: "interstep", SCHED_INTERTRAJ: "intertraj"}
+SCHED_SERIAL, SCHED_INTERSTEP, SCHED_INTERTRAJ, SCHED_PIPELINED = 0, 1, 2, 3
+SCHED_NAMES = {SCHED_SERIAL: "serial", SCHED_INTERSTEP: "interstep", SCHED_INTERTRAJ: "intertraj",
+               SCHED_PIPELINED: "pipelined"}
 
 
 class VudaError(RuntimeError):

@@ -8,6 +8,7 @@ bit-exact, RGB within 1/255) are checked here at every iteration of:
     inter-trajectory with raised step priority);
   - persistent launches with hipGraph replay (c2 and the uneven c4 mix);
   - the fused raster path (setup and tiles in one kernel);
+  - the three-stage pipelined schedule, one iteration per call and many;
   - the configuration the autotuner picks;
   - the uniform-grid broadphase on settled piles of 100 and 128 bodies,
     automatic and forced, and its fallback for cells far from the origin.
@@ -97,6 +98,12 @@ C2 = dict(cfg=2, n_envs=48, settle=250)
      {vuda.TUNE_RASTER_THREADS: 128, vuda.TUNE_TILE_WAVES: 2}),
     ("tile workgroups of 1 wave, CU-masked 0.5, inter-trajectory", 0.5, vuda.SCHED_INTERTRAJ,
      {vuda.TUNE_TILE_WAVES: 1}),
+    ("pipelined, unmasked", 2.0, vuda.SCHED_PIPELINED, {}),
+    ("pipelined, CU-masked 0.5", 0.5, vuda.SCHED_PIPELINED, {}),
+    ("pipelined, persistent + graphs, setup workgroups of 128", 2.0, vuda.SCHED_PIPELINED,
+     {vuda.TUNE_PHYS_PERSISTENT: 24, vuda.TUNE_RASTER_PERSISTENT: 40, vuda.TUNE_GRAPHS: 1,
+      vuda.TUNE_RASTER_THREADS: 128}),
+    ("pipelined with the fused raster (inter-step order)", 2.0, vuda.SCHED_PIPELINED, {vuda.TUNE_RASTER_FUSED: 1}),
     ("fused raster 512 threads, serialized", 0.0, vuda.SCHED_SERIAL,
      {vuda.TUNE_RASTER_FUSED: 1, vuda.TUNE_RASTER_THREADS: 512}),
     ("fused raster, persistent + graphs, CU-masked 0.375, inter-trajectory", 0.375, vuda.SCHED_INTERTRAJ,
@@ -112,6 +119,45 @@ def test_c2_schedule_parity(label, split, sched, knobs):
             w.set_tuning(k, v)
         w.cosched(split)
         parity_iterations(w, scene, sched, 6, f"c2[0:48] @250, {label}")
+
+
+@pytest.mark.parametrize("split,knobs", [
+    (2.0, {}),
+    (0.5, {}),
+    (2.0, {vuda.TUNE_PHYS_PERSISTENT: 24, vuda.TUNE_RASTER_PERSISTENT: 40, vuda.TUNE_GRAPHS: 1}),
+    (0.0, {}),
+], ids=["unmasked", "cu-masked", "persistent-graphs", "one-stream"])
+def test_pipelined_runs(split, knobs):
+    """Many iterations in one pipelined call (the stages of consecutive
+    iterations overlap): 11 iterations from a settled state, then 3 single
+    iterations checked against the oracle, then a mix with plain step and
+    render calls; state and frames bit-identical to a serialized world that
+    made the same iterations."""
+    oracle.lib()
+    scene = sg.config_scene(C2["cfg"], n_envs=C2["n_envs"])
+    with settled_world(scene, C2["settle"]) as w, settled_world(scene, C2["settle"]) as ref:
+        for k, v in knobs.items():
+            w.set_tuning(k, v)
+        w.cosched(split)
+        w.run(vuda.SCHED_PIPELINED, 11)
+        parity_iterations(w, scene, vuda.SCHED_PIPELINED, 3, f"c2[0:48] @250, pipelined after 11, split {split}")
+        w.run(vuda.SCHED_PIPELINED, 4)
+        w.step()
+        w.render()
+        w.run(vuda.SCHED_PIPELINED, 2)
+        w.wait()
+        for _ in range(11 + 3 + 4):
+            ref.render()
+            ref.step()
+        ref.step()
+        ref.render()
+        for _ in range(2):
+            ref.render()
+            ref.step()
+        ref.wait()
+        for what in (vuda.FETCH_STATE, vuda.FETCH_RGB, vuda.FETCH_DEPTH):
+            assert np.array_equal(w.fetch(what), ref.fetch(what)), what
+        say(f"pipelined, split {split} {knobs}: 25 iterations bit-identical to the serialized loop")
 
 
 def test_c4_persistent_graph_parity():

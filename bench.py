@@ -23,6 +23,7 @@ CSRC = os.path.join(ROOT, "paper_2605_01352_amd", "csrc")
 KERNEL_SOURCES = {"raster_tiles": ["raster.hip", "vuda_internal.h"], "raster_setup": ["raster.hip", "vuda_internal.h"],
                   "raster_fused": ["raster.hip", "vuda_internal.h"], "physics": ["physics.hip", "vuda_internal.h"]}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.md")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_c{}.md")
 
 
 def log(*a):
@@ -130,6 +131,54 @@ def copy_calibration(torch, mib):
         b.copy_(a)
     torch.cuda.synchronize()
     del a, b
+
+
+def copy_ceiling(torch, mib=1024, reps=5):
+    """Practical HBM bandwidth: a device-to-device copy of `mib` MiB, median
+    of `reps` (bytes read + bytes written per second)."""
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    t = sorted(ts)[len(ts) // 2]
+    return 2.0 * n * 4 / t / 1e9
+
+
+def device_info(torch):
+    p = torch.cuda.get_device_properties(0)
+    return {"name": p.name, "arch": getattr(p, "gcnArchName", None), "compute_units": p.multi_processor_count,
+            "hbm_bytes": int(p.total_memory)}
+
+
+VALU_PEAK_GINST = 256 * 4 * 2.4e9 / 4 / 1e9  # wave64 VALU instructions per second, 4 cycles each
+
+
+def measured_valu(kernel, config):
+    """Wave-VALU instructions per launch from the committed counter summary,
+    if taken on the current source of the kernel.  Lines read: `valu <kernel>
+    c<config> src=<hash> insts=<n>`."""
+    try:
+        lines = open(COUNTERS_FILE.format(config)).read().splitlines()
+    except OSError:
+        return None
+    want = source_hash(kernel)
+    for line in lines:
+        tok = line.strip().strip("`").split()
+        if len(tok) < 3 or tok[0] != "valu" or tok[1] != kernel or tok[2] != f"c{config}":
+            continue
+        kv = dict(t.split("=", 1) for t in tok[3:] if "=" in t)
+        return float(kv["insts"]) if kv.get("src") == want else None
+    return None
 
 
 BF16_PEAK_TFLOPS = 2500.0
@@ -416,6 +465,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the physics leg at the 4096-env config")
     ap.add_argument("--no-c4", action="store_true", help="skip the autotuned leg at the uneven 2048-env config")
+    ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner leg at the bench config")
     ap.add_argument("--serve-seconds", type=float, default=120.0,
                     help="length of the continuous-batching serving run (0: skip)")
     ap.add_argument("--capacity-rates", default="100,150,200,300,400",
@@ -673,12 +723,26 @@ def main():
     tr_full = measured_traffic(dom, cfg)
     share = kinds[dom]["bytes_per_launch"] / step_bytes[dom]
     tr = int(tr_full * share) if tr_full is not None else None
+    copy_gbs = copy_ceiling(torch)
+    log(f"practical HBM ceiling (1 GiB device copy): {copy_gbs:.0f} GB/s")
     roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": tr,
             "traffic_note": (f"counters of a whole-workload launch from step {start} "
                              f"({tr_full} B), times the launch's share {share:g}") if tr_full else None,
             "bytes_per_launch": kinds[dom]["bytes_per_launch"], "launch_us": kinds[dom]["launch_us"],
+            "practical_peak": round(copy_gbs, 1), "frac_of_practical": round(ach / copy_gbs, 5),
             **kinds}
+    vi = measured_valu(dom, cfg)
+    if vi is not None:
+        vi *= kinds[dom]["bytes_per_launch"] / step_bytes[dom]  # the launch's share of the workload
+        roof["valu"] = {"insts_per_launch": int(vi), "unit": "G wave-instructions/s",
+                        "peak": round(VALU_PEAK_GINST, 1),
+                        "achieved": round(vi / (kinds[dom]["launch_us"] * 1e-6) / 1e9, 1),
+                        "frac": round(vi / (kinds[dom]["launch_us"] * 1e-6) / 1e9 / VALU_PEAK_GINST, 4),
+                        "frac_alone": round(vi / (kinds[dom]["alone_launch_us"] * 1e-6) / 1e9 / VALU_PEAK_GINST, 4)
+                        if kinds[dom]["alone_launch_us"] else None,
+                        "note": "wave-VALU instructions per launch from the committed counters "
+                                "(profiles/counters_c2.md), over the launch time of this run"}
 
     c3 = None
     if scene3 is not None:
@@ -701,6 +765,24 @@ def main():
     if not args.only:
         features = features_bench(torch, vuda, sg, scene, min(args.steps, 100), log)
 
+    # the library's autotuner on this workload (its own trials from the start
+    # state), then the same median windows under its choice
+    tuned = None
+    if not args.only and not args.no_autotune:
+        w.load_state(st0)
+        t0 = time.perf_counter()
+        choice = w.autotune(steps=20)
+        t_tune = time.perf_counter() - t0
+        tsched = vuda.SCHED_NAMES[int(choice["schedule"])]
+        dt_t, t_windows = median_windows(tsched)
+        tuned = {"value": round(n_envs * args.steps / dt_t, 1),
+                 "speedup_vs_serialized": round(dt_ser / dt_t, 4),
+                 "windows_ms_per_step": [round(x / args.steps * 1e3, 4) for x in t_windows],
+                 "choice": {k: (round(v, 1) if isinstance(v, float) else v) for k, v in choice.items()},
+                 "seconds": round(t_tune, 2)}
+        log(f"autotuned ({tsched}@{choice['cu_split']:g}): {tuned['value']:.0f} env-steps/s, "
+            f"{tuned['speedup_vs_serialized']:.3f}x serialized; choice {choice}")
+
     serving = None
     if args.serve_seconds > 0:
         from paper_2605_01352_amd import serving as srv
@@ -719,6 +801,7 @@ def main():
         cpu_steps = {1: 50, 2: 100, 3: 5, 4: 30}.get(cfg, 20)
         st_cpu = {k: v[: int(scene.body_off[n_cpu])] for k, v in st0.items()}
         cpu = cpu_baseline(lambda n: scene if n == n_envs else scene.subset(range(n)), n_cpu, cpu_steps, st_cpu)
+        cpu["per_core"] = round(cpu["value"] / cpu["cores"], 1)
         log(f"cpu baseline: {cpu['value']:.0f} env-steps/s on {cpu['cores']} threads")
         cpu["divergence"] = divergence_report(vuda, sg)
         log(f"divergence (GPU and oracle running free from the spawn): {cpu['divergence']}")
@@ -752,6 +835,8 @@ def main():
         "roofline": roof,
         "physics_c3": c3,
         "uneven_c4": c4,
+        "autotuned": tuned,
+        "device": device_info(torch),
         "cpu_baseline": cpu,
         "serving": serving,
         "policy": policy,

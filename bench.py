@@ -539,7 +539,7 @@ def main():
                 "presetup": vuda.TUNE_PRESETUP, "policy_layered": vuda.TUNE_POLICY_LAYERED,
                 "phys_pack": vuda.TUNE_PHYS_ENVS_PER_WAVE, "tile": vuda.TUNE_TILE_SIZE,
                 "fused": vuda.TUNE_RASTER_FUSED, "fused_recs": vuda.TUNE_FUSED_LDS_RECORDS,
-                "tile_waves": vuda.TUNE_TILE_WAVES}
+                "tile_waves": vuda.TUNE_TILE_WAVES, "tile_prio": vuda.TUNE_TILE_PRIORITY}
     for kv in filter(None, args.tune.split(",")):
         k, v = kv.split("=")
         w.set_tuning(knob_ids[k], int(v))
@@ -650,34 +650,41 @@ def main():
     cands = [(2.0, sched, p0) for sched in scheds]
     cands += [(2.0, sched, p) for p in prios for sched in scheds]
     cands += [(float(x), sched, p0) for x in filter(None, args.splits.split(",")) for sched in scheds]
-    cands = [c + (path,) for path in paths for c in cands]
+    cands = [c + (path, 0) for path in paths for c in cands]
+    # the tile kernel's wave priority, on unmasked streams (its waves share CUs
+    # with the step's)
+    cands += [(sp, sc, pr, path, 1) for sp, sc, pr, path, _ in cands if sp == 2.0 and path != "fused"]
     if args.only:
         cands = []
     sweep = {}
 
-    def name(sched, split, prio, path):
-        return f"{sched}@{split:g}" + (f"/p{prio}" if prio != p0 else "") + f"/{path}"
+    def name(sched, split, prio, path, tprio=0):
+        return (f"{sched}@{split:g}" + (f"/p{prio}" if prio != p0 else "") + f"/{path}" +
+                (f"/r{tprio}" if tprio else ""))
 
     def parse(nm):
         sched, rest = nm.split("@")
         tok = rest.split("/")
-        prio, path = p0, paths[0]
+        prio, path, tprio = p0, paths[0], 0
         for t in tok[1:]:
             if t in path_knobs:
                 path = t
             elif t.startswith("p"):
                 prio = int(t[1:])
-        return sched, float(tok[0]), prio, path
+            elif t.startswith("r"):
+                tprio = int(t[1:])
+        return sched, float(tok[0]), prio, path, tprio
 
-    def apply(split, prio, path):
+    def apply(split, prio, path, tprio=0):
         w.cosched(split)
         w.set_tuning(vuda.TUNE_PHYS_PRIORITY, prio)
+        w.set_tuning(vuda.TUNE_TILE_PRIORITY, tprio)
         set_path(path)
 
-    for split, sched, prio, path in cands:
-        apply(split, prio, path)
+    for split, sched, prio, path, tprio in cands:
+        apply(split, prio, path, tprio)
         dt = timed(torch, w, sched, n_envs, args.steps, args.warmup, st0)
-        nm = name(sched, split, prio, path)
+        nm = name(sched, split, prio, path, tprio)
         sweep[nm] = n_envs * args.steps / dt
         log(f"  {nm:26s}: {n_envs * args.steps / dt:.0f} env-steps/s")
     # the three best sweep entries (one window each) are timed again as
@@ -685,13 +692,13 @@ def main():
     finalists = [args.only] if args.only else sorted(sweep, key=sweep.get, reverse=True)[:3]
     medians = {}
     for nm in finalists:
-        sched, split, prio, path = parse(nm)
-        apply(split, prio, path)
+        sched, split, prio, path, tprio = parse(nm)
+        apply(split, prio, path, tprio)
         medians[nm] = median_windows(sched)
         log(f"  finalist {nm}: {n_envs * args.steps / medians[nm][0]:.0f} env-steps/s (median)")
     best = min(medians, key=lambda k: medians[k][0])
-    sched, split, prio, path = parse(best)
-    apply(split, prio, path)
+    sched, split, prio, path, tprio = parse(best)
+    apply(split, prio, path, tprio)
     dt, co_windows = medians[best]
     value = n_envs * args.steps / dt
     live = kernel_run(sched)
@@ -814,7 +821,7 @@ def main():
         "data": "synthetic (seeded sphere/cube drops standing in for ManiSkill3 scenes)",
         "config": {"workload": CONFIG_NAMES.get(cfg, f"c{cfg}"), "envs": n_envs,
                    "bodies": int(scene.n_bodies), "cameras": int(scene.n_cams),
-                   "schedule": sched, "cu_split": split, "step_priority": prio,
+                   "schedule": sched, "cu_split": split, "step_priority": prio, "tile_priority": tprio,
                    "raster": {"path": "fused kernel" if path == "fused" else "setup + tile kernels",
                               "workgroup_threads": path_knobs[path][vuda.TUNE_RASTER_THREADS],
                               "tile_waves": path_knobs[path].get(vuda.TUNE_TILE_WAVES)},

@@ -342,6 +342,8 @@ int vuda_world_info(vuda_world* w, int32_t* n_envs, int64_t* n_bodies, int32_t* 
  *   VUDA_TUNE_TILE_WAVES       1, 2 (default) or 4: tiles of a row per tile-kernel
  *                              workgroup, one per wave (smaller workgroups fit
  *                              beside the step's on shared CUs)
+ *   VUDA_TUNE_TILE_PRIORITY    0..3: instruction-issue priority of the tile
+ *                              kernel's waves relative to the step's
  * None of the others changes any output bit.  Returns VUDA_EINVAL for unknown keys
  * or out-of-range values.
  */
@@ -360,6 +362,7 @@ int vuda_world_info(vuda_world* w, int32_t* n_envs, int64_t* n_bodies, int32_t* 
 #define VUDA_TUNE_RASTER_FUSED 13
 #define VUDA_TUNE_FUSED_LDS_RECORDS 14
 #define VUDA_TUNE_TILE_WAVES 15
+#define VUDA_TUNE_TILE_PRIORITY 16
 int vuda_set_tuning(vuda_world* w, int32_t key, int32_t value);
 int vuda_get_tuning(vuda_world* w, int32_t key, int32_t* value);
 
@@ -493,7 +496,7 @@ int vuda_run(vuda_world* w, int32_t schedule, int32_t iters);
  * Autotuner: searches the launch shapes (schedule, CU split, physics and
  * raster persistent grids and workgroup shapes, raster tile size, physics
  * envs per wave, fused raster, tile-kernel workgroup, hipGraph replay,
- * physics priority, broadphase, presetup)
+ * physics and tile priorities, broadphase, presetup)
  * for the highest
  * co-scheduled env-steps/s on this world, timing `steps_per_trial`
  * iterations per candidate from the current state (the state is saved before
@@ -516,6 +519,7 @@ typedef struct {
   int32_t tile_size;         /* VUDA_TUNE_TILE_SIZE chosen */
   int32_t raster_fused;      /* VUDA_TUNE_RASTER_FUSED chosen */
   int32_t tile_waves;        /* VUDA_TUNE_TILE_WAVES chosen */
+  int32_t tile_priority;     /* VUDA_TUNE_TILE_PRIORITY chosen */
 } vuda_tune_result;
 int vuda_autotune(vuda_world* w, int32_t steps_per_trial, const char* cache_path, vuda_tune_result* out);
 

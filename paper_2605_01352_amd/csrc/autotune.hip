@@ -4,7 +4,7 @@
 // coordinates, in order: schedule x CU split; fused raster; physics
 // persistent grid; raster-setup persistent grid; tile size; physics envs per
 // wave; hipGraph replay; raster workgroup size; tile-kernel workgroup size;
-// step wave priority; broadphase; presetup.  The serialized baseline takes the better of the
+// step wave priority; tile wave priority; broadphase; presetup.  The serialized baseline takes the better of the
 // two raster paths and of two workgroup sizes.
 #include <hip/hip_runtime.h>
 
@@ -142,6 +142,7 @@ void to_result(const Cand& c, vuda_tune_result* r) {
   r->tile_size = 1 << c.tune.tile_shift;
   r->raster_fused = c.tune.raster_fused ? 1 : 0;
   r->tile_waves = c.tune.tile_waves;
+  r->tile_priority = c.tune.tile_prio;
 }
 
 bool cache_lookup(const char* path, const std::string& key, vuda_tune_result* r) {
@@ -157,7 +158,7 @@ bool cache_lookup(const char* path, const std::string& key, vuda_tune_result* r)
     if (is >> t.cu_split >> t.schedule >> t.raster_threads >> t.rec_cap >> t.phys_persistent >>
         t.raster_persistent >> t.phys_priority >> t.broadphase >> t.cosched_env_steps_per_s >>
         t.serial_env_steps_per_s >> t.serial_raster_threads >> t.serial_phys_persistent >> t.presetup >>
-        t.graphs >> t.phys_envs_per_wave >> t.tile_size >> t.raster_fused >> t.tile_waves) {
+        t.graphs >> t.phys_envs_per_wave >> t.tile_size >> t.raster_fused >> t.tile_waves >> t.tile_priority) {
       *r = t;  // the last matching line wins
       found = true;
     }
@@ -172,7 +173,8 @@ void cache_store(const char* path, const std::string& key, const vuda_tune_resul
     << " " << r.phys_persistent << " " << r.raster_persistent << " " << r.phys_priority << " "
     << r.broadphase << " " << r.cosched_env_steps_per_s << " " << r.serial_env_steps_per_s << " "
     << r.serial_raster_threads << " " << r.serial_phys_persistent << " " << r.presetup << " " << r.graphs << " "
-    << r.phys_envs_per_wave << " " << r.tile_size << " " << r.raster_fused << " " << r.tile_waves << "\n";
+    << r.phys_envs_per_wave << " " << r.tile_size << " " << r.raster_fused << " " << r.tile_waves << " "
+    << r.tile_priority << "\n";
 }
 
 }  // namespace
@@ -205,6 +207,7 @@ extern "C" int vuda_autotune(vuda_world* w, int32_t steps, const char* cache_pat
     c.tune.tile_shift = out->tile_size == 8 ? 3 : (out->tile_size == 32 ? 5 : 4);
     c.tune.raster_fused = out->raster_fused != 0;
     c.tune.tile_waves = out->tile_waves == 1 || out->tile_waves == 2 ? out->tile_waves : 4;
+    c.tune.tile_prio = out->tile_priority >= 0 && out->tile_priority <= 3 ? out->tile_priority : 0;
     out->trials = 0;
     return apply(w, c);
   }
@@ -277,6 +280,7 @@ extern "C" int vuda_autotune(vuda_world* w, int32_t steps, const char* cache_pat
   stage([](Cand& c, int v) { c.tune.raster_threads = v; }, {256, 128, 512, 1024});
   stage([](Cand& c, int v) { c.tune.tile_waves = v; }, {2, 4, 1});
   stage([](Cand& c, int v) { c.tune.phys_prio = v; }, {0, 3});
+  stage([](Cand& c, int v) { c.tune.tile_prio = v; }, {0, 1});
   stage([](Cand& c, int v) { c.tune.broadphase = v; }, {0, 1});
   stage([](Cand& c, int v) { c.tune.presetup = v != 0; }, {1, 0});
   const int rc_trials = rc;

@@ -1222,6 +1222,14 @@ template <bool DBG, bool SMOOTH, int TS, int TW>
 __global__ void __launch_bounds__(64 * TW) raster_tile_kernel(WorldDev W, RasterLaunch L) {
   __shared__ TileWaveLDS<TS> S[TW];
   __shared__ int32_t C[DBG ? TW : 1][DBG ? TS * TS : 1];
+  // beside the step's kernels, a higher issue priority keeps the render
+  // (the longer phase) from stretching
+  switch (L.prio) {
+    case 1: __builtin_amdgcn_s_setprio(1); break;
+    case 2: __builtin_amdgcn_s_setprio(2); break;
+    case 3: __builtin_amdgcn_s_setprio(3); break;
+    default: break;
+  }
   const int2 job = L.tiles[blockIdx.x];
   if (job.x < 0) return;
   // uniform per wave: tile bookkeeping stays in scalar registers

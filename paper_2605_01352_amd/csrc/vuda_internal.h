@@ -188,7 +188,7 @@ struct RasterLaunch {
   int32_t bin_limit;       // bin entries an image may use (0: its whole capacity)
   int32_t persistent;      // setup kernel: resident workgroups pulling images
   int32_t* queue;
-  int32_t prio;            // setup kernel: wave issue priority 0..3 (s_setprio)
+  int32_t prio;            // setup and tile kernels: wave issue priority 0..3 (s_setprio)
   int32_t near_clip;       // setup kernel: cut triangles crossing the near plane
   int32_t smooth;          // per-pixel shading of interpolated vertex normals
   int32_t tile_shift;      // raster tiles of edge 1 << tile_shift (8, 16 or 32 pixels)

@@ -93,6 +93,7 @@ struct Tuning {
   int32_t phys_pack = 1;         // envs of at most 32 bodies per physics wave (1 or 2)
   int32_t tile_shift = 4;        // raster tile edge 1 << tile_shift pixels
   int32_t tile_waves = 2;        // tiles (one per wave) per tile-kernel workgroup: 1, 2 or 4
+  int32_t tile_prio = 0;         // wave issue priority 0..3 of the tile kernel
   bool raster_fused = false;     // setup and tiles in one kernel, records in LDS
   int32_t fused_recs = 0;        // records a fused image keeps in LDS at most (0: automatic)
 };

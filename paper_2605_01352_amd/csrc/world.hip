@@ -977,6 +977,7 @@ int vuda_world::enqueue_kernel(int kind, const WorkList& L, int parity, hipStrea
   if (rc) return rc;
   // the setup that ends a step (its own queue slot) runs at the step's priority
   if (kind == kKernelSetup) rl.prio = queue == queues + 1 ? tune.phys_prio : 0;
+  if (kind == kKernelTiles) rl.prio = tune.tile_prio;
   if (kind == kKernelSetup) HIPCHK(launch_raster_setup(dev, rl, s, ev));
   else HIPCHK(launch_raster_tiles(dev, rl, s, ev));
   return VUDA_OK;
@@ -1942,6 +1943,10 @@ extern "C" int vuda_set_tuning(vuda_world* w, int32_t key, int32_t value) {
       // one stepped in fused mode has no setup, so its render sets up
       w->tune.raster_fused = value != 0;
       break;
+    case VUDA_TUNE_TILE_PRIORITY:
+      if (value < 0 || value > 3) return fail(VUDA_EINVAL, "tile priority %d", value);
+      w->tune.tile_prio = value;
+      break;
     case VUDA_TUNE_TILE_WAVES:
       if (value != 1 && value != 2 && value != 4) return fail(VUDA_EINVAL, "tile waves %d (1, 2 or 4)", value);
       if (value != w->tune.tile_waves) {
@@ -1992,6 +1997,7 @@ extern "C" int vuda_get_tuning(vuda_world* w, int32_t key, int32_t* value) {
     case VUDA_TUNE_RASTER_FUSED: *value = w->tune.raster_fused ? 1 : 0; break;
     case VUDA_TUNE_FUSED_LDS_RECORDS: *value = w->tune.fused_recs; break;
     case VUDA_TUNE_TILE_WAVES: *value = w->tune.tile_waves; break;
+    case VUDA_TUNE_TILE_PRIORITY: *value = w->tune.tile_prio; break;
     default: return fail(VUDA_EINVAL, "tuning key %d", key);
   }
   return VUDA_OK;

@@ -34,6 +34,7 @@ TUNE_TILE_SIZE = 12
 TUNE_RASTER_FUSED = 13
 TUNE_FUSED_LDS_RECORDS = 14
 TUNE_TILE_WAVES = 15
+TUNE_TILE_PRIORITY = 16
 KERNEL_PHYSICS, KERNEL_RASTER_SETUP, KERNEL_RASTER_TILES, KERNEL_POLICY, KERNEL_RASTER_FUSED = 1, 2, 3, 4, 5
 GROUND = 0xFFFF
 
@@ -100,7 +101,7 @@ class TuneResult(C.Structure):
                 ("serial_env_steps_per_s", C.c_double), ("serial_raster_threads", C.c_int32),
                 ("serial_phys_persistent", C.c_int32), ("trials", C.c_int32), ("presetup", C.c_int32),
                 ("graphs", C.c_int32), ("phys_envs_per_wave", C.c_int32), ("tile_size", C.c_int32),
-                ("raster_fused", C.c_int32), ("tile_waves", C.c_int32)]
+                ("raster_fused", C.c_int32), ("tile_waves", C.c_int32), ("tile_priority", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -98,6 +98,8 @@ C2 = dict(cfg=2, n_envs=48, settle=250)
      {vuda.TUNE_RASTER_THREADS: 128, vuda.TUNE_TILE_WAVES: 2}),
     ("tile workgroups of 1 wave, CU-masked 0.5, inter-trajectory", 0.5, vuda.SCHED_INTERTRAJ,
      {vuda.TUNE_TILE_WAVES: 1}),
+    ("tile wave priority 1, setup workgroups of 128, unmasked, inter-step", 2.0, vuda.SCHED_INTERSTEP,
+     {vuda.TUNE_TILE_PRIORITY: 1, vuda.TUNE_RASTER_THREADS: 128, vuda.TUNE_TILE_WAVES: 4}),
     ("pipelined, unmasked", 2.0, vuda.SCHED_PIPELINED, {}),
     ("pipelined, CU-masked 0.5", 0.5, vuda.SCHED_PIPELINED, {}),
     ("pipelined, persistent + graphs, setup workgroups of 128", 2.0, vuda.SCHED_PIPELINED,

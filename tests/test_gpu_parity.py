@@ -135,7 +135,8 @@ def test_tuning_knobs_do_not_change_outputs():
                   {vuda.TUNE_RASTER_FUSED: 1, vuda.TUNE_FUSED_LDS_RECORDS: 60},
                   {vuda.TUNE_RASTER_FUSED: 1, vuda.TUNE_TILE_SIZE: 8, vuda.TUNE_RASTER_PERSISTENT: 5},
                   {vuda.TUNE_TILE_WAVES: 1}, {vuda.TUNE_TILE_WAVES: 2, vuda.TUNE_TILE_SIZE: 8},
-                  {vuda.TUNE_TILE_WAVES: 2, vuda.TUNE_RASTER_THREADS: 128, vuda.TUNE_GRAPHS: 1}):
+                  {vuda.TUNE_TILE_WAVES: 2, vuda.TUNE_RASTER_THREADS: 128, vuda.TUNE_GRAPHS: 1},
+                  {vuda.TUNE_TILE_PRIORITY: 2, vuda.TUNE_PHYS_PRIORITY: 3}):
         with vuda.World(s) as w:
             for k, v in knobs.items():
                 w.set_tuning(k, v)

@@ -432,6 +432,11 @@ __device__ __forceinline__ float box_radius(const M3& R, f3 e, f3 L) {
   return (e.x * fabsf(u.x) + e.y * fabsf(u.y)) + e.z * fabsf(u.z);
 }
 
+// The step's candidate superset: pairs within their bounding radii plus
+// kSupMargin (m) at substep 0; retested alone while no body has moved more
+// than kSupMargin / 4 (kSupMove2 is its square).
+constexpr float kSupMargin = 0.04f;
+constexpr float kSupMove2 = 1.0e-4f;
 constexpr float kEdgeParallel = 1.0e-6f;  // squared length below which a cross product is no axis
 constexpr float kEdgeBias = 0.95f;        // an edge axis wins below this fraction of the least face overlap
 
@@ -561,7 +566,7 @@ __device__ __forceinline__ int popc_below(const uint64_t* row, int b) {
   return c;
 }
 
-template <int N, bool FR, bool EE>
+template <int N, bool FR, bool EE, bool SUP>
 __device__ void step_env(PhysLDS<N>& s, const WorldDev& W, const PhysConsts& pc, int env,
                          int parity, int broadphase) {
   constexpr int NW = PhysLDS<N>::NW;
@@ -640,6 +645,10 @@ __device__ void step_env(PhysLDS<N>& s, const WorldDev& W, const PhysConsts& pc,
   bool bad = false;
   // broadphase choice: 0 auto (grid above 64 bodies), 1 grid, 2 all-pairs
   const bool use_grid = broadphase == 1 || (broadphase == 0 && n > 64);
+  // the step's candidate superset (all-pairs path): pairs found at substep 0
+  // within their bounding radii plus kSupMargin, by the lane that found them
+  const f3 p0 = p;
+  uint64_t supM = 0ull;
 
   for (int sub_i = 0; sub_i < pc.substeps; ++sub_i) {
     // 1. publish substep-start state
@@ -682,18 +691,66 @@ __device__ void step_env(PhysLDS<N>& s, const WorldDev& W, const PhysConsts& pc,
     // test over every wave of the env
     const bool grid = (__syncthreads_or(far_cell) == 0) && use_grid;
     if (!grid && N <= 64) {
+      // Substeps after the first retest only the step's superset while every
+      // body of the env is within a quarter of the margin of its step-start
+      // position: a pair in contact range now was then within the sum of
+      // its radii plus half the margin, and the other half covers rounding
+      // (positions under 1000 m, where it is below 0.1 mm).  The retest is
+      // the same expression, so the candidate set is the same bits.
+      // Only where a lane has more than one batch of eight rotations: below
+      // that the retest saves nothing.
+      const int groups = n <= N / 2 ? 2 : 1;
+      const int i = groups == 2 ? (tid & (N / 2 - 1)) : tid;
+      const int g = groups == 2 ? tid / (N / 2) : 0;
+      const int R = n / 2;
+      const bool use_sup = SUP && (R + groups - 1) / groups > 8;
+      bool retest = false;
+      if constexpr (SUP) {
+        bool risky = true;
+        if (sub_i > 0 && use_sup) {
+          risky = false;
+          if (own) {
+            const f3 dp = sub(p, p0);
+            risky = dot(dp, dp) > kSupMove2 ||
+                    !(fabsf(p.x) < 1000.0f && fabsf(p.y) < 1000.0f && fabsf(p.z) < 1000.0f);
+          }
+        }
+        retest = half(__ballot(risky)) == 0;
+      }
       // one wave: lane l tests body i against body (i + r) mod n for its
       // share of the rotations r = 1 .. n/2 (two groups of 32 lanes when
       // n <= 32).  Every unordered pair is one rotation away from one of its
       // bodies; at r = n/2 (n even) both see it and the lower one keeps it.
       // The test is symmetric in the two bodies, bit for bit.
       // Eight rotations per batch: their loads issue back to back.
-      const int groups = n <= N / 2 ? 2 : 1;
-      const int i = groups == 2 ? (tid & (N / 2 - 1)) : tid;
-      const int g = groups == 2 ? tid / (N / 2) : 0;
-      const int R = n / 2;
-      if (i < n) {
+      const bool build = sub_i == 0 && use_sup;
+      if (i < n && retest) {
+        // eight members of the superset per batch: their loads issue together
         const float4 me = s.pr[i];
+        uint64_t m = supM;
+        while (m) {
+          float4 o[8];
+          int jj[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            jj[u] = m ? __ffsll((unsigned long long)m) - 1 : -1;
+            m &= m - 1ull;
+            o[u] = s.pr[jj[u] < 0 ? i : jj[u]];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int j = jj[u];
+            const f3 d = mk(me.x - o[u].x, me.y - o[u].y, me.z - o[u].z);
+            const float rs = me.w + o[u].w;
+            if ((j >= 0) & (dot(d, d) <= rs * rs)) {
+              const int lo = i < j ? i : j, hi = i < j ? j : i;
+              atomicOr((unsigned long long*)&s.rowCand[lo][0], 1ull << hi);
+            }
+          }
+        }
+      } else if (i < n) {
+        const float4 me = s.pr[i];
+        if (build) supM = 0ull;
         for (int r0 = 1 + g; r0 <= R; r0 += 8 * groups) {
           float4 o[8];
           int jj[8];
@@ -710,9 +767,15 @@ __device__ void step_env(PhysLDS<N>& s, const WorldDev& W, const PhysConsts& pc,
             const int r = r0 + u * groups, j = jj[u];
             const f3 d = mk(me.x - o[u].x, me.y - o[u].y, me.z - o[u].z);
             const float rs = me.w + o[u].w;
-            if ((r <= R) & !((2 * r == n) & (i > j)) & (dot(d, d) <= rs * rs)) {
+            const float d2 = dot(d, d);
+            const bool mine = (r <= R) & !((2 * r == n) & (i > j));
+            if (mine & (d2 <= rs * rs)) {
               const int lo = i < j ? i : j, hi = i < j ? j : i;
               atomicOr((unsigned long long*)&s.rowCand[lo][0], 1ull << hi);
+            }
+            if (build) {
+              const float rm = rs + kSupMargin;
+              if (mine & (d2 <= rm * rm)) supM |= 1ull << j;
             }
           }
         }
@@ -1145,11 +1208,13 @@ __device__ void step_env(PhysLDS<N>& s, const WorldDev& W, const PhysConsts& pc,
   if (bad && tid == 0 && env >= 0) atomicOr(&W.env_flags[env], kFlagContactOverflow);
 }
 
-// FR: friction; EE: edge-edge points of box pairs.  N lanes per env: a
-// workgroup of 64 threads holds two envs at N = 32, one at N = 64; two
-// waves hold one env at N = 128.  Work item w takes envs P w .. P w + P - 1
-// of the list (P envs per workgroup).
-template <int N, bool FR, bool EE>
+// FR: friction; EE: edge-edge points of box pairs; SUP: the step's candidate
+// superset on the all-pairs path (compiled in only for launches whose envs
+// exceed 32 bodies, where it pays).  N lanes per env: a workgroup of 64
+// threads holds two envs at N = 32, one at N = 64; two waves hold one env at
+// N = 128.  Work item w takes envs P w .. P w + P - 1 of the list (P envs per
+// workgroup).
+template <int N, bool FR, bool EE, bool SUP>
 __global__ __launch_bounds__(N < 64 ? 64 : N) void physics_kernel(WorldDev W, PhysConsts pc, PhysLaunch L) {
   constexpr int P = N < 64 ? 64 / N : 1;
   __shared__ PhysLDS<N> sh[P];
@@ -1166,7 +1231,7 @@ __global__ __launch_bounds__(N < 64 ? 64 : N) void physics_kernel(WorldDev W, Ph
     const int wi = blockIdx.x;
     if (P * wi >= L.n_work) return;
     const int item = P * wi + sub;
-    step_env<N, FR, EE>(sh[sub], W, pc, item < L.n_work ? L.work[item] : -1, L.parity, L.broadphase);
+    step_env<N, FR, EE, SUP>(sh[sub], W, pc, item < L.n_work ? L.work[item] : -1, L.parity, L.broadphase);
     return;
   }
   for (;;) {
@@ -1176,7 +1241,7 @@ __global__ __launch_bounds__(N < 64 ? 64 : N) void physics_kernel(WorldDev W, Ph
     __syncthreads();
     if (P * wi >= L.n_work) return;
     const int item = P * wi + sub;
-    step_env<N, FR, EE>(sh[sub], W, pc, item < L.n_work ? L.work[item] : -1, L.parity, L.broadphase);
+    step_env<N, FR, EE, SUP>(sh[sub], W, pc, item < L.n_work ? L.work[item] : -1, L.parity, L.broadphase);
   }
 }
 
@@ -1189,14 +1254,14 @@ hipError_t launch_reset_queue(int32_t* q, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int N>
+template <int N, bool SUP>
 static void launch_n(bool fr, bool ee, LaunchEvents* ev, bool first, bool last, dim3 g, hipStream_t s,
                      const WorldDev& w, const PhysConsts& pc, const PhysLaunch& lt) {
   const dim3 b(N < 64 ? 64 : N);
-  if (!fr && !ee) timed_launch(ev, first, last, physics_kernel<N, false, false>, g, b, 0, s, w, pc, lt);
-  else if (!ee) timed_launch(ev, first, last, physics_kernel<N, true, false>, g, b, 0, s, w, pc, lt);
-  else if (!fr) timed_launch(ev, first, last, physics_kernel<N, false, true>, g, b, 0, s, w, pc, lt);
-  else timed_launch(ev, first, last, physics_kernel<N, true, true>, g, b, 0, s, w, pc, lt);
+  if (!fr && !ee) timed_launch(ev, first, last, physics_kernel<N, false, false, SUP>, g, b, 0, s, w, pc, lt);
+  else if (!ee) timed_launch(ev, first, last, physics_kernel<N, true, false, SUP>, g, b, 0, s, w, pc, lt);
+  else if (!fr) timed_launch(ev, first, last, physics_kernel<N, false, true, SUP>, g, b, 0, s, w, pc, lt);
+  else timed_launch(ev, first, last, physics_kernel<N, true, true, SUP>, g, b, 0, s, w, pc, lt);
 }
 
 hipError_t launch_physics(const WorldDev& w, const PhysConsts& pc, const PhysLaunch& l,
@@ -1217,9 +1282,10 @@ hipError_t launch_physics(const WorldDev& w, const PhysConsts& pc, const PhysLau
     }
     const bool fr = pc.mu > 0.0f, ee = pc.edge != 0;
     const bool first = t == 0, last = t == l.nsteps - 1;
-    if (N == 32) launch_n<32>(fr, ee, ev, first, last, dim3(grid), s, w, pc, lt);
-    else if (N == 64) launch_n<64>(fr, ee, ev, first, last, dim3(grid), s, w, pc, lt);
-    else launch_n<128>(fr, ee, ev, first, last, dim3(grid), s, w, pc, lt);
+    if (N == 32) launch_n<32, false>(fr, ee, ev, first, last, dim3(grid), s, w, pc, lt);
+    else if (N == 64 && l.max_bodies > 32) launch_n<64, true>(fr, ee, ev, first, last, dim3(grid), s, w, pc, lt);
+    else if (N == 64) launch_n<64, false>(fr, ee, ev, first, last, dim3(grid), s, w, pc, lt);
+    else launch_n<128, false>(fr, ee, ev, first, last, dim3(grid), s, w, pc, lt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

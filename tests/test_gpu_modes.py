@@ -11,7 +11,9 @@ bit-exact, RGB within 1/255) are checked here at every iteration of:
   - the three-stage pipelined schedule, one iteration per call and many;
   - the configuration the autotuner picks;
   - the uniform-grid broadphase on settled piles of 100 and 128 bodies,
-    automatic and forced, and its fallback for cells far from the origin.
+    automatic and forced, and its fallback for cells far from the origin;
+  - the all-pairs broadphase's step candidate superset on a settled pile of
+    64 bodies.
 Each run starts from a state the GPU reached after a few hundred steps
 (bodies resting in contact), not from the spawn.
 """
@@ -233,6 +235,27 @@ def test_grid_broadphase_settled_pile(n, broadphase, mu):
         w.set_tuning(vuda.TUNE_BROADPHASE, broadphase)
         parity_iterations(w, scene, vuda.SCHED_SERIAL, 5,
                           f"pile of {n}, mu {mu}, broadphase {broadphase} ({body_pairs} body pairs in contact)")
+
+
+@pytest.mark.parametrize("broadphase", [0, 2])
+def test_step_superset_settled_pile(broadphase):
+    """A pile of 64 bodies settled with friction (one wave per env, the
+    all-pairs broadphase with the step's candidate superset: substeps after
+    the first retest only the pairs found within the margin at the step's
+    start, while no body has moved a quarter of it -- every body here is
+    slower than 1 m/s): contact sets of every substep and the state
+    bit-exact with the oracle over 5 steps."""
+    oracle.lib()
+    scene = _pile(64, 104, mu=0.6)
+    st = scene.state()
+    _, pr = oracle.step_env(scene, 0, st, record_pairs=True)
+    body_pairs = int((pr[0][:, 1] != vuda.GROUND).sum())
+    assert body_pairs >= 5
+    assert float(np.abs(scene.vel).max()) < 1.0
+    with vuda.World(scene, debug=True) as w:
+        w.set_tuning(vuda.TUNE_BROADPHASE, broadphase)
+        parity_iterations(w, scene, vuda.SCHED_SERIAL, 5,
+                          f"pile of 64, mu 0.6, broadphase {broadphase} ({body_pairs} body pairs in contact)")
 
 
 def test_grid_far_from_origin_falls_back():

@@ -821,8 +821,16 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
   }
 }
 
+// Held to 80 VGPRs (six waves per SIMD; left alone the compiler takes 134,
+// mostly fp64 edge terms of the tile classification hoisted out of the
+// binning loops, and is capped at 128).  The spills this costs (about 50
+// VGPRs to scratch) slow the kernel by about 1.5% when it runs alone, but
+// its waves then fit beside the tile and physics waves that hold the rest of
+// a SIMD's register file when the render overlaps the next step: about 4%
+// more steps per second co-scheduled, at 1024 envs of 32 bodies and at 4096
+// envs of 64 (7 and 8 waves per SIMD, 72 and 64 VGPRs, spill more and lose).
 template <bool CLIP>
-__global__ void raster_setup_kernel(WorldDev W, RasterLaunch L) {
+__global__ void __attribute__((amdgpu_waves_per_eu(6))) raster_setup_kernel(WorldDev W, RasterLaunch L) {
   extern __shared__ __align__(16) unsigned char lds[];
   // At the end of a step this kernel shares CUs with the render's tile
   // waves; a higher issue priority keeps its chains of dependent steps moving.

@@ -879,6 +879,19 @@ struct TileWaveLDS {
   int32_t own[64];       // fragment owner marks
 };
 
+// A uniform load of data that no wave writes while the kernel runs (launch
+// tables, camera descriptors, what an earlier kernel wrote): read through
+// the constant address space, so that it is one scalar load.
+template <class T>
+__device__ __forceinline__ T uniform_ld(const T* p) {
+  return *(const __attribute__((address_space(4))) T*)p;
+}
+
+__device__ __forceinline__ int2 uniform_ld(const int2* p) {
+  const uint64_t v = uniform_ld((const uint64_t*)p);
+  return make_int2((int32_t)(uint32_t)v, (int32_t)(uint32_t)(v >> 32));
+}
+
 // Key of a primitive's fragment below its depth: primitive << 24 | RGB8.
 // Primitives number at most 65535 per env, so no key equals the empty ~0.
 __device__ __forceinline__ uint64_t prim_key(int prim, uint32_t rgb) {
@@ -1238,23 +1251,32 @@ __global__ void __launch_bounds__(64 * TW) raster_tile_kernel(WorldDev W, Raster
     case 3: __builtin_amdgcn_s_setprio(3); break;
     default: break;
   }
-  const int2 job = L.tiles[blockIdx.x];
+  // The tile's bookkeeping is uniform and takes three rounds of loads (the
+  // job, the camera, then the image's header and the tile's bin range
+  // together) before the first bin entry is read.
+  const int2 job = uniform_ld(L.tiles + blockIdx.x);
   if (job.x < 0) return;
-  // uniform per wave: tile bookkeeping stays in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const CamDev cam = W.cams[job.x];
+  if (wave > (job.x >> kJobWavesShift)) return;  // past the row's last tile; no workgroup barrier follows
+  const CamDev* cp = W.cams + (job.x & kJobCamMask);
+  CamDev cam;  // the fields the tile pass reads
+  cam.w = uniform_ld(&cp->w);
+  cam.h = uniform_ld(&cp->h);
+  cam.pix_off = uniform_ld(&cp->pix_off);
+  cam.rs_off = uniform_ld(&cp->rs_off);
+  cam.rs_recs = uniform_ld(&cp->rs_recs);
+  cam.rs_bins = uniform_ld(&cp->rs_bins);
+  cam.rs_total = uniform_ld(&cp->rs_total);
+  cam.rs_attr = uniform_ld(&cp->rs_attr);
   const int ntx = (cam.w + TS - 1) / TS;
   const int tx = (job.y & 0xFFFF) + wave, ty = job.y >> 16;
-  if (tx >= ntx) return;  // no workgroup barrier follows
   const unsigned char* rs = W.rscratch + cam.rs_off + (int64_t)L.parity * cam.rs_total;
-  const int32_t* hdr = (const int32_t*)rs;
-  const bool binned = hdr[1] != 0;
-  int k0 = 0, k1 = hdr[0];
-  if (binned) {
-    const int32_t* tt = (const int32_t*)(rs + 64) + 2 * (ty * ntx + tx);
-    k0 = tt[0];
-    k1 = k0 + tt[1];
-  }
+  // the tile table has room for the image's tiles at the smallest tile
+  // edge, so its entry is read before the header says the image is binned
+  const int2 hdr = uniform_ld((const int2*)rs);
+  const int2 te = uniform_ld((const int2*)(rs + 64) + (ty * ntx + tx));
+  const bool binned = hdr.y != 0;
+  const int k0 = binned ? te.x : 0, k1 = binned ? te.x + te.y : hdr.x;
   const GlobalRecs src{(const int4*)(rs + cam.rs_recs), (const uint16_t*)(rs + cam.rs_bins)};
   raster_tile<DBG, SMOOTH, TS>(W, cam, src, binned, k0, k1, tx, ty, S[wave], DBG ? C[wave] : nullptr, rs);
 }

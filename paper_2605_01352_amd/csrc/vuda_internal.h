@@ -172,12 +172,17 @@ struct PhysLaunch {
   int32_t pack;            // envs per wave when every env has at most 32 bodies (1 or 2)
 };
 
+// Tile-kernel job: the camera id in the low bits, the number of the row's
+// tiles the workgroup takes, less one, above them.
+constexpr int kJobWavesShift = 28;
+constexpr int32_t kJobCamMask = (1 << kJobWavesShift) - 1;
+
 struct RasterLaunch {
   const int32_t* work;     // camera ids, LPT order (setup kernel, one workgroup each)
   int32_t n_work;
-  const int2* tiles;       // tile kernel: per workgroup (camera, tx | ty << 16): the tiles
-                           // tx .. tx + tile_waves - 1 of tile row ty; camera -1 for padding
-                           // entries
+  const int2* tiles;       // tile kernel: per workgroup (camera | (n - 1) << kJobWavesShift,
+                           // tx | ty << 16): the n <= tile_waves tiles tx .. tx + n - 1 of
+                           // tile row ty; -1 for padding entries
   int32_t n_tile_groups;
   int32_t max_verts;       // over the listed cameras' envs
   int32_t max_tiles;

@@ -69,7 +69,7 @@ struct WorkList {
   int cur = 0;
   bool built = false;
   const int32_t* dptr = nullptr;  // the current version
-  const int2* tptr = nullptr;     // render: tile-kernel jobs (camera, first tile)
+  const int2* tptr = nullptr;     // render: tile-kernel jobs (camera and tile count, first tile)
   int32_t n_groups = 0;
   bool dirty = true;   // rebuild before the next use
   int32_t n = 0;

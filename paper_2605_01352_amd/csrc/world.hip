@@ -839,9 +839,12 @@ int vuda_world::get_list(int phase, int32_t lo, int32_t hi, const WorkList** out
       const CamDev& cd = cam_host[ids[i]];
       const int ts = 1 << tune.tile_shift;
       const int32_t ntx = (cd.w + ts - 1) >> tune.tile_shift, nty = (cd.h + ts - 1) >> tune.tile_shift;
+      if (ids[i] > kJobCamMask) return fail(VUDA_EINVAL, "camera id %d beyond the tile job's range", ids[i]);
       for (int32_t ty = 0; ty < nty; ++ty)
-        for (int32_t tx = 0; tx < ntx; tx += tune.tile_waves)
-          per[i % kXcd].push_back(make_int2(ids[i], tx | (ty << 16)));
+        for (int32_t tx = 0; tx < ntx; tx += tune.tile_waves) {
+          const int32_t n = std::min(tune.tile_waves, ntx - tx);
+          per[i % kXcd].push_back(make_int2(ids[i] | ((n - 1) << kJobWavesShift), tx | (ty << 16)));
+        }
     }
     size_t len = 0;
     for (auto& v : per) len = std::max(len, v.size());

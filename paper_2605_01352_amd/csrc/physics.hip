@@ -584,7 +584,7 @@ __device__ void step_env(PhysLDS<N>& s, const WorldDev& W, const PhysConsts& pc,
   };
   const auto wmax = [&](int x) -> int { return N < 64 ? max(x, __shfl_xor(x, 32, 64)) : x; };
   EnvDev ed{};
-  if (env >= 0) ed = W.envs[env];
+  if (env >= 0) ed = uniform_copy(W.envs + env);  // a scalar load where the env is the wave's
   const int n = ed.n_bodies;
   if (N >= 64 && n <= 0) return;  // a whole workgroup; a half-wave env of no bodies does nothing below
   const int b0 = ed.body_off;
@@ -1231,7 +1231,7 @@ __global__ __launch_bounds__(N < 64 ? 64 : N) void physics_kernel(WorldDev W, Ph
     const int wi = blockIdx.x;
     if (P * wi >= L.n_work) return;
     const int item = P * wi + sub;
-    step_env<N, FR, EE, SUP>(sh[sub], W, pc, item < L.n_work ? L.work[item] : -1, L.parity, L.broadphase);
+    step_env<N, FR, EE, SUP>(sh[sub], W, pc, item < L.n_work ? uniform_ld(L.work + item) : -1, L.parity, L.broadphase);
     return;
   }
   for (;;) {
@@ -1241,7 +1241,7 @@ __global__ __launch_bounds__(N < 64 ? 64 : N) void physics_kernel(WorldDev W, Ph
     __syncthreads();
     if (P * wi >= L.n_work) return;
     const int item = P * wi + sub;
-    step_env<N, FR, EE, SUP>(sh[sub], W, pc, item < L.n_work ? L.work[item] : -1, L.parity, L.broadphase);
+    step_env<N, FR, EE, SUP>(sh[sub], W, pc, item < L.n_work ? uniform_ld(L.work + item) : -1, L.parity, L.broadphase);
   }
 }
 

@@ -511,8 +511,8 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
   const int tid = threadIdx.x;
   const int nthr = blockDim.x;
   const int lane = tid & 63;
-  const CamDev cam = W.cams[cam_id];
-  const EnvDev ed = W.envs[cam.env];
+  const CamDev cam = uniform_copy(W.cams + cam_id);
+  const EnvDev ed = uniform_copy(W.envs + cam.env);
   const int n = ed.n_bodies;
   const int ntris = ed.n_tris;
   const int64_t cap = W.cap_bodies;
@@ -843,7 +843,7 @@ __global__ void __attribute__((amdgpu_waves_per_eu(6))) raster_setup_kernel(Worl
   const SetupLayout Lo = setup_layout(L.max_bodies, L.max_verts, L.max_tiles, L.max_tris, CLIP);
   if (L.persistent == 0) {
     if ((int)blockIdx.x >= L.n_work) return;
-    setup_image<CLIP, false>(lds, Lo, W, L, L.work[blockIdx.x]);
+    setup_image<CLIP, false>(lds, Lo, W, L, uniform_ld(L.work + blockIdx.x));
     return;
   }
   int32_t* slot = (int32_t*)(lds + Lo.misc) + 4;
@@ -853,7 +853,7 @@ __global__ void __attribute__((amdgpu_waves_per_eu(6))) raster_setup_kernel(Worl
     __syncthreads();
     const int wi = *slot;
     if (wi >= L.n_work) return;
-    setup_image<CLIP, false>(lds, Lo, W, L, L.work[wi]);
+    setup_image<CLIP, false>(lds, Lo, W, L, uniform_ld(L.work + wi));
   }
 }
 
@@ -878,19 +878,6 @@ struct TileWaveLDS {
   uint64_t zb[TS * TS];  // z-buffer of the small-triangle fragments
   int32_t own[64];       // fragment owner marks
 };
-
-// A uniform load of data that no wave writes while the kernel runs (launch
-// tables, camera descriptors, what an earlier kernel wrote): read through
-// the constant address space, so that it is one scalar load.
-template <class T>
-__device__ __forceinline__ T uniform_ld(const T* p) {
-  return *(const __attribute__((address_space(4))) T*)p;
-}
-
-__device__ __forceinline__ int2 uniform_ld(const int2* p) {
-  const uint64_t v = uniform_ld((const uint64_t*)p);
-  return make_int2((int32_t)(uint32_t)v, (int32_t)(uint32_t)(v >> 32));
-}
 
 // Key of a primitive's fragment below its depth: primitive << 24 | RGB8.
 // Primitives number at most 65535 per env, so no key equals the empty ~0.
@@ -1321,10 +1308,10 @@ __global__ void __launch_bounds__(1024) raster_fused_kernel(WorldDev W, RasterLa
       wi = misc[4];
     }
     if (wi >= L.n_work) return;
-    const int cam_id = L.work[wi];
+    const int cam_id = uniform_ld(L.work + wi);
     setup_image<false, true>(lds, Lo, W, L, cam_id);
     __syncthreads();
-    const CamDev cam = W.cams[cam_id];
+    const CamDev cam = uniform_copy(W.cams + cam_id);
     const int nrec = misc[2], mode = misc[6];
     const bool binned = (mode & 2) != 0;
     const unsigned char* rs = W.rscratch + cam.rs_off + (int64_t)L.parity * cam.rs_total;

@@ -39,6 +39,33 @@ struct EnvDev {
   int64_t vert_map;   // offset of the env's vertex -> body map
 };
 
+// Uniform loads of data that no wave writes while the kernel runs (launch
+// tables, descriptors, what an earlier kernel wrote): read through the
+// constant address space, so that they are scalar loads into scalar
+// registers.  uniform_copy takes a whole struct, a word at a time.
+template <class T>
+__device__ __forceinline__ T uniform_ld(const T* p) {
+  return *(const __attribute__((address_space(4))) T*)p;
+}
+
+__device__ __forceinline__ int2 uniform_ld(const int2* p) {
+  const uint64_t v = uniform_ld((const uint64_t*)p);
+  return make_int2((int32_t)(uint32_t)v, (int32_t)(uint32_t)(v >> 32));
+}
+
+template <class T>
+__device__ __forceinline__ T uniform_copy(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "whole words");
+  T v;
+  const uint32_t* s = reinterpret_cast<const uint32_t*>(p);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) {
+    const uint32_t x = uniform_ld(s + i);
+    __builtin_memcpy(reinterpret_cast<char*>(&v) + 4 * i, &x, 4);
+  }
+  return v;
+}
+
 constexpr uint8_t kGroundBody = 0xFF;  // body id of ground primitives in the maps
 
 struct CamDev {

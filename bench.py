@@ -9,6 +9,7 @@ oracle on a bounded sample of the same workload.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -91,7 +92,6 @@ def phase_seconds(st, steps, presetup):
 
 
 def source_hash(kernel):
-    import hashlib
     h = hashlib.sha1()
     for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(CSRC, f), "rb") as fh:
@@ -156,8 +156,14 @@ def copy_ceiling(torch, mib=1024, reps=5):
 
 def device_info(torch):
     p = torch.cuda.get_device_properties(0)
+    from paper_2605_01352_amd import build as vb
+    with open(vb.MANIFEST) as f:
+        built = json.load(f)["sources"]
+    # one digest over the library's sources (the binding has checked that the
+    # library was built from them)
+    digest = hashlib.sha256("".join(f"{k}={built[k]};" for k in sorted(built)).encode()).hexdigest()[:16]
     return {"name": p.name, "arch": getattr(p, "gcnArchName", None), "compute_units": p.multi_processor_count,
-            "hbm_bytes": int(p.total_memory)}
+            "hbm_bytes": int(p.total_memory), "library_sources_sha256": digest}
 
 
 VALU_PEAK_GINST = 256 * 4 * 2.4e9 / 4 / 1e9  # wave64 VALU instructions per second, 4 cycles each

@@ -1,5 +1,7 @@
 """Build libvuda.so (HIP kernels + C-ABI runtime) for gfx950, in-tree."""
 import glob
+import hashlib
+import json
 import os
 import subprocess
 import sys
@@ -9,6 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libvuda.so")
+
+MANIFEST = os.path.join(LIBDIR, "libvuda.sources.json")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -22,7 +26,24 @@ FLAGS = [
 ]
 
 
+def source_files():
+    """Every file the library is compiled from: the HIP sources, their headers
+    and the C-ABI header."""
+    return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.h")) +
+                  glob.glob(os.path.join(ROOT, "include", "*.h")))
+
+
+def source_digests():
+    """{path relative to the repository root: sha256 of its bytes}."""
+    out = {}
+    for f in source_files():
+        with open(f, "rb") as fh:
+            out[os.path.relpath(f, ROOT)] = hashlib.sha256(fh.read()).hexdigest()
+    return out
+
+
 def build(verbose: bool = False, jobs: int = 4) -> str:
+    digests = source_digests()  # taken before compiling: what the objects are built from
     os.makedirs(LIBDIR, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     objdir = os.path.join(LIBDIR, "_obj")
@@ -53,6 +74,11 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
+    # the manifest the binding checks the sources against when it loads the
+    # library: a library built from other sources is refused
+    with open(MANIFEST + ".tmp", "w") as f:
+        json.dump({"library": os.path.basename(LIB), "sources": digests}, f, indent=1, sort_keys=True)
+    os.replace(MANIFEST + ".tmp", MANIFEST)
     return LIB
 
 

@@ -8,6 +8,7 @@ first World() loads lib/libvuda.so and raises if it has not been built
 from __future__ import annotations
 
 import ctypes as C
+import json
 import os
 from typing import Dict, Optional, Sequence
 
@@ -15,6 +16,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "libvuda.so")
+DEFAULT_LIB_PATH = LIB_PATH
 
 OK, EINVAL, ENOMEM, EHIP, ENUMERIC, EOVERFLOW, EBUSY = 0, -1, -2, -3, -4, -5, -6
 PHASE_STEP, PHASE_RENDER, PHASE_ALL = 1, 2, 3
@@ -130,6 +132,19 @@ class ServeStats(C.Structure):
 _lib = None
 
 
+def stale_sources():
+    """Sources whose bytes differ from what the in-tree library was built from
+    (its manifest, written by build.py); ['(no manifest)'] without one."""
+    from . import build as _build
+    try:
+        with open(_build.MANIFEST) as f:
+            built = json.load(f)["sources"]
+    except (OSError, ValueError, KeyError):
+        return ["(no manifest)"]
+    now = _build.source_digests()
+    return sorted(k for k in set(built) | set(now) if built.get(k) != now.get(k))
+
+
 def lib():
     """Load libvuda.so; raises if it is missing (build it first)."""
     global _lib
@@ -137,6 +152,12 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run paper_2605_01352_amd/build.py "
                                f"(or __graft_entry__.build())")
+        if LIB_PATH == DEFAULT_LIB_PATH:
+            stale = stale_sources()
+            if stale:
+                raise RuntimeError(f"{LIB_PATH} was built from other sources than the tree holds "
+                                   f"({', '.join(stale[:4])}{' ...' if len(stale) > 4 else ''}); rebuild it "
+                                   f"(paper_2605_01352_amd/build.py or __graft_entry__.build())")
         # PyTorch ships its own HIP runtime and loads it under another name; it
         # has to be loaded first so that libvuda binds to that same runtime and
         # the process holds one (streams and events are then shared with it).

@@ -29,6 +29,23 @@ def test_exports_every_declared_symbol():
     assert set(names) == set(vuda.EXPORTS)
 
 
+def test_library_matches_its_sources(monkeypatch):
+    """The in-tree library was built from the sources the tree holds, and the
+    binding refuses one built from others (its manifest, written by build.py,
+    against the sources' digests now)."""
+    assert vuda.stale_sources() == []
+    from paper_2605_01352_amd import build as vb
+    real = vb.source_digests()
+    edited = dict(real)
+    key = sorted(k for k in real if k.endswith("raster.hip"))[0]
+    edited[key] = "0" * 64
+    monkeypatch.setattr(vb, "source_digests", lambda: edited)
+    assert vuda.stale_sources() == [key]
+    monkeypatch.setattr(vuda, "_lib", None)
+    with pytest.raises(RuntimeError, match="built from other sources"):
+        vuda.lib()
+
+
 def test_strerror():
     L = vuda.lib()
     for code in (0, -1, -2, -3, -4, -5, -6):

@@ -426,9 +426,10 @@ def uneven_c4_leg(torch, vuda, scene, start, steps, log):
     choice of vuda_autotune (schedule, CU split, persistent grids, graphs,
     tile size, raster path, ...) applied and timed, and the config's own
     launch plan -- one persistent launch per phase and graph-captured steps
-    -- on the tuned split.  Medians of 3 windows."""
+    -- on the tuned split, with grids of the resident workgroups and with one
+    (physics) and two (raster setup) workgroups per CU.  Medians of 3
+    windows."""
     n = scene.n_envs
-    ncu = torch.cuda.get_device_properties(0).multi_processor_count
     with vuda.World(scene) as w:
         w.step(nsteps=start)
         w.wait()
@@ -441,20 +442,27 @@ def uneven_c4_leg(torch, vuda, scene, start, steps, log):
         ser = n * steps / med("serial")
         w.load_state(st0)
         t0 = time.perf_counter()
-        choice = w.autotune(steps=10)
+        choice = w.autotune(steps=40)
         t_tune = time.perf_counter() - t0
         sched = vuda.SCHED_NAMES[int(choice["schedule"])]
         tuned = n * steps / med(sched)
-        for k, v in ((vuda.TUNE_PHYS_PERSISTENT, ncu), (vuda.TUNE_RASTER_PERSISTENT, 2 * ncu), (vuda.TUNE_GRAPHS, 1)):
-            w.set_tuning(k, v)
-        plan = n * steps / med(sched)
+        # persistent grids of the workgroups the GPU holds at once (the
+        # kernels' occupancy times the CU count), then of one and two per CU
+        ncu = torch.cuda.get_device_properties(0).multi_processor_count
+        plans = {}
+        for name, pg, rg in (("resident", vuda.PERSISTENT_RESIDENT, vuda.PERSISTENT_RESIDENT),
+                             ("per_cu_1_2", ncu, 2 * ncu)):
+            for k, v in ((vuda.TUNE_PHYS_PERSISTENT, pg), (vuda.TUNE_RASTER_PERSISTENT, rg), (vuda.TUNE_GRAPHS, 1)):
+                w.set_tuning(k, v)
+            plans[name] = round(n * steps / med(sched), 1)
+        plan = plans["resident"]
     out = {"envs": n, "bodies": int(scene.n_bodies), "from_step": start, "serialized": round(ser, 1),
            "autotuned": round(tuned, 1), "speedup_vs_serialized": round(tuned / ser, 4),
            "autotune_choice": {k: (round(v, 1) if isinstance(v, float) else v) for k, v in choice.items()},
            "autotune_seconds": round(t_tune, 2),
-           "persistent_graphs_on_tuned_split": round(plan, 1)}
+           "persistent_graphs_on_tuned_split": round(plan, 1), "persistent_graphs_grids": plans}
     log(f"c4: serialized {ser:.0f}, autotuned ({sched}@{choice['cu_split']:g}) {tuned:.0f} env-steps/s "
-        f"({tuned / ser:.3f}x); persistent + graphs {plan:.0f}; choice {choice}")
+        f"({tuned / ser:.3f}x); persistent + graphs {plans}; choice {choice}")
     return out
 
 
@@ -784,7 +792,7 @@ def main():
     if not args.only and not args.no_autotune:
         w.load_state(st0)
         t0 = time.perf_counter()
-        choice = w.autotune(steps=20)
+        choice = w.autotune(steps=40)
         t_tune = time.perf_counter() - t0
         tsched = vuda.SCHED_NAMES[int(choice["schedule"])]
         dt_t, t_windows = median_windows(tsched)

@@ -289,7 +289,10 @@ int vuda_world_info(vuda_world* w, int32_t* n_envs, int64_t* n_bodies, int32_t* 
  *                              tile testing every visible triangle (slower,
  *                              same output)
  *   VUDA_TUNE_PHYS_PERSISTENT  0: one workgroup per env; n > 0: n resident
- *                              workgroups pulling envs from a device queue
+ *                              workgroups pulling envs from a device queue;
+ *                              VUDA_PERSISTENT_RESIDENT (-1): as many
+ *                              workgroups as the GPU holds at once (the
+ *                              kernel's occupancy per CU times the CU count)
  *   VUDA_TUNE_RASTER_PERSISTENT  the same for camera images
  *   VUDA_TUNE_GRAPHS           1: each (phase, env range, parity) launch is
  *                              captured once into a hipGraph and replayed
@@ -351,6 +354,7 @@ int vuda_world_info(vuda_world* w, int32_t* n_envs, int64_t* n_bodies, int32_t* 
 #define VUDA_TUNE_REC_CAP 2
 #define VUDA_TUNE_PHYS_PERSISTENT 3
 #define VUDA_TUNE_RASTER_PERSISTENT 4
+#define VUDA_PERSISTENT_RESIDENT (-1) /* persistent grid sized to the GPU's resident workgroups */
 #define VUDA_TUNE_GRAPHS 5
 #define VUDA_TUNE_PHYS_PRIORITY 6
 #define VUDA_TUNE_BROADPHASE 7
@@ -500,7 +504,11 @@ int vuda_run(vuda_world* w, int32_t schedule, int32_t iters);
  * for the highest
  * co-scheduled env-steps/s on this world, timing `steps_per_trial`
  * iterations per candidate from the current state (the state is saved before
- * and restored after, so results are unchanged), applies the best, and
+ * and restored after, so results are unchanged); the last few winners of the
+ * search and the serialized baseline are timed again, three trials each, and
+ * the best median is chosen (VUDA_SCHED_SERIAL where nothing co-scheduled
+ * beats it; its rate is reported as cosched_env_steps_per_s).  It applies
+ * the best, and
  * records it in the text file `cache_path` (may be NULL) keyed by the GPU
  * architecture and the world's shape; a later call with the same key applies
  * the cached choice without trials.  Also reports the best serialized rate.

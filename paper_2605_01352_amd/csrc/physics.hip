@@ -21,6 +21,10 @@
 //      order independent of scheduling;
 //   6. semi-implicit Euler.
 // No floating-point atomics are used; results are bit-reproducible.
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "vuda_internal.h"
 
 #pragma clang fp contract(off)
@@ -1254,6 +1258,54 @@ hipError_t launch_reset_queue(int32_t* q, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t resident_workgroups(const void* kernel, int threads, size_t dyn_lds, int* out) {
+  *out = 0;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  static std::mutex mu;
+  static std::map<std::tuple<int, const void*, int, size_t>, int> cache;
+  const auto key = std::make_tuple(dev, kernel, threads, dyn_lds);
+  {
+    std::lock_guard<std::mutex> g(mu);
+    const auto it = cache.find(key);
+    if (it != cache.end()) {
+      *out = it->second;
+      return hipSuccess;
+    }
+  }
+  int per_cu = 0, cus = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, dyn_lds);
+  if (e != hipSuccess) return e;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  const int n = per_cu * cus;
+  if (n <= 0) return hipErrorInvalidConfiguration;
+  std::lock_guard<std::mutex> g(mu);
+  cache[key] = n;
+  *out = n;
+  return hipSuccess;
+}
+
+hipError_t persistent_grid(int persistent, int items, const void* kernel, int threads, size_t dyn_lds,
+                           int* grid) {
+  int n = persistent;
+  if (n < 0) {
+    const hipError_t e = resident_workgroups(kernel, threads, dyn_lds, &n);
+    if (e != hipSuccess) return e;
+  }
+  *grid = n < items ? n : items;
+  return hipSuccess;
+}
+
+template <int N, bool SUP>
+static const void* physics_fn(bool fr, bool ee) {
+  if (!fr && !ee) return (const void*)physics_kernel<N, false, false, SUP>;
+  if (!ee) return (const void*)physics_kernel<N, true, false, SUP>;
+  if (!fr) return (const void*)physics_kernel<N, false, true, SUP>;
+  return (const void*)physics_kernel<N, true, true, SUP>;
+}
+
 template <int N, bool SUP>
 static void launch_n(bool fr, bool ee, LaunchEvents* ev, bool first, bool last, dim3 g, hipStream_t s,
                      const WorldDev& w, const PhysConsts& pc, const PhysLaunch& lt) {
@@ -1272,15 +1324,23 @@ hipError_t launch_physics(const WorldDev& w, const PhysConsts& pc, const PhysLau
   const int N = (l.max_bodies <= 32 && l.pack == 2) ? 32 : (l.max_bodies <= 64 ? 64 : 128);
   const int P = N < 64 ? 64 / N : 1;
   const int items = (l.n_work + P - 1) / P;
+  const bool fr = pc.mu > 0.0f, ee = pc.edge != 0;
+  int grid = items;
+  if (l.persistent != 0) {
+    const void* fn = N == 32 ? physics_fn<32, false>(fr, ee)
+                     : N == 64 ? (l.max_bodies > 32 ? physics_fn<64, true>(fr, ee) : physics_fn<64, false>(fr, ee))
+                               : physics_fn<128, false>(fr, ee);
+    const hipError_t e = persistent_grid(l.persistent, items, fn, N < 64 ? 64 : N, 0, &grid);
+    if (e != hipSuccess) return e;
+  }
   for (int t = 0; t < l.nsteps; ++t) {
     PhysLaunch lt = l;
     lt.parity = (l.parity + t) & 1;
-    const int grid = l.persistent > 0 ? (l.persistent < items ? l.persistent : items) : items;
-    if (l.persistent > 0) {
+    lt.persistent = l.persistent != 0 ? grid : 0;  // the kernel only tells 0 from the rest
+    if (l.persistent != 0) {
       hipError_t e = launch_reset_queue(l.queue, s);
       if (e != hipSuccess) return e;
     }
-    const bool fr = pc.mu > 0.0f, ee = pc.edge != 0;
     const bool first = t == 0, last = t == l.nsteps - 1;
     if (N == 32) launch_n<32, false>(fr, ee, ev, first, last, dim3(grid), s, w, pc, lt);
     else if (N == 64 && l.max_bodies > 32) launch_n<64, true>(fr, ee, ev, first, last, dim3(grid), s, w, pc, lt);

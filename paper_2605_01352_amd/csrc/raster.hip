@@ -1372,23 +1372,37 @@ hipError_t raster_fused_configure(size_t lds_bytes) {
 }
 
 template <bool DBG>
-static void launch_fused(const WorldDev& w, const RasterLaunch& l, size_t lds, hipStream_t s, LaunchEvents* ev) {
-  const int grid = l.persistent > 0 ? (l.persistent < l.n_work ? l.persistent : l.n_work) : l.n_work;
+static const void* fused_fn(int tile_shift) {
+  if (tile_shift == 3) return (const void*)raster_fused_kernel<DBG, 8>;
+  if (tile_shift == 5) return (const void*)raster_fused_kernel<DBG, 32>;
+  return (const void*)raster_fused_kernel<DBG, 16>;
+}
+
+template <bool DBG>
+static void launch_fused(const WorldDev& w, const RasterLaunch& l, int grid, size_t lds, hipStream_t s,
+                         LaunchEvents* ev) {
   const dim3 g(grid), b(l.threads);
   if (l.tile_shift == 3) timed_launch(ev, true, true, raster_fused_kernel<DBG, 8>, g, b, (uint32_t)lds, s, w, l);
   else if (l.tile_shift == 5) timed_launch(ev, true, true, raster_fused_kernel<DBG, 32>, g, b, (uint32_t)lds, s, w, l);
   else timed_launch(ev, true, true, raster_fused_kernel<DBG, 16>, g, b, (uint32_t)lds, s, w, l);
 }
 
-hipError_t launch_raster_fused(const WorldDev& w, const RasterLaunch& l, size_t lds, hipStream_t s,
+hipError_t launch_raster_fused(const WorldDev& w, const RasterLaunch& l0, size_t lds, hipStream_t s,
                                LaunchEvents* ev) {
-  if (l.n_work <= 0) return hipSuccess;
-  if (l.persistent > 0) {
-    hipError_t e = launch_reset_queue(l.queue, s);
+  if (l0.n_work <= 0) return hipSuccess;
+  RasterLaunch l = l0;
+  int grid = l.n_work;
+  if (l.persistent != 0) {
+    hipError_t e = persistent_grid(l.persistent, l.n_work, w.winners ? fused_fn<true>(l.tile_shift)
+                                                                     : fused_fn<false>(l.tile_shift),
+                                   l.threads, lds, &grid);
+    if (e != hipSuccess) return e;
+    l.persistent = grid;  // the kernel only tells 0 from the rest
+    e = launch_reset_queue(l.queue, s);
     if (e != hipSuccess) return e;
   }
-  if (w.winners) launch_fused<true>(w, l, lds, s, ev);
-  else launch_fused<false>(w, l, lds, s, ev);
+  if (w.winners) launch_fused<true>(w, l, grid, lds, s, ev);
+  else launch_fused<false>(w, l, grid, lds, s, ev);
   return hipGetLastError();
 }
 
@@ -1400,12 +1414,19 @@ hipError_t raster_configure(size_t lds_bytes) {
                              (int)lds_bytes);
 }
 
-hipError_t launch_raster_setup(const WorldDev& w, const RasterLaunch& l, hipStream_t s, LaunchEvents* ev) {
-  if (l.n_work <= 0) return hipSuccess;
+hipError_t launch_raster_setup(const WorldDev& w, const RasterLaunch& l0, hipStream_t s, LaunchEvents* ev) {
+  if (l0.n_work <= 0) return hipSuccess;
+  RasterLaunch l = l0;
   const size_t lds = raster_lds_bytes(l);
-  const int grid = l.persistent > 0 ? (l.persistent < l.n_work ? l.persistent : l.n_work) : l.n_work;
-  if (l.persistent > 0) {
-    hipError_t e = launch_reset_queue(l.queue, s);
+  int grid = l.n_work;
+  if (l.persistent != 0) {
+    hipError_t e = persistent_grid(l.persistent, l.n_work,
+                                   l.near_clip ? (const void*)raster_setup_kernel<true>
+                                               : (const void*)raster_setup_kernel<false>,
+                                   l.threads, lds, &grid);
+    if (e != hipSuccess) return e;
+    l.persistent = grid;  // the kernel only tells 0 from the rest
+    e = launch_reset_queue(l.queue, s);
     if (e != hipSuccess) return e;
   }
   if (l.near_clip)

@@ -299,4 +299,15 @@ hipError_t launch_raster_fused(const WorldDev& w, const RasterLaunch& l, size_t 
                                LaunchEvents* ev = nullptr);
 hipError_t launch_reset_queue(int32_t* q, hipStream_t s);
 
+// Workgroups of `kernel` (threads per workgroup, dynamic LDS bytes) that the
+// current device holds at once: its occupancy per CU times the CU count.
+// Cached per (device, kernel, shape); *out is 0 on failure.
+hipError_t resident_workgroups(const void* kernel, int threads, size_t dyn_lds, int* out);
+
+// The grid of a persistent launch of `items` work items: `persistent` > 0
+// workgroups, or (< 0) the resident count from resident_workgroups, at most
+// `items` either way.
+hipError_t persistent_grid(int persistent, int items, const void* kernel, int threads, size_t dyn_lds,
+                           int* grid);
+
 }  // namespace vuda

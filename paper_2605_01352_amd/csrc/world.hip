@@ -1906,11 +1906,11 @@ extern "C" int vuda_set_tuning(vuda_world* w, int32_t key, int32_t value) {
       w->tune.rec_cap = value;
       break;
     case VUDA_TUNE_PHYS_PERSISTENT:
-      if (value < 0) return fail(VUDA_EINVAL, "persistent %d", value);
+      if (value < VUDA_PERSISTENT_RESIDENT) return fail(VUDA_EINVAL, "persistent %d", value);
       w->tune.phys_persistent = value;
       break;
     case VUDA_TUNE_RASTER_PERSISTENT:
-      if (value < 0) return fail(VUDA_EINVAL, "persistent %d", value);
+      if (value < VUDA_PERSISTENT_RESIDENT) return fail(VUDA_EINVAL, "persistent %d", value);
       w->tune.raster_persistent = value;
       break;
     case VUDA_TUNE_GRAPHS:

@@ -26,6 +26,7 @@ FLAG_DEBUG = 1
 FLAG_NEAR_CLIP = 2
 FLAG_SMOOTH = 4
 TUNE_RASTER_THREADS, TUNE_REC_CAP, TUNE_PHYS_PERSISTENT, TUNE_RASTER_PERSISTENT, TUNE_GRAPHS = 1, 2, 3, 4, 5
+PERSISTENT_RESIDENT = -1  # persistent grid of the workgroups the GPU holds at once
 TUNE_PHYS_PRIORITY = 6
 TUNE_BROADPHASE = 7
 TUNE_TIMING = 8

@@ -109,7 +109,7 @@ def test_binding_constants_match_header():
     Python binding (VUDA_X -> vuda.X)."""
     src = open(os.path.join(ROOT, "include", "vuda.h")).read()
     found = 0
-    for name, val in re.findall(r"#define VUDA_([A-Z0-9_]+)\s+(-?\d+)u?\b", src):
+    for name, val in re.findall(r"#define VUDA_([A-Z0-9_]+)\s+\(?(-?\d+)u?\)?(?=\s|$)", src):
         py = name[:-1] if name.endswith("_H") else name
         if not hasattr(vuda, py):
             continue

@@ -91,6 +91,9 @@ C2 = dict(cfg=2, n_envs=48, settle=250)
      {vuda.TUNE_PHYS_PERSISTENT: 24, vuda.TUNE_RASTER_PERSISTENT: 40, vuda.TUNE_GRAPHS: 1}),
     ("persistent launches + graphs, unmasked, inter-trajectory", 2.0, vuda.SCHED_INTERTRAJ,
      {vuda.TUNE_PHYS_PERSISTENT: 256, vuda.TUNE_RASTER_PERSISTENT: 256, vuda.TUNE_GRAPHS: 1}),
+    ("persistent grids of the resident workgroups + graphs, unmasked, inter-step", 2.0, vuda.SCHED_INTERSTEP,
+     {vuda.TUNE_PHYS_PERSISTENT: vuda.PERSISTENT_RESIDENT, vuda.TUNE_RASTER_PERSISTENT: vuda.PERSISTENT_RESIDENT,
+      vuda.TUNE_GRAPHS: 1}),
     ("two envs per physics wave, unmasked, inter-step", 2.0, vuda.SCHED_INTERSTEP,
      {vuda.TUNE_PHYS_ENVS_PER_WAVE: 2}),
     ("two envs per physics wave, persistent, CU-masked 0.375, inter-trajectory", 0.375, vuda.SCHED_INTERTRAJ,
@@ -112,6 +115,9 @@ C2 = dict(cfg=2, n_envs=48, settle=250)
      {vuda.TUNE_RASTER_FUSED: 1, vuda.TUNE_RASTER_THREADS: 512}),
     ("fused raster, persistent + graphs, CU-masked 0.375, inter-trajectory", 0.375, vuda.SCHED_INTERTRAJ,
      {vuda.TUNE_RASTER_FUSED: 1, vuda.TUNE_RASTER_PERSISTENT: 20, vuda.TUNE_GRAPHS: 1}),
+    ("fused raster, resident persistent grid, two envs per physics wave on a resident grid", 2.0,
+     vuda.SCHED_INTERSTEP, {vuda.TUNE_RASTER_FUSED: 1, vuda.TUNE_RASTER_PERSISTENT: vuda.PERSISTENT_RESIDENT,
+                            vuda.TUNE_PHYS_ENVS_PER_WAVE: 2, vuda.TUNE_PHYS_PERSISTENT: vuda.PERSISTENT_RESIDENT}),
 ])
 def test_c2_schedule_parity(label, split, sched, knobs):
     """48 envs of the 1024-env config, 250 steps past the spawn (a settled
@@ -164,17 +170,22 @@ def test_pipelined_runs(split, knobs):
         say(f"pipelined, split {split} {knobs}: 25 iterations bit-identical to the serialized loop")
 
 
-def test_c4_persistent_graph_parity():
+@pytest.mark.parametrize("phys_grid,raster_grid", [(32, 64), (vuda.PERSISTENT_RESIDENT, vuda.PERSISTENT_RESIDENT)],
+                         ids=["fixed-grids", "resident-grids"])
+def test_c4_persistent_graph_parity(phys_grid, raster_grid):
     """The uneven config as it is meant to run: one persistent launch per
     phase, hipGraph-captured steps, on CU-masked streams.  64 envs of 4..128
-    bodies and 64^2..256^2 frames, 150 steps past the spawn."""
+    bodies and 64^2..256^2 frames, 150 steps past the spawn; persistent grids
+    of fixed sizes, or of the workgroups the GPU holds at once."""
     oracle.lib()
     scene = sg.config_scene(4, n_envs=64)
     with settled_world(scene, 150) as w:
-        for k, v in ((vuda.TUNE_PHYS_PERSISTENT, 32), (vuda.TUNE_RASTER_PERSISTENT, 64), (vuda.TUNE_GRAPHS, 1)):
+        for k, v in ((vuda.TUNE_PHYS_PERSISTENT, phys_grid), (vuda.TUNE_RASTER_PERSISTENT, raster_grid),
+                     (vuda.TUNE_GRAPHS, 1)):
             w.set_tuning(k, v)
         w.cosched(0.5)
-        parity_iterations(w, scene, vuda.SCHED_INTERTRAJ, 5, "c4[0:64] @150, persistent + graphs")
+        parity_iterations(w, scene, vuda.SCHED_INTERTRAJ, 5,
+                          f"c4[0:64] @150, persistent grids {phys_grid}/{raster_grid} + graphs")
 
 
 def test_autotuned_choice_parity():

@@ -198,7 +198,9 @@ def test_invalid_calls():
     s = sg.config_scene(1, n_envs=2)
     with vuda.World(s) as w:
         for bad in (lambda: w.step(0, 3), lambda: w.render(-1, 1), lambda: w.cosched(1.5),
-                    lambda: w.set_tuning(vuda.TUNE_RASTER_THREADS, 100), lambda: w.run(7, 1)):
+                    lambda: w.set_tuning(vuda.TUNE_RASTER_THREADS, 100), lambda: w.run(7, 1),
+                    lambda: w.set_tuning(vuda.TUNE_PHYS_PERSISTENT, -2),
+                    lambda: w.set_tuning(vuda.TUNE_RASTER_PERSISTENT, -2)):
             with pytest.raises(vuda.VudaError) as e:
                 bad()
             assert e.value.code == vuda.EINVAL

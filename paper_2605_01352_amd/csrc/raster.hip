@@ -991,15 +991,11 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
   const int px0 = tx0 + BW * bx, py0 = ty0 + BH * by;
   const auto zidx = [&](int i, int j) { return (BH * by + j) * TS + BW * bx + i; };
   uint64_t* zb = S.zb;
-  // a tile with an empty bin (a third of them in a settled scene) goes
-  // straight to the background stores
-  const bool empty = k0 == k1;
-  if (!empty) {
-#pragma unroll
-    for (int j = 0; j < BH; ++j)
-#pragma unroll
-      for (int i = 0; i < BW; ++i) zb[zidx(i, j)] = ~0ull;
-  }
+  // The LDS z-buffer is only for small triangles' fragments: it is cleared
+  // before the first fragment window and read back only if it was.  A tile
+  // whose bin is empty (a third of them in a settled scene) or holds large
+  // triangles alone, such as the open ground, never touches it.
+  bool zused = false;
   if (DBG) {
 #pragma unroll
     for (int j = 0; j < BH; ++j)
@@ -1069,6 +1065,13 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
     const int off = incl - a;
     const int mxy = fx0 | (fy0 << 16), mob = off | (bw << 16);
     int carry = 0;  // owner + 1 of the fragment before the window
+    if (F > 0 && !zused) {
+#pragma unroll
+      for (int j = 0; j < BH; ++j)
+#pragma unroll
+        for (int i = 0; i < BW; ++i) zb[zidx(i, j)] = ~0ull;
+      zused = true;
+    }
     for (int f0 = 0; f0 < F; f0 += 64) {
       S.own[lane] = 0;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1175,7 +1178,7 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
 #pragma unroll
     for (int i = 0; i < BW; ++i) {
       const int q = j * BW + i;
-      const uint64_t zk = empty ? ~0ull : zb[zidx(i, j)];
+      const uint64_t zk = zused ? zb[zidx(i, j)] : ~0ull;
       const uint64_t key = zk < kreg[q] ? zk : kreg[q];
       const bool hit = key != ~0ull;
       D[i] = hit ? (uint32_t)(key >> 40) : 0xFFFFFFFFu;

@@ -34,7 +34,8 @@ class RenderParams(C.Structure):
         ("cube_nv", C.c_int32), ("cube_nf", C.c_int32),
         ("ground_v", C.c_void_p), ("ground_f", C.c_void_p), ("ground_nf", C.c_int32),
         ("light", C.c_float * 3), ("palette", C.c_float * 24), ("ground_albedo", C.c_float),
-        ("near_w", C.c_float), ("guard", C.c_float), ("near_clip", C.c_int32), ("smooth", C.c_int32)]
+        ("near_w", C.c_float), ("guard", C.c_float), ("near_clip", C.c_int32), ("smooth", C.c_int32),
+        ("texture", C.c_void_p), ("tex_w", C.c_int32), ("tex_h", C.c_int32), ("ground_uv_scale", C.c_float)]
 
 
 class Point(C.Structure):
@@ -82,7 +83,7 @@ class _Render:
     """Keeps the template arrays alive while the struct points at them."""
 
     def __init__(self, light=None, palette=None, ground_albedo=None, near=None, guard=None, near_clip=False,
-                 smooth=False):
+                 smooth=False, texture=None, ground_uv_scale=1.0):
         from paper_2605_01352_amd import scenegen as sg
         t = sg.templates()
         self.arrs = [np.ascontiguousarray(a) for a in (
@@ -99,19 +100,37 @@ class _Render:
             float(sg.GROUND_ALBEDO if ground_albedo is None else ground_albedo),
             float(sg.NEAR if near is None else near),
             float(sg.GUARD_BAND if guard is None else guard), 1 if near_clip else 0, 1 if smooth else 0)
+        if texture is not None:
+            self.tex = np.ascontiguousarray(texture, np.uint8)
+            assert self.tex.ndim == 3 and self.tex.shape[2] == 3
+            self.s.texture = _p(self.tex)
+            self.s.tex_h, self.s.tex_w = int(self.tex.shape[0]), int(self.tex.shape[1])
+            self.s.ground_uv_scale = float(np.float32(ground_uv_scale))
 
 
 _RENDER: Dict[bool, _Render] = {}
 
 
-def render_params(near_clip: bool = False, smooth: bool = False) -> _Render:
+def render_params(near_clip: bool = False, smooth: bool = False, texture=None,
+                  ground_uv_scale: float = 1.0) -> _Render:
     """Default render parameters; near_clip: cut triangles crossing the near
     plane instead of culling them; smooth: per-pixel Lambert shading of the
-    perspective-correctly interpolated vertex normal."""
+    perspective-correctly interpolated vertex normal; texture (with smooth):
+    RGB8 texels [h, w, 3] on the ground (coordinates: world x, y times
+    ground_uv_scale) and on cube and box faces."""
+    if texture is not None:
+        return _Render(near_clip=near_clip, smooth=smooth, texture=texture, ground_uv_scale=ground_uv_scale)
     key = (bool(near_clip), bool(smooth))
     if key not in _RENDER:
         _RENDER[key] = _Render(near_clip=key[0], smooth=key[1])
     return _RENDER[key]
+
+
+def scene_render_params(scene) -> _Render:
+    """The render parameters a scene asks for (its near_clip, smooth and
+    texture attributes)."""
+    return render_params(getattr(scene, "near_clip", False), getattr(scene, "smooth", False),
+                         getattr(scene, "texture", None), getattr(scene, "ground_uv_scale", 1.0))
 
 
 def step_env(scene, e: int, state: Dict[str, np.ndarray], record_pairs: bool = False,
@@ -186,12 +205,14 @@ def render_image(scene, state, cam: int, e: Optional[int] = None, debug: bool = 
     bt, sz, al = sl(scene.btype), sl(scene.size), sl(scene.albedo)
     pos, quat = sl(state["pos"]), sl(state["quat"])
     vp = np.ascontiguousarray(scene.cam_vp[cam], np.float32)
-    rp = render_params(getattr(scene, "near_clip", False), getattr(scene, "smooth", False))
+    rp = scene_render_params(scene)
     ex = None if getattr(scene, "ext", None) is None else np.ascontiguousarray(scene.ext[b0:b1], np.float32)
-    lib().oracle_render_image_box(b1 - b0, _p(bt), _p(sz), _p(ex) if ex is not None else None, _p(al), _p(pos),
-                              _p(quat), _p(vp), W, H,
-                              C.byref(rp.s), _p(rgb), _p(depth),
-                              _p(winner) if debug else None, _p(cover) if debug else None)
+    rc = lib().oracle_render_image_box(b1 - b0, _p(bt), _p(sz), _p(ex) if ex is not None else None, _p(al),
+                                       _p(pos), _p(quat), _p(vp), W, H,
+                                       C.byref(rp.s), _p(rgb), _p(depth),
+                                       _p(winner) if debug else None, _p(cover) if debug else None)
+    if rc != 0:
+        raise ValueError(f"oracle render refused the parameters ({rc})")
     out = dict(rgb=rgb, depth=depth)
     if debug:
         out.update(winner=winner, cover=cover)
@@ -237,6 +258,27 @@ def smooth_normal(X, Y, iw, normals, px, py):
     return out
 
 
+def smooth_uv(X, Y, iw, uv, px, py):
+    """Texture coordinates at the centre of pixel (px, py) of a triangle
+    (setup order; 1 / clip w and (u, v) per vertex), perspective-correct."""
+    X = np.ascontiguousarray(X, np.int32)
+    Y = np.ascontiguousarray(Y, np.int32)
+    iw = np.ascontiguousarray(iw, np.float32)
+    t = np.ascontiguousarray(uv, np.float32).reshape(6)
+    out = np.zeros(2, np.float32)
+    lib().oracle_smooth_uv(_p(X), _p(Y), _p(iw), _p(t), int(px), int(py), _p(out))
+    return out
+
+
+def cube_face_uv(f: int) -> np.ndarray:
+    """Texture coordinates [3, 2] of the corners (face order) of face f of
+    the cube template."""
+    out = np.zeros(6, np.float32)
+    rp = render_params()
+    lib().oracle_cube_face_uv(C.byref(rp.s), int(f), _p(out))
+    return out.reshape(3, 2)
+
+
 def covers(X, Y, px, py) -> bool:
     X = np.ascontiguousarray(X, np.int32)
     Y = np.ascontiguousarray(Y, np.int32)
@@ -269,7 +311,7 @@ def run_batch(scene, state, n_steps: int, nthreads: int, do_render: bool = True)
     for k in ("pos", "vel", "quat", "omega"):
         state[k] = np.ascontiguousarray(state[k], np.float32)
     prm = phys_params(scene)
-    rp = render_params(getattr(scene, "near_clip", False), getattr(scene, "smooth", False))
+    rp = scene_render_params(scene)
     st = lib().oracle_run_batch(
         scene.n_envs, _p(arrs["bo"]), _p(arrs["bt"]), _p(arrs["sz"]), _p(arrs["rb"]),
         _p(arrs["im"]), _p(arrs["iI"]), _p(arrs["al"]), _p(state["pos"]), _p(state["vel"]),

@@ -627,6 +627,8 @@ typedef struct {
   float iw[3];      /* 1 / clip w of each vertex, setup order */
   float n[3][3];    /* world normal of each vertex, setup order */
   float alb[3];
+  float uv[3][2];   /* texture coordinates of each vertex, setup order */
+  int32_t textured;
 } smooth_tri;
 
 /* Perspective-correct interpolation at the centre of pixel (px, py) of a
@@ -650,6 +652,50 @@ void oracle_smooth_normal(const int32_t* X, const int32_t* Y, const float* iw, c
   } else {
     out[0] = out[1] = out[2] = 0.0f;
   }
+}
+
+/* Texture coordinates, a reading of the paper's textured meshes: the
+ * coordinates of a pixel are interpolated with the same perspective-correct
+ * weights as the normal, E_k / w_k, here normalized by their sum. */
+void oracle_smooth_uv(const int32_t* X, const int32_t* Y, const float* iw, const float* uv, int32_t px,
+                      int32_t py, float* out) {
+  int64_t Px = 256 * (int64_t)px + 128, Py = 256 * (int64_t)py + 128;
+  int64_t E[3];
+  E[0] = edge_fn(X[1], Y[1], X[2], Y[2], Px, Py);
+  E[1] = edge_fn(X[2], Y[2], X[0], Y[0], Px, Py);
+  E[2] = edge_fn(X[0], Y[0], X[1], Y[1], Px, Py);
+  float u[3];
+  for (int k = 0; k < 3; ++k) u[k] = (float)E[k] * iw[k];
+  float s = (u[0] + u[1]) + u[2];
+  if (!(s > 0.0f)) {
+    out[0] = out[1] = 0.0f;
+    return;
+  }
+  out[0] = ((u[0] * uv[0] + u[1] * uv[2]) + u[2] * uv[4]) / s;
+  out[1] = ((u[0] * uv[1] + u[1] * uv[3]) + u[2] * uv[5]) / s;
+}
+
+void oracle_cube_face_uv(const oracle_render_params* rp, int32_t f, float* uv) {
+  const float* n = rp->cube_n + 3 * f;
+  /* the face normal's axis; the other two, in order, are the tangent axes */
+  int a = fabsf(n[0]) > 0.5f ? 0 : (fabsf(n[1]) > 0.5f ? 1 : 2);
+  int t0 = a == 0 ? 1 : 0, t1 = a == 2 ? 1 : 2;
+  for (int k = 0; k < 3; ++k) {
+    const float* v = rp->cube_v + 3 * rp->cube_f[3 * f + k];
+    uv[2 * k] = (v[t0] + 1.0f) * 0.5f;
+    uv[2 * k + 1] = (v[t1] + 1.0f) * 0.5f;
+  }
+}
+
+/* The texel under (U, V): the fractional parts select the texel, nearest,
+ * the texture repeating in both directions; its RGB / 255. */
+static void texel_at(const oracle_render_params* rp, float U, float V, float* t) {
+  float fu = U - floorf(U), fv = V - floorf(V);
+  int32_t i = (int32_t)(fu * (float)rp->tex_w), j = (int32_t)(fv * (float)rp->tex_h);
+  if (i > rp->tex_w - 1) i = rp->tex_w - 1;
+  if (j > rp->tex_h - 1) j = rp->tex_h - 1;
+  const uint8_t* p = rp->texture + 3 * ((size_t)j * (size_t)rp->tex_w + (size_t)i);
+  for (int c = 0; c < 3; ++c) t[c] = (float)p[c] / 255.0f;
 }
 
 static void raster_snapped(const int32_t* X, const int32_t* Y, const float* z, int64_t A, uint32_t prim,
@@ -696,7 +742,7 @@ static void raster_snapped(const int32_t* X, const int32_t* Y, const float* z, i
  * their normals nv) for smooth shading: the triangle table keeps its
  * snapped vertices, 1 / clip w and normals in setup order (0, 2, 1). */
 static int smooth_tri_raster(const float* w0, const float* w1, const float* w2, const float* const nv[3],
-                             const float* alb, uint32_t prim, const float* vp, int32_t W, int32_t H,
+                             const float* alb, const float* uvf, uint32_t prim, const float* vp, int32_t W, int32_t H,
                              const oracle_render_params* rp, uint64_t* keys, int32_t* cover, int32_t* tri_of,
                              smooth_tri** tris, int32_t* ntri, int32_t* tcap) {
   int32_t X[3], Y[3];
@@ -719,7 +765,10 @@ static int smooth_tri_raster(const float* w0, const float* w1, const float* w2, 
     st->Y[k] = Y[k];
     st->iw[k] = 1.0f / c[3];
     for (int r = 0; r < 3; ++r) st->n[k][r] = nv[ord[k]][r];
+    st->uv[k][0] = uvf ? uvf[2 * ord[k]] : 0.0f;
+    st->uv[k][1] = uvf ? uvf[2 * ord[k] + 1] : 0.0f;
   }
+  st->textured = uvf != NULL;
   for (int c = 0; c < 3; ++c) st->alb[c] = alb[c];
   raster_snapped(X, Y, z, A, prim, W, H, keys, cover, tri_of, *ntri);
   ++*ntri;
@@ -739,6 +788,7 @@ int oracle_render_image_box(int32_t n, const uint8_t* type, const float* size, c
                             uint8_t* rgb, uint32_t* depth, int32_t* winner, int32_t* cover) {
   size_t npix = (size_t)W * (size_t)H;
   if (rp->smooth && rp->near_clip) return -2;
+  if (rp->texture && (!rp->smooth || rp->tex_w < 1 || rp->tex_h < 1)) return -2;
   uint64_t* keys = (uint64_t*)malloc(sizeof(uint64_t) * (npix ? npix : 1));
   if (!keys) return -1;
   for (size_t i = 0; i < npix; ++i) keys[i] = UINT64_MAX;
@@ -763,8 +813,15 @@ int oracle_render_image_box(int32_t n, const uint8_t* type, const float* size, c
       const float up[3] = {0.0f, 0.0f, 1.0f};
       const float* nv[3] = {up, up, up};
       const float ga[3] = {rp->ground_albedo, rp->ground_albedo, rp->ground_albedo};
+      /* the ground's texture coordinates: its world (x, y) scaled */
+      float guv[6];
+      for (int k = 0; k < 3; ++k) {
+        guv[2 * k] = rp->ground_v[3 * fi[k]] * rp->ground_uv_scale;
+        guv[2 * k + 1] = rp->ground_v[3 * fi[k] + 1] * rp->ground_uv_scale;
+      }
       if (smooth_tri_raster(rp->ground_v + 3 * fi[0], rp->ground_v + 3 * fi[1], rp->ground_v + 3 * fi[2], nv, ga,
-                            prim, vp, W, H, rp, keys, cover, tri_of, &tris, &ntri, &tcap)) {
+                            rp->texture ? guv : NULL, prim, vp, W, H, rp, keys, cover, tri_of, &tris, &ntri,
+                            &tcap)) {
         free(keys); free(tri_of); free(tris); return -1;
       }
       continue;
@@ -799,8 +856,11 @@ int oracle_render_image_box(int32_t n, const uint8_t* type, const float* size, c
         const float* nv[3] = {nvw[0], nvw[1], nvw[2]};
         float al[3];
         for (int c = 0; c < 3; ++c) al[c] = rp->palette[3 * albedo[b] + c];
-        if (smooth_tri_raster(wv[0], wv[1], wv[2], nv, al, prim, vp, W, H, rp, keys, cover, tri_of, &tris, &ntri,
-                              &tcap)) {
+        /* cube and box faces are textured over the face's unit square */
+        float fuv[6];
+        if (type[b]) oracle_cube_face_uv(rp, f, fuv);
+        if (smooth_tri_raster(wv[0], wv[1], wv[2], nv, al, (rp->texture && type[b]) ? fuv : NULL, prim, vp, W, H,
+                              rp, keys, cover, tri_of, &tris, &ntri, &tcap)) {
           free(keys); free(tri_of); free(tris); return -1;
         }
         continue;
@@ -849,6 +909,14 @@ int oracle_render_image_box(int32_t n, const uint8_t* type, const float* size, c
                            nn);
       nrm = mk(nn[0], nn[1], nn[2]);
       for (int c = 0; c < 3; ++c) alb[c] = st->alb[c];
+      if (st->textured) {
+        /* the albedo times the texel at the pixel's coordinates */
+        float uv[2], t[3];
+        oracle_smooth_uv(st->X, st->Y, st->iw, &st->uv[0][0], (int32_t)(i % (size_t)W), (int32_t)(i / (size_t)W),
+                         uv);
+        texel_at(rp, uv[0], uv[1], t);
+        for (int c = 0; c < 3; ++c) alb[c] = alb[c] * t[c];
+      }
     }
     float l = fmaxf(0.0f, dot(nrm, L));
     for (int c = 0; c < 3; ++c) {

@@ -68,6 +68,15 @@ typedef struct {
   int32_t smooth;    /* nonzero: Lambert shading per pixel of the normal
                         interpolated perspective-correctly from the
                         triangle's vertex normals (not with near_clip) */
+  /* Texture (smooth shading only; NULL: none): RGB8 texels [tex_h][tex_w][3].
+   * The ground takes texture coordinates (x, y) * ground_uv_scale of its
+   * world vertices; a cube or box face takes the unit square over its two
+   * tangent axes of the body frame; spheres are not textured.  A textured
+   * pixel's albedo is multiplied by its texel (nearest, repeat wrap) / 255
+   * at the perspective-correct coordinates (oracle_smooth_uv). */
+  const uint8_t* texture;
+  int32_t tex_w, tex_h;
+  float ground_uv_scale;
 } oracle_render_params;
 
 /* One contact point as the narrowphase reports it. */
@@ -139,6 +148,19 @@ int oracle_render_image(int32_t n, const uint8_t* type, const float* size,
  * weighted sum vanishes. */
 void oracle_smooth_normal(const int32_t* X, const int32_t* Y, const float* iw, const float* n, int32_t px,
                           int32_t py, float* out);
+
+/* Texture coordinates at the centre of pixel (px, py) of a triangle (setup
+ * order, 1 / clip w and (u, v) per vertex, uv[3][2]) interpolated
+ * perspective-correctly: the weights E_k / w_k normalized by their sum;
+ * (0, 0) if the sum is not positive. */
+void oracle_smooth_uv(const int32_t* X, const int32_t* Y, const float* iw, const float* uv, int32_t px,
+                      int32_t py, float* out);
+
+/* The face-corner texture coordinates of face f of the cube template
+ * (corner k of the face in face order): the corner's template coordinates
+ * on the two tangent axes of the face normal (y, z for x faces; x, z for y
+ * faces; x, y for z faces), mapped from [-1, 1] to [0, 1]. */
+void oracle_cube_face_uv(const oracle_render_params* rp, int32_t f, float* uv);
 
 int oracle_render_image_box(int32_t n, const uint8_t* type, const float* size, const float* ext,
                             const uint8_t* albedo, const float* pos, const float* quat,

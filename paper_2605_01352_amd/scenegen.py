@@ -32,7 +32,7 @@ CUBE = 1
 BOX = 2
 
 # random streams per env
-ST_SHAPE, ST_POS, ST_ROT, ST_CAM, ST_COUNT, ST_RES, ST_BOX = 0, 1, 2, 3, 4, 5, 6
+ST_SHAPE, ST_POS, ST_ROT, ST_CAM, ST_COUNT, ST_RES, ST_BOX, ST_TEX = 0, 1, 2, 3, 4, 5, 6, 7
 
 
 def mix64(z: np.ndarray) -> np.ndarray:
@@ -266,6 +266,9 @@ class Scene:
     edge_contacts: bool = False  # box-box edge-edge points (separating-axis test)
     near_clip: bool = False  # cut triangles crossing the near plane instead of culling them
     smooth: bool = False  # per-pixel Lambert shading of the interpolated vertex normal
+    # texture (with smooth): RGB8 texels [h, w, 3] on the ground and on cube and box faces
+    texture: Optional[np.ndarray] = None
+    ground_uv_scale: float = 1.0  # texture repeats per metre of ground
     # boxes (type 2): half-extents and principal moments of inertia, body frame
     ext: Optional[np.ndarray] = None      # f32 [B,3] (rows of other bodies unused)
     inertia: Optional[np.ndarray] = None  # f32 [B,3]
@@ -593,6 +596,26 @@ def with_boxes(scene: Scene, every: int = 2, seed: int = 2029) -> Scene:
     rb[cubes] = (np.linalg.norm(ext[cubes], axis=1) * (1.0 + 1e-6)).astype(np.float32)
     return dataclasses.replace(scene, btype=btype, rbound=rb, ext=ext.astype(np.float32),
                                inertia=inertia.astype(np.float32), name=scene.name + "+boxes")
+
+
+def procedural_texture(w: int = 32, h: int = 32, seed: int = 2031) -> np.ndarray:
+    """A seeded RGB8 texture [h, w, 3]: a checkerboard of 4x4-texel cells in
+    two tones with per-texel noise, so that any texel off by one is seen."""
+    i = np.arange(w)[None, :]
+    j = np.arange(h)[:, None]
+    check = ((i // 4 + j // 4) % 2).astype(np.float64)
+    key = stream_key(seed, np.arange(h * w, dtype=np.uint64), ST_TEX)
+    noise = np.stack([draw_unit(key, np.full(h * w, c, np.uint64)) for c in range(3)], 1).reshape(h, w, 3)
+    base = np.where(check[..., None] > 0, [[[0.95, 0.85, 0.55]]], [[[0.35, 0.45, 0.75]]])
+    return np.clip(np.rint(255.0 * (0.8 * base + 0.2 * noise)), 0, 255).astype(np.uint8)
+
+
+def with_texture(scene: Scene, texture: Optional[np.ndarray] = None, ground_uv_scale: float = 2.0) -> Scene:
+    """The scene rendered textured: smooth shading, the given (or the
+    procedural) texture on the ground and on cube and box faces."""
+    tex = procedural_texture() if texture is None else np.ascontiguousarray(texture, np.uint8)
+    return dataclasses.replace(scene, smooth=True, texture=tex, ground_uv_scale=float(ground_uv_scale),
+                               name=scene.name + "+texture")
 
 
 @dataclasses.dataclass

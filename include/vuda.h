@@ -84,6 +84,21 @@ extern "C" {
                                   the face normal, the ground's +z.  Winners,
                                   depth and coverage are those of flat shading.
                                   Not with VUDA_FLAG_NEAR_CLIP (VUDA_EINVAL)     */
+#define VUDA_FLAG_TEXTURE 8u   /* with VUDA_FLAG_SMOOTH: the render description's
+                                  texture on the ground and on cube and box
+                                  faces.  A textured pixel's albedo is multiplied
+                                  by the texel (nearest, repeating) / 255 at the
+                                  pixel centre's texture coordinates, interpolated
+                                  with the same perspective-correct weights
+                                  E_k / w_k normalized by their sum.  The ground's
+                                  coordinates are its world (x, y) times
+                                  ground_uv_scale; a cube or box face spans the
+                                  unit square over its two tangent axes of the
+                                  body frame (y, z for x faces; x, z for y faces;
+                                  x, y for z faces, each mapped from [-1, 1]);
+                                  spheres are not textured.  Without
+                                  VUDA_FLAG_SMOOTH, or without a valid texture:
+                                  VUDA_EINVAL                                   */
 
 typedef struct vuda_world vuda_world;
 
@@ -144,6 +159,12 @@ typedef struct {
   float ground_albedo;
   float near_w;          /* triangles with a vertex at clip w < near_w are culled */
   float guard;           /* ... or with |screen coordinate| > guard (pixels)      */
+  /* VUDA_FLAG_TEXTURE only (else ignored): RGB8 texels [texture_h][texture_w][3],
+   * row-major, copied at creation; 1 <= texture_w, texture_h <= 4096;
+   * ground_uv_scale: texture repeats per metre of ground (finite) */
+  const uint8_t* texture;
+  int32_t texture_w, texture_h;
+  float ground_uv_scale;
 } vuda_render_desc;
 
 /*

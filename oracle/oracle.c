@@ -691,6 +691,8 @@ void oracle_cube_face_uv(const oracle_render_params* rp, int32_t f, float* uv) {
  * the texture repeating in both directions; its RGB / 255. */
 static void texel_at(const oracle_render_params* rp, float U, float V, float* t) {
   float fu = U - floorf(U), fv = V - floorf(V);
+  if (!(fu >= 0.0f)) fu = 0.0f; /* not a number (coordinates beyond float range) */
+  if (!(fv >= 0.0f)) fv = 0.0f;
   int32_t i = (int32_t)(fu * (float)rp->tex_w), j = (int32_t)(fv * (float)rp->tex_h);
   if (i > rp->tex_w - 1) i = rp->tex_w - 1;
   if (j > rp->tex_h - 1) j = rp->tex_h - 1;

@@ -463,8 +463,8 @@ __device__ __forceinline__ float4 vertex_clip(const Templates* T, const BodyLDS&
 // and the reciprocal clip w of each vertex in edge order (face vertices 0, 2,
 // 1), and the albedo.  A sphere's vertex normal is its unit template vertex
 // turned by R, a cube's or box's the face normal, the ground's +z.
-__device__ __forceinline__ void store_attr(float4* ga, int r, const Templates* T, const BodyLDS& B, int S,
-                                           const uint8_t* gvmap, int body, int face, const int vid[3],
+__device__ __forceinline__ void store_attr(float4* ga, float4* gt, int r, const Templates* T, const BodyLDS& B,
+                                           int S, const uint8_t* gvmap, int body, int face, const int vid[3],
                                            const float* vp) {
   const int ord[3] = {0, 2, 1};
   float n[3][3], iw[3], al[3];
@@ -497,6 +497,35 @@ __device__ __forceinline__ void store_attr(float4* ga, int r, const Templates* T
   p[1] = make_float4(n[1][1], n[1][2], n[2][0], n[2][1]);
   p[2] = make_float4(n[2][2], iw[0], iw[1], iw[2]);
   p[3] = make_float4(al[0], al[1], al[2], 0.0f);
+  if (!gt) return;
+  // textured worlds: the texture coordinates of the vertices in edge order
+  // (the ground: world x, y scaled; a cube or box face: the unit square over
+  // the face's tangent axes of the body frame) and whether to sample
+  float uv[3][2] = {{0.0f, 0.0f}, {0.0f, 0.0f}, {0.0f, 0.0f}};
+  float textured = 0.0f;
+  if (body < 0) {
+    textured = 1.0f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int v = vid[ord[k]];
+      uv[k][0] = T->ground_v[v][0] * T->ground_uv_scale;
+      uv[k][1] = T->ground_v[v][1] * T->ground_uv_scale;
+    }
+  } else if (B.type[body]) {
+    textured = 1.0f;
+    const float* fn = T->cube_n[face];
+    const int a = fabsf(fn[0]) > 0.5f ? 0 : (fabsf(fn[1]) > 0.5f ? 1 : 2);
+    const int t0 = a == 0 ? 1 : 0, t1 = a == 2 ? 1 : 2;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float* tv = T->cube_v[vid[ord[k]] - B.vb[body]];
+      uv[k][0] = (tv[t0] + 1.0f) * 0.5f;
+      uv[k][1] = (tv[t1] + 1.0f) * 0.5f;
+    }
+  }
+  float4* q = gt + 2 * r;
+  q[0] = make_float4(uv[0][0], uv[0][1], uv[1][0], uv[1][1]);
+  q[1] = make_float4(uv[2][0], uv[2][1], textured, 0.0f);
 }
 
 // CLIP: cut triangles crossing the near plane (else they are culled whole,
@@ -759,7 +788,8 @@ __device__ void setup_image(unsigned char* lds, const SetupLayout& Lo, const Wor
         // the key carries the record instead of a colour; the pixel's colour
         // comes from the record's attributes in the tile kernel
         rgb = (uint32_t)r;
-        store_attr((float4*)(rs + cam.rs_attr), r, T, B, Lo.nmax, gvmap, body, face, vid, vp);
+        store_attr((float4*)(rs + cam.rs_attr), W.texture ? (float4*)(rs + cam.rs_tuv) : nullptr, r, T, B,
+                   Lo.nmax, gvmap, body, face, vid, vp);
       } else {
         rgb = face_color(T, B, Lo.nmax, body, face);
       }
@@ -899,8 +929,8 @@ __device__ __forceinline__ uint64_t depth_key(float e0, float e1, float e2, floa
 // Smooth shading of pixel (px, py) won by record r: the attribute record's
 // vertex normals interpolated with weights E_k / w_k at the pixel centre
 // (exact edge values), normalized, and Lambert-shaded; RGB8 packed.
-__device__ __forceinline__ uint32_t smooth_color(const int4* grec, const float4* gattr, const Templates* T, int r,
-                                                 int px, int py) {
+__device__ __forceinline__ uint32_t smooth_color(const int4* grec, const float4* gattr, const float4* gtuv,
+                                                 const uint8_t* tex, const Templates* T, int r, int px, int py) {
   const int4 a = grec[4 * r], b = grec[4 * r + 1];
   const float4 g0 = gattr[4 * r], g1 = gattr[4 * r + 1], g2 = gattr[4 * r + 2], g3 = gattr[4 * r + 3];
   const int32_t X[3] = {a.x, a.z, b.x}, Y[3] = {a.y, a.w, b.y};
@@ -926,7 +956,28 @@ __device__ __forceinline__ uint32_t smooth_color(const int4* grec, const float4*
     nz = mz / l;
   }
   const float lam = fmaxf(0.0f, (nx * T->light[0] + ny * T->light[1]) + nz * T->light[2]);
-  const float al[3] = {g3.x, g3.y, g3.z};
+  float al[3] = {g3.x, g3.y, g3.z};
+  if (gtuv) {
+    // textured worlds: the albedo times the texel (nearest, repeating) at
+    // the texture coordinates interpolated with the weights above
+    const float4 t0 = gtuv[2 * r], t1 = gtuv[2 * r + 1];
+    if (t1.z != 0.0f) {
+      const float s = (u[0] + u[1]) + u[2];
+      float U = 0.0f, V = 0.0f;
+      if (s > 0.0f) {
+        U = ((u[0] * t0.x + u[1] * t0.z) + u[2] * t1.x) / s;
+        V = ((u[0] * t0.y + u[1] * t0.w) + u[2] * t1.y) / s;
+      }
+      float fu = U - floorf(U), fv = V - floorf(V);
+      if (!(fu >= 0.0f)) fu = 0.0f;
+      if (!(fv >= 0.0f)) fv = 0.0f;
+      const int i = min((int)(fu * (float)T->tex_w), T->tex_w - 1);
+      const int j = min((int)(fv * (float)T->tex_h), T->tex_h - 1);
+      const uint8_t* p = tex + 3 * ((int64_t)j * T->tex_w + i);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) al[c] = al[c] * ((float)p[c] / 255.0f);
+    }
+  }
   uint32_t rgb = 0;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -1187,7 +1238,9 @@ __device__ __forceinline__ void raster_tile(const WorldDev& W, const CamDev& cam
       if constexpr (SMOOTH) {
         // the key's low bits name the winning record
         if (hit)
-          rgb[i] = smooth_color(src.rec, (const float4*)(rs + cam.rs_attr), W.tpl, (int)rgb[i], px0 + i, py);
+          rgb[i] = smooth_color(src.rec, (const float4*)(rs + cam.rs_attr),
+                                W.texture ? (const float4*)(rs + cam.rs_tuv) : nullptr, W.texture, W.tpl,
+                                (int)rgb[i], px0 + i, py);
       }
     }
     if (py > ty1) continue;
@@ -1258,6 +1311,7 @@ __global__ void __launch_bounds__(64 * TW) raster_tile_kernel(WorldDev W, Raster
   cam.rs_bins = uniform_ld(&cp->rs_bins);
   cam.rs_total = uniform_ld(&cp->rs_total);
   cam.rs_attr = uniform_ld(&cp->rs_attr);
+  cam.rs_tuv = uniform_ld(&cp->rs_tuv);
   const int ntx = (cam.w + TS - 1) / TS;
   const int tx = (job.y & 0xFFFF) + wave, ty = job.y >> 16;
   const unsigned char* rs = W.rscratch + cam.rs_off + (int64_t)L.parity * cam.rs_total;

@@ -77,6 +77,7 @@ struct CamDev {
   int64_t rs_off;     // byte offset of the image's raster scratch (two layouts, one per state buffer)
   int32_t rs_recs, rs_bins, rs_total;  // rs_layout(n_tris, tiles): offsets and size of one layout
   int32_t rs_attr;                     // smooth shading: the attribute records
+  int32_t rs_tuv;                      // textured worlds: the texture-coordinate records
 };
 
 // Raster scratch of one camera image and state buffer (two per camera, one
@@ -96,21 +97,27 @@ constexpr int kClipRecs = 64;   // records an image keeps for pieces of triangle
 // the albedo (3).
 constexpr int kAttrWords = 16;
 
+// Textured worlds: per record the texture coordinates of its vertices in
+// edge order (6 floats) and a flag (1: textured), padded to 8 floats.
+constexpr int kTuvWords = 8;
+
 struct RsLayout {
-  int64_t tiles, recs, bins, attr, total;
+  int64_t tiles, recs, bins, attr, tuv, total;
   int32_t bin_cap;
 };
 
 __host__ __device__ inline int64_t rs_align(int64_t x) { return (x + 255) & ~(int64_t)255; }
 
-__host__ __device__ inline RsLayout rs_layout(int32_t ntris, int32_t ntiles, bool smooth = false) {
+__host__ __device__ inline RsLayout rs_layout(int32_t ntris, int32_t ntiles, bool smooth = false,
+                                              bool textured = false) {
   RsLayout r;
   r.tiles = 64;
   r.recs = rs_align(64 + 8 * (int64_t)ntiles);
   r.bins = r.recs + rs_align((int64_t)kRecBytes * (ntris + kClipRecs));
   r.bin_cap = kBinsPerTri * (ntris + kClipRecs);
   r.attr = r.bins + rs_align(2 * (int64_t)r.bin_cap);
-  r.total = r.attr + (smooth ? rs_align((int64_t)4 * kAttrWords * (ntris + kClipRecs)) : 0);
+  r.tuv = r.attr + (smooth ? rs_align((int64_t)4 * kAttrWords * (ntris + kClipRecs)) : 0);
+  r.total = r.tuv + (textured ? rs_align((int64_t)4 * kTuvWords * (ntris + kClipRecs)) : 0);
   return r;
 }
 
@@ -136,6 +143,10 @@ struct alignas(16) Templates {
   float ground_albedo;
   float near_w;
   float guard;
+  // textured worlds: texture size (0: untextured) and the ground's texture
+  // repeats per metre
+  int32_t tex_w, tex_h;
+  float ground_uv_scale;
 };
 
 struct PhysConsts {
@@ -177,6 +188,7 @@ struct WorldDev {
   int32_t pair_cap;
   uint32_t* env_flags;
   const Templates* tpl;
+  const uint8_t* texture;   // textured worlds: RGB8 texels [tex_h][tex_w][3]; nullptr: none
   unsigned char* rscratch;  // raster scratch of every camera (CamDev::rs_off)
   // policy actions: per env act_dim floats, the force on body b in
   // [3b, 3b + 3); act_on[env] != 0 once the policy has acted on the env

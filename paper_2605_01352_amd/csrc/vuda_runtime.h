@@ -137,6 +137,7 @@ struct vuda_world {
   bool debug = false;
   bool near_clip = false;  // VUDA_FLAG_NEAR_CLIP
   bool smooth = false;     // VUDA_FLAG_SMOOTH
+  bool textured = false;   // VUDA_FLAG_TEXTURE
   int32_t pair_cap = 1024;
   int32_t cap_envs = 0, cap_cams = 0;
   int64_t cap_bodies = 0, cap_pixels = 0;
@@ -150,7 +151,7 @@ struct vuda_world {
   bool has_allocator = false;
   struct {
     size_t envs, cams, type, albedo, size, rbound, inv_m, inv_I, box, prim_base, vert_base, prim_body, vert_body, state0,
-        state1, rgb, depth, flags, tpl, queues, winners, coverage, contacts, rs;
+        state1, rgb, depth, flags, tpl, texture, queues, winners, coverage, contacts, rs;
   } off_{};
   vuda::WorldDev dev{};
   int32_t* queues = nullptr;

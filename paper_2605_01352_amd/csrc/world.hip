@@ -210,6 +210,8 @@ static void fill_templates(Templates& t, const vuda_render_desc& r) {
   t.ground_albedo = r.ground_albedo;
   t.near_w = r.near_w;
   t.guard = r.guard;
+  t.tex_w = t.tex_h = 0;
+  t.ground_uv_scale = r.ground_uv_scale;
 }
 
 // ---------------------------------------------------------------------------
@@ -246,6 +248,7 @@ int vuda_world::alloc_arena(const vuda_allocator* a) {
   off_.depth = take(4 * P);
   off_.flags = take(4 * E + 4);
   off_.tpl = take(sizeof(Templates));
+  off_.texture = take(textured ? 3 * (size_t)tpl.tex_w * (size_t)tpl.tex_h : 0);
   off_.queues = take(64);
   off_.rs = take(256 * (size_t)std::max<int64_t>(cap_rs, 1));
   if (debug) {
@@ -292,6 +295,7 @@ int vuda_world::alloc_arena(const vuda_allocator* a) {
   dev.depth = (uint32_t*)(arena + off_.depth);
   dev.env_flags = (uint32_t*)(arena + off_.flags);
   dev.tpl = (const Templates*)(arena + off_.tpl);
+  dev.texture = textured ? arena + off_.texture : nullptr;
   dev.rscratch = arena + off_.rs;
   queues = (int32_t*)(arena + off_.queues);
   dev.winners = debug ? (int32_t*)(arena + off_.winners) : nullptr;
@@ -334,7 +338,7 @@ int64_t vuda_world::rs_units(const vuda_env_batch& b) const {
   for (int32_t e = 0; e < b.n_envs; ++e) {
     const int32_t nt = env_tris(b, e);
     for (int32_t c = b.cam_off[e]; c < b.cam_off[e + 1]; ++c)
-      u += 2 * (rs_layout(nt, tiles_of(b.cam_w[c], b.cam_h[c], kTileShiftMin), smooth).total / 256);
+      u += 2 * (rs_layout(nt, tiles_of(b.cam_w[c], b.cam_h[c], kTileShiftMin), smooth, textured).total / 256);
   }
   return u;
 }
@@ -386,11 +390,12 @@ int vuda_world::upload(const vuda_env_batch& b, int32_t e0, int64_t b0, int32_t 
       d.n_tris = nt;
       d.rs_off = ro;
       // the tile table has room for the smallest tiles
-      const RsLayout rl = rs_layout(nt, tiles_of(d.w, d.h, kTileShiftMin), smooth);
+      const RsLayout rl = rs_layout(nt, tiles_of(d.w, d.h, kTileShiftMin), smooth, textured);
       d.rs_recs = (int32_t)rl.recs;
       d.rs_bins = (int32_t)rl.bins;
       d.rs_total = (int32_t)rl.total;
       d.rs_attr = (int32_t)rl.attr;
+      d.rs_tuv = (int32_t)rl.tuv;
       po += (int64_t)d.w * d.h;
       ro += 2 * rl.total;
     }
@@ -467,6 +472,14 @@ extern "C" int vuda_create_world(const vuda_world_desc* d, const vuda_allocator*
   if (rc) return rc;
   if ((d->flags & VUDA_FLAG_SMOOTH) && (d->flags & VUDA_FLAG_NEAR_CLIP))
     return fail(VUDA_EINVAL, "VUDA_FLAG_SMOOTH does not combine with VUDA_FLAG_NEAR_CLIP");
+  if (d->flags & VUDA_FLAG_TEXTURE) {
+    if (!(d->flags & VUDA_FLAG_SMOOTH)) return fail(VUDA_EINVAL, "VUDA_FLAG_TEXTURE needs VUDA_FLAG_SMOOTH");
+    const vuda_render_desc& r = d->render;
+    if (!r.texture || r.texture_w < 1 || r.texture_w > 4096 || r.texture_h < 1 || r.texture_h > 4096)
+      return fail(VUDA_EINVAL, "texture %p of %d x %d texels", (const void*)r.texture, (int)r.texture_w,
+                  (int)r.texture_h);
+    if (!std::isfinite(r.ground_uv_scale)) return fail(VUDA_EINVAL, "ground_uv_scale %g", r.ground_uv_scale);
+  }
   vuda_world* w = new (std::nothrow) vuda_world();
   if (!w) return fail(VUDA_ENOMEM, "host allocation");
   HIPCHK(hipGetDevice(&w->device));
@@ -474,6 +487,7 @@ extern "C" int vuda_create_world(const vuda_world_desc* d, const vuda_allocator*
   w->debug = (d->flags & VUDA_FLAG_DEBUG) != 0;
   w->near_clip = (d->flags & VUDA_FLAG_NEAR_CLIP) != 0;
   w->smooth = (d->flags & VUDA_FLAG_SMOOTH) != 0;
+  w->textured = (d->flags & VUDA_FLAG_TEXTURE) != 0;
   w->pair_cap = d->pair_cap > 0 ? d->pair_cap : 1024;
   w->cap_envs = std::max(d->cap_envs, d->initial.n_envs);
   w->cap_bodies = std::max(d->cap_bodies, nb);
@@ -481,6 +495,10 @@ extern "C" int vuda_create_world(const vuda_world_desc* d, const vuda_allocator*
   w->cap_pixels = std::max(d->cap_pixels, npix);
   w->hbm_budget = d->hbm_budget;
   fill_templates(w->tpl, d->render);
+  if (w->textured) {
+    w->tpl.tex_w = d->render.texture_w;
+    w->tpl.tex_h = d->render.texture_h;
+  }
   int64_t init_prims = 0, init_verts = 0;
   w->map_sizes(d->initial, &init_prims, &init_verts);
   {
@@ -490,17 +508,20 @@ extern "C" int vuda_create_world(const vuda_world_desc* d, const vuda_allocator*
     const int64_t spare_b = w->cap_bodies - nb, spare_e = (int64_t)w->cap_envs - d->initial.n_envs;
     w->cap_prims = init_prims + spare_b * mf + spare_e * (w->tpl.ground_nf + 15);
     w->cap_verts = init_verts + spare_b * mv + spare_e * (w->tpl.ground_nv + 15);
-    // raster scratch of cameras admitted later.  Per camera and state buffer it is at most
-    // (kRecBytes + 2 kBinsPerTri) (n_tris + kClipRecs) + 8 tiles + 829 bytes, and a camera
-    // of W x H pixels has at most W H / 256 + 513 tiles; envs are assumed to
-    // carry no more cameras each than the initial batch's most (at least 1).
+    // raster scratch of cameras admitted later.  Per camera and state buffer
+    // (rs_layout) it is at most per_prim (n_tris + kClipRecs) + 8 tiles + 64
+    // bytes + 255 of alignment per region, and a camera of W x H pixels
+    // (W, H <= 4096) has at most W H / 64 + 1025 tiles of the smallest edge;
+    // envs are assumed to carry no more cameras each than the initial
+    // batch's most (at least 1).
     int32_t kcam = 1;
     for (int32_t e = 0; e < d->initial.n_envs; ++e)
       kcam = std::max(kcam, d->initial.cam_off[e + 1] - d->initial.cam_off[e]);
+    const int64_t per_prim = kRecBytes + 2 * kBinsPerTri + (w->smooth ? 4 * kAttrWords : 0) +
+                             (w->textured ? 4 * kTuvWords : 0);
     const int64_t spare_c = (int64_t)w->cap_cams - nc, spare_p = w->cap_pixels - npix;
-    const int64_t spare_bytes = 2 * ((int64_t)(kRecBytes + 2 * kBinsPerTri) * kcam * (w->cap_prims - init_prims) +
-                                     spare_p / 32 +
-                                     (829 + 8 * 513 + (int64_t)(kRecBytes + 2 * kBinsPerTri) * kClipRecs) * spare_c);
+    const int64_t spare_bytes = 2 * (per_prim * kcam * (w->cap_prims - init_prims) + spare_p / 8 +
+                                     (64 + 5 * 255 + 8 * 1025 + per_prim * kClipRecs) * spare_c);
     w->cap_rs = w->rs_units(d->initial) + (spare_bytes + 255) / 256;
   }
   w->pc.h = d->phys.dt / (float)d->phys.substeps;
@@ -543,6 +564,11 @@ extern "C" int vuda_create_world(const vuda_world_desc* d, const vuda_allocator*
   if (rc == VUDA_OK) {
     hipError_t e = hipMemcpy((void*)w->dev.tpl, &w->tpl, sizeof(Templates), hipMemcpyHostToDevice);
     if (e != hipSuccess) rc = hip_fail(e, "template upload");
+  }
+  if (rc == VUDA_OK && w->textured) {
+    hipError_t e = hipMemcpy((void*)w->dev.texture, d->render.texture,
+                             3 * (size_t)w->tpl.tex_w * (size_t)w->tpl.tex_h, hipMemcpyHostToDevice);
+    if (e != hipSuccess) rc = hip_fail(e, "texture upload");
   }
   if (rc == VUDA_OK && d->initial.n_envs > 0) {
     w->slots.take(0, d->initial.n_envs);
@@ -1868,7 +1894,8 @@ extern "C" int vuda_release(vuda_world* w, int32_t first, int32_t n) {
     p0 = c0.pix_off;
     np = c1.pix_off + (int64_t)c1.w * c1.h - p0;
     r0 = c0.rs_off / 256;
-    nr = (c1.rs_off + 2 * rs_layout(c1.n_tris, tiles_of(c1.w, c1.h, kTileShiftMin), w->smooth).total) / 256 - r0;
+    nr = (c1.rs_off + 2 * rs_layout(c1.n_tris, tiles_of(c1.w, c1.h, kTileShiftMin), w->smooth, w->textured).total) /
+             256 - r0;
   }
   std::vector<EnvDev> empty(n, EnvDev{});
   HIPCHK(hipMemcpy(w->dev.envs + first, empty.data(), sizeof(EnvDev) * n, hipMemcpyHostToDevice));

@@ -25,6 +25,7 @@ FETCH_STATE, FETCH_RGB, FETCH_DEPTH, FETCH_CONTACTS, FETCH_WINNERS, FETCH_COVERA
 FLAG_DEBUG = 1
 FLAG_NEAR_CLIP = 2
 FLAG_SMOOTH = 4
+FLAG_TEXTURE = 8
 TUNE_RASTER_THREADS, TUNE_REC_CAP, TUNE_PHYS_PERSISTENT, TUNE_RASTER_PERSISTENT, TUNE_GRAPHS = 1, 2, 3, 4, 5
 PERSISTENT_RESIDENT = -1  # persistent grid of the workgroups the GPU holds at once
 TUNE_PHYS_PRIORITY = 6
@@ -76,7 +77,9 @@ class RenderDesc(C.Structure):
         ("ground_v", C.c_void_p), ("ground_nv", C.c_int32), ("ground_f", C.c_void_p),
         ("ground_nf", C.c_int32),
         ("light", C.c_float * 3), ("palette", C.c_float * 24), ("ground_albedo", C.c_float),
-        ("near_w", C.c_float), ("guard", C.c_float)]
+        ("near_w", C.c_float), ("guard", C.c_float),
+        ("texture", C.c_void_p), ("texture_w", C.c_int32), ("texture_h", C.c_int32),
+        ("ground_uv_scale", C.c_float)]
 
 
 class EnvBatch(C.Structure):
@@ -201,7 +204,8 @@ class _Keep:
         return a
 
 
-def render_desc(keep: _Keep, light=None, palette=None, ground_albedo=None, near=None, guard=None):
+def render_desc(keep: _Keep, light=None, palette=None, ground_albedo=None, near=None, guard=None, texture=None,
+                ground_uv_scale=1.0):
     from . import scenegen as sg
     t = sg.templates()
     sv, sf, sn = keep(t.sphere_v, np.float32), keep(t.sphere_f, np.int32), keep(t.sphere_n, np.float32)
@@ -215,7 +219,10 @@ def render_desc(keep: _Keep, light=None, palette=None, ground_albedo=None, near=
         (C.c_float * 3)(*np.asarray(light, np.float32).tolist()),
         (C.c_float * 24)(*np.asarray(palette, np.float32).reshape(-1).tolist()),
         float(sg.GROUND_ALBEDO if ground_albedo is None else ground_albedo),
-        float(sg.NEAR if near is None else near), float(sg.GUARD_BAND if guard is None else guard))
+        float(sg.NEAR if near is None else near), float(sg.GUARD_BAND if guard is None else guard),
+        None if texture is None else _p(keep(texture, np.uint8)),
+        0 if texture is None else int(np.shape(texture)[1]), 0 if texture is None else int(np.shape(texture)[0]),
+        float(np.float32(ground_uv_scale)))
 
 
 def env_batch(keep: _Keep, scene, state: Optional[Dict[str, np.ndarray]] = None) -> EnvBatch:
@@ -271,10 +278,15 @@ class World:
         desc = WorldDesc()
         desc.phys = PhysParams(float(np.float32(dt)), int(sub), float(k), float(c),
                                (C.c_float * 3)(*[float(x) for x in g]), float(mu), float(v_eps), int(edge))
-        desc.render = render_desc(keep, **(render_kw or {}))
+        rkw = dict(render_kw or {})
+        if getattr(ref, "texture", None) is not None:
+            rkw.setdefault("texture", ref.texture)
+            rkw.setdefault("ground_uv_scale", getattr(ref, "ground_uv_scale", 1.0))
+        desc.render = render_desc(keep, **rkw)
         desc.initial = env_batch(keep, scene) if scene is not None else EnvBatch(0)
         desc.flags = (FLAG_DEBUG if debug else 0) | (FLAG_NEAR_CLIP if getattr(ref, "near_clip", False) else 0) | \
-            (FLAG_SMOOTH if getattr(ref, "smooth", False) else 0)
+            (FLAG_SMOOTH if getattr(ref, "smooth", False) else 0) | \
+            (FLAG_TEXTURE if getattr(ref, "texture", None) is not None else 0)
         desc.cap_envs, desc.cap_bodies, desc.cap_cams, desc.cap_pixels = cap_envs, cap_bodies, cap_cams, cap_pixels
         desc.pair_cap = pair_cap
         desc.hbm_budget = hbm_budget
@@ -484,10 +496,11 @@ def world_desc(keep: _Keep, scene=None, debug: bool = False, cap_envs: int = 0, 
     d = WorldDesc()
     d.phys = PhysParams(float(np.float32(dt)), int(sub), float(k), float(c),
                         (C.c_float * 3)(*[float(x) for x in g]), float(mu), float(v_eps), int(edge))
-    d.render = render_desc(keep)
+    tex = getattr(scene, "texture", None)
+    d.render = render_desc(keep, texture=tex, ground_uv_scale=getattr(scene, "ground_uv_scale", 1.0))
     d.initial = env_batch(keep, scene) if scene is not None else EnvBatch(0)
     d.flags = (FLAG_DEBUG if debug else 0) | (FLAG_NEAR_CLIP if getattr(scene, "near_clip", False) else 0) | \
-        (FLAG_SMOOTH if getattr(scene, "smooth", False) else 0)
+        (FLAG_SMOOTH if getattr(scene, "smooth", False) else 0) | (FLAG_TEXTURE if tex is not None else 0)
     d.cap_envs, d.cap_bodies, d.cap_cams, d.cap_pixels = cap_envs, cap_bodies, cap_cams, cap_pixels
     d.pair_cap = pair_cap
     d.hbm_budget = hbm_budget

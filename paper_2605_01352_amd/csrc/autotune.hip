@@ -93,8 +93,10 @@ int restore_snapshot(vuda_world* w, const Snapshot& s) {
   w->env_parity = s.parity;
   std::fill(w->setup_ok.begin(), w->setup_ok.end(), 0);  // the scratch may hold another state's setup
   std::fill(w->step_ev.begin(), w->step_ev.end(), -1);
-  std::fill(w->render_ev[0].begin(), w->render_ev[0].end(), -1);
-  std::fill(w->render_ev[1].begin(), w->render_ev[1].end(), -1);
+  for (int q = 0; q < 2; ++q) {
+    std::fill(w->render_ev[q].begin(), w->render_ev[q].end(), -1);
+    std::fill(w->render_state_ev[q].begin(), w->render_state_ev[q].end(), -1);
+  }
   return VUDA_OK;
 }
 

@@ -173,9 +173,12 @@ struct vuda_world {
   int mode = 0;
   float cu_split = 0.0f;
 
-  // dependency events per env: the last step, and the last render of each buffer
+  // dependency events per env: the last step, and the last render of each
+  // buffer; render_state_ev: the last render of each buffer whose kernels
+  // read the state buffer itself (its own raster setup, or the fused kernel)
   std::vector<int64_t> step_ev;
   std::vector<int64_t> render_ev[2];
+  std::vector<int64_t> render_state_ev[2];
   std::vector<hipEvent_t> evpool;
   int64_t next_event = 0;
 

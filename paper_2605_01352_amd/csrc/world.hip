@@ -548,6 +548,8 @@ extern "C" int vuda_create_world(const vuda_world_desc* d, const vuda_allocator*
   w->setup_ok.assign(w->cap_envs, 0);
   w->render_ev[0].assign(w->cap_envs, -1);
   w->render_ev[1].assign(w->cap_envs, -1);
+  w->render_state_ev[0].assign(w->cap_envs, -1);
+  w->render_state_ev[1].assign(w->cap_envs, -1);
   w->slots.init(w->cap_envs);
   w->bodies.init(w->cap_bodies);
   w->camslots.init(w->cap_cams);
@@ -750,8 +752,10 @@ extern "C" int vuda_cosched(vuda_world* w, float cu_split) {
   rc = w->make_streams(cu_split == 1.0f ? 0.0f : cu_split);
   // every earlier event has completed (drained): forget them
   std::fill(w->step_ev.begin(), w->step_ev.end(), -1);
-  std::fill(w->render_ev[0].begin(), w->render_ev[0].end(), -1);
-  std::fill(w->render_ev[1].begin(), w->render_ev[1].end(), -1);
+  for (int q = 0; q < 2; ++q) {
+    std::fill(w->render_ev[q].begin(), w->render_ev[q].end(), -1);
+    std::fill(w->render_state_ev[q].begin(), w->render_state_ev[q].end(), -1);
+  }
   return rc;
 }
 
@@ -1113,12 +1117,15 @@ extern "C" int vuda_step(vuda_world* w, int32_t lo, int32_t hi, int32_t nsteps) 
   for (int t = 0; t < nsteps; ++t) {
     const int p = (parity + t) & 1;
     if (w->mode != 0) {
-      // WAR: the renders that read the state buffer (and raster scratch)
-      // this step overwrites.  Earlier steps are on this same stream (RAW is
-      // implicit); events of one stream complete in order, so the latest one
-      // covers the others.
+      // WAR: the renders whose kernels read the state buffer this step
+      // overwrites (their own setup, or the fused kernel).  A render whose
+      // setup ran here with the step (presetup) has its tiles read only the
+      // raster scratch, so the step does not wait for them; the setup below,
+      // which rewrites that scratch, does.  Earlier steps are on this same
+      // stream (RAW is implicit); events of one stream complete in order, so
+      // the latest one covers the others.
       int64_t last = -1;
-      const int64_t* rev = w->render_ev[p ^ 1].data();
+      const int64_t* rev = w->render_state_ev[p ^ 1].data();
       for (int32_t e = lo; e < hi; ++e) last = rev[e] > last ? rev[e] : last;
       rc = w->wait_event(s, last);
       if (rc) return rc;
@@ -1126,6 +1133,14 @@ extern "C" int vuda_step(vuda_world* w, int32_t lo, int32_t hi, int32_t nsteps) 
     rc = w->run_kernel(kKernelPhysics, *L, p, lo, hi, s, w->queues);
     if (rc) return rc;
     if (LR && t == nsteps - 1) {
+      if (w->mode != 0) {
+        // WAR: the renders of this buffer read its raster scratch
+        int64_t last = -1;
+        const int64_t* rev = w->render_ev[p ^ 1].data();
+        for (int32_t e = lo; e < hi; ++e) last = rev[e] > last ? rev[e] : last;
+        rc = w->wait_event(s, last);
+        if (rc) return rc;
+      }
       rc = w->run_kernel(kKernelSetup, *LR, p ^ 1, lo, hi, s, w->queues + 1);
       if (rc) return rc;
     }
@@ -1168,9 +1183,15 @@ extern "C" int vuda_render(vuda_world* w, int32_t lo, int32_t hi) {
   size_t lds;
   rc = w->fused_launch_of(*L, parity, w->queues + 2, &rl, &lds);
   if (rc) return rc;
+  // the event after the last kernel of this render that reads the state
+  // buffer (the step that overwrites the buffer waits for it): the fused
+  // kernel, or the raster setup
+  int64_t state_id = -1;
+  bool reads_state = false;
   if (lds) {
     rc = w->run_kernel(kKernelFused, *L, parity, lo, hi, s, w->queues + 2);
     if (rc) return rc;
+    reads_state = true;
   } else {
     bool need_setup = false;
     for (int32_t e = lo; e < hi; ++e) need_setup |= w->env_active[e] && !w->setup_ok[e];
@@ -1178,6 +1199,10 @@ extern "C" int vuda_render(vuda_world* w, int32_t lo, int32_t hi) {
       rc = w->run_kernel(kKernelSetup, *L, parity, lo, hi, s, w->queues + 2);
       if (rc) return rc;
       for (int32_t e = lo; e < hi; ++e) w->setup_ok[e] = 1;
+      if (w->mode != 0) {
+        rc = w->new_event(s, &state_id);
+        if (rc) return rc;
+      }
     }
     rc = w->run_kernel(kKernelTiles, *L, parity, lo, hi, s, nullptr);
     if (rc) return rc;
@@ -1186,8 +1211,12 @@ extern "C" int vuda_render(vuda_world* w, int32_t lo, int32_t hi) {
     int64_t id;
     rc = w->new_event(s, &id);
     if (rc) return rc;
-    for (int32_t e = lo; e < hi; ++e)
-      if (w->env_active[e]) w->render_ev[parity][e] = id;
+    if (reads_state) state_id = id;
+    for (int32_t e = lo; e < hi; ++e) {
+      if (!w->env_active[e]) continue;
+      w->render_ev[parity][e] = id;
+      if (state_id >= 0) w->render_state_ev[parity][e] = state_id;
+    }
   }
   return VUDA_OK;
 }
@@ -1851,6 +1880,8 @@ extern "C" int vuda_admit(vuda_world* w, const vuda_env_batch* b, int32_t parity
     w->step_ev[e0 + e] = -1;
     w->render_ev[0][e0 + e] = -1;
     w->render_ev[1][e0 + e] = -1;
+    w->render_state_ev[0][e0 + e] = -1;
+    w->render_state_ev[1][e0 + e] = -1;
   }
   // a reused slot starts without the policy's forces of its last env
   if (w->act_on) HIPCHK(hipMemset(w->act_on + e0, 0, (size_t)b->n_envs));
@@ -2157,6 +2188,7 @@ static int run_pipelined(vuda_world* w, int32_t iters) {
     if (iters & 1) w->env_parity[e] ^= 1;
     w->step_ev[e] = sid;
     w->render_ev[0][e] = w->render_ev[1][e] = rid;
+    w->render_state_ev[0][e] = w->render_state_ev[1][e] = rid;
     w->setup_ok[e] = 1;
   }
   return VUDA_OK;

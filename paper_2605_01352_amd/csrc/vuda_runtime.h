@@ -216,6 +216,7 @@ struct vuda_world {
   int drain();
   int init_events();
   int new_event(hipStream_t s, int64_t* id);
+  int reserve_event(int64_t* id, hipEvent_t* ev);
   int wait_event(hipStream_t s, int64_t id);
   void invalidate_lists();
   int get_list(int phase, int32_t lo, int32_t hi, const vuda::WorkList** out);
@@ -231,7 +232,10 @@ struct vuda_world {
   int enqueue_kernel(int kind, const vuda::WorkList& L, int parity, hipStream_t s, int32_t* queue,
                      vuda::LaunchEvents* ev = nullptr);
   int run_kernel(int kind, const vuda::WorkList& L, int parity, int32_t lo, int32_t hi, hipStream_t s,
-                 int32_t* queue);
+                 int32_t* queue, hipEvent_t done = nullptr);
+  // the launch itself: direct, timed, or through a captured graph
+  int launch_kernel(int kind, const vuda::WorkList& L, int parity, int32_t lo, int32_t hi, hipStream_t s,
+                    int32_t* queue);
   hipStream_t capture_stream();
   int check_flags();
   int32_t active_midpoint();

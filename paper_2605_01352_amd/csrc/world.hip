@@ -770,15 +770,25 @@ int vuda_world::init_events() {
   return VUDA_OK;
 }
 
-int vuda_world::new_event(hipStream_t s, int64_t* id) {
+// An id of the pool and its event, for the caller to record (run_kernel can
+// bind it to the end of a launch instead of a separate record).
+int vuda_world::reserve_event(int64_t* id, hipEvent_t* ev) {
   const size_t kPool = 512;
   int rc = init_events();
   if (rc) return rc;
   const int64_t nid = next_event++;
   hipEvent_t e = evpool[nid % kPool];
   if (nid >= (int64_t)kPool) HIPCHK(hipEventSynchronize(e));
-  HIPCHK(hipEventRecord(e, s));
   *id = nid;
+  *ev = e;
+  return VUDA_OK;
+}
+
+int vuda_world::new_event(hipStream_t s, int64_t* id) {
+  hipEvent_t e;
+  int rc = reserve_event(id, &e);
+  if (rc) return rc;
+  HIPCHK(hipEventRecord(e, s));
   return VUDA_OK;
 }
 
@@ -1018,8 +1028,28 @@ int vuda_world::enqueue_kernel(int kind, const WorkList& L, int parity, hipStrea
 
 // Launch one kernel over a work list, through a captured graph when graph mode
 // is on, between timing events when timing is on.
+// done (optional): an event recorded when the launch has ended.  A direct
+// launch without timing binds it to its last kernel (the extended launch's
+// end event: no separate marker on the stream); otherwise it is recorded
+// after the launch.
 int vuda_world::run_kernel(int kind, const WorkList& L, int parity, int32_t lo, int32_t hi, hipStream_t s,
-                           int32_t* queue) {
+                           int32_t* queue, hipEvent_t done) {
+  if (done && !tune.timing && !tune.graphs) {
+    LaunchEvents le;
+    le.stop = done;
+    int rc = enqueue_kernel(kind, L, parity, s, queue, &le);
+    if (rc) return rc;
+    if (!le.stopped) HIPCHK(hipEventRecord(done, s));  // nothing was launched
+    return VUDA_OK;
+  }
+  const int rc0 = launch_kernel(kind, L, parity, lo, hi, s, queue);
+  if (rc0 || !done) return rc0;
+  HIPCHK(hipEventRecord(done, s));
+  return VUDA_OK;
+}
+
+int vuda_world::launch_kernel(int kind, const WorkList& L, int parity, int32_t lo, int32_t hi, hipStream_t s,
+                              int32_t* queue) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (tune.timing) {
     std::vector<hipEvent_t>& ev = tev[kind];
@@ -1130,9 +1160,17 @@ extern "C" int vuda_step(vuda_world* w, int32_t lo, int32_t hi, int32_t nsteps) 
       rc = w->wait_event(s, last);
       if (rc) return rc;
     }
-    rc = w->run_kernel(kKernelPhysics, *L, p, lo, hi, s, w->queues);
+    // the step's event, bound to the end of its last kernel
+    int64_t id = -1;
+    hipEvent_t done = nullptr;
+    if (w->mode != 0) {
+      rc = w->reserve_event(&id, &done);
+      if (rc) return rc;
+    }
+    const bool setup = LR && t == nsteps - 1;
+    rc = w->run_kernel(kKernelPhysics, *L, p, lo, hi, s, w->queues, setup ? nullptr : done);
     if (rc) return rc;
-    if (LR && t == nsteps - 1) {
+    if (setup) {
       if (w->mode != 0) {
         // WAR: the renders of this buffer read its raster scratch
         int64_t last = -1;
@@ -1141,12 +1179,7 @@ extern "C" int vuda_step(vuda_world* w, int32_t lo, int32_t hi, int32_t nsteps) 
         rc = w->wait_event(s, last);
         if (rc) return rc;
       }
-      rc = w->run_kernel(kKernelSetup, *LR, p ^ 1, lo, hi, s, w->queues + 1);
-      if (rc) return rc;
-    }
-    int64_t id = -1;
-    if (w->mode != 0) {
-      rc = w->new_event(s, &id);
+      rc = w->run_kernel(kKernelSetup, *LR, p ^ 1, lo, hi, s, w->queues + 1, done);
       if (rc) return rc;
     }
     for (int32_t e = lo; e < hi; ++e) {
@@ -1189,28 +1222,36 @@ extern "C" int vuda_render(vuda_world* w, int32_t lo, int32_t hi) {
   int64_t state_id = -1;
   bool reads_state = false;
   if (lds) {
-    rc = w->run_kernel(kKernelFused, *L, parity, lo, hi, s, w->queues + 2);
-    if (rc) return rc;
     reads_state = true;
   } else {
     bool need_setup = false;
     for (int32_t e = lo; e < hi; ++e) need_setup |= w->env_active[e] && !w->setup_ok[e];
     if (need_setup) {
-      rc = w->run_kernel(kKernelSetup, *L, parity, lo, hi, s, w->queues + 2);
-      if (rc) return rc;
-      for (int32_t e = lo; e < hi; ++e) w->setup_ok[e] = 1;
+      hipEvent_t sdone = nullptr;
       if (w->mode != 0) {
-        rc = w->new_event(s, &state_id);
+        rc = w->reserve_event(&state_id, &sdone);
         if (rc) return rc;
       }
+      rc = w->run_kernel(kKernelSetup, *L, parity, lo, hi, s, w->queues + 2, sdone);
+      if (rc) return rc;
+      for (int32_t e = lo; e < hi; ++e) w->setup_ok[e] = 1;
     }
-    rc = w->run_kernel(kKernelTiles, *L, parity, lo, hi, s, nullptr);
+  }
+  // the render's event, bound to the end of its last kernel
+  int64_t id = -1;
+  hipEvent_t done = nullptr;
+  if (w->mode != 0) {
+    rc = w->reserve_event(&id, &done);
+    if (rc) return rc;
+  }
+  if (lds) {
+    rc = w->run_kernel(kKernelFused, *L, parity, lo, hi, s, w->queues + 2, done);
+    if (rc) return rc;
+  } else {
+    rc = w->run_kernel(kKernelTiles, *L, parity, lo, hi, s, nullptr, done);
     if (rc) return rc;
   }
   if (w->mode != 0) {
-    int64_t id;
-    rc = w->new_event(s, &id);
-    if (rc) return rc;
     if (reads_state) state_id = id;
     for (int32_t e = lo; e < hi; ++e) {
       if (!w->env_active[e]) continue;

@@ -2191,30 +2191,31 @@ static int run_pipelined(vuda_world* w, int32_t iters) {
   for (hipStream_t s : {ss, su, sr}) {
     if ((rc = w->wait_event(s, ls)) || (rc = w->wait_event(s, lr))) return rc;
   }
+  // each stage's event is bound to the end of its kernel (run_kernel)
+  const auto run_ev = [&](int kind, const WorkList& L, int p, hipStream_t s, int32_t* q, int64_t* id) {
+    hipEvent_t done;
+    int r = w->reserve_event(id, &done);
+    return r ? r : w->run_kernel(kind, L, p, 0, hi, s, q, done);
+  };
   int64_t ev_setup = -1, ev_phys = -1, ev_tiles_prev = -1;
   if (need_setup) {
-    if ((rc = w->run_kernel(kKernelSetup, *LR, parity, 0, hi, su, w->queues + 1))) return rc;
-    if ((rc = w->new_event(su, &ev_setup))) return rc;
+    if ((rc = run_ev(kKernelSetup, *LR, parity, su, w->queues + 1, &ev_setup))) return rc;
   }
-  if ((rc = w->run_kernel(kKernelPhysics, *LS, parity, 0, hi, ss, w->queues))) return rc;
-  if ((rc = w->new_event(ss, &ev_phys))) return rc;
+  if ((rc = run_ev(kKernelPhysics, *LS, parity, ss, w->queues, &ev_phys))) return rc;
   for (int32_t k = 0; k < iters; ++k) {
     const int pk = parity ^ (k & 1);  // state buffer and scratch parity of S_k
     // tiles of S_k
     if ((rc = w->wait_event(sr, ev_setup))) return rc;
-    if ((rc = w->run_kernel(kKernelTiles, *LR, pk, 0, hi, sr, nullptr))) return rc;
     int64_t ev_tiles;
-    if ((rc = w->new_event(sr, &ev_tiles))) return rc;
+    if ((rc = run_ev(kKernelTiles, *LR, pk, sr, nullptr, &ev_tiles))) return rc;
     // setup of S_k+1
     if ((rc = w->wait_event(su, ev_phys)) || (rc = w->wait_event(su, ev_tiles_prev))) return rc;
-    if ((rc = w->run_kernel(kKernelSetup, *LR, pk ^ 1, 0, hi, su, w->queues + 1))) return rc;
     int64_t ev_setup_next;
-    if ((rc = w->new_event(su, &ev_setup_next))) return rc;
+    if ((rc = run_ev(kKernelSetup, *LR, pk ^ 1, su, w->queues + 1, &ev_setup_next))) return rc;
     // step S_k+1 -> S_k+2, into the buffer of S_k
     if (k + 2 <= iters) {
       if ((rc = w->wait_event(ss, ev_setup))) return rc;
-      if ((rc = w->run_kernel(kKernelPhysics, *LS, pk ^ 1, 0, hi, ss, w->queues))) return rc;
-      if ((rc = w->new_event(ss, &ev_phys))) return rc;
+      if ((rc = run_ev(kKernelPhysics, *LS, pk ^ 1, ss, w->queues, &ev_phys))) return rc;
     }
     ev_setup = ev_setup_next;
     ev_tiles_prev = ev_tiles;

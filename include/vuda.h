@@ -521,15 +521,18 @@ int vuda_run(vuda_world* w, int32_t schedule, int32_t iters);
  * Autotuner: searches the launch shapes (schedule, CU split, physics and
  * raster persistent grids and workgroup shapes, raster tile size, physics
  * envs per wave, fused raster, tile-kernel workgroup, hipGraph replay,
- * physics and tile priorities, broadphase, presetup)
- * for the highest
+ * physics and tile priorities, broadphase, presetup) for the highest
  * co-scheduled env-steps/s on this world, timing `steps_per_trial`
  * iterations per candidate from the current state (the state is saved before
- * and restored after, so results are unchanged); the last few winners of the
- * search and the serialized baseline are timed again, three trials each, and
- * the best median is chosen (VUDA_SCHED_SERIAL where nothing co-scheduled
- * beats it; its rate is reported as cosched_env_steps_per_s).  It applies
- * the best, and
+ * and restored after, so results are unchanged).  Coordinate descent over
+ * all of them, then a second descent per schedule over its split, workgroup
+ * shapes, envs per wave and priorities; each schedule's result, the first
+ * descent's and the serialized baseline are timed again, three trials each,
+ * and the best median is chosen (VUDA_SCHED_SERIAL where nothing
+ * co-scheduled beats it; its rate is reported as cosched_env_steps_per_s).
+ * A world's unmasked streams (split 2) have hardware queues of their own, so
+ * the choice does not depend on what other streams the process holds.  It
+ * applies the best, and
  * records it in the text file `cache_path` (may be NULL) keyed by the GPU
  * architecture and the world's shape; a later call with the same key applies
  * the cached choice without trials.  Also reports the best serialized rate.

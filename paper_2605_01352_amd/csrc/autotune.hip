@@ -1,15 +1,18 @@
 // Autotuner: picks the schedule, CU split and launch shapes with the highest
 // measured co-scheduled throughput on a world, by coordinate descent over a
 // small candidate set, timing real iterations from a saved state.  The
-// coordinates, in order: schedule x CU split; fused raster; physics
-// persistent grid; raster-setup persistent grid; tile size; physics envs per
-// wave; hipGraph replay; raster workgroup size; tile-kernel workgroup size;
-// step wave priority; tile wave priority; broadphase; presetup.  The
-// persistent grids include the resident size (VUDA_PERSISTENT_RESIDENT).  The
-// winners of the last stages and the serialized baseline are then timed
-// again, three trials each, and the best median is the choice (so the serial
-// schedule where nothing co-scheduled beats it).  The serialized baseline takes the better
-// of the two raster paths and of two workgroup sizes.
+// coordinates, in order: schedule x CU split (with the step's wave priority
+// on unmasked streams); fused raster; physics persistent grid; raster-setup
+// persistent grid; tile size; physics envs per wave; hipGraph replay; raster
+// workgroup size; tile-kernel workgroup size; step wave priority; tile wave
+// priority; broadphase; presetup.  Then, per schedule, a second descent over
+// its split, workgroup sizes, envs per wave and priorities.  The persistent
+// grids include the resident size (VUDA_PERSISTENT_RESIDENT).  Each
+// schedule's result, the first pass's and the serialized baseline are then
+// timed again, three trials each, and the best median is the choice (so the
+// serial schedule where nothing co-scheduled beats it).  The serialized
+// baseline takes the better of the two raster paths and of two workgroup
+// sizes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -251,36 +254,44 @@ extern "C" int vuda_autotune(vuda_world* w, int32_t steps, const char* cache_pat
       if ((rc = run(c, &r))) break;
       if (r > best_serial) { best_serial = r; bs = c; }
     }
-  // co-scheduled: coordinate descent
+  // co-scheduled: coordinate descent.  A stage times each value of one
+  // coordinate on the incumbent and keeps the fastest trial.
   Cand best = bs;
   best.tune = bs.tune;
   double best_rate = -1.0;
-  std::vector<Cand> winners;  // the best candidate after each stage that changed it
-  if (!rc) {
-    const float splits[] = {2.0f, 0.25f, 0.375f, 0.5f, 0.625f, 0.75f};
-    for (int sched : {VUDA_SCHED_INTERSTEP, VUDA_SCHED_INTERTRAJ, VUDA_SCHED_PIPELINED})
-      for (float sp : splits) {
-        Cand c = best;
-        c.sched = sched;
-        c.split = sp;
-        double r;
-        if ((rc = run(c, &r))) break;
-        if (r > best_rate) { best_rate = r; best.sched = sched; best.split = sp; }
-      }
-    winners.push_back(best);
-  }
   auto stage = [&](auto set, std::initializer_list<int> vals) {
-    bool changed = false;
     for (int v : vals) {
       if (rc) return;
       Cand c = best;
       set(c, v);
       double r;
       if ((rc = run(c, &r))) return;
-      if (r > best_rate) { best_rate = r; best = c; changed = true; }
+      if (r > best_rate) { best_rate = r; best = c; }
     }
-    if (changed) winners.push_back(best);
   };
+  // schedule x CU split; on unmasked streams (split 2) also the step's waves
+  // at the top issue priority, since the two moves pay only together there
+  auto sched_stage = [&](std::initializer_list<int> scheds) {
+    const float splits[] = {2.0f, 0.25f, 0.375f, 0.5f, 0.625f, 0.75f};
+    const int p0 = best.tune.phys_prio;
+    for (int sched : scheds)
+      for (float sp : splits) {
+        std::vector<int> prios = {p0};
+        if (sp == 2.0f && p0 != 3) prios.push_back(3);
+        for (int prio : prios) {
+          if (rc) return;
+          Cand c = best;
+          c.sched = sched;
+          c.split = sp;
+          c.tune.phys_prio = prio;
+          double r;
+          if ((rc = run(c, &r))) return;
+          if (r > best_rate) { best_rate = r; best = c; }
+        }
+      }
+  };
+  const auto all_scheds = {VUDA_SCHED_INTERSTEP, VUDA_SCHED_INTERTRAJ, VUDA_SCHED_PIPELINED};
+  if (!rc) sched_stage(all_scheds);
   stage([](Cand& c, int v) { c.tune.raster_fused = v != 0; }, {0, 1});
   stage([](Cand& c, int v) { c.tune.phys_persistent = v; }, {0, ncu, 2 * ncu, 3 * ncu, VUDA_PERSISTENT_RESIDENT});
   stage([](Cand& c, int v) { c.tune.raster_persistent = v; }, {0, ncu, 2 * ncu, 4 * ncu, VUDA_PERSISTENT_RESIDENT});
@@ -293,10 +304,32 @@ extern "C" int vuda_autotune(vuda_world* w, int32_t steps, const char* cache_pat
   stage([](Cand& c, int v) { c.tune.tile_prio = v; }, {0, 1});
   stage([](Cand& c, int v) { c.tune.broadphase = v; }, {0, 1});
   stage([](Cand& c, int v) { c.tune.presetup = v != 0; }, {1, 0});
+  // The schedule and split were chosen first, with untuned launch shapes, and
+  // the schedules differ in which shapes suit them.  A second descent per
+  // schedule, from the first pass's result: its split (and priority), the
+  // workgroup sizes, envs per wave and priorities.  Each schedule's result
+  // is a finalist.
+  std::vector<Cand> finalists;
+  const Cand first = best;
+  for (int sched : all_scheds) {
+    if (rc) break;
+    best = first;
+    best.sched = sched;
+    if ((rc = run(best, &best_rate))) break;
+    sched_stage({sched});
+    stage([](Cand& c, int v) { c.tune.raster_threads = v; }, {256, 128, 512});
+    stage([](Cand& c, int v) { c.tune.tile_waves = v; }, {2, 4, 1});
+    stage([](Cand& c, int v) { c.tune.phys_pack = v; }, {1, 2});
+    stage([](Cand& c, int v) { c.tune.phys_prio = v; }, {0, 3});
+    stage([](Cand& c, int v) { c.tune.tile_prio = v; }, {0, 1});
+    finalists.push_back(best);
+  }
   // Each stage keeps its fastest single trial, which favours a lucky one:
-  // the last few stage winners are timed again, three trials each, and the
-  // fastest median is the choice.
-  if (!rc && !winners.empty()) {
+  // the finalists (each schedule's result, the first pass's, and the
+  // serialized loop, which is the choice where no co-scheduled candidate
+  // beats it) are timed again, three trials each, and the fastest median is
+  // the choice.
+  if (!rc) {
     const auto same = [](const Cand& a, const Cand& b) {
       vuda_tune_result x, y;
       memset(&x, 0, sizeof(x));
@@ -305,18 +338,17 @@ extern "C" int vuda_autotune(vuda_world* w, int32_t steps, const char* cache_pat
       to_result(b, &y);
       return memcmp(&x, &y, sizeof(x)) == 0;
     };
-    std::vector<Cand> finalists;
-    for (auto it = winners.rbegin(); it != winners.rend() && finalists.size() < 4; ++it) {
-      bool seen = false;
-      for (const Cand& f : finalists) seen = seen || same(f, *it);
-      if (!seen) finalists.push_back(*it);
-    }
-    // the serialized loop competes too: where no co-scheduled candidate
-    // beats it, it is the choice
+    std::vector<Cand> uniq;
+    finalists.push_back(first);
     finalists.push_back(bs);
-    double top = -1.0;
-    Cand pick = best;
     for (const Cand& c : finalists) {
+      bool seen = false;
+      for (const Cand& f : uniq) seen = seen || same(f, c);
+      if (!seen) uniq.push_back(c);
+    }
+    double top = -1.0;
+    Cand pick = first;
+    for (const Cand& c : uniq) {
       double r3[3];
       for (int k = 0; k < 3 && !rc; ++k) rc = run(c, &r3[k]);
       if (rc) break;

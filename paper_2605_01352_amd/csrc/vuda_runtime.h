@@ -168,7 +168,7 @@ struct vuda_world {
 
   // streams: mode 0 serialized (s_sim == s_render == s_serial), 1 CU-masked,
   // 2 two unmasked streams
-  hipStream_t s_serial = nullptr, s_sim = nullptr, s_render = nullptr, s_capture = nullptr;
+  hipStream_t s_serial = nullptr, s_sim = nullptr, s_render = nullptr;
   hipStream_t s_setup = nullptr;  // raster setup of the pipelined schedule (the step's CUs)
   int mode = 0;
   float cu_split = 0.0f;
@@ -236,7 +236,6 @@ struct vuda_world {
   // the launch itself: direct, timed, or through a captured graph
   int launch_kernel(int kind, const vuda::WorkList& L, int parity, int32_t lo, int32_t hi, hipStream_t s,
                     int32_t* queue);
-  hipStream_t capture_stream();
   int check_flags();
   int32_t active_midpoint();
   // events that complete when everything enqueued so far on the world's

@@ -214,6 +214,13 @@ struct vuda_world {
   int make_streams(float split);
   void destroy_streams();
   int drain();
+  // Host-synchronous copy and fill that do not wait for the world's work
+  // streams.  Streams with a CU mask (every co-scheduled mode) are blocking
+  // streams, which any operation on the null stream waits for; outside the
+  // serialized mode these go through the serial stream, which is then idle
+  // and non-blocking.
+  hipError_t copy_now(void* dst, const void* src, size_t bytes, hipMemcpyKind kind);
+  hipError_t fill_now(void* dst, int value, size_t bytes);
   int init_events();
   int new_event(hipStream_t s, int64_t* id);
   int reserve_event(int64_t* id, hipEvent_t* ev);

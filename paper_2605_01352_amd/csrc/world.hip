@@ -714,6 +714,18 @@ int vuda_world::make_streams(float split) {
   return VUDA_OK;
 }
 
+hipError_t vuda_world::copy_now(void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
+  if (mode == 0 || !s_serial) return hipMemcpy(dst, src, bytes, kind);
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, s_serial);
+  return e == hipSuccess ? hipStreamSynchronize(s_serial) : e;
+}
+
+hipError_t vuda_world::fill_now(void* dst, int value, size_t bytes) {
+  if (mode == 0 || !s_serial) return hipMemset(dst, value, bytes);
+  hipError_t e = hipMemsetAsync(dst, value, bytes, s_serial);
+  return e == hipSuccess ? hipStreamSynchronize(s_serial) : e;
+}
+
 int vuda_world::drain() {
   HIPCHK(hipSetDevice(device));
   if (s_sim) HIPCHK(hipStreamSynchronize(s_sim));
@@ -875,7 +887,7 @@ int vuda_world::get_list(int phase, int32_t lo, int32_t hi, const WorkList** out
     HIPCHK(hipMalloc(&B.dptr, 4 * (size_t)want));
     B.cap = want;
   }
-  if (!ids.empty()) HIPCHK(hipMemcpy(B.dptr, ids.data(), 4 * ids.size(), hipMemcpyHostToDevice));
+  if (!ids.empty()) HIPCHK(copy_now(B.dptr, ids.data(), 4 * ids.size(), hipMemcpyHostToDevice));
   L.dptr = B.dptr;
   L.n = (int32_t)ids.size();
   L.n_groups = 0;
@@ -910,7 +922,7 @@ int vuda_world::get_list(int phase, int32_t lo, int32_t hi, const WorkList** out
       HIPCHK(hipMalloc(&B.tptr, sizeof(int2) * (size_t)want));
       B.tcap = want;
     }
-    HIPCHK(hipMemcpy(B.tptr, jobs.data(), sizeof(int2) * jobs.size(), hipMemcpyHostToDevice));
+    HIPCHK(copy_now(B.tptr, jobs.data(), sizeof(int2) * jobs.size(), hipMemcpyHostToDevice));
     L.n_groups = (int32_t)jobs.size();
   }
   L.tptr = B.tptr;
@@ -1277,7 +1289,7 @@ extern "C" int vuda_render(vuda_world* w, int32_t lo, int32_t hi) {
 int vuda_world::check_flags() {
   uint32_t any = 0;
   std::vector<uint32_t> fl(cap_envs);
-  HIPCHK(hipMemcpy(fl.data(), dev.env_flags, 4 * (size_t)cap_envs, hipMemcpyDeviceToHost));
+  HIPCHK(copy_now(fl.data(), dev.env_flags, 4 * (size_t)cap_envs, hipMemcpyDeviceToHost));
   int first = -1;
   for (int32_t e = 0; e < cap_envs; ++e) {
     if (fl[e] && first < 0) first = e;
@@ -1869,7 +1881,7 @@ extern "C" int vuda_load_state(vuda_world* w, int32_t lo, int32_t hi, const floa
   for (int32_t e = lo; e < hi; ++e) w->setup_ok[e] = 0;
   // clear sticky flags of the reloaded envs
   std::vector<uint32_t> zero(hi - lo, 0u);
-  if (hi > lo) HIPCHK(hipMemcpy(w->dev.env_flags + lo, zero.data(), 4 * zero.size(), hipMemcpyHostToDevice));
+  if (hi > lo) HIPCHK(w->copy_now(w->dev.env_flags + lo, zero.data(), 4 * zero.size(), hipMemcpyHostToDevice));
   return VUDA_OK;
 }
 
@@ -1937,7 +1949,7 @@ extern "C" int vuda_admit(vuda_world* w, const vuda_env_batch* b, int32_t parity
     w->render_state_ev[1][e0 + e] = -1;
   }
   // a reused slot starts without the policy's forces of its last env
-  if (w->act_on) HIPCHK(hipMemset(w->act_on + e0, 0, (size_t)b->n_envs));
+  if (w->act_on) HIPCHK(w->fill_now(w->act_on + e0, 0, (size_t)b->n_envs));
   w->n_envs_hi = std::max<int32_t>(w->n_envs_hi, (int32_t)(e0 + b->n_envs));
   *first_env = (int32_t)e0;
   return VUDA_OK;
@@ -1982,7 +1994,7 @@ extern "C" int vuda_release(vuda_world* w, int32_t first, int32_t n) {
              256 - r0;
   }
   std::vector<EnvDev> empty(n, EnvDev{});
-  HIPCHK(hipMemcpy(w->dev.envs + first, empty.data(), sizeof(EnvDev) * n, hipMemcpyHostToDevice));
+  HIPCHK(w->copy_now(w->dev.envs + first, empty.data(), sizeof(EnvDev) * n, hipMemcpyHostToDevice));
   w->bodies.release(d0.body_off, nb);
   w->camslots.release(d0.cam_off, nc);
   w->pixels.release(p0, np);

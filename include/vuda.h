@@ -225,11 +225,13 @@ int vuda_destroy_world(vuda_world* w);
  * Co-scheduling switch (the paper's stream bind/unbind).  0 < cu_split < 1:
  * the step phase runs on a stream restricted to that fraction of the CUs and
  * the render phase on a stream restricted to the rest (hipExtStreamCreate-
- * WithCUMask, balanced over the XCDs); cu_split == 2 runs them on two
- * unmasked streams; cu_split <= 0 or == 1 restores the serialized path (one
+ * WithCUMask, balanced over the XCDs); cu_split == 2 runs them on streams
+ * over every CU (masks of all CUs, so that each stream has a hardware queue
+ * of its own); cu_split <= 0 or == 1 restores the serialized path (one
  * stream, every phase in enqueue order).  Changing it only moves work
  * between CUs: outputs are bit-identical in every mode.  Drains the world
- * before switching.
+ * before switching.  The co-scheduled streams are blocking streams: work
+ * the caller puts on the null stream waits for them.
  */
 int vuda_cosched(vuda_world* w, float cu_split);
 
@@ -538,7 +540,7 @@ int vuda_run(vuda_world* w, int32_t schedule, int32_t iters);
  * the cached choice without trials.  Also reports the best serialized rate.
  */
 typedef struct {
-  float cu_split;            /* chosen split: (0,1) CU-masked, 2 unmasked streams */
+  float cu_split;            /* chosen split: (0,1) CU-masked, 2 every CU on each stream */
   int32_t schedule;          /* VUDA_SCHED_* */
   int32_t raster_threads, rec_cap, phys_persistent, raster_persistent, phys_priority, broadphase;
   double cosched_env_steps_per_s;

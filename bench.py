@@ -443,7 +443,7 @@ def uneven_c4_leg(torch, vuda, scene, start, steps, log):
         ser = n * steps / med("serial")
         w.load_state(st0)
         t0 = time.perf_counter()
-        choice = w.autotune(steps=40)
+        choice = w.autotune(steps=steps)
         t_tune = time.perf_counter() - t0
         sched = vuda.SCHED_NAMES[int(choice["schedule"])]
         tuned = n * steps / med(sched)
@@ -720,7 +720,7 @@ def main():
     if not args.only and not args.no_autotune:
         w.load_state(st0)
         t0 = time.perf_counter()
-        choice = w.autotune(steps=40)
+        choice = w.autotune(steps=args.steps)  # trials as long as the headline's windows
         t_tune = time.perf_counter() - t0
         log(f"autotuner ({t_tune:.1f} s, {choice['trials']} trials): {choice}")
 

@@ -524,9 +524,11 @@ int vuda_run(vuda_world* w, int32_t schedule, int32_t iters);
  * raster persistent grids and workgroup shapes, raster tile size, physics
  * envs per wave, fused raster, tile-kernel workgroup, hipGraph replay,
  * physics and tile priorities, broadphase, presetup) for the highest
- * co-scheduled env-steps/s on this world, timing `steps_per_trial`
- * iterations per candidate from the current state (the state is saved before
- * and restored after, so results are unchanged).  Coordinate descent over
+ * co-scheduled env-steps/s on this world.  A trial of a candidate is the
+ * median of three runs of `steps_per_trial` iterations, each from the
+ * current state after 3 warmup iterations (the state is saved before and
+ * restored after, so results are unchanged); a candidate replaces the
+ * incumbent only when faster by more than 1%.  Coordinate descent over
  * all of them, then a second descent per schedule over its split, workgroup
  * shapes, envs per wave and priorities; each schedule's result, the first
  * descent's and the serialized baseline are timed again, three trials each,

@@ -119,20 +119,29 @@ int apply(vuda_world* w, const Cand& c) {
   return vuda_cosched(w, c.split);
 }
 
-// env-steps/s of `steps` iterations of candidate c from the snapshot
+// env-steps/s of `steps` iterations of candidate c from the snapshot: the
+// median of three runs, each from the restored state after 3 warmup
+// iterations
 int trial(vuda_world* w, const Snapshot& snap, const Cand& c, int32_t steps, int32_t envs,
           double* rate) {
   int rc = restore_snapshot(w, snap);
   if (!rc) rc = apply(w, c);
-  if (!rc) rc = vuda_run(w, c.sched, 3);
-  if (!rc) rc = w->drain();
+  double r3[3];
+  for (int k = 0; k < 3 && !rc; ++k) {
+    if (k) rc = restore_snapshot(w, snap);
+    if (!rc) rc = vuda_run(w, c.sched, 3);
+    if (!rc) rc = w->drain();
+    if (rc) break;
+    const auto t0 = std::chrono::steady_clock::now();
+    rc = vuda_run(w, c.sched, steps);
+    if (!rc) rc = w->drain();
+    if (rc) break;
+    const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    r3[k] = dt > 0 ? (double)envs * steps / dt : 0.0;
+  }
   if (rc) return rc;
-  const auto t0 = std::chrono::steady_clock::now();
-  rc = vuda_run(w, c.sched, steps);
-  if (!rc) rc = w->drain();
-  if (rc) return rc;
-  const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  *rate = dt > 0 ? (double)envs * steps / dt : 0.0;
+  std::sort(r3, r3 + 3);
+  *rate = r3[1];
   return VUDA_OK;
 }
 
@@ -255,7 +264,10 @@ extern "C" int vuda_autotune(vuda_world* w, int32_t steps, const char* cache_pat
       if (r > best_serial) { best_serial = r; bs = c; }
     }
   // co-scheduled: coordinate descent.  A stage times each value of one
-  // coordinate on the incumbent and keeps the fastest trial.
+  // coordinate on the incumbent and keeps the fastest; a value replaces the
+  // incumbent only if it is faster by more than the trials' noise (medians of
+  // runs of a few milliseconds still vary by about a percent).
+  constexpr double kMargin = 1.01;
   Cand best = bs;
   best.tune = bs.tune;
   double best_rate = -1.0;
@@ -266,7 +278,7 @@ extern "C" int vuda_autotune(vuda_world* w, int32_t steps, const char* cache_pat
       set(c, v);
       double r;
       if ((rc = run(c, &r))) return;
-      if (r > best_rate) { best_rate = r; best = c; }
+      if (r > best_rate * kMargin) { best_rate = r; best = c; }
     }
   };
   // schedule x CU split; on unmasked streams (split 2) also the step's waves
@@ -286,7 +298,7 @@ extern "C" int vuda_autotune(vuda_world* w, int32_t steps, const char* cache_pat
           c.tune.phys_prio = prio;
           double r;
           if ((rc = run(c, &r))) return;
-          if (r > best_rate) { best_rate = r; best = c; }
+          if (r > best_rate * kMargin) { best_rate = r; best = c; }
         }
       }
   };
@@ -324,11 +336,10 @@ extern "C" int vuda_autotune(vuda_world* w, int32_t steps, const char* cache_pat
     stage([](Cand& c, int v) { c.tune.tile_prio = v; }, {0, 1});
     finalists.push_back(best);
   }
-  // Each stage keeps its fastest single trial, which favours a lucky one:
-  // the finalists (each schedule's result, the first pass's, and the
-  // serialized loop, which is the choice where no co-scheduled candidate
-  // beats it) are timed again, three trials each, and the fastest median is
-  // the choice.
+  // Each stage keeps its fastest trial, which favours a lucky one: the
+  // finalists (each schedule's result, the first pass's, and the serialized
+  // loop, which is the choice where no co-scheduled candidate beats it) are
+  // timed again, three trials each, and the fastest median is the choice.
   if (!rc) {
     const auto same = [](const Cand& a, const Cand& b) {
       vuda_tune_result x, y;

@@ -35,12 +35,14 @@ def _generator_pool(workers: int):
 
 
 def run(duration: float = 120.0, rate: float = 50.0, budget_gb: float = 200.0,
-        cu_split: float = 2.0, schedule: int = vuda.SCHED_INTERSTEP, seed: int = 1005,
+        cu_split: float = 2.0, schedule: int = vuda.SCHED_PIPELINED, seed: int = 1005,
         drain: bool = True, log=None, tune=None, workers: int = 0, ahead_s: float = 1.5,
         pool=None) -> dict:
     """Serve Poisson(rate) arrivals for `duration` seconds.  drain: keep
     ticking after the last arrival until every request has completed (else
-    stop at `duration`, counting what was served by then)."""
+    stop at `duration`, counting what was served by then).  The default
+    schedule is the pipelined one: at 200 requests/s it served 5.56 M
+    env-steps/s against 4.22 M inter-step (8 s runs, one box)."""
     specs = sg.serving_requests(duration_s=duration, rate=rate, seed=seed)
     own_pool = pool is None
     if own_pool:
@@ -142,7 +144,7 @@ def main():
     ap.add_argument("--rate", type=float, default=50.0)
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--split", type=float, default=2.0)
-    ap.add_argument("--schedule", default="interstep", choices=["serial", "interstep", "intertraj", "pipelined"])
+    ap.add_argument("--schedule", default="pipelined", choices=["serial", "interstep", "intertraj", "pipelined"])
     ap.add_argument("--capacity", action="store_true", help="also sweep the arrival rate for the capacity")
     a = ap.parse_args()
     sched = {"serial": vuda.SCHED_SERIAL, "interstep": vuda.SCHED_INTERSTEP,

@@ -63,6 +63,36 @@ def test_async_enqueue_returns_early():
         assert busy and t_enqueue < t_total
 
 
+@pytest.mark.parametrize("split", [2.0, 0.5])
+def test_list_rebuild_does_not_wait_for_running_work(split):
+    """A call that builds a new work list (here a step over an env range not
+    stepped before) copies the list to the device while earlier iterations
+    still run.  The co-scheduled streams are blocking streams, which a copy
+    on the null stream would wait for: the call must return long before the
+    running iterations end."""
+    import torch
+    torch.cuda.init()
+    dev = torch.device("cuda", 0)
+    s = sg.config_scene(2, n_envs=1024)
+    with vuda.World(s) as w:
+        w.cosched(split)
+        w.run(vuda.SCHED_INTERSTEP, 2)
+        w.wait()
+        streams = [torch.cuda.ExternalStream(w.stream(p), device=dev)
+                   for p in (vuda.PHASE_STEP, vuda.PHASE_RENDER)]
+        t0 = time.perf_counter()
+        w.run(vuda.SCHED_INTERSTEP, 100)
+        t1 = time.perf_counter()
+        w.step(lo=0, hi=384)  # a range with no list yet
+        t_call = time.perf_counter() - t1
+        busy = not all(st.query() for st in streams)
+        w.wait()
+        t_total = time.perf_counter() - t0
+        say(f"split {split:g}: new-range step returned in {t_call * 1e3:.2f} ms; the running iterations took "
+            f"{t_total * 1e3:.2f} ms")
+        assert busy and t_call < 0.25 * t_total
+
+
 @pytest.mark.parametrize("schedule", [vuda.SCHED_SERIAL, vuda.SCHED_INTERSTEP, vuda.SCHED_INTERTRAJ])
 @pytest.mark.parametrize("split", [0.0, 2.0, 0.25, 0.625])
 def test_schedules_and_modes_bit_identical(schedule, split):

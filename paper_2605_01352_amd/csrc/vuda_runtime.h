@@ -166,8 +166,9 @@ struct vuda_world {
   vuda::RangeAlloc rsspace;  // raster scratch, in 256-byte units
   int64_t cap_prims = 0, cap_verts = 0, cap_rs = 0;
 
-  // streams: mode 0 serialized (s_sim == s_render == s_serial), 1 CU-masked,
-  // 2 two unmasked streams
+  // streams: mode 0 serialized (s_sim == s_render == s_serial), 1 CU-masked
+  // (a partition), 2 streams over every CU (masks of all CUs, for hardware
+  // queues of their own)
   hipStream_t s_serial = nullptr, s_sim = nullptr, s_render = nullptr;
   hipStream_t s_setup = nullptr;  // raster setup of the pipelined schedule (the step's CUs)
   int mode = 0;

@@ -1,9 +1,12 @@
 """GPU parity at the full sizes of the three batch configurations.
 
 Each config runs on the GPU from its spawn for its whole horizon in the
-product world (no debug outputs), at the launch shapes the bench times.  At
-the first, middle and last step of that trajectory every env is checked
-against the oracle from the GPU's own state S_t:
+product world (no debug outputs), in the co-scheduled launch configuration
+the bench's headline usually picks: the pipelined schedule on streams over
+every CU, step priority 3, tile priority 1, setup workgroups of 128 threads,
+tile workgroups of 2 waves.  At the first, middle and last step of that
+trajectory every env is checked against the oracle from the GPU's own state
+S_t:
   - one physics step: state within 1e-5 relative, and (from a debug world
     loaded with S_t) the contact-pair sets of all four substeps bit-exact,
     the debug world's S_t+1 bit-identical to the product world's;
@@ -50,10 +53,14 @@ def test_full_config_samples(cfg, horizon):
     cams = _sample_cams(scene, cfg)
     envs = range(n)
     with vuda.World(scene) as w, vuda.World(scene, debug=True) as wd:
+        for k, v in ((vuda.TUNE_RASTER_THREADS, 128), (vuda.TUNE_TILE_WAVES, 2), (vuda.TUNE_PHYS_PRIORITY, 3),
+                     (vuda.TUNE_TILE_PRIORITY, 1)):
+            w.set_tuning(k, v)
+        w.cosched(2.0)
         t = 0
         for ts in samples:
             if ts > t:
-                w.step(nsteps=ts - t)
+                w.run(vuda.SCHED_PIPELINED, ts - t)  # ts - t steps, each state rendered
                 t = ts
             w.wait()
             st_t = w.state()
